@@ -1,0 +1,426 @@
+"""Seeded synthetic inputs for batched LiDAR ray casting.
+
+This module only *produces inputs*: triangle meshes, sensor poses and beam
+patterns.  It holds none of the ray-casting arithmetic, and both the GPU
+path's tests and the FP64 oracle's tests draw their inputs from it.
+
+The paper's scenes (3DGS assets, real LiDAR captures; FGGS-LiDAR Sec. V) are
+not available, so seeded synthetic scenes with the same structure stand in:
+
+* ``room_sphere_scene`` -- closed 10 x 8 x 3 m box room (12 triangles) with a
+  UV sphere (r = 1 m, 64 x 32 segments, 3,968 triangles) at a seeded spot;
+  one seeded interior pose, 16 x 360 beam pattern over -15..+15 deg.
+* ``indoor_scene`` -- closed indoor mesh: marching cubes (spacing ``h``) of a
+  seeded signed-distance union of the room shell and 200 boxes / spheres /
+  vertical cylinders with sizes uniform in 0.1..2 m.  At h = 3.5 cm this is
+  about one million triangles; at h = 2 cm about three million.
+* ``terrain_scene`` -- open outdoor heightfield (fractal value noise, 200 x
+  200 m) plus randomly placed, partly sunk boxes.
+
+Mesh layout everywhere: ``verts`` float32 [nv, 3], ``tris`` int32 [nt, 3].
+Pose layout: float32 [12] row-major ``[R | t]``.  Beam directions: float32
+[n_beams, 3], unit length (computed in FP64, then rounded), index
+``j = elevation_index * n_az + azimuth_index``; sensor frame x forward,
+y left, z up.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sdfmesh.c")
+_LIB = os.path.join(_HERE, "_sdfmesh.so")
+
+ROOM_LO = (0.0, 0.0, 0.0)
+ROOM_HI = (10.0, 8.0, 3.0)
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.sdf_eval.argtypes = [P, ctypes.c_int, P, P, P, ctypes.c_int64, P]
+        lib.sdf_eval.restype = None
+        lib.sdfmesh_build.argtypes = [P, ctypes.c_int, P, P, ctypes.c_double, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.POINTER(ctypes.c_int64)]
+        lib.sdfmesh_build.restype = ctypes.c_int
+        lib.sdfmesh_free.argtypes = [P]
+        lib.sdfmesh_free.restype = None
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# --------------------------------------------------------------------------
+# Beam patterns and poses
+
+def lidar_pattern(n_el: int, el_lo_deg: float, el_hi_deg: float, n_az: int) -> np.ndarray:
+    """Spinning-LiDAR directions: elevations linspace(lo, hi, n_el) inclusive,
+    azimuths a * 2pi / n_az.  FP64, rounded to float32; [n_el * n_az, 3]."""
+    el = np.radians(np.linspace(el_lo_deg, el_hi_deg, n_el, dtype=np.float64))
+    az = np.arange(n_az, dtype=np.float64) * (2.0 * math.pi / n_az)
+    E, A = np.meshgrid(el, az, indexing="ij")
+    d = np.stack([np.cos(E) * np.cos(A), np.cos(E) * np.sin(A), np.sin(E)], axis=-1)
+    return np.ascontiguousarray(d.reshape(-1, 3).astype(np.float32))
+
+
+def yaw_pose(position, yaw: float) -> np.ndarray:
+    """Row-major [R | t] for a rotation about +z by ``yaw`` (float32 [12])."""
+    c, s = math.cos(yaw), math.sin(yaw)
+    x, y, z = (float(v) for v in position)
+    return np.array([c, -s, 0.0, x, s, c, 0.0, y, 0.0, 0.0, 1.0, z], dtype=np.float32)
+
+
+def rpy_pose(position, roll: float, pitch: float, yaw: float) -> np.ndarray:
+    """Row-major [R | t] with R = Rz(yaw) Ry(pitch) Rx(roll) (float32 [12])."""
+    cr, sr = math.cos(roll), math.sin(roll)
+    cp, sp = math.cos(pitch), math.sin(pitch)
+    cy, sy = math.cos(yaw), math.sin(yaw)
+    R = np.array([[cy * cp, cy * sp * sr - sy * cr, cy * sp * cr + sy * sr],
+                  [sy * cp, sy * sp * sr + cy * cr, sy * sp * cr - cy * sr],
+                  [-sp, cp * sr, cp * cr]], dtype=np.float64)
+    P = np.zeros((3, 4), np.float64)
+    P[:, :3] = R
+    P[:, 3] = position
+    return P.reshape(12).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# Simple meshes
+
+def box_room(lo=ROOM_LO, hi=ROOM_HI):
+    """Closed axis-aligned box, 8 vertices, 12 triangles.
+
+    Faces in order -x, +x, -y, +y, -z, +z; face f owns triangles 2f, 2f+1.
+    Each face is the quad (p00, p10, p11, p01) over its two free axes
+    (a, b) = ((f//2 + 1) % 3, (f//2 + 2) % 3), split along p00-p11:
+    triangle 2f = (p00, p10, p11), triangle 2f+1 = (p00, p11, p01)."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    verts = np.array([[(hi if (c >> k) & 1 else lo)[k] for k in range(3)] for c in range(8)],
+                     dtype=np.float32)
+    tris = []
+    for f in range(6):
+        ax, side = f // 2, f % 2
+        a, b = (ax + 1) % 3, (ax + 2) % 3
+
+        def corner(ua, ub):
+            c = (side << ax) | (ua << a) | (ub << b)
+            return c
+        p00, p10, p11, p01 = corner(0, 0), corner(1, 0), corner(1, 1), corner(0, 1)
+        tris.append((p00, p10, p11))
+        tris.append((p00, p11, p01))
+    return verts, np.array(tris, dtype=np.int32)
+
+
+def uv_sphere(center, r: float, n_seg: int = 64, n_ring: int = 32):
+    """UV sphere with vertices on the sphere (FP64, rounded to float32).
+    2 * n_seg * (n_ring - 1) triangles (64 x 32 -> 3,968)."""
+    c = np.asarray(center, np.float64)
+    verts = [c + [0.0, 0.0, r]]
+    for i in range(1, n_ring):
+        th = math.pi * i / n_ring
+        for j in range(n_seg):
+            ph = 2.0 * math.pi * j / n_seg
+            verts.append(c + r * np.array([math.sin(th) * math.cos(ph),
+                                           math.sin(th) * math.sin(ph), math.cos(th)]))
+    verts.append(c + [0.0, 0.0, -r])
+    top, bot = 0, 1 + (n_ring - 1) * n_seg
+
+    def ring(i, j):
+        return 1 + i * n_seg + (j % n_seg)
+    tris = []
+    for j in range(n_seg):
+        tris.append((top, ring(0, j), ring(0, j + 1)))
+    for i in range(n_ring - 2):
+        for j in range(n_seg):
+            a, b = ring(i, j), ring(i, j + 1)
+            c2, d = ring(i + 1, j), ring(i + 1, j + 1)
+            tris.append((a, c2, d))
+            tris.append((a, d, b))
+    for j in range(n_seg):
+        tris.append((bot, ring(n_ring - 2, j + 1), ring(n_ring - 2, j)))
+    return np.array(verts, dtype=np.float32), np.array(tris, dtype=np.int32)
+
+
+def plane_quad(half: float = 1000.0, z: float = 0.0):
+    """Square at height z, [-half, half]^2, two triangles split along (-,-)-(+,+)."""
+    v = np.array([[-half, -half, z], [half, -half, z], [half, half, z], [-half, half, z]],
+                 dtype=np.float32)
+    t = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+    return v, t
+
+
+def concat_meshes(*meshes):
+    vs, ts, off = [], [], 0
+    for v, t in meshes:
+        vs.append(np.asarray(v, np.float32))
+        ts.append(np.asarray(t, np.int32) + off)
+        off += len(v)
+    return np.ascontiguousarray(np.concatenate(vs)), np.ascontiguousarray(np.concatenate(ts))
+
+
+def random_soup(rng: np.random.Generator, n: int, extent: float = 1.0):
+    """n independent random triangles in [-extent, extent]^3 (not closed)."""
+    v = rng.uniform(-extent, extent, size=(n * 3, 3)).astype(np.float32)
+    t = np.arange(n * 3, dtype=np.int32).reshape(n, 3)
+    return v, t
+
+
+# --------------------------------------------------------------------------
+# Scene descriptions
+
+@dataclasses.dataclass
+class Scene:
+    name: str
+    verts: np.ndarray
+    tris: np.ndarray
+    poses: np.ndarray          # float32 [E, 12]
+    dirs: np.ndarray           # float32 [B, 3]
+    t_min: float
+    t_max: float
+    n_az: int
+    meta: dict
+
+    @property
+    def n_rays(self) -> int:
+        return self.poses.shape[0] * self.dirs.shape[0]
+
+
+def room_sphere_scene(seed: int = 0) -> Scene:
+    """Closed 10 x 8 x 3 m box room (12 tris) + UV sphere r = 1 m (64 x 32,
+    3,968 tris) whose centre keeps >= 1.1 m from every wall; one sensor at a
+    seeded interior pose (>= 0.3 m from every surface, yaw uniform); 16 beams
+    over -15..+15 deg x 360 azimuth steps; range [0, 100] m."""
+    rng = np.random.default_rng(seed)
+    lo, hi = np.array(ROOM_LO), np.array(ROOM_HI)
+    c = rng.uniform(lo + 1.1, hi - 1.1)
+    room = box_room()
+    sph = uv_sphere(c, 1.0, 64, 32)
+    verts, tris = concat_meshes(room, sph)
+    while True:
+        p = rng.uniform(lo + 0.3, hi - 0.3)
+        if np.linalg.norm(p - c) >= 1.3:
+            break
+    pose = yaw_pose(p, rng.uniform(0.0, 2.0 * math.pi))[None]
+    dirs = lidar_pattern(16, -15.0, 15.0, 360)
+    return Scene("room_sphere", verts, tris, pose, dirs, 0.0, 100.0, 360,
+                 {"sphere_center": c, "sphere_r": 1.0, "room_lo": lo, "room_hi": hi})
+
+
+@dataclasses.dataclass
+class SdfScene:
+    room: np.ndarray        # [6] lo, hi
+    types: np.ndarray       # int32 [n]
+    params: np.ndarray      # float64 [n, 8]
+
+    def sdf(self, pts) -> np.ndarray:
+        pts = np.ascontiguousarray(pts, np.float64).reshape(-1, 3)
+        out = np.empty(pts.shape[0], np.float64)
+        _load().sdf_eval(_p(self.room), len(self.types), _p(self.types), _p(self.params),
+                         _p(pts), pts.shape[0], _p(out))
+        return out
+
+
+def indoor_sdf(seed: int, n_prims: int = 200, size_lo: float = 0.1,
+               size_hi: float = 2.0) -> SdfScene:
+    """Seeded room shell + union of boxes (yaw-random), spheres and vertical
+    cylinders; full sizes uniform in [size_lo, size_hi] m, centres uniform in
+    the room, primitive type uniform."""
+    rng = np.random.default_rng(seed)
+    room = np.array(ROOM_LO + ROOM_HI, np.float64)
+    types = rng.integers(0, 3, size=n_prims).astype(np.int32)
+    params = np.zeros((n_prims, 8), np.float64)
+    for i in range(n_prims):
+        params[i, :3] = rng.uniform(room[:3], room[3:])
+        s = rng.uniform(size_lo, size_hi, size=3)
+        if types[i] == 0:
+            params[i, 3:6] = 0.5 * s
+            params[i, 6] = rng.uniform(0.0, 2.0 * math.pi)
+        elif types[i] == 1:
+            params[i, 3] = 0.5 * s[0]
+        else:
+            params[i, 3] = 0.5 * s[0]
+            params[i, 4] = 0.5 * s[1]
+    return SdfScene(room, types, np.ascontiguousarray(params))
+
+
+def polygonise(sdf: SdfScene, h: float, pad: int = 3):
+    """Closed mesh of the zero set of ``sdf`` with grid spacing h."""
+    lib = _load()
+    vp, tp = ctypes.c_void_p(), ctypes.c_void_p()
+    nv, nt = ctypes.c_int64(), ctypes.c_int64()
+    rc = lib.sdfmesh_build(_p(sdf.room), len(sdf.types), _p(sdf.types), _p(sdf.params),
+                           float(h), int(pad), ctypes.byref(vp), ctypes.byref(nv),
+                           ctypes.byref(tp), ctypes.byref(nt))
+    if rc != 0:
+        raise MemoryError("sdfmesh_build failed")
+    try:
+        v = np.ctypeslib.as_array(ctypes.cast(vp, ctypes.POINTER(ctypes.c_float)),
+                                  shape=(nv.value, 3)).copy()
+        t = np.ctypeslib.as_array(ctypes.cast(tp, ctypes.POINTER(ctypes.c_int32)),
+                                  shape=(nt.value, 3)).copy()
+    finally:
+        lib.sdfmesh_free(vp)
+        lib.sdfmesh_free(tp)
+    return v, t
+
+
+def free_space_poses(sdf: SdfScene, n: int, seed: int, clearance: float = 0.3) -> np.ndarray:
+    """n poses uniform in free space (field >= clearance), yaw uniform."""
+    rng = np.random.default_rng(seed)
+    lo, hi = sdf.room[:3], sdf.room[3:]
+    out = []
+    while len(out) < n:
+        cand = rng.uniform(lo, hi, size=(max(64, 2 * (n - len(out))), 3))
+        ok = sdf.sdf(cand) >= clearance
+        for p in cand[ok]:
+            if len(out) < n:
+                out.append(yaw_pose(p, rng.uniform(0.0, 2.0 * math.pi)))
+    return np.ascontiguousarray(np.stack(out))
+
+
+_MESH_CACHE: dict = {}
+
+
+def indoor_mesh(seed: int = 1, h: float = 0.035):
+    key = (seed, h)
+    if key not in _MESH_CACHE:
+        sdf = indoor_sdf(seed)
+        _MESH_CACHE[key] = (sdf,) + polygonise(sdf, h)
+    return _MESH_CACHE[key]
+
+
+def indoor_scene(seed: int = 1, h: float = 0.035, n_envs: int = 8, pose_seed: int = 100,
+                 n_el: int = 32, n_az: int = 1024) -> Scene:
+    """Closed indoor mesh (room + 200 primitives, marching cubes at spacing h)
+    with ``n_envs`` seeded free-space poses and a 32-beam spinning pattern
+    over -16..+15 deg x ``n_az`` azimuths; range [0.1, 120] m."""
+    sdf, v, t = indoor_mesh(seed, h)
+    poses = free_space_poses(sdf, n_envs, pose_seed)
+    dirs = lidar_pattern(n_el, -16.0, 15.0, n_az)
+    return Scene(f"indoor_h{h:g}", v, t, poses, dirs, 0.1, 120.0, n_az,
+                 {"sdf": sdf, "h": h, "seed": seed})
+
+
+# --------------------------------------------------------------------------
+# Outdoor terrain
+
+def _value_noise(rng, x, y, octaves=6, base_wavelength=50.0, amplitude=8.0):
+    """Fractal (fBm) value noise on a seeded lattice, smoothstep-interpolated."""
+    out = np.zeros_like(x)
+    amp, wl = amplitude, base_wavelength
+    for _ in range(octaves):
+        n = int(np.ceil(220.0 / wl)) + 3
+        lat = rng.uniform(-1.0, 1.0, size=(n, n))
+        gx, gy = (x + 10.0) / wl, (y + 10.0) / wl
+        ix, iy = np.floor(gx).astype(np.int64), np.floor(gy).astype(np.int64)
+        fx, fy = gx - ix, gy - iy
+        sx, sy = fx * fx * (3 - 2 * fx), fy * fy * (3 - 2 * fy)
+        a = lat[ix, iy]
+        b = lat[ix + 1, iy]
+        c = lat[ix, iy + 1]
+        d = lat[ix + 1, iy + 1]
+        out += amp * ((a * (1 - sx) + b * sx) * (1 - sy) + (c * (1 - sx) + d * sx) * sy)
+        amp *= 0.5
+        wl *= 0.5
+    return out
+
+
+def _box_mesh(center, half, yaw):
+    v, t = box_room(-np.asarray(half), np.asarray(half))
+    v = v.astype(np.float64)
+    c, s = math.cos(yaw), math.sin(yaw)
+    R = np.array([[c, -s, 0], [s, c, 0], [0, 0, 1.0]])
+    return (v @ R.T + center).astype(np.float32), t
+
+
+def terrain_scene(seed: int, n_tris_target: int, n_boxes: int = None, size: float = 200.0):
+    """Heightfield over [0, size]^2 with grid g = size * sqrt(2 / N) (so about
+    N triangles), fBm value noise (6 octaves, 50 m base wavelength, 8 m
+    amplitude), plus 50..500 boxes (extent 0.5..5 m, yaw uniform, sunk 0.2 m
+    into the ground).  Returns (verts, tris, heightfield sampler)."""
+    rng = np.random.default_rng(seed)
+    n_cells = max(2, int(round(math.sqrt(n_tris_target / 2.0))))
+    g = size / n_cells
+    xs = np.linspace(0.0, size, n_cells + 1)
+    X, Y = np.meshgrid(xs, xs, indexing="ij")
+    noise_rng = np.random.default_rng(seed + 7919)
+    Z = _value_noise(noise_rng, X, Y)
+    verts = np.stack([X, Y, Z], -1).reshape(-1, 3)
+    idx = np.arange((n_cells + 1) ** 2).reshape(n_cells + 1, n_cells + 1)
+    a, b = idx[:-1, :-1].ravel(), idx[1:, :-1].ravel()
+    c, d = idx[1:, 1:].ravel(), idx[:-1, 1:].ravel()
+    tris = np.concatenate([np.stack([a, b, c], -1), np.stack([a, c, d], -1)])
+    meshes = [(verts.astype(np.float32), tris.astype(np.int32))]
+
+    def height(px, py):
+        fx = np.clip(np.asarray(px) / g, 0, n_cells - 1e-9)
+        fy = np.clip(np.asarray(py) / g, 0, n_cells - 1e-9)
+        i, j = np.floor(fx).astype(int), np.floor(fy).astype(int)
+        u, v = fx - i, fy - j
+        z00, z10, z11, z01 = Z[i, j], Z[i + 1, j], Z[i + 1, j + 1], Z[i, j + 1]
+        # matches the (a,b,c) / (a,c,d) split: lower triangle when v <= u
+        lower = v <= u
+        zl = z00 + u * (z10 - z00) + v * (z11 - z10)
+        zu = z00 + v * (z01 - z00) + u * (z11 - z01)
+        return np.where(lower, zl, zu)
+
+    nb = n_boxes if n_boxes is not None else int(rng.integers(50, 501))
+    boxes = []
+    for _ in range(nb):
+        half = rng.uniform(0.25, 2.5, size=3)
+        cx, cy = rng.uniform(5.0, size - 5.0, size=2)
+        yaw = rng.uniform(0.0, 2.0 * math.pi)
+        cz = float(height(cx, cy)) + half[2] - 0.2
+        meshes.append(_box_mesh(np.array([cx, cy, cz]), half, yaw))
+        boxes.append((cx, cy, cz, *half, yaw))
+    v, t = concat_meshes(*meshes)
+    return v, t, height, np.array(boxes, np.float64).reshape(-1, 7)
+
+
+def terrain_poses(height, boxes, n: int, seed: int, size: float = 200.0):
+    """n poses 1.5..3 m above the terrain, outside every box, yaw uniform."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        x, y = rng.uniform(10.0, size - 10.0, size=2)
+        inside = False
+        for (cx, cy, cz, hx, hy, hz, yaw) in boxes:
+            c, s = math.cos(yaw), math.sin(yaw)
+            lx, ly = c * (x - cx) + s * (y - cy), -s * (x - cx) + c * (y - cy)
+            if abs(lx) < hx + 0.5 and abs(ly) < hy + 0.5:
+                inside = True
+                break
+        if inside:
+            continue
+        z = float(height(x, y)) + rng.uniform(1.5, 3.0)
+        out.append(yaw_pose((x, y, z), rng.uniform(0.0, 2.0 * math.pi)))
+    return np.ascontiguousarray(np.stack(out))
