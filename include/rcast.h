@@ -1,0 +1,189 @@
+/*
+ * rcast.h -- C ABI of librcast: batched LiDAR ray casting on one MI355X.
+ *
+ * The library implements the ray-casting stage of FGGS-LiDAR (Sec. IV-C):
+ * a triangle mesh M = {(v_k0, v_k1, v_k2)}, per-environment sensor poses
+ * T_s = [R_s | t_s] in SE(3) and a scan pattern of unit directions d_j go
+ * in; for every (environment, beam) the nearest intersection
+ *     t*_j = min_k eta(r_j, tri_k),  r_j(t) = t_s + t * R_s d_j,
+ * over t in [t_min, t_max] comes out, as a range image plus the index of
+ * the triangle hit.  The search runs over a linear BVH built on the GPU
+ * (Sec. IV-A "LBVH construction": Morton codes of the primitives inside the
+ * scene box, radix sort, hierarchy from longest common prefixes, bottom-up
+ * box reduction; Sec. IV-C reuses it for triangle boxes) and prunes every
+ * node whose entry distance exceeds the best hit so far.
+ *
+ * Conventions
+ *   - Every call returns rc_status; nothing throws across the ABI.  On
+ *     failure rc_last_error() gives a message for the calling thread.
+ *   - Pointers are DEVICE pointers unless a parameter says "host".
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is
+ *     stream-ordered: a call returns once the work is enqueued.
+ *   - Handles are small integers owned by the context.
+ *   - Scene and pattern calls on one context are serialised internally;
+ *     rc_raycast_batch may be called from several threads.
+ *   - Results: range in metres as float32, +INFINITY on a miss; hit id is
+ *     the triangle's index in the uploaded index array, -1 on a miss.  The
+ *     test is two-sided, [t_min, t_max] is closed, exact ties go to the
+ *     lowest triangle index, and zero-area triangles are never hit.
+ *   - Ray model: origin = translation column of the pose; direction =
+ *     normalize(R * b_j) (computed in FP64, then rounded to FP32).  Pose
+ *     layout: float32 [12], row-major [R | t] (3 rows of 4).
+ */
+#ifndef RCAST_H
+#define RCAST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rc_ctx rc_ctx;
+
+typedef enum {
+    RC_OK = 0,
+    RC_PENDING = 1,
+    RC_E_INVAL = -1,    /* bad argument, handle or input data             */
+    RC_E_NOMEM = -2,    /* device memory or the context's budget exhausted */
+    RC_E_NOTFOUND = -3, /* unknown handle or ticket                        */
+    RC_E_BUSY = -4,     /* resource in use                                 */
+    RC_E_DEVICE = -5,   /* a HIP runtime call failed                       */
+    RC_E_STATE = -6     /* call not valid in the current state (e.g. no BVH) */
+} rc_status;
+
+enum { RC_NODE_FP32 = 0, RC_NODE_Q8 = 1 };
+
+/* Message describing the last failing call made by this thread ("" if none).
+ * The pointer stays valid until the next call on the same thread. */
+const char *rc_last_error(void);
+
+/* Library version, for the binding to check it loaded the right file. */
+int32_t rc_version(void);
+
+/* Create a context on HIP device `device`.  `hbm_budget_bytes` caps the
+ * device memory the context may hold for scenes, patterns and internal
+ * buffers (0 = no cap beyond the device itself).  *out receives the handle.
+ * Errors: RC_E_INVAL (bad device or NULL out), RC_E_DEVICE. */
+rc_status rc_create(int device, uint64_t hbm_budget_bytes, rc_ctx **out);
+
+/* Wait for all work the context enqueued, then free everything it owns. */
+void rc_destroy(rc_ctx *ctx);
+
+/* Copy a triangle mesh (the mesh M of Sec. IV-C) into the context.
+ *   verts_xyz : float32 [n_verts][3]
+ *   tri_idx   : int32   [n_tris][3], indices into verts
+ *   src_is_device : 1 if both arrays are device pointers, 0 if host
+ * The caller keeps ownership of its arrays; the library copies them and
+ * validates indices (0 <= i < n_verts) and that every vertex is finite.
+ * n_tris may be 0 (every ray then misses).  The copy is complete when the
+ * call returns.  *out_scene receives the scene handle.
+ * Errors: RC_E_INVAL (bad sizes, index out of range, non-finite vertex),
+ * RC_E_NOMEM (budget), RC_E_DEVICE. */
+rc_status rc_scene_upload(rc_ctx *ctx, const float *verts_xyz, int64_t n_verts,
+                          const int32_t *tri_idx, int64_t n_tris,
+                          int src_is_device, void *stream, int32_t *out_scene);
+
+/* Options for rc_lbvh_build.  Zero-initialised means the defaults. */
+typedef struct {
+    int32_t morton_bits; /* bits per axis, 1..10 (0 = 10)                    */
+    int32_t node_format; /* RC_NODE_FP32 (binary nodes with FP32 child boxes)
+                            or RC_NODE_Q8 (8-bit quantised child boxes)       */
+    int32_t reserved[6];
+} rc_build_opts;
+
+/* Build (or rebuild) the BVH of `scene` on the GPU (Sec. IV-A LBVH
+ * construction, applied to triangle boxes as in Sec. IV-C).  Runs on
+ * `stream`; the BVH stays resident until the scene is released.  A later
+ * raycast on any stream must be ordered after this call's stream work.
+ * Errors: RC_E_NOTFOUND (scene), RC_E_INVAL (options), RC_E_NOMEM, RC_E_DEVICE. */
+rc_status rc_lbvh_build(rc_ctx *ctx, int32_t scene, const rc_build_opts *opts,
+                        void *stream);
+
+/* Drop a scene.  Waits for the device to finish outstanding work, then
+ * frees the scene's memory.  Errors: RC_E_NOTFOUND. */
+rc_status rc_scene_release(rc_ctx *ctx, int32_t scene);
+
+/* Copy a scan pattern (the unit directions d_j of Sec. IV-C) in.
+ *   dirs_xyz : HOST float32 [n_beams][3]; the library normalises each
+ *              direction after rotating it, so lengths need not be 1
+ *   n_az_hint: beams per elevation ring (0 if unknown); used to shape
+ *              coherent ray tiles
+ * Errors: RC_E_INVAL (n_beams < 1, non-finite or zero direction),
+ * RC_E_NOMEM, RC_E_DEVICE. */
+rc_status rc_pattern_upload(rc_ctx *ctx, const float *dirs_xyz, int32_t n_beams,
+                            int32_t n_az_hint, int32_t *out_pattern);
+
+/* One job of a batch: n_envs sensor poses against one scene and pattern.
+ * Its results occupy out[out_offset + e * n_beams + j]. */
+typedef struct {
+    int32_t scene;
+    int32_t pattern;
+    int32_t n_envs;
+    int32_t reserved0;
+    const float *poses_3x4; /* DEVICE float32 [n_envs][12], row-major [R|t] */
+    float t_min, t_max;     /* closed range interval, 0 <= t_min <= t_max   */
+    int64_t out_offset;
+} rc_job;
+
+/* Cast every ray of every job (Sec. IV-C nearest intersection, batched over
+ * environments and scenes in one launch).  out_range (float32) and out_hit
+ * (int32) are DEVICE arrays owned by the caller, large enough for every
+ * job's slice.  Stream-ordered on `stream`.
+ * Errors: RC_E_INVAL (bad job), RC_E_NOTFOUND (scene/pattern),
+ * RC_E_STATE (scene has no BVH), RC_E_DEVICE. */
+rc_status rc_raycast_batch(rc_ctx *ctx, const rc_job *jobs, int32_t n_jobs,
+                           float *out_range, int32_t *out_hit, void *stream);
+
+/* Same contract as rc_raycast_batch, but every ray is tested against every
+ * triangle (the naive O(N_r * N_tri) baseline of Sec. IV-C) with the same
+ * FP32 triangle test.  A GPU cross-check of the BVH path: for rays that
+ * are not near-ties its output is bit-identical to rc_raycast_batch. */
+rc_status rc_raycast_bruteforce(rc_ctx *ctx, const rc_job *jobs, int32_t n_jobs,
+                                float *out_range, int32_t *out_hit, void *stream);
+
+/* Instrumented traversal: like rc_raycast_batch, and additionally writes
+ * per-ray counts of BVH node records fetched (out_nodes) and triangles
+ * tested (out_tris), DEVICE int32 arrays laid out like out_range.  These
+ * are N_nodes(r_j) and K_j of the per-ray cost model of Sec. IV-C. */
+rc_status rc_raycast_stats(rc_ctx *ctx, const rc_job *jobs, int32_t n_jobs,
+                           float *out_range, int32_t *out_hit, int32_t *out_nodes,
+                           int32_t *out_tris, void *stream);
+
+/* Introspection of a built scene. */
+typedef struct {
+    int64_t n_verts, n_tris;
+    int64_t n_nodes;        /* internal nodes of the binary BVH            */
+    int32_t depth;          /* longest root-to-leaf path (edges)           */
+    int32_t node_format;
+    int32_t morton_bits;
+    int32_t has_bvh;
+    uint64_t device_bytes;  /* device memory held by the scene             */
+    float scene_lo[3], scene_hi[3];
+} rc_scene_info;
+
+rc_status rc_scene_get_info(rc_ctx *ctx, int32_t scene, rc_scene_info *out);
+
+/* Copy an internal array of a built scene to HOST memory (for tests of the
+ * build kernels).  `what`:
+ *   RC_DBG_MORTON   uint32 [n_tris]  Morton code of each triangle (input order)
+ *   RC_DBG_SORTED   uint32 [n_tris]  triangle index in leaf (sorted) order
+ *   RC_DBG_TOPOLOGY int32  [n_nodes][3]  left, right, parent of each internal
+ *                   node; children >= 0 are internal nodes, a child c < 0 is
+ *                   the leaf holding sorted triangle ~c; the root's parent is -1
+ *   RC_DBG_NODES    raw node records (format-dependent bytes)
+ *   RC_DBG_TRIS     raw triangle records (48 bytes each)
+ * `bytes` must equal the array's size.  Synchronises the device. */
+enum { RC_DBG_MORTON = 1, RC_DBG_SORTED = 2, RC_DBG_TOPOLOGY = 3,
+       RC_DBG_NODES = 4, RC_DBG_TRIS = 5 };
+rc_status rc_scene_debug_copy(rc_ctx *ctx, int32_t scene, int32_t what,
+                              void *host_dst, uint64_t bytes);
+
+/* Bytes the context currently holds on the device. */
+uint64_t rc_device_bytes(rc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RCAST_H */

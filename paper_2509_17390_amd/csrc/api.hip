@@ -1,0 +1,565 @@
+// api.hip -- the C ABI of librcast (see include/rcast.h).
+//
+// Host-side runtime: a context per device owns scene and pattern tables, the
+// LBVH build workspace and a ring of job-table slots (pinned staging buffer
+// + device buffer + completion event), so a batch call only enqueues one
+// small host-to-device copy and one traversal launch on the caller's stream.
+#include "rcast.h"
+#include "rc_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+rc_status fail(rc_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(RC_E_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                \
+    } while (0)
+
+struct Scene {
+    bool alive = false;
+    int64_t nv = 0, nt = 0;
+    float *verts = nullptr;
+    int32_t *tris = nullptr;
+    bool has_bvh = false;
+    int morton_bits = 10;
+    int node_format = RC_NODE_FP32;
+    uint32_t *morton = nullptr;
+    uint32_t *sorted = nullptr;
+    int32_t *topo = nullptr;
+    NodeRec *nodes = nullptr;
+    TriRec *trirecs = nullptr;
+    float *box_dev = nullptr;    // [8]: box (6) + depth (as int bits, 1) + pad
+    uint64_t bytes = 0;
+};
+
+struct Pattern {
+    bool alive = false;
+    float *dirs = nullptr;
+    int32_t n_beams = 0, n_az = 0;
+    uint64_t bytes = 0;
+};
+
+constexpr int kSlots = 8;
+
+struct JobSlot {
+    DevJob *host = nullptr;  // pinned
+    DevJob *dev = nullptr;
+    int cap = 0;
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
+
+}  // namespace
+
+struct rc_ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    std::mutex mu;        // scenes, patterns, workspace
+    std::mutex job_mu;    // job slots
+    std::vector<Scene> scenes;
+    std::vector<Pattern> patterns;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipEvent_t ws_event = nullptr;
+    bool ws_event_recorded = false;
+    JobSlot slots[kSlots];
+    int next_slot = 0;
+    int32_t *flags_dev = nullptr;
+};
+
+namespace {
+
+rc_status dev_alloc(rc_ctx *c, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (c->budget && c->used + bytes > c->budget)
+        return fail(RC_E_NOMEM, "device budget exceeded: %llu + %llu > %llu bytes",
+                    (unsigned long long)c->used, (unsigned long long)bytes,
+                    (unsigned long long)c->budget);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(RC_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    c->used += bytes;
+    return RC_OK;
+}
+
+void dev_free(rc_ctx *c, void *p, size_t bytes)
+{
+    if (!p) return;
+    if (bytes == 0) bytes = 256;
+    (void)hipFree(p);
+    c->used -= bytes;
+}
+
+size_t scene_bvh_bytes(int64_t nt)
+{
+    int64_t ni = nt > 1 ? nt - 1 : 1;
+    return sizeof(uint32_t) * nt * 2 + sizeof(int32_t) * 3 * ni + sizeof(NodeRec) * ni +
+           sizeof(TriRec) * nt;
+}
+
+void free_bvh(rc_ctx *c, Scene &s)
+{
+    int64_t nt = s.nt, ni = nt > 1 ? nt - 1 : 1;
+    dev_free(c, s.morton, sizeof(uint32_t) * nt);
+    dev_free(c, s.sorted, sizeof(uint32_t) * nt);
+    dev_free(c, s.topo, sizeof(int32_t) * 3 * ni);
+    dev_free(c, s.nodes, sizeof(NodeRec) * ni);
+    dev_free(c, s.trirecs, sizeof(TriRec) * nt);
+    s.morton = s.sorted = nullptr;
+    s.topo = nullptr;
+    s.nodes = nullptr;
+    s.trirecs = nullptr;
+    s.has_bvh = false;
+}
+
+void free_scene(rc_ctx *c, Scene &s)
+{
+    free_bvh(c, s);
+    dev_free(c, s.verts, sizeof(float) * 3 * s.nv);
+    dev_free(c, s.tris, sizeof(int32_t) * 3 * s.nt);
+    dev_free(c, s.box_dev, sizeof(float) * 8);
+    s = Scene();
+}
+
+Scene *get_scene(rc_ctx *c, int32_t id)
+{
+    if (id < 0 || id >= (int32_t)c->scenes.size() || !c->scenes[id].alive) return nullptr;
+    return &c->scenes[id];
+}
+
+Pattern *get_pattern(rc_ctx *c, int32_t id)
+{
+    if (id < 0 || id >= (int32_t)c->patterns.size() || !c->patterns[id].alive) return nullptr;
+    return &c->patterns[id];
+}
+
+// Build the device job table for a batch; shared by every trace entry point.
+rc_status prepare_jobs(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, std::vector<DevJob> &out,
+                       int64_t &total)
+{
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(RC_E_INVAL, "bad job list");
+    out.resize(n_jobs);
+    total = 0;
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (int i = 0; i < n_jobs; ++i) {
+        const rc_job &j = jobs[i];
+        Scene *s = get_scene(c, j.scene);
+        if (!s) return fail(RC_E_NOTFOUND, "job %d: unknown scene %d", i, j.scene);
+        Pattern *p = get_pattern(c, j.pattern);
+        if (!p) return fail(RC_E_NOTFOUND, "job %d: unknown pattern %d", i, j.pattern);
+        if (s->nt > 0 && !s->has_bvh)
+            return fail(RC_E_STATE, "job %d: scene %d has no BVH (call rc_lbvh_build)", i, j.scene);
+        if (j.n_envs < 0) return fail(RC_E_INVAL, "job %d: n_envs < 0", i);
+        if (j.n_envs > 0 && !j.poses_3x4) return fail(RC_E_INVAL, "job %d: poses is NULL", i);
+        if (!(j.t_min >= 0.0f) || !(j.t_max >= j.t_min) || !isfinite(j.t_min))
+            return fail(RC_E_INVAL, "job %d: need 0 <= t_min <= t_max", i);
+        if (j.out_offset < 0) return fail(RC_E_INVAL, "job %d: out_offset < 0", i);
+        int64_t nr = (int64_t)j.n_envs * p->n_beams;
+        if (nr > (int64_t)0x7fffffff) return fail(RC_E_INVAL, "job %d: more than 2^31-1 rays", i);
+        DevJob &d = out[i];
+        d.nodes = s->nodes;
+        d.tris = s->trirecs;
+        d.dirs = p->dirs;
+        d.poses = j.poses_3x4;
+        d.ray_begin = total;
+        d.n_rays = nr;
+        d.out_offset = j.out_offset;
+        d.n_beams = p->n_beams;
+        d.n_envs = j.n_envs;
+        d.n_tris = (int32_t)s->nt;
+        d.root_leaf = s->nt == 1 ? 1 : 0;
+        d.t_min = j.t_min;
+        d.t_max = j.t_max;
+        total += nr;
+    }
+    return RC_OK;
+}
+
+// Copy a job table into the next ring slot; returns the device pointer.
+rc_status stage_jobs(rc_ctx *c, const std::vector<DevJob> &dj, hipStream_t stream, DevJob **dev,
+                     JobSlot **slot_out)
+{
+    JobSlot &sl = c->slots[c->next_slot];
+    c->next_slot = (c->next_slot + 1) % kSlots;
+    if (sl.used) HIP_TRY(hipEventSynchronize(sl.done));
+    int need = (int)dj.size() > 0 ? (int)dj.size() : 1;
+    if (need > sl.cap) {
+        int cap = 64;
+        while (cap < need) cap *= 2;
+        if (sl.host) (void)hipHostFree(sl.host);
+        if (sl.dev) dev_free(c, sl.dev, sizeof(DevJob) * sl.cap);
+        sl.host = nullptr;
+        sl.dev = nullptr;
+        sl.cap = 0;
+        HIP_TRY(hipHostMalloc((void **)&sl.host, sizeof(DevJob) * cap, hipHostMallocDefault));
+        rc_status st = dev_alloc(c, (void **)&sl.dev, sizeof(DevJob) * cap);
+        if (st != RC_OK) return st;
+        sl.cap = cap;
+    }
+    memcpy(sl.host, dj.data(), sizeof(DevJob) * dj.size());
+    HIP_TRY(hipMemcpyAsync(sl.dev, sl.host, sizeof(DevJob) * dj.size(), hipMemcpyHostToDevice,
+                           stream));
+    *dev = sl.dev;
+    *slot_out = &sl;
+    return RC_OK;
+}
+
+rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, float *out_range,
+                       int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, void *stream)
+{
+    if (!c) return fail(RC_E_INVAL, "null context");
+    std::vector<DevJob> dj;
+    int64_t total = 0;
+    rc_status st = prepare_jobs(c, jobs, n_jobs, dj, total);
+    if (st != RC_OK) return st;
+    if (total == 0) return RC_OK;
+    if (!out_range || !out_hit) return fail(RC_E_INVAL, "null output");
+    if (mode == TRACE_STATS && (!out_nodes || !out_tris)) return fail(RC_E_INVAL, "null stats output");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(c->job_mu);
+    DevJob *djd = nullptr;
+    JobSlot *slot = nullptr;
+    st = stage_jobs(c, dj, s, &djd, &slot);
+    if (st != RC_OK) return st;
+    HIP_TRY(trace_launch(mode, djd, n_jobs, total, out_range, out_hit, out_nodes, out_tris, s));
+    HIP_TRY(hipEventRecord(slot->done, s));
+    slot->used = true;
+    return RC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rc_last_error(void) { return g_err.c_str(); }
+
+int32_t rc_version(void) { return 1; }
+
+rc_status rc_create(int device, uint64_t hbm_budget_bytes, rc_ctx **out)
+{
+    if (!out) return fail(RC_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(RC_E_INVAL, "device %d not in [0, %d)", device, n);
+    HIP_TRY(hipSetDevice(device));
+    rc_ctx *c = new rc_ctx();
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    hipError_t e = hipEventCreateWithFlags(&c->ws_event, hipEventDisableTiming);
+    for (int i = 0; e == hipSuccess && i < kSlots; ++i)
+        e = hipEventCreateWithFlags(&c->slots[i].done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->flags_dev, 256);
+    if (e != hipSuccess) {
+        rc_destroy(c);
+        return fail(RC_E_DEVICE, "context setup failed: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return RC_OK;
+}
+
+void rc_destroy(rc_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto &s : c->scenes)
+        if (s.alive) free_scene(c, s);
+    for (auto &p : c->patterns)
+        if (p.alive) dev_free(c, p.dirs, p.bytes);
+    for (auto &sl : c->slots) {
+        if (sl.host) (void)hipHostFree(sl.host);
+        if (sl.dev) dev_free(c, sl.dev, sizeof(DevJob) * sl.cap);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    if (c->ws) dev_free(c, c->ws, c->ws_bytes);
+    if (c->ws_event) (void)hipEventDestroy(c->ws_event);
+    if (c->flags_dev) (void)hipFree(c->flags_dev);
+    delete c;
+}
+
+rc_status rc_scene_upload(rc_ctx *c, const float *verts, int64_t nv, const int32_t *tris,
+                          int64_t nt, int src_is_device, void *stream, int32_t *out_scene)
+{
+    if (!c || !out_scene) return fail(RC_E_INVAL, "null context or out_scene");
+    if (nv < 0 || nt < 0) return fail(RC_E_INVAL, "negative sizes");
+    if (nt > 0x7ffffffeLL) return fail(RC_E_INVAL, "too many triangles (%lld)", (long long)nt);
+    if ((nv > 0 && !verts) || (nt > 0 && !tris)) return fail(RC_E_INVAL, "null mesh array");
+    if (nt > 0 && nv == 0) return fail(RC_E_INVAL, "triangles without vertices");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(c->mu);
+    Scene sc;
+    sc.nv = nv;
+    sc.nt = nt;
+    rc_status st = dev_alloc(c, (void **)&sc.verts, sizeof(float) * 3 * nv);
+    if (st == RC_OK) st = dev_alloc(c, (void **)&sc.tris, sizeof(int32_t) * 3 * nt);
+    if (st == RC_OK) st = dev_alloc(c, (void **)&sc.box_dev, sizeof(float) * 8);
+    if (st != RC_OK) {
+        free_scene(c, sc);
+        return st;
+    }
+    hipMemcpyKind kind = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipError_t e = hipSuccess;
+    if (nv) e = hipMemcpyAsync(sc.verts, verts, sizeof(float) * 3 * nv, kind, s);
+    if (e == hipSuccess && nt) e = hipMemcpyAsync(sc.tris, tris, sizeof(int32_t) * 3 * nt, kind, s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->flags_dev, 0, sizeof(int32_t), s);
+    if (e == hipSuccess) e = validate_mesh_launch(sc.verts, nv, sc.tris, nt, c->flags_dev, s);
+    int32_t flags = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&flags, c->flags_dev, sizeof(int32_t),
+                                            hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_scene(c, sc);
+        return fail(RC_E_DEVICE, "scene upload failed: %s", hipGetErrorString(e));
+    }
+    if (flags) {
+        free_scene(c, sc);
+        return fail(RC_E_INVAL, "invalid mesh:%s%s", (flags & 1) ? " index out of range" : "",
+                    (flags & 2) ? " non-finite vertex" : "");
+    }
+    sc.alive = true;
+    sc.bytes = sizeof(float) * 3 * nv + sizeof(int32_t) * 3 * nt;
+    int32_t id = -1;
+    for (size_t i = 0; i < c->scenes.size(); ++i)
+        if (!c->scenes[i].alive) { id = (int32_t)i; break; }
+    if (id < 0) {
+        id = (int32_t)c->scenes.size();
+        c->scenes.push_back(sc);
+    } else {
+        c->scenes[id] = sc;
+    }
+    *out_scene = id;
+    return RC_OK;
+}
+
+rc_status rc_lbvh_build(rc_ctx *c, int32_t scene, const rc_build_opts *opts, void *stream)
+{
+    if (!c) return fail(RC_E_INVAL, "null context");
+    int bits = 10, fmt = RC_NODE_FP32;
+    if (opts) {
+        if (opts->morton_bits) bits = opts->morton_bits;
+        fmt = opts->node_format;
+    }
+    if (bits < 1 || bits > 10) return fail(RC_E_INVAL, "morton_bits must be in 1..10");
+    if (fmt != RC_NODE_FP32) return fail(RC_E_INVAL, "node format %d not supported", fmt);
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(c->mu);
+    Scene *sc = get_scene(c, scene);
+    if (!sc) return fail(RC_E_NOTFOUND, "unknown scene %d", scene);
+    const int64_t nt = sc->nt, ni = nt > 1 ? nt - 1 : 1;
+    if (nt > 0 && !sc->nodes) {
+        rc_status st = dev_alloc(c, (void **)&sc->morton, sizeof(uint32_t) * nt);
+        if (st == RC_OK) st = dev_alloc(c, (void **)&sc->sorted, sizeof(uint32_t) * nt);
+        if (st == RC_OK) st = dev_alloc(c, (void **)&sc->topo, sizeof(int32_t) * 3 * ni);
+        if (st == RC_OK) st = dev_alloc(c, (void **)&sc->nodes, sizeof(NodeRec) * ni);
+        if (st == RC_OK) st = dev_alloc(c, (void **)&sc->trirecs, sizeof(TriRec) * nt);
+        if (st != RC_OK) {
+            free_bvh(c, *sc);
+            return st;
+        }
+        sc->bytes += scene_bvh_bytes(nt);
+    }
+    if (nt > 0) {
+        size_t need = lbvh_workspace_bytes(nt);
+        if (need > c->ws_bytes) {
+            if (c->ws) {
+                HIP_TRY(hipDeviceSynchronize());
+                dev_free(c, c->ws, c->ws_bytes);
+                c->ws = nullptr;
+                c->ws_bytes = 0;
+            }
+            rc_status st = dev_alloc(c, &c->ws, need);
+            if (st != RC_OK) return st;
+            c->ws_bytes = need;
+            c->ws_event_recorded = false;
+        }
+        if (c->ws_event_recorded) HIP_TRY(hipStreamWaitEvent(s, c->ws_event, 0));
+        BuildBuffers b;
+        b.verts = sc->verts;
+        b.tris = sc->tris;
+        b.nv = sc->nv;
+        b.nt = nt;
+        b.morton_bits = bits;
+        b.ws = c->ws;
+        b.ws_bytes = c->ws_bytes;
+        b.morton = sc->morton;
+        b.sorted = sc->sorted;
+        b.topo = sc->topo;
+        b.nodes = sc->nodes;
+        b.trirecs = sc->trirecs;
+        b.scene_box = sc->box_dev;
+        b.depth_out = reinterpret_cast<int32_t *>(sc->box_dev + 6);
+        HIP_TRY(lbvh_build_launch(b, s));
+        HIP_TRY(hipEventRecord(c->ws_event, s));
+        c->ws_event_recorded = true;
+    }
+    sc->has_bvh = true;
+    sc->morton_bits = bits;
+    sc->node_format = fmt;
+    return RC_OK;
+}
+
+rc_status rc_scene_release(rc_ctx *c, int32_t scene)
+{
+    if (!c) return fail(RC_E_INVAL, "null context");
+    HIP_TRY(hipSetDevice(c->device));
+    std::lock_guard<std::mutex> lk(c->mu);
+    Scene *sc = get_scene(c, scene);
+    if (!sc) return fail(RC_E_NOTFOUND, "unknown scene %d", scene);
+    HIP_TRY(hipDeviceSynchronize());
+    free_scene(c, *sc);
+    return RC_OK;
+}
+
+rc_status rc_pattern_upload(rc_ctx *c, const float *dirs, int32_t n_beams, int32_t n_az_hint,
+                            int32_t *out_pattern)
+{
+    if (!c || !out_pattern) return fail(RC_E_INVAL, "null context or out_pattern");
+    if (n_beams < 1 || !dirs) return fail(RC_E_INVAL, "need n_beams >= 1 and a direction array");
+    for (int32_t j = 0; j < n_beams; ++j) {
+        const float *d = dirs + 3 * (int64_t)j;
+        if (!isfinite(d[0]) || !isfinite(d[1]) || !isfinite(d[2]))
+            return fail(RC_E_INVAL, "beam %d is not finite", j);
+        if (d[0] == 0.0f && d[1] == 0.0f && d[2] == 0.0f)
+            return fail(RC_E_INVAL, "beam %d is the zero vector", j);
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    std::lock_guard<std::mutex> lk(c->mu);
+    Pattern p;
+    p.n_beams = n_beams;
+    p.n_az = n_az_hint > 0 ? n_az_hint : n_beams;
+    p.bytes = sizeof(float) * 3 * (size_t)n_beams;
+    rc_status st = dev_alloc(c, (void **)&p.dirs, p.bytes);
+    if (st != RC_OK) return st;
+    hipError_t e = hipMemcpy(p.dirs, dirs, p.bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        dev_free(c, p.dirs, p.bytes);
+        return fail(RC_E_DEVICE, "pattern copy failed: %s", hipGetErrorString(e));
+    }
+    p.alive = true;
+    int32_t id = -1;
+    for (size_t i = 0; i < c->patterns.size(); ++i)
+        if (!c->patterns[i].alive) { id = (int32_t)i; break; }
+    if (id < 0) {
+        id = (int32_t)c->patterns.size();
+        c->patterns.push_back(p);
+    } else {
+        c->patterns[id] = p;
+    }
+    *out_pattern = id;
+    return RC_OK;
+}
+
+rc_status rc_raycast_batch(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *out_range,
+                           int32_t *out_hit, void *stream)
+{
+    return trace_common(c, TRACE_BVH, jobs, n_jobs, out_range, out_hit, nullptr, nullptr, stream);
+}
+
+rc_status rc_raycast_bruteforce(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *out_range,
+                                int32_t *out_hit, void *stream)
+{
+    return trace_common(c, TRACE_BRUTE, jobs, n_jobs, out_range, out_hit, nullptr, nullptr,
+                        stream);
+}
+
+rc_status rc_raycast_stats(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *out_range,
+                           int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, void *stream)
+{
+    return trace_common(c, TRACE_STATS, jobs, n_jobs, out_range, out_hit, out_nodes, out_tris,
+                        stream);
+}
+
+rc_status rc_scene_get_info(rc_ctx *c, int32_t scene, rc_scene_info *out)
+{
+    if (!c || !out) return fail(RC_E_INVAL, "null argument");
+    HIP_TRY(hipSetDevice(c->device));
+    std::lock_guard<std::mutex> lk(c->mu);
+    Scene *sc = get_scene(c, scene);
+    if (!sc) return fail(RC_E_NOTFOUND, "unknown scene %d", scene);
+    memset(out, 0, sizeof *out);
+    out->n_verts = sc->nv;
+    out->n_tris = sc->nt;
+    out->n_nodes = sc->nt > 1 ? sc->nt - 1 : 0;
+    out->node_format = sc->node_format;
+    out->morton_bits = sc->morton_bits;
+    out->has_bvh = sc->has_bvh ? 1 : 0;
+    out->device_bytes = sc->bytes;
+    if (sc->has_bvh && sc->nt > 0) {
+        float hb[8];
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipMemcpy(hb, sc->box_dev, sizeof hb, hipMemcpyDeviceToHost));
+        for (int a = 0; a < 3; ++a) {
+            out->scene_lo[a] = hb[a];
+            out->scene_hi[a] = hb[3 + a];
+        }
+        int32_t depth;
+        memcpy(&depth, &hb[6], sizeof depth);
+        out->depth = depth;
+    }
+    return RC_OK;
+}
+
+rc_status rc_scene_debug_copy(rc_ctx *c, int32_t scene, int32_t what, void *dst, uint64_t bytes)
+{
+    if (!c || !dst) return fail(RC_E_INVAL, "null argument");
+    HIP_TRY(hipSetDevice(c->device));
+    std::lock_guard<std::mutex> lk(c->mu);
+    Scene *sc = get_scene(c, scene);
+    if (!sc) return fail(RC_E_NOTFOUND, "unknown scene %d", scene);
+    if (!sc->has_bvh) return fail(RC_E_STATE, "scene %d has no BVH", scene);
+    const int64_t nt = sc->nt, ni = nt > 1 ? nt - 1 : 0;
+    const void *src = nullptr;
+    uint64_t size = 0;
+    switch (what) {
+    case RC_DBG_MORTON: src = sc->morton; size = 4ull * nt; break;
+    case RC_DBG_SORTED: src = sc->sorted; size = 4ull * nt; break;
+    case RC_DBG_TOPOLOGY: src = sc->topo; size = 12ull * ni; break;
+    case RC_DBG_NODES: src = sc->nodes; size = sizeof(NodeRec) * (uint64_t)ni; break;
+    case RC_DBG_TRIS: src = sc->trirecs; size = sizeof(TriRec) * (uint64_t)nt; break;
+    default: return fail(RC_E_INVAL, "unknown debug array %d", what);
+    }
+    if (bytes != size)
+        return fail(RC_E_INVAL, "array %d holds %llu bytes, %llu requested", what,
+                    (unsigned long long)size, (unsigned long long)bytes);
+    if (size == 0) return RC_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(dst, src, size, hipMemcpyDeviceToHost));
+    return RC_OK;
+}
+
+uint64_t rc_device_bytes(rc_ctx *c) { return c ? c->used : 0; }
+
+}  // extern "C"

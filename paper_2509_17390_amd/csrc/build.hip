@@ -1,0 +1,467 @@
+// build.hip -- GPU linear BVH over triangle boxes (gfx950).
+//
+// FGGS-LiDAR Sec. IV-A "LBVH construction" (reused for triangles in
+// Sec. IV-C): every primitive centre is quantised inside the scene box,
+//   u_i = floor(2^b (c_i - o) / L),  m_i = Morton(u_i),
+// the primitives are radix-sorted by m_i, the hierarchy follows from the
+// longest common prefix of the sorted codes (Karras 2012: ties between equal
+// codes are broken by the index, so every internal node splits on a distinct
+// bit of the 3b + 32 bit augmented key), and node boxes are reduced bottom-up.
+//
+// Stages, one kernel each (radix sort: three per 8-bit digit):
+//   tri_bounds   triangle boxes + scene box (wave reduction, then atomics)
+//   morton       centre of the triangle box -> 3b-bit code
+//   radix sort   per-tile digit histogram / exclusive scan / stable scatter
+//                ranked in LDS with wave64 ballots
+//   karras       children and parent of every internal node
+//   refit        bottom-up: each leaf walks up; the second arrival at a node
+//                (agent-scope acquire/release counter) merges both child boxes
+//                into the parent's record; node heights give the tree depth
+//   tri_records  triangles reordered into leaf order (48-byte records)
+#include "rc_internal.h"
+
+#include <math.h>
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 8;
+constexpr int kTile = kBlock * kItems;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+__device__ __forceinline__ uint32_t f2o(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float o2f(uint32_t u)
+{
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_init_box(uint32_t *box)
+{
+    if (threadIdx.x < 3) box[threadIdx.x] = f2o(INFINITY);
+    else if (threadIdx.x < 6) box[threadIdx.x] = f2o(-INFINITY);
+}
+
+// triangle boxes (AoS lo.xyz hi.xyz) and their union
+__global__ __launch_bounds__(kBlock) void k_tri_bounds(const float *__restrict__ verts,
+                                                       const int32_t *__restrict__ tris,
+                                                       int64_t nt, float *__restrict__ bounds,
+                                                       uint32_t *__restrict__ box)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float lo[3] = {INFINITY, INFINITY, INFINITY};
+    float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (i < nt) {
+        for (int k = 0; k < 3; ++k) {
+            const float *v = verts + 3 * (int64_t)tris[3 * i + k];
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = fminf(lo[a], v[a]);
+                hi[a] = fmaxf(hi[a], v[a]);
+            }
+        }
+        float *b = bounds + 6 * i;
+        b[0] = lo[0]; b[1] = lo[1]; b[2] = lo[2];
+        b[3] = hi[0]; b[4] = hi[1]; b[5] = hi[2];
+    }
+    float r[6];
+    for (int a = 0; a < 3; ++a) {
+        r[a] = wave_min(lo[a]);
+        r[3 + a] = wave_max(hi[a]);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(box + a, f2o(r[a]));
+            atomicMax(box + 3 + a, f2o(r[3 + a]));
+        }
+    }
+}
+
+__global__ void k_box_to_float(const uint32_t *box, float *out)
+{
+    if (threadIdx.x < 6) out[threadIdx.x] = o2f(box[threadIdx.x]);
+}
+
+__device__ __forceinline__ uint32_t expand_bits(uint32_t v)
+{
+    // spread the low 10 bits of v so that bit k moves to bit 3k
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// Morton code of each triangle-box centre; x takes the most significant
+// position of every 3-bit group
+__global__ __launch_bounds__(kBlock) void k_morton(const float *__restrict__ bounds,
+                                                   const float *__restrict__ scene_box,
+                                                   int64_t nt, int bits,
+                                                   uint32_t *__restrict__ morton,
+                                                   uint32_t *__restrict__ keys,
+                                                   uint32_t *__restrict__ vals)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    const float *b = bounds + 6 * i;
+    const float cells = (float)(1u << bits);
+    uint32_t u[3];
+    for (int a = 0; a < 3; ++a) {
+        float o = scene_box[a];
+        float L = scene_box[3 + a] - o;
+        float scale = L > 0.0f ? cells / L : 0.0f;
+        float c = (b[a] + b[3 + a]) * 0.5f;
+        float q = floorf((c - o) * scale);
+        q = fminf(fmaxf(q, 0.0f), cells - 1.0f);
+        u[a] = (uint32_t)q;
+    }
+    uint32_t m = (expand_bits(u[0]) << 2) | (expand_bits(u[1]) << 1) | expand_bits(u[2]);
+    morton[i] = m;
+    keys[i] = m;
+    vals[i] = (uint32_t)i;
+}
+
+// ---- radix sort ------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_hist(const uint32_t *__restrict__ keys, int64_t n,
+                                                 int shift, uint32_t *__restrict__ hist,
+                                                 int nblocks)
+{
+    __shared__ uint32_t h[kRadix];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int r = 0; r < kItems; ++r) {
+        int64_t i = base + r * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of n counts in one block of 1024 threads
+__global__ __launch_bounds__(1024) void k_scan(uint32_t *__restrict__ data, int64_t n)
+{
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int64_t base = 0; base < n; base += 1024) {
+        int64_t i = base + threadIdx.x;
+        uint32_t v = i < n ? data[i] : 0u;
+        // inclusive wave scan
+        uint32_t x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        if (w == 0) {
+            uint32_t s = lane < 16 ? wsum[lane] : 0u;
+            for (int o = 1; o < 16; o <<= 1) {
+                uint32_t y = __shfl_up(s, o, 64);
+                if (lane >= o) s += y;
+            }
+            if (lane < 16) wsum[lane] = s;
+        }
+        __syncthreads();
+        uint32_t wave_off = w > 0 ? wsum[w - 1] : 0u;
+        uint32_t c = carry;
+        if (i < n) data[i] = c + wave_off + x - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = c + wave_off + x;
+        __syncthreads();
+    }
+}
+
+// stable scatter: tile order is (round, thread); ranks come from ballots
+__global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__ keys_in,
+                                                    const uint32_t *__restrict__ vals_in,
+                                                    uint32_t *__restrict__ keys_out,
+                                                    uint32_t *__restrict__ vals_out, int64_t n,
+                                                    int shift, const uint32_t *__restrict__ offs,
+                                                    int nblocks)
+{
+    __shared__ uint32_t base_of[kRadix];
+    __shared__ uint32_t running[kRadix];
+    __shared__ uint32_t wcount[kBlock / 64][kRadix];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    base_of[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    running[tid] = 0;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int r = 0; r < kItems; ++r) {
+        for (int j = tid; j < (kBlock / 64) * kRadix; j += kBlock) (&wcount[0][0])[j] = 0;
+        __syncthreads();
+        int64_t i = base + r * kBlock + tid;
+        bool valid = i < n;
+        uint32_t key = valid ? keys_in[i] : 0u;
+        uint32_t val = valid ? vals_in[i] : 0u;
+        uint32_t d = (key >> shift) & (kRadix - 1);
+        uint64_t peers = __ballot(valid);
+        for (int bit = 0; bit < kRadixBits; ++bit) {
+            bool set = (d >> bit) & 1u;
+            uint64_t m = __ballot(set);
+            peers &= set ? m : ~m;
+        }
+        uint32_t rank = __popcll(peers & lt);
+        if (valid && rank == 0) wcount[w][d] = __popcll(peers);
+        __syncthreads();
+        {
+            uint32_t run = running[tid];
+            for (int ww = 0; ww < kBlock / 64; ++ww) {
+                uint32_t c = wcount[ww][tid];
+                wcount[ww][tid] = run;
+                run += c;
+            }
+            running[tid] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base_of[d] + wcount[w][d] + rank;
+            keys_out[pos] = key;
+            vals_out[pos] = val;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- hierarchy -------------------------------------------------------------
+__device__ __forceinline__ int delta(const uint32_t *keys, int64_t n, int64_t i, int64_t j)
+{
+    if (j < 0 || j >= n) return -1;
+    uint32_t a = keys[i], b = keys[j];
+    if (a == b) return 32 + __clz((uint32_t)(i ^ j));
+    return __clz(a ^ b);
+}
+
+// Internal node i of the radix tree over sorted keys (Karras 2012, Sec. 4):
+// the direction of its range, the range end, then the split position.
+__global__ __launch_bounds__(kBlock) void k_karras(const uint32_t *__restrict__ keys, int64_t n,
+                                                   int32_t *__restrict__ topo,
+                                                   int32_t *__restrict__ leaf_parent,
+                                                   NodeRec *__restrict__ nodes)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    int d = (delta(keys, n, i, i + 1) - delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+    int dmin = delta(keys, n, i, i - d);
+    int64_t lmax = 2;
+    while (delta(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int64_t l = 0;
+    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+        if (delta(keys, n, i, i + (l + t) * d) > dmin) l += t;
+    int64_t j = i + l * d;
+    int dnode = delta(keys, n, i, j);
+    int64_t s = 0;
+    int64_t t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (delta(keys, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
+    int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+    int32_t left = (lo == gamma) ? ~(int32_t)gamma : (int32_t)gamma;
+    int32_t right = (hi == gamma + 1) ? ~(int32_t)(gamma + 1) : (int32_t)(gamma + 1);
+    topo[3 * i + 0] = left;
+    topo[3 * i + 1] = right;
+    if (left >= 0) topo[3 * left + 2] = (int32_t)i; else leaf_parent[~left] = (int32_t)i;
+    if (right >= 0) topo[3 * right + 2] = (int32_t)i; else leaf_parent[~right] = (int32_t)i;
+    if (i == 0) topo[2] = -1;
+    nodes[i].q3 = make_int4(left, right, 0, 0);
+}
+
+__device__ __forceinline__ void store_child_box(NodeRec *node, int slot, const float lo[3],
+                                                const float hi[3])
+{
+    float2 *q = reinterpret_cast<float2 *>(node);
+    // q0..q2 hold (L.lo, L.hi, R.lo, R.hi) per axis: float2 index 2*axis + slot
+    q[0 + slot] = make_float2(lo[0], hi[0]);
+    q[2 + slot] = make_float2(lo[1], hi[1]);
+    q[4 + slot] = make_float2(lo[2], hi[2]);
+}
+
+// bottom-up box reduction; one thread per leaf
+__global__ __launch_bounds__(kBlock) void k_refit(const float *__restrict__ bounds,
+                                                  const uint32_t *__restrict__ sorted, int64_t n,
+                                                  const int32_t *__restrict__ topo,
+                                                  const int32_t *__restrict__ leaf_parent,
+                                                  uint32_t *__restrict__ arrive,
+                                                  int32_t *__restrict__ height,
+                                                  NodeRec *nodes, int32_t *depth_out)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float *b = bounds + 6 * (int64_t)sorted[k];
+    float lo[3] = {b[0], b[1], b[2]};
+    float hi[3] = {b[3], b[4], b[5]};
+    int32_t child = ~(int32_t)k;
+    int32_t h = 0;
+    int32_t p = leaf_parent[k];
+    while (p >= 0) {
+        int slot = (topo[3 * p + 0] == child) ? 0 : 1;
+        store_child_box(nodes + p, slot, lo, hi);
+        if (slot == 0) height[2 * p + 0] = h; else height[2 * p + 1] = h;
+        // release our child box, acquire the sibling's
+        uint32_t prev = __hip_atomic_fetch_add(arrive + p, 1u, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == 0) return;  // first arrival: the sibling finishes the node
+        const NodeRec nr = nodes[p];
+        lo[0] = fminf(nr.q0.x, nr.q0.z); hi[0] = fmaxf(nr.q0.y, nr.q0.w);
+        lo[1] = fminf(nr.q1.x, nr.q1.z); hi[1] = fmaxf(nr.q1.y, nr.q1.w);
+        lo[2] = fminf(nr.q2.x, nr.q2.z); hi[2] = fmaxf(nr.q2.y, nr.q2.w);
+        int32_t h0 = height[2 * p + 0], h1 = height[2 * p + 1];
+        h = 1 + (h0 > h1 ? h0 : h1);
+        child = p;
+        p = topo[3 * p + 2];
+    }
+    depth_out[0] = h;  // only the thread that completes the root gets here
+}
+
+__global__ __launch_bounds__(kBlock) void k_tri_records(const float *__restrict__ verts,
+                                                        const int32_t *__restrict__ tris,
+                                                        const uint32_t *__restrict__ sorted,
+                                                        int64_t n, TriRec *__restrict__ out)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t t = sorted[k];
+    const float *a = verts + 3 * (int64_t)tris[3 * (int64_t)t + 0];
+    const float *b = verts + 3 * (int64_t)tris[3 * (int64_t)t + 1];
+    const float *c = verts + 3 * (int64_t)tris[3 * (int64_t)t + 2];
+    TriRec r;
+    r.a = make_float4(a[0], a[1], a[2], b[0]);
+    r.b = make_float4(b[1], b[2], c[0], c[1]);
+    r.c = make_float4(c[2], __int_as_float((int32_t)t), 0.0f, 0.0f);
+    out[k] = r;
+}
+
+__global__ void k_single_tri_depth(int32_t *depth_out) { depth_out[0] = 0; }
+
+__global__ __launch_bounds__(kBlock) void k_validate(const float *__restrict__ verts, int64_t nv,
+                                                     const int32_t *__restrict__ tris, int64_t nt,
+                                                     int32_t *flags)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int f = 0;
+    if (i < nt) {
+        for (int k = 0; k < 3; ++k) {
+            int32_t v = tris[3 * i + k];
+            if (v < 0 || v >= nv) f |= 1;
+        }
+    }
+    if (i < nv) {
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(verts[3 * i + a])) f |= 2;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+size_t lbvh_workspace_bytes(int64_t nt)
+{
+    int64_t nblocks = (nt + kTile - 1) / kTile;
+    if (nblocks < 1) nblocks = 1;
+    size_t s = 0;
+    s += align_up(sizeof(float) * 6 * (size_t)nt);       // bounds
+    s += 4 * align_up(sizeof(uint32_t) * (size_t)nt);     // keys/vals ping-pong
+    s += align_up(sizeof(uint32_t) * kRadix * (size_t)nblocks);  // histograms
+    s += align_up(sizeof(int32_t) * (size_t)nt);          // leaf parents
+    s += align_up(sizeof(uint32_t) * (size_t)nt);         // arrival counters
+    s += align_up(sizeof(int32_t) * 2 * (size_t)nt);      // child heights
+    s += align_up(sizeof(uint32_t) * 8);                  // scene box (ordered)
+    return s;
+}
+
+hipError_t validate_mesh_launch(const float *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                                int32_t *flags, hipStream_t s)
+{
+    int64_t n = nv > nt ? nv : nt;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, verts, nv, tris,
+                       nt, flags);
+    return hipGetLastError();
+}
+
+hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
+{
+    const int64_t n = b.nt;
+    if (n <= 0) return hipSuccess;
+    const int64_t nblocks = (n + kTile - 1) / kTile;
+    char *w = static_cast<char *>(b.ws);
+    auto take = [&](size_t bytes) {
+        char *p = w;
+        w += align_up(bytes);
+        return p;
+    };
+    float *bounds = reinterpret_cast<float *>(take(sizeof(float) * 6 * n));
+    uint32_t *keys0 = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * n));
+    uint32_t *keys1 = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * n));
+    uint32_t *vals0 = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * n));
+    uint32_t *vals1 = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * n));
+    uint32_t *hist = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * kRadix * nblocks));
+    int32_t *leaf_parent = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * n));
+    uint32_t *arrive = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * n));
+    int32_t *height = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * 2 * n));
+    uint32_t *obox = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * 8));
+    if ((size_t)(w - static_cast<char *>(b.ws)) > b.ws_bytes) return hipErrorInvalidValue;
+
+    hipLaunchKernelGGL(k_init_box, dim3(1), dim3(64), 0, s, obox);
+    hipLaunchKernelGGL(k_tri_bounds, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, b.verts,
+                       b.tris, n, bounds, obox);
+    hipLaunchKernelGGL(k_box_to_float, dim3(1), dim3(64), 0, s, obox, b.scene_box);
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, bounds,
+                       b.scene_box, n, b.morton_bits, b.morton, keys0, vals0);
+    const int key_bits = 3 * b.morton_bits;
+    uint32_t *kin = keys0, *kout = keys1, *vin = vals0, *vout = vals1;
+    for (int shift = 0; shift < key_bits; shift += kRadixBits) {
+        hipLaunchKernelGGL(k_hist, dim3((unsigned)nblocks), dim3(kBlock), 0, s, kin, n, shift,
+                           hist, (int)nblocks);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, (int64_t)kRadix * nblocks);
+        hipLaunchKernelGGL(k_scatter, dim3((unsigned)nblocks), dim3(kBlock), 0, s, kin, vin,
+                           kout, vout, n, shift, hist, (int)nblocks);
+        uint32_t *t = kin; kin = kout; kout = t;
+        t = vin; vin = vout; vout = t;
+    }
+    hipError_t e = hipMemcpyAsync(b.sorted, vin, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tri_records, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, b.verts,
+                       b.tris, b.sorted, n, b.trirecs);
+    if (n == 1) {
+        hipLaunchKernelGGL(k_single_tri_depth, dim3(1), dim3(1), 0, s, b.depth_out);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_karras, dim3(grid_for(n - 1, kBlock)), dim3(kBlock), 0, s, kin, n,
+                       b.topo, leaf_parent, b.nodes);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, arrive, n, 0u);
+    hipLaunchKernelGGL(k_refit, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, bounds, b.sorted,
+                       n, b.topo, leaf_parent, arrive, height, b.nodes, b.depth_out);
+    return hipGetLastError();
+}

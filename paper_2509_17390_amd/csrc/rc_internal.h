@@ -1,0 +1,83 @@
+// rc_internal.h -- shared declarations of librcast (device layouts, launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// ---------------------------------------------------------------------------
+// Device data layouts.
+//
+// Binary BVH node record, 64 bytes = 4 x float4, child boxes stored
+// coordinate-major so one float4 holds one axis of both children:
+//   q0 = (L.lo.x, L.hi.x, R.lo.x, R.hi.x)
+//   q1 = (L.lo.y, L.hi.y, R.lo.y, R.hi.y)
+//   q2 = (L.lo.z, L.hi.z, R.lo.z, R.hi.z)
+//   q3 = (ref L, ref R, -, -)   as int bits
+// A child reference c >= 0 is an internal node index; c < 0 is the leaf
+// holding triangle record ~c (leaf order).  Node 0 is the root.
+//
+// Triangle record, 48 bytes = 3 x float4, in leaf order:
+//   (v0.x v0.y v0.z v1.x) (v1.y v1.z v2.x v2.y) (v2.z id - -)
+// where id is the triangle's index in the uploaded mesh (int bits).
+struct NodeRec {
+    float4 q0, q1, q2;
+    int4 q3;
+};
+static_assert(sizeof(NodeRec) == 64, "node record is 64 bytes");
+
+struct TriRec {
+    float4 a, b, c;
+};
+static_assert(sizeof(TriRec) == 48, "triangle record is 48 bytes");
+
+// One job as the traversal kernels see it.
+struct DevJob {
+    const NodeRec *nodes;   // null when the scene has no triangle
+    const TriRec *tris;
+    const float *dirs;      // [n_beams][3]
+    const float *poses;     // [n_envs][12]
+    int64_t ray_begin;      // first flattened ray of this job in the launch
+    int64_t n_rays;         // n_envs * n_beams
+    int64_t out_offset;
+    int32_t n_beams;
+    int32_t n_envs;
+    int32_t n_tris;
+    int32_t root_leaf;      // 1 when the scene is a single triangle (no nodes)
+    float t_min, t_max;
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (implemented in build.hip / trace.hip).  All return hipError_t.
+
+struct BuildBuffers {
+    // inputs
+    const float *verts;      // [nv][3]
+    const int32_t *tris;     // [nt][3]
+    int64_t nv, nt;
+    int morton_bits;
+    // workspace (caller-sized via lbvh_workspace_bytes)
+    void *ws;
+    size_t ws_bytes;
+    // outputs (persistent per scene)
+    uint32_t *morton;        // [nt]    input order
+    uint32_t *sorted;        // [nt]    triangle index per leaf
+    int32_t *topo;           // [nt-1][3] left, right, parent
+    NodeRec *nodes;          // [max(nt-1,1)]
+    TriRec *trirecs;         // [nt]
+    float *scene_box;        // [6] lo xyz, hi xyz (device)
+    int32_t *depth_out;      // [1] device: tree depth
+};
+
+size_t lbvh_workspace_bytes(int64_t nt);
+hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s);
+
+// validation of uploaded meshes: writes flags[0] |= 1 (bad index),
+// |= 2 (non-finite vertex)
+hipError_t validate_mesh_launch(const float *verts, int64_t nv, const int32_t *tris,
+                                int64_t nt, int32_t *flags, hipStream_t s);
+
+enum TraceMode { TRACE_BVH = 0, TRACE_BRUTE = 1, TRACE_STATS = 2 };
+
+hipError_t trace_launch(int mode, const DevJob *jobs, int n_jobs, int64_t total_rays,
+                        float *out_range, int32_t *out_hit, int32_t *out_nodes,
+                        int32_t *out_tris, hipStream_t s);

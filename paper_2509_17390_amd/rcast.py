@@ -1,0 +1,272 @@
+"""Thin ctypes binding of librcast (include/rcast.h).
+
+Argument marshalling only: every step of the ray-casting path runs in the
+HIP library.  PyTorch supplies device memory and the current stream.  If
+the library has not been built, every entry point raises -- there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_lib", "librcast.so")
+
+RC_OK = 0
+RC_PENDING = 1
+RC_E_INVAL = -1
+RC_E_NOMEM = -2
+RC_E_NOTFOUND = -3
+RC_E_BUSY = -4
+RC_E_DEVICE = -5
+RC_E_STATE = -6
+
+RC_NODE_FP32 = 0
+RC_NODE_Q8 = 1
+
+RC_DBG_MORTON = 1
+RC_DBG_SORTED = 2
+RC_DBG_TOPOLOGY = 3
+RC_DBG_NODES = 4
+RC_DBG_TRIS = 5
+
+# every symbol include/rcast.h declares
+EXPORTED = [
+    "rc_last_error", "rc_version", "rc_create", "rc_destroy", "rc_scene_upload",
+    "rc_lbvh_build", "rc_scene_release", "rc_pattern_upload", "rc_raycast_batch",
+    "rc_raycast_bruteforce", "rc_raycast_stats", "rc_scene_get_info",
+    "rc_scene_debug_copy", "rc_device_bytes",
+]
+
+
+class RcastError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"rcast error {status}: {msg}")
+        self.status = status
+
+
+class rc_build_opts(ctypes.Structure):
+    _fields_ = [("morton_bits", ctypes.c_int32), ("node_format", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+class rc_job(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_int32), ("pattern", ctypes.c_int32),
+                ("n_envs", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("poses_3x4", ctypes.c_void_p), ("t_min", ctypes.c_float),
+                ("t_max", ctypes.c_float), ("out_offset", ctypes.c_int64)]
+
+
+class rc_scene_info(ctypes.Structure):
+    _fields_ = [("n_verts", ctypes.c_int64), ("n_tris", ctypes.c_int64),
+                ("n_nodes", ctypes.c_int64), ("depth", ctypes.c_int32),
+                ("node_format", ctypes.c_int32), ("morton_bits", ctypes.c_int32),
+                ("has_bvh", ctypes.c_int32), ("device_bytes", ctypes.c_uint64),
+                ("scene_lo", ctypes.c_float * 3), ("scene_hi", ctypes.c_float * 3)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load librcast.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2509_17390_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    S = ctypes.c_int
+    sig = {
+        "rc_last_error": ([], ctypes.c_char_p),
+        "rc_version": ([], I32),
+        "rc_create": ([ctypes.c_int, U64, ctypes.POINTER(P)], S),
+        "rc_destroy": ([P], None),
+        "rc_scene_upload": ([P, P, I64, P, I64, ctypes.c_int, P, ctypes.POINTER(I32)], S),
+        "rc_lbvh_build": ([P, I32, ctypes.POINTER(rc_build_opts), P], S),
+        "rc_scene_release": ([P, I32], S),
+        "rc_pattern_upload": ([P, P, I32, I32, ctypes.POINTER(I32)], S),
+        "rc_raycast_batch": ([P, ctypes.POINTER(rc_job), I32, P, P, P], S),
+        "rc_raycast_bruteforce": ([P, ctypes.POINTER(rc_job), I32, P, P, P], S),
+        "rc_raycast_stats": ([P, ctypes.POINTER(rc_job), I32, P, P, P, P, P], S),
+        "rc_scene_get_info": ([P, I32, ctypes.POINTER(rc_scene_info)], S),
+        "rc_scene_debug_copy": ([P, I32, I32, P, U64], S),
+        "rc_device_bytes": ([P], U64),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != RC_OK:
+        msg = load().rc_last_error()
+        raise RcastError(status, msg.decode() if msg else "")
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _ptr(x) -> int:
+    """Device pointer of a torch tensor (or host pointer of a numpy array)."""
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return int(x.data_ptr())
+
+
+@dataclasses.dataclass
+class Job:
+    scene: int
+    pattern: int
+    poses: object            # torch float32 cuda tensor [n_envs, 12]
+    t_min: float
+    t_max: float
+    out_offset: int = 0
+
+    @property
+    def n_envs(self) -> int:
+        return int(self.poses.shape[0])
+
+
+class Context:
+    """A librcast context on one device."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.rc_create(int(device), int(budget_bytes), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        self._n_beams = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().rc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover - best effort
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- scenes ---------------------------------------------------------------
+    def upload_scene(self, verts, tris, stream=None) -> int:
+        """verts [nv,3] float32, tris [nt,3] int32: numpy (host) or torch cuda."""
+        on_dev = not isinstance(verts, np.ndarray)
+        if on_dev:
+            assert verts.is_cuda and tris.is_cuda and verts.is_contiguous() and tris.is_contiguous()
+            nv, nt = int(verts.shape[0]), int(tris.shape[0])
+            vp, tp = _ptr(verts), _ptr(tris)
+            sp = _stream_ptr(stream)
+        else:
+            verts = np.ascontiguousarray(verts, np.float32).reshape(-1, 3)
+            tris = np.ascontiguousarray(tris, np.int32).reshape(-1, 3)
+            nv, nt = verts.shape[0], tris.shape[0]
+            vp, tp = verts.ctypes.data, tris.ctypes.data
+            sp = 0
+        out = ctypes.c_int32()
+        _check(load().rc_scene_upload(self._h, vp, nv, tp, nt, int(on_dev), sp, ctypes.byref(out)))
+        return out.value
+
+    def build(self, scene: int, morton_bits: int = 10, node_format: int = RC_NODE_FP32,
+              stream=None):
+        o = rc_build_opts(morton_bits, node_format)
+        _check(load().rc_lbvh_build(self._h, scene, ctypes.byref(o), _stream_ptr(stream)))
+
+    def release_scene(self, scene: int):
+        _check(load().rc_scene_release(self._h, scene))
+
+    def scene_info(self, scene: int) -> rc_scene_info:
+        info = rc_scene_info()
+        _check(load().rc_scene_get_info(self._h, scene, ctypes.byref(info)))
+        return info
+
+    def debug_copy(self, scene: int, what: int) -> np.ndarray:
+        info = self.scene_info(scene)
+        nt, ni = info.n_tris, info.n_nodes
+        if what == RC_DBG_MORTON or what == RC_DBG_SORTED:
+            a = np.empty(nt, np.uint32)
+        elif what == RC_DBG_TOPOLOGY:
+            a = np.empty((ni, 3), np.int32)
+        elif what == RC_DBG_NODES:
+            a = np.empty((ni, 16), np.float32)
+        elif what == RC_DBG_TRIS:
+            a = np.empty((nt, 12), np.float32)
+        else:
+            raise ValueError(what)
+        _check(load().rc_scene_debug_copy(self._h, scene, what, a.ctypes.data, a.nbytes))
+        return a
+
+    def device_bytes(self) -> int:
+        return int(load().rc_device_bytes(self._h))
+
+    # -- patterns ------------------------------------------------------------
+    def upload_pattern(self, dirs, n_az: int = 0) -> int:
+        d = np.ascontiguousarray(dirs, np.float32).reshape(-1, 3)
+        out = ctypes.c_int32()
+        _check(load().rc_pattern_upload(self._h, d.ctypes.data, d.shape[0], int(n_az),
+                                        ctypes.byref(out)))
+        self._n_beams[out.value] = d.shape[0]
+        return out.value
+
+    def n_beams(self, pattern: int) -> int:
+        return self._n_beams[pattern]
+
+    # -- ray casting ---------------------------------------------------------
+    @staticmethod
+    def _jobs(jobs: Sequence[Job]):
+        arr = (rc_job * max(1, len(jobs)))()
+        for i, j in enumerate(jobs):
+            assert j.poses.is_cuda and j.poses.is_contiguous()
+            arr[i] = rc_job(int(j.scene), int(j.pattern), j.n_envs, 0, _ptr(j.poses),
+                            float(j.t_min), float(j.t_max), int(j.out_offset))
+        return arr
+
+    def raycast(self, jobs: Sequence[Job], out_range, out_hit, stream=None, mode: str = "bvh",
+                out_nodes=None, out_tris=None):
+        arr = self._jobs(jobs)
+        lib = load()
+        sp = _stream_ptr(stream)
+        if mode == "bvh":
+            _check(lib.rc_raycast_batch(self._h, arr, len(jobs), _ptr(out_range), _ptr(out_hit), sp))
+        elif mode == "brute":
+            _check(lib.rc_raycast_bruteforce(self._h, arr, len(jobs), _ptr(out_range),
+                                             _ptr(out_hit), sp))
+        elif mode == "stats":
+            _check(lib.rc_raycast_stats(self._h, arr, len(jobs), _ptr(out_range), _ptr(out_hit),
+                                        _ptr(out_nodes), _ptr(out_tris), sp))
+        else:
+            raise ValueError(mode)
+
+    def total_rays(self, jobs: Sequence[Job]) -> int:
+        return max((j.out_offset + j.n_envs * self.n_beams(j.pattern) for j in jobs), default=0)
+
+    def cast(self, jobs: Sequence[Job], mode: str = "bvh", stream=None):
+        """Allocate outputs, cast, and return (range, hit) torch tensors."""
+        import torch
+        n = self.total_rays(jobs)
+        dev = torch.device("cuda", self.device)
+        rng = torch.empty(n, dtype=torch.float32, device=dev)
+        hit = torch.empty(n, dtype=torch.int32, device=dev)
+        if mode == "stats":
+            nodes = torch.empty(n, dtype=torch.int32, device=dev)
+            tris = torch.empty(n, dtype=torch.int32, device=dev)
+            self.raycast(jobs, rng, hit, stream, mode, nodes, tris)
+            return rng, hit, nodes, tris
+        self.raycast(jobs, rng, hit, stream, mode)
+        return rng, hit
