@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--h", type=float, default=0.035, help="marching-cubes spacing (m)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -156,6 +158,15 @@ def main():
     ms_step = dt * 1e3 / args.steps
     trace_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     log(f"step {ms_step:.2f} ms, traversal {trace_ms:.2f} ms")
+
+    if args.calib_copy:
+        # a plain copy of known size: 1 GiB read + 1 GiB written, so byte
+        # counters of the traversal kernel can be scaled to bytes
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # instrumented pass (untimed): node records fetched and triangles tested
     n_nodes = torch.empty(n_rays, dtype=torch.int32, device=dev)
