@@ -182,6 +182,42 @@ rc_status rc_scene_debug_copy(rc_ctx *ctx, int32_t scene, int32_t what,
 /* Bytes the context currently holds on the device. */
 uint64_t rc_device_bytes(rc_ctx *ctx);
 
+/* Launch shape of the traversal.  Every setting gives bit-identical results
+ * (the closest hit is the lexicographic minimum of (t, triangle id) and box
+ * culling is conservative); they only change speed.
+ *   persistent    1: persistent waves that take rays from per-XCD work
+ *                 queues and refill idle lanes by wavefront ballot;
+ *                 0: one ray per thread, one launch-wide grid (default)
+ *   stack_lds     traversal-stack entries per lane kept in LDS (deeper
+ *                 entries spill to scratch): 8, 16 or 24 for the persistent
+ *                 kernel; 0, 8 (default) or 16 otherwise
+ *   refill_min    a persistent wave refills once this many of its 64 lanes
+ *                 are idle (1..64, default 64)
+ *   blocks_per_cu persistent grid = CUs x this (0 = occupancy limit)
+ *   tile_az/el    packet tile: consecutive rays of an environment cover a
+ *                 tile_az x tile_el block of (azimuth, elevation) beams; used
+ *                 for a job when tile_az divides the pattern's n_az hint and
+ *                 tile_el its ring count; 0 = plain beam order (default
+ *                 16 x 4) */
+typedef struct {
+    int32_t persistent;
+    int32_t stack_lds;
+    int32_t refill_min;
+    int32_t blocks_per_cu;
+    int32_t tile_az;
+    int32_t tile_el;
+    int32_t chunk_max;     /* largest ray chunk a persistent wave claims per
+                              atomic (64..2^20; 0 = 4096); chunks shrink as
+                              the queue empties */
+    int32_t waves_cap;     /* 1 (default): one-ray-per-thread kernel compiled
+                              for at most 64 VGPRs (8 waves per SIMD) */
+} rc_tuning;
+
+/* Set (NULL: reset to defaults) or read the context's traversal tuning.
+ * Applies to launches enqueued after the call.  Errors: RC_E_INVAL. */
+rc_status rc_set_tuning(rc_ctx *ctx, const rc_tuning *tuning);
+rc_status rc_get_tuning(rc_ctx *ctx, rc_tuning *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,8 +65,9 @@ struct Pattern {
 
 constexpr int kSlots = 8;
 
+// A slot holds one launch's job table followed by its work queues.
 struct JobSlot {
-    DevJob *host = nullptr;  // pinned
+    DevJob *host = nullptr;  // pinned: DevJob[cap] then WorkQueues
     DevJob *dev = nullptr;
     int cap = 0;
     hipEvent_t done = nullptr;
@@ -90,6 +91,7 @@ struct rc_ctx {
     JobSlot slots[kSlots];
     int next_slot = 0;
     int32_t *flags_dev = nullptr;
+    rc_tuning tuning{};
 };
 
 namespace {
@@ -162,9 +164,40 @@ Pattern *get_pattern(rc_ctx *c, int32_t id)
     return &c->patterns[id];
 }
 
+// Packet tile of a job: the tuned tile when it divides the pattern, else
+// one elevation ring at a time (plain beam order).
+void pick_tile(const rc_tuning &t, int32_t n_beams, int32_t n_az, DevJob &d)
+{
+    if (n_az < 1 || n_beams % n_az != 0) n_az = n_beams;
+    const int32_t n_el = n_beams / n_az;
+    d.n_az = n_az;
+    d.tile_az = n_az;
+    d.tile_el = 1;
+    d.pad = 0;
+    if (t.tile_az > 0 && t.tile_el > 0 && n_az % t.tile_az == 0 && n_el % t.tile_el == 0) {
+        d.tile_az = t.tile_az;
+        d.tile_el = t.tile_el;
+    }
+}
+
+rc_tuning default_tuning()
+{
+    rc_tuning t;
+    memset(&t, 0, sizeof t);
+    t.persistent = 0;
+    t.stack_lds = 8;
+    t.refill_min = 64;
+    t.blocks_per_cu = 0;
+    t.tile_az = 16;
+    t.tile_el = 4;
+    t.chunk_max = 4096;
+    t.waves_cap = 1;
+    return t;
+}
+
 // Build the device job table for a batch; shared by every trace entry point.
-rc_status prepare_jobs(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, std::vector<DevJob> &out,
-                       int64_t &total)
+rc_status prepare_jobs(rc_ctx *c, const rc_tuning &tuning, const rc_job *jobs, int32_t n_jobs,
+                       std::vector<DevJob> &out, int64_t &total)
 {
     if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(RC_E_INVAL, "bad job list");
     out.resize(n_jobs);
@@ -199,14 +232,17 @@ rc_status prepare_jobs(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, std::vecto
         d.root_leaf = s->nt == 1 ? 1 : 0;
         d.t_min = j.t_min;
         d.t_max = j.t_max;
+        pick_tile(tuning, p->n_beams, p->n_az, d);
         total += nr;
     }
     return RC_OK;
 }
 
 // Copy a job table into the next ring slot; returns the device pointer.
-rc_status stage_jobs(rc_ctx *c, const std::vector<DevJob> &dj, hipStream_t stream, DevJob **dev,
-                     JobSlot **slot_out)
+size_t slot_bytes(int cap) { return sizeof(DevJob) * cap + sizeof(WorkQueues); }
+
+rc_status stage_jobs(rc_ctx *c, const std::vector<DevJob> &dj, int64_t total, hipStream_t stream,
+                     DevJob **dev, WorkQueues **queues, JobSlot **slot_out)
 {
     JobSlot &sl = c->slots[c->next_slot];
     c->next_slot = (c->next_slot + 1) % kSlots;
@@ -216,19 +252,24 @@ rc_status stage_jobs(rc_ctx *c, const std::vector<DevJob> &dj, hipStream_t strea
         int cap = 64;
         while (cap < need) cap *= 2;
         if (sl.host) (void)hipHostFree(sl.host);
-        if (sl.dev) dev_free(c, sl.dev, sizeof(DevJob) * sl.cap);
+        if (sl.dev) dev_free(c, sl.dev, slot_bytes(sl.cap));
         sl.host = nullptr;
         sl.dev = nullptr;
         sl.cap = 0;
-        HIP_TRY(hipHostMalloc((void **)&sl.host, sizeof(DevJob) * cap, hipHostMallocDefault));
-        rc_status st = dev_alloc(c, (void **)&sl.dev, sizeof(DevJob) * cap);
+        HIP_TRY(hipHostMalloc((void **)&sl.host, slot_bytes(cap), hipHostMallocDefault));
+        rc_status st = dev_alloc(c, (void **)&sl.dev, slot_bytes(cap));
         if (st != RC_OK) return st;
         sl.cap = cap;
     }
     memcpy(sl.host, dj.data(), sizeof(DevJob) * dj.size());
+    WorkQueues *hq = reinterpret_cast<WorkQueues *>(sl.host + sl.cap);
+    init_queues(*hq, total);
     HIP_TRY(hipMemcpyAsync(sl.dev, sl.host, sizeof(DevJob) * dj.size(), hipMemcpyHostToDevice,
                            stream));
+    WorkQueues *dq = reinterpret_cast<WorkQueues *>(sl.dev + sl.cap);
+    HIP_TRY(hipMemcpyAsync(dq, hq, sizeof(WorkQueues), hipMemcpyHostToDevice, stream));
     *dev = sl.dev;
+    *queues = dq;
     *slot_out = &sl;
     return RC_OK;
 }
@@ -237,9 +278,14 @@ rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, 
                        int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, void *stream)
 {
     if (!c) return fail(RC_E_INVAL, "null context");
+    rc_tuning tuning;
+    {
+        std::lock_guard<std::mutex> lk(c->job_mu);
+        tuning = c->tuning;
+    }
     std::vector<DevJob> dj;
     int64_t total = 0;
-    rc_status st = prepare_jobs(c, jobs, n_jobs, dj, total);
+    rc_status st = prepare_jobs(c, tuning, jobs, n_jobs, dj, total);
     if (st != RC_OK) return st;
     if (total == 0) return RC_OK;
     if (!out_range || !out_hit) return fail(RC_E_INVAL, "null output");
@@ -248,10 +294,19 @@ rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(c->job_mu);
     DevJob *djd = nullptr;
+    WorkQueues *dq = nullptr;
     JobSlot *slot = nullptr;
-    st = stage_jobs(c, dj, s, &djd, &slot);
+    st = stage_jobs(c, dj, total, s, &djd, &dq, &slot);
     if (st != RC_OK) return st;
-    HIP_TRY(trace_launch(mode, djd, n_jobs, total, out_range, out_hit, out_nodes, out_tris, s));
+    TraceConfig cfg;
+    cfg.persistent = tuning.persistent;
+    cfg.stack_lds = tuning.stack_lds;
+    cfg.refill_min = tuning.refill_min;
+    cfg.blocks_per_cu = tuning.blocks_per_cu;
+    cfg.chunk_max = tuning.chunk_max;
+    cfg.waves_cap = tuning.waves_cap;
+    HIP_TRY(trace_launch(mode, cfg, djd, n_jobs, dq, total, out_range, out_hit, out_nodes,
+                         out_tris, s));
     HIP_TRY(hipEventRecord(slot->done, s));
     slot->used = true;
     return RC_OK;
@@ -276,6 +331,7 @@ rc_status rc_create(int device, uint64_t hbm_budget_bytes, rc_ctx **out)
     rc_ctx *c = new rc_ctx();
     c->device = device;
     c->budget = hbm_budget_bytes;
+    c->tuning = default_tuning();
     hipError_t e = hipEventCreateWithFlags(&c->ws_event, hipEventDisableTiming);
     for (int i = 0; e == hipSuccess && i < kSlots; ++i)
         e = hipEventCreateWithFlags(&c->slots[i].done, hipEventDisableTiming);
@@ -299,7 +355,7 @@ void rc_destroy(rc_ctx *c)
         if (p.alive) dev_free(c, p.dirs, p.bytes);
     for (auto &sl : c->slots) {
         if (sl.host) (void)hipHostFree(sl.host);
-        if (sl.dev) dev_free(c, sl.dev, sizeof(DevJob) * sl.cap);
+        if (sl.dev) dev_free(c, sl.dev, slot_bytes(sl.cap));
         if (sl.done) (void)hipEventDestroy(sl.done);
     }
     if (c->ws) dev_free(c, c->ws, c->ws_bytes);
@@ -561,5 +617,38 @@ rc_status rc_scene_debug_copy(rc_ctx *c, int32_t scene, int32_t what, void *dst,
 }
 
 uint64_t rc_device_bytes(rc_ctx *c) { return c ? c->used : 0; }
+
+rc_status rc_set_tuning(rc_ctx *c, const rc_tuning *t)
+{
+    if (!c) return fail(RC_E_INVAL, "null context");
+    if (!t) {
+        std::lock_guard<std::mutex> lk(c->job_mu);
+        c->tuning = default_tuning();
+        return RC_OK;
+    }
+    if (t->persistent != 0 && t->persistent != 1) return fail(RC_E_INVAL, "persistent must be 0 or 1");
+    if (t->persistent && t->stack_lds != 8 && t->stack_lds != 16 && t->stack_lds != 24)
+        return fail(RC_E_INVAL, "persistent traversal needs stack_lds in {8, 16, 24}");
+    if (!t->persistent && t->stack_lds != 0 && t->stack_lds != 8 && t->stack_lds != 16)
+        return fail(RC_E_INVAL, "one-ray-per-thread traversal needs stack_lds in {0, 8, 16}");
+    if (t->chunk_max != 0 && (t->chunk_max < 64 || t->chunk_max > (1 << 20)))
+        return fail(RC_E_INVAL, "chunk_max must be 0 or 64..2^20");
+    if (t->waves_cap != 0 && t->waves_cap != 1) return fail(RC_E_INVAL, "waves_cap must be 0 or 1");
+    if (t->refill_min < 1 || t->refill_min > 64) return fail(RC_E_INVAL, "refill_min must be 1..64");
+    if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return fail(RC_E_INVAL, "blocks_per_cu must be 0..64");
+    if (t->tile_az < 0 || t->tile_el < 0 || (int64_t)t->tile_az * t->tile_el > (1 << 20))
+        return fail(RC_E_INVAL, "bad tile shape");
+    std::lock_guard<std::mutex> lk(c->job_mu);
+    c->tuning = *t;
+    return RC_OK;
+}
+
+rc_status rc_get_tuning(rc_ctx *c, rc_tuning *t)
+{
+    if (!c || !t) return fail(RC_E_INVAL, "null argument");
+    std::lock_guard<std::mutex> lk(c->job_mu);
+    *t = c->tuning;
+    return RC_OK;
+}
 
 }  // extern "C"

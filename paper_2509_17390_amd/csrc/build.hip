@@ -11,12 +11,13 @@
 // Stages, one kernel each (radix sort: three per 8-bit digit):
 //   tri_bounds   triangle boxes + scene box (wave reduction, then atomics)
 //   morton       centre of the triangle box -> 3b-bit code
-//   radix sort   per-tile digit histogram / exclusive scan / stable scatter
-//                ranked in LDS with wave64 ballots
+//   radix sort   per-tile digit histogram / per-digit scan of tile counts /
+//                stable scatter ranked in LDS with wave64 ballots
 //   karras       children and parent of every internal node
 //   refit        bottom-up: each leaf walks up; the second arrival at a node
-//                (agent-scope acquire/release counter) merges both child boxes
-//                into the parent's record; node heights give the tree depth
+//                merges both child boxes into the parent's record (LDS
+//                counters inside a block's leaf chunk, agent-scope counters
+//                across chunks); node heights give the tree depth
 //   tri_records  triangles reordered into leaf order (48-byte records)
 #include "rc_internal.h"
 
@@ -63,16 +64,19 @@ __global__ void k_init_box(uint32_t *box)
     else if (threadIdx.x < 6) box[threadIdx.x] = f2o(-INFINITY);
 }
 
-// triangle boxes (AoS lo.xyz hi.xyz) and their union
+// triangle boxes (AoS lo.xyz hi.xyz) and their union: grid-stride loop,
+// wave then block reduction, one set of atomics per block
 __global__ __launch_bounds__(kBlock) void k_tri_bounds(const float *__restrict__ verts,
                                                        const int32_t *__restrict__ tris,
                                                        int64_t nt, float *__restrict__ bounds,
                                                        uint32_t *__restrict__ box)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    float lo[3] = {INFINITY, INFINITY, INFINITY};
-    float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    if (i < nt) {
+    __shared__ float red[kBlock / 64][6];
+    float acc[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nt;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float lo[3] = {INFINITY, INFINITY, INFINITY};
+        float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (int k = 0; k < 3; ++k) {
             const float *v = verts + 3 * (int64_t)tris[3 * i + k];
             for (int a = 0; a < 3; ++a) {
@@ -83,17 +87,24 @@ __global__ __launch_bounds__(kBlock) void k_tri_bounds(const float *__restrict__
         float *b = bounds + 6 * i;
         b[0] = lo[0]; b[1] = lo[1]; b[2] = lo[2];
         b[3] = hi[0]; b[4] = hi[1]; b[5] = hi[2];
-    }
-    float r[6];
-    for (int a = 0; a < 3; ++a) {
-        r[a] = wave_min(lo[a]);
-        r[3 + a] = wave_max(hi[a]);
-    }
-    if ((threadIdx.x & 63) == 0) {
         for (int a = 0; a < 3; ++a) {
-            atomicMin(box + a, f2o(r[a]));
-            atomicMax(box + 3 + a, f2o(r[3 + a]));
+            acc[a] = fminf(acc[a], lo[a]);
+            acc[3 + a] = fmaxf(acc[3 + a], hi[a]);
         }
+    }
+    for (int a = 0; a < 3; ++a) {
+        acc[a] = wave_min(acc[a]);
+        acc[3 + a] = wave_max(acc[3 + a]);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 6; ++a) red[w][a] = acc[a];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int a = threadIdx.x;
+        float v = red[0][a];
+        for (int ww = 1; ww < kBlock / 64; ++ww) v = a < 3 ? fminf(v, red[ww][a]) : fmaxf(v, red[ww][a]);
+        if (a < 3) atomicMin(box + a, f2o(v)); else atomicMax(box + a, f2o(v));
     }
 }
 
@@ -159,41 +170,45 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint32_t *__restrict__ ke
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// exclusive scan of n counts in one block of 1024 threads
-__global__ __launch_bounds__(1024) void k_scan(uint32_t *__restrict__ data, int64_t n)
+// block-wide exclusive scan of one value per thread (kBlock threads);
+// returns the exclusive prefix, *total receives the block sum
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *total)
 {
-    __shared__ uint32_t wsum[16];
-    __shared__ uint32_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
+    __shared__ uint32_t wsum[kBlock / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int64_t base = 0; base < n; base += 1024) {
-        int64_t i = base + threadIdx.x;
-        uint32_t v = i < n ? data[i] : 0u;
-        // inclusive wave scan
-        uint32_t x = v;
-        for (int o = 1; o < 64; o <<= 1) {
-            uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) wsum[w] = x;
-        __syncthreads();
-        if (w == 0) {
-            uint32_t s = lane < 16 ? wsum[lane] : 0u;
-            for (int o = 1; o < 16; o <<= 1) {
-                uint32_t y = __shfl_up(s, o, 64);
-                if (lane >= o) s += y;
-            }
-            if (lane < 16) wsum[lane] = s;
-        }
-        __syncthreads();
-        uint32_t wave_off = w > 0 ? wsum[w - 1] : 0u;
-        uint32_t c = carry;
-        if (i < n) data[i] = c + wave_off + x - v;
-        __syncthreads();
-        if (threadIdx.x == 1023) carry = c + wave_off + x;
-        __syncthreads();
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
     }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int ww = 0; ww < kBlock / 64; ++ww) {
+        if (ww < w) off += wsum[ww];
+        tot += wsum[ww];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+// one block per digit: exclusive scan of that digit's per-tile counts
+// (in place) and the digit's total
+__global__ __launch_bounds__(kBlock) void k_scan_digits(uint32_t *__restrict__ hist, int nblocks,
+                                                        uint32_t *__restrict__ digit_tot)
+{
+    uint32_t *h = hist + (int64_t)blockIdx.x * nblocks;
+    uint32_t carry = 0;
+    for (int base = 0; base < nblocks; base += kBlock) {
+        const int i = base + threadIdx.x;
+        const uint32_t v = i < nblocks ? h[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(v, &tot);
+        if (i < nblocks) h[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
 // stable scatter: tile order is (round, thread); ranks come from ballots
@@ -202,13 +217,18 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t *__restrict__
                                                     uint32_t *__restrict__ keys_out,
                                                     uint32_t *__restrict__ vals_out, int64_t n,
                                                     int shift, const uint32_t *__restrict__ offs,
+                                                    const uint32_t *__restrict__ digit_tot,
                                                     int nblocks)
 {
     __shared__ uint32_t base_of[kRadix];
     __shared__ uint32_t running[kRadix];
     __shared__ uint32_t wcount[kBlock / 64][kRadix];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    base_of[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    {
+        uint32_t tot;
+        const uint32_t digit_base = block_exclusive_scan(digit_tot[tid], &tot);
+        base_of[tid] = digit_base + offs[(int64_t)tid * nblocks + blockIdx.x];
+    }
     running[tid] = 0;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     int64_t base = (int64_t)blockIdx.x * kTile;
@@ -262,6 +282,7 @@ __device__ __forceinline__ int delta(const uint32_t *keys, int64_t n, int64_t i,
 __global__ __launch_bounds__(kBlock) void k_karras(const uint32_t *__restrict__ keys, int64_t n,
                                                    int32_t *__restrict__ topo,
                                                    int32_t *__restrict__ leaf_parent,
+                                                   int2 *__restrict__ range,
                                                    NodeRec *__restrict__ nodes)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -290,6 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_karras(const uint32_t *__restrict__ 
     if (left >= 0) topo[3 * left + 2] = (int32_t)i; else leaf_parent[~left] = (int32_t)i;
     if (right >= 0) topo[3 * right + 2] = (int32_t)i; else leaf_parent[~right] = (int32_t)i;
     if (i == 0) topo[2] = -1;
+    range[i] = make_int2((int32_t)lo, (int32_t)hi);
     nodes[i].q3 = make_int4(left, right, 0, 0);
 }
 
@@ -303,16 +325,28 @@ __device__ __forceinline__ void store_child_box(NodeRec *node, int slot, const f
     q[4 + slot] = make_float2(lo[2], hi[2]);
 }
 
-// bottom-up box reduction; one thread per leaf
-__global__ __launch_bounds__(kBlock) void k_refit(const float *__restrict__ bounds,
-                                                  const uint32_t *__restrict__ sorted, int64_t n,
-                                                  const int32_t *__restrict__ topo,
-                                                  const int32_t *__restrict__ leaf_parent,
-                                                  uint32_t *__restrict__ arrive,
-                                                  int32_t *__restrict__ height,
-                                                  NodeRec *nodes, int32_t *depth_out)
+// Bottom-up box reduction, one thread per leaf.  A block owns a chunk of
+// kRefitBlock consecutive leaves; a node whose leaf range lies inside the
+// chunk has both children finished by this block, so its arrival counter
+// lives in LDS and workgroup-scope ordering suffices.  Only nodes spanning
+// chunks (a few per chunk boundary and level) use agent-scope counters in
+// global memory, whose release/acquire order the node records across XCDs.
+constexpr int kRefitBlock = 1024;
+
+__global__ __launch_bounds__(kRefitBlock) void k_refit(const float *__restrict__ bounds,
+                                                       const uint32_t *__restrict__ sorted,
+                                                       int64_t n, const int32_t *__restrict__ topo,
+                                                       const int32_t *__restrict__ leaf_parent,
+                                                       const int2 *__restrict__ range,
+                                                       uint32_t *__restrict__ arrive,
+                                                       int32_t *__restrict__ height,
+                                                       NodeRec *nodes, int32_t *depth_out)
 {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint32_t local_arrive[kRefitBlock];
+    local_arrive[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t c0 = (int64_t)blockIdx.x * kRefitBlock;
+    const int64_t k = c0 + threadIdx.x;
     if (k >= n) return;
     const float *b = bounds + 6 * (int64_t)sorted[k];
     float lo[3] = {b[0], b[1], b[2]};
@@ -324,9 +358,14 @@ __global__ __launch_bounds__(kBlock) void k_refit(const float *__restrict__ boun
         int slot = (topo[3 * p + 0] == child) ? 0 : 1;
         store_child_box(nodes + p, slot, lo, hi);
         if (slot == 0) height[2 * p + 0] = h; else height[2 * p + 1] = h;
-        // release our child box, acquire the sibling's
-        uint32_t prev = __hip_atomic_fetch_add(arrive + p, 1u, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+        const int2 rg = range[p];
+        uint32_t prev;
+        if (rg.x >= c0 && rg.y < c0 + kRefitBlock)
+            prev = __hip_atomic_fetch_add(local_arrive + (p - c0), 1u, __ATOMIC_ACQ_REL,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+            prev = __hip_atomic_fetch_add(arrive + p, 1u, __ATOMIC_ACQ_REL,
+                                          __HIP_MEMORY_SCOPE_AGENT);
         if (prev == 0) return;  // first arrival: the sibling finishes the node
         const NodeRec nr = nodes[p];
         lo[0] = fminf(nr.q0.x, nr.q0.z); hi[0] = fmaxf(nr.q0.y, nr.q0.w);
@@ -396,6 +435,8 @@ size_t lbvh_workspace_bytes(int64_t nt)
     s += align_up(sizeof(int32_t) * (size_t)nt);          // leaf parents
     s += align_up(sizeof(uint32_t) * (size_t)nt);         // arrival counters
     s += align_up(sizeof(int32_t) * 2 * (size_t)nt);      // child heights
+    s += align_up(sizeof(int32_t) * 2 * (size_t)nt);      // node leaf ranges
+    s += align_up(sizeof(uint32_t) * kRadix);             // digit totals
     s += align_up(sizeof(uint32_t) * 8);                  // scene box (ordered)
     return s;
 }
@@ -430,12 +471,15 @@ hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
     int32_t *leaf_parent = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * n));
     uint32_t *arrive = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * n));
     int32_t *height = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * 2 * n));
+    int2 *range = reinterpret_cast<int2 *>(take(sizeof(int32_t) * 2 * n));
+    uint32_t *digit_tot = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * kRadix));
     uint32_t *obox = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * 8));
     if ((size_t)(w - static_cast<char *>(b.ws)) > b.ws_bytes) return hipErrorInvalidValue;
 
     hipLaunchKernelGGL(k_init_box, dim3(1), dim3(64), 0, s, obox);
-    hipLaunchKernelGGL(k_tri_bounds, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, b.verts,
-                       b.tris, n, bounds, obox);
+    const unsigned bgrid = grid_for(n, kBlock) < 2048u ? grid_for(n, kBlock) : 2048u;
+    hipLaunchKernelGGL(k_tri_bounds, dim3(bgrid), dim3(kBlock), 0, s, b.verts, b.tris, n, bounds,
+                       obox);
     hipLaunchKernelGGL(k_box_to_float, dim3(1), dim3(64), 0, s, obox, b.scene_box);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, bounds,
                        b.scene_box, n, b.morton_bits, b.morton, keys0, vals0);
@@ -444,9 +488,10 @@ hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
     for (int shift = 0; shift < key_bits; shift += kRadixBits) {
         hipLaunchKernelGGL(k_hist, dim3((unsigned)nblocks), dim3(kBlock), 0, s, kin, n, shift,
                            hist, (int)nblocks);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, (int64_t)kRadix * nblocks);
+        hipLaunchKernelGGL(k_scan_digits, dim3(kRadix), dim3(kBlock), 0, s, hist, (int)nblocks,
+                           digit_tot);
         hipLaunchKernelGGL(k_scatter, dim3((unsigned)nblocks), dim3(kBlock), 0, s, kin, vin,
-                           kout, vout, n, shift, hist, (int)nblocks);
+                           kout, vout, n, shift, hist, digit_tot, (int)nblocks);
         uint32_t *t = kin; kin = kout; kout = t;
         t = vin; vin = vout; vout = t;
     }
@@ -459,9 +504,10 @@ hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_karras, dim3(grid_for(n - 1, kBlock)), dim3(kBlock), 0, s, kin, n,
-                       b.topo, leaf_parent, b.nodes);
+                       b.topo, leaf_parent, range, b.nodes);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, arrive, n, 0u);
-    hipLaunchKernelGGL(k_refit, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, bounds, b.sorted,
-                       n, b.topo, leaf_parent, arrive, height, b.nodes, b.depth_out);
+    hipLaunchKernelGGL(k_refit, dim3(grid_for(n, kRefitBlock)), dim3(kRefitBlock), 0, s, bounds,
+                       b.sorted, n, b.topo, leaf_parent, range, arrive, height, b.nodes,
+                       b.depth_out);
     return hipGetLastError();
 }

@@ -44,6 +44,29 @@ struct DevJob {
     int32_t n_tris;
     int32_t root_leaf;      // 1 when the scene is a single triangle (no nodes)
     float t_min, t_max;
+    int32_t n_az;           // beams per elevation ring (n_beams % n_az == 0)
+    int32_t tile_az;        // packet tile: tile_az x tile_el beams, row-major;
+    int32_t tile_el;        //   tile_az | n_az and tile_el | n_beams / n_az
+    int32_t pad;
+};
+
+// Work queues of the persistent traversal: the launch's flattened ray range
+// is cut into kQueues contiguous parts, one per XCD; a wave takes rays from
+// its XCD's part and steals from the others when that part is exhausted.
+constexpr int kQueues = 8;
+struct WorkQueues {
+    unsigned long long head[kQueues];
+    unsigned long long end[kQueues];
+};
+
+// Launch shape of the traversal (run-time tunable, see rc_tuning).
+struct TraceConfig {
+    int persistent;     // 1: persistent waves with refill; 0: one ray per thread
+    int stack_lds;      // LDS stack entries per lane (8, 16 or 24)
+    int refill_min;     // refill when at least this many lanes are idle (1..64)
+    int blocks_per_cu;  // persistent grid = CUs x blocks_per_cu (0: occupancy limit)
+    int chunk_max;      // largest ray chunk a persistent wave takes per atomic
+    int waves_cap;      // 1: cap registers for 8 waves per SIMD (one-ray-per-thread kernel)
 };
 
 // ---------------------------------------------------------------------------
@@ -78,6 +101,9 @@ hipError_t validate_mesh_launch(const float *verts, int64_t nv, const int32_t *t
 
 enum TraceMode { TRACE_BVH = 0, TRACE_BRUTE = 1, TRACE_STATS = 2 };
 
-hipError_t trace_launch(int mode, const DevJob *jobs, int n_jobs, int64_t total_rays,
-                        float *out_range, int32_t *out_hit, int32_t *out_nodes,
-                        int32_t *out_tris, hipStream_t s);
+hipError_t trace_launch(int mode, const TraceConfig &cfg, const DevJob *jobs, int n_jobs,
+                        WorkQueues *queues, int64_t total_rays, float *out_range,
+                        int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, hipStream_t s);
+
+// Fill queue ranges for a launch of total_rays rays (host side).
+void init_queues(WorkQueues &q, int64_t total_rays);

@@ -5,6 +5,24 @@
 // entry distance exceeds the best hit so far (and every triangle beyond it);
 // the result is the nearest intersection t*_j over [t_min, t_max].
 //
+// Execution (gfx950, wave64):
+//  * Persistent waves.  The launch's rays are split into one contiguous
+//    range per XCD (workgroups are dispatched round-robin over the 8 XCDs,
+//    so block b runs on XCD b % 8 and takes rays from range b % 8 first,
+//    keeping neighbouring environments in one L2); when its range is empty
+//    a wave steals from the others.
+//  * Wavefront-ballot refill: a wave keeps traversing while fewer than
+//    `refill_min` of its 64 lanes are idle; then one lane takes that many
+//    consecutive rays from the queue with a single atomic and the idle lanes
+//    pick them up in lane order (prefix count of the idle ballot).
+//  * Packet tiling: consecutive queue entries of an environment map to a
+//    tile_az x tile_el block of beams, so a refill brings in rays with
+//    nearly equal directions.
+//  * Stack: the first `SS` entries of every lane's traversal stack live in
+//    LDS (slot-major, so the 64 lanes of a wave touch 64 consecutive words);
+//    deeper entries spill to scratch.  A Karras tree over 3b-bit codes plus
+//    index tie-breaks is at most 62 levels deep, so 64 entries always suffice.
+//
 // Numerics (compiled with -ffp-contract=off so every variant rounds alike):
 //  * Ray: direction R_s d_j is formed and normalised in FP64, then rounded to
 //    FP32 for the traversal.
@@ -22,8 +40,8 @@
 //    is only culled when it cannot hold a triangle whose FP32 distance would
 //    beat the current best.
 //  * Candidates compare as (t, triangle id) pairs, so exact ties go to the
-//    lowest id whatever the visit order: the BVH kernel and the brute-force
-//    kernel agree bit for bit.
+//    lowest id whatever the visit order: every kernel variant, the BVH and
+//    the brute-force kernel agree bit for bit.
 //  * The winner's range is recomputed in FP64 from the FP64 ray and the
 //    triangle's plane, then rounded to FP32.
 #include "rc_internal.h"
@@ -35,7 +53,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kStack = 64;           // >= depth of any Karras tree (62 key bits)
 constexpr float kErrU = 2.384185791015625e-07f;  // 2^-22: sign certificate factor
-constexpr float kBoxGrow = 1.0f + 3.5762786865234375e-07f * 2.0f;  // > 1 + 2 gamma_3
+constexpr float kBoxGrow = 7.152557373046875e-07f;  // 12u > 2 gamma_3: far-distance growth
 constexpr float kCullRel = 6.103515625e-05f;     // 2^-14 relative culling margin
 
 struct RayW {
@@ -51,19 +69,21 @@ __device__ __forceinline__ float sel3(float a, float b, float c, int k)
     return k == 0 ? a : (k == 1 ? b : c);
 }
 
-__device__ __forceinline__ void make_ray(const DevJob &jb, int64_t local, RayW &r, float d32[3])
+// FP64 unit direction R * b / |R * b|
+__device__ __forceinline__ void ray_dir64(const float *p, const float *b, double d[3])
 {
-    const uint32_t nb = (uint32_t)jb.n_beams;
-    const uint32_t e = (uint32_t)(local / nb);
-    const uint32_t j = (uint32_t)(local - (int64_t)e * nb);
-    const float *p = jb.poses + 12 * (int64_t)e;
-    const float *b = jb.dirs + 3 * (int64_t)j;
-    double bx = b[0], by = b[1], bz = b[2];
-    double d[3];
     for (int i = 0; i < 3; ++i)
-        d[i] = (double)p[4 * i + 0] * bx + (double)p[4 * i + 1] * by + (double)p[4 * i + 2] * bz;
+        d[i] = (double)p[4 * i + 0] * (double)b[0] + (double)p[4 * i + 1] * (double)b[1] +
+               (double)p[4 * i + 2] * (double)b[2];
     double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    for (int i = 0; i < 3; ++i) d32[i] = (float)(d[i] / n);
+    for (int i = 0; i < 3; ++i) d[i] /= n;
+}
+
+__device__ __forceinline__ void make_ray(const float *p, const float *b, RayW &r)
+{
+    double d[3];
+    ray_dir64(p, b, d);
+    float d32[3] = {(float)d[0], (float)d[1], (float)d[2]};
     r.org[0] = p[3];
     r.org[1] = p[7];
     r.org[2] = p[11];
@@ -149,19 +169,10 @@ __device__ __forceinline__ bool better(float t, int id, float bt, int bid)
 }
 
 // FP64 range of the winning triangle along the FP64 ray (plane equation).
-__device__ float refine_range(const DevJob &jb, int64_t local, const TriRec &tr, float t32)
+__device__ float refine_range(const float *p, const float *b, const TriRec &tr, float t32)
 {
-    const uint32_t nb = (uint32_t)jb.n_beams;
-    const uint32_t e = (uint32_t)(local / nb);
-    const uint32_t j = (uint32_t)(local - (int64_t)e * nb);
-    const float *p = jb.poses + 12 * (int64_t)e;
-    const float *b = jb.dirs + 3 * (int64_t)j;
     double d[3];
-    for (int i = 0; i < 3; ++i)
-        d[i] = (double)p[4 * i + 0] * (double)b[0] + (double)p[4 * i + 1] * (double)b[1] +
-               (double)p[4 * i + 2] * (double)b[2];
-    double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    for (int i = 0; i < 3; ++i) d[i] /= n;
+    ray_dir64(p, b, d);
     const double o[3] = {p[3], p[7], p[11]};
     const double v0[3] = {tr.a.x, tr.a.y, tr.a.z};
     const double v1[3] = {tr.a.w, tr.b.x, tr.b.y};
@@ -195,139 +206,386 @@ __device__ __forceinline__ float slab(const RayW &r, float lox, float hix, float
     const float ty0 = (loy - r.org[1]) * r.inv[1], ty1 = (hiy - r.org[1]) * r.inv[1];
     const float tz0 = (loz - r.org[2]) * r.inv[2], tz1 = (hiz - r.org[2]) * r.inv[2];
     const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), t_lo));
-    const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * kBoxGrow;
+    float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
+    tf = tf + fabsf(tf) * kBoxGrow;
     return (tn <= tf && tn <= t_hi) ? tn : INFINITY;
 }
 
+// ---------------------------------------------------------------------------
+// Per-lane traversal state and stack.
+
+template <int SS>
+struct LaneStack {
+    int *ln;     // LDS: entry k of this lane at ln[k * kBlock]
+    float *lt;
+    int sn[kStack - SS];    // entries SS.. in scratch (only touched when deep)
+    float st[kStack - SS];
+    __device__ __forceinline__ void put(int k, int n, float t)
+    {
+        if (SS > 0 && k < SS) { ln[k * kBlock] = n; lt[k * kBlock] = t; }
+        else { sn[k - SS] = n; st[k - SS] = t; }
+    }
+    __device__ __forceinline__ void get(int k, int &n, float &t) const
+    {
+        if (SS > 0 && k < SS) { n = ln[k * kBlock]; t = lt[k * kBlock]; }
+        else { n = sn[k - SS]; t = st[k - SS]; }
+    }
+};
+
+struct LaneRay {
+    RayW r;
+    const NodeRec *nodes;
+    const TriRec *tris;
+    const float *pose;
+    const float *beam;
+    int64_t out;
+    float t_min, t_max, t_lo, t_hi, best_t;
+    int best_id, best_leaf, node, sp, n_tris_scene, fetched;
+    int n_nodes, n_tris;
+    bool corrupt;
+};
+
+// which beam the q-th ray of an environment is (packet tiling)
+__device__ __forceinline__ uint32_t tile_beam(const DevJob &jb, uint32_t q)
+{
+    const uint32_t tw = (uint32_t)jb.tile_az, th = (uint32_t)jb.tile_el;
+    const uint32_t naz = (uint32_t)jb.n_az;
+    const uint32_t per = tw * th;
+    const uint32_t tile = q / per, rr = q - tile * per;
+    const uint32_t tiles_az = naz / tw;
+    const uint32_t te = tile / tiles_az, ta = tile - te * tiles_az;
+    const uint32_t row = rr / tw, col = rr - row * tw;
+    return (te * th + row) * naz + ta * tw + col;
+}
+
+__device__ __forceinline__ void test_leaf(LaneRay &L, int leaf)
+{
+    const TriRec tr = L.tris[leaf];
+    float t;
+    ++L.n_tris;
+    if (woop32(L.r, tr.a, tr.b, tr.c, &t) && t >= L.t_min && t <= L.t_max) {
+        const int id = __float_as_int(tr.c.y);
+        if (better(t, id, L.best_t, L.best_id)) {
+            L.best_t = t;
+            L.best_id = id;
+            L.best_leaf = leaf;
+            L.t_hi = t * (1.0f + kCullRel);
+        }
+    }
+}
+
+// Set up the ray with flattened launch index g; returns true if it still
+// needs traversal (false: already finished, e.g. empty scene).
+__device__ __forceinline__ bool setup_ray(const DevJob *__restrict__ jobs, int n_jobs, int64_t g,
+                                          LaneRay &L)
+{
+    const DevJob &jb = jobs[find_job(jobs, n_jobs, g)];
+    const int64_t local = g - jb.ray_begin;
+    const uint32_t nb = (uint32_t)jb.n_beams;
+    const uint32_t e = (uint32_t)(local / nb);
+    const uint32_t q = (uint32_t)(local - (int64_t)e * nb);
+    const uint32_t beam = tile_beam(jb, q);
+    L.pose = jb.poses + 12 * (int64_t)e;
+    L.beam = jb.dirs + 3 * (int64_t)beam;
+    L.out = jb.out_offset + (int64_t)e * nb + beam;
+    make_ray(L.pose, L.beam, L.r);
+    L.nodes = jb.nodes;
+    L.tris = jb.tris;
+    L.n_tris_scene = jb.n_tris;
+    L.t_min = jb.t_min;
+    L.t_max = jb.t_max;
+    L.t_lo = jb.t_min * (1.0f - kCullRel);
+    L.t_hi = jb.t_max * (1.0f + kCullRel);
+    L.best_t = INFINITY;
+    L.best_id = 0x7fffffff;
+    L.best_leaf = -1;
+    L.node = 0;
+    L.sp = 0;
+    L.fetched = 0;
+    L.n_nodes = 0;
+    L.n_tris = 0;
+    L.corrupt = false;
+    if (jb.n_tris == 0) return false;
+    if (jb.root_leaf) {
+        test_leaf(L, 0);
+        return false;
+    }
+    return true;
+}
+
+// One internal-node visit.  Returns true when the ray has finished.
+template <int SS>
+__device__ __forceinline__ bool node_step(LaneRay &L, LaneStack<SS> &S)
+{
+    // a correct traversal fetches each of the n_tris - 1 records at most
+    // once; the cap only guards against a corrupted tree
+    if (++L.fetched > L.n_tris_scene + 64) { L.corrupt = true; return true; }
+    const NodeRec nd = L.nodes[L.node];
+    ++L.n_nodes;
+    const float tl = slab(L.r, nd.q0.x, nd.q0.y, nd.q1.x, nd.q1.y, nd.q2.x, nd.q2.y, L.t_lo, L.t_hi);
+    const float tr = slab(L.r, nd.q0.z, nd.q0.w, nd.q1.z, nd.q1.w, nd.q2.z, nd.q2.w, L.t_lo, L.t_hi);
+    const int cl = nd.q3.x, cr = nd.q3.y;
+    bool hl = tl < INFINITY, hr = tr < INFINITY;
+    // leaves are tested on the spot, nearer one first
+    {
+        int l0 = -1, l1 = -1;
+        float t1 = 0.0f;
+        if (hl && cl < 0) { l0 = ~cl; hl = false; }
+        if (hr && cr < 0) {
+            if (l0 < 0) l0 = ~cr;
+            else if (tr < tl) { l1 = l0; t1 = tl; l0 = ~cr; }
+            else { l1 = ~cr; t1 = tr; }
+            hr = false;
+        }
+        if (l0 >= 0) test_leaf(L, l0);
+        if (l1 >= 0 && t1 <= L.t_hi) test_leaf(L, l1);
+    }
+    hl = hl && tl <= L.t_hi;
+    hr = hr && tr <= L.t_hi;
+    if (hl && hr) {
+        const bool lnear = tl <= tr;
+        if (L.sp == kStack) { L.corrupt = true; return true; }  // deeper than any Karras tree
+        S.put(L.sp, lnear ? cr : cl, lnear ? tr : tl);
+        ++L.sp;
+        L.node = lnear ? cl : cr;
+        return false;
+    }
+    if (hl) { L.node = cl; return false; }
+    if (hr) { L.node = cr; return false; }
+    // pop the nearest pending subtree still in range
+    while (L.sp > 0) {
+        --L.sp;
+        int n;
+        float t;
+        S.get(L.sp, n, t);
+        if (t <= L.t_hi) { L.node = n; return false; }
+    }
+    return true;
+}
+
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_trace(const DevJob *__restrict__ jobs, int n_jobs,
+__device__ __forceinline__ void finish_ray(const LaneRay &L, float *__restrict__ out_range,
+                                           int32_t *__restrict__ out_hit,
+                                           int32_t *__restrict__ out_nodes,
+                                           int32_t *__restrict__ out_tris)
+{
+    if (L.corrupt) {
+        out_range[L.out] = NAN;  // never a valid result: flags a broken hierarchy
+        out_hit[L.out] = -2;
+    } else if (L.best_leaf >= 0) {
+        const TriRec tr = L.tris[L.best_leaf];
+        out_range[L.out] = refine_range(L.pose, L.beam, tr, L.best_t);
+        out_hit[L.out] = L.best_id;
+    } else {
+        out_range[L.out] = INFINITY;
+        out_hit[L.out] = -1;
+    }
+    if (MODE == TRACE_STATS) {
+        out_nodes[L.out] = L.n_nodes;
+        out_tris[L.out] = L.n_tris;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One ray per thread (also the brute-force cross-check).
+template <int MODE, int SS, int WAVES>
+__global__ __launch_bounds__(kBlock, WAVES) void k_trace(const DevJob *__restrict__ jobs, int n_jobs,
                                                   int64_t total, float *__restrict__ out_range,
                                                   int32_t *__restrict__ out_hit,
                                                   int32_t *__restrict__ out_nodes,
                                                   int32_t *__restrict__ out_tris)
 {
+    __shared__ int s_node[SS > 0 ? SS * kBlock : 1];
+    __shared__ float s_t[SS > 0 ? SS * kBlock : 1];
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (g >= total) return;
-    const DevJob jb = jobs[find_job(jobs, n_jobs, g)];
-    const int64_t local = g - jb.ray_begin;
-    RayW r;
-    float d32[3];
-    make_ray(jb, local, r, d32);
-
-    float best_t = INFINITY;
-    int best_id = 0x7fffffff;
-    int best_leaf = -1;
-    int n_nodes = 0, n_tris = 0;
-    bool corrupt = false;
-    const float t_min = jb.t_min, t_max = jb.t_max;
-    const float t_lo = t_min * (1.0f - kCullRel);
-    float t_hi = t_max * (1.0f + kCullRel);
-
-    auto test_leaf = [&](int leaf) {
-        const TriRec tr = jb.tris[leaf];
-        float t;
-        ++n_tris;
-        if (woop32(r, tr.a, tr.b, tr.c, &t) && t >= t_min && t <= t_max) {
-            const int id = __float_as_int(tr.c.y);
-            if (better(t, id, best_t, best_id)) {
-                best_t = t;
-                best_id = id;
-                best_leaf = leaf;
-                t_hi = best_t * (1.0f + kCullRel);
-            }
-        }
-    };
-
+    LaneRay L;
+    LaneStack<SS> S;
+    S.ln = s_node + threadIdx.x;
+    S.lt = s_t + threadIdx.x;
+    bool go = setup_ray(jobs, n_jobs, g, L);
     if (MODE == TRACE_BRUTE) {
-        for (int k = 0; k < jb.n_tris; ++k) test_leaf(k);
-    } else if (jb.n_tris > 0) {
-        if (jb.root_leaf) {
-            test_leaf(0);
-        } else {
-            int stack_node[kStack];
-            float stack_t[kStack];
-            int sp = 0;
-            int node = 0;
-            // a correct traversal fetches each of the n_tris - 1 records at
-            // most once; the cap only guards against a corrupted tree
-            const int max_fetch = jb.n_tris + 64;
-            int fetched = 0;
-            while (true) {
-                if (++fetched > max_fetch) { corrupt = true; break; }
-                const NodeRec nd = jb.nodes[node];
-                ++n_nodes;
-                const float tl = slab(r, nd.q0.x, nd.q0.y, nd.q1.x, nd.q1.y, nd.q2.x, nd.q2.y,
-                                      t_lo, t_hi);
-                const float tr = slab(r, nd.q0.z, nd.q0.w, nd.q1.z, nd.q1.w, nd.q2.z, nd.q2.w,
-                                      t_lo, t_hi);
-                int cl = nd.q3.x, cr = nd.q3.y;
-                bool hl = tl < INFINITY, hr = tr < INFINITY;
-                // leaves are tested on the spot, nearer one first
-                if (hl && cl < 0 && hr && cr < 0) {
-                    if (tl <= tr) { test_leaf(~cl); if (tr <= t_hi) test_leaf(~cr); }
-                    else { test_leaf(~cr); if (tl <= t_hi) test_leaf(~cl); }
-                    hl = hr = false;
-                } else {
-                    if (hl && cl < 0) { test_leaf(~cl); hl = false; }
-                    if (hr && cr < 0) { test_leaf(~cr); hr = false; }
+        for (int k = 0; go && k < L.n_tris_scene; ++k) test_leaf(L, k);
+    } else {
+        while (go) go = !node_step<SS>(L, S);
+    }
+    finish_ray<MODE>(L, out_range, out_hit, out_nodes, out_tris);
+}
+
+// Persistent waves with per-XCD queues, stealing and ballot refill.  Each
+// wave keeps a private pool of consecutive ray indices [pool_next, pool_end)
+// in scalar registers and refills idle lanes from it; the pool itself is
+// refilled with one atomic per chunk, the chunk shrinking with the work left
+// in the queue (guided self-scheduling: 4 * remaining / waves, clamped to
+// [64, chunk_max]) so the tail stays balanced.
+template <int MODE, int SS>
+__global__ __launch_bounds__(kBlock) void k_trace_persistent(
+    const DevJob *__restrict__ jobs, int n_jobs, WorkQueues *queues, int refill_min, int chunk_max,
+    float *__restrict__ out_range, int32_t *__restrict__ out_hit,
+    int32_t *__restrict__ out_nodes, int32_t *__restrict__ out_tris)
+{
+    __shared__ int s_node[SS * kBlock];
+    __shared__ float s_t[SS * kBlock];
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const unsigned long long n_waves = (unsigned long long)gridDim.x * (kBlock / 64);
+    LaneRay L;
+    LaneStack<SS> S;
+    S.ln = s_node + threadIdx.x;
+    S.lt = s_t + threadIdx.x;
+    int xq = blockIdx.x % kQueues;
+    bool exhausted = false;   // wave-uniform
+    bool active = false;
+    unsigned long long pool_next = 0, pool_end = 0;   // wave-uniform
+    while (true) {
+        unsigned long long am = __ballot(active);
+        if (!exhausted && 64 - __popcll(am) >= refill_min) {
+            unsigned long long idle = ~am;
+            for (int round = 0; round < 2 && idle != 0 && !exhausted; ++round) {
+                if (pool_next >= pool_end) {
+                    // new chunk: own XCD's range first, then steal
+                    bool got = false;
+                    for (int tries = 0; tries < kQueues && !got; ++tries) {
+                        const int x = (xq + tries) % kQueues;
+                        const unsigned long long e = queues->end[x];
+                        const unsigned long long h = __hip_atomic_load(
+                            &queues->head[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (h >= e) continue;
+                        unsigned long long chunk = 4 * (e - h) / n_waves;
+                        chunk = (chunk + 63) & ~63ull;
+                        if (chunk < 64) chunk = 64;
+                        if (chunk > (unsigned long long)chunk_max) chunk = chunk_max;
+                        unsigned long long b = 0;
+                        if (lane == 0) b = atomicAdd(&queues->head[x], chunk);
+                        const unsigned int blo = __builtin_amdgcn_readfirstlane((unsigned int)b);
+                        const unsigned int bhi =
+                            __builtin_amdgcn_readfirstlane((unsigned int)(b >> 32));
+                        b = ((unsigned long long)bhi << 32) | blo;
+                        if (b < e) {
+                            got = true;
+                            pool_next = b;
+                            pool_end = b + chunk < e ? b + chunk : e;
+                            xq = x;
+                        }
+                    }
+                    if (!got) {
+                        exhausted = true;
+                        break;
+                    }
                 }
-                hl = hl && tl <= t_hi;
-                hr = hr && tr <= t_hi;
-                if (hl && hr) {
-                    const bool lnear = tl <= tr;
-                    node = lnear ? cl : cr;
-                    if (sp == kStack) { corrupt = true; break; }  // deeper than any Karras tree
-                    stack_node[sp] = lnear ? cr : cl;
-                    stack_t[sp] = lnear ? tr : tl;
-                    ++sp;
-                    continue;
+                const unsigned long long avail = pool_end - pool_next;
+                const unsigned long long want = (unsigned long long)__popcll(idle);
+                const unsigned long long take = want < avail ? want : avail;
+                const unsigned long long rank = __popcll(idle & lt_mask);
+                const bool mine = ((idle >> lane) & 1ull) && rank < take;
+                if (mine) {
+                    active = setup_ray(jobs, n_jobs, (int64_t)(pool_next + rank), L);
+                    if (!active) finish_ray<MODE>(L, out_range, out_hit, out_nodes, out_tris);
                 }
-                if (hl) { node = cl; continue; }
-                if (hr) { node = cr; continue; }
-                // pop the nearest pending subtree still in range
-                bool found = false;
-                while (sp > 0) {
-                    --sp;
-                    if (stack_t[sp] <= t_hi) { node = stack_node[sp]; found = true; break; }
-                }
-                if (!found) break;
+                pool_next += take;
+                idle &= ~__ballot(mine);
             }
+            am = __ballot(active);
+        }
+        if (am == 0) {
+            if (exhausted) break;
+            continue;
+        }
+        while (true) {
+            if (active) {
+                if (node_step<SS>(L, S)) {
+                    finish_ray<MODE>(L, out_range, out_hit, out_nodes, out_tris);
+                    active = false;
+                }
+            }
+            am = __ballot(active);
+            if (am == 0) break;
+            if (!exhausted && 64 - __popcll(am) >= refill_min) break;
         }
     }
-    const int64_t o = jb.out_offset + local;
-    if (corrupt) {
-        out_range[o] = NAN;  // never a valid result: flags a broken hierarchy
-        out_hit[o] = -2;
-    } else if (best_leaf >= 0) {
-        const TriRec tr = jb.tris[best_leaf];
-        out_range[o] = refine_range(jb, local, tr, best_t);
-        out_hit[o] = best_id;
-    } else {
-        out_range[o] = INFINITY;
-        out_hit[o] = -1;
+}
+
+template <int MODE, int SS>
+hipError_t launch_persistent(const TraceConfig &cfg, const DevJob *jobs, int n_jobs,
+                             WorkQueues *queues, float *out_range, int32_t *out_hit,
+                             int32_t *out_nodes, int32_t *out_tris, hipStream_t s)
+{
+    static int cus = 0;
+    static int occ = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
     }
-    if (MODE == TRACE_STATS) {
-        out_nodes[o] = n_nodes;
-        out_tris[o] = n_tris;
+    if (occ == 0) {
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, reinterpret_cast<const void *>(k_trace_persistent<MODE, SS>), kBlock, 0);
+        if (e != hipSuccess || occ < 1) occ = 1;
     }
+    const int per_cu = cfg.blocks_per_cu > 0 ? cfg.blocks_per_cu : occ;
+    int refill = cfg.refill_min < 1 ? 1 : (cfg.refill_min > 64 ? 64 : cfg.refill_min);
+    const int chunk = cfg.chunk_max >= 64 ? cfg.chunk_max : 4096;
+    hipLaunchKernelGGL((k_trace_persistent<MODE, SS>), dim3(cus * per_cu), dim3(kBlock), 0, s,
+                       jobs, n_jobs, queues, refill, chunk, out_range, out_hit, out_nodes,
+                       out_tris);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_mode(const TraceConfig &cfg, const DevJob *jobs, int n_jobs, WorkQueues *queues,
+                       int64_t total, float *out_range, int32_t *out_hit, int32_t *out_nodes,
+                       int32_t *out_tris, hipStream_t s)
+{
+    if (cfg.persistent && MODE != TRACE_BRUTE) {
+        switch (cfg.stack_lds) {
+        case 8:
+            return launch_persistent<MODE, 8>(cfg, jobs, n_jobs, queues, out_range, out_hit,
+                                              out_nodes, out_tris, s);
+        case 24:
+            return launch_persistent<MODE, 24>(cfg, jobs, n_jobs, queues, out_range, out_hit,
+                                               out_nodes, out_tris, s);
+        default:
+            return launch_persistent<MODE, 16>(cfg, jobs, n_jobs, queues, out_range, out_hit,
+                                               out_nodes, out_tris, s);
+        }
+    }
+    const dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
+#define RC_GRID(SS_, W_)                                                                     \
+    hipLaunchKernelGGL((k_trace<MODE, SS_, W_>), grid, dim3(kBlock), 0, s, jobs, n_jobs, total, \
+                       out_range, out_hit, out_nodes, out_tris)
+    if (MODE == TRACE_BRUTE) RC_GRID(0, 1);
+    else if (cfg.stack_lds == 0 && cfg.waves_cap) RC_GRID(0, 8);
+    else if (cfg.stack_lds == 0) RC_GRID(0, 1);
+    else if (cfg.stack_lds == 8 && cfg.waves_cap) RC_GRID(8, 8);
+    else if (cfg.stack_lds == 8) RC_GRID(8, 1);
+    else RC_GRID(16, 1);
+#undef RC_GRID
+    return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t trace_launch(int mode, const DevJob *jobs, int n_jobs, int64_t total_rays,
-                        float *out_range, int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris,
-                        hipStream_t s)
+void init_queues(WorkQueues &q, int64_t total_rays)
+{
+    for (int x = 0; x < kQueues; ++x) {
+        q.head[x] = (unsigned long long)(total_rays * x / kQueues);
+        q.end[x] = (unsigned long long)(total_rays * (x + 1) / kQueues);
+    }
+}
+
+hipError_t trace_launch(int mode, const TraceConfig &cfg, const DevJob *jobs, int n_jobs,
+                        WorkQueues *queues, int64_t total_rays, float *out_range,
+                        int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, hipStream_t s)
 {
     if (total_rays <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((total_rays + kBlock - 1) / kBlock));
     if (mode == TRACE_BVH)
-        hipLaunchKernelGGL(k_trace<TRACE_BVH>, grid, dim3(kBlock), 0, s, jobs, n_jobs, total_rays,
-                           out_range, out_hit, out_nodes, out_tris);
-    else if (mode == TRACE_BRUTE)
-        hipLaunchKernelGGL(k_trace<TRACE_BRUTE>, grid, dim3(kBlock), 0, s, jobs, n_jobs,
-                           total_rays, out_range, out_hit, out_nodes, out_tris);
-    else
-        hipLaunchKernelGGL(k_trace<TRACE_STATS>, grid, dim3(kBlock), 0, s, jobs, n_jobs,
-                           total_rays, out_range, out_hit, out_nodes, out_tris);
-    return hipGetLastError();
+        return launch_mode<TRACE_BVH>(cfg, jobs, n_jobs, queues, total_rays, out_range, out_hit,
+                                      out_nodes, out_tris, s);
+    if (mode == TRACE_BRUTE)
+        return launch_mode<TRACE_BRUTE>(cfg, jobs, n_jobs, queues, total_rays, out_range,
+                                        out_hit, out_nodes, out_tris, s);
+    return launch_mode<TRACE_STATS>(cfg, jobs, n_jobs, queues, total_rays, out_range, out_hit,
+                                    out_nodes, out_tris, s);
 }

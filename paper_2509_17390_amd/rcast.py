@@ -40,7 +40,7 @@ EXPORTED = [
     "rc_last_error", "rc_version", "rc_create", "rc_destroy", "rc_scene_upload",
     "rc_lbvh_build", "rc_scene_release", "rc_pattern_upload", "rc_raycast_batch",
     "rc_raycast_bruteforce", "rc_raycast_stats", "rc_scene_get_info",
-    "rc_scene_debug_copy", "rc_device_bytes",
+    "rc_scene_debug_copy", "rc_device_bytes", "rc_set_tuning", "rc_get_tuning",
 ]
 
 
@@ -68,6 +68,16 @@ class rc_scene_info(ctypes.Structure):
                 ("node_format", ctypes.c_int32), ("morton_bits", ctypes.c_int32),
                 ("has_bvh", ctypes.c_int32), ("device_bytes", ctypes.c_uint64),
                 ("scene_lo", ctypes.c_float * 3), ("scene_hi", ctypes.c_float * 3)]
+
+
+class rc_tuning(ctypes.Structure):
+    _fields_ = [("persistent", ctypes.c_int32), ("stack_lds", ctypes.c_int32),
+                ("refill_min", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("tile_az", ctypes.c_int32), ("tile_el", ctypes.c_int32),
+                ("chunk_max", ctypes.c_int32), ("waves_cap", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -99,6 +109,8 @@ def load() -> ctypes.CDLL:
         "rc_scene_get_info": ([P, I32, ctypes.POINTER(rc_scene_info)], S),
         "rc_scene_debug_copy": ([P, I32, I32, P, U64], S),
         "rc_device_bytes": ([P], U64),
+        "rc_set_tuning": ([P, ctypes.POINTER(rc_tuning)], S),
+        "rc_get_tuning": ([P, ctypes.POINTER(rc_tuning)], S),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -214,6 +226,21 @@ class Context:
 
     def device_bytes(self) -> int:
         return int(load().rc_device_bytes(self._h))
+
+    def get_tuning(self) -> dict:
+        t = rc_tuning()
+        _check(load().rc_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        """Update traversal tuning fields (see rc_tuning); reset() restores defaults."""
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = rc_tuning(**cur)
+        _check(load().rc_set_tuning(self._h, ctypes.byref(t)))
+
+    def reset_tuning(self):
+        _check(load().rc_set_tuning(self._h, None))
 
     # -- patterns ------------------------------------------------------------
     def upload_pattern(self, dirs, n_az: int = 0) -> int:

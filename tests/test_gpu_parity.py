@@ -196,3 +196,58 @@ def test_duplicate_and_degenerate_triangles(ctx):
     assert clear.mean() > 0.95
     assert np.array_equal(h[clear], i_o[clear])
     assert np.all(np.abs(r[clear] - t_o[clear]) <= 1e-4 + 1e-6 * t_o[clear])
+
+
+TUNINGS = [
+    dict(persistent=0, stack_lds=0, refill_min=32, blocks_per_cu=0, tile_az=0, tile_el=0),
+    dict(persistent=0, stack_lds=16, refill_min=32, blocks_per_cu=0, tile_az=0, tile_el=0),
+    dict(persistent=1, stack_lds=8, refill_min=1, blocks_per_cu=0, tile_az=0, tile_el=0),
+    dict(persistent=1, stack_lds=16, refill_min=32, blocks_per_cu=1, tile_az=16, tile_el=4),
+    dict(persistent=1, stack_lds=24, refill_min=64, blocks_per_cu=2, tile_az=8, tile_el=8),
+    dict(persistent=1, stack_lds=16, refill_min=48, blocks_per_cu=0, tile_az=64, tile_el=1),
+]
+
+
+def test_tuning_variants_bit_identical(ctx):
+    # every launch shape (persistent or not, stack depth in LDS, refill
+    # threshold, grid size, packet tile) must give bit-identical results
+    import torch
+    s = synth.indoor_scene(seed=3, h=0.1, n_envs=6, n_az=256)
+    scene = ctx.upload_scene(s.verts, s.tris)
+    ctx.build(scene)
+    pat = ctx.upload_pattern(s.dirs, s.n_az)
+    poses = cuda(s.poses)
+    job = [Job(scene, pat, poses, s.t_min, s.t_max)]
+    ref = None
+    try:
+        for tn in TUNINGS:
+            log(f"tuning {tn}")
+            ctx.set_tuning(**tn)
+            r, h = ctx.cast(job)
+            r2, h2, nn, nt = ctx.cast(job, mode="stats")
+            torch.cuda.synchronize()
+            assert torch.equal(h, h2) and torch.equal(r.view(torch.int32), r2.view(torch.int32))
+            if ref is None:
+                ref = (r.clone(), h.clone())
+                assert bool((h >= 0).all())
+            else:
+                assert torch.equal(h, ref[1])
+                assert torch.equal(r.view(torch.int32), ref[0].view(torch.int32))
+    finally:
+        ctx.reset_tuning()
+
+
+def test_tuning_rejects_bad_values(ctx):
+    with pytest.raises(RcastError):
+        ctx.set_tuning(persistent=1, stack_lds=5)
+    with pytest.raises(RcastError):
+        ctx.set_tuning(refill_min=0)
+    with pytest.raises(RcastError):
+        ctx.set_tuning(refill_min=65)
+    default = Context(0)
+    try:
+        ctx.set_tuning(persistent=1, stack_lds=24, refill_min=7)
+        ctx.reset_tuning()
+        assert ctx.get_tuning() == default.get_tuning()
+    finally:
+        default.close()
