@@ -96,6 +96,10 @@ typedef struct {
  * construction, applied to triangle boxes as in Sec. IV-C).  Runs on
  * `stream`; the BVH stays resident until the scene is released.  A later
  * raycast on any stream must be ordered after this call's stream work.
+ * With node_format = RC_NODE_Q8 the binary tree is also collapsed into
+ * 4-wide nodes whose child boxes are 8-bit offsets in the node's frame,
+ * rounded outward; a launch whose scenes all carry them traverses those
+ * (results are bit-identical to the FP32 nodes).
  * Errors: RC_E_NOTFOUND (scene), RC_E_INVAL (options), RC_E_NOMEM, RC_E_DEVICE. */
 rc_status rc_lbvh_build(rc_ctx *ctx, int32_t scene, const rc_build_opts *opts,
                         void *stream);
@@ -154,6 +158,7 @@ rc_status rc_raycast_stats(rc_ctx *ctx, const rc_job *jobs, int32_t n_jobs,
 typedef struct {
     int64_t n_verts, n_tris;
     int64_t n_nodes;        /* internal nodes of the binary BVH            */
+    int64_t n_q8_nodes;     /* quantised 4-wide nodes (RC_NODE_Q8), else 0 */
     int32_t depth;          /* longest root-to-leaf path (edges)           */
     int32_t node_format;
     int32_t morton_bits;
@@ -173,9 +178,11 @@ rc_status rc_scene_get_info(rc_ctx *ctx, int32_t scene, rc_scene_info *out);
  *                   the leaf holding sorted triangle ~c; the root's parent is -1
  *   RC_DBG_NODES    raw node records (format-dependent bytes)
  *   RC_DBG_TRIS     raw triangle records (48 bytes each)
+ *   RC_DBG_Q8NODES  quantised 4-wide node records, 64 bytes each, sized for
+ *                   n_nodes records (the first n_q8_nodes are used)
  * `bytes` must equal the array's size.  Synchronises the device. */
 enum { RC_DBG_MORTON = 1, RC_DBG_SORTED = 2, RC_DBG_TOPOLOGY = 3,
-       RC_DBG_NODES = 4, RC_DBG_TRIS = 5 };
+       RC_DBG_NODES = 4, RC_DBG_TRIS = 5, RC_DBG_Q8NODES = 6 };
 rc_status rc_scene_debug_copy(rc_ctx *ctx, int32_t scene, int32_t what,
                               void *host_dst, uint64_t bytes);
 
@@ -190,7 +197,7 @@ uint64_t rc_device_bytes(rc_ctx *ctx);
  *                 0: one ray per thread, one launch-wide grid (default)
  *   stack_lds     traversal-stack entries per lane kept in LDS (deeper
  *                 entries spill to scratch): 8, 16 or 24 for the persistent
- *                 kernel; 0, 8 (default) or 16 otherwise
+ *                 kernel; 0 (default), 8 or 16 otherwise
  *   refill_min    a persistent wave refills once this many of its 64 lanes
  *                 are idle (1..64, default 64)
  *   blocks_per_cu persistent grid = CUs x this (0 = occupancy limit)

@@ -52,7 +52,8 @@ struct Scene {
     int32_t *topo = nullptr;
     NodeRec *nodes = nullptr;
     TriRec *trirecs = nullptr;
-    float *box_dev = nullptr;    // [8]: box (6) + depth (as int bits, 1) + pad
+    NodeRec *q8nodes = nullptr;  // quantised 4-wide nodes (node_format == RC_NODE_Q8)
+    float *box_dev = nullptr;    // [8]: box (6) + depth (int bits) + quantised node count
     uint64_t bytes = 0;
 };
 
@@ -136,6 +137,8 @@ void free_bvh(rc_ctx *c, Scene &s)
     dev_free(c, s.topo, sizeof(int32_t) * 3 * ni);
     dev_free(c, s.nodes, sizeof(NodeRec) * ni);
     dev_free(c, s.trirecs, sizeof(TriRec) * nt);
+    dev_free(c, s.q8nodes, sizeof(NodeRec) * ni);
+    s.q8nodes = nullptr;
     s.morton = s.sorted = nullptr;
     s.topo = nullptr;
     s.nodes = nullptr;
@@ -185,7 +188,7 @@ rc_tuning default_tuning()
     rc_tuning t;
     memset(&t, 0, sizeof t);
     t.persistent = 0;
-    t.stack_lds = 8;
+    t.stack_lds = 0;
     t.refill_min = 64;
     t.blocks_per_cu = 0;
     t.tile_az = 16;
@@ -197,11 +200,12 @@ rc_tuning default_tuning()
 
 // Build the device job table for a batch; shared by every trace entry point.
 rc_status prepare_jobs(rc_ctx *c, const rc_tuning &tuning, const rc_job *jobs, int32_t n_jobs,
-                       std::vector<DevJob> &out, int64_t &total)
+                       std::vector<DevJob> &out, int64_t &total, int &fmt)
 {
     if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(RC_E_INVAL, "bad job list");
     out.resize(n_jobs);
     total = 0;
+    bool all_q8 = true;
     std::lock_guard<std::mutex> lk(c->mu);
     for (int i = 0; i < n_jobs; ++i) {
         const rc_job &j = jobs[i];
@@ -220,6 +224,7 @@ rc_status prepare_jobs(rc_ctx *c, const rc_tuning &tuning, const rc_job *jobs, i
         if (nr > (int64_t)0x7fffffff) return fail(RC_E_INVAL, "job %d: more than 2^31-1 rays", i);
         DevJob &d = out[i];
         d.nodes = s->nodes;
+        if (s->node_format != RC_NODE_Q8) all_q8 = false;
         d.tris = s->trirecs;
         d.dirs = p->dirs;
         d.poses = j.poses_3x4;
@@ -235,6 +240,10 @@ rc_status prepare_jobs(rc_ctx *c, const rc_tuning &tuning, const rc_job *jobs, i
         pick_tile(tuning, p->n_beams, p->n_az, d);
         total += nr;
     }
+    // quantised nodes only when every scene of the launch has them
+    fmt = (all_q8 && n_jobs > 0) ? FMT_Q8 : FMT_BINARY;
+    if (fmt == FMT_Q8)
+        for (int i = 0; i < n_jobs; ++i) out[i].nodes = get_scene(c, jobs[i].scene)->q8nodes;
     return RC_OK;
 }
 
@@ -285,7 +294,8 @@ rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, 
     }
     std::vector<DevJob> dj;
     int64_t total = 0;
-    rc_status st = prepare_jobs(c, tuning, jobs, n_jobs, dj, total);
+    int fmt = FMT_BINARY;
+    rc_status st = prepare_jobs(c, tuning, jobs, n_jobs, dj, total, fmt);
     if (st != RC_OK) return st;
     if (total == 0) return RC_OK;
     if (!out_range || !out_hit) return fail(RC_E_INVAL, "null output");
@@ -305,7 +315,7 @@ rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, 
     cfg.blocks_per_cu = tuning.blocks_per_cu;
     cfg.chunk_max = tuning.chunk_max;
     cfg.waves_cap = tuning.waves_cap;
-    HIP_TRY(trace_launch(mode, cfg, djd, n_jobs, dq, total, out_range, out_hit, out_nodes,
+    HIP_TRY(trace_launch(mode, fmt, cfg, djd, n_jobs, dq, total, out_range, out_hit, out_nodes,
                          out_tris, s));
     HIP_TRY(hipEventRecord(slot->done, s));
     slot->used = true;
@@ -428,7 +438,8 @@ rc_status rc_lbvh_build(rc_ctx *c, int32_t scene, const rc_build_opts *opts, voi
         fmt = opts->node_format;
     }
     if (bits < 1 || bits > 10) return fail(RC_E_INVAL, "morton_bits must be in 1..10");
-    if (fmt != RC_NODE_FP32) return fail(RC_E_INVAL, "node format %d not supported", fmt);
+    if (fmt != RC_NODE_FP32 && fmt != RC_NODE_Q8)
+        return fail(RC_E_INVAL, "node format %d not supported", fmt);
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(c->mu);
@@ -446,6 +457,11 @@ rc_status rc_lbvh_build(rc_ctx *c, int32_t scene, const rc_build_opts *opts, voi
             return st;
         }
         sc->bytes += scene_bvh_bytes(nt);
+    }
+    if (nt > 0 && fmt == RC_NODE_Q8 && !sc->q8nodes) {
+        rc_status st = dev_alloc(c, (void **)&sc->q8nodes, sizeof(NodeRec) * ni);
+        if (st != RC_OK) return st;
+        sc->bytes += sizeof(NodeRec) * ni;
     }
     if (nt > 0) {
         size_t need = lbvh_workspace_bytes(nt);
@@ -477,6 +493,8 @@ rc_status rc_lbvh_build(rc_ctx *c, int32_t scene, const rc_build_opts *opts, voi
         b.trirecs = sc->trirecs;
         b.scene_box = sc->box_dev;
         b.depth_out = reinterpret_cast<int32_t *>(sc->box_dev + 6);
+        b.q8nodes = fmt == RC_NODE_Q8 ? sc->q8nodes : nullptr;
+        b.q8_count = reinterpret_cast<uint32_t *>(sc->box_dev + 7);
         HIP_TRY(lbvh_build_launch(b, s));
         HIP_TRY(hipEventRecord(c->ws_event, s));
         c->ws_event_recorded = true;
@@ -584,6 +602,9 @@ rc_status rc_scene_get_info(rc_ctx *c, int32_t scene, rc_scene_info *out)
         int32_t depth;
         memcpy(&depth, &hb[6], sizeof depth);
         out->depth = depth;
+        uint32_t nq;
+        memcpy(&nq, &hb[7], sizeof nq);
+        out->n_q8_nodes = sc->node_format == RC_NODE_Q8 ? (sc->nt > 1 ? nq : 0) : 0;
     }
     return RC_OK;
 }
@@ -605,6 +626,11 @@ rc_status rc_scene_debug_copy(rc_ctx *c, int32_t scene, int32_t what, void *dst,
     case RC_DBG_TOPOLOGY: src = sc->topo; size = 12ull * ni; break;
     case RC_DBG_NODES: src = sc->nodes; size = sizeof(NodeRec) * (uint64_t)ni; break;
     case RC_DBG_TRIS: src = sc->trirecs; size = sizeof(TriRec) * (uint64_t)nt; break;
+    case RC_DBG_Q8NODES:
+        if (sc->node_format != RC_NODE_Q8) return fail(RC_E_STATE, "scene %d has no Q8 nodes", scene);
+        src = sc->q8nodes;
+        size = sizeof(NodeRec) * (uint64_t)ni;
+        break;
     default: return fail(RC_E_INVAL, "unknown debug array %d", what);
     }
     if (bytes != size)

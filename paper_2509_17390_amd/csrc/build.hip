@@ -19,6 +19,9 @@
 //                counters inside a block's leaf chunk, agent-scope counters
 //                across chunks); node heights give the tree depth
 //   tri_records  triangles reordered into leaf order (48-byte records)
+//   collapse     optional: 4-wide nodes with 8-bit child boxes in each node's
+//                frame (node depths, prefix count of even-depth nodes, then
+//                one thread per 4-wide node)
 #include "rc_internal.h"
 
 #include <math.h>
@@ -397,6 +400,138 @@ __global__ __launch_bounds__(kBlock) void k_tri_records(const float *__restrict_
     out[k] = r;
 }
 
+// ---- quantised 4-wide nodes ------------------------------------------------
+// Depth of every internal node (edges from the root), by walking up.
+__global__ __launch_bounds__(kBlock) void k_node_depth(const int32_t *__restrict__ topo,
+                                                       int64_t ni, int32_t *__restrict__ depth)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni) return;
+    int32_t d = 0;
+    for (int32_t p = topo[3 * i + 2]; p >= 0 && d <= 64; p = topo[3 * p + 2]) ++d;
+    depth[i] = d;
+}
+
+// Nodes at even depth become 4-wide nodes; their compact index is the
+// exclusive prefix count of even-depth nodes (three-kernel scan).
+__global__ __launch_bounds__(kBlock) void k_even_local(const int32_t *__restrict__ depth,
+                                                       int64_t ni, uint32_t *__restrict__ qidx,
+                                                       uint32_t *__restrict__ bsum)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t v = (i < ni && (depth[i] & 1) == 0) ? 1u : 0u;
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan(v, &tot);
+    if (i < ni) qidx[i] = ex;
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_sums(uint32_t *__restrict__ bsum, int nb,
+                                                      uint32_t *__restrict__ total)
+{
+    uint32_t carry = 0;
+    for (int base = 0; base < nb; base += kBlock) {
+        const int i = base + threadIdx.x;
+        const uint32_t v = i < nb ? bsum[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(v, &tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) total[0] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t *__restrict__ qidx, int64_t ni,
+                                                     const uint32_t *__restrict__ bsum)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ni) qidx[i] += bsum[blockIdx.x];
+}
+
+__device__ __forceinline__ void slot_box(const NodeRec &nd, int slot, float lo[3], float hi[3])
+{
+    if (slot == 0) {
+        lo[0] = nd.q0.x; hi[0] = nd.q0.y; lo[1] = nd.q1.x; hi[1] = nd.q1.y;
+        lo[2] = nd.q2.x; hi[2] = nd.q2.y;
+    } else {
+        lo[0] = nd.q0.z; hi[0] = nd.q0.w; lo[1] = nd.q1.z; hi[1] = nd.q1.w;
+        lo[2] = nd.q2.z; hi[2] = nd.q2.w;
+    }
+}
+
+// One 4-wide node per even-depth binary node: its children are the binary
+// node's children, with every internal (odd-depth) child replaced by that
+// child's own two children.  Boxes are quantised to 8 bits in the node's
+// frame: scale_a = smallest power of two with 255 * scale_a >= extent_a,
+// qlo = floor((lo - origin) / scale), qhi = ceil((hi - origin) / scale),
+// computed in FP64 (exact here), so every decoded box contains its child.
+__global__ __launch_bounds__(kBlock) void k_collapse4(const NodeRec *__restrict__ nodes,
+                                                      const int32_t *__restrict__ depth,
+                                                      const uint32_t *__restrict__ qidx,
+                                                      int64_t ni, NodeRec *__restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni || (depth[i] & 1)) return;
+    int32_t ref[4] = {kEmptyChild, kEmptyChild, kEmptyChild, kEmptyChild};
+    float clo[4][3], chi[4][3];
+    int m = 0;
+    const NodeRec nd = nodes[i];
+    for (int s = 0; s < 2; ++s) {
+        const int32_t c = s == 0 ? nd.q3.x : nd.q3.y;
+        if (c < 0) {
+            slot_box(nd, s, clo[m], chi[m]);
+            ref[m++] = c;
+        } else {
+            const NodeRec cd = nodes[c];
+            for (int s2 = 0; s2 < 2; ++s2) {
+                const int32_t g = s2 == 0 ? cd.q3.x : cd.q3.y;
+                slot_box(cd, s2, clo[m], chi[m]);
+                ref[m++] = g < 0 ? g : (int32_t)qidx[g];
+            }
+        }
+    }
+    float olo[3], ohi[3];
+    for (int a = 0; a < 3; ++a) {
+        olo[a] = clo[0][a];
+        ohi[a] = chi[0][a];
+        for (int k = 1; k < m; ++k) {
+            olo[a] = fminf(olo[a], clo[k][a]);
+            ohi[a] = fmaxf(ohi[a], chi[k][a]);
+        }
+    }
+    float scale[3];
+    uint32_t qlo[3] = {0u, 0u, 0u}, qhi[3] = {0u, 0u, 0u};
+    for (int a = 0; a < 3; ++a) {
+        const double ext = (double)ohi[a] - (double)olo[a];
+        double sc = 0.0;
+        if (ext > 0.0) {
+            int e = (int)ceil(log2(ext / 255.0));
+            if (e < -100) e = -100;
+            sc = ldexp(1.0, e);
+            while (255.0 * sc < ext) sc *= 2.0;
+        }
+        scale[a] = (float)sc;
+        for (int k = 0; k < m; ++k) {
+            double lo = 0.0, hi = 0.0;
+            if (sc > 0.0) {
+                lo = floor(((double)clo[k][a] - (double)olo[a]) / sc);
+                hi = ceil(((double)chi[k][a] - (double)olo[a]) / sc);
+            }
+            lo = fmin(fmax(lo, 0.0), 255.0);
+            hi = fmin(fmax(hi, 0.0), 255.0);
+            qlo[a] |= (uint32_t)lo << (8 * k);
+            qhi[a] |= (uint32_t)hi << (8 * k);
+        }
+    }
+    NodeRec r;
+    r.q0 = make_float4(olo[0], olo[1], olo[2], scale[0]);
+    r.q1 = make_float4(scale[1], scale[2], __uint_as_float(qlo[0]), __uint_as_float(qhi[0]));
+    r.q2 = make_float4(__uint_as_float(qlo[1]), __uint_as_float(qhi[1]), __uint_as_float(qlo[2]),
+                       __uint_as_float(qhi[2]));
+    r.q3 = make_int4(ref[0], ref[1], ref[2], ref[3]);
+    out[qidx[i]] = r;
+}
+
 __global__ void k_single_tri_depth(int32_t *depth_out) { depth_out[0] = 0; }
 
 __global__ __launch_bounds__(kBlock) void k_validate(const float *__restrict__ verts, int64_t nv,
@@ -437,6 +572,9 @@ size_t lbvh_workspace_bytes(int64_t nt)
     s += align_up(sizeof(int32_t) * 2 * (size_t)nt);      // child heights
     s += align_up(sizeof(int32_t) * 2 * (size_t)nt);      // node leaf ranges
     s += align_up(sizeof(uint32_t) * kRadix);             // digit totals
+    s += align_up(sizeof(int32_t) * (size_t)nt);          // node depths
+    s += align_up(sizeof(uint32_t) * (size_t)nt);         // 4-wide node index
+    s += align_up(sizeof(uint32_t) * ((size_t)nt / kBlock + 2));  // scan block sums
     s += align_up(sizeof(uint32_t) * 8);                  // scene box (ordered)
     return s;
 }
@@ -473,6 +611,9 @@ hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
     int32_t *height = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * 2 * n));
     int2 *range = reinterpret_cast<int2 *>(take(sizeof(int32_t) * 2 * n));
     uint32_t *digit_tot = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * kRadix));
+    int32_t *ndepth = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * n));
+    uint32_t *qidx = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * n));
+    uint32_t *bsum = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * (n / kBlock + 2)));
     uint32_t *obox = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * 8));
     if ((size_t)(w - static_cast<char *>(b.ws)) > b.ws_bytes) return hipErrorInvalidValue;
 
@@ -509,5 +650,15 @@ hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
     hipLaunchKernelGGL(k_refit, dim3(grid_for(n, kRefitBlock)), dim3(kRefitBlock), 0, s, bounds,
                        b.sorted, n, b.topo, leaf_parent, range, arrive, height, b.nodes,
                        b.depth_out);
+    if (b.q8nodes) {
+        const int64_t ni = n - 1;
+        const unsigned g = grid_for(ni, kBlock);
+        hipLaunchKernelGGL(k_node_depth, dim3(g), dim3(kBlock), 0, s, b.topo, ni, ndepth);
+        hipLaunchKernelGGL(k_even_local, dim3(g), dim3(kBlock), 0, s, ndepth, ni, qidx, bsum);
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, bsum, (int)g, b.q8_count);
+        hipLaunchKernelGGL(k_scan_add, dim3(g), dim3(kBlock), 0, s, qidx, ni, bsum);
+        hipLaunchKernelGGL(k_collapse4, dim3(g), dim3(kBlock), 0, s, b.nodes, ndepth, qidx, ni,
+                           b.q8nodes);
+    }
     return hipGetLastError();
 }

@@ -30,6 +30,17 @@ struct TriRec {
 };
 static_assert(sizeof(TriRec) == 48, "triangle record is 48 bytes");
 
+// Quantised 4-wide node, 64 bytes (the binary tree collapsed two levels at a
+// time).  Child k's box in the node's frame:
+//   lo_a = origin_a + qlo_a[k] * scale_a,  hi_a = origin_a + qhi_a[k] * scale_a
+// with 8-bit q (byte k of a packed word) and scale_a a power of two, rounded
+// outward so the decoded box contains the child's exact FP32 box.
+//   q0 = (origin.x, origin.y, origin.z, scale.x)
+//   q1 = (scale.y, scale.z, qlo_x, qhi_x)        (q words as uint bits)
+//   q2 = (qlo_y, qhi_y, qlo_z, qhi_z)
+//   q3 = child refs: >= 0 Q8 node, < 0 leaf ~triangle record, INT_MIN empty
+constexpr int32_t kEmptyChild = (int32_t)0x80000000;
+
 // One job as the traversal kernels see it.
 struct DevJob {
     const NodeRec *nodes;   // null when the scene has no triangle
@@ -89,6 +100,8 @@ struct BuildBuffers {
     TriRec *trirecs;         // [nt]
     float *scene_box;        // [6] lo xyz, hi xyz (device)
     int32_t *depth_out;      // [1] device: tree depth
+    NodeRec *q8nodes;        // [max(nt-1,1)] quantised 4-wide nodes, or null
+    uint32_t *q8_count;      // [1] device: number of quantised nodes
 };
 
 size_t lbvh_workspace_bytes(int64_t nt);
@@ -101,7 +114,9 @@ hipError_t validate_mesh_launch(const float *verts, int64_t nv, const int32_t *t
 
 enum TraceMode { TRACE_BVH = 0, TRACE_BRUTE = 1, TRACE_STATS = 2 };
 
-hipError_t trace_launch(int mode, const TraceConfig &cfg, const DevJob *jobs, int n_jobs,
+enum NodeFormat { FMT_BINARY = 0, FMT_Q8 = 1 };
+
+hipError_t trace_launch(int mode, int fmt, const TraceConfig &cfg, const DevJob *jobs, int n_jobs,
                         WorkQueues *queues, int64_t total_rays, float *out_range,
                         int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, hipStream_t s);
 

@@ -214,12 +214,12 @@ __device__ __forceinline__ float slab(const RayW &r, float lox, float hix, float
 // ---------------------------------------------------------------------------
 // Per-lane traversal state and stack.
 
-template <int SS>
+template <int SS, int STK>
 struct LaneStack {
     int *ln;     // LDS: entry k of this lane at ln[k * kBlock]
     float *lt;
-    int sn[kStack - SS];    // entries SS.. in scratch (only touched when deep)
-    float st[kStack - SS];
+    int sn[STK - SS];    // entries SS.. in scratch (only touched when deep)
+    float st[STK - SS];
     __device__ __forceinline__ void put(int k, int n, float t)
     {
         if (SS > 0 && k < SS) { ln[k * kBlock] = n; lt[k * kBlock] = t; }
@@ -314,8 +314,8 @@ __device__ __forceinline__ bool setup_ray(const DevJob *__restrict__ jobs, int n
 }
 
 // One internal-node visit.  Returns true when the ray has finished.
-template <int SS>
-__device__ __forceinline__ bool node_step(LaneRay &L, LaneStack<SS> &S)
+template <int SS, int STK>
+__device__ __forceinline__ bool node_step(LaneRay &L, LaneStack<SS, STK> &S)
 {
     // a correct traversal fetches each of the n_tris - 1 records at most
     // once; the cap only guards against a corrupted tree
@@ -344,7 +344,7 @@ __device__ __forceinline__ bool node_step(LaneRay &L, LaneStack<SS> &S)
     hr = hr && tr <= L.t_hi;
     if (hl && hr) {
         const bool lnear = tl <= tr;
-        if (L.sp == kStack) { L.corrupt = true; return true; }  // deeper than any Karras tree
+        if (L.sp == STK) { L.corrupt = true; return true; }  // deeper than any Karras tree
         S.put(L.sp, lnear ? cr : cl, lnear ? tr : tl);
         ++L.sp;
         L.node = lnear ? cl : cr;
@@ -361,6 +361,95 @@ __device__ __forceinline__ bool node_step(LaneRay &L, LaneStack<SS> &S)
         if (t <= L.t_hi) { L.node = n; return false; }
     }
     return true;
+}
+
+// Quantised 4-wide node visit.  Each child plane is evaluated in the node's
+// frame as t = q * (scale * inv) + (origin - o) * inv with one FMA; the
+// entry (exit) distances are lowered (raised) by E_a = 8u (|a| + 255 |b|),
+// which bounds the rounding of a, b and the FMA against the exact plane
+// distance, so a child box is never culled when its exact box would not be.
+constexpr float kQErr = 4.76837158203125e-07f;   // 8u, u = 2^-24
+constexpr int kStackQ8 = 96;                     // 3 pushes per level x 31 levels + 1
+
+__device__ __forceinline__ float qbyte(uint32_t w, int k)
+{
+    return (float)((w >> (8 * k)) & 0xffu);
+}
+
+template <int SS, int STK>
+__device__ __forceinline__ bool node_step_q8(LaneRay &L, LaneStack<SS, STK> &S)
+{
+    if (++L.fetched > L.n_tris_scene + 64) { L.corrupt = true; return true; }
+    const NodeRec nd = L.nodes[L.node];
+    ++L.n_nodes;
+    const float org[3] = {nd.q0.x, nd.q0.y, nd.q0.z};
+    const float scl[3] = {nd.q0.w, nd.q1.x, nd.q1.y};
+    const uint32_t qlo[3] = {__float_as_uint(nd.q1.z), __float_as_uint(nd.q2.x),
+                             __float_as_uint(nd.q2.z)};
+    const uint32_t qhi[3] = {__float_as_uint(nd.q1.w), __float_as_uint(nd.q2.y),
+                             __float_as_uint(nd.q2.w)};
+    float an[3], af[3], bb[3];
+    uint32_t qn[3], qf[3];
+    for (int a = 0; a < 3; ++a) {
+        const float inv = L.r.inv[a];
+        const float aa = (org[a] - L.r.org[a]) * inv;
+        const float b = scl[a] * inv;
+        const float E = kQErr * (fabsf(aa) + 255.0f * fabsf(b));
+        an[a] = aa - E;
+        af[a] = aa + E;
+        bb[a] = b;
+        const bool neg = inv < 0.0f;
+        qn[a] = neg ? qhi[a] : qlo[a];
+        qf[a] = neg ? qlo[a] : qhi[a];
+    }
+    const int32_t cref[4] = {nd.q3.x, nd.q3.y, nd.q3.z, nd.q3.w};
+    float t[4];
+    int32_t ref[4];
+    for (int k = 0; k < 4; ++k) {
+        const float en = fmaxf(fmaxf(fmaf(qbyte(qn[0], k), bb[0], an[0]),
+                                     fmaf(qbyte(qn[1], k), bb[1], an[1])),
+                               fmaxf(fmaf(qbyte(qn[2], k), bb[2], an[2]), L.t_lo));
+        const float ex = fminf(fminf(fmaf(qbyte(qf[0], k), bb[0], af[0]),
+                                     fmaf(qbyte(qf[1], k), bb[1], af[1])),
+                               fmaf(qbyte(qf[2], k), bb[2], af[2]));
+        const bool hit = cref[k] != kEmptyChild && en <= ex && en <= L.t_hi;
+        t[k] = hit ? en : INFINITY;
+        ref[k] = cref[k];
+    }
+    // ascending by entry distance (5 compare-exchanges)
+#define RC_CSWAP(i, j)                                                  \
+    if (t[j] < t[i]) {                                                  \
+        float tt = t[i]; t[i] = t[j]; t[j] = tt;                        \
+        int32_t rr = ref[i]; ref[i] = ref[j]; ref[j] = rr;              \
+    }
+    RC_CSWAP(0, 1) RC_CSWAP(2, 3) RC_CSWAP(0, 2) RC_CSWAP(1, 3) RC_CSWAP(1, 2)
+#undef RC_CSWAP
+    // leaves on the spot, nearest first
+    for (int k = 0; k < 4; ++k)
+        if (ref[k] < 0 && t[k] <= L.t_hi) test_leaf(L, ~ref[k]);
+    // internal children: push farthest first, then continue with the nearest
+    for (int k = 3; k >= 0; --k) {
+        if (ref[k] >= 0 && t[k] <= L.t_hi) {
+            if (L.sp == STK) { L.corrupt = true; return true; }
+            S.put(L.sp, ref[k], t[k]);
+            ++L.sp;
+        }
+    }
+    while (L.sp > 0) {
+        --L.sp;
+        int n;
+        float tt;
+        S.get(L.sp, n, tt);
+        if (tt <= L.t_hi) { L.node = n; return false; }
+    }
+    return true;
+}
+
+template <int FMT, int SS, int STK>
+__device__ __forceinline__ bool visit(LaneRay &L, LaneStack<SS, STK> &S)
+{
+    if (FMT == FMT_Q8) return node_step_q8<SS, STK>(L, S);
+    return node_step<SS, STK>(L, S);
 }
 
 template <int MODE>
@@ -388,7 +477,7 @@ __device__ __forceinline__ void finish_ray(const LaneRay &L, float *__restrict__
 
 // ---------------------------------------------------------------------------
 // One ray per thread (also the brute-force cross-check).
-template <int MODE, int SS, int WAVES>
+template <int MODE, int FMT, int SS, int WAVES>
 __global__ __launch_bounds__(kBlock, WAVES) void k_trace(const DevJob *__restrict__ jobs, int n_jobs,
                                                   int64_t total, float *__restrict__ out_range,
                                                   int32_t *__restrict__ out_hit,
@@ -400,14 +489,14 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_trace(const DevJob *__restric
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (g >= total) return;
     LaneRay L;
-    LaneStack<SS> S;
+    LaneStack<SS, FMT == FMT_Q8 ? kStackQ8 : kStack> S;
     S.ln = s_node + threadIdx.x;
     S.lt = s_t + threadIdx.x;
     bool go = setup_ray(jobs, n_jobs, g, L);
     if (MODE == TRACE_BRUTE) {
         for (int k = 0; go && k < L.n_tris_scene; ++k) test_leaf(L, k);
     } else {
-        while (go) go = !node_step<SS>(L, S);
+        while (go) go = !visit<FMT>(L, S);
     }
     finish_ray<MODE>(L, out_range, out_hit, out_nodes, out_tris);
 }
@@ -418,7 +507,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_trace(const DevJob *__restric
 // refilled with one atomic per chunk, the chunk shrinking with the work left
 // in the queue (guided self-scheduling: 4 * remaining / waves, clamped to
 // [64, chunk_max]) so the tail stays balanced.
-template <int MODE, int SS>
+template <int MODE, int FMT, int SS>
 __global__ __launch_bounds__(kBlock) void k_trace_persistent(
     const DevJob *__restrict__ jobs, int n_jobs, WorkQueues *queues, int refill_min, int chunk_max,
     float *__restrict__ out_range, int32_t *__restrict__ out_hit,
@@ -430,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_persistent(
     const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const unsigned long long n_waves = (unsigned long long)gridDim.x * (kBlock / 64);
     LaneRay L;
-    LaneStack<SS> S;
+    LaneStack<SS, FMT == FMT_Q8 ? kStackQ8 : kStack> S;
     S.ln = s_node + threadIdx.x;
     S.lt = s_t + threadIdx.x;
     int xq = blockIdx.x % kQueues;
@@ -493,7 +582,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_persistent(
         }
         while (true) {
             if (active) {
-                if (node_step<SS>(L, S)) {
+                if (visit<FMT>(L, S)) {
                     finish_ray<MODE>(L, out_range, out_hit, out_nodes, out_tris);
                     active = false;
                 }
@@ -505,7 +594,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_persistent(
     }
 }
 
-template <int MODE, int SS>
+template <int MODE, int FMT, int SS>
 hipError_t launch_persistent(const TraceConfig &cfg, const DevJob *jobs, int n_jobs,
                              WorkQueues *queues, float *out_range, int32_t *out_hit,
                              int32_t *out_nodes, int32_t *out_tris, hipStream_t s)
@@ -521,19 +610,19 @@ hipError_t launch_persistent(const TraceConfig &cfg, const DevJob *jobs, int n_j
     }
     if (occ == 0) {
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void *>(k_trace_persistent<MODE, SS>), kBlock, 0);
+            &occ, reinterpret_cast<const void *>(k_trace_persistent<MODE, FMT, SS>), kBlock, 0);
         if (e != hipSuccess || occ < 1) occ = 1;
     }
     const int per_cu = cfg.blocks_per_cu > 0 ? cfg.blocks_per_cu : occ;
     int refill = cfg.refill_min < 1 ? 1 : (cfg.refill_min > 64 ? 64 : cfg.refill_min);
     const int chunk = cfg.chunk_max >= 64 ? cfg.chunk_max : 4096;
-    hipLaunchKernelGGL((k_trace_persistent<MODE, SS>), dim3(cus * per_cu), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_trace_persistent<MODE, FMT, SS>), dim3(cus * per_cu), dim3(kBlock), 0, s,
                        jobs, n_jobs, queues, refill, chunk, out_range, out_hit, out_nodes,
                        out_tris);
     return hipGetLastError();
 }
 
-template <int MODE>
+template <int MODE, int FMT>
 hipError_t launch_mode(const TraceConfig &cfg, const DevJob *jobs, int n_jobs, WorkQueues *queues,
                        int64_t total, float *out_range, int32_t *out_hit, int32_t *out_nodes,
                        int32_t *out_tris, hipStream_t s)
@@ -541,20 +630,20 @@ hipError_t launch_mode(const TraceConfig &cfg, const DevJob *jobs, int n_jobs, W
     if (cfg.persistent && MODE != TRACE_BRUTE) {
         switch (cfg.stack_lds) {
         case 8:
-            return launch_persistent<MODE, 8>(cfg, jobs, n_jobs, queues, out_range, out_hit,
-                                              out_nodes, out_tris, s);
+            return launch_persistent<MODE, FMT, 8>(cfg, jobs, n_jobs, queues, out_range, out_hit,
+                                                   out_nodes, out_tris, s);
         case 24:
-            return launch_persistent<MODE, 24>(cfg, jobs, n_jobs, queues, out_range, out_hit,
-                                               out_nodes, out_tris, s);
+            return launch_persistent<MODE, FMT, 24>(cfg, jobs, n_jobs, queues, out_range, out_hit,
+                                                    out_nodes, out_tris, s);
         default:
-            return launch_persistent<MODE, 16>(cfg, jobs, n_jobs, queues, out_range, out_hit,
-                                               out_nodes, out_tris, s);
+            return launch_persistent<MODE, FMT, 16>(cfg, jobs, n_jobs, queues, out_range, out_hit,
+                                                    out_nodes, out_tris, s);
         }
     }
     const dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
 #define RC_GRID(SS_, W_)                                                                     \
-    hipLaunchKernelGGL((k_trace<MODE, SS_, W_>), grid, dim3(kBlock), 0, s, jobs, n_jobs, total, \
-                       out_range, out_hit, out_nodes, out_tris)
+    hipLaunchKernelGGL((k_trace<MODE, FMT, SS_, W_>), grid, dim3(kBlock), 0, s, jobs, n_jobs,    \
+                       total, out_range, out_hit, out_nodes, out_tris)
     if (MODE == TRACE_BRUTE) RC_GRID(0, 1);
     else if (cfg.stack_lds == 0 && cfg.waves_cap) RC_GRID(0, 8);
     else if (cfg.stack_lds == 0) RC_GRID(0, 1);
@@ -575,17 +664,24 @@ void init_queues(WorkQueues &q, int64_t total_rays)
     }
 }
 
-hipError_t trace_launch(int mode, const TraceConfig &cfg, const DevJob *jobs, int n_jobs,
-                        WorkQueues *queues, int64_t total_rays, float *out_range,
+hipError_t trace_launch(int mode, int fmt, const TraceConfig &cfg, const DevJob *jobs,
+                        int n_jobs, WorkQueues *queues, int64_t total_rays, float *out_range,
                         int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, hipStream_t s)
 {
     if (total_rays <= 0) return hipSuccess;
-    if (mode == TRACE_BVH)
-        return launch_mode<TRACE_BVH>(cfg, jobs, n_jobs, queues, total_rays, out_range, out_hit,
-                                      out_nodes, out_tris, s);
     if (mode == TRACE_BRUTE)
-        return launch_mode<TRACE_BRUTE>(cfg, jobs, n_jobs, queues, total_rays, out_range,
-                                        out_hit, out_nodes, out_tris, s);
-    return launch_mode<TRACE_STATS>(cfg, jobs, n_jobs, queues, total_rays, out_range, out_hit,
-                                    out_nodes, out_tris, s);
+        return launch_mode<TRACE_BRUTE, FMT_BINARY>(cfg, jobs, n_jobs, queues, total_rays,
+                                                    out_range, out_hit, out_nodes, out_tris, s);
+    if (fmt == FMT_Q8) {
+        if (mode == TRACE_BVH)
+            return launch_mode<TRACE_BVH, FMT_Q8>(cfg, jobs, n_jobs, queues, total_rays,
+                                                  out_range, out_hit, out_nodes, out_tris, s);
+        return launch_mode<TRACE_STATS, FMT_Q8>(cfg, jobs, n_jobs, queues, total_rays, out_range,
+                                                out_hit, out_nodes, out_tris, s);
+    }
+    if (mode == TRACE_BVH)
+        return launch_mode<TRACE_BVH, FMT_BINARY>(cfg, jobs, n_jobs, queues, total_rays,
+                                                  out_range, out_hit, out_nodes, out_tris, s);
+    return launch_mode<TRACE_STATS, FMT_BINARY>(cfg, jobs, n_jobs, queues, total_rays, out_range,
+                                                out_hit, out_nodes, out_tris, s);
 }

@@ -34,6 +34,7 @@ RC_DBG_SORTED = 2
 RC_DBG_TOPOLOGY = 3
 RC_DBG_NODES = 4
 RC_DBG_TRIS = 5
+RC_DBG_Q8NODES = 6
 
 # every symbol include/rcast.h declares
 EXPORTED = [
@@ -64,7 +65,8 @@ class rc_job(ctypes.Structure):
 
 class rc_scene_info(ctypes.Structure):
     _fields_ = [("n_verts", ctypes.c_int64), ("n_tris", ctypes.c_int64),
-                ("n_nodes", ctypes.c_int64), ("depth", ctypes.c_int32),
+                ("n_nodes", ctypes.c_int64), ("n_q8_nodes", ctypes.c_int64),
+                ("depth", ctypes.c_int32),
                 ("node_format", ctypes.c_int32), ("morton_bits", ctypes.c_int32),
                 ("has_bvh", ctypes.c_int32), ("device_bytes", ctypes.c_uint64),
                 ("scene_lo", ctypes.c_float * 3), ("scene_hi", ctypes.c_float * 3)]
@@ -215,7 +217,7 @@ class Context:
             a = np.empty(nt, np.uint32)
         elif what == RC_DBG_TOPOLOGY:
             a = np.empty((ni, 3), np.int32)
-        elif what == RC_DBG_NODES:
+        elif what == RC_DBG_NODES or what == RC_DBG_Q8NODES:
             a = np.empty((ni, 16), np.float32)
         elif what == RC_DBG_TRIS:
             a = np.empty((nt, 12), np.float32)

@@ -32,7 +32,7 @@ def test_struct_layouts_match_header():
     # rc_job: 4 int32, pointer, 2 float, int64 -> 40 bytes on LP64
     assert ctypes.sizeof(rcast.rc_job) == 40
     assert ctypes.sizeof(rcast.rc_build_opts) == 32
-    assert rcast.rc_scene_info.scene_lo.offset == 48
+    assert rcast.rc_scene_info.scene_lo.offset == 56
     assert ctypes.sizeof(rcast.rc_tuning) == 32
 
 

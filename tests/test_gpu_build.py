@@ -180,3 +180,86 @@ def test_rebuild_is_deterministic(ctx):
     for _ in range(3):
         ctx.build(sid)
         assert np.array_equal(ctx.debug_copy(sid, rcast.RC_DBG_NODES).view(np.int32), a)
+
+
+def check_q8(ctx, v, t):
+    """Quantised 4-wide nodes: every leaf reached exactly once from the root,
+    each decoded child box (origin + q * scale, exact in FP64) contains the
+    exact box of the triangles below it, and is at most one quantisation step
+    looser on every side."""
+    s = ctx.upload_scene(v, t)
+    ctx.build(s, node_format=rcast.RC_NODE_Q8)
+    info = ctx.scene_info(s)
+    n = len(t)
+    order = ctx.debug_copy(s, rcast.RC_DBG_SORTED)
+    P = v[t[order]].astype(np.float64)
+    tlo, thi = P.min(axis=1), P.max(axis=1)
+    if n < 2:
+        return
+    raw = ctx.debug_copy(s, rcast.RC_DBG_Q8NODES)[: info.n_q8_nodes]
+    assert 0 < info.n_q8_nodes <= n - 1
+    f = raw.astype(np.float64)
+    u = raw.view(np.uint32)
+    refs = raw[:, 12:16].view(np.int32)
+    seen = np.zeros(n, np.int64)
+    empty = np.int32(-2 ** 31)
+
+    def qbytes(w):
+        return [(int(w) >> (8 * k)) & 0xFF for k in range(4)]
+
+    # post-order so subtree boxes are known before their parents
+    post, st = [], [0]
+    while st:
+        i = st.pop()
+        post.append(i)
+        for c in refs[i]:
+            if c >= 0 and c != empty:
+                st.append(int(c))
+    sub_lo, sub_hi = {}, {}
+    for i in reversed(post):
+        org, scl = f[i, 0:3], np.array([f[i, 3], f[i, 4], f[i, 5]])
+        qlo = [qbytes(u[i, 6]), qbytes(u[i, 8]), qbytes(u[i, 10])]
+        qhi = [qbytes(u[i, 7]), qbytes(u[i, 9]), qbytes(u[i, 11])]
+        assert np.all(scl >= 0)
+        lo_all, hi_all = np.full(3, np.inf), np.full(3, -np.inf)
+        for k in range(4):
+            c = int(refs[i, k])
+            if c == empty:
+                continue
+            if c < 0:
+                seen[~c] += 1
+                elo, ehi = tlo[~c], thi[~c]
+            else:
+                elo, ehi = sub_lo[c], sub_hi[c]
+            dlo = org + np.array([qlo[a][k] for a in range(3)]) * scl
+            dhi = org + np.array([qhi[a][k] for a in range(3)]) * scl
+            assert np.all(dlo <= elo) and np.all(dhi >= ehi), (i, k)
+            assert np.all(elo - dlo < scl + 1e-30) and np.all(dhi - ehi < scl + 1e-30), (i, k)
+            lo_all, hi_all = np.minimum(lo_all, elo), np.maximum(hi_all, ehi)
+        sub_lo[i], sub_hi[i] = lo_all, hi_all
+    assert np.all(seen == 1)
+    return s
+
+
+def test_q8_nodes_room_sphere(ctx):
+    s = synth.room_sphere_scene(0)
+    log("q8 room_sphere")
+    check_q8(ctx, s.verts, s.tris)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 17, 1000])
+def test_q8_nodes_soups(ctx, n):
+    v, t = synth.random_soup(np.random.default_rng(50 + n), n, 2.0)
+    log(f"q8 soup n={n}")
+    check_q8(ctx, v, t)
+
+
+def test_q8_nodes_mc_mesh_and_flat_axes(ctx):
+    sdf = synth.indoor_sdf(9, n_prims=40)
+    v, t = synth.polygonise(sdf, 0.12)
+    log(f"q8 mc tris={len(t)}")
+    check_q8(ctx, v, t)
+    # a flat (zero-extent) axis: all triangles in the plane z = 1
+    v2, t2 = synth.random_soup(np.random.default_rng(3), 300, 5.0)
+    v2[:, 2] = 1.0
+    check_q8(ctx, v2, t2)

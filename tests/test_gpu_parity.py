@@ -199,12 +199,13 @@ def test_duplicate_and_degenerate_triangles(ctx):
 
 
 TUNINGS = [
-    dict(persistent=0, stack_lds=0, refill_min=32, blocks_per_cu=0, tile_az=0, tile_el=0),
-    dict(persistent=0, stack_lds=16, refill_min=32, blocks_per_cu=0, tile_az=0, tile_el=0),
-    dict(persistent=1, stack_lds=8, refill_min=1, blocks_per_cu=0, tile_az=0, tile_el=0),
-    dict(persistent=1, stack_lds=16, refill_min=32, blocks_per_cu=1, tile_az=16, tile_el=4),
-    dict(persistent=1, stack_lds=24, refill_min=64, blocks_per_cu=2, tile_az=8, tile_el=8),
-    dict(persistent=1, stack_lds=16, refill_min=48, blocks_per_cu=0, tile_az=64, tile_el=1),
+    dict(persistent=0, stack_lds=8, refill_min=64, blocks_per_cu=0, tile_az=16, tile_el=4, chunk_max=4096, waves_cap=1),
+    dict(persistent=0, stack_lds=0, refill_min=32, blocks_per_cu=0, tile_az=0, tile_el=0, chunk_max=1024, waves_cap=0),
+    dict(persistent=0, stack_lds=16, refill_min=32, blocks_per_cu=0, tile_az=0, tile_el=0, chunk_max=1024, waves_cap=0),
+    dict(persistent=1, stack_lds=8, refill_min=1, blocks_per_cu=0, tile_az=0, tile_el=0, chunk_max=1024, waves_cap=0),
+    dict(persistent=1, stack_lds=16, refill_min=32, blocks_per_cu=1, tile_az=16, tile_el=4, chunk_max=1024, waves_cap=0),
+    dict(persistent=1, stack_lds=24, refill_min=64, blocks_per_cu=2, tile_az=8, tile_el=8, chunk_max=1024, waves_cap=0),
+    dict(persistent=1, stack_lds=16, refill_min=48, blocks_per_cu=0, tile_az=64, tile_el=1, chunk_max=1024, waves_cap=0),
 ]
 
 
@@ -251,3 +252,75 @@ def test_tuning_rejects_bad_values(ctx):
         assert ctx.get_tuning() == default.get_tuning()
     finally:
         default.close()
+
+
+def _cast_both(ctx, verts, tris, poses, dirs, t_min, t_max, n_az=0):
+    import torch
+    out = []
+    for fmt in (0, 1):
+        scene = ctx.upload_scene(verts, tris)
+        ctx.build(scene, node_format=fmt)
+        pat = ctx.upload_pattern(dirs, n_az)
+        r, h = ctx.cast([Job(scene, pat, cuda(poses), t_min, t_max)])
+        torch.cuda.synchronize()
+        out.append((r.cpu().numpy(), h.cpu().numpy()))
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_q8_equals_fp32_and_oracle_room_sphere(ctx, seed):
+    s = synth.room_sphere_scene(seed)
+    log(f"q8 room_sphere seed={seed}")
+    (r32, h32), (rq, hq) = _cast_both(ctx, s.verts, s.tris, s.poses, s.dirs, s.t_min, s.t_max,
+                                      s.n_az)
+    assert np.array_equal(h32, hq) and np.array_equal(r32.view(np.int32), rq.view(np.int32))
+    compare_with_oracle(s.verts, s.tris, s.poses, s.dirs, s.t_min, s.t_max, rq, hq)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 64, 257, 1000])
+def test_q8_equals_fp32_soups(ctx, n):
+    rng_ = np.random.default_rng(2000 + n)
+    v, t = synth.random_soup(rng_, n, 1.0)
+    poses = np.stack([synth.rpy_pose(rng_.uniform(-2, 2, 3), *rng_.uniform(-np.pi, np.pi, 3))
+                      for _ in range(3)])
+    dirs = synth.lidar_pattern(9, -60.0, 60.0, 71)
+    log(f"q8 soup n={n}")
+    (r32, h32), (rq, hq) = _cast_both(ctx, v, t, poses, dirs, 0.0, 50.0)
+    assert np.array_equal(h32, hq) and np.array_equal(r32.view(np.int32), rq.view(np.int32))
+
+
+def test_q8_equals_fp32_indoor_1m(ctx):
+    s = synth.indoor_scene(seed=1, h=0.035, n_envs=8)
+    log(f"q8 indoor 1M tris={len(s.tris)}")
+    (r32, h32), (rq, hq) = _cast_both(ctx, s.verts, s.tris, s.poses, s.dirs, s.t_min, s.t_max,
+                                      s.n_az)
+    assert np.all(hq >= 0)
+    same = (h32 == hq) & (r32.view(np.int32) == rq.view(np.int32))
+    assert same.all(), np.flatnonzero(~same)[:10]
+    idx = np.sort(np.random.default_rng(7).choice(s.n_rays, 1024, replace=False))
+    st = compare_with_oracle(s.verts, s.tris, s.poses, s.dirs, s.t_min, s.t_max, rq, hq,
+                             ray_idx=idx)
+    log(str(st))
+
+
+def test_q8_tuning_variants_bit_identical(ctx):
+    import torch
+    s = synth.indoor_scene(seed=3, h=0.1, n_envs=6, n_az=256)
+    scene = ctx.upload_scene(s.verts, s.tris)
+    ctx.build(scene, node_format=1)
+    pat = ctx.upload_pattern(s.dirs, s.n_az)
+    job = [Job(scene, pat, cuda(s.poses), s.t_min, s.t_max)]
+    ref = None
+    try:
+        for tn in TUNINGS:
+            log(f"q8 tuning {tn}")
+            ctx.set_tuning(**tn)
+            r, h = ctx.cast(job)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = (r.clone(), h.clone())
+            else:
+                assert torch.equal(h, ref[1])
+                assert torch.equal(r.view(torch.int32), ref[0].view(torch.int32))
+    finally:
+        ctx.reset_tuning()
