@@ -8,8 +8,10 @@ each with a seeded free-space pose (yaw uniform), 32 x 1024 beams
 
 A step is the whole hot path on inputs already resident in HBM: the LBVH
 build over the mesh (triangle boxes, Morton codes, radix sort, hierarchy,
-refit, leaf-order records) followed by one batched ray-cast launch writing
-range and hit id for every ray.  ``value`` = rays per step / step time.
+refit, leaf-order records, 4-wide quantised nodes) followed by one batched
+ray-cast launch (autotuned launch shape, replayed from a hipGraph) writing
+range and hit id for every ray.  ``value`` = rays per step / step time.  The
+same is timed with plain FP32 nodes and reported under ``forms``.
 
 Also reported:
   * roofline -- algorithmic bytes of the traversal kernel per launch
@@ -133,31 +135,53 @@ def main():
     job = [Job(scene, pat, poses_d, s.t_min, s.t_max, 0)]
     stream = torch.cuda.current_stream()
 
-    def step(ev=None):
-        ctx.build(scene, stream=stream)
-        if ev is not None:
-            ev[0].record(stream)
-        ctx.raycast(job, out_r, out_h, stream=stream)
-        if ev is not None:
-            ev[1].record(stream)
+    forms = {}
+    outputs = {}
+    for name, fmt in (("fp32", 0), ("q8", 1)):
+        # setup (untimed): build this form, autotune the launch shape on the
+        # real batch, capture the launch in a graph
+        ctx.build(scene, node_format=fmt, stream=stream)
+        torch.cuda.synchronize()
+        best, tune_ms = ctx.autotune(job, out_r, out_h, reps=2, stream=stream)
+        graph = ctx.graph(job, out_r, out_h)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+        def step(ev=None):
+            ctx.build(scene, node_format=fmt, stream=stream)
+            if ev is not None:
+                ev[0].record(stream)
+            graph.launch(stream)
+            if ev is not None:
+                ev[1].record(stream)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(evs[i])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms_step = dt * 1e3 / args.steps
+        trace_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        graph.close()
+        outputs[name] = (out_r.clone(), out_h.clone())
+        forms[name] = {"ms_per_step": round(ms_step, 3), "Mrays_s": round(n_rays / ms_step / 1e3, 2),
+                       "frame_ms": round(trace_ms, 3),
+                       "frame_Mrays_s": round(n_rays / trace_ms / 1e3, 2),
+                       "build_ms": round(ms_step - trace_ms, 3), "tuning": best,
+                       "autotune_best_ms": round(tune_ms, 3)}
+        log(f"{name}: step {ms_step:.2f} ms, traversal {trace_ms:.2f} ms, tuning {best}")
     info = ctx.scene_info(scene)
-    log(f"bvh depth {info.depth}; timing {args.steps} steps")
-
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(evs[i])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_step = dt * 1e3 / args.steps
-    trace_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    log(f"step {ms_step:.2f} ms, traversal {trace_ms:.2f} ms")
+    same_forms = bool(torch.equal(outputs["fp32"][1], outputs["q8"][1]) and
+                      torch.equal(outputs["fp32"][0].view(torch.int32),
+                                  outputs["q8"][0].view(torch.int32)))
+    head = "q8"
+    ms_step = forms[head]["ms_per_step"]
+    trace_ms = forms[head]["frame_ms"]
+    out_r, out_h = outputs[head]
 
     if args.calib_copy:
         # a plain copy of known size: 1 GiB read + 1 GiB written, so byte
@@ -168,16 +192,22 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # instrumented pass (untimed): node records fetched and triangles tested
-    n_nodes = torch.empty(n_rays, dtype=torch.int32, device=dev)
-    n_tris = torch.empty(n_rays, dtype=torch.int32, device=dev)
-    r2 = torch.empty_like(out_r)
-    h2 = torch.empty_like(out_h)
-    ctx.raycast(job, r2, h2, stream=stream, mode="stats", out_nodes=n_nodes, out_tris=n_tris)
-    torch.cuda.synchronize()
-    same = bool(torch.equal(h2, out_h))
-    mean_nodes = float(n_nodes.double().mean())
-    mean_tris = float(n_tris.double().mean())
+    # instrumented passes (untimed): node records fetched and triangles
+    # tested per ray.  The cost-model bytes use the plain FP32 tree for both
+    # forms (the same denominator), so fewer bytes in the Q8 form show as a
+    # gain; the Q8 form's own record counts are reported beside it.
+    def stats(fmt):
+        ctx.build(scene, node_format=fmt, stream=stream)
+        nn = torch.empty(n_rays, dtype=torch.int32, device=dev)
+        nt = torch.empty(n_rays, dtype=torch.int32, device=dev)
+        r2 = torch.empty_like(out_r)
+        h2 = torch.empty_like(out_h)
+        ctx.raycast(job, r2, h2, stream=stream, mode="stats", out_nodes=nn, out_tris=nt)
+        torch.cuda.synchronize()
+        return float(nn.double().mean()), float(nt.double().mean()), bool(torch.equal(h2, out_h))
+
+    mean_nodes, mean_tris, same = stats(0)
+    q8_nodes, q8_tris, same_q8 = stats(1)
     b_ray = NODE_BYTES * mean_nodes + TRI_BYTES * mean_tris + OUT_BYTES
     alg_bytes = b_ray * n_rays
     achieved = alg_bytes / (trace_ms * 1e-3) / 1e9
@@ -210,24 +240,31 @@ def main():
         "config": {
             "workload": f"batched raycast: {args.envs} envs x 32x1024 beams on a "
                         f"{len(s.tris)}-triangle closed indoor mesh (marching cubes at "
-                        f"{args.h} m), step = LBVH build + one batched launch",
+                        f"{args.h} m), step = LBVH build (Q8 nodes) + one graph-captured "
+                        f"batched launch",
+            "node_format": "q8",
             "envs": args.envs, "beams": int(len(s.dirs)), "tris": int(len(s.tris)),
             "rays_per_step": int(n_rays), "t_range": [s.t_min, s.t_max],
         },
         "frame_only": {"ms": round(trace_ms, 3),
                        "Mrays_s": round(n_rays / (trace_ms * 1e-3) / 1e6, 2)},
         "build_ms": round(ms_step - trace_ms, 3),
+        "forms": forms,
+        "forms_bit_identical": same_forms,
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_trace<TRACE_BVH>",
+            "kernel": "k_trace<TRACE_BVH, FMT_Q8> (graph replay)",
             "bytes_per_ray": round(b_ray, 1), "mean_node_records": round(mean_nodes, 2),
-            "mean_tri_tests": round(mean_tris, 2), "kernel_hash": khash,
+            "mean_tri_tests": round(mean_tris, 2),
+            "q8_mean_node_records": round(q8_nodes, 2), "q8_mean_tri_tests": round(q8_tris, 2),
+            "kernel_hash": khash,
         },
         "cpu_baseline": cpu,
         "misses": misses,
-        "stats_pass_matches": same,
+        "stats_pass_matches": same and same_q8,
+        "bvh_depth": info.depth,
         "serving": None,
     }
     print(json.dumps(out), flush=True)

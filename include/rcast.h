@@ -225,6 +225,33 @@ typedef struct {
 rc_status rc_set_tuning(rc_ctx *ctx, const rc_tuning *tuning);
 rc_status rc_get_tuning(rc_ctx *ctx, rc_tuning *out);
 
+/* Autotuner: launch the batch once per candidate launch shape (warm-up,
+ * then the fastest of `reps` launches timed with HIP events on `stream`),
+ * keep the fastest as the context's tuning and report it.  Candidates:
+ * one-ray-per-thread with stack_lds {0, 8} x waves_cap {1, 0} x tiles
+ * {16x4, 8x8, 32x2, plain}; persistent with stack_lds {8, 16} x refill_min
+ * {48, 64} x blocks_per_cu {2, 4}.  Every candidate writes the same,
+ * complete results into out_range / out_hit.  Synchronises `stream`.
+ * Errors: as rc_raycast_batch. */
+rc_status rc_autotune(rc_ctx *ctx, const rc_job *jobs, int32_t n_jobs, float *out_range,
+                      int32_t *out_hit, void *stream, int32_t reps, rc_tuning *out_best,
+                      float *out_ms);
+
+/* A batch captured in a hipGraph (queue reset + one traversal launch) for
+ * replay, e.g. once per simulation frame.  The job table (scenes, patterns,
+ * pose and output pointers, ranges, offsets) and the context's tuning are
+ * fixed at creation; callers update pose contents in place between
+ * replays.  Scenes must outlive the graph; rebuilding a scene's BVH in place
+ * is allowed (ordered on the stream before the replay).  The graph holds no
+ * hipMemset node.  Replays on one graph must not overlap (they share the
+ * graph's work queues): order them on one stream.
+ * Errors: as rc_raycast_batch; RC_E_DEVICE if capture fails. */
+typedef struct rc_graph rc_graph;
+rc_status rc_graph_create(rc_ctx *ctx, const rc_job *jobs, int32_t n_jobs, float *out_range,
+                          int32_t *out_hit, rc_graph **out);
+rc_status rc_graph_launch(rc_graph *graph, void *stream);
+void rc_graph_destroy(rc_graph *graph);
+
 #ifdef __cplusplus
 }
 #endif

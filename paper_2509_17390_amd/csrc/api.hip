@@ -183,6 +183,8 @@ void pick_tile(const rc_tuning &t, int32_t n_beams, int32_t n_az, DevJob &d)
     }
 }
 
+rc_status check_tuning(const rc_tuning *t);
+
 rc_tuning default_tuning()
 {
     rc_tuning t;
@@ -283,14 +285,28 @@ rc_status stage_jobs(rc_ctx *c, const std::vector<DevJob> &dj, int64_t total, hi
     return RC_OK;
 }
 
+TraceConfig config_of(const rc_tuning &t)
+{
+    TraceConfig cfg;
+    cfg.persistent = t.persistent;
+    cfg.stack_lds = t.stack_lds;
+    cfg.refill_min = t.refill_min;
+    cfg.blocks_per_cu = t.blocks_per_cu;
+    cfg.chunk_max = t.chunk_max;
+    cfg.waves_cap = t.waves_cap;
+    return cfg;
+}
+
+// Stage and launch one batch; `forced` overrides the context's tuning.
 rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, float *out_range,
-                       int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, void *stream)
+                       int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, void *stream,
+                       const rc_tuning *forced = nullptr)
 {
     if (!c) return fail(RC_E_INVAL, "null context");
     rc_tuning tuning;
     {
         std::lock_guard<std::mutex> lk(c->job_mu);
-        tuning = c->tuning;
+        tuning = forced ? *forced : c->tuning;
     }
     std::vector<DevJob> dj;
     int64_t total = 0;
@@ -308,15 +324,8 @@ rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, 
     JobSlot *slot = nullptr;
     st = stage_jobs(c, dj, total, s, &djd, &dq, &slot);
     if (st != RC_OK) return st;
-    TraceConfig cfg;
-    cfg.persistent = tuning.persistent;
-    cfg.stack_lds = tuning.stack_lds;
-    cfg.refill_min = tuning.refill_min;
-    cfg.blocks_per_cu = tuning.blocks_per_cu;
-    cfg.chunk_max = tuning.chunk_max;
-    cfg.waves_cap = tuning.waves_cap;
-    HIP_TRY(trace_launch(mode, fmt, cfg, djd, n_jobs, dq, total, out_range, out_hit, out_nodes,
-                         out_tris, s));
+    HIP_TRY(trace_launch(mode, fmt, config_of(tuning), djd, n_jobs, dq, total, out_range, out_hit,
+                         out_nodes, out_tris, s));
     HIP_TRY(hipEventRecord(slot->done, s));
     slot->used = true;
     return RC_OK;
@@ -652,6 +661,19 @@ rc_status rc_set_tuning(rc_ctx *c, const rc_tuning *t)
         c->tuning = default_tuning();
         return RC_OK;
     }
+    rc_status st = check_tuning(t);
+    if (st != RC_OK) return st;
+    std::lock_guard<std::mutex> lk(c->job_mu);
+    c->tuning = *t;
+    return RC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+rc_status check_tuning(const rc_tuning *t)
+{
     if (t->persistent != 0 && t->persistent != 1) return fail(RC_E_INVAL, "persistent must be 0 or 1");
     if (t->persistent && t->stack_lds != 8 && t->stack_lds != 16 && t->stack_lds != 24)
         return fail(RC_E_INVAL, "persistent traversal needs stack_lds in {8, 16, 24}");
@@ -664,8 +686,91 @@ rc_status rc_set_tuning(rc_ctx *c, const rc_tuning *t)
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return fail(RC_E_INVAL, "blocks_per_cu must be 0..64");
     if (t->tile_az < 0 || t->tile_el < 0 || (int64_t)t->tile_az * t->tile_el > (1 << 20))
         return fail(RC_E_INVAL, "bad tile shape");
-    std::lock_guard<std::mutex> lk(c->job_mu);
-    c->tuning = *t;
+    return RC_OK;
+}
+
+// Candidate launch shapes for the autotuner (all give identical results).
+std::vector<rc_tuning> tuning_candidates()
+{
+    std::vector<rc_tuning> v;
+    const int tiles[4][2] = {{16, 4}, {8, 8}, {32, 2}, {0, 0}};
+    for (int ss : {0, 8})
+        for (int cap : {1, 0})
+            for (auto &tl : tiles) {
+                rc_tuning t = default_tuning();
+                t.persistent = 0;
+                t.stack_lds = ss;
+                t.waves_cap = cap;
+                t.tile_az = tl[0];
+                t.tile_el = tl[1];
+                v.push_back(t);
+            }
+    for (int ss : {8, 16})
+        for (int rm : {48, 64})
+            for (int b : {2, 4}) {
+                rc_tuning t = default_tuning();
+                t.persistent = 1;
+                t.stack_lds = ss;
+                t.refill_min = rm;
+                t.blocks_per_cu = b;
+                t.waves_cap = 0;
+                t.chunk_max = 1024;
+                v.push_back(t);
+            }
+    return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+rc_status rc_autotune(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *out_range,
+                      int32_t *out_hit, void *stream, int32_t reps, rc_tuning *out_best,
+                      float *out_ms)
+{
+    if (!c) return fail(RC_E_INVAL, "null context");
+    if (reps < 1) reps = 1;
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    rc_tuning best = default_tuning();
+    float best_ms = INFINITY;
+    rc_status result = RC_OK;
+    for (const rc_tuning &cand : tuning_candidates()) {
+        // warm-up, then the fastest of `reps` timed launches
+        rc_status st = trace_common(c, TRACE_BVH, jobs, n_jobs, out_range, out_hit, nullptr,
+                                    nullptr, stream, &cand);
+        if (st != RC_OK) { result = st; break; }
+        float ms = INFINITY;
+        for (int r = 0; r < reps && st == RC_OK; ++r) {
+            hipError_t e = hipEventRecord(e0, s);
+            if (e == hipSuccess)
+                st = trace_common(c, TRACE_BVH, jobs, n_jobs, out_range, out_hit, nullptr,
+                                  nullptr, stream, &cand);
+            if (e == hipSuccess && st == RC_OK) e = hipEventRecord(e1, s);
+            if (e == hipSuccess && st == RC_OK) e = hipEventSynchronize(e1);
+            float t = 0.0f;
+            if (e == hipSuccess && st == RC_OK) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) st = fail(RC_E_DEVICE, "autotune timing failed: %s", hipGetErrorString(e));
+            if (st == RC_OK && t < ms) ms = t;
+        }
+        if (st != RC_OK) { result = st; break; }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != RC_OK) return result;
+    {
+        std::lock_guard<std::mutex> lk(c->job_mu);
+        c->tuning = best;
+    }
+    if (out_best) *out_best = best;
+    if (out_ms) *out_ms = best_ms;
     return RC_OK;
 }
 
@@ -675,6 +780,108 @@ rc_status rc_get_tuning(rc_ctx *c, rc_tuning *t)
     std::lock_guard<std::mutex> lk(c->job_mu);
     *t = c->tuning;
     return RC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Captured launches.
+
+struct rc_graph {
+    rc_ctx *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    char *dev = nullptr;
+    size_t bytes = 0;
+    int64_t rays = 0;
+};
+
+extern "C" {
+
+rc_status rc_graph_create(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *out_range,
+                          int32_t *out_hit, rc_graph **out)
+{
+    if (!c || !out) return fail(RC_E_INVAL, "null argument");
+    *out = nullptr;
+    rc_tuning tuning;
+    {
+        std::lock_guard<std::mutex> lk(c->job_mu);
+        tuning = c->tuning;
+    }
+    std::vector<DevJob> dj;
+    int64_t total = 0;
+    int fmt = FMT_BINARY;
+    rc_status st = prepare_jobs(c, tuning, jobs, n_jobs, dj, total, fmt);
+    if (st != RC_OK) return st;
+    if (total > 0 && (!out_range || !out_hit)) return fail(RC_E_INVAL, "null output");
+    HIP_TRY(hipSetDevice(c->device));
+    rc_graph *g = new rc_graph();
+    g->ctx = c;
+    g->rays = total;
+    const size_t nj = dj.empty() ? 1 : dj.size();
+    g->bytes = sizeof(DevJob) * nj + 2 * sizeof(WorkQueues);
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        st = dev_alloc(c, (void **)&g->dev, g->bytes);
+    }
+    if (st != RC_OK) {
+        delete g;
+        return st;
+    }
+    std::vector<char> host(g->bytes, 0);
+    memcpy(host.data(), dj.data(), sizeof(DevJob) * dj.size());
+    WorkQueues init;
+    init_queues(init, total);
+    memcpy(host.data() + sizeof(DevJob) * nj + sizeof(WorkQueues), &init, sizeof init);
+    DevJob *djd = reinterpret_cast<DevJob *>(g->dev);
+    WorkQueues *live = reinterpret_cast<WorkQueues *>(g->dev + sizeof(DevJob) * nj);
+    WorkQueues *tmpl = live + 1;
+    hipError_t e = hipMemcpy(g->dev, host.data(), g->bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess && total > 0) {
+        e = queue_reset_launch(live, tmpl, g->cap);
+        if (e == hipSuccess)
+            e = trace_launch(TRACE_BVH, fmt, config_of(tuning), djd, n_jobs, live, total,
+                             out_range, out_hit, nullptr, nullptr, g->cap);
+        if (e != hipSuccess) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(g->cap, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+        }
+    }
+    if (e == hipSuccess) e = hipStreamEndCapture(g->cap, &g->graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        rc_graph_destroy(g);
+        return fail(RC_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return RC_OK;
+}
+
+rc_status rc_graph_launch(rc_graph *g, void *stream)
+{
+    if (!g) return fail(RC_E_INVAL, "null graph");
+    HIP_TRY(hipSetDevice(g->ctx->device));
+    HIP_TRY(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    return RC_OK;
+}
+
+void rc_graph_destroy(rc_graph *g)
+{
+    if (!g) return;
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    if (g->dev) {
+        std::lock_guard<std::mutex> lk(g->ctx->mu);
+        dev_free(g->ctx, g->dev, g->bytes);
+    }
+    delete g;
 }
 
 }  // extern "C"

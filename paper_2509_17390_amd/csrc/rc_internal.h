@@ -122,3 +122,7 @@ hipError_t trace_launch(int mode, int fmt, const TraceConfig &cfg, const DevJob 
 
 // Fill queue ranges for a launch of total_rays rays (host side).
 void init_queues(WorkQueues &q, int64_t total_rays);
+
+// Copy a queue template over the live queues (a kernel, so that it can be
+// captured into a graph and replayed).
+hipError_t queue_reset_launch(WorkQueues *live, const WorkQueues *tmpl, hipStream_t s);

@@ -656,6 +656,23 @@ hipError_t launch_mode(const TraceConfig &cfg, const DevJob *jobs, int n_jobs, W
 
 }  // namespace
 
+namespace {
+__global__ void k_queue_reset(WorkQueues *live, const WorkQueues *tmpl)
+{
+    const int i = threadIdx.x;
+    if (i < kQueues) {
+        live->head[i] = tmpl->head[i];
+        live->end[i] = tmpl->end[i];
+    }
+}
+}  // namespace
+
+hipError_t queue_reset_launch(WorkQueues *live, const WorkQueues *tmpl, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, live, tmpl);
+    return hipGetLastError();
+}
+
 void init_queues(WorkQueues &q, int64_t total_rays)
 {
     for (int x = 0; x < kQueues; ++x) {

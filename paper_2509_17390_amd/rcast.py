@@ -42,6 +42,7 @@ EXPORTED = [
     "rc_lbvh_build", "rc_scene_release", "rc_pattern_upload", "rc_raycast_batch",
     "rc_raycast_bruteforce", "rc_raycast_stats", "rc_scene_get_info",
     "rc_scene_debug_copy", "rc_device_bytes", "rc_set_tuning", "rc_get_tuning",
+    "rc_autotune", "rc_graph_create", "rc_graph_launch", "rc_graph_destroy",
 ]
 
 
@@ -113,6 +114,11 @@ def load() -> ctypes.CDLL:
         "rc_device_bytes": ([P], U64),
         "rc_set_tuning": ([P, ctypes.POINTER(rc_tuning)], S),
         "rc_get_tuning": ([P, ctypes.POINTER(rc_tuning)], S),
+        "rc_autotune": ([P, ctypes.POINTER(rc_job), I32, P, P, P, I32, ctypes.POINTER(rc_tuning),
+                         ctypes.POINTER(ctypes.c_float)], S),
+        "rc_graph_create": ([P, ctypes.POINTER(rc_job), I32, P, P, ctypes.POINTER(P)], S),
+        "rc_graph_launch": ([P, P], S),
+        "rc_graph_destroy": ([P], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -282,6 +288,20 @@ class Context:
         else:
             raise ValueError(mode)
 
+    def autotune(self, jobs: Sequence[Job], out_range, out_hit, reps: int = 2, stream=None):
+        """Time the candidate launch shapes on this batch; keep and return the
+        fastest (dict) and its time in ms."""
+        arr = self._jobs(jobs)
+        best = rc_tuning()
+        ms = ctypes.c_float()
+        _check(load().rc_autotune(self._h, arr, len(jobs), _ptr(out_range), _ptr(out_hit),
+                                  _stream_ptr(stream), int(reps), ctypes.byref(best),
+                                  ctypes.byref(ms)))
+        return best.as_dict(), float(ms.value)
+
+    def graph(self, jobs: Sequence[Job], out_range, out_hit) -> "Graph":
+        return Graph(self, jobs, out_range, out_hit)
+
     def total_rays(self, jobs: Sequence[Job]) -> int:
         return max((j.out_offset + j.n_envs * self.n_beams(j.pattern) for j in jobs), default=0)
 
@@ -299,3 +319,29 @@ class Context:
             return rng, hit, nodes, tris
         self.raycast(jobs, rng, hit, stream, mode)
         return rng, hit
+
+
+class Graph:
+    """A batch captured once (rc_graph_create) and replayed with launch()."""
+
+    def __init__(self, ctx: Context, jobs: Sequence[Job], out_range, out_hit):
+        self._ctx = ctx
+        self._keep = (list(jobs), out_range, out_hit)   # keep buffers alive
+        h = ctypes.c_void_p()
+        _check(load().rc_graph_create(ctx._h, Context._jobs(jobs), len(jobs), _ptr(out_range),
+                                      _ptr(out_hit), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(load().rc_graph_launch(self._h, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().rc_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover - best effort
+        try:
+            self.close()
+        except Exception:
+            pass

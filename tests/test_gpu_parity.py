@@ -324,3 +324,59 @@ def test_q8_tuning_variants_bit_identical(ctx):
                 assert torch.equal(r.view(torch.int32), ref[0].view(torch.int32))
     finally:
         ctx.reset_tuning()
+
+
+def test_autotune_keeps_results_and_sets_tuning(ctx):
+    import torch
+    s = synth.indoor_scene(seed=4, h=0.1, n_envs=16, n_az=256)
+    scene = ctx.upload_scene(s.verts, s.tris)
+    ctx.build(scene, node_format=1)
+    pat = ctx.upload_pattern(s.dirs, s.n_az)
+    job = [Job(scene, pat, cuda(s.poses), s.t_min, s.t_max)]
+    try:
+        ref_r, ref_h = ctx.cast(job)
+        r = torch.full_like(ref_r, -1.0)
+        h = torch.full_like(ref_h, -7)
+        log("autotune")
+        best, ms = ctx.autotune(job, r, h, reps=1)
+        torch.cuda.synchronize()
+        assert ms > 0 and ctx.get_tuning() == best
+        assert torch.equal(h, ref_h) and torch.equal(r.view(torch.int32), ref_r.view(torch.int32))
+    finally:
+        ctx.reset_tuning()
+
+
+@pytest.mark.parametrize("fmt,persistent", [(0, 0), (1, 0), (1, 1)])
+def test_graph_replays_match_eager(ctx, fmt, persistent):
+    # capture once, move the sensors between replays (eager torch work and a
+    # sync in between), and check every replay against an eager launch
+    import torch
+    s = synth.indoor_scene(seed=6, h=0.1, n_envs=12, n_az=256)
+    scene = ctx.upload_scene(s.verts, s.tris)
+    ctx.build(scene, node_format=fmt)
+    pat = ctx.upload_pattern(s.dirs, s.n_az)
+    poses = cuda(s.poses)
+    n = s.n_rays
+    r = torch.empty(n, dtype=torch.float32, device="cuda")
+    h = torch.empty(n, dtype=torch.int32, device="cuda")
+    try:
+        if persistent:
+            ctx.set_tuning(persistent=1, stack_lds=8, refill_min=48, blocks_per_cu=2,
+                           chunk_max=1024, waves_cap=0)
+        job = [Job(scene, pat, poses, s.t_min, s.t_max)]
+        g = ctx.graph(job, r, h)
+        sdf = s.meta["sdf"]
+        for rep in range(4):
+            newp = synth.free_space_poses(sdf, len(s.poses), 50 + rep)
+            poses.copy_(torch.from_numpy(newp).cuda())
+            torch.cuda.synchronize()
+            log(f"graph replay {rep} fmt={fmt} persistent={persistent}")
+            g.launch()
+            torch.cuda.synchronize()
+            er, eh = ctx.cast(job)
+            torch.cuda.synchronize()
+            assert torch.equal(h, eh) and torch.equal(r.view(torch.int32), er.view(torch.int32))
+            assert bool((h >= 0).all())
+        g.close()
+    finally:
+        ctx.reset_tuning()
