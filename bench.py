@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--h", type=float, default=0.035, help="marching-cubes spacing (m)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch shape (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -142,7 +144,11 @@ def main():
         # real batch, capture the launch in a graph
         ctx.build(scene, node_format=fmt, stream=stream)
         torch.cuda.synchronize()
-        best, tune_ms = ctx.autotune(job, out_r, out_h, reps=2, stream=stream)
+        if args.no_autotune:
+            ctx.reset_tuning()
+            best, tune_ms = ctx.get_tuning(), float("nan")
+        else:
+            best, tune_ms = ctx.autotune(job, out_r, out_h, reps=2, stream=stream)
         graph = ctx.graph(job, out_r, out_h)
 
         def step(ev=None):
@@ -172,7 +178,7 @@ def main():
                        "frame_ms": round(trace_ms, 3),
                        "frame_Mrays_s": round(n_rays / trace_ms / 1e3, 2),
                        "build_ms": round(ms_step - trace_ms, 3), "tuning": best,
-                       "autotune_best_ms": round(tune_ms, 3)}
+                       "autotune_best_ms": None if tune_ms != tune_ms else round(tune_ms, 3)}
         log(f"{name}: step {ms_step:.2f} ms, traversal {trace_ms:.2f} ms, tuning {best}")
     info = ctx.scene_info(scene)
     same_forms = bool(torch.equal(outputs["fp32"][1], outputs["q8"][1]) and
