@@ -35,6 +35,10 @@
 
 #include <stdint.h>
 
+#if defined(__GNUC__) || defined(__clang__)
+#pragma GCC visibility push(default)
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -252,8 +256,95 @@ rc_status rc_graph_create(rc_ctx *ctx, const rc_job *jobs, int32_t n_jobs, float
 rc_status rc_graph_launch(rc_graph *graph, void *stream);
 void rc_graph_destroy(rc_graph *graph);
 
+/* ---------------------------------------------------------------------
+ * Serving: requests of different scenes, environment counts and beam
+ * patterns arrive at any time and are batched continuously.  Requests are
+ * admitted in arrival order as soon as their footprint (8 bytes of output
+ * per ray + 48 bytes of pose per environment) fits in the server's arenas;
+ * all requests admitted at one moment share one batched launch, and up to
+ * max_inflight launches run at once on separate streams.  Each request's
+ * results are bit-identical to casting it alone with rc_raycast_batch.
+ * Scenes and patterns must stay resident while their requests are queued
+ * or running (a request whose scene was released fails with
+ * RC_E_NOTFOUND). */
+typedef struct {
+    int32_t scene;
+    int32_t pattern;
+    int32_t n_envs;           /* >= 1                                        */
+    int32_t reserved0;
+    const float *poses_3x4;   /* HOST float32 [n_envs][12]; copied by submit */
+    float t_min, t_max;       /* closed range interval                       */
+} rc_request;
+
+typedef struct {
+    uint64_t arena_bytes;     /* device memory for admitted requests
+                                 (0 = 4 GiB; >= 1 MiB); 1/64 holds poses     */
+    int32_t max_inflight;     /* launches in flight at once, 1..8 (0 = 2)    */
+    int32_t max_batch_rays_m; /* cap on rays per launch, millions (0 = none) */
+    int32_t mock_ns_per_ray;  /* mock context: simulated device time per ray */
+    int32_t mock_fail_scene;  /* mock context: requests on scene
+                                 (mock_fail_scene - 1) fail with RC_E_DEVICE
+                                 (0 = none)                                  */
+    int32_t reserved[4];
+} rc_serve_opts;
+
+typedef struct {
+    uint64_t submitted, completed, failed, rejected, cancelled;
+    uint64_t launches;            /* batched launches issued                 */
+    uint64_t max_batch_requests;  /* most requests folded into one launch    */
+    uint64_t bytes_in_use, peak_bytes;  /* arena bytes held by requests      */
+    uint64_t out_capacity_bytes;
+    uint64_t pending, inflight, peak_inflight;
+} rc_serve_stats;
+
+/* Start / stop the context's server (one per context).  Stop waits for
+ * launched work and invalidates every ticket. Errors: RC_E_INVAL (options),
+ * RC_E_STATE (already running / not running), RC_E_NOMEM, RC_E_DEVICE. */
+rc_status rc_serve_start(rc_ctx *ctx, const rc_serve_opts *opts);
+rc_status rc_serve_stop(rc_ctx *ctx);
+
+/* Queue a request; never blocks on the device.  *out_ticket identifies it.
+ * Errors: RC_E_STATE (server not running, scene without BVH),
+ * RC_E_NOTFOUND (scene/pattern), RC_E_INVAL (sizes, non-finite pose),
+ * RC_E_NOMEM (the request could never fit in the arenas). */
+rc_status rc_serve_submit(rc_ctx *ctx, const rc_request *request, uint64_t *out_ticket);
+
+/* Wait up to timeout_us (0: just check, < 0: forever) for a ticket.
+ * RC_OK: *out_range / *out_hit point at its results (DEVICE memory for a
+ * GPU context, host memory for a mock context; n_envs * n_beams entries,
+ * [env][beam]) and *latency_ms is completion minus submission time.
+ * RC_PENDING: not finished yet.  A failed request returns its error status.
+ * Errors: RC_E_NOTFOUND (ticket), RC_E_STATE. */
+rc_status rc_serve_poll(rc_ctx *ctx, uint64_t ticket, int64_t timeout_us,
+                        const float **out_range, const int32_t **out_hit, double *latency_ms);
+
+/* Drop a ticket: frees its results (or cancels it if still queued).
+ * Errors: RC_E_NOTFOUND, RC_E_BUSY (currently on the device). */
+rc_status rc_serve_release(rc_ctx *ctx, uint64_t ticket);
+
+/* Copy a finished ticket's results (n_envs * n_beams floats and int32s)
+ * into caller buffers, host (dst_is_host = 1) or device; either may be NULL.
+ * Synchronous.  RC_PENDING if the ticket has not finished; a failed request
+ * returns its error status.  Errors: RC_E_NOTFOUND, RC_E_STATE, RC_E_DEVICE. */
+rc_status rc_serve_copy(rc_ctx *ctx, uint64_t ticket, float *range_dst, int32_t *hit_dst,
+                        int dst_is_host);
+
+/* Counters of the running server. */
+rc_status rc_serve_get_stats(rc_ctx *ctx, rc_serve_stats *out);
+
+/* Device id of a host-only context for rc_create: no HIP calls; scenes and
+ * patterns hold their sizes only (rc_scene_upload needs host arrays);
+ * rc_raycast_* report RC_E_STATE; the server runs requests on a simulated
+ * device that writes range = ray index within the request and
+ * hit = scene id.  For testing the scheduler without a GPU. */
+#define RC_DEVICE_MOCK (-1)
+
 #ifdef __cplusplus
 }
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#pragma GCC visibility pop
 #endif
 
 #endif /* RCAST_H */

@@ -20,12 +20,12 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT_DIR = os.path.join(PKG, "_lib")
 OBJ_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "librcast.so")
-SOURCES = ["api.hip", "build.hip", "trace.hip"]
+SOURCES = ["api.hip", "build.hip", "trace.hip", "serve.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
-    "-ffp-contract=off",
+    "-ffp-contract=off", "-fvisibility=hidden",
     # packed FP32 instructions stay off (the compiler must not form them)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",

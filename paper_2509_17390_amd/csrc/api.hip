@@ -4,8 +4,7 @@
 // LBVH build workspace and a ring of job-table slots (pinned staging buffer
 // + device buffer + completion event), so a batch call only enqueues one
 // small host-to-device copy and one traversal launch on the caller's stream.
-#include "rcast.h"
-#include "rc_internal.h"
+#include "ctx.h"
 
 #include <math.h>
 #include <stdarg.h>
@@ -16,7 +15,7 @@
 #include <string>
 #include <vector>
 
-namespace {
+namespace rc {
 
 thread_local std::string g_err;
 
@@ -30,72 +29,6 @@ rc_status fail(rc_status s, const char *fmt, ...)
     g_err = buf;
     return s;
 }
-
-#define HIP_TRY(expr)                                                                       \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return fail(RC_E_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
-                        __FILE__, __LINE__);                                                \
-    } while (0)
-
-struct Scene {
-    bool alive = false;
-    int64_t nv = 0, nt = 0;
-    float *verts = nullptr;
-    int32_t *tris = nullptr;
-    bool has_bvh = false;
-    int morton_bits = 10;
-    int node_format = RC_NODE_FP32;
-    uint32_t *morton = nullptr;
-    uint32_t *sorted = nullptr;
-    int32_t *topo = nullptr;
-    NodeRec *nodes = nullptr;
-    TriRec *trirecs = nullptr;
-    NodeRec *q8nodes = nullptr;  // quantised 4-wide nodes (node_format == RC_NODE_Q8)
-    float *box_dev = nullptr;    // [8]: box (6) + depth (int bits) + quantised node count
-    uint64_t bytes = 0;
-};
-
-struct Pattern {
-    bool alive = false;
-    float *dirs = nullptr;
-    int32_t n_beams = 0, n_az = 0;
-    uint64_t bytes = 0;
-};
-
-constexpr int kSlots = 8;
-
-// A slot holds one launch's job table followed by its work queues.
-struct JobSlot {
-    DevJob *host = nullptr;  // pinned: DevJob[cap] then WorkQueues
-    DevJob *dev = nullptr;
-    int cap = 0;
-    hipEvent_t done = nullptr;
-    bool used = false;
-};
-
-}  // namespace
-
-struct rc_ctx {
-    int device = 0;
-    uint64_t budget = 0;
-    uint64_t used = 0;
-    std::mutex mu;        // scenes, patterns, workspace
-    std::mutex job_mu;    // job slots
-    std::vector<Scene> scenes;
-    std::vector<Pattern> patterns;
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
-    hipEvent_t ws_event = nullptr;
-    bool ws_event_recorded = false;
-    JobSlot slots[kSlots];
-    int next_slot = 0;
-    int32_t *flags_dev = nullptr;
-    rc_tuning tuning{};
-};
-
-namespace {
 
 rc_status dev_alloc(rc_ctx *c, void **p, size_t bytes)
 {
@@ -300,9 +233,10 @@ TraceConfig config_of(const rc_tuning &t)
 // Stage and launch one batch; `forced` overrides the context's tuning.
 rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, float *out_range,
                        int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, void *stream,
-                       const rc_tuning *forced = nullptr)
+                       const rc_tuning *forced)
 {
     if (!c) return fail(RC_E_INVAL, "null context");
+    if (c->mock) return fail(RC_E_STATE, "a mock context has no device to cast on");
     rc_tuning tuning;
     {
         std::lock_guard<std::mutex> lk(c->job_mu);
@@ -331,7 +265,9 @@ rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, 
     return RC_OK;
 }
 
-}  // namespace
+}  // namespace rc
+
+using namespace rc;
 
 extern "C" {
 
@@ -343,6 +279,15 @@ rc_status rc_create(int device, uint64_t hbm_budget_bytes, rc_ctx **out)
 {
     if (!out) return fail(RC_E_INVAL, "out is NULL");
     *out = nullptr;
+    if (device == RC_DEVICE_MOCK) {
+        rc_ctx *c = new rc_ctx();
+        c->device = RC_DEVICE_MOCK;
+        c->mock = true;
+        c->budget = hbm_budget_bytes;
+        c->tuning = default_tuning();
+        *out = c;
+        return RC_OK;
+    }
     int n = 0;
     HIP_TRY(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(RC_E_INVAL, "device %d not in [0, %d)", device, n);
@@ -366,6 +311,11 @@ rc_status rc_create(int device, uint64_t hbm_budget_bytes, rc_ctx **out)
 void rc_destroy(rc_ctx *c)
 {
     if (!c) return;
+    serve_shutdown(c);
+    if (c->mock) {
+        delete c;
+        return;
+    }
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     for (auto &s : c->scenes)
@@ -391,6 +341,21 @@ rc_status rc_scene_upload(rc_ctx *c, const float *verts, int64_t nv, const int32
     if (nt > 0x7ffffffeLL) return fail(RC_E_INVAL, "too many triangles (%lld)", (long long)nt);
     if ((nv > 0 && !verts) || (nt > 0 && !tris)) return fail(RC_E_INVAL, "null mesh array");
     if (nt > 0 && nv == 0) return fail(RC_E_INVAL, "triangles without vertices");
+    if (c->mock) {
+        if (src_is_device) return fail(RC_E_INVAL, "a mock context takes host arrays only");
+        for (int64_t i = 0; i < 3 * nt; ++i)
+            if (tris[i] < 0 || tris[i] >= nv) return fail(RC_E_INVAL, "invalid mesh: index out of range");
+        for (int64_t i = 0; i < 3 * nv; ++i)
+            if (!isfinite(verts[i])) return fail(RC_E_INVAL, "invalid mesh: non-finite vertex");
+        std::lock_guard<std::mutex> lk(c->mu);
+        Scene sc;
+        sc.alive = true;
+        sc.nv = nv;
+        sc.nt = nt;
+        c->scenes.push_back(sc);
+        *out_scene = (int32_t)c->scenes.size() - 1;
+        return RC_OK;
+    }
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(c->mu);
@@ -449,6 +414,15 @@ rc_status rc_lbvh_build(rc_ctx *c, int32_t scene, const rc_build_opts *opts, voi
     if (bits < 1 || bits > 10) return fail(RC_E_INVAL, "morton_bits must be in 1..10");
     if (fmt != RC_NODE_FP32 && fmt != RC_NODE_Q8)
         return fail(RC_E_INVAL, "node format %d not supported", fmt);
+    if (c->mock) {
+        std::lock_guard<std::mutex> lk(c->mu);
+        Scene *sc = get_scene(c, scene);
+        if (!sc) return fail(RC_E_NOTFOUND, "unknown scene %d", scene);
+        sc->has_bvh = true;
+        sc->morton_bits = bits;
+        sc->node_format = fmt;
+        return RC_OK;
+    }
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(c->mu);
@@ -517,6 +491,13 @@ rc_status rc_lbvh_build(rc_ctx *c, int32_t scene, const rc_build_opts *opts, voi
 rc_status rc_scene_release(rc_ctx *c, int32_t scene)
 {
     if (!c) return fail(RC_E_INVAL, "null context");
+    if (c->mock) {
+        std::lock_guard<std::mutex> lk(c->mu);
+        Scene *sc = get_scene(c, scene);
+        if (!sc) return fail(RC_E_NOTFOUND, "unknown scene %d", scene);
+        *sc = Scene();
+        return RC_OK;
+    }
     HIP_TRY(hipSetDevice(c->device));
     std::lock_guard<std::mutex> lk(c->mu);
     Scene *sc = get_scene(c, scene);
@@ -537,6 +518,16 @@ rc_status rc_pattern_upload(rc_ctx *c, const float *dirs, int32_t n_beams, int32
             return fail(RC_E_INVAL, "beam %d is not finite", j);
         if (d[0] == 0.0f && d[1] == 0.0f && d[2] == 0.0f)
             return fail(RC_E_INVAL, "beam %d is the zero vector", j);
+    }
+    if (c->mock) {
+        std::lock_guard<std::mutex> lk(c->mu);
+        Pattern p;
+        p.alive = true;
+        p.n_beams = n_beams;
+        p.n_az = n_az_hint > 0 ? n_az_hint : n_beams;
+        c->patterns.push_back(p);
+        *out_pattern = (int32_t)c->patterns.size() - 1;
+        return RC_OK;
     }
     HIP_TRY(hipSetDevice(c->device));
     std::lock_guard<std::mutex> lk(c->mu);
@@ -588,6 +579,18 @@ rc_status rc_raycast_stats(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float 
 rc_status rc_scene_get_info(rc_ctx *c, int32_t scene, rc_scene_info *out)
 {
     if (!c || !out) return fail(RC_E_INVAL, "null argument");
+    if (c->mock) {
+        std::lock_guard<std::mutex> lk(c->mu);
+        Scene *sc = get_scene(c, scene);
+        if (!sc) return fail(RC_E_NOTFOUND, "unknown scene %d", scene);
+        memset(out, 0, sizeof *out);
+        out->n_verts = sc->nv;
+        out->n_tris = sc->nt;
+        out->has_bvh = sc->has_bvh ? 1 : 0;
+        out->node_format = sc->node_format;
+        out->morton_bits = sc->morton_bits;
+        return RC_OK;
+    }
     HIP_TRY(hipSetDevice(c->device));
     std::lock_guard<std::mutex> lk(c->mu);
     Scene *sc = get_scene(c, scene);
@@ -621,6 +624,7 @@ rc_status rc_scene_get_info(rc_ctx *c, int32_t scene, rc_scene_info *out)
 rc_status rc_scene_debug_copy(rc_ctx *c, int32_t scene, int32_t what, void *dst, uint64_t bytes)
 {
     if (!c || !dst) return fail(RC_E_INVAL, "null argument");
+    if (c->mock) return fail(RC_E_STATE, "a mock context holds no device arrays");
     HIP_TRY(hipSetDevice(c->device));
     std::lock_guard<std::mutex> lk(c->mu);
     Scene *sc = get_scene(c, scene);
@@ -670,7 +674,7 @@ rc_status rc_set_tuning(rc_ctx *c, const rc_tuning *t)
 
 }  // extern "C"
 
-namespace {
+namespace rc {
 
 rc_status check_tuning(const rc_tuning *t)
 {
@@ -720,7 +724,7 @@ std::vector<rc_tuning> tuning_candidates()
     return v;
 }
 
-}  // namespace
+}  // namespace rc
 
 extern "C" {
 
@@ -729,6 +733,7 @@ rc_status rc_autotune(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *out_
                       float *out_ms)
 {
     if (!c) return fail(RC_E_INVAL, "null context");
+    if (c->mock) return fail(RC_E_STATE, "a mock context has no device to tune");
     if (reps < 1) reps = 1;
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -804,6 +809,7 @@ rc_status rc_graph_create(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *
 {
     if (!c || !out) return fail(RC_E_INVAL, "null argument");
     *out = nullptr;
+    if (c->mock) return fail(RC_E_STATE, "a mock context cannot capture launches");
     rc_tuning tuning;
     {
         std::lock_guard<std::mutex> lk(c->job_mu);

@@ -1,0 +1,102 @@
+// ctx.h -- host-side context of librcast, shared by the C ABI (api.hip) and
+// the serving scheduler (serve.hip).  Not part of the public interface.
+#pragma once
+
+#include "rcast.h"
+#include "rc_internal.h"
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace rc {
+
+// Set the calling thread's error text and return `s`.
+rc_status fail(rc_status s, const char *fmt, ...);
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::rc::fail(RC_E_DEVICE, "%s failed: %s (%s:%d)", #expr,                  \
+                              hipGetErrorString(e_), __FILE__, __LINE__);                   \
+    } while (0)
+
+struct Scene {
+    bool alive = false;
+    int64_t nv = 0, nt = 0;
+    float *verts = nullptr;
+    int32_t *tris = nullptr;
+    bool has_bvh = false;
+    int morton_bits = 10;
+    int node_format = RC_NODE_FP32;
+    uint32_t *morton = nullptr;
+    uint32_t *sorted = nullptr;
+    int32_t *topo = nullptr;
+    NodeRec *nodes = nullptr;
+    TriRec *trirecs = nullptr;
+    NodeRec *q8nodes = nullptr;  // quantised 4-wide nodes (node_format == RC_NODE_Q8)
+    float *box_dev = nullptr;    // [8]: box (6) + depth (int bits) + quantised node count
+    uint64_t bytes = 0;
+};
+
+struct Pattern {
+    bool alive = false;
+    float *dirs = nullptr;
+    int32_t n_beams = 0, n_az = 0;
+    uint64_t bytes = 0;
+};
+
+constexpr int kSlots = 8;
+
+// A slot holds one launch's job table followed by its work queues.
+struct JobSlot {
+    DevJob *host = nullptr;  // pinned: DevJob[cap] then WorkQueues
+    DevJob *dev = nullptr;
+    int cap = 0;
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
+
+struct ServeState;  // serve.hip
+
+}  // namespace rc
+
+struct rc_ctx {
+    int device = 0;
+    bool mock = false;    // host-only context (no HIP): serving runs on a simulated device
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    std::mutex mu;        // scenes, patterns, workspace
+    std::mutex job_mu;    // job slots, tuning
+    std::vector<rc::Scene> scenes;
+    std::vector<rc::Pattern> patterns;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipEvent_t ws_event = nullptr;
+    bool ws_event_recorded = false;
+    rc::JobSlot slots[rc::kSlots];
+    int next_slot = 0;
+    int32_t *flags_dev = nullptr;
+    rc_tuning tuning{};
+    rc::ServeState *serve = nullptr;
+};
+
+namespace rc {
+
+rc_status dev_alloc(rc_ctx *c, void **p, size_t bytes);
+void dev_free(rc_ctx *c, void *p, size_t bytes);
+Scene *get_scene(rc_ctx *c, int32_t id);      // caller holds c->mu
+Pattern *get_pattern(rc_ctx *c, int32_t id);  // caller holds c->mu
+rc_tuning default_tuning();
+
+// Stage one batch and launch it on `stream`; `forced` overrides the
+// context's tuning.  Thread-safe.
+rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, float *out_range,
+                       int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, void *stream,
+                       const rc_tuning *forced = nullptr);
+
+// Serving scheduler hooks (serve.hip).
+void serve_shutdown(rc_ctx *c);  // stop the scheduler, wait for in-flight work
+
+}  // namespace rc

@@ -43,7 +43,11 @@ EXPORTED = [
     "rc_raycast_bruteforce", "rc_raycast_stats", "rc_scene_get_info",
     "rc_scene_debug_copy", "rc_device_bytes", "rc_set_tuning", "rc_get_tuning",
     "rc_autotune", "rc_graph_create", "rc_graph_launch", "rc_graph_destroy",
+    "rc_serve_start", "rc_serve_stop", "rc_serve_submit", "rc_serve_poll", "rc_serve_release",
+    "rc_serve_copy", "rc_serve_get_stats",
 ]
+
+RC_DEVICE_MOCK = -1
 
 
 class RcastError(RuntimeError):
@@ -83,6 +87,29 @@ class rc_tuning(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class rc_request(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_int32), ("pattern", ctypes.c_int32),
+                ("n_envs", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("poses_3x4", ctypes.c_void_p), ("t_min", ctypes.c_float),
+                ("t_max", ctypes.c_float)]
+
+
+class rc_serve_opts(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32),
+                ("max_batch_rays_m", ctypes.c_int32), ("mock_ns_per_ray", ctypes.c_int32),
+                ("mock_fail_scene", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class rc_serve_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in (
+        "submitted", "completed", "failed", "rejected", "cancelled", "launches",
+        "max_batch_requests", "bytes_in_use", "peak_bytes", "out_capacity_bytes", "pending",
+        "inflight", "peak_inflight")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -119,6 +146,14 @@ def load() -> ctypes.CDLL:
         "rc_graph_create": ([P, ctypes.POINTER(rc_job), I32, P, P, ctypes.POINTER(P)], S),
         "rc_graph_launch": ([P, P], S),
         "rc_graph_destroy": ([P], None),
+        "rc_serve_start": ([P, ctypes.POINTER(rc_serve_opts)], S),
+        "rc_serve_stop": ([P], S),
+        "rc_serve_submit": ([P, ctypes.POINTER(rc_request), ctypes.POINTER(U64)], S),
+        "rc_serve_poll": ([P, U64, I64, ctypes.POINTER(P), ctypes.POINTER(P),
+                           ctypes.POINTER(ctypes.c_double)], S),
+        "rc_serve_release": ([P, U64], S),
+        "rc_serve_copy": ([P, U64, P, P, ctypes.c_int], S),
+        "rc_serve_get_stats": ([P, ctypes.POINTER(rc_serve_stats)], S),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -203,10 +238,13 @@ class Context:
         _check(load().rc_scene_upload(self._h, vp, nv, tp, nt, int(on_dev), sp, ctypes.byref(out)))
         return out.value
 
+    def _sp(self, stream) -> int:
+        return 0 if self.device == RC_DEVICE_MOCK else _stream_ptr(stream)
+
     def build(self, scene: int, morton_bits: int = 10, node_format: int = RC_NODE_FP32,
               stream=None):
         o = rc_build_opts(morton_bits, node_format)
-        _check(load().rc_lbvh_build(self._h, scene, ctypes.byref(o), _stream_ptr(stream)))
+        _check(load().rc_lbvh_build(self._h, scene, ctypes.byref(o), self._sp(stream)))
 
     def release_scene(self, scene: int):
         _check(load().rc_scene_release(self._h, scene))
@@ -301,6 +339,52 @@ class Context:
 
     def graph(self, jobs: Sequence[Job], out_range, out_hit) -> "Graph":
         return Graph(self, jobs, out_range, out_hit)
+
+    # -- serving -------------------------------------------------------------
+    def serve_start(self, arena_bytes: int = 0, max_inflight: int = 0, max_batch_rays_m: int = 0,
+                    mock_ns_per_ray: int = 0, mock_fail_scene: int = 0):
+        o = rc_serve_opts(arena_bytes, max_inflight, max_batch_rays_m, mock_ns_per_ray,
+                          mock_fail_scene)
+        _check(load().rc_serve_start(self._h, ctypes.byref(o)))
+
+    def serve_stop(self):
+        _check(load().rc_serve_stop(self._h))
+
+    def submit(self, scene: int, pattern: int, poses, t_min: float, t_max: float) -> int:
+        """Queue a request; poses are host float32 [n_envs, 12] (copied)."""
+        p = np.ascontiguousarray(poses, np.float32).reshape(-1, 12)
+        rq = rc_request(int(scene), int(pattern), p.shape[0], 0, p.ctypes.data, float(t_min),
+                        float(t_max))
+        t = ctypes.c_uint64()
+        _check(load().rc_serve_submit(self._h, ctypes.byref(rq), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, timeout_us: int = 0):
+        """(status, latency_ms); status RC_OK, RC_PENDING or an error code."""
+        r, h = ctypes.c_void_p(), ctypes.c_void_p()
+        lat = ctypes.c_double()
+        st = load().rc_serve_poll(self._h, int(ticket), int(timeout_us), ctypes.byref(r),
+                                  ctypes.byref(h), ctypes.byref(lat))
+        return st, float(lat.value)
+
+    def fetch(self, ticket: int, n_rays: int):
+        """Copy a finished ticket's results to host numpy arrays."""
+        rng = np.empty(n_rays, np.float32)
+        hit = np.empty(n_rays, np.int32)
+        _check(load().rc_serve_copy(self._h, int(ticket), rng.ctypes.data, hit.ctypes.data, 1))
+        return rng, hit
+
+    def fetch_into(self, ticket: int, out_range, out_hit):
+        """Copy a finished ticket's results into device tensors."""
+        _check(load().rc_serve_copy(self._h, int(ticket), _ptr(out_range), _ptr(out_hit), 0))
+
+    def release(self, ticket: int):
+        _check(load().rc_serve_release(self._h, int(ticket)))
+
+    def serve_stats(self) -> dict:
+        st = rc_serve_stats()
+        _check(load().rc_serve_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
 
     def total_rays(self, jobs: Sequence[Job]) -> int:
         return max((j.out_offset + j.n_envs * self.n_beams(j.pattern) for j in jobs), default=0)

@@ -1,0 +1,117 @@
+"""Serving on the GPU: each request's result is bit-identical whether cast
+alone or served in a continuously batched mix of scenes (FP32 and Q8
+nodes), environment counts and beam patterns; admission stays within the
+arena; results survive concurrent submitters."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import cuda, log
+from paper_2509_17390_amd import Context, Job, RcastError
+from paper_2509_17390_amd.rcast import RC_OK
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def world():
+    import torch
+    assert torch.cuda.is_available()
+    ctx = Context(0)
+    scenes = []
+    a = synth.room_sphere_scene(2)
+    sa = ctx.upload_scene(a.verts, a.tris)
+    ctx.build(sa, node_format=0)
+    scenes.append((sa, synth.free_space_poses(synth.indoor_sdf(0, n_prims=0), 64, 1)))
+    for k, fmt in ((1, 1), (2, 0)):
+        sdf = synth.indoor_sdf(20 + k, n_prims=80)
+        v, t = synth.polygonise(sdf, 0.08)
+        s = ctx.upload_scene(v, t)
+        ctx.build(s, node_format=fmt)
+        scenes.append((s, synth.free_space_poses(sdf, 64, 2 + k)))
+    pats = [(ctx.upload_pattern(synth.lidar_pattern(16, -15, 15, 360), 360), 5760),
+            (ctx.upload_pattern(synth.lidar_pattern(32, -16, 15, 512), 512), 16384),
+            (ctx.upload_pattern(synth.lidar_pattern(8, -10, 10, 100), 100), 800)]
+    yield ctx, scenes, pats
+    ctx.close()
+
+
+def make_requests(scenes, pats, n, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        s, pool = scenes[rng.integers(len(scenes))]
+        p, nb = pats[rng.integers(len(pats))]
+        envs = int(rng.integers(1, 9))
+        idx = rng.choice(len(pool), envs, replace=False)
+        reqs.append(dict(scene=s, pattern=p, n_beams=nb, poses=pool[idx],
+                         t_min=float(rng.choice([0.0, 0.1])), t_max=float(rng.choice([30.0, 120.0]))))
+    return reqs
+
+
+def cast_alone(ctx, r):
+    import torch
+    rng, hit = ctx.cast([Job(r["scene"], r["pattern"], cuda(r["poses"]), r["t_min"], r["t_max"])])
+    torch.cuda.synchronize()
+    return rng.cpu().numpy(), hit.cpu().numpy()
+
+
+def test_served_results_equal_alone(world):
+    ctx, scenes, pats = world
+    reqs = make_requests(scenes, pats, 40, 0)
+    alone = [cast_alone(ctx, r) for r in reqs]
+    ctx.serve_start(arena_bytes=256 << 20, max_inflight=3)
+    try:
+        tickets = [None] * len(reqs)
+
+        def submitter(part):
+            for i in range(part, len(reqs), 2):
+                r = reqs[i]
+                tickets[i] = ctx.submit(r["scene"], r["pattern"], r["poses"], r["t_min"], r["t_max"])
+                time.sleep(0.0005 * (i % 3))
+
+        th = [threading.Thread(target=submitter, args=(k,)) for k in range(2)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        log("served mix submitted")
+        for i, r in enumerate(reqs):
+            st, lat = ctx.poll(tickets[i], 30_000_000)
+            assert st == RC_OK, (i, st)
+            n = len(r["poses"]) * r["n_beams"]
+            rng, hit = ctx.fetch(tickets[i], n)
+            assert np.array_equal(hit, alone[i][1]), i
+            assert np.array_equal(rng.view(np.int32), alone[i][0].view(np.int32)), i
+            ctx.release(tickets[i])
+        s = ctx.serve_stats()
+        log(str(s))
+        assert s["completed"] == len(reqs) and s["bytes_in_use"] == 0
+        assert s["launches"] <= len(reqs)
+    finally:
+        ctx.serve_stop()
+
+
+def test_admission_within_small_arena(world):
+    ctx, scenes, pats = world
+    reqs = make_requests(scenes, pats, 30, 1)
+    arena = 2 << 20          # (2 MiB - 256 KiB) / 8 = 229,376 rays of output
+    ctx.serve_start(arena_bytes=arena, max_inflight=2)
+    try:
+        ts = [ctx.submit(r["scene"], r["pattern"], r["poses"], r["t_min"], r["t_max"])
+              for r in reqs]
+        for i, tk in enumerate(ts):
+            st, _ = ctx.poll(tk, 30_000_000)
+            assert st == RC_OK
+            ctx.release(tk)
+        s = ctx.serve_stats()
+        assert s["peak_bytes"] <= arena and s["completed"] == len(reqs)
+        with pytest.raises(RcastError) as e:
+            big = np.repeat(scenes[0][1][:1], 64, 0)
+            ctx.submit(scenes[0][0], pats[1][0], big, 0.0, 10.0)   # 1M rays: never fits
+        assert e.value.status == -2
+    finally:
+        ctx.serve_stop()
