@@ -107,6 +107,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shape (profiling runs)")
+    ap.add_argument("--workload", choices=("batched", "uneven", "serve"), default="batched",
+                    help="batched: 4096 envs on the 1M-triangle mesh (default); uneven: 64 "
+                         "resident terrains, 1024 envs, mixed patterns in one launch; serve: "
+                         "Poisson requests against 16 resident scenes, served vs per-request")
+    ap.add_argument("--scenes", type=int, default=0, help="uneven/serve: scene count override")
+    ap.add_argument("--requests", type=int, default=200, help="serve: requests per rate")
+    ap.add_argument("--rates", type=str, default="0.3,0.6,0.9",
+                    help="serve: arrival rates as fractions of the measured capacity")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -114,6 +122,11 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         log("bench.py: only --gpus 1 is supported (single-GPU build)")
         return 2
+
+    if args.workload == "uneven":
+        return run_uneven(args)
+    if args.workload == "serve":
+        return run_serve(args)
 
     import torch
     import synth
@@ -272,6 +285,250 @@ def main():
         "stats_pass_matches": same and same_q8,
         "bvh_depth": info.depth,
         "serving": None,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+def _stats_bytes(ctx, jobs, n_rays, torch, dev, stream):
+    """Mean node records / triangle tests per ray of the current launch form."""
+    nn = torch.empty(n_rays, dtype=torch.int32, device=dev)
+    nt = torch.empty(n_rays, dtype=torch.int32, device=dev)
+    r = torch.empty(n_rays, dtype=torch.float32, device=dev)
+    h = torch.empty(n_rays, dtype=torch.int32, device=dev)
+    ctx.raycast(jobs, r, h, stream=stream, mode="stats", out_nodes=nn, out_tris=nt)
+    torch.cuda.synchronize()
+    return float(nn.double().mean()), float(nt.double().mean())
+
+
+def run_uneven(args):
+    """64 resident terrain scenes (50k..5M triangles, log-uniform), 1024
+    environments each bound to a random scene and one of three beam patterns
+    (16x360, 64x1024, 128x2048), cast in one batched launch.  Scenes and
+    BVHs are resident (built once, timed separately); a step is one launch."""
+    import torch
+    import synth
+    from paper_2509_17390_amd import Context, Job
+
+    dev = torch.device("cuda", 0)
+    n_scenes = args.scenes or 64
+    log(f"generating {n_scenes} terrains ...")
+    w = synth.uneven_world(seed=0, n_scenes=n_scenes, n_envs=1024)
+    tris_total = int(sum(len(t) for _, t in w.scenes))
+    ctx = Context(0)
+    stream = torch.cuda.current_stream()
+    sids = [ctx.upload_scene(v, t) for v, t in w.scenes]
+    pids = [ctx.upload_pattern(d, na) for d, na in zip(w.patterns, w.n_az)]
+    # one job per (scene, pattern) group of environments
+    jobs, off = [], 0
+    poses_keep = []
+    for k in range(n_scenes):
+        for pi in range(len(w.patterns)):
+            idx = np.flatnonzero((w.env_scene == k) & (w.env_pattern == pi))
+            if len(idx) == 0:
+                continue
+            pt = torch.from_numpy(w.poses[idx]).to(dev)
+            poses_keep.append(pt)
+            jobs.append(Job(sids[k], pids[pi], pt, w.t_min, w.t_max, off))
+            off += len(idx) * len(w.patterns[pi])
+    n_rays = off
+    out_r = torch.empty(n_rays, dtype=torch.float32, device=dev)
+    out_h = torch.empty(n_rays, dtype=torch.int32, device=dev)
+    forms, outputs = {}, {}
+    for name, fmt in (("fp32", 0), ("q8", 1)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for sid in sids:
+            ctx.build(sid, node_format=fmt, stream=stream)
+        torch.cuda.synchronize()
+        build_ms = (time.perf_counter() - t0) * 1e3
+        best, _ = ctx.autotune(jobs, out_r, out_h, reps=1, stream=stream)
+        graph = ctx.graph(jobs, out_r, out_h)
+        for _ in range(args.warmup):
+            graph.launch(stream)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for a, b in evs:
+            a.record(stream)
+            graph.launch(stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        kms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        graph.close()
+        outputs[name] = (out_r.clone(), out_h.clone())
+        nodes, tt = _stats_bytes(ctx, jobs, n_rays, torch, dev, stream)
+        forms[name] = {"ms_per_step": round(ms, 3), "Mrays_s": round(n_rays / ms / 1e3, 2),
+                       "kernel_ms": round(kms, 3), "build_all_scenes_ms": round(build_ms, 1),
+                       "tuning": best, "mean_node_records": round(nodes, 2),
+                       "mean_tri_tests": round(tt, 2)}
+        log(f"uneven {name}: {ms:.2f} ms/launch, {forms[name]['Mrays_s']} Mrays/s")
+    same = bool(torch.equal(outputs["fp32"][1], outputs["q8"][1]) and
+                torch.equal(outputs["fp32"][0].view(torch.int32), outputs["q8"][0].view(torch.int32)))
+    b_ray = NODE_BYTES * forms["fp32"]["mean_node_records"] + TRI_BYTES * forms["fp32"]["mean_tri_tests"] + OUT_BYTES
+    kms = forms["q8"]["kernel_ms"]
+    achieved = b_ray * n_rays / (kms * 1e-3) / 1e9
+    out = {
+        "metric": "Mrays/s, uneven batch: 64 resident scenes, 1024 envs, mixed patterns, one launch",
+        "value": forms["q8"]["Mrays_s"], "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": forms["q8"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{n_scenes} terrains ({tris_total} triangles in total), 1024 envs "
+                               f"over {len(jobs)} jobs, patterns 16x360 / 64x1024 / 128x2048, "
+                               f"step = one graph-replayed launch on resident Q8 BVHs",
+                   "scenes": n_scenes, "tris_total": tris_total, "envs": 1024, "jobs": len(jobs),
+                   "rays_per_step": int(n_rays), "node_format": "q8"},
+        "forms": forms, "forms_bit_identical": same,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_ray": round(b_ray, 1)},
+        "misses": int((outputs["q8"][1] < 0).sum()),
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+def run_serve(args):
+    """Poisson-arriving requests against 16 resident terrain scenes.  Each
+    request: 1..4096 environments (log-uniform), a pattern of 16/32/64/128
+    rings x 360..2048 azimuths, a random scene.  Served: continuous batching
+    on Q8 BVHs (rc_serve_*).  Baseline: the same requests one at a time in
+    arrival order with plain FP32 BVHs (rc_raycast_batch + synchronize).
+    Rates are fractions of the server's measured capacity."""
+    import threading
+
+    import torch
+    import synth
+    from paper_2509_17390_amd import Context, Job
+    from paper_2509_17390_amd.rcast import RC_OK
+
+    dev = torch.device("cuda", 0)
+    n_scenes = args.scenes or 16
+    rng = np.random.default_rng(1)
+    log(f"generating {n_scenes} terrains ...")
+    sizes = np.exp(rng.uniform(np.log(5e4), np.log(5e6), n_scenes))
+    ctx = Context(0)
+    stream = torch.cuda.current_stream()
+    q8_ids, fp_ids, pose_pools = [], [], []
+    for k, n in enumerate(sizes):
+        v, t, height, boxes = synth.terrain_scene(500 + k, int(n))
+        a = ctx.upload_scene(v, t)
+        ctx.build(a, node_format=1, stream=stream)
+        b = ctx.upload_scene(v, t)
+        ctx.build(b, node_format=0, stream=stream)
+        q8_ids.append(a)
+        fp_ids.append(b)
+        pose_pools.append(synth.terrain_poses(height, boxes, 256, 900 + k))
+    torch.cuda.synchronize()
+    spans = {16: (-15.0, 15.0), 32: (-16.0, 15.0), 64: (-25.0, 3.0), 128: (-22.5, 22.5)}
+    bank = []
+    for ne in (16, 32, 64, 128):
+        for na in (360, 512, 1024, 1440, 2048):
+            lo, hi = spans[ne]
+            bank.append((ctx.upload_pattern(synth.lidar_pattern(ne, lo, hi, na), na), ne * na))
+
+    def make_reqs(n, seed):
+        g = np.random.default_rng(seed)
+        out = []
+        for _ in range(n):
+            envs = int(min(4096, max(1, round(np.exp(g.uniform(0, np.log(4096)))))))
+            sc = int(g.integers(n_scenes))
+            pi = int(g.integers(len(bank)))
+            pool = pose_pools[sc]
+            poses = pool[g.integers(0, len(pool), envs)]
+            out.append((sc, pi, poses, envs * bank[pi][1]))
+        return out
+
+    def serve_run(reqs, arrivals):
+        ctx.serve_start(arena_bytes=48 << 30, max_inflight=3)
+        tickets = [None] * len(reqs)
+        t0 = time.perf_counter()
+
+        def submitter():
+            for i, (sc, pi, poses, _) in enumerate(reqs):
+                dt = arrivals[i] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[i] = ctx.submit(q8_ids[sc], bank[pi][0], poses, 0.1, 120.0)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        lat = []
+        for i in range(len(reqs)):
+            while tickets[i] is None:
+                time.sleep(0.0002)
+            st, l = ctx.poll(tickets[i], -1)
+            assert st == RC_OK, st
+            lat.append(l)
+            ctx.release(tickets[i])
+        th.join()
+        wall = time.perf_counter() - t0
+        stats = ctx.serve_stats()
+        ctx.serve_stop()
+        return np.array(lat), wall, stats
+
+    def baseline_run(reqs, arrivals):
+        lat = []
+        t0 = time.perf_counter()
+        for i, (sc, pi, poses, n) in enumerate(reqs):
+            dt = arrivals[i] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            r = torch.empty(n, dtype=torch.float32, device=dev)
+            h = torch.empty(n, dtype=torch.int32, device=dev)
+            pd = torch.from_numpy(poses).to(dev)
+            ctx.raycast([Job(fp_ids[sc], bank[pi][0], pd, 0.1, 120.0)], r, h, stream=stream)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0 - arrivals[i]) * 1e3)
+            del r, h, pd
+        return np.array(lat), time.perf_counter() - t0
+
+    # capacity: everything submitted at once
+    calib = make_reqs(args.requests, 7)
+    lat, wall, _ = serve_run(calib, np.zeros(len(calib)))
+    rays = sum(r[3] for r in calib)
+    cap_rps = len(calib) / wall
+    log(f"capacity {cap_rps:.1f} req/s, {rays / wall / 1e6:.0f} Mrays/s saturated")
+    rates = [float(x) for x in args.rates.split(",")]
+    results = []
+    for k, frac in enumerate(rates):
+        lam = frac * cap_rps
+        reqs = make_reqs(args.requests, 100 + k)
+        arrivals = np.cumsum(np.random.default_rng(200 + k).exponential(1.0 / lam, len(reqs)))
+        arrivals -= arrivals[0]
+        rays = sum(r[3] for r in reqs)
+        sl, sw, st = serve_run(reqs, arrivals)
+        bl, bw = baseline_run(reqs, arrivals)
+        results.append({
+            "rate_frac": frac, "lambda_req_s": round(lam, 2), "requests": len(reqs),
+            "mean_rays_per_request": round(rays / len(reqs)),
+            "served": {"p50_ms": round(float(np.percentile(sl, 50)), 3),
+                       "p99_ms": round(float(np.percentile(sl, 99)), 3),
+                       "Mrays_s": round(rays / sw / 1e6, 1), "launches": st["launches"],
+                       "max_batch_requests": st["max_batch_requests"],
+                       "peak_inflight": st["peak_inflight"],
+                       "peak_arena_GB": round(st["peak_bytes"] / 1e9, 2)},
+            "per_request_fp32": {"p50_ms": round(float(np.percentile(bl, 50)), 3),
+                                 "p99_ms": round(float(np.percentile(bl, 99)), 3),
+                                 "Mrays_s": round(rays / bw / 1e6, 1)},
+        })
+        log(json.dumps(results[-1]))
+    head = results[-1]
+    out = {
+        "metric": "p50/p99 request latency and Mrays/s, served (Q8, continuous batching) vs "
+                  "plain per-request FP32",
+        "value": head["served"]["Mrays_s"], "unit": "Mrays/s", "n_gpus": 1,
+        "steps": args.requests, "warmup": 0, "ms_per_step": head["served"]["p50_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"Poisson requests, {n_scenes} resident terrains "
+                               f"({int(sizes.sum())} triangles), 1..4096 envs, 20 patterns",
+                   "capacity_req_s": round(cap_rps, 2)},
+        "rates": results,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

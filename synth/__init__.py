@@ -424,3 +424,56 @@ def terrain_poses(height, boxes, n: int, seed: int, size: float = 200.0):
         z = float(height(x, y)) + rng.uniform(1.5, 3.0)
         out.append(yaw_pose((x, y, z), rng.uniform(0.0, 2.0 * math.pi)))
     return np.ascontiguousarray(np.stack(out))
+
+
+# --------------------------------------------------------------------------
+# Uneven multi-scene batch
+
+UNEVEN_PATTERNS = (
+    # (n_el, el_lo, el_hi, n_az)
+    (16, -15.0, 15.0, 360),
+    (64, -25.0, 3.0, 1024),
+    (128, -22.5, 22.5, 2048),
+)
+
+
+@dataclasses.dataclass
+class UnevenWorld:
+    scenes: list            # [(verts, tris)]
+    env_scene: np.ndarray   # int32 [E]: scene of each environment
+    env_pattern: np.ndarray # int32 [E]: index into patterns
+    poses: np.ndarray       # float32 [E, 12]
+    patterns: list          # float32 [B_i, 3] per pattern
+    n_az: list
+    t_min: float = 0.1
+    t_max: float = 120.0
+
+    @property
+    def n_rays(self) -> int:
+        return int(sum(len(self.patterns[p]) for p in self.env_pattern))
+
+
+def uneven_world(seed: int = 0, n_scenes: int = 64, n_envs: int = 1024,
+                 tri_lo: float = 50_000, tri_hi: float = 5_000_000) -> UnevenWorld:
+    """Resident outdoor scenes with log-uniform triangle counts in
+    [tri_lo, tri_hi] (heightfield + 50..500 boxes each); every environment is
+    bound to a uniformly drawn scene and beam pattern, with a pose 1.5..3 m
+    above that scene's ground."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(math.log(tri_lo), math.log(tri_hi), n_scenes))
+    scenes, samplers = [], []
+    for k, n in enumerate(sizes):
+        v, t, height, boxes = terrain_scene(seed * 1000 + k, int(n))
+        scenes.append((v, t))
+        samplers.append((height, boxes))
+    env_scene = rng.integers(0, n_scenes, n_envs).astype(np.int32)
+    env_pattern = rng.integers(0, len(UNEVEN_PATTERNS), n_envs).astype(np.int32)
+    poses = np.zeros((n_envs, 12), np.float32)
+    for k in range(n_scenes):
+        idx = np.flatnonzero(env_scene == k)
+        if len(idx):
+            h, b = samplers[k]
+            poses[idx] = terrain_poses(h, b, len(idx), seed * 7919 + k)
+    patterns = [lidar_pattern(ne, lo, hi, na) for ne, lo, hi, na in UNEVEN_PATTERNS]
+    return UnevenWorld(scenes, env_scene, env_pattern, poses, patterns,
+                       [p[3] for p in UNEVEN_PATTERNS])

@@ -380,3 +380,38 @@ def test_graph_replays_match_eager(ctx, fmt, persistent):
         g.close()
     finally:
         ctx.reset_tuning()
+
+
+def test_uneven_multi_scene_batch(ctx):
+    # several resident terrains, environments bound to random scenes and to
+    # three beam patterns, all in one launch: equal to each job cast alone,
+    # and to the oracle on a sample of every job's rays
+    import torch
+    w = synth.uneven_world(seed=3, n_scenes=5, n_envs=20, tri_lo=20_000, tri_hi=150_000)
+    sids = [ctx.upload_scene(v, t) for v, t in w.scenes]
+    for k, sid in enumerate(sids):
+        ctx.build(sid, node_format=k % 2)   # FP32 and Q8 scenes in one launch
+    pids = [ctx.upload_pattern(d, na) for d, na in zip(w.patterns, w.n_az)]
+    jobs, meta, off = [], [], 0
+    for k in range(len(sids)):
+        for pi in range(len(pids)):
+            idx = np.flatnonzero((w.env_scene == k) & (w.env_pattern == pi))
+            if len(idx):
+                jobs.append(Job(sids[k], pids[pi], cuda(w.poses[idx]), w.t_min, w.t_max, off))
+                meta.append((k, pi, idx))
+                off += len(idx) * len(w.patterns[pi])
+    log(f"uneven batch: {len(jobs)} jobs, {off} rays")
+    r_all, h_all = ctx.cast(jobs)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    for j, (k, pi, idx) in zip(jobs, meta):
+        n = len(idx) * len(w.patterns[pi])
+        r1, h1 = ctx.cast([Job(j.scene, j.pattern, j.poses, j.t_min, j.t_max, 0)])
+        sl = slice(j.out_offset, j.out_offset + n)
+        assert torch.equal(h_all[sl], h1) and torch.equal(r_all[sl].view(torch.int32),
+                                                          r1.view(torch.int32))
+        v, t = w.scenes[k]
+        sample = np.sort(rng.choice(n, min(n, 150), replace=False))
+        compare_with_oracle(v, t, w.poses[idx], w.patterns[pi], w.t_min, w.t_max,
+                            r1.cpu().numpy(), h1.cpu().numpy(), ray_idx=sample,
+                            min_checked_frac=0.9)
