@@ -51,6 +51,7 @@
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int64_t kMaxRaysPerDispatch = (int64_t)1 << 30;
 constexpr int kStack = 64;           // >= depth of any Karras tree (62 key bits)
 constexpr float kErrU = 2.384185791015625e-07f;  // 2^-22: sign certificate factor
 constexpr float kBoxGrow = 7.152557373046875e-07f;  // 12u > 2 gamma_3: far-distance growth
@@ -479,14 +480,15 @@ __device__ __forceinline__ void finish_ray(const LaneRay &L, float *__restrict__
 // One ray per thread (also the brute-force cross-check).
 template <int MODE, int FMT, int SS, int WAVES>
 __global__ __launch_bounds__(kBlock, WAVES) void k_trace(const DevJob *__restrict__ jobs, int n_jobs,
-                                                  int64_t total, float *__restrict__ out_range,
+                                                  int64_t g0, int64_t total,
+                                                  float *__restrict__ out_range,
                                                   int32_t *__restrict__ out_hit,
                                                   int32_t *__restrict__ out_nodes,
                                                   int32_t *__restrict__ out_tris)
 {
     __shared__ int s_node[SS > 0 ? SS * kBlock : 1];
     __shared__ float s_t[SS > 0 ? SS * kBlock : 1];
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t g = g0 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (g >= total) return;
     LaneRay L;
     LaneStack<SS, FMT == FMT_Q8 ? kStackQ8 : kStack> S;
@@ -640,18 +642,25 @@ hipError_t launch_mode(const TraceConfig &cfg, const DevJob *jobs, int n_jobs, W
                                                     out_nodes, out_tris, s);
         }
     }
-    const dim3 grid((unsigned)((total + kBlock - 1) / kBlock));
+    // one thread per ray; a dispatch holds at most 2^32 work-items, so large
+    // batches go out as several dispatches of kMaxRaysPerDispatch rays
+    for (int64_t g0 = 0; g0 < total; g0 += kMaxRaysPerDispatch) {
+        const int64_t n = total - g0 < kMaxRaysPerDispatch ? total - g0 : kMaxRaysPerDispatch;
+        const dim3 grid((unsigned)((n + kBlock - 1) / kBlock));
 #define RC_GRID(SS_, W_)                                                                     \
-    hipLaunchKernelGGL((k_trace<MODE, FMT, SS_, W_>), grid, dim3(kBlock), 0, s, jobs, n_jobs,    \
-                       total, out_range, out_hit, out_nodes, out_tris)
-    if (MODE == TRACE_BRUTE) RC_GRID(0, 1);
-    else if (cfg.stack_lds == 0 && cfg.waves_cap) RC_GRID(0, 8);
-    else if (cfg.stack_lds == 0) RC_GRID(0, 1);
-    else if (cfg.stack_lds == 8 && cfg.waves_cap) RC_GRID(8, 8);
-    else if (cfg.stack_lds == 8) RC_GRID(8, 1);
-    else RC_GRID(16, 1);
+        hipLaunchKernelGGL((k_trace<MODE, FMT, SS_, W_>), grid, dim3(kBlock), 0, s, jobs,        \
+                           n_jobs, g0, total, out_range, out_hit, out_nodes, out_tris)
+        if (MODE == TRACE_BRUTE) RC_GRID(0, 1);
+        else if (cfg.stack_lds == 0 && cfg.waves_cap) RC_GRID(0, 8);
+        else if (cfg.stack_lds == 0) RC_GRID(0, 1);
+        else if (cfg.stack_lds == 8 && cfg.waves_cap) RC_GRID(8, 8);
+        else if (cfg.stack_lds == 8) RC_GRID(8, 1);
+        else RC_GRID(16, 1);
 #undef RC_GRID
-    return hipGetLastError();
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace

@@ -415,3 +415,35 @@ def test_uneven_multi_scene_batch(ctx):
         compare_with_oracle(v, t, w.poses[idx], w.patterns[pi], w.t_min, w.t_max,
                             r1.cpu().numpy(), h1.cpu().numpy(), ray_idx=sample,
                             min_checked_frac=0.9)
+
+
+def test_batch_larger_than_one_dispatch(ctx):
+    # 3 jobs x 1.5e9 rays = 4.5e9 rays in one call: more work-items than one
+    # dispatch can hold, so the library splits the launch; every ray must be
+    # written.  A single triangle keeps the traversal trivial.
+    import torch
+    tri = np.array([[5, -50, -50], [5, 50, -50], [5, 0, 50]], np.float32)
+    s1 = ctx.upload_scene(tri, np.array([[0, 1, 2]], np.int32))
+    ctx.build(s1)
+    nb = 1 << 15
+    az = np.linspace(-0.5, 0.5, nb)
+    dirs = np.stack([np.cos(az), np.sin(az), np.zeros(nb)], -1).astype(np.float32)
+    pat = ctx.upload_pattern(dirs, nb)
+    envs = 45_776          # x 32768 beams = 1.5e9 rays per job
+    pose = cuda(np.repeat(synth.yaw_pose((0, 0, 0), 0.0)[None], envs, 0))
+    per = envs * nb
+    total = 3 * per
+    assert total > 2 ** 32
+    r = torch.full((total,), -1.0, dtype=torch.float32, device="cuda")
+    h = torch.full((total,), -7, dtype=torch.int32, device="cuda")
+    jobs = [Job(s1, pat, pose, 0.0, 100.0, k * per) for k in range(3)]
+    log(f"batch of {total} rays")
+    ctx.raycast(jobs, r, h)
+    torch.cuda.synchronize()
+    assert bool((h == 0).all())
+    exp = torch.from_numpy((5.0 / np.cos(az)).astype(np.float32)).cuda()
+    last = r[-nb:]
+    assert float((last - exp).abs().max()) < 1e-4
+    del r, h
+    torch.cuda.empty_cache()
+    ctx.release_scene(s1)
