@@ -65,6 +65,41 @@ struct RayW {
     float inv[3];      // 1 / direction, world axes (clamped away from 0)
 };
 
+// Node and triangle records are read through global-address-space pointers:
+// the record arrays are reached through the job table, so the compiler would
+// otherwise emit flat loads, which must be waited for as a group (they count
+// on both the vector-memory and the LDS counters) and cannot use the global
+// addressing forms.
+typedef float gvec4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const gvec4 gvec4_g;
+
+__device__ __forceinline__ float4 ldg4(const void *p, int64_t i)
+{
+    const gvec4 v = ((const gvec4_g *)p)[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ NodeRec load_node(const NodeRec *nodes, int i)
+{
+    NodeRec n;
+    n.q0 = ldg4(nodes, 4 * (int64_t)i);
+    n.q1 = ldg4(nodes, 4 * (int64_t)i + 1);
+    n.q2 = ldg4(nodes, 4 * (int64_t)i + 2);
+    const float4 w = ldg4(nodes, 4 * (int64_t)i + 3);
+    n.q3 = make_int4(__float_as_int(w.x), __float_as_int(w.y), __float_as_int(w.z),
+                     __float_as_int(w.w));
+    return n;
+}
+
+__device__ __forceinline__ TriRec load_tri(const TriRec *tris, int i)
+{
+    TriRec t;
+    t.a = ldg4(tris, 3 * (int64_t)i);
+    t.b = ldg4(tris, 3 * (int64_t)i + 1);
+    t.c = ldg4(tris, 3 * (int64_t)i + 2);
+    return t;
+}
+
 __device__ __forceinline__ float sel3(float a, float b, float c, int k)
 {
     return k == 0 ? a : (k == 1 ? b : c);
@@ -261,7 +296,7 @@ __device__ __forceinline__ uint32_t tile_beam(const DevJob &jb, uint32_t q)
 
 __device__ __forceinline__ void test_leaf(LaneRay &L, int leaf)
 {
-    const TriRec tr = L.tris[leaf];
+    const TriRec tr = load_tri(L.tris, leaf);
     float t;
     ++L.n_tris;
     if (woop32(L.r, tr.a, tr.b, tr.c, &t) && t >= L.t_min && t <= L.t_max) {
@@ -321,7 +356,7 @@ __device__ __forceinline__ bool node_step(LaneRay &L, LaneStack<SS, STK> &S)
     // a correct traversal fetches each of the n_tris - 1 records at most
     // once; the cap only guards against a corrupted tree
     if (++L.fetched > L.n_tris_scene + 64) { L.corrupt = true; return true; }
-    const NodeRec nd = L.nodes[L.node];
+    const NodeRec nd = load_node(L.nodes, L.node);
     ++L.n_nodes;
     const float tl = slab(L.r, nd.q0.x, nd.q0.y, nd.q1.x, nd.q1.y, nd.q2.x, nd.q2.y, L.t_lo, L.t_hi);
     const float tr = slab(L.r, nd.q0.z, nd.q0.w, nd.q1.z, nd.q1.w, nd.q2.z, nd.q2.w, L.t_lo, L.t_hi);
@@ -381,7 +416,7 @@ template <int SS, int STK>
 __device__ __forceinline__ bool node_step_q8(LaneRay &L, LaneStack<SS, STK> &S)
 {
     if (++L.fetched > L.n_tris_scene + 64) { L.corrupt = true; return true; }
-    const NodeRec nd = L.nodes[L.node];
+    const NodeRec nd = load_node(L.nodes, L.node);
     ++L.n_nodes;
     const float org[3] = {nd.q0.x, nd.q0.y, nd.q0.z};
     const float scl[3] = {nd.q0.w, nd.q1.x, nd.q1.y};
@@ -425,17 +460,36 @@ __device__ __forceinline__ bool node_step_q8(LaneRay &L, LaneStack<SS, STK> &S)
     }
     RC_CSWAP(0, 1) RC_CSWAP(2, 3) RC_CSWAP(0, 2) RC_CSWAP(1, 3) RC_CSWAP(1, 2)
 #undef RC_CSWAP
-    // leaves on the spot, nearest first
+    // leaves on the spot, nearest first.  One loop iteration per leaf of
+    // this lane (not one code copy per child slot), so lanes whose leaves sit
+    // in different slots test them together.
+    uint32_t lm = 0;
     for (int k = 0; k < 4; ++k)
-        if (ref[k] < 0 && t[k] <= L.t_hi) test_leaf(L, ~ref[k]);
-    // internal children: push farthest first, then continue with the nearest
+        lm |= (ref[k] < 0 && t[k] <= L.t_hi) ? 1u << k : 0u;
+#pragma unroll 1
+    while (lm != 0u) {
+        const int k = __builtin_ctz(lm);
+        lm &= lm - 1u;
+        const float tk = k == 0 ? t[0] : (k == 1 ? t[1] : (k == 2 ? t[2] : t[3]));
+        const int32_t rk = k == 0 ? ref[0] : (k == 1 ? ref[1] : (k == 2 ? ref[2] : ref[3]));
+        if (tk <= L.t_hi) test_leaf(L, ~rk);
+    }
+    // internal children: continue with the nearest, push the others
+    // farthest first
+    int next = -1;
+    float next_t = 0.0f;
     for (int k = 3; k >= 0; --k) {
         if (ref[k] >= 0 && t[k] <= L.t_hi) {
-            if (L.sp == STK) { L.corrupt = true; return true; }
-            S.put(L.sp, ref[k], t[k]);
-            ++L.sp;
+            if (next >= 0) {
+                if (L.sp == STK) { L.corrupt = true; return true; }
+                S.put(L.sp, next, next_t);
+                ++L.sp;
+            }
+            next = ref[k];
+            next_t = t[k];
         }
     }
+    if (next >= 0) { L.node = next; return false; }
     while (L.sp > 0) {
         --L.sp;
         int n;
@@ -463,7 +517,7 @@ __device__ __forceinline__ void finish_ray(const LaneRay &L, float *__restrict__
         out_range[L.out] = NAN;  // never a valid result: flags a broken hierarchy
         out_hit[L.out] = -2;
     } else if (L.best_leaf >= 0) {
-        const TriRec tr = L.tris[L.best_leaf];
+        const TriRec tr = load_tri(L.tris, L.best_leaf);
         out_range[L.out] = refine_range(L.pose, L.beam, tr, L.best_t);
         out_hit[L.out] = L.best_id;
     } else {
