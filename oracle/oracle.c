@@ -190,7 +190,8 @@ static void closest_hit(const double o[3], const double d[3],
  * and the smaller angle to a or b otherwise.
  *
  * A ray is "ambiguous" when a second triangle is hit within tol(t*) of t*,
- * or when any hit lies within tol of t_min or t_max; tol(t) = 1e-4 + 1e-6 t.
+ * or when any hit lies within tol of t_min or of a finite t_max;
+ * tol(t) = 1e-4 + 1e-6 t.
  * Several results are correct for such rays. */
 static double tol_of(double t) { return 1e-4 + 1e-6 * fabs(t); }
 
@@ -279,8 +280,9 @@ static void check_ray(const double o[3], const double d[3], const float *verts,
                              verts + 3 * (int64_t)tris[3 * k + 2]};
         double t;
         if (woop_test(&f, v[0], v[1], v[2], &t)) {
+            /* an infinite t_max has no neighbourhood: nothing is near it */
             if (fabs(t - t_min) <= tol_of(t_min) ||
-                fabs(t - t_max) <= tol_of(t_max))
+                (isfinite(t_max) && fabs(t - t_max) <= tol_of(t_max)))
                 fl |= FLAG_AMBIGUOUS;
             if (k != best_id && t >= t_min - tol_of(t_min) &&
                 t <= t_max + tol_of(t_max)) {

@@ -388,6 +388,14 @@ def test_ambiguous_flag():
     _, ii, fl, _, _ = oracle.raycast(v, t, pose_at((0.1, 0.3, 3.0))[None], d, 0.0, 3.00005,
                                      checked=True)
     assert fl[0] & oracle.FLAG_AMBIGUOUS
+    # an unbounded range (t_max = inf) has no upper end to be near: the same
+    # hit is clean, at the same distance, as under a distant finite bound
+    tt_inf, ii_inf, fl_inf, _, _ = oracle.raycast(v, t, pose_at((0.1, 0.3, 3.0))[None], d, 0.0,
+                                                  np.inf, checked=True)
+    tt_big, ii_big, fl_big, _, _ = oracle.raycast(v, t, pose_at((0.1, 0.3, 3.0))[None], d, 0.0,
+                                                  1e9, checked=True)
+    assert fl_inf[0] == fl_big[0] == 0
+    assert ii_inf[0] == ii_big[0] >= 0 and abs(tt_inf[0] - 3.0) < 1e-12
 
 
 def test_ray_index_sample_matches_full():
