@@ -86,13 +86,16 @@ def cpu_baseline(verts, tris, poses, dirs, t_min, t_max, g_range, g_hit, budget_
     gh, gr = g_hit[idx], g_range[idx]
     same_id = int((gh == ids).sum())
     ok = (gh == ids) & (ids >= 0)
-    rng_ok = int((np.abs(gr[ok] - t[ok]) <= 1e-4 + 1e-6 * t[ok]).sum())
+    err = np.abs(gr[ok].astype(np.float64) - t[ok])
+    rng_ok = int((err <= 1e-4 + 1e-6 * t[ok]).sum())
     return {
         "value": n / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
         "sample": f"{n} seeded rays of the same workload (all envs/beams), FP64 brute force "
                   f"over all {len(tris)} triangles, {dt:.1f} s",
         "gpu_agreement": {"rays": n, "same_id": same_id, "range_ok_of_same_id_hits": rng_ok,
-                          "hits": int((ids >= 0).sum())},
+                          "hits": int((ids >= 0).sum()),
+                          "max_range_err_m": float(err.max()) if err.size else 0.0,
+                          "max_rel_range_err": float((err / t[ok]).max()) if err.size else 0.0},
     }
 
 
@@ -411,7 +414,7 @@ def run_serve(args):
     import torch
     import synth
     from paper_2509_17390_amd import Context, Job
-    from paper_2509_17390_amd.rcast import RC_OK
+    from paper_2509_17390_amd.rcast import RC_OK, last_error
 
     dev = torch.device("cuda", 0)
     n_scenes = args.scenes or 16
@@ -470,7 +473,7 @@ def run_serve(args):
             while tickets[i] is None:
                 time.sleep(0.0002)
             st, l = ctx.poll(tickets[i], -1)
-            assert st == RC_OK, st
+            assert st == RC_OK, (st, last_error())
             lat.append(l)
             ctx.release(tickets[i])
         th.join()

@@ -109,11 +109,15 @@ void pick_tile(const rc_tuning &t, int32_t n_beams, int32_t n_az, DevJob &d)
     d.n_az = n_az;
     d.tile_az = n_az;
     d.tile_el = 1;
-    d.pad = 0;
     if (t.tile_az > 0 && t.tile_el > 0 && n_az % t.tile_az == 0 && n_el % t.tile_el == 0) {
         d.tile_az = t.tile_az;
         d.tile_el = t.tile_el;
     }
+    d.tiles_az = n_az / d.tile_az;
+    d.div_beams = udiv_magic((uint32_t)(n_beams > 0 ? n_beams : 1));
+    d.div_tile = udiv_magic((uint32_t)(d.tile_az * d.tile_el));
+    d.div_tiles_az = udiv_magic((uint32_t)(n_az / d.tile_az));
+    d.div_tile_az = udiv_magic((uint32_t)d.tile_az);
 }
 
 rc_status check_tuning(const rc_tuning *t);

@@ -328,12 +328,20 @@ __device__ __forceinline__ void store_child_box(NodeRec *node, int slot, const f
     q[4 + slot] = make_float2(lo[2], hi[2]);
 }
 
-// Bottom-up box reduction, one thread per leaf.  A block owns a chunk of
-// kRefitBlock consecutive leaves; a node whose leaf range lies inside the
-// chunk has both children finished by this block, so its arrival counter
-// lives in LDS and workgroup-scope ordering suffices.  Only nodes spanning
-// chunks (a few per chunk boundary and level) use agent-scope counters in
-// global memory, whose release/acquire order the node records across XCDs.
+// Bottom-up box reduction in two kernels.
+//
+// k_refit: one thread per leaf.  A block owns a chunk of kRefitBlock
+// consecutive leaves; a node whose leaf range lies inside the chunk has both
+// children finished by this block, so its arrival counter lives in LDS and
+// workgroup-scope ordering suffices.  A thread whose walk reaches a node
+// spanning chunks writes its child box there and leaves the node on a list.
+//
+// k_refit_top: one block finishes the spanning nodes (a few per chunk
+// boundary and level) with arrival counters in global memory.  The kernel
+// boundary publishes the first kernel's records, and inside one block
+// workgroup-scope ordering suffices again, so no step needs the agent-scope
+// release/acquire that would write back and invalidate whole L2 caches
+// (one per XCD) on every arrival.
 constexpr int kRefitBlock = 1024;
 
 __global__ __launch_bounds__(kRefitBlock) void k_refit(const float *__restrict__ bounds,
@@ -341,9 +349,10 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(const float *__restrict__
                                                        int64_t n, const int32_t *__restrict__ topo,
                                                        const int32_t *__restrict__ leaf_parent,
                                                        const int2 *__restrict__ range,
-                                                       uint32_t *__restrict__ arrive,
                                                        int32_t *__restrict__ height,
-                                                       NodeRec *nodes, int32_t *depth_out)
+                                                       NodeRec *nodes, int32_t *depth_out,
+                                                       int32_t *__restrict__ pend,
+                                                       uint32_t *__restrict__ pend_count)
 {
     __shared__ uint32_t local_arrive[kRefitBlock];
     local_arrive[threadIdx.x] = 0;
@@ -362,13 +371,16 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(const float *__restrict__
         store_child_box(nodes + p, slot, lo, hi);
         if (slot == 0) height[2 * p + 0] = h; else height[2 * p + 1] = h;
         const int2 rg = range[p];
-        uint32_t prev;
-        if (rg.x >= c0 && rg.y < c0 + kRefitBlock)
-            prev = __hip_atomic_fetch_add(local_arrive + (p - c0), 1u, __ATOMIC_ACQ_REL,
-                                          __HIP_MEMORY_SCOPE_WORKGROUP);
-        else
-            prev = __hip_atomic_fetch_add(arrive + p, 1u, __ATOMIC_ACQ_REL,
-                                          __HIP_MEMORY_SCOPE_AGENT);
+        if (rg.x < c0 || rg.y >= c0 + kRefitBlock) {
+            // spans chunks: finished by k_refit_top (a unique list slot is
+            // all this counter provides, so no ordering is asked of it)
+            const uint32_t at = __hip_atomic_fetch_add(pend_count, 1u, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            pend[at] = p;
+            return;
+        }
+        const uint32_t prev = __hip_atomic_fetch_add(local_arrive + (p - c0), 1u, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
         if (prev == 0) return;  // first arrival: the sibling finishes the node
         const NodeRec nr = nodes[p];
         lo[0] = fminf(nr.q0.x, nr.q0.z); hi[0] = fmaxf(nr.q0.y, nr.q0.w);
@@ -379,7 +391,41 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(const float *__restrict__
         child = p;
         p = topo[3 * p + 2];
     }
-    depth_out[0] = h;  // only the thread that completes the root gets here
+    depth_out[0] = h;  // the root lies inside this chunk (n <= kRefitBlock)
+}
+
+__global__ __launch_bounds__(kRefitBlock) void k_refit_top(const int32_t *__restrict__ topo,
+                                                           uint32_t *__restrict__ arrive,
+                                                           int32_t *__restrict__ height,
+                                                           NodeRec *nodes, int32_t *depth_out,
+                                                           const int32_t *__restrict__ pend,
+                                                           const uint32_t *__restrict__ pend_count)
+{
+    const uint32_t cnt = *pend_count;
+    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+        int32_t p = pend[i];
+        while (true) {
+            const uint32_t prev = __hip_atomic_fetch_add(arrive + p, 1u, __ATOMIC_ACQ_REL,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (prev == 0) break;   // first arrival: the sibling finishes the node
+            const NodeRec nr = nodes[p];
+            float lo[3], hi[3];
+            lo[0] = fminf(nr.q0.x, nr.q0.z); hi[0] = fmaxf(nr.q0.y, nr.q0.w);
+            lo[1] = fminf(nr.q1.x, nr.q1.z); hi[1] = fmaxf(nr.q1.y, nr.q1.w);
+            lo[2] = fminf(nr.q2.x, nr.q2.z); hi[2] = fmaxf(nr.q2.y, nr.q2.w);
+            const int32_t h0 = height[2 * p + 0], h1 = height[2 * p + 1];
+            const int32_t h = 1 + (h0 > h1 ? h0 : h1);
+            const int32_t pp = topo[3 * p + 2];
+            if (pp < 0) {
+                depth_out[0] = h;   // the root
+                break;
+            }
+            const int slot = (topo[3 * pp + 0] == p) ? 0 : 1;
+            store_child_box(nodes + pp, slot, lo, hi);
+            height[2 * pp + slot] = h;
+            p = pp;
+        }
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_tri_records(const float *__restrict__ verts,
@@ -576,6 +622,8 @@ size_t lbvh_workspace_bytes(int64_t nt)
     s += align_up(sizeof(uint32_t) * (size_t)nt);         // 4-wide node index
     s += align_up(sizeof(uint32_t) * ((size_t)nt / kBlock + 2));  // scan block sums
     s += align_up(sizeof(uint32_t) * 8);                  // scene box (ordered)
+    s += align_up(sizeof(int32_t) * (size_t)nt);          // spanning nodes left to refit
+    s += align_up(sizeof(uint32_t) * 1);                  // their count
     return s;
 }
 
@@ -615,6 +663,8 @@ hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
     uint32_t *qidx = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * n));
     uint32_t *bsum = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * (n / kBlock + 2)));
     uint32_t *obox = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * 8));
+    int32_t *pend = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * n));
+    uint32_t *pend_count = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t)));
     if ((size_t)(w - static_cast<char *>(b.ws)) > b.ws_bytes) return hipErrorInvalidValue;
 
     hipLaunchKernelGGL(k_init_box, dim3(1), dim3(64), 0, s, obox);
@@ -647,9 +697,12 @@ hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
     hipLaunchKernelGGL(k_karras, dim3(grid_for(n - 1, kBlock)), dim3(kBlock), 0, s, kin, n,
                        b.topo, leaf_parent, range, b.nodes);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, arrive, n, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, pend_count, (int64_t)1, 0u);
     hipLaunchKernelGGL(k_refit, dim3(grid_for(n, kRefitBlock)), dim3(kRefitBlock), 0, s, bounds,
-                       b.sorted, n, b.topo, leaf_parent, range, arrive, height, b.nodes,
-                       b.depth_out);
+                       b.sorted, n, b.topo, leaf_parent, range, height, b.nodes, b.depth_out,
+                       pend, pend_count);
+    hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(kRefitBlock), 0, s, b.topo, arrive, height,
+                       b.nodes, b.depth_out, pend, pend_count);
     if (b.q8nodes) {
         const int64_t ni = n - 1;
         const unsigned g = grid_for(ni, kBlock);

@@ -42,6 +42,26 @@ static_assert(sizeof(TriRec) == 48, "triangle record is 48 bytes");
 constexpr int32_t kEmptyChild = (int32_t)0x80000000;
 
 // One job as the traversal kernels see it.
+// Unsigned 32-bit division by a divisor fixed per launch, as a multiply and
+// shifts (Granlund & Montgomery 1994, Fig. 4.1): with l = ceil(log2 d),
+// m = floor(2^32 (2^l - d) / d) + 1, t = mulhi(m, n):
+// n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0), for every n < 2^32.
+struct UDiv {
+    uint32_t m;
+    uint32_t sh;   // min(l, 1) | max(l - 1, 0) << 8
+};
+
+inline UDiv udiv_magic(uint32_t d)
+{
+    uint32_t l = 0;
+    while (l < 32 && ((uint64_t)1 << l) < d) ++l;
+    const uint64_t m = ((((uint64_t)1 << l) - d) << 32) / d + 1;
+    UDiv u;
+    u.m = (uint32_t)m;
+    u.sh = (l > 0 ? 1u : 0u) | ((l > 0 ? l - 1 : 0u) << 8);
+    return u;
+}
+
 struct DevJob {
     const NodeRec *nodes;   // null when the scene has no triangle
     const TriRec *tris;
@@ -58,8 +78,13 @@ struct DevJob {
     int32_t n_az;           // beams per elevation ring (n_beams % n_az == 0)
     int32_t tile_az;        // packet tile: tile_az x tile_el beams, row-major;
     int32_t tile_el;        //   tile_az | n_az and tile_el | n_beams / n_az
-    int32_t pad;
+    int32_t tiles_az;       // n_az / tile_az
+    UDiv div_beams;         // by n_beams
+    UDiv div_tile;          // by tile_az * tile_el
+    UDiv div_tiles_az;      // by n_az / tile_az
+    UDiv div_tile_az;       // by tile_az
 };
+static_assert(sizeof(DevJob) == 128, "job record is 128 bytes");
 
 // Work queues of the persistent traversal: the launch's flattened ray range
 // is cut into kQueues contiguous parts, one per XCD; a wave takes rays from

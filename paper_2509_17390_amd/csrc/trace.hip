@@ -46,6 +46,7 @@
 //    triangle's plane, then rounded to FP32.
 #include "rc_internal.h"
 
+#include <float.h>
 #include <math.h>
 
 namespace {
@@ -111,8 +112,8 @@ __device__ __forceinline__ void ray_dir64(const float *p, const float *b, double
     for (int i = 0; i < 3; ++i)
         d[i] = (double)p[4 * i + 0] * (double)b[0] + (double)p[4 * i + 1] * (double)b[1] +
                (double)p[4 * i + 2] * (double)b[2];
-    double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    for (int i = 0; i < 3; ++i) d[i] /= n;
+    const double rn = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int i = 0; i < 3; ++i) d[i] *= rn;
 }
 
 __device__ __forceinline__ void make_ray(const float *p, const float *b, RayW &r)
@@ -176,9 +177,11 @@ __device__ __forceinline__ bool woop32(const RayW &r, const float4 &q0, const fl
     const float C_x = sel3(q1.z, q1.w, q2.x, r.kx) - r.o[0];
     const float C_y = sel3(q1.z, q1.w, q2.x, r.ky) - r.o[1];
     const float C_z = sel3(q1.z, q1.w, q2.x, r.kz) - r.o[2];
-    const float Ax = A_x - r.Sx * A_z, Ay = A_y - r.Sy * A_z;
-    const float Bx = B_x - r.Sx * B_z, By = B_y - r.Sy * B_z;
-    const float Cx = C_x - r.Sx * C_z, Cy = C_y - r.Sy * C_z;
+    // shear with one rounding per coordinate; a vertex shared by several
+    // triangles gets the same sheared coordinates in each
+    const float Ax = fmaf(-r.Sx, A_z, A_x), Ay = fmaf(-r.Sy, A_z, A_y);
+    const float Bx = fmaf(-r.Sx, B_z, B_x), By = fmaf(-r.Sy, B_z, B_y);
+    const float Cx = fmaf(-r.Sx, C_z, C_x), Cy = fmaf(-r.Sy, C_z, C_y);
     const float u1 = Cx * By, u2 = Cy * Bx;
     const float v1 = Ax * Cy, v2 = Ay * Cx;
     const float w1 = Bx * Ay, w2 = By * Ax;
@@ -194,7 +197,7 @@ __device__ __forceinline__ bool woop32(const RayW &r, const float4 &q0, const fl
         return woop64(Ax, Ay, Bx, By, Cx, Cy, A_z, B_z, C_z, r.Sz, t_out);
     // all three signs certain and equal
     const float det = U + V + W;
-    const float T = U * (r.Sz * A_z) + V * (r.Sz * B_z) + W * (r.Sz * C_z);
+    const float T = r.Sz * fmaf(U, A_z, fmaf(V, B_z, W * C_z));
     *t_out = T / det;
     return true;
 }
@@ -281,16 +284,22 @@ struct LaneRay {
     bool corrupt;
 };
 
+__device__ __forceinline__ uint32_t udiv(uint32_t n, UDiv u)
+{
+    const uint32_t t = __umulhi(u.m, n);
+    return (t + ((n - t) >> (u.sh & 0xffu))) >> (u.sh >> 8);
+}
+
 // which beam the q-th ray of an environment is (packet tiling)
 __device__ __forceinline__ uint32_t tile_beam(const DevJob &jb, uint32_t q)
 {
     const uint32_t tw = (uint32_t)jb.tile_az, th = (uint32_t)jb.tile_el;
     const uint32_t naz = (uint32_t)jb.n_az;
     const uint32_t per = tw * th;
-    const uint32_t tile = q / per, rr = q - tile * per;
-    const uint32_t tiles_az = naz / tw;
-    const uint32_t te = tile / tiles_az, ta = tile - te * tiles_az;
-    const uint32_t row = rr / tw, col = rr - row * tw;
+    const uint32_t tile = udiv(q, jb.div_tile), rr = q - tile * per;
+    const uint32_t tiles_az = (uint32_t)jb.tiles_az;
+    const uint32_t te = udiv(tile, jb.div_tiles_az), ta = tile - te * tiles_az;
+    const uint32_t row = udiv(rr, jb.div_tile_az), col = rr - row * tw;
     return (te * th + row) * naz + ta * tw + col;
 }
 
@@ -316,10 +325,10 @@ __device__ __forceinline__ bool setup_ray(const DevJob *__restrict__ jobs, int n
                                           LaneRay &L)
 {
     const DevJob &jb = jobs[find_job(jobs, n_jobs, g)];
-    const int64_t local = g - jb.ray_begin;
+    const uint32_t local = (uint32_t)(g - jb.ray_begin);   // a job holds < 2^31 rays
     const uint32_t nb = (uint32_t)jb.n_beams;
-    const uint32_t e = (uint32_t)(local / nb);
-    const uint32_t q = (uint32_t)(local - (int64_t)e * nb);
+    const uint32_t e = udiv(local, jb.div_beams);
+    const uint32_t q = local - e * nb;
     const uint32_t beam = tile_beam(jb, q);
     L.pose = jb.poses + 12 * (int64_t)e;
     L.beam = jb.dirs + 3 * (int64_t)beam;
@@ -430,7 +439,9 @@ __device__ __forceinline__ bool node_step_q8(LaneRay &L, LaneStack<SS, STK> &S)
         const float inv = L.r.inv[a];
         const float aa = (org[a] - L.r.org[a]) * inv;
         const float b = scl[a] * inv;
-        const float E = kQErr * (fabsf(aa) + 255.0f * fabsf(b));
+        // one FMA and one product: E stays above 8u (|a| + 255 |b|) up to
+        // two roundings, well inside the bound's factor-two slack
+        const float E = kQErr * fmaf(255.0f, fabsf(b), fabsf(aa));
         an[a] = aa - E;
         af[a] = aa + E;
         bb[a] = b;
@@ -442,14 +453,15 @@ __device__ __forceinline__ bool node_step_q8(LaneRay &L, LaneStack<SS, STK> &S)
     float t[4];
     int32_t ref[4];
     for (int k = 0; k < 4; ++k) {
+        // [t_lo, t_hi] folded into the entry and exit distances
         const float en = fmaxf(fmaxf(fmaf(qbyte(qn[0], k), bb[0], an[0]),
                                      fmaf(qbyte(qn[1], k), bb[1], an[1])),
                                fmaxf(fmaf(qbyte(qn[2], k), bb[2], an[2]), L.t_lo));
         const float ex = fminf(fminf(fmaf(qbyte(qf[0], k), bb[0], af[0]),
                                      fmaf(qbyte(qf[1], k), bb[1], af[1])),
-                               fmaf(qbyte(qf[2], k), bb[2], af[2]));
-        const bool hit = cref[k] != kEmptyChild && en <= ex && en <= L.t_hi;
-        t[k] = hit ? en : INFINITY;
+                               fminf(fmaf(qbyte(qf[2], k), bb[2], af[2]), L.t_hi));
+        const bool hit = cref[k] != kEmptyChild && en <= ex;
+        t[k] = hit ? en : INFINITY;   // a hit's entry distance is finite
         ref[k] = cref[k];
     }
     // ascending by entry distance (5 compare-exchanges)
@@ -462,10 +474,11 @@ __device__ __forceinline__ bool node_step_q8(LaneRay &L, LaneStack<SS, STK> &S)
 #undef RC_CSWAP
     // leaves on the spot, nearest first.  One loop iteration per leaf of
     // this lane (not one code copy per child slot), so lanes whose leaves sit
-    // in different slots test them together.
+    // in different slots test them together.  Missed children carry +inf,
+    // which also t_hi = +inf (an unbounded range) must not admit.
     uint32_t lm = 0;
     for (int k = 0; k < 4; ++k)
-        lm |= (ref[k] < 0 && t[k] <= L.t_hi) ? 1u << k : 0u;
+        lm |= (ref[k] < 0 && t[k] < INFINITY) ? 1u << k : 0u;
 #pragma unroll 1
     while (lm != 0u) {
         const int k = __builtin_ctz(lm);
@@ -478,8 +491,9 @@ __device__ __forceinline__ bool node_step_q8(LaneRay &L, LaneStack<SS, STK> &S)
     // farthest first
     int next = -1;
     float next_t = 0.0f;
+    const float lim = fminf(L.t_hi, FLT_MAX);
     for (int k = 3; k >= 0; --k) {
-        if (ref[k] >= 0 && t[k] <= L.t_hi) {
+        if (ref[k] >= 0 && t[k] <= lim) {
             if (next >= 0) {
                 if (L.sp == STK) { L.corrupt = true; return true; }
                 S.put(L.sp, next, next_t);

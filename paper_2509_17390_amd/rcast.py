@@ -163,6 +163,12 @@ def load() -> ctypes.CDLL:
     return lib
 
 
+def last_error() -> str:
+    """Text of the last error the library reported on this thread."""
+    msg = load().rc_last_error()
+    return msg.decode() if msg else ""
+
+
 def _check(status: int):
     if status != RC_OK:
         msg = load().rc_last_error()
@@ -360,7 +366,8 @@ class Context:
         return t.value
 
     def poll(self, ticket: int, timeout_us: int = 0):
-        """(status, latency_ms); status RC_OK, RC_PENDING or an error code."""
+        """(status, latency_ms); status RC_OK, RC_PENDING or an error code
+        (its text: ``last_error()`` on the same thread)."""
         r, h = ctypes.c_void_p(), ctypes.c_void_p()
         lat = ctypes.c_double()
         st = load().rc_serve_poll(self._h, int(ticket), int(timeout_us), ctypes.byref(r),

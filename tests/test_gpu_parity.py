@@ -289,6 +289,34 @@ def test_q8_equals_fp32_soups(ctx, n):
     assert np.array_equal(h32, hq) and np.array_equal(r32.view(np.int32), rq.view(np.int32))
 
 
+@pytest.mark.parametrize("closed", [True, False])
+def test_unbounded_range(ctx, closed):
+    """t_max = +inf: the interval is [t_min, inf).  Closed room: every ray
+    hits, exactly as with a finite bound beyond the room.  Open soup: rays
+    that miss everything must come back as misses (missed and empty child
+    slots carry +inf, which an infinite bound must not admit)."""
+    if closed:
+        s = synth.room_sphere_scene(0)
+        v, t, poses, dirs, n_az = s.verts, s.tris, s.poses, s.dirs, s.n_az
+    else:
+        rng_ = np.random.default_rng(77)
+        v, t = synth.random_soup(rng_, 300, 1.0)
+        poses = np.stack([synth.rpy_pose(rng_.uniform(-2, 2, 3), *rng_.uniform(-np.pi, np.pi, 3))
+                          for _ in range(3)])
+        dirs, n_az = synth.lidar_pattern(9, -60.0, 60.0, 71), 71
+    log(f"unbounded range closed={closed}")
+    (r32, h32), (rq, hq) = _cast_both(ctx, v, t, poses, dirs, 0.0, np.inf, n_az)
+    assert np.array_equal(h32, hq) and np.array_equal(r32.view(np.int32), rq.view(np.int32))
+    stats = compare_with_oracle(v, t, poses, dirs, 0.0, np.inf, rq, hq)
+    if closed:
+        assert stats["hits"] == stats["rays"]
+        (rb, hb), _ = _cast_both(ctx, v, t, poses, dirs, 0.0, 1e6, n_az)
+        assert np.array_equal(hb, hq) and np.array_equal(rb.view(np.int32), rq.view(np.int32))
+    else:
+        assert 0 < stats["hits"] < stats["rays"]
+        assert np.all(np.isinf(rq[hq < 0]))
+
+
 def test_q8_equals_fp32_indoor_1m(ctx):
     s = synth.indoor_scene(seed=1, h=0.035, n_envs=8)
     log(f"q8 indoor 1M tris={len(s.tris)}")
