@@ -54,17 +54,19 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_hash: str, rays: int):
-    """HBM bytes per launch measured by rocprofv3 counters (profiles/), or
-    None when absent or taken on a different kernel source."""
+def load_traffic(kernel_hash: str, rays: int, tuning: dict):
+    """Counters of the traversal kernel measured by rocprofv3 (profiles/):
+    HBM bytes per launch, L2 hit rate, VALU utilisation.  None when absent or
+    taken on a different kernel source, workload or launch shape."""
     p = os.path.join(ROOT, "profiles", "trace_traffic.json")
     if not os.path.exists(p):
         return None
     with open(p) as fh:
         d = json.load(fh)
-    if d.get("kernel_hash") != kernel_hash or d.get("rays") != rays:
+    if (d.get("kernel_hash") != kernel_hash or d.get("rays") != rays
+            or d.get("tuning") != tuning):
         return None
-    return d.get("bytes_per_launch")
+    return d
 
 
 def cpu_baseline(verts, tris, poses, dirs, t_min, t_max, g_range, g_hit, budget_s):
@@ -241,7 +243,8 @@ def main():
     alg_bytes = b_ray * n_rays
     achieved = alg_bytes / (trace_ms * 1e-3) / 1e9
     khash = kernel_source_hash()
-    traffic = load_traffic(khash, n_rays)
+    counters = load_traffic(khash, n_rays, forms["q8"]["tuning"])
+    traffic = counters["bytes_per_launch"] if counters else None
 
     g_range = out_r.cpu().numpy()
     g_hit = out_h.cpu().numpy()
@@ -289,6 +292,10 @@ def main():
             "mean_tri_tests": round(mean_tris, 2),
             "q8_mean_node_records": round(q8_nodes, 2), "q8_mean_tri_tests": round(q8_tris, 2),
             "kernel_hash": khash,
+            "counters": None if counters is None else {
+                k: counters[k] for k in ("hbm_GBs", "l2_hit_pct", "valu_util_pct",
+                                         "valu_active_threads", "valu_insts_per_wave",
+                                         "read_bytes", "write_bytes")},
         },
         "cpu_baseline": cpu,
         "misses": misses,

@@ -234,10 +234,47 @@ TraceConfig config_of(const rc_tuning &t)
     return cfg;
 }
 
+size_t stage_bytes(int cap) { return sizeof(WorkQueues) + sizeof(DevJob) * (size_t)cap; }
+
+void stage_free(rc_ctx *c, StageBuf &b)
+{
+    std::lock_guard<std::mutex> lk(c->mu);
+    dev_free(c, b.dev, stage_bytes(b.cap));
+    b.dev = nullptr;
+    b.cap = 0;
+}
+
+// Copy a job table into caller-owned staging (no host wait: the caller
+// orders reuse, see StageBuf).
+rc_status stage_own(rc_ctx *c, StageBuf &b, const std::vector<DevJob> &dj, int64_t total,
+                    hipStream_t stream, DevJob **dev, WorkQueues **queues)
+{
+    const int need = (int)dj.size() > 0 ? (int)dj.size() : 1;
+    if (need > b.cap) {
+        int cap = 64;
+        while (cap < need) cap *= 2;
+        std::lock_guard<std::mutex> lk(c->mu);
+        dev_free(c, b.dev, stage_bytes(b.cap));
+        b.dev = nullptr;
+        b.cap = 0;
+        rc_status st = dev_alloc(c, (void **)&b.dev, stage_bytes(cap));
+        if (st != RC_OK) return st;
+        b.cap = cap;
+    }
+    const size_t bytes = sizeof(WorkQueues) + sizeof(DevJob) * dj.size();
+    b.host.resize(bytes);
+    init_queues(*reinterpret_cast<WorkQueues *>(b.host.data()), total);
+    memcpy(b.host.data() + sizeof(WorkQueues), dj.data(), sizeof(DevJob) * dj.size());
+    HIP_TRY(hipMemcpyAsync(b.dev, b.host.data(), bytes, hipMemcpyHostToDevice, stream));
+    *queues = reinterpret_cast<WorkQueues *>(b.dev);
+    *dev = reinterpret_cast<DevJob *>(b.dev + sizeof(WorkQueues));
+    return RC_OK;
+}
+
 // Stage and launch one batch; `forced` overrides the context's tuning.
 rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, float *out_range,
                        int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, void *stream,
-                       const rc_tuning *forced)
+                       const rc_tuning *forced, StageBuf *own)
 {
     if (!c) return fail(RC_E_INVAL, "null context");
     if (c->mock) return fail(RC_E_STATE, "a mock context has no device to cast on");
@@ -256,9 +293,16 @@ rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, 
     if (mode == TRACE_STATS && (!out_nodes || !out_tris)) return fail(RC_E_INVAL, "null stats output");
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    std::lock_guard<std::mutex> lk(c->job_mu);
     DevJob *djd = nullptr;
     WorkQueues *dq = nullptr;
+    if (own) {
+        st = stage_own(c, *own, dj, total, s, &djd, &dq);
+        if (st != RC_OK) return st;
+        HIP_TRY(trace_launch(mode, fmt, config_of(tuning), djd, n_jobs, dq, total, out_range,
+                             out_hit, out_nodes, out_tris, s));
+        return RC_OK;
+    }
+    std::lock_guard<std::mutex> lk(c->job_mu);
     JobSlot *slot = nullptr;
     st = stage_jobs(c, dj, total, s, &djd, &dq, &slot);
     if (st != RC_OK) return st;

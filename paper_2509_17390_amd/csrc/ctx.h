@@ -90,11 +90,23 @@ Scene *get_scene(rc_ctx *c, int32_t id);      // caller holds c->mu
 Pattern *get_pattern(rc_ctx *c, int32_t id);  // caller holds c->mu
 rc_tuning default_tuning();
 
+// Job table staging owned by one caller stream (the request server keeps
+// one per stream).  Device layout: WorkQueues, then DevJob[cap].  The caller
+// guarantees that no launch still reads `dev` when it stages the next batch
+// and keeps `host` unchanged until the launch has completed.
+struct StageBuf {
+    char *dev = nullptr;
+    int cap = 0;
+    std::vector<char> host;
+};
+
 // Stage one batch and launch it on `stream`; `forced` overrides the
-// context's tuning.  Thread-safe.
+// context's tuning; `own` replaces the context's shared staging ring.
+// Thread-safe.
 rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, float *out_range,
                        int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, void *stream,
-                       const rc_tuning *forced = nullptr);
+                       const rc_tuning *forced = nullptr, StageBuf *own = nullptr);
+void stage_free(rc_ctx *c, StageBuf &b);
 
 // Serving scheduler hooks (serve.hip).
 void serve_shutdown(rc_ctx *c);  // stop the scheduler, wait for in-flight work

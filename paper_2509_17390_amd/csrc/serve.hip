@@ -127,6 +127,7 @@ struct ServeState {
     uint64_t range_bytes = 0, pose_bytes = 0;
     std::vector<hipStream_t> streams;
     std::vector<int> stream_busy;
+    std::vector<StageBuf> stage;   // job table per stream
     int inflight = 0;
     rc_serve_stats stats{};
     // mock device: one simulated execution queue per stream, so launches on
@@ -282,7 +283,7 @@ rc_status launch_batch(ServeState &S, Batch *b, std::string &err)
     rc_status st = RC_OK;
     if (!jobs.empty())
         st = trace_common(c, TRACE_BVH, jobs.data(), (int32_t)jobs.size(), S.range_buf, S.hit_buf,
-                          nullptr, nullptr, s);
+                          nullptr, nullptr, s, nullptr, &S.stage[b->stream]);
     if (st != RC_OK) {
         err = rc_last_error();
         return st;
@@ -346,6 +347,9 @@ void worker_loop(ServeState *Sp)
         lk.unlock();
         std::string err;
         rc_status st = launch_batch(S, b, err);
+        // a failed launch may have left copies from this stream's staging
+        // in flight: let them drain before the stream is handed out again
+        if (st != RC_OK && !S.ctx->mock) (void)hipStreamSynchronize(S.streams[si]);
         lk.lock();
         if (st != RC_OK) {
             for (Request *r : b->reqs)
@@ -392,6 +396,7 @@ void serve_shutdown(rc_ctx *c)
         free(S->pose_buf);
     } else {
         for (hipStream_t s : S->streams) (void)hipStreamDestroy(s);
+        for (StageBuf &b : S->stage) stage_free(c, b);
         std::lock_guard<std::mutex> lk(c->mu);
         dev_free(c, S->range_buf, S->range_bytes);
         dev_free(c, S->hit_buf, S->range_bytes);
@@ -464,6 +469,7 @@ rc_status rc_serve_start(rc_ctx *c, const rc_serve_opts *opts)
         return st;
     }
     S->stream_busy.assign(o.max_inflight, 0);
+    S->stage.resize(o.max_inflight);
     S->stats.out_capacity_bytes = out_rays * 8;
     c->serve = S;
     S->worker = std::thread(worker_loop, S);
