@@ -119,8 +119,8 @@ def main():
                          "Poisson requests against 16 resident scenes, served vs per-request; "
                          "frame: one sensor, 128x2048 beams, 6.4M-triangle mesh, frames/s")
     ap.add_argument("--scenes", type=int, default=0, help="uneven/serve: scene count override")
-    ap.add_argument("--requests", type=int, default=200, help="serve: requests per rate")
-    ap.add_argument("--rates", type=str, default="0.3,0.6,0.9",
+    ap.add_argument("--requests", type=int, default=1000, help="serve: requests per rate")
+    ap.add_argument("--rates", type=str, default="0.1,0.3,0.5,0.7,0.9,1.1",
                     help="serve: arrival rates as fractions of the measured capacity")
     ap.add_argument("--batch-cap-m", type=int, default=64,
                     help="serve: most rays per batched launch, in millions (0: no cap)")
