@@ -330,9 +330,9 @@ __device__ __forceinline__ void store_child_box(NodeRec *node, int slot, const f
 
 // Bottom-up box reduction in two kernels.
 //
-// k_refit: one thread per leaf.  A block owns a chunk of kRefitBlock
-// consecutive leaves; a node whose leaf range lies inside the chunk has both
-// children finished by this block, so its arrival counter lives in LDS and
+// k_refit: a thread walks up from kRefitLeavesPerThread leaves in turn.
+// A block owns a chunk of kRefitChunk consecutive leaves; a node whose leaf
+// range lies inside the chunk has both children finished by this block, so its arrival counter lives in LDS and
 // workgroup-scope ordering suffices.  A thread whose walk reaches a node
 // spanning chunks writes its child box there and leaves the node on a list.
 //
@@ -343,6 +343,8 @@ __device__ __forceinline__ void store_child_box(NodeRec *node, int slot, const f
 // release/acquire that would write back and invalidate whole L2 caches
 // (one per XCD) on every arrival.
 constexpr int kRefitBlock = 1024;
+constexpr int kRefitLeavesPerThread = 4;   // larger chunks: fewer spanning nodes
+constexpr int kRefitChunk = kRefitBlock * kRefitLeavesPerThread;   // leaves per block
 
 __global__ __launch_bounds__(kRefitBlock) void k_refit(const float *__restrict__ bounds,
                                                        const uint32_t *__restrict__ sorted,
@@ -354,44 +356,51 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(const float *__restrict__
                                                        int32_t *__restrict__ pend,
                                                        uint32_t *__restrict__ pend_count)
 {
-    __shared__ uint32_t local_arrive[kRefitBlock];
-    local_arrive[threadIdx.x] = 0;
+    __shared__ uint32_t local_arrive[kRefitChunk];
+    for (int i = threadIdx.x; i < kRefitChunk; i += kRefitBlock) local_arrive[i] = 0;
     __syncthreads();
-    const int64_t c0 = (int64_t)blockIdx.x * kRefitBlock;
-    const int64_t k = c0 + threadIdx.x;
-    if (k >= n) return;
-    const float *b = bounds + 6 * (int64_t)sorted[k];
-    float lo[3] = {b[0], b[1], b[2]};
-    float hi[3] = {b[3], b[4], b[5]};
-    int32_t child = ~(int32_t)k;
-    int32_t h = 0;
-    int32_t p = leaf_parent[k];
-    while (p >= 0) {
-        int slot = (topo[3 * p + 0] == child) ? 0 : 1;
-        store_child_box(nodes + p, slot, lo, hi);
-        if (slot == 0) height[2 * p + 0] = h; else height[2 * p + 1] = h;
-        const int2 rg = range[p];
-        if (rg.x < c0 || rg.y >= c0 + kRefitBlock) {
-            // spans chunks: finished by k_refit_top (a unique list slot is
-            // all this counter provides, so no ordering is asked of it)
-            const uint32_t at = __hip_atomic_fetch_add(pend_count, 1u, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-            pend[at] = p;
-            return;
+    const int64_t c0 = (int64_t)blockIdx.x * kRefitChunk;
+    const int64_t c1 = c0 + kRefitChunk < n ? c0 + kRefitChunk : n;
+    for (int64_t k = c0 + threadIdx.x; k < c1; k += kRefitBlock) {
+        const float *b = bounds + 6 * (int64_t)sorted[k];
+        float lo[3] = {b[0], b[1], b[2]};
+        float hi[3] = {b[3], b[4], b[5]};
+        int32_t child = ~(int32_t)k;
+        int32_t h = 0;
+        int32_t p = leaf_parent[k];
+        bool root = true;
+        while (p >= 0) {
+            int slot = (topo[3 * p + 0] == child) ? 0 : 1;
+            store_child_box(nodes + p, slot, lo, hi);
+            if (slot == 0) height[2 * p + 0] = h; else height[2 * p + 1] = h;
+            const int2 rg = range[p];
+            if (rg.x < c0 || rg.y >= c0 + kRefitChunk) {
+                // spans chunks: finished by k_refit_top (a unique list slot is
+                // all this counter provides, so no ordering is asked of it)
+                const uint32_t at = __hip_atomic_fetch_add(pend_count, 1u, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                pend[at] = p;
+                root = false;
+                break;
+            }
+            const uint32_t prev = __hip_atomic_fetch_add(local_arrive + (p - c0), 1u,
+                                                         __ATOMIC_ACQ_REL,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (prev == 0) {   // first arrival: the sibling finishes the node
+                root = false;
+                break;
+            }
+            const NodeRec nr = nodes[p];
+            lo[0] = fminf(nr.q0.x, nr.q0.z); hi[0] = fmaxf(nr.q0.y, nr.q0.w);
+            lo[1] = fminf(nr.q1.x, nr.q1.z); hi[1] = fmaxf(nr.q1.y, nr.q1.w);
+            lo[2] = fminf(nr.q2.x, nr.q2.z); hi[2] = fmaxf(nr.q2.y, nr.q2.w);
+            int32_t h0 = height[2 * p + 0], h1 = height[2 * p + 1];
+            h = 1 + (h0 > h1 ? h0 : h1);
+            child = p;
+            p = topo[3 * p + 2];
         }
-        const uint32_t prev = __hip_atomic_fetch_add(local_arrive + (p - c0), 1u, __ATOMIC_ACQ_REL,
-                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (prev == 0) return;  // first arrival: the sibling finishes the node
-        const NodeRec nr = nodes[p];
-        lo[0] = fminf(nr.q0.x, nr.q0.z); hi[0] = fmaxf(nr.q0.y, nr.q0.w);
-        lo[1] = fminf(nr.q1.x, nr.q1.z); hi[1] = fmaxf(nr.q1.y, nr.q1.w);
-        lo[2] = fminf(nr.q2.x, nr.q2.z); hi[2] = fmaxf(nr.q2.y, nr.q2.w);
-        int32_t h0 = height[2 * p + 0], h1 = height[2 * p + 1];
-        h = 1 + (h0 > h1 ? h0 : h1);
-        child = p;
-        p = topo[3 * p + 2];
+        if (root) depth_out[0] = h;   // the root lies inside this chunk (n <= kRefitChunk)
     }
-    depth_out[0] = h;  // the root lies inside this chunk (n <= kRefitBlock)
 }
 
 __global__ __launch_bounds__(kRefitBlock) void k_refit_top(const int32_t *__restrict__ topo,
@@ -698,7 +707,7 @@ hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
                        b.topo, leaf_parent, range, b.nodes);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, arrive, n, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, s, pend_count, (int64_t)1, 0u);
-    hipLaunchKernelGGL(k_refit, dim3(grid_for(n, kRefitBlock)), dim3(kRefitBlock), 0, s, bounds,
+    hipLaunchKernelGGL(k_refit, dim3(grid_for(n, kRefitChunk)), dim3(kRefitBlock), 0, s, bounds,
                        b.sorted, n, b.topo, leaf_parent, range, height, b.nodes, b.depth_out,
                        pend, pend_count);
     hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(kRefitBlock), 0, s, b.topo, arrive, height,
