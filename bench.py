@@ -54,7 +54,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_hash: str, rays: int, tuning: dict):
+def load_traffic(kernel_hash: str, rays: int, tris: int, tuning: dict):
     """Counters of the traversal kernel measured by rocprofv3 (profiles/):
     HBM bytes per launch, L2 hit rate, VALU utilisation.  None when absent or
     taken on a different kernel source, workload or launch shape."""
@@ -64,7 +64,7 @@ def load_traffic(kernel_hash: str, rays: int, tuning: dict):
     with open(p) as fh:
         d = json.load(fh)
     if (d.get("kernel_hash") != kernel_hash or d.get("rays") != rays
-            or d.get("tuning") != tuning):
+            or d.get("tris") != tris or d.get("tuning") != tuning):
         return None
     return d
 
@@ -243,7 +243,7 @@ def main():
     alg_bytes = b_ray * n_rays
     achieved = alg_bytes / (trace_ms * 1e-3) / 1e9
     khash = kernel_source_hash()
-    counters = load_traffic(khash, n_rays, forms["q8"]["tuning"])
+    counters = load_traffic(khash, n_rays, int(len(s.tris)), forms["q8"]["tuning"])
     traffic = counters["bytes_per_launch"] if counters else None
 
     g_range = out_r.cpu().numpy()
