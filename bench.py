@@ -47,10 +47,17 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the traversal kernel's code (trace.hip and rc_internal.h with
+    comments and whitespace removed), so profiled counters stay attached to
+    the code they were measured on, not to its comments."""
+    import re
     h = hashlib.sha256()
     for f in ("trace.hip", "rc_internal.h"):
-        with open(os.path.join(ROOT, "paper_2509_17390_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2509_17390_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

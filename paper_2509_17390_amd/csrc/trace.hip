@@ -5,23 +5,30 @@
 // entry distance exceeds the best hit so far (and every triangle beyond it);
 // the result is the nearest intersection t*_j over [t_min, t_max].
 //
-// Execution (gfx950, wave64):
+// Execution (gfx950, wave64).  The launch shape is a runtime choice
+// (rc_tuning, picked per workload by the autotuner):
+//  * One ray per lane over a flat grid (the default).  Rays are numbered
+//    job by job and environment by environment; inside an environment,
+//    consecutive lanes take a tile_az x tile_el block of beams (packet
+//    tiling), so a wave's 64 rays have nearly equal directions and walk
+//    nearly the same nodes.  A register cap (launch bounds) keeps 8 waves per
+//    SIMD resident; the traversal stack lives in scratch.
 //  * Persistent waves.  The launch's rays are split into one contiguous
 //    range per XCD (workgroups are dispatched round-robin over the 8 XCDs,
 //    so block b runs on XCD b % 8 and takes rays from range b % 8 first,
 //    keeping neighbouring environments in one L2); when its range is empty
-//    a wave steals from the others.
-//  * Wavefront-ballot refill: a wave keeps traversing while fewer than
-//    `refill_min` of its 64 lanes are idle; then one lane takes that many
-//    consecutive rays from the queue with a single atomic and the idle lanes
-//    pick them up in lane order (prefix count of the idle ballot).
-//  * Packet tiling: consecutive queue entries of an environment map to a
-//    tile_az x tile_el block of beams, so a refill brings in rays with
-//    nearly equal directions.
-//  * Stack: the first `SS` entries of every lane's traversal stack live in
-//    LDS (slot-major, so the 64 lanes of a wave touch 64 consecutive words);
-//    deeper entries spill to scratch.  A Karras tree over 3b-bit codes plus
-//    index tie-breaks is at most 62 levels deep, so 64 entries always suffice.
+//    a wave steals from the others.  Wavefront-ballot refill: a wave keeps
+//    traversing while fewer than `refill_min` of its 64 lanes are idle; the
+//    idle lanes then take consecutive rays from the wave's pool in lane order
+//    (prefix count of the idle ballot).
+//  * Stack: optionally the first `SS` entries of every lane's traversal
+//    stack live in LDS (slot-major, so the 64 lanes of a wave touch 64
+//    consecutive words); deeper entries are in scratch.  A Karras tree over
+//    3b-bit codes plus index tie-breaks is at most 62 levels deep, so 64
+//    entries always suffice (96 for 4-wide nodes: at most three pushes per
+//    level).
+//  * Node formats: the binary tree with FP32 child boxes, or 4-wide nodes
+//    with 8-bit child boxes in the node's frame (see node_step_q8).
 //
 // Numerics (compiled with -ffp-contract=off so every variant rounds alike):
 //  * Ray: direction R_s d_j is formed and normalised in FP64, then rounded to

@@ -289,6 +289,33 @@ def test_q8_equals_fp32_soups(ctx, n):
     assert np.array_equal(h32, hq) and np.array_equal(r32.view(np.int32), rq.view(np.int32))
 
 
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_far_from_origin(ctx, fmt):
+    """The room + sphere scene and its sensor moved 10-25 km away from the
+    world origin (coordinates rounded to FP32 there, as a user would hold
+    them): the FP32 traversal must still meet the parity bar.  Differences
+    v - o of nearby points are exact in FP32 (Sterbenz), so only the shear and
+    the ray rounding err, both far inside the 1e-6 rad edge margin."""
+    import torch
+    s = synth.room_sphere_scene(2)
+    off = np.array([1.2e4, -2.5e4, 3.0e3])
+    v = (s.verts.astype(np.float64) + off).astype(np.float32)
+    poses = s.poses.astype(np.float64).copy()
+    poses[:, [3, 7, 11]] += off
+    poses = poses.astype(np.float32)
+    log(f"far from origin fmt={fmt}")
+    scene = ctx.upload_scene(v, s.tris)
+    ctx.build(scene, node_format=fmt)
+    pat = ctx.upload_pattern(s.dirs, s.n_az)
+    r, h = ctx.cast([Job(scene, pat, cuda(poses), s.t_min, s.t_max)])
+    torch.cuda.synchronize()
+    r, h = r.cpu().numpy(), h.cpu().numpy()
+    assert np.all(h >= 0)   # still a closed room
+    st = compare_with_oracle(v, s.tris, poses, s.dirs, s.t_min, s.t_max, r, h)
+    log(str(st))
+    ctx.release_scene(scene)
+
+
 @pytest.mark.parametrize("closed", [True, False])
 def test_unbounded_range(ctx, closed):
     """t_max = +inf: the interval is [t_min, inf).  Closed room: every ray
