@@ -261,8 +261,9 @@ void rc_graph_destroy(rc_graph *graph);
  * patterns arrive at any time and are batched continuously.  Requests are
  * admitted in arrival order as soon as their footprint (8 bytes of output
  * per ray + 48 bytes of pose per environment) fits in the server's arenas;
- * all requests admitted at one moment share one batched launch, and up to
- * max_inflight launches run at once on separate streams.  Each request's
+ * the requests admitted at one moment share one batched launch (up to
+ * max_batch_rays_m million rays), and up to max_inflight launches run at
+ * once on separate streams.  Each request's
  * results are bit-identical to casting it alone with rc_raycast_batch.
  * Scenes and patterns must stay resident while their requests are queued
  * or running (a request whose scene was released fails with
@@ -280,7 +281,9 @@ typedef struct {
     uint64_t arena_bytes;     /* device memory for admitted requests
                                  (0 = 4 GiB; >= 1 MiB); 1/64 holds poses     */
     int32_t max_inflight;     /* launches in flight at once, 1..8 (0 = 2)    */
-    int32_t max_batch_rays_m; /* cap on rays per launch, millions (0 = none) */
+    int32_t max_batch_rays_m; /* cap on rays per launch, millions (0 = none):
+                                 admission stops before a request that would
+                                 exceed it; a larger request runs alone     */
     int32_t mock_ns_per_ray;  /* mock context: simulated device time per ray */
     int32_t mock_fail_scene;  /* mock context: requests on scene
                                  (mock_fail_scene - 1) fail with RC_E_DEVICE

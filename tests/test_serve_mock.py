@@ -166,6 +166,27 @@ def test_continuous_batching_overlaps_small_with_large():
     c.close()
 
 
+def test_batch_cap_splits_launches_and_runs_large_requests_alone():
+    c, scenes, pats = mock_ctx()
+    # 1M rays per launch at most; requests of 400k rays (two fit) and one of
+    # 3M rays (above the cap: runs alone)
+    c.serve_start(arena_bytes=256 << 20, max_inflight=1, max_batch_rays_m=1,
+                  mock_ns_per_ray=20)
+    block = c.submit(scenes[0], pats[1], poses(100), 0.0, 1.0)   # 100k rays, holds the slot
+    time.sleep(0.005)
+    small = [c.submit(scenes[1], pats[1], poses(400), 0.0, 1.0) for _ in range(6)]
+    big = c.submit(scenes[2], pats[2], poses(600), 0.0, 1.0)     # 3M rays
+    for tk in [block] + small + [big]:
+        assert wait(c, tk)[0] == RC_OK
+    s = c.serve_stats()
+    assert s["max_batch_requests"] == 2      # never more than the cap allows
+    assert s["launches"] >= 1 + 3 + 1
+    rng, hit = c.fetch(big, 3_000_000)
+    assert np.array_equal(rng[:10], np.arange(10, dtype=np.float32)) and np.all(hit == scenes[2])
+    c.serve_stop()
+    c.close()
+
+
 def test_concurrent_submitters():
     c, scenes, pats = mock_ctx()
     c.serve_start(arena_bytes=64 << 20, max_inflight=3, mock_ns_per_ray=5)
