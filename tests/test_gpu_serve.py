@@ -59,11 +59,12 @@ def cast_alone(ctx, r):
     return rng.cpu().numpy(), hit.cpu().numpy()
 
 
-def test_served_results_equal_alone(world):
+@pytest.mark.parametrize("cap_m", [0, 1])
+def test_served_results_equal_alone(world, cap_m):
     ctx, scenes, pats = world
-    reqs = make_requests(scenes, pats, 40, 0)
+    reqs = make_requests(scenes, pats, 40, cap_m)
     alone = [cast_alone(ctx, r) for r in reqs]
-    ctx.serve_start(arena_bytes=256 << 20, max_inflight=3)
+    ctx.serve_start(arena_bytes=256 << 20, max_inflight=3, max_batch_rays_m=cap_m)
     try:
         tickets = [None] * len(reqs)
 
