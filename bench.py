@@ -39,6 +39,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_GWI = 256 * 4 * 2.4 / 4   # G wave64 VALU instructions/s
 NODE_BYTES, TRI_BYTES, OUT_BYTES = 64, 40, 8
 
 
@@ -303,6 +304,19 @@ def main():
                 k: counters[k] for k in ("hbm_GBs", "l2_hit_pct", "valu_util_pct",
                                          "valu_active_threads", "valu_insts_per_wave",
                                          "read_bytes", "write_bytes")},
+        },
+        # the bound the counters show: vector-instruction issue.  Peak: one
+        # wave64 VALU instruction per SIMD every 4 cycles, 4 SIMDs x 256 CUs
+        # at 2.4 GHz = 614.4 G wave-instructions/s (gfx950 can co-issue a
+        # second one in some cycles, so the fraction can pass 1)
+        "roofline_valu": None if counters is None else {
+            "bound": "alu", "unit": "G wave-instructions/s",
+            "achieved": round(counters["valu_insts_per_wave"] * (n_rays / 64)
+                              / (trace_ms * 1e-3) / 1e9, 1),
+            "peak": VALU_PEAK_GWI,
+            "frac": round(counters["valu_insts_per_wave"] * (n_rays / 64)
+                          / (trace_ms * 1e-3) / 1e9 / VALU_PEAK_GWI, 4),
+            "active_lanes_of_64": counters["valu_active_threads"],
         },
         "cpu_baseline": cpu,
         "misses": misses,
