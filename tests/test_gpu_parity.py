@@ -289,6 +289,35 @@ def test_q8_equals_fp32_soups(ctx, n):
     assert np.array_equal(h32, hq) and np.array_equal(r32.view(np.int32), rq.view(np.int32))
 
 
+@pytest.mark.parametrize("n_el,n_az", [(1, 1), (1, 97), (3, 1025), (7, 64)])
+def test_odd_pattern_sizes(ctx, n_el, n_az):
+    """Patterns whose sizes the packet tile does not divide (one beam, a
+    prime count, rings of 1025) fall back to ring order; many environments
+    per job exercise the ray index -> (environment, beam) map."""
+    import torch
+    s = synth.room_sphere_scene(1)
+    dirs = synth.lidar_pattern(n_el, -20.0, 20.0, n_az) if n_el > 1 else \
+        synth.lidar_pattern(1, 5.0, 5.0, n_az)
+    rng_ = np.random.default_rng(n_el * 1000 + n_az)
+    p0 = s.poses[0].reshape(3, 4)[:, 3]
+    poses = np.stack([synth.yaw_pose(p0 + rng_.uniform(-0.1, 0.1, 3), rng_.uniform(0, 6.283))
+                      for _ in range(37)])
+    log(f"odd pattern {n_el}x{n_az}")
+    res = []
+    for fmt in (0, 1):
+        scene = ctx.upload_scene(s.verts, s.tris)
+        ctx.build(scene, node_format=fmt)
+        pat = ctx.upload_pattern(dirs, n_az)
+        r, h = ctx.cast([Job(scene, pat, cuda(poses), s.t_min, s.t_max)])
+        torch.cuda.synchronize()
+        res.append((r.cpu().numpy(), h.cpu().numpy()))
+        ctx.release_scene(scene)
+    (r32, h32), (rq, hq) = res
+    assert np.array_equal(h32, hq) and np.array_equal(r32.view(np.int32), rq.view(np.int32))
+    assert np.all(hq >= 0)
+    compare_with_oracle(s.verts, s.tris, poses, dirs, s.t_min, s.t_max, rq, hq)
+
+
 @pytest.mark.parametrize("fmt", [0, 1])
 def test_far_from_origin(ctx, fmt):
     """The room + sphere scene and its sensor moved 10-25 km away from the
