@@ -46,3 +46,11 @@ def test_error_path_without_device_is_clean():
     assert st == rcast.RC_E_DEVICE or st == rcast.RC_E_INVAL
     assert lib.rc_last_error()
     assert not h.value
+
+
+def test_c_driver_builds_against_header_and_library():
+    """The header is plain C (C11) and the library links from C: the ABI
+    driver of the GPU test compiles and links here (it runs on the GPU)."""
+    import __graft_entry__
+    exe = __graft_entry__.build_abi_driver()
+    assert os.path.exists(exe) and os.access(exe, os.X_OK)
