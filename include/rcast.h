@@ -222,6 +222,10 @@ typedef struct {
                               the queue empties */
     int32_t waves_cap;     /* 1 (default): one-ray-per-thread kernel compiled
                               for at most 64 VGPRs (8 waves per SIMD) */
+    int32_t group_waves;   /* waves per workgroup of the one-ray-per-thread
+                              grid: 1 (default; a finished wave frees its slot
+                              at once) or 4 (spreads a small launch over more
+                              CUs) */
 } rc_tuning;
 
 /* Set (NULL: reset to defaults) or read the context's traversal tuning.
@@ -233,8 +237,10 @@ rc_status rc_get_tuning(rc_ctx *ctx, rc_tuning *out);
  * then the fastest of `reps` launches timed with HIP events on `stream`),
  * keep the fastest as the context's tuning and report it.  Candidates:
  * one-ray-per-thread with stack_lds {0, 8} x waves_cap {1, 0} x tiles
- * {16x4, 8x8, 32x2, plain}; persistent with stack_lds {8, 16} x refill_min
- * {48, 64} x blocks_per_cu {2, 4}.  Every candidate writes the same,
+ * {16x4, 8x8, 32x2, plain} in one-wave workgroups, and with stack_lds
+ * {0, 8} x waves_cap {1, 0} x tiles {16x4, plain} in four-wave workgroups;
+ * persistent with stack_lds {8, 16} x refill_min {48, 64} x blocks_per_cu
+ * {2, 4}.  Every candidate writes the same,
  * complete results into out_range / out_hit.  Synchronises `stream`.
  * Errors: as rc_raycast_batch. */
 rc_status rc_autotune(rc_ctx *ctx, const rc_job *jobs, int32_t n_jobs, float *out_range,

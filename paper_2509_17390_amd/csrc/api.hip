@@ -134,6 +134,7 @@ rc_tuning default_tuning()
     t.tile_el = 4;
     t.chunk_max = 4096;
     t.waves_cap = 1;
+    t.group_waves = 1;
     return t;
 }
 
@@ -231,6 +232,7 @@ TraceConfig config_of(const rc_tuning &t)
     cfg.blocks_per_cu = t.blocks_per_cu;
     cfg.chunk_max = t.chunk_max;
     cfg.waves_cap = t.waves_cap;
+    cfg.group_waves = t.group_waves;
     return cfg;
 }
 
@@ -734,6 +736,7 @@ rc_status check_tuning(const rc_tuning *t)
     if (t->chunk_max != 0 && (t->chunk_max < 64 || t->chunk_max > (1 << 20)))
         return fail(RC_E_INVAL, "chunk_max must be 0 or 64..2^20");
     if (t->waves_cap != 0 && t->waves_cap != 1) return fail(RC_E_INVAL, "waves_cap must be 0 or 1");
+    if (t->group_waves != 1 && t->group_waves != 4) return fail(RC_E_INVAL, "group_waves must be 1 or 4");
     if (t->refill_min < 1 || t->refill_min > 64) return fail(RC_E_INVAL, "refill_min must be 1..64");
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return fail(RC_E_INVAL, "blocks_per_cu must be 0..64");
     if (t->tile_az < 0 || t->tile_el < 0 || (int64_t)t->tile_az * t->tile_el > (1 << 20))
@@ -746,17 +749,20 @@ std::vector<rc_tuning> tuning_candidates()
 {
     std::vector<rc_tuning> v;
     const int tiles[4][2] = {{16, 4}, {8, 8}, {32, 2}, {0, 0}};
-    for (int ss : {0, 8})
-        for (int cap : {1, 0})
-            for (auto &tl : tiles) {
-                rc_tuning t = default_tuning();
-                t.persistent = 0;
-                t.stack_lds = ss;
-                t.waves_cap = cap;
-                t.tile_az = tl[0];
-                t.tile_el = tl[1];
-                v.push_back(t);
-            }
+    for (int gw : {1, 4})
+        for (int ss : {0, 8})
+            for (int cap : {1, 0})
+                for (auto &tl : tiles) {
+                    if (gw == 4 && tl[0] != 16 && tl[0] != 0) continue;
+                    rc_tuning t = default_tuning();
+                    t.persistent = 0;
+                    t.stack_lds = ss;
+                    t.waves_cap = cap;
+                    t.tile_az = tl[0];
+                    t.tile_el = tl[1];
+                    t.group_waves = gw;
+                    v.push_back(t);
+                }
     for (int ss : {8, 16})
         for (int rm : {48, 64})
             for (int b : {2, 4}) {

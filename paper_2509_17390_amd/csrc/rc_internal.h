@@ -103,6 +103,7 @@ struct TraceConfig {
     int blocks_per_cu;  // persistent grid = CUs x blocks_per_cu (0: occupancy limit)
     int chunk_max;      // largest ray chunk a persistent wave takes per atomic
     int waves_cap;      // 1: cap registers for 8 waves per SIMD (one-ray-per-thread kernel)
+    int group_waves;    // waves per workgroup of the one-ray-per-thread grid (1 or 4)
 };
 
 // ---------------------------------------------------------------------------

@@ -12,10 +12,11 @@
 //    consecutive lanes take a tile_az x tile_el block of beams (packet
 //    tiling), so a wave's 64 rays have nearly equal directions and walk
 //    nearly the same nodes.  A register cap (launch bounds) keeps 8 waves per
-//    SIMD resident; the traversal stack lives in scratch.  Each workgroup is
-//    one wave: a wave whose rays are done frees its slot at once instead of
-//    waiting for the slowest wave of a larger workgroup (10% faster than
-//    four-wave workgroups on the headline batch).
+//    SIMD resident; the traversal stack lives in scratch.  By default each
+//    workgroup is one wave: a wave whose rays are done frees its slot at once
+//    instead of waiting for the slowest wave of a larger workgroup (10%
+//    faster than four-wave workgroups on the headline batch); four-wave
+//    workgroups spread a small launch over more CUs.
 //  * Persistent waves.  The launch's rays are split into one contiguous
 //    range per XCD (workgroups are dispatched round-robin over the 8 XCDs,
 //    so block b runs on XCD b % 8 and takes rays from range b % 8 first,
@@ -62,8 +63,6 @@
 namespace {
 
 constexpr int kBlock = 256;      // persistent kernel: 4 waves per workgroup
-constexpr int kGridBlock = 64;   // one-ray-per-lane grid: one wave per workgroup, so a
-                                 // finished wave frees its slot without waiting for others
 constexpr int64_t kMaxRaysPerDispatch = (int64_t)1 << 30;
 constexpr int kStack = 64;           // >= depth of any Karras tree (62 key bits)
 constexpr float kErrU = 2.384185791015625e-07f;  // 2^-22: sign certificate factor
@@ -558,20 +557,20 @@ __device__ __forceinline__ void finish_ray(const LaneRay &L, float *__restrict__
 
 // ---------------------------------------------------------------------------
 // One ray per thread (also the brute-force cross-check).
-template <int MODE, int FMT, int SS, int WAVES>
-__global__ __launch_bounds__(kGridBlock, WAVES) void k_trace(const DevJob *__restrict__ jobs, int n_jobs,
+template <int MODE, int FMT, int SS, int WAVES, int BLK>
+__global__ __launch_bounds__(BLK, WAVES) void k_trace(const DevJob *__restrict__ jobs, int n_jobs,
                                                   int64_t g0, int64_t total,
                                                   float *__restrict__ out_range,
                                                   int32_t *__restrict__ out_hit,
                                                   int32_t *__restrict__ out_nodes,
                                                   int32_t *__restrict__ out_tris)
 {
-    __shared__ int s_node[SS > 0 ? SS * kGridBlock : 1];
-    __shared__ float s_t[SS > 0 ? SS * kGridBlock : 1];
-    const int64_t g = g0 + (int64_t)blockIdx.x * kGridBlock + threadIdx.x;
+    __shared__ int s_node[SS > 0 ? SS * BLK : 1];
+    __shared__ float s_t[SS > 0 ? SS * BLK : 1];
+    const int64_t g = g0 + (int64_t)blockIdx.x * BLK + threadIdx.x;
     if (g >= total) return;
     LaneRay L;
-    LaneStack<SS, FMT == FMT_Q8 ? kStackQ8 : kStack, kGridBlock> S;
+    LaneStack<SS, FMT == FMT_Q8 ? kStackQ8 : kStack, BLK> S;
     S.ln = s_node + threadIdx.x;
     S.lt = s_t + threadIdx.x;
     bool go = setup_ray(jobs, n_jobs, g, L);
@@ -724,19 +723,23 @@ hipError_t launch_mode(const TraceConfig &cfg, const DevJob *jobs, int n_jobs, W
     }
     // one thread per ray; a dispatch holds at most 2^32 work-items, so large
     // batches go out as several dispatches of kMaxRaysPerDispatch rays
+    const int blk = cfg.group_waves == 4 ? 256 : 64;
     for (int64_t g0 = 0; g0 < total; g0 += kMaxRaysPerDispatch) {
         const int64_t n = total - g0 < kMaxRaysPerDispatch ? total - g0 : kMaxRaysPerDispatch;
-        const dim3 grid((unsigned)((n + kGridBlock - 1) / kGridBlock));
-#define RC_GRID(SS_, W_)                                                                     \
-        hipLaunchKernelGGL((k_trace<MODE, FMT, SS_, W_>), grid, dim3(kGridBlock), 0, s, jobs,    \
+        const dim3 grid((unsigned)((n + blk - 1) / blk));
+#define RC_GRID2(SS_, W_, B_)                                                                \
+        hipLaunchKernelGGL((k_trace<MODE, FMT, SS_, W_, B_>), grid, dim3(B_), 0, s, jobs,      \
                            n_jobs, g0, total, out_range, out_hit, out_nodes, out_tris)
-        if (MODE == TRACE_BRUTE) RC_GRID(0, 1);
+#define RC_GRID(SS_, W_)                                                                     \
+        if (blk == 256) RC_GRID2(SS_, W_, 256); else RC_GRID2(SS_, W_, 64)
+        if (MODE == TRACE_BRUTE) RC_GRID2(0, 1, 64);
         else if (cfg.stack_lds == 0 && cfg.waves_cap) RC_GRID(0, 8);
         else if (cfg.stack_lds == 0) RC_GRID(0, 1);
         else if (cfg.stack_lds == 8 && cfg.waves_cap) RC_GRID(8, 8);
         else if (cfg.stack_lds == 8) RC_GRID(8, 1);
         else RC_GRID(16, 1);
 #undef RC_GRID
+#undef RC_GRID2
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -33,7 +33,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(rcast.rc_job) == 40
     assert ctypes.sizeof(rcast.rc_build_opts) == 32
     assert rcast.rc_scene_info.scene_lo.offset == 56
-    assert ctypes.sizeof(rcast.rc_tuning) == 32
+    assert ctypes.sizeof(rcast.rc_tuning) == 36
 
 
 def test_error_path_without_device_is_clean():

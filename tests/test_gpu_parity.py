@@ -206,6 +206,8 @@ TUNINGS = [
     dict(persistent=1, stack_lds=16, refill_min=32, blocks_per_cu=1, tile_az=16, tile_el=4, chunk_max=1024, waves_cap=0),
     dict(persistent=1, stack_lds=24, refill_min=64, blocks_per_cu=2, tile_az=8, tile_el=8, chunk_max=1024, waves_cap=0),
     dict(persistent=1, stack_lds=16, refill_min=48, blocks_per_cu=0, tile_az=64, tile_el=1, chunk_max=1024, waves_cap=0),
+    dict(persistent=0, stack_lds=0, refill_min=64, blocks_per_cu=0, tile_az=16, tile_el=4, chunk_max=4096, waves_cap=1, group_waves=4),
+    dict(persistent=0, stack_lds=16, refill_min=64, blocks_per_cu=0, tile_az=0, tile_el=0, chunk_max=4096, waves_cap=0, group_waves=4),
 ]
 
 
@@ -245,6 +247,8 @@ def test_tuning_rejects_bad_values(ctx):
         ctx.set_tuning(refill_min=0)
     with pytest.raises(RcastError):
         ctx.set_tuning(refill_min=65)
+    with pytest.raises(RcastError):
+        ctx.set_tuning(group_waves=2)
     default = Context(0)
     try:
         ctx.set_tuning(persistent=1, stack_lds=24, refill_min=7)
