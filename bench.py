@@ -65,14 +65,18 @@ def kernel_source_hash() -> str:
 def load_traffic(kernel_hash: str, rays: int, tris: int, tuning: dict):
     """Counters of the traversal kernel measured by rocprofv3 (profiles/):
     HBM bytes per launch, L2 hit rate, VALU utilisation.  None when absent or
-    taken on a different kernel source, workload or launch shape."""
+    taken on a different kernel code, workload or kernel variant."""
     p = os.path.join(ROOT, "profiles", "trace_traffic.json")
     if not os.path.exists(p):
         return None
     with open(p) as fh:
         d = json.load(fh)
+    # the kernel variant is fixed by these fields (the packet tile only
+    # reorders the rays of the same kernel)
+    variant = ("persistent", "stack_lds", "waves_cap", "group_waves")
+    t0 = d.get("tuning") or {}
     if (d.get("kernel_hash") != kernel_hash or d.get("rays") != rays
-            or d.get("tris") != tris or d.get("tuning") != tuning):
+            or d.get("tris") != tris or any(t0.get(k) != tuning.get(k) for k in variant)):
         return None
     return d
 
