@@ -137,6 +137,10 @@ def main():
     ap.add_argument("--batch-cap-m", type=int, default=64,
                     help="serve: most rays per batched launch, in millions (0: no cap)")
     ap.add_argument("--inflight", type=int, default=3, help="serve: launches in flight")
+    ap.add_argument("--policy", type=int, default=0,
+                    help="serve: admission order, 0 arrival order, 1 fewest rays first with aging")
+    ap.add_argument("--max-wait-ms", type=int, default=0,
+                    help="serve, policy 1: age after which a request goes first (0: 200 ms)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -487,7 +491,8 @@ def run_serve(args):
 
     def serve_run(reqs, arrivals):
         ctx.serve_start(arena_bytes=48 << 30, max_inflight=args.inflight,
-                        max_batch_rays_m=args.batch_cap_m)
+                        max_batch_rays_m=args.batch_cap_m, policy=args.policy,
+                        max_wait_ms=args.max_wait_ms)
         tickets = [None] * len(reqs)
         t0 = time.perf_counter()
 
@@ -571,7 +576,8 @@ def run_serve(args):
         "config": {"workload": f"Poisson requests, {n_scenes} resident terrains "
                                f"({int(sizes.sum())} triangles), 1..4096 envs, 20 patterns",
                    "capacity_req_s": round(cap_rps, 2), "batch_cap_m_rays": args.batch_cap_m,
-                   "max_inflight": args.inflight},
+                   "max_inflight": args.inflight, "policy": args.policy,
+                   "max_wait_ms": args.max_wait_ms or 200},
         "rates": results,
     }
     print(json.dumps(out), flush=True)

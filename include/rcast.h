@@ -294,7 +294,13 @@ typedef struct {
     int32_t mock_fail_scene;  /* mock context: requests on scene
                                  (mock_fail_scene - 1) fail with RC_E_DEVICE
                                  (0 = none)                                  */
-    int32_t reserved[4];
+    int32_t policy;           /* admission order: 0 = arrival order, never
+                                 overtaking (default); 1 = fewest rays first
+                                 among requests queued less than max_wait_ms,
+                                 older ones first in arrival order           */
+    int32_t max_wait_ms;      /* policy 1: age after which a request goes
+                                 ahead of younger ones (0 = 200 ms)          */
+    int32_t reserved[2];
 } rc_serve_opts;
 
 typedef struct {

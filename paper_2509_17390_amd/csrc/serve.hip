@@ -24,6 +24,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -306,34 +307,65 @@ void worker_loop(ServeState *Sp)
             return S.stop || (!S.pending.empty() && S.inflight < S.opts.max_inflight);
         });
         if (S.stop) break;
-        // admit in arrival order while the head fits; stop at the first
-        // request that does not (no overtaking, hence no starvation)
         Batch *b = new Batch();
         b->S = &S;
         int64_t rays = 0;
         const int64_t cap = (int64_t)S.opts.max_batch_rays_m * 1000000;
-        while (!S.pending.empty()) {
-            Request *r = S.pending.front();
-            if (cap > 0 && !b->reqs.empty() && rays + r->n_rays > cap) break;
+        // admission order: arrival order (policy 0), or requests queued
+        // longer than max_wait_ms in arrival order followed by the younger
+        // ones by ray count (policy 1)
+        std::vector<Request *> order(S.pending.begin(), S.pending.end());
+        size_t n_old = order.size();
+        if (S.opts.policy == 1) {
+            const auto now = Clock::now();
+            const auto limit = std::chrono::milliseconds(S.opts.max_wait_ms);
+            auto young = std::stable_partition(order.begin(), order.end(), [&](Request *r) {
+                return now - r->t_submit >= limit;
+            });
+            n_old = (size_t)(young - order.begin());
+            std::stable_sort(young, order.end(),
+                             [](Request *a, Request *c2) { return a->n_rays < c2->n_rays; });
+        }
+        bool any = false;
+        for (size_t k = 0; k < order.size(); ++k) {
+            Request *r = order[k];
+            const bool in_order = k < n_old;   // may not be overtaken
+            bool fits = !(cap > 0 && !b->reqs.empty() && rays + r->n_rays > cap);
             uint64_t oo = 0, po = 0;
-            if (!S.out_arena.alloc((uint64_t)r->n_rays, &oo)) break;
-            if (!S.pose_arena.alloc((uint64_t)r->req.n_envs * 12, &po)) {
+            if (fits && !S.out_arena.alloc((uint64_t)r->n_rays, &oo)) fits = false;
+            if (fits && !S.pose_arena.alloc((uint64_t)r->req.n_envs * 12, &po)) {
                 S.out_arena.release(oo, (uint64_t)r->n_rays);
-                break;
+                fits = false;
+            }
+            if (!fits) {
+                if (in_order) break;   // nothing behind it may go first
+                continue;              // a smaller young request may still fit
             }
             r->out_off = oo;
             r->pose_off = po;
             r->has_mem = true;
             r->state = REQ_RUNNING;
-            S.pending.pop_front();
             b->reqs.push_back(r);
+            any = true;
             rays += r->n_rays;
+        }
+        if (any) {
+            // drop the admitted (now running) requests from the queue,
+            // keeping the order of the rest
+            std::deque<Request *> rest;
+            for (Request *r : S.pending)
+                if (r->state == REQ_PENDING) rest.push_back(r);
+            S.pending.swap(rest);
         }
         if (b->reqs.empty()) {
             delete b;
-            // the head does not fit yet: wait until memory is returned
-            const uint64_t gen = S.generation;
-            S.cv.wait(lk, [&] { return S.stop || S.generation != gen || S.pending.empty(); });
+            // nothing fits yet: wait until memory is returned or (for the
+            // small-first order) a new request arrives
+            const uint64_t gen = S.generation, sub = S.stats.submitted;
+            S.cv.wait(lk, [&] {
+                return S.stop || S.generation != gen || S.pending.empty() ||
+                       (S.opts.policy == 1 && S.stats.submitted != sub);
+            });
             continue;
         }
         int si = 0;
@@ -424,6 +456,9 @@ rc_status rc_serve_start(rc_ctx *c, const rc_serve_opts *opts)
     if (o.max_batch_rays_m < 0) return fail(RC_E_INVAL, "max_batch_rays_m < 0");
     if (o.mock_ns_per_ray < 0) return fail(RC_E_INVAL, "mock_ns_per_ray < 0");
     if (o.arena_bytes < (1u << 20)) return fail(RC_E_INVAL, "arena_bytes must be >= 1 MiB");
+    if (o.policy != 0 && o.policy != 1) return fail(RC_E_INVAL, "policy must be 0 or 1");
+    if (o.max_wait_ms < 0) return fail(RC_E_INVAL, "max_wait_ms < 0");
+    if (o.max_wait_ms == 0) o.max_wait_ms = 200;
     ServeState *S = new ServeState();
     S->ctx = c;
     S->opts = o;

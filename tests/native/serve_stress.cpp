@@ -5,7 +5,9 @@
 // patterns, poll them to completion, check the simulated results
 // (range = ray index within the request, hit = scene id), copy them out and
 // release the ticket; a fifth thread polls statistics.  One scene's
-// requests fail on purpose.  Exit status 0 when every check passes.
+// requests fail on purpose.  Runs once with arrival-order admission and once
+// with small-first admission under a per-launch ray cap.  Exit status 0 when
+// every check passes.
 #include "rcast.h"
 
 #include <atomic>
@@ -42,11 +44,16 @@ int main()
         for (int j = 0; j < nb[p]; ++j) d[3 * j] = 1.0f;
         CHECK(rc_pattern_upload(c, d.data(), nb[p], 0, &pat[p]) == RC_OK);
     }
+    // first in arrival order, then small-first with aging and a ray cap
+    for (int policy = 0; policy < 2; ++policy) {
     rc_serve_opts o{};
     o.arena_bytes = 4u << 20;
     o.max_inflight = 3;
     o.mock_ns_per_ray = 20;
     o.mock_fail_scene = scene[2] + 1;
+    o.policy = policy;
+    o.max_wait_ms = 5;
+    o.max_batch_rays_m = policy;
     CHECK(rc_serve_start(c, &o) == RC_OK);
 
     std::atomic<bool> done{false};
@@ -109,6 +116,7 @@ int main()
     CHECK(rc_serve_get_stats(c, &s) == RC_OK);
     CHECK(s.submitted == 240 && s.completed + s.failed == 240 && s.bytes_in_use == 0);
     CHECK(rc_serve_stop(c) == RC_OK);
+    }
     rc_destroy(c);
     std::printf("serve_stress: %s\n", g_bad.load() ? "FAILED" : "ok");
     return g_bad.load() ? 1 : 0;

@@ -187,6 +187,53 @@ def test_batch_cap_splits_launches_and_runs_large_requests_alone():
     c.close()
 
 
+def _completion_order(c, tickets, timeout_s=20.0):
+    done = {}
+    t0 = time.perf_counter()
+    while len(done) < len(tickets) and time.perf_counter() - t0 < timeout_s:
+        for tk in tickets:
+            if tk not in done and c.poll(tk, 0)[0] == RC_OK:
+                done[tk] = time.perf_counter()
+                c.release(tk)            # results hold arena memory until released
+        time.sleep(0.0005)
+    assert len(done) == len(tickets)
+    return done
+
+
+@pytest.mark.parametrize("policy,max_wait_ms,small_first", [(0, 0, False), (1, 10_000, True),
+                                                           (1, 20, False)])
+def test_admission_policy(policy, max_wait_ms, small_first):
+    """A 200k-ray request queued ahead of five 10k-ray ones while a 100k-ray
+    launch holds the only slot; the arena takes 229k rays.  Arrival order
+    runs the large one first; small-first runs the small ones first unless
+    the large one has already waited max_wait_ms."""
+    c, scenes, pats = mock_ctx()
+    c.serve_start(arena_bytes=2 << 20, max_inflight=1, mock_ns_per_ray=1000,
+                  policy=policy, max_wait_ms=max_wait_ms)
+    block = c.submit(scenes[0], pats[1], poses(100), 0.0, 1.0)   # 100k rays: 0.1 s
+    time.sleep(0.01)
+    big = c.submit(scenes[1], pats[2], poses(40), 0.0, 1.0)      # 200k rays
+    time.sleep(0.05)                                             # big ages 50 ms
+    small = [c.submit(scenes[2], pats[1], poses(10), 0.0, 1.0) for _ in range(5)]
+    done = _completion_order(c, [block, big] + small)
+    last_small = max(done[tk] for tk in small)
+    if small_first:
+        assert last_small < done[big]
+    else:
+        assert done[big] <= last_small
+    c.serve_stop()
+    c.close()
+
+
+def test_bad_policy_rejected():
+    c, scenes, pats = mock_ctx()
+    with pytest.raises(RcastError):
+        c.serve_start(policy=2)
+    with pytest.raises(RcastError):
+        c.serve_start(policy=1, max_wait_ms=-1)
+    c.close()
+
+
 def test_concurrent_submitters():
     c, scenes, pats = mock_ctx()
     c.serve_start(arena_bytes=64 << 20, max_inflight=3, mock_ns_per_ray=5)
