@@ -59,12 +59,13 @@ def cast_alone(ctx, r):
     return rng.cpu().numpy(), hit.cpu().numpy()
 
 
-@pytest.mark.parametrize("cap_m", [0, 1])
-def test_served_results_equal_alone(world, cap_m):
+@pytest.mark.parametrize("cap_m,policy", [(0, 0), (1, 0), (1, 1)])
+def test_served_results_equal_alone(world, cap_m, policy):
     ctx, scenes, pats = world
-    reqs = make_requests(scenes, pats, 40, cap_m)
+    reqs = make_requests(scenes, pats, 40, cap_m + 2 * policy)
     alone = [cast_alone(ctx, r) for r in reqs]
-    ctx.serve_start(arena_bytes=256 << 20, max_inflight=3, max_batch_rays_m=cap_m)
+    ctx.serve_start(arena_bytes=256 << 20, max_inflight=3, max_batch_rays_m=cap_m,
+                    policy=policy, max_wait_ms=5)
     try:
         tickets = [None] * len(reqs)
 
