@@ -347,6 +347,99 @@ rc_status rc_serve_copy(rc_ctx *ctx, uint64_t ticket, float *range_dst, int32_t 
 /* Counters of the running server. */
 rc_status rc_serve_get_stats(rc_ctx *ctx, rc_serve_stats *out);
 
+/* ------------------------------------------------------------------------
+ * Gaussian-to-occupancy conversion (Sec. IV-A, "Grid query and occupancy
+ * evaluation", on the Gaussian model of Sec. III-A).
+ *
+ * A Gaussian G_i has mean mu_i, covariance Sigma_i = R_i S_i S_i^T R_i^T and
+ * opacity alpha_i; its box b_i is the axis-aligned box of the k-sigma
+ * ellipsoid, mu_i +- k sqrt(diag Sigma_i).  On a voxel grid (origin o,
+ * spacing h, voxel (i, j, k) = the cell o + [i, i+1] x [j, j+1] x [k, k+1] h
+ * with centre v = o + (i + 1/2, j + 1/2, k + 1/2) h) cut into tiles of 8^3
+ * voxels, each voxel receives
+ *     D(v) = sum over G_i in C_tile of
+ *            exp(-1/2 (v - mu_i)^T Sigma_i^-1 (v - mu_i)) alpha_i^2,
+ *     C_tile = { G_i : b_i meets the tile's box }  (closed boxes),
+ * then V_occ = [D(v) > theta] and Surf = V_occ and not (V_occ on all six
+ * face neighbours), neighbours outside the grid counting as unoccupied.
+ * C_tile is found by querying an LBVH over the boxes (Morton codes of the
+ * box centres, radix sort, Karras hierarchy, bottom-up box reduction).
+ * Box ends and tile-box ends are evaluated in FP64 and rounded to the
+ * nearest float32, so membership is an exact float32 comparison.
+ * ---------------------------------------------------------------------- */
+
+/* Copy n Gaussians in (3DGS parameterisation, with activations applied):
+ *   means_xyz  float32 [n][3]
+ *   quats_wxyz float32 [n][4]  rotation quaternion (w, x, y, z); need not be
+ *                              unit length (R is the rotation of q / |q|)
+ *   scales_xyz float32 [n][3]  linear scales, > 0 (S = diag(s))
+ *   opacity    float32 [n]     alpha in [0, 1]
+ *   src_is_device: 1 if all four arrays are device pointers, 0 if host.
+ * The caller keeps ownership; the copy is complete when the call returns.
+ * n may be 0 (every density is then 0).  *out_set receives the handle.
+ * Errors: RC_E_INVAL (sizes, non-finite value, scale <= 0, zero quaternion,
+ * opacity outside [0, 1]), RC_E_NOMEM, RC_E_DEVICE. */
+rc_status rc_gauss_upload(rc_ctx *ctx, const float *means_xyz, const float *quats_wxyz,
+                          const float *scales_xyz, const float *opacity, int64_t n,
+                          int src_is_device, void *stream, int32_t *out_set);
+
+/* Options for rc_gauss_build.  Zero-initialised means the defaults. */
+typedef struct {
+    float cutoff_sigma;   /* k of the k-sigma boxes, > 0 (0 = 3)            */
+    int32_t morton_bits;  /* bits per axis, 1..10 (0 = 10)                  */
+    int32_t reserved[6];
+} rc_gauss_opts;
+
+/* Compute the Gaussian boxes and build the LBVH over them (Sec. IV-A LBVH
+ * construction) plus the per-leaf evaluation records, on `stream`.  A later
+ * rc_voxelize on any stream must be ordered after this call's work.
+ * Errors: RC_E_NOTFOUND (set), RC_E_INVAL (options), RC_E_NOMEM, RC_E_DEVICE. */
+rc_status rc_gauss_build(rc_ctx *ctx, int32_t set, const rc_gauss_opts *opts, void *stream);
+
+/* Drop a Gaussian set.  Waits for the device, then frees its memory.
+ * Errors: RC_E_NOTFOUND. */
+rc_status rc_gauss_release(rc_ctx *ctx, int32_t set);
+
+/* Voxel grid of one conversion. */
+typedef struct {
+    float origin[3];     /* o, metres                                        */
+    float spacing;       /* h > 0, metres                                    */
+    int32_t dims[3];     /* nx, ny, nz >= 1; at most 2^30 voxels per axis    */
+    int32_t tile;        /* tile edge B in voxels: 8 (0 = 8)                 */
+    float theta;         /* density threshold (finite)                       */
+    int32_t reserved[3];
+} rc_grid;
+
+/* Convert a built set on `grid`.  Outputs are DEVICE arrays owned by the
+ * caller, laid out [nz][ny][nx] (x fastest):
+ *   out_density float32 D(v), or NULL
+ *   out_occ     uint8   V_occ (0/1), or NULL
+ *   out_surf    uint8   Surf (0/1), or NULL; needs out_occ
+ * At least one output must be given.  Stream-ordered on `stream`.  The
+ * density is accumulated in fixed point with units of 2^-31 per term, so
+ * results are identical from run to run; V_occ is taken on the float32 D.
+ * Errors: RC_E_INVAL (grid, outputs), RC_E_NOTFOUND (set), RC_E_STATE (set
+ * not built), RC_E_DEVICE. */
+rc_status rc_voxelize(rc_ctx *ctx, int32_t set, const rc_grid *grid, float *out_density,
+                      uint8_t *out_occ, uint8_t *out_surf, void *stream);
+
+/* |C_tile| of every tile, DEVICE int32 [tz][ty][tx] with t = ceil(n / 8)
+ * per axis (the query of rc_voxelize without the evaluation).  Same errors. */
+rc_status rc_voxelize_counts(rc_ctx *ctx, int32_t set, const rc_grid *grid,
+                             int32_t *out_tile_counts, void *stream);
+
+/* Copy an internal array of a built set to HOST memory (for tests):
+ *   RC_GDBG_BOXES     float32 [n][6]  Gaussian boxes lo xyz, hi xyz (input order)
+ *   RC_GDBG_SORTED    uint32 [n]      Gaussian index in leaf order
+ *   RC_GDBG_TOPOLOGY  int32 [n-1][3]  as RC_DBG_TOPOLOGY
+ *   RC_GDBG_RECORDS   64 bytes per leaf: mu xyz, alpha^2 2^31, the whitening
+ *                     matrix c0 S^-1 R^T (row-major, c0 = sqrt(log2(e) / 2)),
+ *                     the Gaussian's index (int bits), 2 unused
+ * `bytes` must equal the array's size.  Synchronises the device. */
+enum { RC_GDBG_BOXES = 1, RC_GDBG_SORTED = 2, RC_GDBG_TOPOLOGY = 3, RC_GDBG_RECORDS = 4 };
+rc_status rc_gauss_debug_copy(rc_ctx *ctx, int32_t set, int32_t what, void *host_dst,
+                              uint64_t bytes);
+
 /* Device id of a host-only context for rc_create: no HIP calls; scenes and
  * patterns hold their sizes only (rc_scene_upload needs host arrays);
  * rc_raycast_* report RC_E_STATE; the server runs requests on a simulated

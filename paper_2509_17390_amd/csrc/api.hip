@@ -315,6 +315,24 @@ rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, 
     return RC_OK;
 }
 
+rc_status ensure_build_ws(rc_ctx *c, size_t need, hipStream_t s)
+{
+    if (need > c->ws_bytes) {
+        if (c->ws) {
+            HIP_TRY(hipDeviceSynchronize());
+            dev_free(c, c->ws, c->ws_bytes);
+            c->ws = nullptr;
+            c->ws_bytes = 0;
+        }
+        rc_status st = dev_alloc(c, &c->ws, need);
+        if (st != RC_OK) return st;
+        c->ws_bytes = need;
+        c->ws_event_recorded = false;
+    }
+    if (c->ws_event_recorded) HIP_TRY(hipStreamWaitEvent(s, c->ws_event, 0));
+    return RC_OK;
+}
+
 }  // namespace rc
 
 using namespace rc;
@@ -372,6 +390,8 @@ void rc_destroy(rc_ctx *c)
         if (s.alive) free_scene(c, s);
     for (auto &p : c->patterns)
         if (p.alive) dev_free(c, p.dirs, p.bytes);
+    for (auto &g : c->gsets)
+        if (g.alive) free_gauss_set(c, g);
     for (auto &sl : c->slots) {
         if (sl.host) (void)hipHostFree(sl.host);
         if (sl.dev) dev_free(c, sl.dev, slot_bytes(sl.cap));
@@ -497,20 +517,8 @@ rc_status rc_lbvh_build(rc_ctx *c, int32_t scene, const rc_build_opts *opts, voi
         sc->bytes += sizeof(NodeRec) * ni;
     }
     if (nt > 0) {
-        size_t need = lbvh_workspace_bytes(nt);
-        if (need > c->ws_bytes) {
-            if (c->ws) {
-                HIP_TRY(hipDeviceSynchronize());
-                dev_free(c, c->ws, c->ws_bytes);
-                c->ws = nullptr;
-                c->ws_bytes = 0;
-            }
-            rc_status st = dev_alloc(c, &c->ws, need);
-            if (st != RC_OK) return st;
-            c->ws_bytes = need;
-            c->ws_event_recorded = false;
-        }
-        if (c->ws_event_recorded) HIP_TRY(hipStreamWaitEvent(s, c->ws_event, 0));
+        rc_status st = ensure_build_ws(c, lbvh_workspace_bytes(nt), s);
+        if (st != RC_OK) return st;
         BuildBuffers b;
         b.verts = sc->verts;
         b.tris = sc->tris;

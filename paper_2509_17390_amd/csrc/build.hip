@@ -111,6 +111,36 @@ __global__ __launch_bounds__(kBlock) void k_tri_bounds(const float *__restrict__
     }
 }
 
+// union of ready-made primitive boxes (same reduction as k_tri_bounds)
+__global__ __launch_bounds__(kBlock) void k_box_union(const float *__restrict__ bounds, int64_t n,
+                                                      uint32_t *__restrict__ box)
+{
+    __shared__ float red[kBlock / 64][6];
+    float acc[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float *b = bounds + 6 * i;
+        for (int a = 0; a < 3; ++a) {
+            acc[a] = fminf(acc[a], b[a]);
+            acc[3 + a] = fmaxf(acc[3 + a], b[3 + a]);
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        acc[a] = wave_min(acc[a]);
+        acc[3 + a] = wave_max(acc[3 + a]);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 6; ++a) red[w][a] = acc[a];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int a = threadIdx.x;
+        float v = red[0][a];
+        for (int ww = 1; ww < kBlock / 64; ++ww) v = a < 3 ? fminf(v, red[ww][a]) : fmaxf(v, red[ww][a]);
+        if (a < 3) atomicMin(box + a, f2o(v)); else atomicMax(box + a, f2o(v));
+    }
+}
+
 __global__ void k_box_to_float(const uint32_t *box, float *out)
 {
     if (threadIdx.x < 6) out[threadIdx.x] = o2f(box[threadIdx.x]);
@@ -678,8 +708,13 @@ hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
 
     hipLaunchKernelGGL(k_init_box, dim3(1), dim3(64), 0, s, obox);
     const unsigned bgrid = grid_for(n, kBlock) < 2048u ? grid_for(n, kBlock) : 2048u;
-    hipLaunchKernelGGL(k_tri_bounds, dim3(bgrid), dim3(kBlock), 0, s, b.verts, b.tris, n, bounds,
-                       obox);
+    if (b.prim_boxes) {
+        bounds = const_cast<float *>(b.prim_boxes);
+        hipLaunchKernelGGL(k_box_union, dim3(bgrid), dim3(kBlock), 0, s, b.prim_boxes, n, obox);
+    } else {
+        hipLaunchKernelGGL(k_tri_bounds, dim3(bgrid), dim3(kBlock), 0, s, b.verts, b.tris, n,
+                           bounds, obox);
+    }
     hipLaunchKernelGGL(k_box_to_float, dim3(1), dim3(64), 0, s, obox, b.scene_box);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, bounds,
                        b.scene_box, n, b.morton_bits, b.morton, keys0, vals0);
@@ -697,8 +732,9 @@ hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
     }
     hipError_t e = hipMemcpyAsync(b.sorted, vin, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tri_records, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, b.verts,
-                       b.tris, b.sorted, n, b.trirecs);
+    if (b.trirecs)
+        hipLaunchKernelGGL(k_tri_records, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, b.verts,
+                           b.tris, b.sorted, n, b.trirecs);
     if (n == 1) {
         hipLaunchKernelGGL(k_single_tri_depth, dim3(1), dim3(1), 0, s, b.depth_out);
         return hipGetLastError();

@@ -47,6 +47,35 @@ struct Pattern {
     uint64_t bytes = 0;
 };
 
+// A set of Gaussians (Sec. III-A) and its LBVH (Sec. IV-A).
+struct GaussSet {
+    bool alive = false;
+    int64_t n = 0;
+    float *params = nullptr;     // mean [n][3], quat [n][4], scale [n][3], opacity [n]
+    float *boxes = nullptr;      // [n][6] Gaussian boxes (input order)
+    bool has_bvh = false;
+    float cutoff = 3.0f;         // k of the k-sigma boxes
+    int morton_bits = 10;
+    uint32_t *morton = nullptr;
+    uint32_t *sorted = nullptr;
+    int32_t *topo = nullptr;
+    NodeRec *nodes = nullptr;
+    GaussRec *recs = nullptr;    // [n] evaluation records in leaf order
+    float *box_dev = nullptr;    // [8]: box (6) + depth (int bits) + unused
+    uint64_t bytes = 0;
+
+    GaussParams view() const
+    {
+        GaussParams p;
+        p.mean = params;
+        p.quat = params + 3 * n;
+        p.scale = params + 7 * n;
+        p.opacity = params + 10 * n;
+        p.n = n;
+        return p;
+    }
+};
+
 constexpr int kSlots = 8;
 
 // A slot holds one launch's job table followed by its work queues.
@@ -71,6 +100,7 @@ struct rc_ctx {
     std::mutex job_mu;    // job slots, tuning
     std::vector<rc::Scene> scenes;
     std::vector<rc::Pattern> patterns;
+    std::vector<rc::GaussSet> gsets;
     void *ws = nullptr;
     size_t ws_bytes = 0;
     hipEvent_t ws_event = nullptr;
@@ -88,6 +118,11 @@ rc_status dev_alloc(rc_ctx *c, void **p, size_t bytes);
 void dev_free(rc_ctx *c, void *p, size_t bytes);
 Scene *get_scene(rc_ctx *c, int32_t id);      // caller holds c->mu
 Pattern *get_pattern(rc_ctx *c, int32_t id);  // caller holds c->mu
+void free_gauss_set(rc_ctx *c, GaussSet &g);  // caller holds c->mu
+
+// Grow the shared LBVH build workspace to at least `need` bytes and order
+// `s` after the previous build that used it.  Caller holds c->mu.
+rc_status ensure_build_ws(rc_ctx *c, size_t need, hipStream_t s);
 rc_tuning default_tuning();
 
 // Job table staging owned by one caller stream (the request server keeps

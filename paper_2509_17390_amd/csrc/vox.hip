@@ -1,0 +1,314 @@
+// vox.hip -- C ABI of the Gaussian-to-occupancy conversion (FGGS-LiDAR
+// Sec. IV-A on the Gaussian model of Sec. III-A): Gaussian sets, their
+// LBVH, and the tiled density / occupancy / surface launches.
+#include "ctx.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+
+namespace rc {
+
+void free_gauss_set(rc_ctx *c, GaussSet &g)
+{
+    const int64_t n = g.n, ni = n > 1 ? n - 1 : 1;
+    dev_free(c, g.params, sizeof(float) * 11 * n);
+    dev_free(c, g.boxes, sizeof(float) * 6 * n);
+    dev_free(c, g.morton, sizeof(uint32_t) * n);
+    dev_free(c, g.sorted, sizeof(uint32_t) * n);
+    dev_free(c, g.topo, sizeof(int32_t) * 3 * ni);
+    dev_free(c, g.nodes, sizeof(NodeRec) * ni);
+    dev_free(c, g.recs, sizeof(GaussRec) * n);
+    dev_free(c, g.box_dev, sizeof(float) * 8);
+    g = GaussSet();
+}
+
+namespace {
+
+GaussSet *get_gset(rc_ctx *c, int32_t id)
+{
+    if (id < 0 || id >= (int32_t)c->gsets.size() || !c->gsets[id].alive) return nullptr;
+    return &c->gsets[id];
+}
+
+// Checks the grid and fills the launch description.
+rc_status make_grid(const rc_grid *gr, VoxGrid &g)
+{
+    if (!gr) return fail(RC_E_INVAL, "null grid");
+    const int tile = gr->tile ? gr->tile : kVoxTile;
+    if (tile != kVoxTile) return fail(RC_E_INVAL, "tile edge %d not supported (8)", gr->tile);
+    if (!(gr->spacing > 0.0f) || !isfinite(gr->spacing))
+        return fail(RC_E_INVAL, "spacing must be finite and > 0");
+    if (!isfinite(gr->theta)) return fail(RC_E_INVAL, "theta must be finite");
+    for (int a = 0; a < 3; ++a) {
+        if (!isfinite(gr->origin[a])) return fail(RC_E_INVAL, "origin must be finite");
+        if (gr->dims[a] < 1 || gr->dims[a] > (1 << 30))
+            return fail(RC_E_INVAL, "dims must be in 1..2^30");
+        const double far = fabs((double)gr->origin[a]) + (double)gr->dims[a] * gr->spacing;
+        if (!(far < 1e38)) return fail(RC_E_INVAL, "grid extends beyond the float range");
+    }
+    memset(&g, 0, sizeof g);
+    for (int a = 0; a < 3; ++a) g.o[a] = gr->origin[a];
+    g.h = gr->spacing;
+    g.nx = gr->dims[0];
+    g.ny = gr->dims[1];
+    g.nz = gr->dims[2];
+    g.tx = (g.nx + kVoxTile - 1) / kVoxTile;
+    g.ty = (g.ny + kVoxTile - 1) / kVoxTile;
+    g.tz = (g.nz + kVoxTile - 1) / kVoxTile;
+    g.n_tiles = (int64_t)g.tx * g.ty * g.tz;
+    if (g.n_tiles > 0x7ffffff0LL) return fail(RC_E_INVAL, "too many tiles (%lld)", (long long)g.n_tiles);
+    g.theta = gr->theta;
+    return RC_OK;
+}
+
+// Looks up a built set for a conversion launch (caller holds c->mu).
+rc_status built_set(rc_ctx *c, int32_t set, GaussSet **out)
+{
+    GaussSet *g = get_gset(c, set);
+    if (!g) return fail(RC_E_NOTFOUND, "unknown Gaussian set %d", set);
+    if (!g->has_bvh) return fail(RC_E_STATE, "Gaussian set %d is not built (call rc_gauss_build)", set);
+    *out = g;
+    return RC_OK;
+}
+
+}  // namespace
+}  // namespace rc
+
+using namespace rc;
+
+rc_status rc_gauss_upload(rc_ctx *c, const float *means, const float *quats, const float *scales,
+                          const float *opacity, int64_t n, int src_is_device, void *stream,
+                          int32_t *out_set)
+{
+    if (!c || !out_set) return fail(RC_E_INVAL, "null context or out_set");
+    if (n < 0) return fail(RC_E_INVAL, "negative size");
+    if (n > 0x7ffffffeLL) return fail(RC_E_INVAL, "too many Gaussians (%lld)", (long long)n);
+    if (n > 0 && (!means || !quats || !scales || !opacity))
+        return fail(RC_E_INVAL, "null Gaussian array");
+    if (c->mock) return fail(RC_E_STATE, "a mock context does not convert Gaussians");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(c->mu);
+    GaussSet g;
+    g.n = n;
+    rc_status st = dev_alloc(c, (void **)&g.params, sizeof(float) * 11 * n);
+    if (st == RC_OK) st = dev_alloc(c, (void **)&g.box_dev, sizeof(float) * 8);
+    if (st != RC_OK) {
+        free_gauss_set(c, g);
+        return st;
+    }
+    const GaussParams p = g.view();
+    const hipMemcpyKind kind = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipError_t e = hipSuccess;
+    if (n) e = hipMemcpyAsync((void *)p.mean, means, sizeof(float) * 3 * n, kind, s);
+    if (e == hipSuccess && n) e = hipMemcpyAsync((void *)p.quat, quats, sizeof(float) * 4 * n, kind, s);
+    if (e == hipSuccess && n) e = hipMemcpyAsync((void *)p.scale, scales, sizeof(float) * 3 * n, kind, s);
+    if (e == hipSuccess && n) e = hipMemcpyAsync((void *)p.opacity, opacity, sizeof(float) * n, kind, s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->flags_dev, 0, sizeof(int32_t), s);
+    if (e == hipSuccess) e = gauss_validate_launch(p, c->flags_dev, s);
+    int32_t flags = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&flags, c->flags_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_gauss_set(c, g);
+        return fail(RC_E_DEVICE, "Gaussian upload failed: %s", hipGetErrorString(e));
+    }
+    if (flags) {
+        free_gauss_set(c, g);
+        return fail(RC_E_INVAL, "invalid Gaussians:%s%s%s%s", (flags & 1) ? " non-finite value" : "",
+                    (flags & 2) ? " scale <= 0" : "", (flags & 4) ? " zero quaternion" : "",
+                    (flags & 8) ? " opacity outside [0, 1]" : "");
+    }
+    g.alive = true;
+    g.bytes = sizeof(float) * 11 * n;
+    int32_t id = -1;
+    for (size_t i = 0; i < c->gsets.size(); ++i)
+        if (!c->gsets[i].alive) { id = (int32_t)i; break; }
+    if (id < 0) {
+        id = (int32_t)c->gsets.size();
+        c->gsets.push_back(g);
+    } else {
+        c->gsets[id] = g;
+    }
+    *out_set = id;
+    return RC_OK;
+}
+
+rc_status rc_gauss_build(rc_ctx *c, int32_t set, const rc_gauss_opts *opts, void *stream)
+{
+    if (!c) return fail(RC_E_INVAL, "null context");
+    float k = 3.0f;
+    int bits = 10;
+    if (opts) {
+        if (opts->cutoff_sigma != 0.0f) k = opts->cutoff_sigma;
+        if (opts->morton_bits) bits = opts->morton_bits;
+    }
+    if (!(k > 0.0f) || !isfinite(k)) return fail(RC_E_INVAL, "cutoff_sigma must be finite and > 0");
+    if (bits < 1 || bits > 10) return fail(RC_E_INVAL, "morton_bits must be in 1..10");
+    if (c->mock) return fail(RC_E_STATE, "a mock context does not convert Gaussians");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(c->mu);
+    GaussSet *g = get_gset(c, set);
+    if (!g) return fail(RC_E_NOTFOUND, "unknown Gaussian set %d", set);
+    const int64_t n = g->n, ni = n > 1 ? n - 1 : 1;
+    if (n > 0 && !g->nodes) {
+        rc_status st = dev_alloc(c, (void **)&g->boxes, sizeof(float) * 6 * n);
+        if (st == RC_OK) st = dev_alloc(c, (void **)&g->morton, sizeof(uint32_t) * n);
+        if (st == RC_OK) st = dev_alloc(c, (void **)&g->sorted, sizeof(uint32_t) * n);
+        if (st == RC_OK) st = dev_alloc(c, (void **)&g->topo, sizeof(int32_t) * 3 * ni);
+        if (st == RC_OK) st = dev_alloc(c, (void **)&g->nodes, sizeof(NodeRec) * ni);
+        if (st == RC_OK) st = dev_alloc(c, (void **)&g->recs, sizeof(GaussRec) * n);
+        if (st != RC_OK) {
+            dev_free(c, g->boxes, sizeof(float) * 6 * n);
+            dev_free(c, g->morton, sizeof(uint32_t) * n);
+            dev_free(c, g->sorted, sizeof(uint32_t) * n);
+            dev_free(c, g->topo, sizeof(int32_t) * 3 * ni);
+            dev_free(c, g->nodes, sizeof(NodeRec) * ni);
+            dev_free(c, g->recs, sizeof(GaussRec) * n);
+            g->boxes = nullptr;
+            g->morton = g->sorted = nullptr;
+            g->topo = nullptr;
+            g->nodes = nullptr;
+            g->recs = nullptr;
+            return st;
+        }
+        g->bytes += sizeof(float) * 6 * n + sizeof(uint32_t) * 2 * n + sizeof(int32_t) * 3 * ni +
+                    sizeof(NodeRec) * ni + sizeof(GaussRec) * n;
+    }
+    if (n > 0) {
+        rc_status st = ensure_build_ws(c, lbvh_workspace_bytes(n), s);
+        if (st != RC_OK) return st;
+        const GaussParams p = g->view();
+        HIP_TRY(gauss_boxes_launch(p, k, g->boxes, s));
+        BuildBuffers b;
+        b.verts = nullptr;
+        b.tris = nullptr;
+        b.prim_boxes = g->boxes;
+        b.nv = 0;
+        b.nt = n;
+        b.morton_bits = bits;
+        b.ws = c->ws;
+        b.ws_bytes = c->ws_bytes;
+        b.morton = g->morton;
+        b.sorted = g->sorted;
+        b.topo = g->topo;
+        b.nodes = g->nodes;
+        b.trirecs = nullptr;
+        b.scene_box = g->box_dev;
+        b.depth_out = reinterpret_cast<int32_t *>(g->box_dev + 6);
+        b.q8nodes = nullptr;
+        b.q8_count = nullptr;
+        HIP_TRY(lbvh_build_launch(b, s));
+        HIP_TRY(gauss_records_launch(p, g->sorted, g->recs, s));
+        HIP_TRY(hipEventRecord(c->ws_event, s));
+        c->ws_event_recorded = true;
+    }
+    g->has_bvh = true;
+    g->cutoff = k;
+    g->morton_bits = bits;
+    return RC_OK;
+}
+
+rc_status rc_gauss_release(rc_ctx *c, int32_t set)
+{
+    if (!c) return fail(RC_E_INVAL, "null context");
+    if (c->mock) return fail(RC_E_STATE, "a mock context does not convert Gaussians");
+    HIP_TRY(hipSetDevice(c->device));
+    std::lock_guard<std::mutex> lk(c->mu);
+    GaussSet *g = get_gset(c, set);
+    if (!g) return fail(RC_E_NOTFOUND, "unknown Gaussian set %d", set);
+    HIP_TRY(hipDeviceSynchronize());
+    free_gauss_set(c, *g);
+    return RC_OK;
+}
+
+rc_status rc_voxelize(rc_ctx *c, int32_t set, const rc_grid *grid, float *out_density,
+                      uint8_t *out_occ, uint8_t *out_surf, void *stream)
+{
+    if (!c) return fail(RC_E_INVAL, "null context");
+    if (!out_density && !out_occ && !out_surf) return fail(RC_E_INVAL, "no output given");
+    if (out_surf && !out_occ) return fail(RC_E_INVAL, "the surface mask needs out_occ");
+    VoxGrid vg;
+    rc_status st = make_grid(grid, vg);
+    if (st != RC_OK) return st;
+    if (c->mock) return fail(RC_E_STATE, "a mock context does not convert Gaussians");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const NodeRec *nodes;
+    const GaussRec *recs;
+    const float *boxes;
+    int64_t n;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        GaussSet *g;
+        st = built_set(c, set, &g);
+        if (st != RC_OK) return st;
+        nodes = g->nodes;
+        recs = g->recs;
+        boxes = g->boxes;
+        n = g->n;
+    }
+    HIP_TRY(voxelize_launch(0, nodes, recs, boxes, n, vg, out_density, out_occ, nullptr, s));
+    if (out_surf) HIP_TRY(surface_launch(out_occ, out_surf, vg, s));
+    return RC_OK;
+}
+
+rc_status rc_voxelize_counts(rc_ctx *c, int32_t set, const rc_grid *grid, int32_t *out_counts,
+                             void *stream)
+{
+    if (!c || !out_counts) return fail(RC_E_INVAL, "null argument");
+    VoxGrid vg;
+    rc_status st = make_grid(grid, vg);
+    if (st != RC_OK) return st;
+    if (c->mock) return fail(RC_E_STATE, "a mock context does not convert Gaussians");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const NodeRec *nodes;
+    const GaussRec *recs;
+    const float *boxes;
+    int64_t n;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        GaussSet *g;
+        st = built_set(c, set, &g);
+        if (st != RC_OK) return st;
+        nodes = g->nodes;
+        recs = g->recs;
+        boxes = g->boxes;
+        n = g->n;
+    }
+    HIP_TRY(voxelize_launch(1, nodes, recs, boxes, n, vg, nullptr, nullptr, out_counts, s));
+    return RC_OK;
+}
+
+rc_status rc_gauss_debug_copy(rc_ctx *c, int32_t set, int32_t what, void *dst, uint64_t bytes)
+{
+    if (!c || !dst) return fail(RC_E_INVAL, "null argument");
+    if (c->mock) return fail(RC_E_STATE, "a mock context holds no device arrays");
+    HIP_TRY(hipSetDevice(c->device));
+    std::lock_guard<std::mutex> lk(c->mu);
+    GaussSet *g;
+    rc_status st = built_set(c, set, &g);
+    if (st != RC_OK) return st;
+    const int64_t n = g->n, ni = n > 1 ? n - 1 : 0;
+    const void *src = nullptr;
+    uint64_t size = 0;
+    switch (what) {
+    case RC_GDBG_BOXES: src = g->boxes; size = 24ull * n; break;
+    case RC_GDBG_SORTED: src = g->sorted; size = 4ull * n; break;
+    case RC_GDBG_TOPOLOGY: src = g->topo; size = 12ull * ni; break;
+    case RC_GDBG_RECORDS: src = g->recs; size = sizeof(GaussRec) * (uint64_t)n; break;
+    default: return fail(RC_E_INVAL, "unknown debug array %d", what);
+    }
+    if (bytes != size)
+        return fail(RC_E_INVAL, "array %d holds %llu bytes, %llu requested", what,
+                    (unsigned long long)size, (unsigned long long)bytes);
+    if (size == 0) return RC_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(dst, src, size, hipMemcpyDeviceToHost));
+    return RC_OK;
+}

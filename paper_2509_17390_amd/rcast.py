@@ -36,6 +36,11 @@ RC_DBG_NODES = 4
 RC_DBG_TRIS = 5
 RC_DBG_Q8NODES = 6
 
+RC_GDBG_BOXES = 1
+RC_GDBG_SORTED = 2
+RC_GDBG_TOPOLOGY = 3
+RC_GDBG_RECORDS = 4
+
 # every symbol include/rcast.h declares
 EXPORTED = [
     "rc_last_error", "rc_version", "rc_create", "rc_destroy", "rc_scene_upload",
@@ -44,7 +49,8 @@ EXPORTED = [
     "rc_scene_debug_copy", "rc_device_bytes", "rc_set_tuning", "rc_get_tuning",
     "rc_autotune", "rc_graph_create", "rc_graph_launch", "rc_graph_destroy",
     "rc_serve_start", "rc_serve_stop", "rc_serve_submit", "rc_serve_poll", "rc_serve_release",
-    "rc_serve_copy", "rc_serve_get_stats",
+    "rc_serve_copy", "rc_serve_get_stats", "rc_gauss_upload", "rc_gauss_build",
+    "rc_gauss_release", "rc_voxelize", "rc_voxelize_counts", "rc_gauss_debug_copy",
 ]
 
 RC_DEVICE_MOCK = -1
@@ -112,6 +118,17 @@ class rc_serve_stats(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class rc_gauss_opts(ctypes.Structure):
+    _fields_ = [("cutoff_sigma", ctypes.c_float), ("morton_bits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+class rc_grid(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_float * 3), ("spacing", ctypes.c_float),
+                ("dims", ctypes.c_int32 * 3), ("tile", ctypes.c_int32),
+                ("theta", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
+
+
 _lib = None
 
 
@@ -156,6 +173,12 @@ def load() -> ctypes.CDLL:
         "rc_serve_release": ([P, U64], S),
         "rc_serve_copy": ([P, U64, P, P, ctypes.c_int], S),
         "rc_serve_get_stats": ([P, ctypes.POINTER(rc_serve_stats)], S),
+        "rc_gauss_upload": ([P, P, P, P, P, I64, ctypes.c_int, P, ctypes.POINTER(I32)], S),
+        "rc_gauss_build": ([P, I32, ctypes.POINTER(rc_gauss_opts), P], S),
+        "rc_gauss_release": ([P, I32], S),
+        "rc_voxelize": ([P, I32, ctypes.POINTER(rc_grid), P, P, P, P], S),
+        "rc_voxelize_counts": ([P, I32, ctypes.POINTER(rc_grid), P, P], S),
+        "rc_gauss_debug_copy": ([P, I32, I32, P, U64], S),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -295,6 +318,75 @@ class Context:
 
     def reset_tuning(self):
         _check(load().rc_set_tuning(self._h, None))
+
+    # -- Gaussian-to-occupancy conversion -------------------------------------
+    def upload_gaussians(self, means, quats, scales, opacity, stream=None) -> int:
+        """means [n,3], quats [n,4] (w,x,y,z), scales [n,3], opacity [n], float32:
+        numpy (host) or torch cuda tensors."""
+        arrs = [means, quats, scales, opacity]
+        on_dev = not isinstance(means, np.ndarray)
+        if on_dev:
+            for a in arrs:
+                assert a.is_cuda and a.is_contiguous()
+            n = int(means.shape[0])
+            ptrs = [_ptr(a) for a in arrs]
+            sp = _stream_ptr(stream)
+        else:
+            widths = (3, 4, 3, 1)
+            arrs = [np.ascontiguousarray(a, np.float32).reshape(-1, w) for a, w in zip(arrs, widths)]
+            n = arrs[0].shape[0]
+            ptrs = [a.ctypes.data for a in arrs]
+            sp = 0
+        out = ctypes.c_int32()
+        _check(load().rc_gauss_upload(self._h, *ptrs, n, int(on_dev), sp, ctypes.byref(out)))
+        self._gauss_n = getattr(self, "_gauss_n", {})
+        self._gauss_n[out.value] = n
+        return out.value
+
+    def build_gaussians(self, gset: int, cutoff_sigma: float = 3.0, morton_bits: int = 10,
+                        stream=None):
+        o = rc_gauss_opts(float(cutoff_sigma), int(morton_bits))
+        _check(load().rc_gauss_build(self._h, gset, ctypes.byref(o), _stream_ptr(stream)))
+
+    def release_gaussians(self, gset: int):
+        _check(load().rc_gauss_release(self._h, gset))
+
+    @staticmethod
+    def grid(origin, spacing: float, dims, theta: float, tile: int = 8) -> rc_grid:
+        g = rc_grid()
+        for a in range(3):
+            g.origin[a] = float(origin[a])
+            g.dims[a] = int(dims[a])
+        g.spacing = float(spacing)
+        g.tile = int(tile)
+        g.theta = float(theta)
+        return g
+
+    def voxelize(self, gset: int, grid: rc_grid, out_density=None, out_occ=None, out_surf=None,
+                 stream=None):
+        """Device outputs (torch cuda tensors, [nz, ny, nx]): float32 density,
+        uint8 occupancy, uint8 surface mask; any may be None."""
+        p = [0 if t is None else _ptr(t) for t in (out_density, out_occ, out_surf)]
+        _check(load().rc_voxelize(self._h, gset, ctypes.byref(grid), *p, _stream_ptr(stream)))
+
+    def voxelize_counts(self, gset: int, grid: rc_grid, out_counts, stream=None):
+        _check(load().rc_voxelize_counts(self._h, gset, ctypes.byref(grid), _ptr(out_counts),
+                                         _stream_ptr(stream)))
+
+    def gauss_debug_copy(self, gset: int, what: int) -> np.ndarray:
+        n = self._gauss_n[gset]
+        if what == RC_GDBG_BOXES:
+            a = np.empty((n, 6), np.float32)
+        elif what == RC_GDBG_SORTED:
+            a = np.empty(n, np.uint32)
+        elif what == RC_GDBG_TOPOLOGY:
+            a = np.empty((max(n - 1, 0), 3), np.int32)
+        elif what == RC_GDBG_RECORDS:
+            a = np.empty((n, 16), np.float32)
+        else:
+            raise ValueError(what)
+        _check(load().rc_gauss_debug_copy(self._h, gset, what, a.ctypes.data, a.nbytes))
+        return a
 
     # -- patterns ------------------------------------------------------------
     def upload_pattern(self, dirs, n_az: int = 0) -> int:

@@ -477,3 +477,90 @@ def uneven_world(seed: int = 0, n_scenes: int = 64, n_envs: int = 1024,
     patterns = [lidar_pattern(ne, lo, hi, na) for ne, lo, hi, na in UNEVEN_PATTERNS]
     return UnevenWorld(scenes, env_scene, env_pattern, poses, patterns,
                        [p[3] for p in UNEVEN_PATTERNS])
+
+
+# --------------------------------------------------------------------------
+# Gaussian scenes (inputs of the Gaussian-to-occupancy conversion)
+#
+# Layout: means float32 [n, 3]; quats float32 [n, 4] as (w, x, y, z), not
+# necessarily unit length; scales float32 [n, 3] (linear, > 0); opacity
+# float32 [n] in [0, 1].  Trained 3DGS assets are not available, so seeded
+# Gaussians with their structure stand in: flat discs lying on surfaces,
+# plus a few low-opacity floaters in free space.
+
+def random_gaussians(rng: np.random.Generator, n: int, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                     s_lo: float = 0.02, s_hi: float = 0.2, a_lo: float = 0.05, a_hi: float = 1.0):
+    """n Gaussians: means uniform in [lo, hi], quaternions with normal
+    components (arbitrary length), scales log-uniform in [s_lo, s_hi],
+    opacity uniform in [a_lo, a_hi]."""
+    means = rng.uniform(lo, hi, (n, 3)).astype(np.float32)
+    quats = rng.normal(size=(n, 4)).astype(np.float32)
+    scales = np.exp(rng.uniform(math.log(s_lo), math.log(s_hi), (n, 3))).astype(np.float32)
+    opac = rng.uniform(a_lo, a_hi, n).astype(np.float32)
+    return means, quats, scales, opac
+
+
+def _quat_mul(a, b):
+    """Hamilton product of (w, x, y, z) quaternion arrays."""
+    aw, ax, ay, az = a[:, 0], a[:, 1], a[:, 2], a[:, 3]
+    bw, bx, by, bz = b[:, 0], b[:, 1], b[:, 2], b[:, 3]
+    return np.stack([aw * bw - ax * bx - ay * by - az * bz,
+                     aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx,
+                     aw * bz + ax * by - ay * bx + az * bw], axis=1)
+
+
+def splat_scene(seed: int = 1, n: int = 1_000_000, h_mesh: float = 0.035,
+                floaters: float = 0.03, tan_scale: float = 0.02):
+    """3DGS-like Gaussians on the indoor scene (room + 200 primitives,
+    marching cubes at ``h_mesh``): points sampled uniformly by area on the
+    surface, the disc normal (smallest scale) along the surface normal with a
+    random twist, tangential scales log-normal around ``tan_scale`` metres,
+    normal scale 20..60 % of the smaller tangential one; opacity mostly high.
+    A ``floaters`` fraction lies in free space: near-isotropic, 1..10 cm,
+    opacity 0.01..0.2.  Returns (means, quats, scales, opacity, room box)."""
+    sdf, v, t = indoor_mesh(seed, h_mesh)
+    rng = np.random.default_rng(1000 + seed)
+    n_float = int(round(n * floaters))
+    n_surf = n - n_float
+    a = v[t[:, 0]].astype(np.float64)
+    b = v[t[:, 1]].astype(np.float64)
+    c = v[t[:, 2]].astype(np.float64)
+    cr = np.cross(b - a, c - a)
+    area = 0.5 * np.linalg.norm(cr, axis=1)
+    ok = area > 0
+    cdf = np.cumsum(np.where(ok, area, 0.0))
+    pick = np.searchsorted(cdf, rng.uniform(0, cdf[-1], n_surf), side="right")
+    pick = np.minimum(pick, len(area) - 1)
+    r1 = np.sqrt(rng.uniform(size=n_surf))
+    r2 = rng.uniform(size=n_surf)
+    pts = ((1 - r1)[:, None] * a[pick] + (r1 * (1 - r2))[:, None] * b[pick]
+           + (r1 * r2)[:, None] * c[pick])
+    nrm = cr[pick] / np.linalg.norm(cr[pick], axis=1, keepdims=True)
+    # rotation taking +z to the normal, then a random twist about it
+    qa = np.stack([1 + nrm[:, 2], -nrm[:, 1], nrm[:, 0], np.zeros(n_surf)], axis=1)
+    flip = qa[:, 0] < 1e-9
+    qa[flip] = (0.0, 1.0, 0.0, 0.0)
+    qa /= np.linalg.norm(qa, axis=1, keepdims=True)
+    phi = rng.uniform(0, 2 * math.pi, n_surf)
+    qt = np.stack([np.cos(phi / 2), np.zeros(n_surf), np.zeros(n_surf), np.sin(phi / 2)], axis=1)
+    q_surf = _quat_mul(qa, qt)
+    st = np.exp(rng.normal(math.log(tan_scale), 0.4, (n_surf, 2)))
+    sn = np.minimum(st[:, 0], st[:, 1]) * rng.uniform(0.2, 0.6, n_surf)
+    s_surf = np.stack([st[:, 0], st[:, 1], sn], axis=1)
+    hi_op = rng.uniform(size=n_surf) < 0.7
+    a_surf = np.where(hi_op, rng.uniform(0.6, 1.0, n_surf), rng.uniform(0.05, 0.6, n_surf))
+    lo, hi = np.asarray(sdf.room[:3]), np.asarray(sdf.room[3:])
+    m_fl = rng.uniform(lo, hi, (n_float, 3))
+    q_fl = rng.normal(size=(n_float, 4))
+    base = np.exp(rng.uniform(math.log(0.01), math.log(0.1), n_float))
+    s_fl = base[:, None] * rng.uniform(0.7, 1.3, (n_float, 3))
+    a_fl = rng.uniform(0.01, 0.2, n_float)
+    means = np.concatenate([pts, m_fl]).astype(np.float32)
+    quats = np.concatenate([q_surf, q_fl]).astype(np.float32)
+    scales = np.concatenate([s_surf, s_fl]).astype(np.float32)
+    opac = np.concatenate([a_surf, a_fl]).astype(np.float32)
+    perm = rng.permutation(n)
+    return (np.ascontiguousarray(means[perm]), np.ascontiguousarray(quats[perm]),
+            np.ascontiguousarray(scales[perm]), np.ascontiguousarray(opac[perm]),
+            np.asarray(sdf.room, dtype=np.float64))

@@ -34,6 +34,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(rcast.rc_build_opts) == 32
     assert rcast.rc_scene_info.scene_lo.offset == 56
     assert ctypes.sizeof(rcast.rc_tuning) == 36
+    assert ctypes.sizeof(rcast.rc_gauss_opts) == 32
+    assert ctypes.sizeof(rcast.rc_grid) == 48
 
 
 def test_error_path_without_device_is_clean():
