@@ -47,13 +47,13 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    """Hash of the traversal kernel's code (trace.hip and rc_internal.h with
-    comments and whitespace removed), so profiled counters stay attached to
-    the code they were measured on, not to its comments."""
+def kernel_source_hash(files=("trace.hip", "rc_internal.h")) -> str:
+    """Hash of a kernel's code (by default the traversal: trace.hip and
+    rc_internal.h) with comments and whitespace removed, so profiled counters
+    stay attached to the code they were measured on, not to its comments."""
     import re
     h = hashlib.sha256()
-    for f in ("trace.hip", "rc_internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2509_17390_amd", "csrc", f)) as fh:
             src = fh.read()
         src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
@@ -765,6 +765,20 @@ def run_voxelize(args):
     tile_vox = vz[:, None, None] * vy[None, :, None] * vx[None, None, :]
     pairs = int((counts * tile_vox).sum())
     tflops = pairs * PAIR_FLOPS / (dens_ms * 1e-3) / 1e12
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    khash = kernel_source_hash(("gauss.hip", "gauss_internal.h", "rc_internal.h"))
+    counters = None
+    cp = os.path.join(ROOT, "profiles", "voxelize_counters.json")
+    if os.path.exists(cp):
+        with open(cp) as fh:
+            c = json.load(fh)
+        if c.get("kernel_hash") == khash and c.get("gaussians") == n and c.get("voxels") == n_vox:
+            counters = c
     occ_n = int(O.sum().item())
     surf_n = int(S.sum().item())
     cpu = None
@@ -790,8 +804,23 @@ def run_voxelize(args):
                     "brute_force_pairs": int(n) * n_vox},
         "roofline": {"bound": "alu", "achieved": round(tflops, 2),
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-                     "kernel": "k_voxelize<0>", "flops_per_pair": PAIR_FLOPS},
+                     "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": None if counters is None else counters["bytes_per_launch"],
+                     "kernel": "k_voxelize<0>", "flops_per_pair": PAIR_FLOPS,
+                     "kernel_hash": khash,
+                     "counters": None if counters is None else {
+                         k: counters[k] for k in ("hbm_GBs", "valu_util_pct",
+                                                  "valu_active_threads", "valu_insts_per_wave",
+                                                  "read_bytes", "write_bytes")}},
+        # instruction issue of the same kernel (one wave64 VALU instruction per
+        # SIMD every 4 cycles, 1024 SIMDs at 2.4 GHz)
+        "roofline_valu": None if counters is None else {
+            "bound": "alu", "unit": "G wave-instructions/s",
+            "achieved": round(counters["valu_insts_per_wave"] * counters["waves"]
+                              / (dens_ms * 1e-3) / 1e9, 1),
+            "peak": VALU_PEAK_GWI,
+            "frac": round(counters["valu_insts_per_wave"] * counters["waves"]
+                          / (dens_ms * 1e-3) / 1e9 / VALU_PEAK_GWI, 4)},
         "occupied": occ_n, "surface": surf_n,
         "cpu_baseline": cpu,
     }

@@ -1,4 +1,5 @@
-// build.hip -- GPU linear BVH over triangle boxes (gfx950).
+// build.hip -- GPU linear BVH over primitive boxes (gfx950): triangle boxes
+// for ray casting, or ready-made Gaussian boxes.
 //
 // FGGS-LiDAR Sec. IV-A "LBVH construction" (reused for triangles in
 // Sec. IV-C): every primitive centre is quantised inside the scene box,
@@ -9,7 +10,8 @@
 // bit of the 3b + 32 bit augmented key), and node boxes are reduced bottom-up.
 //
 // Stages, one kernel each (radix sort: three per 8-bit digit):
-//   tri_bounds   triangle boxes + scene box (wave reduction, then atomics)
+//   tri_bounds   triangle boxes + per-block partial scene boxes, folded by
+//                one more block (or: union of ready-made primitive boxes)
 //   morton       centre of the triangle box -> 3b-bit code
 //   radix sort   per-tile digit histogram / per-digit scan of tile counts /
 //                stable scatter ranked in LDS with wave64 ballots
@@ -18,11 +20,12 @@
 //                merges both child boxes into the parent's record (LDS
 //                counters inside a block's leaf chunk, agent-scope counters
 //                across chunks); node heights give the tree depth
-//   tri_records  triangles reordered into leaf order (48-byte records)
+//   tri_records  triangles reordered into leaf order (48-byte records; not
+//                for ready-made boxes)
 //   collapse     optional: 4-wide nodes with 8-bit child boxes in each node's
 //                frame (node depths, prefix count of even-depth nodes, then
 //                one thread per 4-wide node)
-#include "rc_internal.h"
+#include "gauss_internal.h"
 
 #include <math.h>
 
@@ -33,16 +36,6 @@ constexpr int kItems = 8;
 constexpr int kTile = kBlock * kItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
-
-__device__ __forceinline__ uint32_t f2o(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float o2f(uint32_t u)
-{
-    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
-}
 
 __device__ __forceinline__ float wave_min(float v)
 {
@@ -61,20 +54,36 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
     if (i < n) p[i] = v;
 }
 
-__global__ void k_init_box(uint32_t *box)
+constexpr int kBoundBlocks = 512;   // blocks of the box reductions
+
+// Block-wide min/max of acc[0..2] / acc[3..5]; thread 0 writes out[6].
+__device__ __forceinline__ void block_box(float acc[6], float *out)
 {
-    if (threadIdx.x < 3) box[threadIdx.x] = f2o(INFINITY);
-    else if (threadIdx.x < 6) box[threadIdx.x] = f2o(-INFINITY);
+    __shared__ float red[kBlock / 64][6];
+    for (int a = 0; a < 3; ++a) {
+        acc[a] = wave_min(acc[a]);
+        acc[3 + a] = wave_max(acc[3 + a]);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 6; ++a) red[w][a] = acc[a];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int a = threadIdx.x;
+        float v = red[0][a];
+        for (int ww = 1; ww < kBlock / 64; ++ww) v = a < 3 ? fminf(v, red[ww][a]) : fmaxf(v, red[ww][a]);
+        out[a] = v;
+    }
 }
 
-// triangle boxes (AoS lo.xyz hi.xyz) and their union: grid-stride loop,
-// wave then block reduction, one set of atomics per block
+// Triangle boxes (AoS lo.xyz hi.xyz) and one partial scene box per block
+// (grid-stride loop; the partials are folded by k_bounds_final, so no
+// atomics: min/max are exact in any order).
 __global__ __launch_bounds__(kBlock) void k_tri_bounds(const float *__restrict__ verts,
                                                        const int32_t *__restrict__ tris,
                                                        int64_t nt, float *__restrict__ bounds,
-                                                       uint32_t *__restrict__ box)
+                                                       float *__restrict__ partial)
 {
-    __shared__ float red[kBlock / 64][6];
     float acc[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nt;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -95,27 +104,13 @@ __global__ __launch_bounds__(kBlock) void k_tri_bounds(const float *__restrict__
             acc[3 + a] = fmaxf(acc[3 + a], hi[a]);
         }
     }
-    for (int a = 0; a < 3; ++a) {
-        acc[a] = wave_min(acc[a]);
-        acc[3 + a] = wave_max(acc[3 + a]);
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0)
-        for (int a = 0; a < 6; ++a) red[w][a] = acc[a];
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        const int a = threadIdx.x;
-        float v = red[0][a];
-        for (int ww = 1; ww < kBlock / 64; ++ww) v = a < 3 ? fminf(v, red[ww][a]) : fmaxf(v, red[ww][a]);
-        if (a < 3) atomicMin(box + a, f2o(v)); else atomicMax(box + a, f2o(v));
-    }
+    block_box(acc, partial + 6 * blockIdx.x);
 }
 
-// union of ready-made primitive boxes (same reduction as k_tri_bounds)
+// Partial unions of ready-made primitive boxes.
 __global__ __launch_bounds__(kBlock) void k_box_union(const float *__restrict__ bounds, int64_t n,
-                                                      uint32_t *__restrict__ box)
+                                                      float *__restrict__ partial)
 {
-    __shared__ float red[kBlock / 64][6];
     float acc[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -125,25 +120,20 @@ __global__ __launch_bounds__(kBlock) void k_box_union(const float *__restrict__ 
             acc[3 + a] = fmaxf(acc[3 + a], b[3 + a]);
         }
     }
-    for (int a = 0; a < 3; ++a) {
-        acc[a] = wave_min(acc[a]);
-        acc[3 + a] = wave_max(acc[3 + a]);
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0)
-        for (int a = 0; a < 6; ++a) red[w][a] = acc[a];
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        const int a = threadIdx.x;
-        float v = red[0][a];
-        for (int ww = 1; ww < kBlock / 64; ++ww) v = a < 3 ? fminf(v, red[ww][a]) : fmaxf(v, red[ww][a]);
-        if (a < 3) atomicMin(box + a, f2o(v)); else atomicMax(box + a, f2o(v));
-    }
+    block_box(acc, partial + 6 * blockIdx.x);
 }
 
-__global__ void k_box_to_float(const uint32_t *box, float *out)
+// One block: the scene box from the per-block partials.
+__global__ __launch_bounds__(kBlock) void k_bounds_final(const float *__restrict__ partial,
+                                                         int nparts, float *__restrict__ box)
 {
-    if (threadIdx.x < 6) out[threadIdx.x] = o2f(box[threadIdx.x]);
+    float acc[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int p = threadIdx.x; p < nparts; p += kBlock)
+        for (int a = 0; a < 3; ++a) {
+            acc[a] = fminf(acc[a], partial[6 * p + a]);
+            acc[3 + a] = fmaxf(acc[3 + a], partial[6 * p + 3 + a]);
+        }
+    block_box(acc, box);
 }
 
 __device__ __forceinline__ uint32_t expand_bits(uint32_t v)
@@ -660,7 +650,7 @@ size_t lbvh_workspace_bytes(int64_t nt)
     s += align_up(sizeof(int32_t) * (size_t)nt);          // node depths
     s += align_up(sizeof(uint32_t) * (size_t)nt);         // 4-wide node index
     s += align_up(sizeof(uint32_t) * ((size_t)nt / kBlock + 2));  // scan block sums
-    s += align_up(sizeof(uint32_t) * 8);                  // scene box (ordered)
+    s += align_up(sizeof(float) * 6 * kBoundBlocks);      // partial scene boxes
     s += align_up(sizeof(int32_t) * (size_t)nt);          // spanning nodes left to refit
     s += align_up(sizeof(uint32_t) * 1);                  // their count
     return s;
@@ -676,7 +666,9 @@ hipError_t validate_mesh_launch(const float *verts, int64_t nv, const int32_t *t
     return hipGetLastError();
 }
 
-hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
+namespace {
+
+hipError_t lbvh_build_any(const BuildBuffers &b, const float *prim_boxes, hipStream_t s)
 {
     const int64_t n = b.nt;
     if (n <= 0) return hipSuccess;
@@ -701,21 +693,22 @@ hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
     int32_t *ndepth = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * n));
     uint32_t *qidx = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * n));
     uint32_t *bsum = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * (n / kBlock + 2)));
-    uint32_t *obox = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * 8));
+    float *partial = reinterpret_cast<float *>(take(sizeof(float) * 6 * kBoundBlocks));
     int32_t *pend = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * n));
     uint32_t *pend_count = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t)));
     if ((size_t)(w - static_cast<char *>(b.ws)) > b.ws_bytes) return hipErrorInvalidValue;
 
-    hipLaunchKernelGGL(k_init_box, dim3(1), dim3(64), 0, s, obox);
-    const unsigned bgrid = grid_for(n, kBlock) < 2048u ? grid_for(n, kBlock) : 2048u;
-    if (b.prim_boxes) {
-        bounds = const_cast<float *>(b.prim_boxes);
-        hipLaunchKernelGGL(k_box_union, dim3(bgrid), dim3(kBlock), 0, s, b.prim_boxes, n, obox);
+    const unsigned bgrid = grid_for(n, kBlock) < (unsigned)kBoundBlocks ? grid_for(n, kBlock)
+                                                                         : (unsigned)kBoundBlocks;
+    if (prim_boxes) {
+        bounds = const_cast<float *>(prim_boxes);
+        hipLaunchKernelGGL(k_box_union, dim3(bgrid), dim3(kBlock), 0, s, prim_boxes, n, partial);
     } else {
         hipLaunchKernelGGL(k_tri_bounds, dim3(bgrid), dim3(kBlock), 0, s, b.verts, b.tris, n,
-                           bounds, obox);
+                           bounds, partial);
     }
-    hipLaunchKernelGGL(k_box_to_float, dim3(1), dim3(64), 0, s, obox, b.scene_box);
+    hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(kBlock), 0, s, partial, (int)bgrid,
+                       b.scene_box);
     hipLaunchKernelGGL(k_morton, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, bounds,
                        b.scene_box, n, b.morton_bits, b.morton, keys0, vals0);
     const int key_bits = 3 * b.morton_bits;
@@ -759,4 +752,17 @@ hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
                            b.q8nodes);
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t lbvh_build_launch(const BuildBuffers &b, hipStream_t s)
+{
+    return lbvh_build_any(b, nullptr, s);
+}
+
+hipError_t lbvh_build_boxes_launch(const BuildBuffers &b, const float *boxes, hipStream_t s)
+{
+    if (b.trirecs) return hipErrorInvalidValue;
+    return lbvh_build_any(b, boxes, s);
 }

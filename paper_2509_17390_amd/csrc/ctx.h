@@ -4,6 +4,7 @@
 
 #include "rcast.h"
 #include "rc_internal.h"
+#include "gauss_internal.h"
 
 #include <mutex>
 #include <string>
@@ -51,7 +52,7 @@ struct Pattern {
 struct GaussSet {
     bool alive = false;
     int64_t n = 0;
-    float *params = nullptr;     // mean [n][3], quat [n][4], scale [n][3], opacity [n]
+    float4 *params = nullptr;    // [n][3]: (mu, alpha) (quaternion) (scale, 0)
     float *boxes = nullptr;      // [n][6] Gaussian boxes (input order)
     bool has_bvh = false;
     float cutoff = 3.0f;         // k of the k-sigma boxes
@@ -67,10 +68,7 @@ struct GaussSet {
     GaussParams view() const
     {
         GaussParams p;
-        p.mean = params;
-        p.quat = params + 3 * n;
-        p.scale = params + 7 * n;
-        p.opacity = params + 10 * n;
+        p.g = params;
         p.n = n;
         return p;
     }

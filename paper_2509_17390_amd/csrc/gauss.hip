@@ -10,6 +10,7 @@
 //   V_occ   D > theta;  Surf = V_occ and not (all six face neighbours occupied)
 //
 // Kernels:
+//   k_gauss_pack      the uploaded arrays interleaved, 48 bytes per Gaussian
 //   k_gauss_validate  input checks at upload
 //   k_gauss_boxes     b_i: FP64 in one fixed operation order (the library is
 //                     built without contraction), each end rounded to the
@@ -30,7 +31,7 @@
 // returns culling-set members: it is deterministic and needs no sorting.
 // A term with w alpha^2 2^31 < 1/4 rounds to zero, so voxels where the
 // exponent exceeds 33 skip the exponential exactly.
-#include "rc_internal.h"
+#include "gauss_internal.h"
 
 #include <math.h>
 
@@ -46,9 +47,9 @@ constexpr double kFix = 2147483648.0;        // 2^31: fixed-point unit of one te
 
 // R of q / |q| for q = (w, x, y, z); every step one FP64 operation, in the
 // order the Gaussian boxes are defined with.
-__device__ __forceinline__ void rotation64(const float *q4, double R[3][3])
+__device__ __forceinline__ void rotation64(const float4 q4, double R[3][3])
 {
-    const double w = q4[0], x = q4[1], y = q4[2], z = q4[3];
+    const double w = q4.x, x = q4.y, y = q4.z, z = q4.w;
     const double n = ((w * w + x * x) + y * y) + z * z;
     const double s = 2.0 / n;
     R[0][0] = 1.0 - s * (y * y + z * z);
@@ -62,26 +63,28 @@ __device__ __forceinline__ void rotation64(const float *q4, double R[3][3])
     R[2][2] = 1.0 - s * (x * x + y * y);
 }
 
+__global__ __launch_bounds__(kBlock) void k_gauss_pack(GaussArrays a, float4 *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    out[3 * i + 0] = make_float4(a.mean[3 * i], a.mean[3 * i + 1], a.mean[3 * i + 2], a.opacity[i]);
+    out[3 * i + 1] = make_float4(a.quat[4 * i], a.quat[4 * i + 1], a.quat[4 * i + 2], a.quat[4 * i + 3]);
+    out[3 * i + 2] = make_float4(a.scale[3 * i], a.scale[3 * i + 1], a.scale[3 * i + 2], 0.0f);
+}
+
 __global__ __launch_bounds__(kBlock) void k_gauss_validate(GaussParams p, int32_t *flags)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.n) return;
+    const float4 m = p.g[3 * i], q = p.g[3 * i + 1], s = p.g[3 * i + 2];
     int f = 0;
-    double qn = 0.0;
-    for (int a = 0; a < 4; ++a) {
-        const float v = p.quat[4 * i + a];
-        if (!isfinite(v)) f |= 1;
-        qn += (double)v * v;
-    }
+    const float v[11] = {m.x, m.y, m.z, m.w, q.x, q.y, q.z, q.w, s.x, s.y, s.z};
+    for (int k = 0; k < 11; ++k)
+        if (!isfinite(v[k])) f |= 1;
+    const double qn = (double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z + (double)q.w * q.w;
     if (!(qn > 0.0)) f |= 4;
-    for (int a = 0; a < 3; ++a) {
-        const float m = p.mean[3 * i + a], s = p.scale[3 * i + a];
-        if (!isfinite(m) || !isfinite(s)) f |= 1;
-        if (!(s > 0.0f)) f |= 2;
-    }
-    const float al = p.opacity[i];
-    if (!isfinite(al)) f |= 1;
-    else if (al < 0.0f || al > 1.0f) f |= 8;
+    if (!(s.x > 0.0f) || !(s.y > 0.0f) || !(s.z > 0.0f)) f |= 2;
+    if (isfinite(m.w) && (m.w < 0.0f || m.w > 1.0f)) f |= 8;
     if (f) atomicOr(flags, f);
 }
 
@@ -90,16 +93,17 @@ __global__ __launch_bounds__(kBlock) void k_gauss_boxes(GaussParams p, double k,
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.n) return;
+    const float4 m = p.g[3 * i], sc = p.g[3 * i + 2];
     double R[3][3];
-    rotation64(p.quat + 4 * i, R);
-    const double s0 = p.scale[3 * i + 0], s1 = p.scale[3 * i + 1], s2 = p.scale[3 * i + 2];
+    rotation64(p.g[3 * i + 1], R);
+    const double s0 = sc.x, s1 = sc.y, s2 = sc.z;
+    const double mu[3] = {m.x, m.y, m.z};
     for (int a = 0; a < 3; ++a) {
         const double c0 = R[a][0] * s0, c1 = R[a][1] * s1, c2 = R[a][2] * s2;
         const double saa = (c0 * c0 + c1 * c1) + c2 * c2;
         const double e = k * sqrt(saa);
-        const double m = p.mean[3 * i + a];
-        boxes[6 * i + a] = (float)(m - e);
-        boxes[6 * i + 3 + a] = (float)(m + e);
+        boxes[6 * i + a] = (float)(mu[a] - e);
+        boxes[6 * i + 3 + a] = (float)(mu[a] + e);
     }
 }
 
@@ -110,17 +114,16 @@ __global__ __launch_bounds__(kBlock) void k_gauss_records(GaussParams p,
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= p.n) return;
     const int64_t i = sorted[k];
+    const float4 m = p.g[3 * i], sc = p.g[3 * i + 2];
     double R[3][3];
-    rotation64(p.quat + 4 * i, R);
+    rotation64(p.g[3 * i + 1], R);
+    const double inv[3] = {kC0 / (double)sc.x, kC0 / (double)sc.y, kC0 / (double)sc.z};
     float M[9];
-    for (int r = 0; r < 3; ++r) {
-        const double inv = kC0 / (double)p.scale[3 * i + r];
-        for (int j = 0; j < 3; ++j) M[3 * r + j] = (float)(R[j][r] * inv);   // (S^-1 R^T)_rj
-    }
-    const double al = p.opacity[i];
+    for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 3; ++j) M[3 * r + j] = (float)(R[j][r] * inv[r]);   // (S^-1 R^T)_rj
+    const double al = m.w;
     GaussRec g;
-    g.r0 = make_float4(p.mean[3 * i], p.mean[3 * i + 1], p.mean[3 * i + 2],
-                       (float)(al * al * kFix));
+    g.r0 = make_float4(m.x, m.y, m.z, (float)(al * al * kFix));
     g.r1 = make_float4(M[0], M[1], M[2], M[3]);
     g.r2 = make_float4(M[4], M[5], M[6], M[7]);
     g.r3 = make_float4(M[8], __int_as_float((int32_t)i), 0.0f, 0.0f);
@@ -322,30 +325,53 @@ __global__ __launch_bounds__(64) void k_voxelize(const NodeRec *__restrict__ nod
     }
 }
 
-// One thread per voxel of a row; rows are (z, y) pairs.
+__device__ __forceinline__ uint32_t udiv32(uint32_t n, UDiv d)
+{
+    const uint32_t t = __umulhi(n, d.m);
+    return (t + ((n - t) >> (d.sh & 0xffu))) >> (d.sh >> 8);
+}
+
+// Four consecutive voxels of a row per thread; rows are (z, y) pairs.
 __global__ __launch_bounds__(kBlock) void k_surface(const uint8_t *__restrict__ occ,
                                                     uint8_t *__restrict__ surf, int nx, int ny,
-                                                    int nz, int xblocks)
+                                                    int nz, uint32_t n_threads, int quads,
+                                                    UDiv div_quads, UDiv div_ny)
 {
-    const int64_t row = (int64_t)blockIdx.x / xblocks;
-    const int x = (int)(blockIdx.x % xblocks) * kBlock + threadIdx.x;
-    if (x >= nx) return;
-    const int y = (int)(row % ny), z = (int)(row / ny);
+    const uint32_t t = blockIdx.x * (uint32_t)kBlock + threadIdx.x;
+    if (t >= n_threads) return;
+    const uint32_t row = udiv32(t, div_quads);
+    const int x0 = 4 * (int)(t - row * (uint32_t)quads);
+    const uint32_t zz = udiv32(row, div_ny);
+    const int y = (int)(row - zz * (uint32_t)ny), z = (int)zz;
     const int64_t sxy = (int64_t)nx * ny;
-    const int64_t i = row * nx + x;
-    uint8_t s = 0;
-    if (occ[i]) {
-        const bool interior = x > 0 && x < nx - 1 && y > 0 && y < ny - 1 && z > 0 &&
-                              z < nz - 1 && occ[i - 1] && occ[i + 1] && occ[i - nx] &&
-                              occ[i + nx] && occ[i - sxy] && occ[i + sxy];
-        s = interior ? 0 : 1;
+    const int64_t base = (int64_t)row * nx;
+    const bool ym = y > 0, yp = y < ny - 1, zm = z > 0, zp = z < nz - 1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int x = x0 + k;
+        if (x >= nx) break;
+        const int64_t i = base + x;
+        uint8_t s = 0;
+        if (occ[i]) {
+            const bool interior = x > 0 && x < nx - 1 && ym && yp && zm && zp && occ[i - 1] &&
+                                  occ[i + 1] && occ[i - nx] && occ[i + nx] && occ[i - sxy] &&
+                                  occ[i + sxy];
+            s = interior ? 0 : 1;
+        }
+        surf[i] = s;
     }
-    surf[i] = s;
 }
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 }  // namespace
+
+hipError_t gauss_pack_launch(const GaussArrays &a, float4 *out, hipStream_t s)
+{
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gauss_pack, dim3(grid_for(a.n, kBlock)), dim3(kBlock), 0, s, a, out);
+    return hipGetLastError();
+}
 
 hipError_t gauss_validate_launch(const GaussParams &p, int32_t *flags, hipStream_t s)
 {
@@ -390,11 +416,13 @@ hipError_t voxelize_launch(int mode, const NodeRec *nodes, const GaussRec *recs,
 
 hipError_t surface_launch(const uint8_t *occ, uint8_t *surf, const VoxGrid &g, hipStream_t s)
 {
-    const int xblocks = (int)grid_for(g.nx, kBlock);
-    const int64_t blocks = (int64_t)xblocks * g.ny * g.nz;
-    if (blocks <= 0) return hipSuccess;
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_surface, dim3((unsigned)blocks), dim3(kBlock), 0, s, occ, surf, g.nx,
-                       g.ny, g.nz, xblocks);
+    const int quads = (g.nx + 3) / 4;
+    const int64_t rows = (int64_t)g.ny * g.nz;
+    const int64_t threads = (int64_t)quads * rows;
+    if (threads <= 0) return hipSuccess;
+    if (threads > 0xffffff00LL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_surface, dim3(grid_for(threads, kBlock)), dim3(kBlock), 0, s, occ, surf,
+                       g.nx, g.ny, g.nz, (uint32_t)threads, quads, udiv_magic((uint32_t)quads),
+                       udiv_magic((uint32_t)g.ny));
     return hipGetLastError();
 }

@@ -13,7 +13,7 @@ namespace rc {
 void free_gauss_set(rc_ctx *c, GaussSet &g)
 {
     const int64_t n = g.n, ni = n > 1 ? n - 1 : 1;
-    dev_free(c, g.params, sizeof(float) * 11 * n);
+    dev_free(c, g.params, sizeof(float4) * 3 * n);
     dev_free(c, g.boxes, sizeof(float) * 6 * n);
     dev_free(c, g.morton, sizeof(uint32_t) * n);
     dev_free(c, g.sorted, sizeof(uint32_t) * n);
@@ -93,25 +93,44 @@ rc_status rc_gauss_upload(rc_ctx *c, const float *means, const float *quats, con
     std::lock_guard<std::mutex> lk(c->mu);
     GaussSet g;
     g.n = n;
-    rc_status st = dev_alloc(c, (void **)&g.params, sizeof(float) * 11 * n);
+    rc_status st = dev_alloc(c, (void **)&g.params, sizeof(float4) * 3 * n);
     if (st == RC_OK) st = dev_alloc(c, (void **)&g.box_dev, sizeof(float) * 8);
+    // host arrays are staged on the device first (11 floats per Gaussian)
+    float *stage = nullptr;
+    if (st == RC_OK && !src_is_device && n > 0) st = dev_alloc(c, (void **)&stage, sizeof(float) * 11 * n);
     if (st != RC_OK) {
         free_gauss_set(c, g);
         return st;
     }
-    const GaussParams p = g.view();
-    const hipMemcpyKind kind = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    GaussArrays arr;
+    arr.n = n;
     hipError_t e = hipSuccess;
-    if (n) e = hipMemcpyAsync((void *)p.mean, means, sizeof(float) * 3 * n, kind, s);
-    if (e == hipSuccess && n) e = hipMemcpyAsync((void *)p.quat, quats, sizeof(float) * 4 * n, kind, s);
-    if (e == hipSuccess && n) e = hipMemcpyAsync((void *)p.scale, scales, sizeof(float) * 3 * n, kind, s);
-    if (e == hipSuccess && n) e = hipMemcpyAsync((void *)p.opacity, opacity, sizeof(float) * n, kind, s);
+    if (src_is_device) {
+        arr.mean = means;
+        arr.quat = quats;
+        arr.scale = scales;
+        arr.opacity = opacity;
+    } else {
+        arr.mean = stage;
+        arr.quat = stage + 3 * n;
+        arr.scale = stage + 7 * n;
+        arr.opacity = stage + 10 * n;
+        const hipMemcpyKind kind = hipMemcpyHostToDevice;
+        if (n) e = hipMemcpyAsync((void *)arr.mean, means, sizeof(float) * 3 * n, kind, s);
+        if (e == hipSuccess && n) e = hipMemcpyAsync((void *)arr.quat, quats, sizeof(float) * 4 * n, kind, s);
+        if (e == hipSuccess && n) e = hipMemcpyAsync((void *)arr.scale, scales, sizeof(float) * 3 * n, kind, s);
+        if (e == hipSuccess && n) e = hipMemcpyAsync((void *)arr.opacity, opacity, sizeof(float) * n, kind, s);
+    }
+    const GaussParams p = g.view();
+    if (e == hipSuccess) e = gauss_pack_launch(arr, g.params, s);
     if (e == hipSuccess) e = hipMemsetAsync(c->flags_dev, 0, sizeof(int32_t), s);
     if (e == hipSuccess) e = gauss_validate_launch(p, c->flags_dev, s);
     int32_t flags = 0;
     if (e == hipSuccess)
         e = hipMemcpyAsync(&flags, c->flags_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) (void)hipDeviceSynchronize();   // nothing may still use the buffers
+    if (stage) dev_free(c, stage, sizeof(float) * 11 * n);
     if (e != hipSuccess) {
         free_gauss_set(c, g);
         return fail(RC_E_DEVICE, "Gaussian upload failed: %s", hipGetErrorString(e));
@@ -123,7 +142,7 @@ rc_status rc_gauss_upload(rc_ctx *c, const float *means, const float *quats, con
                     (flags & 8) ? " opacity outside [0, 1]" : "");
     }
     g.alive = true;
-    g.bytes = sizeof(float) * 11 * n;
+    g.bytes = sizeof(float4) * 3 * n;
     int32_t id = -1;
     for (size_t i = 0; i < c->gsets.size(); ++i)
         if (!c->gsets[i].alive) { id = (int32_t)i; break; }
@@ -187,7 +206,6 @@ rc_status rc_gauss_build(rc_ctx *c, int32_t set, const rc_gauss_opts *opts, void
         BuildBuffers b;
         b.verts = nullptr;
         b.tris = nullptr;
-        b.prim_boxes = g->boxes;
         b.nv = 0;
         b.nt = n;
         b.morton_bits = bits;
@@ -202,7 +220,7 @@ rc_status rc_gauss_build(rc_ctx *c, int32_t set, const rc_gauss_opts *opts, void
         b.depth_out = reinterpret_cast<int32_t *>(g->box_dev + 6);
         b.q8nodes = nullptr;
         b.q8_count = nullptr;
-        HIP_TRY(lbvh_build_launch(b, s));
+        HIP_TRY(lbvh_build_boxes_launch(b, g->boxes, s));
         HIP_TRY(gauss_records_launch(p, g->sorted, g->recs, s));
         HIP_TRY(hipEventRecord(c->ws_event, s));
         c->ws_event_recorded = true;

@@ -15,7 +15,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2509_17390_amd", "csrc")
-SOURCES = ["api.hip", "build.hip", "trace.hip", "serve.hip"]
+from paper_2509_17390_amd.build import SOURCES  # every source of the library
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 pytestmark = pytest.mark.timeout(600)
