@@ -1,0 +1,296 @@
+"""CPU oracle for the narrow-band TSDF and marching cubes -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  The product library never does, and the two share no
+code (the marching-cubes table is generated here by its own implementation
+of the construction described below).
+
+What it computes is FGGS-LiDAR Sec. IV-B ("Binary denoising and
+re-thresholding", "Narrow-band TSDF", "Isosurface extraction") on the
+surface mask V of Sec. IV-A, written out directly with numpy and scipy:
+
+  V'      = G * V                       (smoothing eq.)
+  V~      = [V' >= tau]                 (fixed re-threshold eq.)
+  O       = the 6-connected component of free voxels (V~ = 0) joined to a
+            padded frame around the grid;  s = +1 on O, -1 elsewhere
+  S_0     = { x : some 6-neighbour y has V~(y) != V~(x) }   (boundary set)
+  p(x)    = the first shell S_m of a 6-neighbour expansion from S_0 that
+            reaches x;  delta = p h                            (distance eq.)
+  phi     = clip(s delta, -r, r)                                (TSDF eq.)
+  mesh    = marching cubes of phi at iso on the lattice of voxel centres
+
+Readings taken where the paper is silent (each is also listed in the design
+notes):
+
+  T1  The Gaussian kernel of scale sigma (metres; sigma_v = sigma / h voxels)
+      is the binomial kernel with n = max(1, round(2 sigma_v^2)) steps,
+      weights C(2n, n + k) for k = -n..n (variance n / 2, the discrete
+      Gaussian of integer weights), separable on the three axes, zero outside
+      the grid; V' = sum / 2^(6n).  All sums are exact integers, and V~ is
+      decided exactly: sum >= ceil(tau 2^(6n)).  n <= 10.
+  T2  Fixed threshold only (the quantile variant is not built).
+  T3  The padded frame is free, so a free voxel on the grid boundary is
+      outside; in S_0 a neighbour outside the grid counts as free (0).
+  T4  Shells are counted up to P = ceil(r / h); a voxel not reached by then
+      gets |phi| = r.  delta = p h is a float32 product, then clipped.
+  T5  Marching cubes: lattice points are voxel centres, cells are 2 x 2 x 2
+      groups of them; a corner is inside when phi < iso.  A crossed edge
+      (one corner inside) carries one vertex, at t = (iso - phi_a) /
+      (phi_b - phi_a) from its lower corner a (float32, in this operation
+      order: x = c_a + t h with c_a the float32 centre).  Vertices are
+      numbered by (lattice point, axis +x/+y/+z); triangles by (cell,
+      position in the case).  The case table: on each cube face, walk its
+      corners counter-clockwise about the outward normal; each crossing from
+      outside to inside starts a segment that ends at the next crossing from
+      inside to outside (so diagonal inside corners on a face are kept apart);
+      chaining the segments of the six faces gives closed loops; each loop
+      starts at its lowest-numbered edge (edges numbered by (axis, lower
+      corner)) and loops are taken in that order.  Each loop is cut into a
+      fan (a, v_i, v_i+1) from its first vertex a (in loop order) whose
+      diagonals all cross the cube's interior, i.e. join edges that share no
+      face (a diagonal lying on a face could overlap the neighbouring cell's
+      triangles; every loop of the 256 cases has such a vertex).  Triangles
+      face the outside region (phi >= iso).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy import ndimage
+
+# cube corners: bit k of the case index is corner k; corner k = (k & 1, k >> 1 & 1, k >> 2 & 1)
+CORNERS = [(k & 1, (k >> 1) & 1, (k >> 2) & 1) for k in range(8)]
+# cube edges: (corner a, corner b) with b = a + unit vector along `axis`; ordered by (axis, a)
+EDGES = []
+for axis in range(3):
+    for a in range(8):
+        if not (a >> axis) & 1:
+            EDGES.append((a, a | (1 << axis), axis))
+EDGE_ID = {(a, b): i for i, (a, b, _) in enumerate(EDGES)}
+EDGE_ID.update({(b, a): i for i, (a, b, _) in enumerate(EDGES)})
+
+
+def _faces():
+    """Six faces, each as its 4 corners counter-clockwise about the outward
+    normal (right-handed)."""
+    faces = []
+    for axis in range(3):
+        u, v = (axis + 1) % 3, (axis + 2) % 3          # (u, v, axis) right-handed
+        for side in (0, 1):
+            def corner(cu, cv):
+                c = [0, 0, 0]
+                c[axis], c[u], c[v] = side, cu, cv
+                return c[0] | (c[1] << 1) | (c[2] << 2)
+            ring = [corner(0, 0), corner(1, 0), corner(1, 1), corner(0, 1)]   # CCW about +axis
+            if side == 0:
+                ring = ring[::-1]                                            # outward is -axis
+            faces.append(ring)
+    return faces
+
+
+FACES = _faces()
+
+
+def case_loops(case: int):
+    """Closed loops of cube edges for one case (reading T5)."""
+    inside = [(case >> k) & 1 for k in range(8)]
+    succ = {}
+    for ring in FACES:
+        cross = []   # (position along the walk, edge, kind) kind 'in' = outside->inside
+        for i in range(4):
+            a, b = ring[i], ring[(i + 1) % 4]
+            if inside[a] != inside[b]:
+                cross.append((i, EDGE_ID[(a, b)], "in" if inside[b] else "out"))
+        for j, (i, e, kind) in enumerate(cross):
+            if kind != "in":
+                continue
+            for step in range(1, len(cross)):
+                _, e2, k2 = cross[(j + step) % len(cross)]
+                if k2 == "out":
+                    succ[e] = e2
+                    break
+    loops = []
+    seen = set()
+    for e0 in sorted(succ):
+        if e0 in seen:
+            continue
+        loop = [e0]
+        seen.add(e0)
+        e = succ[e0]
+        while e != e0:
+            loop.append(e)
+            seen.add(e)
+            e = succ[e]
+        loops.append(loop)
+    return loops
+
+
+def _edge_faces():
+    out = {}
+    for fi, ring in enumerate(FACES):
+        for i in range(4):
+            out.setdefault(EDGE_ID[(ring[i], ring[(i + 1) % 4])], set()).add(fi)
+    return out
+
+
+EDGE_FACES = _edge_faces()
+
+
+def fan_apex(loop):
+    """Position in the loop of the first vertex whose diagonals join edges
+    with no common face (reading T5)."""
+    k = len(loop)
+    for j in range(k):
+        if all(not (EDGE_FACES[loop[j]] & EDGE_FACES[loop[i]])
+               for i in range(k) if i not in (j, (j + 1) % k, (j - 1) % k)):
+            return j
+    raise AssertionError("no interior fan apex")
+
+
+def case_table():
+    """Triangles (edge triples) of every case, [256] lists."""
+    table = []
+    for case in range(256):
+        tris = []
+        for loop in case_loops(case):
+            j = fan_apex(loop)
+            ring = loop[j:] + loop[:j]
+            for i in range(1, len(ring) - 1):
+                tris.append((ring[0], ring[i], ring[i + 1]))
+        table.append(tris)
+    return table
+
+
+_TABLE = None
+
+
+def table():
+    global _TABLE
+    if _TABLE is None:
+        _TABLE = case_table()
+    return _TABLE
+
+
+# ---------------------------------------------------------------------------
+def binomial_steps(sigma_m: float, h: float) -> int:
+    sv = float(np.float32(sigma_m)) / float(np.float32(h))
+    n = max(1, int(round(2.0 * sv * sv)))
+    if n > 10:
+        raise ValueError("smoothing scale too large (n > 10)")
+    return n
+
+
+def denoise(surf, sigma_m: float, h: float, tau: float):
+    """V~ = [G * V >= tau] with the binomial kernel of reading T1 (exact
+    integers).  surf: uint8 [nz][ny][nx].  Returns (V~ uint8, sum int64)."""
+    n = binomial_steps(sigma_m, h)
+    w = np.array([math.comb(2 * n, n + k) for k in range(-n, n + 1)], dtype=np.int64)
+    acc = np.asarray(surf).astype(np.int64)
+    for axis in (2, 1, 0):
+        acc = ndimage.correlate1d(acc, w, axis=axis, mode="constant", cval=0)
+    thr = math.ceil(float(np.float32(tau)) * 2.0 ** (6 * n))
+    return (acc >= thr).astype(np.uint8), acc
+
+
+def outside(vt):
+    """O: free voxels 6-connected to the padded frame (reading T3)."""
+    free = np.pad(np.asarray(vt) == 0, 1, mode="constant", constant_values=True)
+    lab, _ = ndimage.label(free)          # 6-connectivity (the default structure)
+    return (lab == lab[0, 0, 0])[1:-1, 1:-1, 1:-1]
+
+
+def boundary_set(vt):
+    """S_0 (reading T3: outside the grid counts as 0)."""
+    v = np.pad(np.asarray(vt).astype(np.int8), 1, mode="constant", constant_values=0)
+    c = v[1:-1, 1:-1, 1:-1]
+    s = np.zeros(c.shape, dtype=bool)
+    for sl in [(slice(0, -2), slice(1, -1), slice(1, -1)), (slice(2, None), slice(1, -1), slice(1, -1)),
+               (slice(1, -1), slice(0, -2), slice(1, -1)), (slice(1, -1), slice(2, None), slice(1, -1)),
+               (slice(1, -1), slice(1, -1), slice(0, -2)), (slice(1, -1), slice(1, -1), slice(2, None))]:
+        s |= v[sl] != c
+    return s
+
+
+def shells(s0, P: int):
+    """p(x): first-arrival shell of a 6-neighbour expansion from S_0; -1 if
+    not reached within P shells.  Breadth-first by explicit layers."""
+    p = np.full(s0.shape, -1, dtype=np.int32)
+    p[s0] = 0
+    front = s0.copy()
+    for m in range(1, P + 1):
+        f = np.pad(front, 1, mode="constant", constant_values=False)
+        nb = (f[:-2, 1:-1, 1:-1] | f[2:, 1:-1, 1:-1] | f[1:-1, :-2, 1:-1] | f[1:-1, 2:, 1:-1]
+              | f[1:-1, 1:-1, :-2] | f[1:-1, 1:-1, 2:])
+        new = nb & (p < 0)
+        p[new] = m
+        front = new
+    return p
+
+
+def tsdf(surf, h: float, sigma_m: float, tau: float, r: float):
+    """(phi float32, V~, sign, p) for the surface mask `surf` (readings T1-T4)."""
+    vt, _ = denoise(surf, sigma_m, h, tau)
+    sgn = np.where(outside(vt), 1, -1).astype(np.int8)
+    hf, rf = np.float32(h), np.float32(r)
+    P = int(math.ceil(float(rf) / float(hf)))
+    p = shells(boundary_set(vt), P)
+    delta = np.where(p >= 0, p.astype(np.float32) * hf, rf).astype(np.float32)
+    phi = np.clip(sgn.astype(np.float32) * delta, -rf, rf).astype(np.float32)
+    return phi, vt, sgn, p
+
+
+def marching_cubes(phi, origin, h: float, iso: float = 0.0):
+    """Mesh of phi at iso (reading T5): (verts float32 [nv, 3], tris int32
+    [nt, 3]) in the canonical numbering."""
+    phi = np.asarray(phi, dtype=np.float32)
+    nz, ny, nx = phi.shape
+    isof = np.float32(iso)
+    hf = np.float32(h)
+    o = np.asarray(origin, dtype=np.float32).astype(np.float64)
+    cx = (o[0] + (np.arange(nx) + 0.5) * float(hf)).astype(np.float32)
+    cy = (o[1] + (np.arange(ny) + 0.5) * float(hf)).astype(np.float32)
+    cz = (o[2] + (np.arange(nz) + 0.5) * float(hf)).astype(np.float32)
+    inside = phi < isof
+    # vertices: crossed lattice edges numbered by (point, axis)
+    n_pts = nx * ny * nz
+    crossed = np.zeros((n_pts, 3), dtype=bool)
+    ins = inside.ravel()
+    flat = phi.ravel()
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ix, iy, iz = ix.ravel(), iy.ravel(), iz.ravel()
+    steps = (1, nx, nx * ny)
+    limits = (ix < nx - 1, iy < ny - 1, iz < nz - 1)
+    for axis in range(3):
+        ok = limits[axis]
+        idx = np.nonzero(ok)[0]
+        crossed[idx, axis] = ins[idx] != ins[idx + steps[axis]]
+    vid = np.full((n_pts, 3), -1, dtype=np.int64)
+    order = np.nonzero(crossed.ravel())[0]
+    vid.ravel()[order] = np.arange(order.size)
+    pt, ax = order // 3, order % 3
+    fa = flat[pt]
+    fb = flat[pt + np.array(steps)[ax]]
+    t = ((isof - fa) / (fb - fa)).astype(np.float32)
+    verts = np.stack([cx[ix[pt]], cy[iy[pt]], cz[iz[pt]]], axis=1).astype(np.float32)
+    moved = (verts[np.arange(pt.size), ax] + (t * hf).astype(np.float32)).astype(np.float32)
+    verts[np.arange(pt.size), ax] = moved
+    # triangles: cells numbered by their lowest lattice point
+    tab = table()
+    cell = np.nonzero(limits[0] & limits[1] & limits[2])[0]
+    case = np.zeros(cell.size, dtype=np.int64)
+    for k, (dx, dy, dz) in enumerate(CORNERS):
+        case |= ins[cell + dx + dy * nx + dz * nx * ny].astype(np.int64) << k
+    busy = (case != 0) & (case != 255)          # the other cases have no triangle
+    cell, case = cell[busy], case[busy]
+    tris = []
+    for c, cs in zip(cell, case):
+        for tri in tab[cs]:
+            ids = []
+            for e in tri:
+                a, _, axis = EDGES[e]
+                dx, dy, dz = CORNERS[a]
+                ids.append(vid[c + dx + dy * nx + dz * nx * ny, axis])
+            tris.append(ids)
+    tris = np.array(tris, dtype=np.int32).reshape(-1, 3)
+    return verts, tris

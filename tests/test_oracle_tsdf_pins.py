@@ -1,0 +1,202 @@
+"""Pins of the TSDF / marching-cubes oracle (oracle/tsdf.py), FGGS-LiDAR
+Sec. IV-B: closed forms, invariants, independent library routes and brute
+force."""
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+from oracle import tsdf as ot
+
+
+def test_single_corner_cases_cut_the_corner_facing_away():
+    tab = ot.table()
+    assert tab[0] == [] and tab[255] == []
+    for k in range(8):
+        tris = tab[1 << k]
+        assert len(tris) == 1
+        edges = set(tris[0])
+        at_k = {i for i, (a, b, _) in enumerate(ot.EDGES) if k in (a, b)}
+        assert edges == at_k
+        # orientation: normal points away from the inside corner
+        pts = []
+        for e in tris[0]:
+            a, b, _ = ot.EDGES[e]
+            pts.append((np.array(ot.CORNERS[a]) + np.array(ot.CORNERS[b])) / 2.0)
+        n = np.cross(pts[1] - pts[0], pts[2] - pts[0])
+        assert n @ (np.mean(pts, axis=0) - np.array(ot.CORNERS[k])) > 0
+
+
+def test_every_case_uses_each_crossed_edge_once():
+    for c in range(256):
+        ins = [(c >> k) & 1 for k in range(8)]
+        crossed = sorted(i for i, (a, b, _) in enumerate(ot.EDGES) if ins[a] != ins[b])
+        used = sorted(e for loop in ot.case_loops(c) for e in loop)
+        assert used == crossed
+        assert len(ot.table()[c]) == sum(len(l) - 2 for l in ot.case_loops(c))
+
+
+def test_fans_never_lie_on_a_cube_face():
+    for c in range(256):
+        for tri in ot.table()[c]:
+            # at least one pair of the triangle's edges shares no face, so the
+            # triangle is not contained in a face
+            common = ot.EDGE_FACES[tri[0]] & ot.EDGE_FACES[tri[1]] & ot.EDGE_FACES[tri[2]]
+            assert not common, (c, tri)
+
+
+def _edges_of(tris):
+    d = {}
+    for t in tris:
+        for i in range(3):
+            a, b = int(t[i]), int(t[(i + 1) % 3])
+            d[(a, b)] = d.get((a, b), 0) + 1
+    return d
+
+
+def _closed_and_oriented(tris):
+    d = _edges_of(tris)
+    return all(v == 1 for v in d.values()) and all(d.get((b, a), 0) == 1 for (a, b) in d)
+
+
+def test_sphere_mesh_closed_form():
+    """phi = |x - c| - R: vertices within h^2 / R of the sphere, closed and
+    consistently oriented (every directed edge once, its reverse once),
+    Euler characteristic 2, enclosed volume 4/3 pi R^3 within the
+    discretisation error."""
+    h, R = 0.1, 1.3
+    n = 34
+    o = (-1.7, -1.7, -1.7)
+    iz, iy, ix = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    X = o[0] + (ix + 0.5) * h
+    Y = o[1] + (iy + 0.5) * h
+    Z = o[2] + (iz + 0.5) * h
+    c = np.array([0.013, -0.021, 0.034])
+    phi = (np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) - R).astype(np.float32)
+    v, t = ot.marching_cubes(phi, o, h, 0.0)
+    d = np.linalg.norm(v.astype(np.float64) - c, axis=1)
+    assert np.max(np.abs(d - R)) < h * h / R
+    assert _closed_and_oriented(t)
+    E = len(_edges_of(t)) // 2
+    assert len(v) - E + len(t) == 2
+    a, b, cc = (v[t[:, k]].astype(np.float64) for k in range(3))
+    vol = np.sum(np.einsum("ij,ij->i", a, np.cross(b, cc))) / 6.0
+    assert vol == pytest.approx(4.0 / 3.0 * math.pi * R ** 3, rel=0.02)
+
+
+def test_random_fields_give_closed_oriented_meshes():
+    rng = np.random.default_rng(3)
+    for trial in range(20):
+        phi = rng.normal(size=(9, 10, 11)).astype(np.float32)
+        phi[0, :, :] = phi[-1, :, :] = 1.0        # outside on the grid boundary
+        phi[:, 0, :] = phi[:, -1, :] = 1.0
+        phi[:, :, 0] = phi[:, :, -1] = 1.0
+        v, t = ot.marching_cubes(phi, (0, 0, 0), 1.0, 0.0)
+        assert _closed_and_oriented(t), trial
+        a, b, cc = (v[t[:, k]].astype(np.float64) for k in range(3))
+        assert np.sum(np.einsum("ij,ij->i", a, np.cross(b, cc))) > 0
+
+
+def test_vertex_positions_closed_form():
+    """Two-point field: the vertex lies at the linear zero crossing."""
+    phi = np.array([[[-1.0, 3.0]]], dtype=np.float32).reshape(1, 1, 2)
+    phi = np.broadcast_to(phi, (2, 2, 2)).copy()
+    v, t = ot.marching_cubes(phi, (0, 0, 0), 0.5, 0.0)
+    assert len(t) == 2 and len(v) == 4
+    np.testing.assert_array_equal(v[:, 0], np.float32(0.25 + 0.25 * 0.5))
+    # a corner exactly at iso is outside (inside is phi < iso): the vertex
+    # sits on that corner (t = 1)
+    phi0 = np.broadcast_to(np.array([-1.0, 0.0], np.float32).reshape(1, 1, 2), (2, 2, 2)).copy()
+    v0, t0 = ot.marching_cubes(phi0, (0, 0, 0), 0.5, 0.0)
+    assert len(t0) == 2
+    np.testing.assert_array_equal(v0[:, 0], np.float32(0.75))
+
+
+def test_binomial_smoothing_closed_forms():
+    n = ot.binomial_steps(0.02, 0.02)          # sigma = 1 voxel -> n = 2, [1 4 6 4 1]
+    assert n == 2
+    surf = np.zeros((9, 9, 9), np.uint8)
+    surf[4, 4, 4] = 1
+    vt, acc = ot.denoise(surf, 0.02, 0.02, 0.0001)
+    w = np.array([1, 4, 6, 4, 1])
+    want = np.zeros((9, 9, 9), np.int64)
+    want[2:7, 2:7, 2:7] = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    np.testing.assert_array_equal(acc, want)
+    full = np.ones((12, 12, 12), np.uint8)
+    _, acc = ot.denoise(full, 0.02, 0.02, 0.5)
+    assert acc[6, 6, 6] == 2 ** 12 and acc[0, 6, 6] == 2 ** 12 * 11 // 16
+
+
+def test_binomial_smoothing_matches_a_3d_convolution():
+    rng = np.random.default_rng(5)
+    surf = (rng.random((13, 14, 15)) < 0.2).astype(np.uint8)
+    n = ot.binomial_steps(0.03, 0.02)
+    w = np.array([math.comb(2 * n, n + k) for k in range(-n, n + 1)], dtype=np.float64)
+    k3 = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    ref = ndimage.convolve(surf.astype(np.float64), k3, mode="constant", cval=0.0)
+    _, acc = ot.denoise(surf, 0.03, 0.02, 0.5)
+    np.testing.assert_array_equal(acc.astype(np.float64), ref)
+
+
+def test_threshold_is_inclusive_and_exact():
+    surf = np.ones((5, 5, 5), np.uint8)
+    vt, acc = ot.denoise(surf, 0.02, 0.02, 1.0)
+    assert vt[2, 2, 2] == 1 and acc[2, 2, 2] == 2 ** 12
+    assert vt.sum() == 1
+
+
+def test_flood_fill_cavities_and_tunnels():
+    vt = np.zeros((11, 11, 11), np.uint8)
+    vt[2:9, 2:9, 2:9] = 1
+    vt[3:8, 3:8, 3:8] = 0                      # closed cavity
+    o = ot.outside(vt)
+    assert o[0, 0, 0] and o[1, 5, 5] and not o[5, 5, 5]
+    vt2 = vt.copy()
+    vt2[5, 5, 2] = 0                           # a tunnel through one wall
+    o2 = ot.outside(vt2)
+    assert o2[5, 5, 5]
+    # brute force: iterate a 6-neighbour propagation from the frame
+    for grid, want in ((vt, o), (vt2, o2)):
+        free = np.pad(grid == 0, 1, constant_values=True)
+        lab = np.zeros_like(free)
+        lab[0, :, :] = lab[-1, :, :] = lab[:, 0, :] = lab[:, -1, :] = lab[:, :, 0] = lab[:, :, -1] = True
+        while True:
+            p = np.pad(lab, 1)
+            nb = (p[:-2, 1:-1, 1:-1] | p[2:, 1:-1, 1:-1] | p[1:-1, :-2, 1:-1] | p[1:-1, 2:, 1:-1]
+                  | p[1:-1, 1:-1, :-2] | p[1:-1, 1:-1, 2:])
+            new = lab | (nb & free)
+            if np.array_equal(new, lab):
+                break
+            lab = new
+        np.testing.assert_array_equal(lab[1:-1, 1:-1, 1:-1], want)
+
+
+def test_shells_are_taxicab_distances_to_the_boundary_set():
+    rng = np.random.default_rng(9)
+    vt = (rng.random((12, 13, 14)) < 0.05).astype(np.uint8)
+    s0 = ot.boundary_set(vt)
+    p = ot.shells(s0, 40)
+    ref = ndimage.distance_transform_cdt(~s0, metric="taxicab")
+    np.testing.assert_array_equal(p, ref)
+
+
+def test_half_space_tsdf_closed_form():
+    """Occupied for x >= 10 (a wall), h = 0.1, r = 0.35: S_0 is the two
+    layers x = 9, 10; |phi| = 0.1 * (distance to them), clipped at r; the
+    free side is outside (+), the wall side inside (-).  The smallest
+    kernel ([1 2 1] / 4 per axis) keeps the wall at tau = 0.4: a wall corner
+    on the grid boundary gets (3/4)^3 = 0.42, the free layer next to it 1/4."""
+    surf = np.zeros((6, 7, 20), np.uint8)
+    surf[:, :, 10:] = 1
+    phi, vt, sgn, p = ot.tsdf(surf, 0.1, 0.0001, 0.4, 0.35)
+    assert np.array_equal(vt, surf)
+    # S_0 also holds the wall's voxels on the grid boundary (the frame is
+    # free): inside the wall p is the distance to its nearest face
+    z, y, x = np.meshgrid(np.arange(6), np.arange(7), np.arange(20), indexing="ij")
+    wall_d = np.minimum.reduce([x - 10, 19 - x, y, 6 - y, z, 5 - z])
+    dist = np.where(x <= 9, 9 - x, wall_d)
+    want = np.clip(np.where(x <= 9, 1, -1) * (dist.astype(np.float32) * np.float32(0.1)),
+                   -np.float32(0.35), np.float32(0.35)).astype(np.float32)
+    np.testing.assert_array_equal(phi, want)
+    assert np.array_equal(sgn == 1, x <= 9)
