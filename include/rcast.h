@@ -440,6 +440,61 @@ enum { RC_GDBG_BOXES = 1, RC_GDBG_SORTED = 2, RC_GDBG_TOPOLOGY = 3, RC_GDBG_RECO
 rc_status rc_gauss_debug_copy(rc_ctx *ctx, int32_t set, int32_t what, void *host_dst,
                               uint64_t bytes);
 
+/* ------------------------------------------------------------------------
+ * Narrow-band TSDF and marching cubes (Sec. IV-B), from a surface mask V on
+ * a grid (origin, spacing, dims of rc_grid; its tile and theta are unused):
+ *   V'    = G * V, G the binomial kernel of n = max(1, round(2 sigma^2))
+ *           steps (sigma in voxels, halves rounded up): integer weights
+ *           C(2n, n + k), k = -n..n, separable, zero outside the grid;
+ *           V~ = [V' >= tau], decided exactly on the integer sums
+ *   O     = free voxels (V~ = 0) 6-connected to a free frame around the grid;
+ *           s = +1 on O, -1 elsewhere
+ *   S_0   = voxels with a 6-neighbour of the other V~ value (frame = 0)
+ *   p     = first shell of a 6-neighbour expansion from S_0 reaching the
+ *           voxel, counted up to ceil(band / h)
+ *   phi   = clip(s p h, -band, band) (band where p was not reached)
+ * Marching cubes runs on the lattice of voxel centres: a corner is inside
+ * when phi < iso; each crossed lattice edge carries one vertex at
+ * t = (iso - phi_a) / (phi_b - phi_a) from its lower end; vertices are
+ * numbered by (voxel, axis x/y/z), triangles by (cell, position in the case
+ * table); triangles face the region phi >= iso.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    float sigma_smooth;   /* smoothing scale, metres, > 0 (n <= 10)          */
+    float tau;            /* re-threshold (finite)                           */
+    float band;           /* r, metres, > 0; band / spacing <= 250           */
+    int32_t reserved[5];
+} rc_tsdf_opts;
+
+/* TSDF of the DEVICE uint8 surface mask `surf` [nz][ny][nx] into the DEVICE
+ * float32 `out_phi` (same layout); `out_vtilde` (DEVICE uint8, or NULL)
+ * receives V~.  Runs on `stream` and returns when phi is complete (the
+ * outside labelling repeats until it settles, reading a flag each sweep).
+ * Scratch device memory of about 15 bytes per voxel is kept by the context
+ * (grown on demand, reused by later calls, freed by rc_destroy).
+ * Errors: RC_E_INVAL (grid, options), RC_E_NOMEM, RC_E_DEVICE. */
+rc_status rc_tsdf(rc_ctx *ctx, const rc_grid *grid, const uint8_t *surf,
+                  const rc_tsdf_opts *opts, float *out_phi, uint8_t *out_vtilde, void *stream);
+
+/* Marching cubes of the DEVICE float32 field `phi` [nz][ny][nx] at `iso`.
+ * Always writes the mesh size to *n_verts / *n_tris.  With out_verts (DEVICE
+ * float32 [cap_verts][3]) and out_tris (DEVICE int32 [cap_tris][3]) given
+ * and large enough, also writes the mesh; with both NULL only counts (call
+ * once to size, once to fill; a capacity already large enough fills in one
+ * call).  Synchronous.  Scratch of about 17 bytes per voxel is kept by the
+ * context like rc_tsdf's.  Grids up to 2^29 voxels.
+ * Errors: RC_E_INVAL, RC_E_NOMEM (capacity too small: sizes still written),
+ * RC_E_DEVICE. */
+rc_status rc_marching_cubes(rc_ctx *ctx, const rc_grid *grid, const float *phi, float iso,
+                            float *out_verts, int32_t *out_tris, int64_t cap_verts,
+                            int64_t cap_tris, int64_t *n_verts, int64_t *n_tris, void *stream);
+
+/* The marching-cubes case table, HOST arrays: count[256] triangles per case
+ * (corner k inside sets bit k; corner k = (k & 1, k >> 1 & 1, k >> 2 & 1))
+ * and tris[256][15] cube-edge ids, -1 padded (edge 4 a + j joins the j-th
+ * corner, ascending, with bit a clear to its neighbour along axis a). */
+rc_status rc_marching_cubes_table(uint8_t *count, int8_t *tris);
+
 /* Device id of a host-only context for rc_create: no HIP calls; scenes and
  * patterns hold their sizes only (rc_scene_upload needs host arrays);
  * rc_raycast_* report RC_E_STATE; the server runs requests on a simulated

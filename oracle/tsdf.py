@@ -23,7 +23,7 @@ Readings taken where the paper is silent (each is also listed in the design
 notes):
 
   T1  The Gaussian kernel of scale sigma (metres; sigma_v = sigma / h voxels)
-      is the binomial kernel with n = max(1, round(2 sigma_v^2)) steps,
+      is the binomial kernel with n = max(1, floor(2 sigma_v^2 + 1/2)) steps,
       weights C(2n, n + k) for k = -n..n (variance n / 2, the discrete
       Gaussian of integer weights), separable on the three axes, zero outside
       the grid; V' = sum / 2^(6n).  All sums are exact integers, and V~ is
@@ -175,7 +175,7 @@ def table():
 # ---------------------------------------------------------------------------
 def binomial_steps(sigma_m: float, h: float) -> int:
     sv = float(np.float32(sigma_m)) / float(np.float32(h))
-    n = max(1, int(round(2.0 * sv * sv)))
+    n = max(1, int(math.floor(2.0 * sv * sv + 0.5)))
     if n > 10:
         raise ValueError("smoothing scale too large (n > 10)")
     return n

@@ -392,6 +392,8 @@ void rc_destroy(rc_ctx *c)
         if (p.alive) dev_free(c, p.dirs, p.bytes);
     for (auto &g : c->gsets)
         if (g.alive) free_gauss_set(c, g);
+    if (c->mc_table) dev_free(c, c->mc_table, 256 + 256 * 15);
+    if (c->mesh_ws) dev_free(c, c->mesh_ws, c->mesh_ws_bytes);
     for (auto &sl : c->slots) {
         if (sl.host) (void)hipHostFree(sl.host);
         if (sl.dev) dev_free(c, sl.dev, slot_bytes(sl.cap));

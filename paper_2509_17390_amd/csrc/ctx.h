@@ -108,6 +108,10 @@ struct rc_ctx {
     int32_t *flags_dev = nullptr;
     rc_tuning tuning{};
     rc::ServeState *serve = nullptr;
+    uint8_t *mc_table = nullptr;   // marching-cubes case table on the device (256 + 256 * 15 bytes)
+    std::mutex mesh_mu;            // TSDF / marching-cubes calls and their scratch
+    void *mesh_ws = nullptr;       // grow-only scratch of those calls
+    size_t mesh_ws_bytes = 0;
 };
 
 namespace rc {

@@ -65,3 +65,46 @@ hipError_t voxelize_launch(int mode, const NodeRec *nodes, const GaussRec *recs,
                            float *density, uint8_t *occ, int32_t *tile_counts, hipStream_t s);
 // Surface mask from occupancy.
 hipError_t surface_launch(const uint8_t *occ, uint8_t *surf, const VoxGrid &g, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Narrow-band TSDF and marching cubes (tsdf.hip).
+
+struct TsdfGrid {
+    double o[3];          // origin (float32 input, exact)
+    double h;             // spacing (float32 input, exact)
+    float hf;             // the same spacing as float32
+    int32_t nx, ny, nz;
+    int64_t n;            // voxels
+};
+
+// Binomial smoothing kernel: n steps, weights C(2n, n + k) for k = -n..n.
+constexpr int kMaxBinomial = 10;
+struct Binomial {
+    int32_t n;
+    uint32_t w[2 * kMaxBinomial + 1];
+};
+
+// V~ = [sum >= thr] of the separable binomial smoothing of `surf`; a (u32)
+// and b (u64) hold the x and xy passes.
+hipError_t tsdf_smooth_launch(const uint8_t *surf, uint32_t *a, uint64_t *b, uint8_t *vt,
+                              const TsdfGrid &g, const Binomial &w, uint64_t thr, hipStream_t s);
+hipError_t tsdf_flood_init_launch(const uint8_t *vt, uint8_t *lab, const TsdfGrid &g,
+                                  hipStream_t s);
+// One round of the outside labelling (line sweeps along x, y, z);
+// *changed |= 1 if any voxel changed.
+hipError_t tsdf_flood_round_launch(uint8_t *lab, const TsdfGrid &g, int32_t *changed,
+                                   hipStream_t s);
+hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint8_t *lab, uint8_t *p, float *phi,
+                                  const TsdfGrid &g, int shells, float h, float r, hipStream_t s);
+
+// Marching cubes: the case table (count[256], tri[256][15] edge ids, -1
+// padded), the count pass with both exclusive scans (vsums / tsums hold
+// mc_scan_sums_len(n) entries, the grand total last), and the emit pass.
+void mc_table_copy(uint8_t *count, int8_t *tri);
+int64_t mc_scan_sums_len(int64_t n);
+hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
+                           uint8_t *mask, uint32_t *vcount, uint32_t *tcount, uint32_t *voff,
+                           uint32_t *toff, uint32_t *vsums, uint32_t *tsums, hipStream_t s);
+hipError_t mc_emit_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
+                          const int8_t *tris_of, const uint8_t *mask, const uint32_t *voff,
+                          const uint32_t *toff, float *verts, int32_t *tris, hipStream_t s);

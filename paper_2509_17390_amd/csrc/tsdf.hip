@@ -1,0 +1,582 @@
+// tsdf.hip -- denoising, flood-fill sign, narrow-band TSDF and marching cubes
+// on gfx950 (FGGS-LiDAR Sec. IV-B).
+//
+//   V'    = G * V (binomial kernel of n steps: integer weights C(2n, n+k),
+//           the discrete Gaussian of variance n / 2), separable, exact in
+//           64-bit integers; V~ = [V' >= tau], decided on the exact sum
+//   O     = free voxels 6-connected to a free frame around the grid:
+//           rounds of line sweeps along x, y and z (one thread per line,
+//           spreading along whole free runs) until a round changes nothing
+//   S_0   = voxels with a 6-neighbour of the other V~ value (frame = free)
+//   p     = shell index of a 6-neighbour expansion from S_0, one launch per
+//           shell up to ceil(r / h)
+//   phi   = clip(s p h, -r, r), s = +1 on O, -1 elsewhere
+//   mesh  = marching cubes of phi at iso on the voxel-centre lattice:
+//           per point, count crossed lattice edges (one vertex each) and the
+//           triangles of the cell it anchors; exclusive scans give every
+//           vertex and triangle its slot; a second pass writes them.  The case
+//           table is built on the host from a walk over the cube's faces.
+#include "gauss_internal.h"
+
+#include <math.h>
+
+#include <mutex>
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kScanItems = 4;                  // per thread in the block scan
+constexpr int kScanTile = kBlock * kScanItems;
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+// ---- smoothing and re-threshold ------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_smooth_x(const uint8_t *__restrict__ v,
+                                                     uint32_t *__restrict__ out, TsdfGrid g,
+                                                     Binomial w)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    const int x = (int)(i % g.nx);
+    uint32_t s = 0;
+    for (int k = -w.n; k <= w.n; ++k) {
+        const int xx = x + k;
+        if (xx >= 0 && xx < g.nx && v[i + k]) s += w.w[k + w.n];
+    }
+    out[i] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_smooth_y(const uint32_t *__restrict__ a,
+                                                     uint64_t *__restrict__ out, TsdfGrid g,
+                                                     Binomial w)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    const int y = (int)((i / g.nx) % g.ny);
+    uint64_t s = 0;
+    for (int k = -w.n; k <= w.n; ++k) {
+        const int yy = y + k;
+        if (yy >= 0 && yy < g.ny) s += (uint64_t)w.w[k + w.n] * a[i + (int64_t)k * g.nx];
+    }
+    out[i] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_smooth_z(const uint64_t *__restrict__ b,
+                                                     uint8_t *__restrict__ vt, TsdfGrid g,
+                                                     Binomial w, uint64_t thr)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    const int64_t sxy = (int64_t)g.nx * g.ny;
+    const int z = (int)(i / sxy);
+    uint64_t s = 0;
+    for (int k = -w.n; k <= w.n; ++k) {
+        const int zz = z + k;
+        if (zz >= 0 && zz < g.nz) s += (uint64_t)w.w[k + w.n] * b[i + (int64_t)k * sxy];
+    }
+    vt[i] = s >= thr ? 1 : 0;
+}
+
+// ---- outside labelling -----------------------------------------------------
+// lab: 0 occupied, 1 free (not yet known to be outside), 2 outside
+__global__ __launch_bounds__(kBlock) void k_flood_init(const uint8_t *__restrict__ vt,
+                                                       uint8_t *__restrict__ lab, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) lab[i] = vt[i] ? 0 : 1;
+}
+
+// One line of the grid along `axis` per thread: "outside" spreads along
+// every run of free voxels that touches an outside voxel or the frame (the
+// frame lies beyond both ends of the line), in a forward and a backward walk.
+// Repeating the sweep along x, y and z reaches the 6-connected fixed point:
+// a path to the frame is a chain of axis-parallel runs, one run per sweep.
+// Labels only go from 1 to 2, so concurrent lines never undo each other.
+template <int AXIS>
+__global__ __launch_bounds__(kBlock) void k_flood_lines(uint8_t *__restrict__ lab, TsdfGrid g,
+                                                        int32_t *__restrict__ changed)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t sxy = (int64_t)g.nx * g.ny;
+    int64_t base, step;
+    int len;
+    if (AXIS == 0) {          // lines (y, z): t = z ny + y
+        if (t >= (int64_t)g.ny * g.nz) return;
+        base = t * g.nx;
+        step = 1;
+        len = g.nx;
+    } else if (AXIS == 1) {   // lines (x, z): t = z nx + x
+        if (t >= (int64_t)g.nx * g.nz) return;
+        const int64_t z = t / g.nx, x = t - z * g.nx;
+        base = z * sxy + x;
+        step = g.nx;
+        len = g.ny;
+    } else {                  // lines (x, y): t = y nx + x
+        if (t >= sxy) return;
+        base = t;
+        step = sxy;
+        len = g.nz;
+    }
+    // chunks of 16 voxels: the loads of a chunk are independent of each
+    // other and of the walk, so they are issued together
+    constexpr int CH = 16;
+    bool any = false;
+    bool reach = true;        // the frame before the first voxel
+    for (int k0 = 0; k0 < len; k0 += CH) {
+        uint8_t v[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j)
+            v[j] = k0 + j < len ? lab[base + (int64_t)(k0 + j) * step] : (uint8_t)0;
+        uint32_t set = 0;
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            if (v[j] == 0) reach = false;
+            else if (v[j] == 2) reach = true;
+            else if (reach) {
+                v[j] = 2;
+                set |= 1u << j;
+            }
+        }
+        if (set) {
+            any = true;
+#pragma unroll
+            for (int j = 0; j < CH; ++j)
+                if ((set >> j) & 1u) lab[base + (int64_t)(k0 + j) * step] = 2;
+        }
+    }
+    reach = true;             // the frame after the last voxel
+    for (int k1 = len; k1 > 0; k1 -= CH) {
+        uint8_t v[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j)
+            v[j] = k1 - 1 - j >= 0 ? lab[base + (int64_t)(k1 - 1 - j) * step] : (uint8_t)0;
+        uint32_t set = 0;
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            if (v[j] == 0) reach = false;
+            else if (v[j] == 2) reach = true;
+            else if (reach) {
+                v[j] = 2;
+                set |= 1u << j;
+            }
+        }
+        if (set) {
+            any = true;
+#pragma unroll
+            for (int j = 0; j < CH; ++j)
+                if ((set >> j) & 1u) lab[base + (int64_t)(k1 - 1 - j) * step] = 2;
+        }
+    }
+    if (any) atomicOr(changed, 1);
+}
+
+// ---- distance shells and phi -----------------------------------------------
+__device__ __forceinline__ void coords(int64_t i, const TsdfGrid &g, int &x, int &y, int &z)
+{
+    x = (int)(i % g.nx);
+    const int64_t r = i / g.nx;
+    y = (int)(r % g.ny);
+    z = (int)(r / g.ny);
+}
+
+// p = 0 on S_0 (a 6-neighbour with the other V~ value; outside the grid is
+// 0), else 255 (not reached)
+__global__ __launch_bounds__(kBlock) void k_shell0(const uint8_t *__restrict__ vt,
+                                                   uint8_t *__restrict__ p, TsdfGrid g)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int x, y, z;
+    coords(i, g, x, y, z);
+    const int64_t sxy = (int64_t)g.nx * g.ny;
+    const uint8_t c = vt[i];
+    const uint8_t nb[6] = {x > 0 ? vt[i - 1] : (uint8_t)0, x < g.nx - 1 ? vt[i + 1] : (uint8_t)0,
+                           y > 0 ? vt[i - g.nx] : (uint8_t)0,
+                           y < g.ny - 1 ? vt[i + g.nx] : (uint8_t)0,
+                           z > 0 ? vt[i - sxy] : (uint8_t)0, z < g.nz - 1 ? vt[i + sxy] : (uint8_t)0};
+    bool edge = false;
+    for (int k = 0; k < 6; ++k) edge |= nb[k] != c;
+    p[i] = edge ? 0 : 255;
+}
+
+// shell m: unreached voxels with a 6-neighbour in shell m - 1
+__global__ __launch_bounds__(kBlock) void k_shell(uint8_t *__restrict__ p, TsdfGrid g, int m)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n || p[i] != 255) return;
+    int x, y, z;
+    coords(i, g, x, y, z);
+    const int64_t sxy = (int64_t)g.nx * g.ny;
+    const uint8_t prev = (uint8_t)(m - 1);
+    const bool hit = (x > 0 && p[i - 1] == prev) || (x < g.nx - 1 && p[i + 1] == prev) ||
+                     (y > 0 && p[i - g.nx] == prev) || (y < g.ny - 1 && p[i + g.nx] == prev) ||
+                     (z > 0 && p[i - sxy] == prev) || (z < g.nz - 1 && p[i + sxy] == prev);
+    if (hit) p[i] = (uint8_t)m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_phi(const uint8_t *__restrict__ p,
+                                                const uint8_t *__restrict__ lab,
+                                                float *__restrict__ phi, TsdfGrid g, float h,
+                                                float r)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    const float delta = p[i] == 255 ? r : (float)p[i] * h;
+    const float s = lab[i] == 2 ? delta : -delta;
+    phi[i] = fminf(fmaxf(s, -r), r);
+}
+
+// ---- marching cubes --------------------------------------------------------
+// Per lattice point: mask of crossed edges +x/+y/+z (bits 0..2), vertex
+// count, and the triangle count of the cell it anchors.
+__device__ __forceinline__ int cell_case(const float *__restrict__ phi, int64_t i, int64_t sx,
+                                         int64_t sxy, float iso)
+{
+    int c = 0;
+    for (int k = 0; k < 8; ++k) {
+        const int64_t j = i + ((k & 1) ? 1 : 0) + ((k & 2) ? sx : 0) + ((k & 4) ? sxy : 0);
+        c |= (phi[j] < iso ? 1 : 0) << k;
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mc_count(const float *__restrict__ phi, TsdfGrid g,
+                                                     float iso, const uint8_t *__restrict__ ntri,
+                                                     uint8_t *__restrict__ mask,
+                                                     uint32_t *__restrict__ vcount,
+                                                     uint32_t *__restrict__ tcount)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int x, y, z;
+    coords(i, g, x, y, z);
+    const int64_t sx = g.nx, sxy = (int64_t)g.nx * g.ny;
+    const bool in = phi[i] < iso;
+    int m = 0;
+    if (x < g.nx - 1 && (phi[i + 1] < iso) != in) m |= 1;
+    if (y < g.ny - 1 && (phi[i + sx] < iso) != in) m |= 2;
+    if (z < g.nz - 1 && (phi[i + sxy] < iso) != in) m |= 4;
+    mask[i] = (uint8_t)m;
+    vcount[i] = (uint32_t)__popc(m);
+    uint32_t t = 0;
+    if (x < g.nx - 1 && y < g.ny - 1 && z < g.nz - 1) t = ntri[cell_case(phi, i, sx, sxy, iso)];
+    tcount[i] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ phi, TsdfGrid g,
+                                                    float iso, const uint8_t *__restrict__ ntri,
+                                                    const int8_t *__restrict__ tris_of,
+                                                    const uint8_t *__restrict__ mask,
+                                                    const uint32_t *__restrict__ voff,
+                                                    const uint32_t *__restrict__ toff,
+                                                    float *__restrict__ verts,
+                                                    int32_t *__restrict__ tris)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int x, y, z;
+    coords(i, g, x, y, z);
+    const int64_t sx = g.nx, sxy = (int64_t)g.nx * g.ny;
+    const int m = mask[i];
+    if (m) {
+        const float c[3] = {(float)(g.o[0] + ((double)x + 0.5) * g.h),
+                            (float)(g.o[1] + ((double)y + 0.5) * g.h),
+                            (float)(g.o[2] + ((double)z + 0.5) * g.h)};
+        const float fa = phi[i];
+        const int64_t step[3] = {1, sx, sxy};
+        uint32_t v = voff[i];
+        for (int a = 0; a < 3; ++a) {
+            if (!((m >> a) & 1)) continue;
+            const float fb = phi[i + step[a]];
+            const float t = __fdiv_rn(iso - fa, fb - fa);
+            float p[3] = {c[0], c[1], c[2]};
+            p[a] = __fadd_rn(c[a], __fmul_rn(t, g.hf));
+            verts[3 * (int64_t)v + 0] = p[0];
+            verts[3 * (int64_t)v + 1] = p[1];
+            verts[3 * (int64_t)v + 2] = p[2];
+            ++v;
+        }
+    }
+    if (x < g.nx - 1 && y < g.ny - 1 && z < g.nz - 1) {
+        const int cs = cell_case(phi, i, sx, sxy, iso);
+        const int nt = ntri[cs];
+        uint32_t t0 = toff[i];
+        for (int k = 0; k < nt; ++k) {
+            for (int e = 0; e < 3; ++e) {
+                const int edge = tris_of[cs * 15 + 3 * k + e];
+                // edges are numbered (axis, lower corner): 4 per axis
+                const int axis = edge >> 2, nth = edge & 3;
+                // the nth corner (ascending) whose bit `axis` is clear
+                const int lo = nth & ((1 << axis) - 1);
+                const int corner = ((nth >> axis) << (axis + 1)) | lo;
+                const int64_t q = i + ((corner & 1) ? 1 : 0) + ((corner & 2) ? sx : 0) +
+                                  ((corner & 4) ? sxy : 0);
+                const int mq = mask[q];
+                const uint32_t id = voff[q] + (uint32_t)__popc(mq & ((1 << axis) - 1));
+                tris[3 * ((int64_t)t0 + k) + e] = (int32_t)id;
+            }
+        }
+    }
+}
+
+// ---- exclusive scan of uint32 (three kernels) ------------------------------
+__device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *total)
+{
+    __shared__ uint32_t ws[kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) ws[w] = x;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int k = 0; k < kBlock / 64; ++k) {
+        if (k < w) off += ws[k];
+        tot += ws[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const uint32_t *__restrict__ in,
+                                                       uint32_t *__restrict__ out, int64_t n,
+                                                       uint32_t *__restrict__ sums)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems], s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_scan_excl(s, &tot);
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// one block: exclusive scan of the tile sums in place, grand total after them
+__global__ __launch_bounds__(kBlock) void k_scan_sums(uint32_t *__restrict__ sums, int nb)
+{
+    uint32_t carry = 0;
+    for (int base = 0; base < nb; base += kBlock) {
+        const int i = base + threadIdx.x;
+        const uint32_t v = i < nb ? sums[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_scan_excl(v, &tot);
+        if (i < nb) sums[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) sums[nb] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t *__restrict__ out, int64_t n,
+                                                     const uint32_t *__restrict__ sums)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const uint32_t add = sums[blockIdx.x];
+    for (int k = threadIdx.x; k < kScanTile; k += kBlock)
+        if (base + k < n) out[base + k] += add;
+}
+
+// ---- the case table (host) -------------------------------------------------
+// Corner k of a cell is (k & 1, k >> 1 & 1, k >> 2 & 1); edge e = 4 axis + j
+// joins the j-th corner (ascending) with bit `axis` clear to that corner plus
+// the unit step along `axis`.
+struct Table {
+    uint8_t count[256];
+    int8_t tri[256][15];
+};
+
+void make_table(Table &t)
+{
+    int ea[12], eb[12];
+    int edge_of[8][8];
+    for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b) edge_of[a][b] = -1;
+    int ne = 0;
+    for (int axis = 0; axis < 3; ++axis)
+        for (int a = 0; a < 8; ++a)
+            if (!((a >> axis) & 1)) {
+                ea[ne] = a;
+                eb[ne] = a | (1 << axis);
+                edge_of[a][eb[ne]] = edge_of[eb[ne]][a] = ne;
+                ++ne;
+            }
+    // faces: corners counter-clockwise about the outward normal
+    int face[6][4];
+    int nf = 0;
+    for (int axis = 0; axis < 3; ++axis) {
+        const int u = (axis + 1) % 3, v = (axis + 2) % 3;
+        for (int side = 0; side < 2; ++side) {
+            const int uv[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};   // about +axis
+            for (int k = 0; k < 4; ++k) {
+                const int kk = side ? k : 3 - k;                     // -axis: reversed
+                const int cu = uv[kk][0], cv = uv[kk][1];
+                face[nf][k] = (side << axis) | (cu << u) | (cv << v);
+            }
+            ++nf;
+        }
+    }
+    unsigned efaces[12] = {0};
+    for (int f = 0; f < 6; ++f)
+        for (int k = 0; k < 4; ++k) efaces[edge_of[face[f][k]][face[f][(k + 1) % 4]]] |= 1u << f;
+    (void)ea;
+    (void)eb;
+    for (int cs = 0; cs < 256; ++cs) {
+        int succ[12];
+        for (int e = 0; e < 12; ++e) succ[e] = -1;
+        for (int f = 0; f < 6; ++f) {
+            int ce[4], cin[4], nc = 0;   // crossings in walk order; cin = outside->inside
+            for (int k = 0; k < 4; ++k) {
+                const int a = face[f][k], b = face[f][(k + 1) % 4];
+                const int ia = (cs >> a) & 1, ib = (cs >> b) & 1;
+                if (ia != ib) {
+                    ce[nc] = edge_of[a][b];
+                    cin[nc] = ib;
+                    ++nc;
+                }
+            }
+            for (int j = 0; j < nc; ++j) {
+                if (!cin[j]) continue;
+                for (int s = 1; s < nc; ++s) {
+                    const int q = (j + s) % nc;
+                    if (!cin[q]) {
+                        succ[ce[j]] = ce[q];
+                        break;
+                    }
+                }
+            }
+        }
+        int n = 0;
+        bool seen[12] = {false};
+        for (int e0 = 0; e0 < 12; ++e0) {
+            if (succ[e0] < 0 || seen[e0]) continue;
+            int loop[12], k = 0;
+            int e = e0;
+            do {
+                loop[k++] = e;
+                seen[e] = true;
+                e = succ[e];
+            } while (e != e0);
+            // fan apex: first vertex whose diagonals join edges sharing no face
+            int apex = 0;
+            for (int j = 0; j < k; ++j) {
+                bool ok = true;
+                for (int q = 0; q < k && ok; ++q) {
+                    if (q == j || q == (j + 1) % k || q == (j + k - 1) % k) continue;
+                    if (efaces[loop[j]] & efaces[loop[q]]) ok = false;
+                }
+                if (ok) {
+                    apex = j;
+                    break;
+                }
+            }
+            for (int q = 1; q + 1 < k; ++q) {
+                t.tri[cs][3 * n + 0] = (int8_t)loop[apex];
+                t.tri[cs][3 * n + 1] = (int8_t)loop[(apex + q) % k];
+                t.tri[cs][3 * n + 2] = (int8_t)loop[(apex + q + 1) % k];
+                ++n;
+            }
+        }
+        t.count[cs] = (uint8_t)n;
+        for (int q = 3 * n; q < 15; ++q) t.tri[cs][q] = -1;
+    }
+}
+
+const Table &table()
+{
+    static Table t;
+    static std::once_flag once;
+    std::call_once(once, [] { make_table(t); });
+    return t;
+}
+
+hipError_t scan_launch(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *sums,
+                       hipStream_t s)
+{
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, sums, (int)nb);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kBlock), 0, s, out, n, sums);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+void mc_table_copy(uint8_t *count, int8_t *tri)
+{
+    const Table &t = table();
+    for (int c = 0; c < 256; ++c) {
+        count[c] = t.count[c];
+        for (int q = 0; q < 15; ++q) tri[15 * c + q] = t.tri[c][q];
+    }
+}
+
+int64_t mc_scan_sums_len(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+hipError_t tsdf_smooth_launch(const uint8_t *surf, uint32_t *a, uint64_t *b, uint8_t *vt,
+                              const TsdfGrid &g, const Binomial &w, uint64_t thr, hipStream_t s)
+{
+    const unsigned grid = grid_for(g.n, kBlock);
+    hipLaunchKernelGGL(k_smooth_x, dim3(grid), dim3(kBlock), 0, s, surf, a, g, w);
+    hipLaunchKernelGGL(k_smooth_y, dim3(grid), dim3(kBlock), 0, s, a, b, g, w);
+    hipLaunchKernelGGL(k_smooth_z, dim3(grid), dim3(kBlock), 0, s, b, vt, g, w, thr);
+    return hipGetLastError();
+}
+
+hipError_t tsdf_flood_init_launch(const uint8_t *vt, uint8_t *lab, const TsdfGrid &g,
+                                  hipStream_t s)
+{
+    hipLaunchKernelGGL(k_flood_init, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, vt, lab,
+                       g.n);
+    return hipGetLastError();
+}
+
+hipError_t tsdf_flood_round_launch(uint8_t *lab, const TsdfGrid &g, int32_t *changed,
+                                   hipStream_t s)
+{
+    hipLaunchKernelGGL(k_flood_lines<0>, dim3(grid_for((int64_t)g.ny * g.nz, kBlock)),
+                       dim3(kBlock), 0, s, lab, g, changed);
+    hipLaunchKernelGGL(k_flood_lines<1>, dim3(grid_for((int64_t)g.nx * g.nz, kBlock)),
+                       dim3(kBlock), 0, s, lab, g, changed);
+    hipLaunchKernelGGL(k_flood_lines<2>, dim3(grid_for((int64_t)g.nx * g.ny, kBlock)),
+                       dim3(kBlock), 0, s, lab, g, changed);
+    return hipGetLastError();
+}
+
+hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint8_t *lab, uint8_t *p, float *phi,
+                                  const TsdfGrid &g, int shells, float h, float r, hipStream_t s)
+{
+    const unsigned grid = grid_for(g.n, kBlock);
+    hipLaunchKernelGGL(k_shell0, dim3(grid), dim3(kBlock), 0, s, vt, p, g);
+    for (int m = 1; m <= shells; ++m)
+        hipLaunchKernelGGL(k_shell, dim3(grid), dim3(kBlock), 0, s, p, g, m);
+    hipLaunchKernelGGL(k_phi, dim3(grid), dim3(kBlock), 0, s, p, lab, phi, g, h, r);
+    return hipGetLastError();
+}
+
+hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
+                           uint8_t *mask, uint32_t *vcount, uint32_t *tcount, uint32_t *voff,
+                           uint32_t *toff, uint32_t *vsums, uint32_t *tsums, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mc_count, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, phi, g, iso,
+                       ntri, mask, vcount, tcount);
+    hipError_t e = scan_launch(vcount, voff, g.n, vsums, s);
+    if (e == hipSuccess) e = scan_launch(tcount, toff, g.n, tsums, s);
+    return e;
+}
+
+hipError_t mc_emit_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
+                          const int8_t *tris_of, const uint8_t *mask, const uint32_t *voff,
+                          const uint32_t *toff, float *verts, int32_t *tris, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mc_emit, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, phi, g, iso,
+                       ntri, tris_of, mask, voff, toff, verts, tris);
+    return hipGetLastError();
+}

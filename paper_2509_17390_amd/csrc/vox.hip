@@ -7,6 +7,8 @@
 #include <string.h>
 
 #include <mutex>
+#include <utility>
+#include <vector>
 
 namespace rc {
 
@@ -328,5 +330,196 @@ rc_status rc_gauss_debug_copy(rc_ctx *c, int32_t set, int32_t what, void *dst, u
     if (size == 0) return RC_OK;
     HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipMemcpy(dst, src, size, hipMemcpyDeviceToHost));
+    return RC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Narrow-band TSDF and marching cubes (Sec. IV-B).
+
+namespace {
+
+rc_status make_tsdf_grid(const rc_grid *gr, TsdfGrid &g)
+{
+    if (!gr) return fail(RC_E_INVAL, "null grid");
+    if (!(gr->spacing > 0.0f) || !isfinite(gr->spacing))
+        return fail(RC_E_INVAL, "spacing must be finite and > 0");
+    for (int a = 0; a < 3; ++a) {
+        if (!isfinite(gr->origin[a])) return fail(RC_E_INVAL, "origin must be finite");
+        if (gr->dims[a] < 1 || gr->dims[a] > (1 << 30))
+            return fail(RC_E_INVAL, "dims must be in 1..2^30");
+        const double far = fabs((double)gr->origin[a]) + (double)gr->dims[a] * gr->spacing;
+        if (!(far < 1e38)) return fail(RC_E_INVAL, "grid extends beyond the float range");
+    }
+    memset(&g, 0, sizeof g);
+    for (int a = 0; a < 3; ++a) g.o[a] = gr->origin[a];
+    g.h = gr->spacing;
+    g.hf = gr->spacing;
+    g.nx = gr->dims[0];
+    g.ny = gr->dims[1];
+    g.nz = gr->dims[2];
+    g.n = (int64_t)g.nx * g.ny * g.nz;
+    if (g.n > ((int64_t)1 << 34)) return fail(RC_E_INVAL, "grid too large");
+    return RC_OK;
+}
+
+// Sub-buffers carved from the context's grow-only TSDF / marching-cubes
+// scratch (the caller holds c->mesh_mu for the whole call; the calls are
+// synchronous, so nothing still uses the scratch when it is regrown).
+struct Scratch {
+    rc_ctx *c;
+    size_t used = 0;
+    std::vector<std::pair<void **, size_t>> want;
+    explicit Scratch(rc_ctx *ctx) : c(ctx) {}
+    template <class T>
+    void take(T **p, size_t bytes)
+    {
+        want.push_back({(void **)p, (bytes + 255) & ~(size_t)255});
+    }
+    rc_status commit()
+    {
+        size_t need = 0;
+        for (auto &w : want) need += w.second;
+        if (need > c->mesh_ws_bytes) {
+            if (c->mesh_ws) dev_free(c, c->mesh_ws, c->mesh_ws_bytes);
+            c->mesh_ws = nullptr;
+            c->mesh_ws_bytes = 0;
+            rc_status st = dev_alloc(c, &c->mesh_ws, need);
+            if (st != RC_OK) return st;
+            c->mesh_ws_bytes = need;
+        }
+        char *base = static_cast<char *>(c->mesh_ws);
+        for (auto &w : want) {
+            *w.first = base;
+            base += w.second;
+        }
+        return RC_OK;
+    }
+};
+
+}  // namespace
+
+rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_tsdf_opts *opts,
+                  float *out_phi, uint8_t *out_vtilde, void *stream)
+{
+    if (!c || !surf || !out_phi || !opts) return fail(RC_E_INVAL, "null argument");
+    TsdfGrid g;
+    rc_status st = make_tsdf_grid(grid, g);
+    if (st != RC_OK) return st;
+    const float sigma = opts->sigma_smooth, tau = opts->tau, r = opts->band;
+    if (!(sigma > 0.0f) || !isfinite(sigma)) return fail(RC_E_INVAL, "sigma_smooth must be finite and > 0");
+    if (!isfinite(tau)) return fail(RC_E_INVAL, "tau must be finite");
+    if (!(r > 0.0f) || !isfinite(r)) return fail(RC_E_INVAL, "band must be finite and > 0");
+    const double sv = (double)sigma / (double)g.hf;
+    const double nn = floor(2.0 * sv * sv + 0.5);
+    Binomial w;
+    memset(&w, 0, sizeof w);
+    w.n = nn < 1.0 ? 1 : (nn > kMaxBinomial ? kMaxBinomial + 1 : (int)nn);
+    if (w.n > kMaxBinomial) return fail(RC_E_INVAL, "sigma_smooth too large for the spacing (n > 10)");
+    for (int k = 0; k <= 2 * w.n; ++k) {   // C(2n, k)
+        uint64_t b = 1;
+        for (int q = 1; q <= k; ++q) b = b * (uint64_t)(2 * w.n - q + 1) / (uint64_t)q;
+        w.w[k] = (uint32_t)b;
+    }
+    const double thr_d = ceil((double)tau * ldexp(1.0, 6 * w.n));
+    const uint64_t thr = thr_d <= 0.0 ? 0ull : (uint64_t)thr_d;
+    const double shells_d = ceil((double)r / (double)g.hf);
+    if (shells_d > 250.0) return fail(RC_E_INVAL, "band / spacing above 250 shells");
+    const int shells = (int)shells_d;
+    if (c->mock) return fail(RC_E_STATE, "a mock context does not build TSDFs");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(c->mesh_mu);
+    Scratch ws(c);
+    uint32_t *a;
+    uint64_t *b;
+    uint8_t *vt = out_vtilde, *lab, *p;
+    int32_t *flag;
+    ws.take(&a, sizeof(uint32_t) * g.n);
+    ws.take(&b, sizeof(uint64_t) * g.n);
+    if (!vt) ws.take(&vt, g.n);
+    ws.take(&lab, g.n);
+    ws.take(&p, g.n);
+    ws.take(&flag, sizeof(int32_t));
+    st = ws.commit();
+    if (st != RC_OK) return st;
+    HIP_TRY(tsdf_smooth_launch(surf, a, b, vt, g, w, thr, s));
+    HIP_TRY(tsdf_flood_init_launch(vt, lab, g, s));
+    // rounds until one changes nothing (one flag read per round)
+    for (int64_t it = 0;; ++it) {
+        int32_t changed = 0;
+        HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+        HIP_TRY(tsdf_flood_round_launch(lab, g, flag, s));
+        HIP_TRY(hipMemcpyAsync(&changed, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (!changed) break;
+        if (it > g.n) return fail(RC_E_DEVICE, "outside labelling did not settle");
+    }
+    HIP_TRY(tsdf_shells_phi_launch(vt, lab, p, out_phi, g, shells, g.hf, r, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return RC_OK;
+}
+
+rc_status rc_marching_cubes(rc_ctx *c, const rc_grid *grid, const float *phi, float iso,
+                            float *out_verts, int32_t *out_tris, int64_t cap_verts,
+                            int64_t cap_tris, int64_t *n_verts, int64_t *n_tris, void *stream)
+{
+    if (!c || !phi || !n_verts || !n_tris) return fail(RC_E_INVAL, "null argument");
+    if (!isfinite(iso)) return fail(RC_E_INVAL, "iso must be finite");
+    if ((out_verts == nullptr) != (out_tris == nullptr))
+        return fail(RC_E_INVAL, "give both output arrays or neither");
+    TsdfGrid g;
+    rc_status st = make_tsdf_grid(grid, g);
+    if (st != RC_OK) return st;
+    // at most 3 vertices per lattice point and 5 triangles per cell: 32-bit
+    // counts and int32 vertex ids hold grids up to 2^29 voxels
+    if (g.n > ((int64_t)1 << 29)) return fail(RC_E_INVAL, "grid too large for 32-bit counts");
+    if (c->mock) return fail(RC_E_STATE, "a mock context does not extract meshes");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        if (!c->mc_table) {
+            uint8_t host[256 + 256 * 15];
+            mc_table_copy(host, reinterpret_cast<int8_t *>(host + 256));
+            st = dev_alloc(c, (void **)&c->mc_table, sizeof host);
+            if (st != RC_OK) return st;
+            HIP_TRY(hipMemcpy(c->mc_table, host, sizeof host, hipMemcpyHostToDevice));
+        }
+    }
+    const uint8_t *ntri = c->mc_table;
+    const int8_t *tris_of = reinterpret_cast<const int8_t *>(c->mc_table + 256);
+    std::lock_guard<std::mutex> lk(c->mesh_mu);
+    Scratch ws(c);
+    uint8_t *mask;
+    uint32_t *vc, *tc, *voff, *toff, *vs, *ts;
+    const int64_t ns = mc_scan_sums_len(g.n);
+    ws.take(&mask, g.n);
+    ws.take(&vc, sizeof(uint32_t) * g.n);
+    ws.take(&tc, sizeof(uint32_t) * g.n);
+    ws.take(&voff, sizeof(uint32_t) * g.n);
+    ws.take(&toff, sizeof(uint32_t) * g.n);
+    ws.take(&vs, sizeof(uint32_t) * ns);
+    ws.take(&ts, sizeof(uint32_t) * ns);
+    st = ws.commit();
+    if (st != RC_OK) return st;
+    HIP_TRY(mc_count_launch(phi, g, iso, ntri, mask, vc, tc, voff, toff, vs, ts, s));
+    uint32_t tot[2];
+    HIP_TRY(hipMemcpyAsync(&tot[0], vs + ns - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&tot[1], ts + ns - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_verts = tot[0];
+    *n_tris = tot[1];
+    if (!out_verts) return RC_OK;
+    if (cap_verts < (int64_t)tot[0] || cap_tris < (int64_t)tot[1])
+        return fail(RC_E_NOMEM, "mesh needs %u vertices and %u triangles", tot[0], tot[1]);
+    HIP_TRY(mc_emit_launch(phi, g, iso, ntri, tris_of, mask, voff, toff, out_verts, out_tris, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return RC_OK;
+}
+
+rc_status rc_marching_cubes_table(uint8_t *count, int8_t *tris)
+{
+    if (!count || !tris) return fail(RC_E_INVAL, "null argument");
+    mc_table_copy(count, tris);
     return RC_OK;
 }

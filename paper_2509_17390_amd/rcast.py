@@ -51,6 +51,7 @@ EXPORTED = [
     "rc_serve_start", "rc_serve_stop", "rc_serve_submit", "rc_serve_poll", "rc_serve_release",
     "rc_serve_copy", "rc_serve_get_stats", "rc_gauss_upload", "rc_gauss_build",
     "rc_gauss_release", "rc_voxelize", "rc_voxelize_counts", "rc_gauss_debug_copy",
+    "rc_tsdf", "rc_marching_cubes", "rc_marching_cubes_table",
 ]
 
 RC_DEVICE_MOCK = -1
@@ -129,6 +130,11 @@ class rc_grid(ctypes.Structure):
                 ("theta", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
 
 
+class rc_tsdf_opts(ctypes.Structure):
+    _fields_ = [("sigma_smooth", ctypes.c_float), ("tau", ctypes.c_float),
+                ("band", ctypes.c_float), ("reserved", ctypes.c_int32 * 5)]
+
+
 _lib = None
 
 
@@ -179,6 +185,10 @@ def load() -> ctypes.CDLL:
         "rc_voxelize": ([P, I32, ctypes.POINTER(rc_grid), P, P, P, P], S),
         "rc_voxelize_counts": ([P, I32, ctypes.POINTER(rc_grid), P, P], S),
         "rc_gauss_debug_copy": ([P, I32, I32, P, U64], S),
+        "rc_tsdf": ([P, ctypes.POINTER(rc_grid), P, ctypes.POINTER(rc_tsdf_opts), P, P, P], S),
+        "rc_marching_cubes": ([P, ctypes.POINTER(rc_grid), P, ctypes.c_float, P, P, I64, I64,
+                               ctypes.POINTER(I64), ctypes.POINTER(I64), P], S),
+        "rc_marching_cubes_table": ([P, P], S),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -388,6 +398,47 @@ class Context:
         _check(load().rc_gauss_debug_copy(self._h, gset, what, a.ctypes.data, a.nbytes))
         return a
 
+    def tsdf(self, grid: rc_grid, surf, out_phi, sigma_smooth: float, tau: float, band: float,
+             out_vtilde=None, stream=None):
+        """Narrow-band TSDF of a device uint8 surface mask into device float32
+        out_phi (both [nz, ny, nx]); synchronous."""
+        o = rc_tsdf_opts(float(sigma_smooth), float(tau), float(band))
+        _check(load().rc_tsdf(self._h, ctypes.byref(grid), _ptr(surf), ctypes.byref(o),
+                              _ptr(out_phi), 0 if out_vtilde is None else _ptr(out_vtilde),
+                              _stream_ptr(stream)))
+
+    def marching_cubes(self, grid: rc_grid, phi, iso: float = 0.0, stream=None):
+        """Mesh of a device float32 field: (verts [nv, 3] float32, tris [nt, 3]
+        int32) as torch cuda tensors."""
+        import torch
+        nv, nt = ctypes.c_int64(), ctypes.c_int64()
+        lib = load()
+        sp = _stream_ptr(stream)
+        dev = phi.device
+        cap_v, cap_t = getattr(self, "_mc_cap", (0, 0))
+        if cap_v and cap_t:
+            # the previous mesh's size (+10 %) as capacity: one pass if it fits
+            verts = torch.empty((cap_v, 3), dtype=torch.float32, device=dev)
+            tris = torch.empty((cap_t, 3), dtype=torch.int32, device=dev)
+            st = lib.rc_marching_cubes(self._h, ctypes.byref(grid), _ptr(phi), float(iso),
+                                       _ptr(verts), _ptr(tris), cap_v, cap_t,
+                                       ctypes.byref(nv), ctypes.byref(nt), sp)
+            if st == RC_OK:
+                return verts[:nv.value], tris[:nt.value]
+            if st != RC_E_NOMEM:
+                _check(st)
+        else:
+            _check(lib.rc_marching_cubes(self._h, ctypes.byref(grid), _ptr(phi), float(iso),
+                                         None, None, 0, 0, ctypes.byref(nv), ctypes.byref(nt),
+                                         sp))
+        self._mc_cap = (max(1, int(nv.value * 1.1) + 16), max(1, int(nt.value * 1.1) + 16))
+        verts = torch.empty((max(nv.value, 1), 3), dtype=torch.float32, device=dev)
+        tris = torch.empty((max(nt.value, 1), 3), dtype=torch.int32, device=dev)
+        _check(lib.rc_marching_cubes(self._h, ctypes.byref(grid), _ptr(phi), float(iso),
+                                     _ptr(verts), _ptr(tris), nv.value, nt.value,
+                                     ctypes.byref(nv), ctypes.byref(nt), sp))
+        return verts[:nv.value], tris[:nt.value]
+
     # -- patterns ------------------------------------------------------------
     def upload_pattern(self, dirs, n_az: int = 0) -> int:
         d = np.ascontiguousarray(dirs, np.float32).reshape(-1, 3)
@@ -531,3 +582,12 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def marching_cubes_table():
+    """The library's marching-cubes case table: (count uint8 [256], tris int8
+    [256, 15])."""
+    count = np.zeros(256, np.uint8)
+    tris = np.zeros((256, 15), np.int8)
+    _check(load().rc_marching_cubes_table(count.ctypes.data, tris.ctypes.data))
+    return count, tris

@@ -1,0 +1,167 @@
+"""Denoising, flood-fill sign, narrow-band TSDF and marching cubes on the GPU
+vs the oracle (oracle/tsdf.py), FGGS-LiDAR Sec. IV-B.
+
+Parity bar: every output is bit-exact.  V~ is decided on exact integer sums,
+the sign and shell indices are integer, phi is one float32 product and a
+clip, and the mesh vertices are the same float32 operations in the same
+order (t = (iso - phi_a) / (phi_b - phi_a), x = c_a + t h); vertex and
+triangle numbering is canonical.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import cuda, log
+from oracle import gauss as og
+from oracle import tsdf as ot
+from paper_2509_17390_amd import Context
+from paper_2509_17390_amd import rcast
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def gpu_tsdf(ctx, surf, origin, h, sigma, tau, band):
+    import torch
+    nz, ny, nx = surf.shape
+    g = ctx.grid(origin, h, (nx, ny, nz), 0.0)
+    phi = torch.full((nz, ny, nx), 7.0, dtype=torch.float32, device="cuda")
+    vt = torch.full((nz, ny, nx), 9, dtype=torch.uint8, device="cuda")
+    ctx.tsdf(g, cuda(surf), phi, sigma, tau, band, out_vtilde=vt)
+    torch.cuda.synchronize()
+    return phi.cpu().numpy(), vt.cpu().numpy(), g
+
+
+def check_tsdf(ctx, surf, origin, h, sigma, tau, band, tag=""):
+    phi_g, vt_g, g = gpu_tsdf(ctx, surf, origin, h, sigma, tau, band)
+    phi, vt, sgn, p = ot.tsdf(surf, h, sigma, tau, band)
+    np.testing.assert_array_equal(vt_g, vt)
+    np.testing.assert_array_equal(phi_g.view(np.uint32), phi.view(np.uint32))
+    log(f"{tag}: {surf.size} voxels, V~ {int(vt.sum())}, outside {int((sgn > 0).sum())}")
+    return phi_g, g
+
+
+def check_mc(ctx, phi, g, origin, h, iso, tag=""):
+    import torch
+    v, t = ctx.marching_cubes(g, cuda(phi), iso)
+    torch.cuda.synchronize()
+    v, t = v.cpu().numpy(), t.cpu().numpy()
+    vo, to = ot.marching_cubes(phi, origin, h, iso)
+    assert v.shape == vo.shape and t.shape == to.shape, (v.shape, vo.shape, t.shape, to.shape)
+    np.testing.assert_array_equal(v.view(np.uint32), vo.view(np.uint32))
+    np.testing.assert_array_equal(t, to)
+    log(f"{tag}: {len(v)} vertices, {len(t)} triangles")
+    return v, t
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_random_masks(ctx, seed):
+    rng = np.random.default_rng(seed)
+    surf = (rng.random((19, 23, 29)) < 0.15).astype(np.uint8)
+    for sigma, tau, band in ((0.02, 0.05, 0.06), (0.035, 0.2, 0.1), (0.01, 0.5, 0.02)):
+        phi, g = check_tsdf(ctx, surf, (0.1, -0.2, 0.3), 0.02, sigma, tau, band,
+                            tag=f"random {seed} sigma {sigma}")
+        check_mc(ctx, phi, g, (0.1, -0.2, 0.3), 0.02, 0.0, tag=f"random {seed} mc")
+
+
+def test_cavity_and_tunnel(ctx):
+    surf = np.zeros((20, 21, 22), np.uint8)
+    surf[3:17, 3:18, 3:19] = 1
+    surf[4:16, 4:17, 4:18] = 0                        # closed shell
+    phi, g = check_tsdf(ctx, surf, (0, 0, 0), 0.05, 0.001, 0.4, 0.2, tag="shell")
+    assert phi[10, 10, 10] < 0                        # the cavity is not outside
+    surf[10, 10, 3] = 0                               # a tunnel
+    phi2, _ = check_tsdf(ctx, surf, (0, 0, 0), 0.05, 0.001, 0.4, 0.2, tag="tunnel")
+    assert phi2[10, 10, 10] > 0
+
+
+def test_gaussian_surface_to_mesh(ctx):
+    """Surface mask from the Gaussian conversion of a region of the indoor
+    scene, then TSDF and marching cubes."""
+    import torch
+    m, q, s, a, room = synth.splat_scene(1, 200000)
+    lo = np.array([-0.1, 2.0, 0.9])
+    grid = og.Grid(lo, 0.02, (44, 40, 36), tile=8, theta=0.2)
+    hi = lo + 0.02 * np.array(grid.dims)
+    boxes = og.gauss_boxes(m, q, s, 3.0)
+    sel = np.all((boxes[:, :3] <= hi + 0.3) & (boxes[:, 3:] >= lo - 0.3), axis=1)
+    gset = ctx.upload_gaussians(m[sel], q[sel], s[sel], a[sel])
+    ctx.build_gaussians(gset)
+    nx, ny, nz = grid.dims
+    O = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda")
+    S = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda")
+    ctx.voxelize(gset, ctx.grid(lo, 0.02, grid.dims, 0.2), None, O, S)
+    torch.cuda.synchronize()
+    surf = S.cpu().numpy()
+    ctx.release_gaussians(gset)
+    phi, g = check_tsdf(ctx, surf, lo, 0.02, 0.02, 0.15, 0.06, tag="splat")
+    v, t = check_mc(ctx, phi, g, lo, 0.02, 0.0, tag="splat mc")
+    assert len(t) > 1000
+
+
+def test_sphere_field_and_exact_iso(ctx):
+    n = 31
+    iz, iy, ix = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    h = 0.1
+    X, Y, Z = (-1.5 + (ix + 0.5) * h, -1.5 + (iy + 0.5) * h, -1.5 + (iz + 0.5) * h)
+    phi = (np.sqrt(X ** 2 + Y ** 2 + Z ** 2) - 1.1).astype(np.float32)
+    import torch
+    g = ctx.grid((-1.5, -1.5, -1.5), h, (n, n, n), 0.0)
+    for iso in (0.0, 0.05, -0.2):
+        check_mc(ctx, phi, g, (-1.5, -1.5, -1.5), h, iso, tag=f"sphere iso {iso}")
+    q = np.round(phi * 10).astype(np.float32) / 10   # many corners exactly at iso
+    check_mc(ctx, q, g, (-1.5, -1.5, -1.5), h, 0.0, tag="sphere quantised")
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 2, 2), (1, 5, 7), (9, 1, 4)])
+def test_tiny_grids(ctx, dims):
+    rng = np.random.default_rng(sum(dims))
+    nx, ny, nz = dims
+    surf = (rng.random((nz, ny, nx)) < 0.5).astype(np.uint8)
+    phi, g = check_tsdf(ctx, surf, (0, 0, 0), 0.1, 0.1, 0.3, 0.3, tag=f"tiny {dims}")
+    check_mc(ctx, phi, g, (0, 0, 0), 0.1, 0.0, tag=f"tiny {dims} mc")
+
+
+def test_constant_fields_have_no_mesh(ctx):
+    import torch
+    g = ctx.grid((0, 0, 0), 0.1, (10, 11, 12), 0.0)
+    for val in (-1.0, 1.0, 0.0):
+        phi = torch.full((12, 11, 10), val, dtype=torch.float32, device="cuda")
+        v, t = ctx.marching_cubes(g, phi, 0.0)
+        assert v.shape[0] == 0 and t.shape[0] == 0
+
+
+def test_errors(ctx):
+    import torch
+    g = ctx.grid((0, 0, 0), 0.01, (8, 8, 8), 0.0)
+    surf = torch.zeros((8, 8, 8), dtype=torch.uint8, device="cuda")
+    phi = torch.zeros((8, 8, 8), dtype=torch.float32, device="cuda")
+    for sigma, tau, band in ((0.1, 0.5, 0.02), (0.01, 0.5, 3.0), (0.0, 0.5, 0.02),
+                             (0.01, float("nan"), 0.02), (0.01, 0.5, -1.0)):
+        with pytest.raises(rcast.RcastError) as e:
+            ctx.tsdf(g, surf, phi, sigma, tau, band)
+        assert e.value.status == rcast.RC_E_INVAL
+    # capacity too small: sizes are still reported
+    field = torch.ones((8, 8, 8), dtype=torch.float32, device="cuda")
+    field[3:5, 3:5, 3:5] = -1.0
+    import ctypes
+    lib = rcast.load()
+    nv, nt = ctypes.c_int64(), ctypes.c_int64()
+    V = torch.empty((1, 3), dtype=torch.float32, device="cuda")
+    T = torch.empty((1, 3), dtype=torch.int32, device="cuda")
+    st = lib.rc_marching_cubes(ctx._h, ctypes.byref(g), field.data_ptr(), 0.0, V.data_ptr(),
+                               T.data_ptr(), 1, 1, ctypes.byref(nv), ctypes.byref(nt),
+                               torch.cuda.current_stream().cuda_stream)
+    assert st == rcast.RC_E_NOMEM and nv.value > 1 and nt.value > 1
+    st = lib.rc_marching_cubes(ctx._h, ctypes.byref(g), field.data_ptr(), 0.0, V.data_ptr(),
+                               None, 1, 1, ctypes.byref(nv), ctypes.byref(nt),
+                               torch.cuda.current_stream().cuda_stream)
+    assert st == rcast.RC_E_INVAL
