@@ -495,6 +495,39 @@ rc_status rc_marching_cubes(rc_ctx *ctx, const rc_grid *grid, const float *phi, 
  * corner, ascending, with bit a clear to its neighbour along axis a). */
 rc_status rc_marching_cubes_table(uint8_t *count, int8_t *tris);
 
+/* ------------------------------------------------------------------------
+ * Point-cloud fidelity (Sec. V "Metrics"): between a simulated LiDAR cloud P
+ * and a ground-truth cloud G,
+ *   d(p, G) = min over g of |p - g| (Euclidean, FP64 from float32 points),
+ *   CD = (mean over P of d(p, G) + mean over G of d(g, P)) / 2,
+ *   precision = share of P with d(p, G) <= tau, recall = share of G with
+ *   d(g, P) <= tau, F = 2 precision recall / (precision + recall).
+ * Nearest neighbours are exact (an LBVH over the reference points, FP64
+ * distances, exact box pruning); ties go to the lowest reference index.
+ * ---------------------------------------------------------------------- */
+
+/* For every query point, the distance to and index of its nearest reference
+ * point.  ref_xyz, query_xyz: DEVICE float32 [n][3]; out_dist: DEVICE float64
+ * [n_query]; out_idx: DEVICE int32 [n_query].  n_ref = 0 gives +INFINITY and
+ * -1.  Synchronous; scratch is kept by the context.
+ * Errors: RC_E_INVAL, RC_E_NOMEM, RC_E_DEVICE. */
+rc_status rc_nearest(rc_ctx *ctx, const float *ref_xyz, int64_t n_ref, const float *query_xyz,
+                     int64_t n_query, double *out_dist, int32_t *out_idx, void *stream);
+
+typedef struct {
+    double chamfer;     /* CD, metres                                       */
+    double mean_pg;     /* mean over P of d(p, G)                           */
+    double mean_gp;     /* mean over G of d(g, P)                           */
+    double precision, recall, fscore;
+    int64_t n_p, n_g;
+} rc_fidelity;
+
+/* CD and F-score at `tau` (metres; the paper uses 0.05) of DEVICE float32
+ * clouds P [n_p][3] and G [n_g][3], both non-empty.  Synchronous.
+ * Errors: RC_E_INVAL, RC_E_NOMEM, RC_E_DEVICE. */
+rc_status rc_chamfer_fscore(rc_ctx *ctx, const float *p_xyz, int64_t n_p, const float *g_xyz,
+                            int64_t n_g, float tau, rc_fidelity *out, void *stream);
+
 /* Device id of a host-only context for rc_create: no HIP calls; scenes and
  * patterns hold their sizes only (rc_scene_upload needs host arrays);
  * rc_raycast_* report RC_E_STATE; the server runs requests on a simulated

@@ -108,3 +108,22 @@ hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const
 hipError_t mc_emit_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
                           const int8_t *tris_of, const uint8_t *mask, const uint32_t *voff,
                           const uint32_t *toff, float *verts, int32_t *tris, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Nearest neighbours and fidelity metrics (nn.hip).
+
+// Scratch of nearest_launch for a reference cloud of n_ref points (build
+// arrays, then the partial sums of metric_sums_launch at nn_metric_offset).
+size_t nn_scratch_bytes(int64_t n_ref);
+size_t nn_metric_offset(int64_t n_ref);
+// LBVH build workspace (BuildBuffers::ws) for n_ref points.
+size_t nn_workspace_bytes(int64_t n_ref);
+// d(q, ref) (FP64) and the lowest index of a nearest reference point for
+// every query; ref and query are float32 [n][3] on the device.
+hipError_t nearest_launch(const float *ref, int64_t n_ref, const float *query, int64_t n_q,
+                          double *out_d, int32_t *out_i, void *scratch, void *ws, size_t ws_bytes,
+                          hipStream_t s);
+// *out_sum = sum of d, *out_cnt = number of d <= tau (fixed summation order);
+// partial sums use the scratch at byte offset `off`.
+hipError_t metric_sums_launch(const double *d, int64_t n, double tau, void *scratch, size_t off,
+                              double *out_sum, unsigned long long *out_cnt, hipStream_t s);

@@ -523,3 +523,109 @@ rc_status rc_marching_cubes_table(uint8_t *count, int8_t *tris)
     mc_table_copy(count, tris);
     return RC_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Nearest neighbours and fidelity metrics (Sec. V).
+
+namespace {
+
+rc_status check_cloud(const float *p, int64_t n, const char *what)
+{
+    if (n < 0) return fail(RC_E_INVAL, "%s: negative size", what);
+    if (n > 0x7ffffffeLL) return fail(RC_E_INVAL, "%s: too many points", what);
+    if (n > 0 && !p) return fail(RC_E_INVAL, "%s: null array", what);
+    return RC_OK;
+}
+
+}  // namespace
+
+rc_status rc_nearest(rc_ctx *c, const float *ref, int64_t n_ref, const float *query,
+                     int64_t n_query, double *out_dist, int32_t *out_idx, void *stream)
+{
+    if (!c) return fail(RC_E_INVAL, "null context");
+    rc_status st = check_cloud(ref, n_ref, "reference");
+    if (st == RC_OK) st = check_cloud(query, n_query, "query");
+    if (st != RC_OK) return st;
+    if (n_query > 0 && (!out_dist || !out_idx)) return fail(RC_E_INVAL, "null output");
+    if (c->mock) return fail(RC_E_STATE, "a mock context does not search point clouds");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(c->mesh_mu);
+    Scratch ws(c);
+    char *scr;
+    ws.take(&scr, nn_scratch_bytes(n_ref));
+    st = ws.commit();
+    if (st != RC_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk2(c->mu);
+        st = ensure_build_ws(c, nn_workspace_bytes(n_ref), s);
+        if (st != RC_OK) return st;
+        HIP_TRY(nearest_launch(ref, n_ref, query, n_query, out_dist, out_idx, scr, c->ws,
+                               c->ws_bytes, s));
+        HIP_TRY(hipEventRecord(c->ws_event, s));
+        c->ws_event_recorded = true;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return RC_OK;
+}
+
+rc_status rc_chamfer_fscore(rc_ctx *c, const float *p, int64_t n_p, const float *g, int64_t n_g,
+                            float tau, rc_fidelity *out, void *stream)
+{
+    if (!c || !out) return fail(RC_E_INVAL, "null argument");
+    rc_status st = check_cloud(p, n_p, "P");
+    if (st == RC_OK) st = check_cloud(g, n_g, "G");
+    if (st != RC_OK) return st;
+    if (n_p == 0 || n_g == 0) return fail(RC_E_INVAL, "both clouds must hold points");
+    if (!(tau >= 0.0f) || !isfinite(tau)) return fail(RC_E_INVAL, "tau must be finite and >= 0");
+    if (c->mock) return fail(RC_E_STATE, "a mock context does not search point clouds");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(c->mesh_mu);
+    const size_t nn = nn_scratch_bytes(n_p) > nn_scratch_bytes(n_g) ? nn_scratch_bytes(n_p)
+                                                                      : nn_scratch_bytes(n_g);
+    Scratch ws(c);
+    char *scr;
+    double *dpg, *dgp, *sums;
+    int32_t *ipg, *igp;
+    unsigned long long *cnts;
+    ws.take(&scr, nn);
+    ws.take(&dpg, sizeof(double) * n_p);
+    ws.take(&ipg, sizeof(int32_t) * n_p);
+    ws.take(&dgp, sizeof(double) * n_g);
+    ws.take(&igp, sizeof(int32_t) * n_g);
+    ws.take(&sums, sizeof(double) * 2);
+    ws.take(&cnts, sizeof(unsigned long long) * 2);
+    st = ws.commit();
+    if (st != RC_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk2(c->mu);
+        const int64_t nmax = n_p > n_g ? n_p : n_g;
+        st = ensure_build_ws(c, nn_workspace_bytes(nmax), s);
+        if (st != RC_OK) return st;
+        HIP_TRY(nearest_launch(g, n_g, p, n_p, dpg, ipg, scr, c->ws, c->ws_bytes, s));
+        HIP_TRY(metric_sums_launch(dpg, n_p, (double)tau, scr, nn_metric_offset(n_g), &sums[0],
+                                   &cnts[0], s));
+        HIP_TRY(nearest_launch(p, n_p, g, n_g, dgp, igp, scr, c->ws, c->ws_bytes, s));
+        HIP_TRY(metric_sums_launch(dgp, n_g, (double)tau, scr, nn_metric_offset(n_p), &sums[1],
+                                   &cnts[1], s));
+        HIP_TRY(hipEventRecord(c->ws_event, s));
+        c->ws_event_recorded = true;
+    }
+    double hs[2];
+    unsigned long long hc[2];
+    HIP_TRY(hipMemcpyAsync(hs, sums, sizeof hs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hc, cnts, sizeof hc, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    memset(out, 0, sizeof *out);
+    out->n_p = n_p;
+    out->n_g = n_g;
+    out->mean_pg = hs[0] / (double)n_p;
+    out->mean_gp = hs[1] / (double)n_g;
+    out->chamfer = 0.5 * (out->mean_pg + out->mean_gp);
+    out->precision = (double)hc[0] / (double)n_p;
+    out->recall = (double)hc[1] / (double)n_g;
+    const double pr = out->precision + out->recall;
+    out->fscore = pr > 0.0 ? 2.0 * out->precision * out->recall / pr : 0.0;
+    return RC_OK;
+}

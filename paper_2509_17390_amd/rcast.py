@@ -51,7 +51,8 @@ EXPORTED = [
     "rc_serve_start", "rc_serve_stop", "rc_serve_submit", "rc_serve_poll", "rc_serve_release",
     "rc_serve_copy", "rc_serve_get_stats", "rc_gauss_upload", "rc_gauss_build",
     "rc_gauss_release", "rc_voxelize", "rc_voxelize_counts", "rc_gauss_debug_copy",
-    "rc_tsdf", "rc_marching_cubes", "rc_marching_cubes_table",
+    "rc_tsdf", "rc_marching_cubes", "rc_marching_cubes_table", "rc_nearest",
+    "rc_chamfer_fscore",
 ]
 
 RC_DEVICE_MOCK = -1
@@ -135,6 +136,16 @@ class rc_tsdf_opts(ctypes.Structure):
                 ("band", ctypes.c_float), ("reserved", ctypes.c_int32 * 5)]
 
 
+class rc_fidelity(ctypes.Structure):
+    _fields_ = [("chamfer", ctypes.c_double), ("mean_pg", ctypes.c_double),
+                ("mean_gp", ctypes.c_double), ("precision", ctypes.c_double),
+                ("recall", ctypes.c_double), ("fscore", ctypes.c_double),
+                ("n_p", ctypes.c_int64), ("n_g", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -189,6 +200,9 @@ def load() -> ctypes.CDLL:
         "rc_marching_cubes": ([P, ctypes.POINTER(rc_grid), P, ctypes.c_float, P, P, I64, I64,
                                ctypes.POINTER(I64), ctypes.POINTER(I64), P], S),
         "rc_marching_cubes_table": ([P, P], S),
+        "rc_nearest": ([P, P, I64, P, I64, P, P, P], S),
+        "rc_chamfer_fscore": ([P, P, I64, P, I64, ctypes.c_float, ctypes.POINTER(rc_fidelity),
+                               P], S),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -438,6 +452,27 @@ class Context:
                                      _ptr(verts), _ptr(tris), nv.value, nt.value,
                                      ctypes.byref(nv), ctypes.byref(nt), sp))
         return verts[:nv.value], tris[:nt.value]
+
+    # -- point-cloud fidelity --------------------------------------------------
+    def nearest(self, ref, query, stream=None):
+        """Nearest reference point of every query (device float32 [n, 3]
+        tensors): (distances float64, indices int32) as torch cuda tensors."""
+        import torch
+        n_q = int(query.shape[0])
+        d = torch.empty(max(n_q, 1), dtype=torch.float64, device=query.device)
+        i = torch.empty(max(n_q, 1), dtype=torch.int32, device=query.device)
+        _check(load().rc_nearest(self._h, _ptr(ref) if ref.shape[0] else None, int(ref.shape[0]),
+                                 _ptr(query) if n_q else None, n_q, _ptr(d), _ptr(i),
+                                 _stream_ptr(stream)))
+        return d[:n_q], i[:n_q]
+
+    def chamfer_fscore(self, P, G, tau: float = 0.05, stream=None) -> dict:
+        """CD and F-score of device float32 clouds P, G ([n, 3] tensors)."""
+        out = rc_fidelity()
+        _check(load().rc_chamfer_fscore(self._h, _ptr(P), int(P.shape[0]), _ptr(G),
+                                        int(G.shape[0]), float(tau), ctypes.byref(out),
+                                        _stream_ptr(stream)))
+        return out.as_dict()
 
     # -- patterns ------------------------------------------------------------
     def upload_pattern(self, dirs, n_az: int = 0) -> int:

@@ -37,6 +37,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(rcast.rc_gauss_opts) == 32
     assert ctypes.sizeof(rcast.rc_grid) == 48
     assert ctypes.sizeof(rcast.rc_tsdf_opts) == 32
+    assert ctypes.sizeof(rcast.rc_fidelity) == 64
 
 
 def test_error_path_without_device_is_clean():
