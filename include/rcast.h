@@ -528,6 +528,20 @@ typedef struct {
 rc_status rc_chamfer_fscore(rc_ctx *ctx, const float *p_xyz, int64_t n_p, const float *g_xyz,
                             int64_t n_g, float tau, rc_fidelity *out, void *stream);
 
+/* Taubin smoothing (Sec. IV-B "Mesh optimization"; the paper's defaults are
+ * lambda = 0.5, mu = -0.53), in place on the DEVICE float32 vertex array
+ * verts_xyz [n_verts][3] of the mesh tri_idx (DEVICE int32 [n_tris][3]).
+ * Each iteration moves every vertex by lambda, then by mu, times the
+ * umbrella operator (mean of its distinct edge neighbours minus itself);
+ * vertices on an edge of a single triangle and vertices without neighbours
+ * stay in place.  Float32, neighbours summed in ascending index order.
+ * Synchronous.  At most 32 triangles per vertex.
+ * Errors: RC_E_INVAL (sizes, indices, non-finite vertex or parameters,
+ * valence), RC_E_NOMEM, RC_E_DEVICE. */
+rc_status rc_taubin_smooth(rc_ctx *ctx, float *verts_xyz, int64_t n_verts, const int32_t *tri_idx,
+                           int64_t n_tris, float lambda, float mu, int32_t iterations,
+                           void *stream);
+
 /* Device id of a host-only context for rc_create: no HIP calls; scenes and
  * patterns hold their sizes only (rc_scene_upload needs host arrays);
  * rc_raycast_* report RC_E_STATE; the server runs requests on a simulated

@@ -127,3 +127,18 @@ hipError_t nearest_launch(const float *ref, int64_t n_ref, const float *query, i
 // partial sums use the scratch at byte offset `off`.
 hipError_t metric_sums_launch(const double *d, int64_t n, double tau, void *scratch, size_t off,
                               double *out_sum, unsigned long long *out_cnt, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Mesh optimisation (meshopt.hip).
+
+constexpr int kNbrCap = 64;   // neighbour slots per vertex (two per incident triangle)
+// Distinct sorted neighbours (slots [nv][kNbrCap], deg [nv]) and the fixed
+// flag (boundary or isolated) of every vertex; *flags |= 1 when a vertex
+// has more than kNbrCap neighbour slots.  cnt: [nv] scratch.
+hipError_t nbr_build_launch(const int32_t *tris, int64_t nt, int64_t nv, int32_t *slots,
+                            uint32_t *cnt, int32_t *deg, uint8_t *fixed, int32_t *flags,
+                            hipStream_t s);
+// `iterations` Taubin iterations in place (tmp: [nv][3] scratch).
+hipError_t taubin_launch(float *verts, float *tmp, const int32_t *slots, const int32_t *deg,
+                         const uint8_t *fixed, int64_t nv, float lambda, float mu, int iterations,
+                         hipStream_t s);

@@ -629,3 +629,49 @@ rc_status rc_chamfer_fscore(rc_ctx *c, const float *p, int64_t n_p, const float 
     out->fscore = pr > 0.0 ? 2.0 * out->precision * out->recall / pr : 0.0;
     return RC_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Mesh optimisation (Sec. IV-B).
+
+rc_status rc_taubin_smooth(rc_ctx *c, float *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                           float lambda, float mu, int32_t iterations, void *stream)
+{
+    if (!c) return fail(RC_E_INVAL, "null context");
+    if (nv < 0 || nt < 0) return fail(RC_E_INVAL, "negative sizes");
+    if (nv > 0x7ffffffeLL || nt > 0x7ffffffeLL) return fail(RC_E_INVAL, "mesh too large");
+    if ((nv > 0 && !verts) || (nt > 0 && !tris)) return fail(RC_E_INVAL, "null mesh array");
+    if (nt > 0 && nv == 0) return fail(RC_E_INVAL, "triangles without vertices");
+    if (!isfinite(lambda) || !isfinite(mu)) return fail(RC_E_INVAL, "lambda and mu must be finite");
+    if (iterations < 0 || iterations > 100000) return fail(RC_E_INVAL, "iterations out of range");
+    if (c->mock) return fail(RC_E_STATE, "a mock context does not smooth meshes");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(c->mesh_mu);
+    Scratch ws(c);
+    int32_t *slots, *deg, *flags;
+    uint32_t *cnt;
+    uint8_t *fixed;
+    float *tmp;
+    ws.take(&slots, sizeof(int32_t) * kNbrCap * (size_t)nv);
+    ws.take(&cnt, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&deg, sizeof(int32_t) * (size_t)nv);
+    ws.take(&fixed, (size_t)nv);
+    ws.take(&tmp, sizeof(float) * 3 * (size_t)nv);
+    ws.take(&flags, sizeof(int32_t));
+    rc_status st = ws.commit();
+    if (st != RC_OK) return st;
+    int32_t hf = 0;
+    HIP_TRY(hipMemsetAsync(flags, 0, sizeof(int32_t), s));
+    HIP_TRY(validate_mesh_launch(verts, nv, tris, nt, flags, s));
+    HIP_TRY(hipMemcpyAsync(&hf, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hf) return fail(RC_E_INVAL, "invalid mesh:%s%s", (hf & 1) ? " index out of range" : "",
+                        (hf & 2) ? " non-finite vertex" : "");
+    HIP_TRY(nbr_build_launch(tris, nt, nv, slots, cnt, deg, fixed, flags, s));
+    HIP_TRY(hipMemcpyAsync(&hf, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hf) return fail(RC_E_INVAL, "a vertex has more than %d incident triangle corners", kNbrCap / 2);
+    HIP_TRY(taubin_launch(verts, tmp, slots, deg, fixed, nv, lambda, mu, iterations, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return RC_OK;
+}

@@ -52,7 +52,7 @@ EXPORTED = [
     "rc_serve_copy", "rc_serve_get_stats", "rc_gauss_upload", "rc_gauss_build",
     "rc_gauss_release", "rc_voxelize", "rc_voxelize_counts", "rc_gauss_debug_copy",
     "rc_tsdf", "rc_marching_cubes", "rc_marching_cubes_table", "rc_nearest",
-    "rc_chamfer_fscore",
+    "rc_chamfer_fscore", "rc_taubin_smooth",
 ]
 
 RC_DEVICE_MOCK = -1
@@ -201,6 +201,7 @@ def load() -> ctypes.CDLL:
                                ctypes.POINTER(I64), ctypes.POINTER(I64), P], S),
         "rc_marching_cubes_table": ([P, P], S),
         "rc_nearest": ([P, P, I64, P, I64, P, P, P], S),
+        "rc_taubin_smooth": ([P, P, I64, P, I64, ctypes.c_float, ctypes.c_float, I32, P], S),
         "rc_chamfer_fscore": ([P, P, I64, P, I64, ctypes.c_float, ctypes.POINTER(rc_fidelity),
                                P], S),
     }
@@ -452,6 +453,15 @@ class Context:
                                      _ptr(verts), _ptr(tris), nv.value, nt.value,
                                      ctypes.byref(nv), ctypes.byref(nt), sp))
         return verts[:nv.value], tris[:nt.value]
+
+    # -- mesh optimisation -------------------------------------------------------
+    def taubin(self, verts, tris, lam: float = 0.5, mu: float = -0.53, iterations: int = 10,
+               stream=None):
+        """Taubin smoothing in place of a device float32 [nv, 3] vertex tensor."""
+        assert verts.is_cuda and verts.is_contiguous() and tris.is_cuda and tris.is_contiguous()
+        _check(load().rc_taubin_smooth(self._h, _ptr(verts), int(verts.shape[0]), _ptr(tris),
+                                       int(tris.shape[0]), float(lam), float(mu),
+                                       int(iterations), _stream_ptr(stream)))
 
     # -- point-cloud fidelity --------------------------------------------------
     def nearest(self, ref, query, stream=None):

@@ -1,0 +1,91 @@
+"""Taubin smoothing on the GPU vs the oracle (oracle/mesh.py), FGGS-LiDAR
+Sec. IV-B "Mesh optimization".  Parity bar: bit-exact vertex positions
+(both sides run the same float32 operations in the same order)."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import cuda, log
+from oracle import mesh as omesh
+from oracle import tsdf as ot
+from paper_2509_17390_amd import Context
+from paper_2509_17390_amd import rcast
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def check(ctx, v, t, lam=0.5, mu=-0.53, it=10, tag=""):
+    import torch
+    vd = cuda(v)
+    ctx.taubin(vd, cuda(t), lam, mu, it)
+    torch.cuda.synchronize()
+    got = vd.cpu().numpy()
+    want = omesh.taubin(v, t, lam, mu, it)
+    np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
+    log(f"{tag}: {len(v)} vertices, {len(t)} triangles, {it} iterations, bit-exact")
+    return got
+
+
+def test_noisy_sphere(ctx):
+    v, t = synth.uv_sphere((0.1, -0.2, 0.3), 1.0, 24, 16)   # poles: 24 triangles
+    rng = np.random.default_rng(1)
+    v = (v * (1 + 0.01 * rng.normal(size=(len(v), 1)))).astype(np.float32)
+    check(ctx, v, t, tag="sphere")
+
+
+def test_open_patch_keeps_its_boundary(ctx):
+    rng = np.random.default_rng(2)
+    n = 30
+    xs, ys = np.meshgrid(np.arange(n, dtype=float), np.arange(n, dtype=float), indexing="xy")
+    v = np.stack([xs.ravel(), ys.ravel(), 0.2 * rng.normal(size=n * n)], axis=1).astype(np.float32)
+    t = []
+    for j in range(n - 1):
+        for i in range(n - 1):
+            a, b, c, d = j * n + i, j * n + i + 1, (j + 1) * n + i, (j + 1) * n + i + 1
+            t += [[a, b, d], [a, d, c]]
+    t = np.array(t, np.int32)
+    out = check(ctx, v, t, it=7, tag="patch")
+    _, _, bnd = omesh.neighbours(len(v), t)
+    assert np.array_equal(out[bnd], v[bnd])
+
+
+def test_marching_cubes_mesh(ctx):
+    n, h = 40, 0.05
+    iz, iy, ix = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    X, Y, Z = ((ix + 0.5) * h - 1, (iy + 0.5) * h - 1, (iz + 0.5) * h - 1)
+    phi = (np.maximum(np.abs(X), np.maximum(np.abs(Y), np.abs(Z))) - 0.6).astype(np.float32)
+    v, t = ot.marching_cubes(phi, (-1, -1, -1), h, 0.0)
+    check(ctx, v, t, it=5, tag="marching-cubes cube")
+
+
+def test_degenerate_and_isolated(ctx):
+    v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0.5], [5, 5, 5]], np.float32)
+    t = np.array([[0, 1, 2], [1, 3, 2], [1, 1, 3]], np.int32)   # one repeated index
+    check(ctx, v, t, it=3, tag="degenerate")
+    check(ctx, v, t, it=0, tag="zero iterations")
+
+
+def test_errors(ctx):
+    import torch
+    v = torch.zeros((3, 3), dtype=torch.float32, device="cuda")
+    bad = torch.tensor([[0, 1, 3]], dtype=torch.int32, device="cuda")
+    with pytest.raises(rcast.RcastError) as e:
+        ctx.taubin(v, bad)
+    assert e.value.status == rcast.RC_E_INVAL
+    # valence above the limit: a fan of 40 triangles around vertex 0
+    k = 40
+    ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
+    vf = np.concatenate([[[0, 0, 0]], np.stack([np.cos(ang), np.sin(ang), 0 * ang], 1)]).astype(np.float32)
+    tf = np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)], np.int32)
+    with pytest.raises(rcast.RcastError) as e:
+        ctx.taubin(cuda(vf), cuda(tf))
+    assert e.value.status == rcast.RC_E_INVAL
