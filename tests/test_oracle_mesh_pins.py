@@ -81,3 +81,117 @@ def test_matches_a_sparse_matrix_route():
             x = x + f * (L @ x)
     out = omesh.taubin(v, t, 0.5, -0.53, 4)
     np.testing.assert_allclose(out, x, rtol=0, atol=2e-5)
+
+
+# ---- quadric-error decimation by vertex clustering ----------------------------
+
+def box_mesh(n=12, size=(2.0, 1.5, 1.0)):
+    """A closed box surface with sharp edges: each face an n x n grid of
+    quads split in two, vertices shared along the edges."""
+    index = {}
+    verts = []
+
+    def vid(p):
+        key = tuple(round(x * 1e6) for x in p)
+        if key not in index:
+            index[key] = len(verts)
+            verts.append(p)
+        return index[key]
+
+    tris = []
+    for axis in range(3):
+        u, w = (axis + 1) % 3, (axis + 2) % 3
+        for side in (0, 1):
+            g = [[None] * (n + 1) for _ in range(n + 1)]
+            for i in range(n + 1):
+                for j in range(n + 1):
+                    p = [0.0, 0.0, 0.0]
+                    p[axis] = side * size[axis]
+                    p[u] = size[u] * i / n
+                    p[w] = size[w] * j / n
+                    g[i][j] = vid(tuple(p))
+            for i in range(n):
+                for j in range(n):
+                    a_, b_, c_, d_ = g[i][j], g[i + 1][j], g[i + 1][j + 1], g[i][j + 1]
+                    if side == 1:
+                        tris += [[a_, b_, c_], [a_, c_, d_]]
+                    else:
+                        tris += [[a_, c_, b_], [a_, d_, c_]]
+    return np.array(verts, np.float32), np.array(tris, np.int32)
+
+
+def test_face_quadric_closed_form():
+    v = np.array([[0, 0, 0.5], [2, 0, 0.5], [0, 3, 0.5]], np.float32)
+    K = omesh.face_quadrics(v, [[0, 1, 2]])[0]
+    # plane z = 0.5: p = (0, 0, 1, -0.5), area 3
+    want = {(2, 2): 3.0, (2, 3): -1.5, (3, 3): 0.75}
+    for k, ij in enumerate(omesh.UPPER):
+        assert K[k] == pytest.approx(want.get(ij, 0.0), abs=1e-15)
+
+
+def test_vertex_quadrics_brute_force():
+    rng = np.random.default_rng(4)
+    v = rng.uniform(0, 1, (30, 3)).astype(np.float32)
+    t = rng.integers(0, 30, (60, 3))
+    K = omesh.face_quadrics(v, t)
+    Q = omesh.vertex_quadrics(30, t, K)
+    for i in range(30):
+        want = np.zeros(10)
+        for j in range(len(t)):
+            if i in set(t[j].tolist()):
+                want = want + K[j]
+        np.testing.assert_allclose(Q[i], want, rtol=1e-12, atol=1e-15)
+
+
+def test_ratio_one_keeps_the_mesh():
+    """Cells far smaller than the edges: every vertex is its own group and
+    stays where it is (its quadric's minimiser or, on flat parts, its own
+    position); only the numbering follows the cells."""
+    v, t = box_mesh(8)
+    dv, dt, c = omesh.decimate(v, t, 1.0)
+    assert len(dt) == len(t) and len(dv) == len(v)
+    key = lambda a: a[np.lexsort(a.T[::-1])]
+    np.testing.assert_allclose(key(dv.astype(np.float64)), key(v.astype(np.float64)), atol=1e-6)
+    # the same triangles, renumbered
+    tri_pts = lambda vv, tt: sorted(tuple(sorted(map(tuple, np.round(vv[x], 5).tolist()))) for x in tt)
+    assert tri_pts(dv, dt) == tri_pts(v, t)
+
+
+def test_box_corners_are_recovered_exactly():
+    """Quadric minimisers of corner groups sit on the box corners (three
+    planes meet there, the quadric has full rank); groups on one face or
+    along an edge fall back to their mean, which stays inside the box and
+    within a cell of its surface."""
+    v, t = box_mesh(12)
+    dv, dt, c = omesh.decimate(v, t, 0.1)
+    assert len(dt) <= int(0.1 * len(t))
+    lo, hi = v.min(axis=0).astype(np.float64), v.max(axis=0).astype(np.float64)
+    corners = np.array([[x, y, z] for x in (lo[0], hi[0]) for y in (lo[1], hi[1]) for z in (lo[2], hi[2])])
+    for cc in corners:
+        assert np.min(np.linalg.norm(dv.astype(np.float64) - cc, axis=1)) < 1e-6
+    d = dv.astype(np.float64)
+    assert np.all(d >= lo - 1e-6) and np.all(d <= hi + 1e-6)
+    off = np.min(np.abs(np.concatenate([d - lo, d - hi], axis=1)), axis=1)
+    assert np.all(off <= c)
+
+
+def test_boundary_vertices_are_protected():
+    v, t = grid_patch(20, jitter=0.05, seed=5)
+    dv, dt, c = omesh.decimate(v, t, 0.2)
+    _, _, bnd = omesh.neighbours(len(v), t)
+    kept = {tuple(p) for p in dv.tolist()}
+    for p in v[bnd].tolist():
+        assert tuple(p) in kept
+
+
+def test_sphere_keeps_its_radius():
+    from oracle import tsdf as ot
+    n, h = 50, 0.06
+    iz, iy, ix = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    X, Y, Z = ((ix + 0.5) * h - 1.5, (iy + 0.5) * h - 1.5, (iz + 0.5) * h - 1.5)
+    phi = (np.sqrt(X ** 2 + Y ** 2 + Z ** 2) - 1.0).astype(np.float32)
+    v, t = ot.marching_cubes(phi, (-1.5, -1.5, -1.5), h, 0.0)
+    dv, dt, c = omesh.decimate(v, t, 0.1)
+    assert len(dt) <= int(0.1 * len(t)) and len(dt) > 0.05 * len(t)
+    r = np.linalg.norm(dv.astype(np.float64), axis=1)
+    assert np.all(np.abs(r - 1.0) < 0.01)
