@@ -542,6 +542,25 @@ rc_status rc_taubin_smooth(rc_ctx *ctx, float *verts_xyz, int64_t n_verts, const
                            int64_t n_tris, float lambda, float mu, int32_t iterations,
                            void *stream);
 
+/* Quadric-error decimation (Sec. IV-B "Mesh optimization") by vertex
+ * clustering: vertices are grouped by a uniform grid of cell size c
+ * anchored at the mesh's box minimum (vertices on an edge of one triangle
+ * keep groups of their own); each group becomes one vertex at the minimiser
+ * of the sum of its vertices' quadrics (area-weighted planes of the
+ * incident triangles) when that is well posed and lies within the group's
+ * cell widened by one cell, else at its vertices' mean; triangles whose
+ * corners fall into three groups are kept in input order.  c is the
+ * smallest of a geometric bisection (24 steps, between extent / 1023 and
+ * the extent) whose face count is at most floor(ratio * n_tris).
+ * verts_xyz, tri_idx: DEVICE input mesh; out_verts (DEVICE float32
+ * [n_verts][3]) and out_tris (DEVICE int32 [n_tris][3]) receive the result
+ * (never larger than the input); sizes in *n_verts_out / *n_tris_out and
+ * the cell size in *cell_out (may be NULL).  Synchronous.  At most 32
+ * triangles per vertex.  Errors: RC_E_INVAL, RC_E_NOMEM, RC_E_DEVICE. */
+rc_status rc_decimate(rc_ctx *ctx, const float *verts_xyz, int64_t n_verts, const int32_t *tri_idx,
+                      int64_t n_tris, float ratio, float *out_verts, int32_t *out_tris,
+                      int64_t *n_verts_out, int64_t *n_tris_out, float *cell_out, void *stream);
+
 /* Device id of a host-only context for rc_create: no HIP calls; scenes and
  * patterns hold their sizes only (rc_scene_upload needs host arrays);
  * rc_raycast_* report RC_E_STATE; the server runs requests on a simulated

@@ -766,3 +766,33 @@ hipError_t lbvh_build_boxes_launch(const BuildBuffers &b, const float *boxes, hi
     if (b.trirecs) return hipErrorInvalidValue;
     return lbvh_build_any(b, boxes, s);
 }
+
+size_t radix_sort_ws_bytes(int64_t n)
+{
+    const int64_t nblocks = n > 0 ? (n + kTile - 1) / kTile : 1;
+    return align_up(sizeof(uint32_t) * kRadix * (size_t)nblocks) + align_up(sizeof(uint32_t) * kRadix);
+}
+
+hipError_t radix_sort_launch(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp,
+                             int64_t n, int key_bits, void *ws, hipStream_t s, int *in_tmp)
+{
+    *in_tmp = 0;
+    if (n <= 0) return hipSuccess;
+    const int64_t nblocks = (n + kTile - 1) / kTile;
+    uint32_t *hist = static_cast<uint32_t *>(ws);
+    uint32_t *digit_tot = reinterpret_cast<uint32_t *>(
+        static_cast<char *>(ws) + align_up(sizeof(uint32_t) * kRadix * (size_t)nblocks));
+    uint32_t *kin = keys, *kout = keys_tmp, *vin = vals, *vout = vals_tmp;
+    for (int shift = 0; shift < key_bits; shift += kRadixBits) {
+        hipLaunchKernelGGL(k_hist, dim3((unsigned)nblocks), dim3(kBlock), 0, s, kin, n, shift,
+                           hist, (int)nblocks);
+        hipLaunchKernelGGL(k_scan_digits, dim3(kRadix), dim3(kBlock), 0, s, hist, (int)nblocks,
+                           digit_tot);
+        hipLaunchKernelGGL(k_scatter, dim3((unsigned)nblocks), dim3(kBlock), 0, s, kin, vin,
+                           kout, vout, n, shift, hist, digit_tot, (int)nblocks);
+        uint32_t *t = kin; kin = kout; kout = t;
+        t = vin; vin = vout; vout = t;
+        *in_tmp ^= 1;
+    }
+    return hipGetLastError();
+}

@@ -142,3 +142,50 @@ hipError_t nbr_build_launch(const int32_t *tris, int64_t nt, int64_t nv, int32_t
 hipError_t taubin_launch(float *verts, float *tmp, const int32_t *slots, const int32_t *deg,
                          const uint8_t *fixed, int64_t nv, float lambda, float mu, int iterations,
                          hipStream_t s);
+
+// Stable LSD radix sort of (keys, vals) by the low key_bits bits of keys
+// (build.hip); *in_tmp = 1 when the result is in (keys_tmp, vals_tmp).
+size_t radix_sort_ws_bytes(int64_t n);
+hipError_t radix_sort_launch(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp,
+                             int64_t n, int key_bits, void *ws, hipStream_t s, int *in_tmp);
+// Exclusive scan of uint32 (tsdf.hip); sums holds mc_scan_sums_len(n)
+// entries, the grand total last.
+hipError_t scan_u32_launch(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *sums,
+                           hipStream_t s);
+
+// Quadric-error decimation by vertex clustering (meshopt.hip).
+constexpr uint32_t kBoundaryKey = 0x40000000u;   // above every cell key (cells < 2^30)
+// incident triangles of every vertex, distinct and ascending (slots
+// [nv][kNbrCap], tdeg [nv]); *flags |= 1 on overflow.  cnt: [nv] scratch.
+hipError_t tri_lists_launch(const int32_t *tris, int64_t nt, int64_t nv, int32_t *slots,
+                            uint32_t *cnt, int32_t *tdeg, int32_t *flags, hipStream_t s);
+// Q [nv][10] FP64: sum of the incident triangles' area-weighted plane quadrics.
+hipError_t vertex_quadrics_launch(const float *verts, const int32_t *tris, const int32_t *slots,
+                                  const int32_t *tdeg, int64_t nv, double *Q, hipStream_t s);
+// Box of the vertices: out[6] = lo xyz, hi xyz (partial: kMinmaxBlocks x 6 scratch).
+constexpr int kMinmaxBlocks = 256;
+hipError_t points_box_launch(const float *verts, int64_t nv, float *partial, float *out,
+                             hipStream_t s);
+// bnd[v] = 1 for vertices on an edge of one triangle (from nbr_build_launch).
+hipError_t boundary_flags_launch(const uint8_t *fixed, const int32_t *deg, int64_t nv,
+                                 uint8_t *bnd, hipStream_t s);
+// Cell key of every vertex (kBoundaryKey for boundary vertices), vals = index.
+hipError_t cell_keys_launch(const float *verts, int64_t nv, const uint8_t *boundary,
+                            const double *lo, double c, int64_t n0, int64_t n1, uint32_t *keys,
+                            uint32_t *vals, hipStream_t s);
+// From sorted (keys, vals): group-start flags, then (after a scan into gpos)
+// the group of every vertex and the first sorted position of every group.
+hipError_t group_flags_launch(const uint32_t *keys, int64_t nv, uint32_t *flag, hipStream_t s);
+hipError_t group_ids_launch(const uint32_t *vals, const uint32_t *flag, const uint32_t *gpos,
+                            int64_t nv, uint32_t *gid, uint32_t *gstart, hipStream_t s);
+// keep[t] = 1 when the three corners of t lie in three groups; used[g] = 1
+// for every group a kept triangle touches (used must be zeroed first).
+hipError_t keep_launch(const int32_t *tris, int64_t nt, const uint32_t *gid, uint32_t *keep,
+                       uint32_t *used, hipStream_t s);
+// Representatives of the used groups and the kept triangles, renumbered.
+hipError_t decimate_emit_launch(const float *verts, const double *Q, const uint8_t *boundary,
+                                const uint32_t *vals, const uint32_t *gstart, int64_t ngroups,
+                                int64_t nv, const uint32_t *used, const uint32_t *newid,
+                                const double *lo, double c, const int32_t *tris, int64_t nt,
+                                const uint32_t *gid, const uint32_t *keep, const uint32_t *tpos,
+                                float *out_verts, int32_t *out_tris, hipStream_t s);

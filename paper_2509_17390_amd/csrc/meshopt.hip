@@ -7,6 +7,8 @@
 //   an edge of a single triangle (the boundary) and vertices without
 //   neighbours stay in place.
 //
+// Decimation: quadric-error vertex clustering (see decimate_emit below).
+//
 // Neighbour lists: every triangle appends its two other corners to each
 // corner's slots (atomic slot counter, at most kNbrCap per vertex); each
 // vertex then sorts its slots, keeps distinct entries and marks itself
@@ -135,5 +137,389 @@ hipError_t taubin_launch(float *verts, float *tmp, const int32_t *slots, const i
         hipLaunchKernelGGL(k_umbrella, dim3(g), dim3(kBlock), 0, s, tmp, verts, slots, deg, fixed,
                            nv, mu);
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Quadric-error decimation by vertex clustering.
+//
+// Every vertex gets the sum Q of the area-weighted plane quadrics of its
+// incident triangles (ascending triangle index).  For a cell size c, the
+// vertices are keyed by their cell of a grid anchored at the mesh's box
+// minimum (boundary vertices, on an edge of one triangle, keep groups of
+// their own) and sorted stably by key, which puts every group's vertices
+// together in ascending index order; a triangle survives when its corners
+// lie in three groups.  Each surviving group becomes one vertex at the
+// minimiser of its summed quadric (Cramer's rule when the matrix is well
+// conditioned and the point stays within the group's cell widened by one
+// cell), else at its members' mean.  All sums run in fixed orders in FP64,
+// so the mesh is deterministic.
+namespace {
+
+__global__ __launch_bounds__(kBlock) void k_boundary_flags(const uint8_t *__restrict__ fixed,
+                                                           const int32_t *__restrict__ deg,
+                                                           int64_t nv, uint8_t *__restrict__ bnd)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v < nv) bnd[v] = (fixed[v] && deg[v] > 0) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_tri_fill(const int32_t *__restrict__ tris, int64_t nt,
+                                                     int32_t *__restrict__ slots,
+                                                     uint32_t *__restrict__ cnt,
+                                                     int32_t *__restrict__ flags)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nt) return;
+    const int32_t c[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
+    for (int k = 0; k < 3; ++k) {
+        if ((k > 0 && c[k] == c[0]) || (k > 1 && c[k] == c[1])) continue;   // distinct corners
+        const uint32_t at = atomicAdd(&cnt[c[k]], 1u);
+        if (at < (uint32_t)kNbrCap) slots[(int64_t)c[k] * kNbrCap + at] = (int32_t)t;
+        else atomicOr(flags, 1);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_tri_sort(int32_t *__restrict__ slots,
+                                                     const uint32_t *__restrict__ cnt, int64_t nv,
+                                                     int32_t *__restrict__ tdeg)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nv) return;
+    const int n = cnt[v] < (uint32_t)kNbrCap ? (int)cnt[v] : kNbrCap;
+    int32_t *s = slots + v * kNbrCap;
+    for (int k = 1; k < n; ++k) {
+        const int32_t x = s[k];
+        int j = k;
+        while (j > 0 && s[j - 1] > x) {
+            s[j] = s[j - 1];
+            --j;
+        }
+        s[j] = x;
+    }
+    tdeg[v] = n;
+}
+
+// area-weighted plane quadric of triangle t (upper triangle of the 4x4
+// matrix, row by row), in a fixed operation order
+__device__ void face_quadric(const float *__restrict__ verts, const int32_t *__restrict__ tris,
+                             int64_t t, double K[10])
+{
+    const int64_t ia = tris[3 * t], ib = tris[3 * t + 1], ic = tris[3 * t + 2];
+    const double ax = verts[3 * ia], ay = verts[3 * ia + 1], az = verts[3 * ia + 2];
+    const double e1x = (double)verts[3 * ib] - ax, e1y = (double)verts[3 * ib + 1] - ay,
+                 e1z = (double)verts[3 * ib + 2] - az;
+    const double e2x = (double)verts[3 * ic] - ax, e2y = (double)verts[3 * ic + 1] - ay,
+                 e2z = (double)verts[3 * ic + 2] - az;
+    const double nx = e1y * e2z - e1z * e2y;
+    const double ny = e1z * e2x - e1x * e2z;
+    const double nz = e1x * e2y - e1y * e2x;
+    const double ln = sqrt((nx * nx + ny * ny) + nz * nz);
+    if (!(ln > 0.0)) {
+        for (int k = 0; k < 10; ++k) K[k] = 0.0;
+        return;
+    }
+    const double ux = nx / ln, uy = ny / ln, uz = nz / ln;
+    const double d = -((ux * ax + uy * ay) + uz * az);
+    const double w = 0.5 * ln;
+    const double p[4] = {ux, uy, uz, d};
+    int k = 0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = i; j < 4; ++j) K[k++] = w * (p[i] * p[j]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_vertex_quadrics(const float *__restrict__ verts,
+                                                            const int32_t *__restrict__ tris,
+                                                            const int32_t *__restrict__ slots,
+                                                            const int32_t *__restrict__ tdeg,
+                                                            int64_t nv, double *__restrict__ Q)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nv) return;
+    double q[10];
+    for (int k = 0; k < 10; ++k) q[k] = 0.0;
+    const int n = tdeg[v];
+    for (int j = 0; j < n; ++j) {
+        double K[10];
+        face_quadric(verts, tris, slots[v * kNbrCap + j], K);
+        for (int k = 0; k < 10; ++k) q[k] = q[k] + K[k];
+    }
+    for (int k = 0; k < 10; ++k) Q[10 * v + k] = q[k];
+}
+
+__global__ __launch_bounds__(kBlock) void k_points_minmax(const float *__restrict__ verts,
+                                                          int64_t nv, float *__restrict__ partial)
+{
+    __shared__ float red[kBlock][6];
+    float acc[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nv;
+         i += (int64_t)gridDim.x * kBlock)
+        for (int a = 0; a < 3; ++a) {
+            acc[a] = fminf(acc[a], verts[3 * i + a]);
+            acc[3 + a] = fmaxf(acc[3 + a], verts[3 * i + a]);
+        }
+    for (int a = 0; a < 6; ++a) red[threadIdx.x][a] = acc[a];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int a = 0; a < 6; ++a)
+                red[threadIdx.x][a] = a < 3 ? fminf(red[threadIdx.x][a], red[threadIdx.x + w][a])
+                                            : fmaxf(red[threadIdx.x][a], red[threadIdx.x + w][a]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) partial[6 * blockIdx.x + threadIdx.x] = red[0][threadIdx.x];
+}
+
+__global__ void k_points_final(const float *__restrict__ partial, int nb, float *__restrict__ out)
+{
+    const int a = threadIdx.x;
+    if (a >= 6) return;
+    float v = partial[a];
+    for (int b = 1; b < nb; ++b) v = a < 3 ? fminf(v, partial[6 * b + a]) : fmaxf(v, partial[6 * b + a]);
+    out[a] = v;
+}
+
+__device__ __forceinline__ int64_t cell_of(double x, double lo, double c)
+{
+    return (int64_t)floor((x - lo) / c);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_keys(const float *__restrict__ verts, int64_t nv,
+                                                      const uint8_t *__restrict__ bnd,
+                                                      const double *__restrict__ lo, double c,
+                                                      int64_t n0, int64_t n1,
+                                                      uint32_t *__restrict__ keys,
+                                                      uint32_t *__restrict__ vals)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nv) return;
+    uint32_t key = kBoundaryKey;
+    if (!bnd[v]) {
+        const int64_t ix = cell_of(verts[3 * v], lo[0], c), iy = cell_of(verts[3 * v + 1], lo[1], c),
+                      iz = cell_of(verts[3 * v + 2], lo[2], c);
+        key = (uint32_t)(ix + n0 * (iy + n1 * iz));
+    }
+    keys[v] = key;
+    vals[v] = (uint32_t)v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_group_flags(const uint32_t *__restrict__ keys,
+                                                        int64_t nv, uint32_t *__restrict__ flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nv) return;
+    flag[i] = (i == 0 || keys[i] != keys[i - 1] || keys[i] == kBoundaryKey) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_group_ids(const uint32_t *__restrict__ vals,
+                                                      const uint32_t *__restrict__ flag,
+                                                      const uint32_t *__restrict__ gpos, int64_t nv,
+                                                      uint32_t *__restrict__ gid,
+                                                      uint32_t *__restrict__ gstart)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nv) return;
+    const uint32_t g = gpos[i] + flag[i] - 1u;
+    gid[vals[i]] = g;
+    if (flag[i]) gstart[g] = (uint32_t)i;
+    if (i == nv - 1) gstart[g + 1] = (uint32_t)nv;
+}
+
+__global__ __launch_bounds__(kBlock) void k_keep(const int32_t *__restrict__ tris, int64_t nt,
+                                                 const uint32_t *__restrict__ gid,
+                                                 uint32_t *__restrict__ keep,
+                                                 uint32_t *__restrict__ used)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nt) return;
+    const uint32_t a = gid[tris[3 * t]], b = gid[tris[3 * t + 1]], c = gid[tris[3 * t + 2]];
+    const bool k = a != b && b != c && a != c;
+    keep[t] = k ? 1u : 0u;
+    if (k) {
+        used[a] = 1u;
+        used[b] = 1u;
+        used[c] = 1u;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_emit_groups(const float *__restrict__ verts,
+                                                        const double *__restrict__ Q,
+                                                        const uint8_t *__restrict__ bnd,
+                                                        const uint32_t *__restrict__ vals,
+                                                        const uint32_t *__restrict__ gstart,
+                                                        int64_t ngroups,
+                                                        const uint32_t *__restrict__ used,
+                                                        const uint32_t *__restrict__ newid,
+                                                        const double *__restrict__ lo, double c,
+                                                        float *__restrict__ out)
+{
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= ngroups || !used[g]) return;
+    const uint32_t b = gstart[g], e = gstart[g + 1];
+    const int64_t v0 = vals[b];
+    float *o = out + 3 * (int64_t)newid[g];
+    if (bnd[v0]) {
+        o[0] = verts[3 * v0];
+        o[1] = verts[3 * v0 + 1];
+        o[2] = verts[3 * v0 + 2];
+        return;
+    }
+    double q[10];
+    for (int k = 0; k < 10; ++k) q[k] = 0.0;
+    for (uint32_t i = b; i < e; ++i) {
+        const int64_t v = vals[i];
+        for (int k = 0; k < 10; ++k) q[k] = q[k] + Q[10 * v + k];
+    }
+    const double a00 = q[0], a01 = q[1], a02 = q[2], b0 = -q[3];
+    const double a11 = q[4], a12 = q[5], b1 = -q[6];
+    const double a22 = q[7], b2 = -q[8];
+    const double det = a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) +
+                       a02 * (a01 * a12 - a11 * a02);
+    const double tr = (a00 + a11) + a22;
+    const double t3 = tr / 3.0;
+    if (tr > 0.0 && fabs(det) > 1e-6 * ((t3 * t3) * t3)) {
+        const double x0 = (b0 * (a11 * a22 - a12 * a12) - a01 * (b1 * a22 - a12 * b2) +
+                           a02 * (b1 * a12 - a11 * b2)) / det;
+        const double x1 = (a00 * (b1 * a22 - a12 * b2) - b0 * (a01 * a22 - a12 * a02) +
+                           a02 * (a01 * b2 - b1 * a02)) / det;
+        const double x2 = (a00 * (a11 * b2 - b1 * a12) - a01 * (a01 * b2 - b1 * a02) +
+                           b0 * (a01 * a12 - a11 * a02)) / det;
+        const double x[3] = {x0, x1, x2};
+        bool inside = true;
+        for (int a = 0; a < 3; ++a) {
+            const int64_t ci = cell_of(verts[3 * v0 + a], lo[a], c);
+            const double cmin = lo[a] + (double)(ci - 1) * c;
+            const double cmax = lo[a] + (double)(ci + 2) * c;
+            inside = inside && x[a] >= cmin && x[a] <= cmax;
+        }
+        if (inside) {
+            o[0] = (float)x0;
+            o[1] = (float)x1;
+            o[2] = (float)x2;
+            return;
+        }
+    }
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (uint32_t i = b; i < e; ++i) {
+        const int64_t v = vals[i];
+        sx = sx + (double)verts[3 * v];
+        sy = sy + (double)verts[3 * v + 1];
+        sz = sz + (double)verts[3 * v + 2];
+    }
+    const double m = (double)(e - b);
+    o[0] = (float)(sx / m);
+    o[1] = (float)(sy / m);
+    o[2] = (float)(sz / m);
+}
+
+__global__ __launch_bounds__(kBlock) void k_emit_tris(const int32_t *__restrict__ tris, int64_t nt,
+                                                      const uint32_t *__restrict__ gid,
+                                                      const uint32_t *__restrict__ keep,
+                                                      const uint32_t *__restrict__ tpos,
+                                                      const uint32_t *__restrict__ newid,
+                                                      int32_t *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nt || !keep[t]) return;
+    const int64_t p = tpos[t];
+    for (int k = 0; k < 3; ++k) out[3 * p + k] = (int32_t)newid[gid[tris[3 * t + k]]];
+}
+
+}  // namespace
+
+hipError_t tri_lists_launch(const int32_t *tris, int64_t nt, int64_t nv, int32_t *slots,
+                            uint32_t *cnt, int32_t *tdeg, int32_t *flags, hipStream_t s)
+{
+    if (nv == 0) return hipSuccess;
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * nv, s);
+    if (e != hipSuccess) return e;
+    if (nt > 0)
+        hipLaunchKernelGGL(k_tri_fill, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, s, tris, nt,
+                           slots, cnt, flags);
+    hipLaunchKernelGGL(k_tri_sort, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, slots, cnt, nv,
+                       tdeg);
+    return hipGetLastError();
+}
+
+hipError_t vertex_quadrics_launch(const float *verts, const int32_t *tris, const int32_t *slots,
+                                  const int32_t *tdeg, int64_t nv, double *Q, hipStream_t s)
+{
+    if (nv == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_vertex_quadrics, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, verts,
+                       tris, slots, tdeg, nv, Q);
+    return hipGetLastError();
+}
+
+hipError_t boundary_flags_launch(const uint8_t *fixed, const int32_t *deg, int64_t nv,
+                                 uint8_t *bnd, hipStream_t s)
+{
+    if (nv == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_boundary_flags, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, fixed,
+                       deg, nv, bnd);
+    return hipGetLastError();
+}
+
+hipError_t points_box_launch(const float *verts, int64_t nv, float *partial, float *out,
+                             hipStream_t s)
+{
+    const unsigned nb = grid_for(nv, kBlock) < (unsigned)kMinmaxBlocks ? grid_for(nv, kBlock)
+                                                                      : (unsigned)kMinmaxBlocks;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_points_minmax, dim3(nb), dim3(kBlock), 0, s, verts, nv, partial);
+    hipLaunchKernelGGL(k_points_final, dim3(1), dim3(64), 0, s, partial, (int)nb, out);
+    return hipGetLastError();
+}
+
+hipError_t cell_keys_launch(const float *verts, int64_t nv, const uint8_t *boundary,
+                            const double *lo, double c, int64_t n0, int64_t n1, uint32_t *keys,
+                            uint32_t *vals, hipStream_t s)
+{
+    if (nv == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cell_keys, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, verts, nv,
+                       boundary, lo, c, n0, n1, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t group_flags_launch(const uint32_t *keys, int64_t nv, uint32_t *flag, hipStream_t s)
+{
+    if (nv == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_group_flags, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, keys, nv,
+                       flag);
+    return hipGetLastError();
+}
+
+hipError_t group_ids_launch(const uint32_t *vals, const uint32_t *flag, const uint32_t *gpos,
+                            int64_t nv, uint32_t *gid, uint32_t *gstart, hipStream_t s)
+{
+    if (nv == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_group_ids, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, vals, flag,
+                       gpos, nv, gid, gstart);
+    return hipGetLastError();
+}
+
+hipError_t keep_launch(const int32_t *tris, int64_t nt, const uint32_t *gid, uint32_t *keep,
+                       uint32_t *used, hipStream_t s)
+{
+    if (nt == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keep, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, s, tris, nt, gid, keep,
+                       used);
+    return hipGetLastError();
+}
+
+hipError_t decimate_emit_launch(const float *verts, const double *Q, const uint8_t *boundary,
+                                const uint32_t *vals, const uint32_t *gstart, int64_t ngroups,
+                                int64_t nv, const uint32_t *used, const uint32_t *newid,
+                                const double *lo, double c, const int32_t *tris, int64_t nt,
+                                const uint32_t *gid, const uint32_t *keep, const uint32_t *tpos,
+                                float *out_verts, int32_t *out_tris, hipStream_t s)
+{
+    (void)nv;
+    if (ngroups > 0)
+        hipLaunchKernelGGL(k_emit_groups, dim3(grid_for(ngroups, kBlock)), dim3(kBlock), 0, s,
+                           verts, Q, boundary, vals, gstart, ngroups, used, newid, lo, c,
+                           out_verts);
+    if (nt > 0)
+        hipLaunchKernelGGL(k_emit_tris, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, s, tris, nt,
+                           gid, keep, tpos, newid, out_tris);
     return hipGetLastError();
 }

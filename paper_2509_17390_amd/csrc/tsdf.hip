@@ -580,3 +580,10 @@ hipError_t mc_emit_launch(const float *phi, const TsdfGrid &g, float iso, const 
                        ntri, tris_of, mask, voff, toff, verts, tris);
     return hipGetLastError();
 }
+
+hipError_t scan_u32_launch(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *sums,
+                           hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    return scan_launch(in, out, n, sums, s);
+}

@@ -675,3 +675,138 @@ rc_status rc_taubin_smooth(rc_ctx *c, float *verts, int64_t nv, const int32_t *t
     HIP_TRY(hipStreamSynchronize(s));
     return RC_OK;
 }
+
+rc_status rc_decimate(rc_ctx *c, const float *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                      float ratio, float *out_verts, int32_t *out_tris, int64_t *n_verts_out,
+                      int64_t *n_tris_out, float *cell_out, void *stream)
+{
+    if (!c || !n_verts_out || !n_tris_out) return fail(RC_E_INVAL, "null argument");
+    if (nv < 1 || nt < 1) return fail(RC_E_INVAL, "the mesh needs vertices and triangles");
+    if (nv > 0x7ffffffeLL || nt > 0x7ffffffeLL) return fail(RC_E_INVAL, "mesh too large");
+    if (!verts || !tris || !out_verts || !out_tris) return fail(RC_E_INVAL, "null mesh array");
+    if (!(ratio > 0.0f) || !isfinite(ratio)) return fail(RC_E_INVAL, "ratio must be finite and > 0");
+    if (c->mock) return fail(RC_E_STATE, "a mock context does not decimate meshes");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(c->mesh_mu);
+    Scratch ws(c);
+    int32_t *slots, *deg, *tdeg, *flags;
+    uint32_t *cnt, *keys, *vals, *keys2, *vals2, *flag, *gpos, *gid, *gstart, *keep, *tpos, *used,
+        *newid, *sums;
+    uint8_t *fixed, *bnd;
+    double *Q, *lo;
+    float *partial, *box;
+    char *sortws;
+    const size_t nss = (size_t)mc_scan_sums_len(nv > nt ? nv : nt);
+    ws.take(&slots, sizeof(int32_t) * kNbrCap * (size_t)nv);
+    ws.take(&cnt, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&deg, sizeof(int32_t) * (size_t)nv);
+    ws.take(&tdeg, sizeof(int32_t) * (size_t)nv);
+    ws.take(&fixed, (size_t)nv);
+    ws.take(&bnd, (size_t)nv);
+    ws.take(&Q, sizeof(double) * 10 * (size_t)nv);
+    ws.take(&keys, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&vals, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&keys2, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&vals2, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&flag, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&gpos, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&gid, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&gstart, sizeof(uint32_t) * ((size_t)nv + 1));
+    ws.take(&used, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&newid, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&keep, sizeof(uint32_t) * (size_t)nt);
+    ws.take(&tpos, sizeof(uint32_t) * (size_t)nt);
+    ws.take(&sums, sizeof(uint32_t) * nss);
+    ws.take(&partial, sizeof(float) * 6 * kMinmaxBlocks);
+    ws.take(&box, sizeof(float) * 8);
+    ws.take(&lo, sizeof(double) * 4);
+    ws.take(&sortws, radix_sort_ws_bytes(nv));
+    ws.take(&flags, sizeof(int32_t));
+    rc_status st = ws.commit();
+    if (st != RC_OK) return st;
+    int32_t hf = 0;
+    HIP_TRY(hipMemsetAsync(flags, 0, sizeof(int32_t), s));
+    HIP_TRY(validate_mesh_launch(verts, nv, tris, nt, flags, s));
+    HIP_TRY(hipMemcpyAsync(&hf, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hf) return fail(RC_E_INVAL, "invalid mesh:%s%s", (hf & 1) ? " index out of range" : "",
+                        (hf & 2) ? " non-finite vertex" : "");
+    // boundary vertices, per-vertex quadrics, box
+    HIP_TRY(nbr_build_launch(tris, nt, nv, slots, cnt, deg, fixed, flags, s));
+    HIP_TRY(boundary_flags_launch(fixed, deg, nv, bnd, s));
+    HIP_TRY(tri_lists_launch(tris, nt, nv, slots, cnt, tdeg, flags, s));
+    HIP_TRY(vertex_quadrics_launch(verts, tris, slots, tdeg, nv, Q, s));
+    HIP_TRY(points_box_launch(verts, nv, partial, box, s));
+    float hb[6];
+    HIP_TRY(hipMemcpyAsync(hb, box, sizeof hb, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&hf, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hf) return fail(RC_E_INVAL, "a vertex has more than %d incident triangles", kNbrCap / 2);
+    const double hlo[3] = {hb[0], hb[1], hb[2]};
+    HIP_TRY(hipMemcpyAsync(lo, hlo, sizeof hlo, hipMemcpyHostToDevice, s));
+    double ext = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double e = (double)hb[3 + a] - (double)hb[a];
+        if (e > ext) ext = e;
+    }
+    // one grouping at cell size cs: keys, stable sort, groups, kept triangles
+    int64_t ngroups = 0;
+    uint32_t *sk = keys, *sv = vals;
+    auto group = [&](double cs, int64_t *kept) -> rc_status {
+        int64_t n[3];
+        for (int a = 0; a < 3; ++a) n[a] = (int64_t)floor(((double)hb[3 + a] - (double)hb[a]) / cs) + 1;
+        if (n[0] * n[1] * n[2] > (int64_t)kBoundaryKey) return fail(RC_E_DEVICE, "cell grid too fine");
+        HIP_TRY(cell_keys_launch(verts, nv, bnd, lo, cs, n[0], n[1], keys, vals, s));
+        int in_tmp = 0;
+        HIP_TRY(radix_sort_launch(keys, vals, keys2, vals2, nv, 32, sortws, s, &in_tmp));
+        sk = in_tmp ? keys2 : keys;
+        sv = in_tmp ? vals2 : vals;
+        HIP_TRY(group_flags_launch(sk, nv, flag, s));
+        HIP_TRY(scan_u32_launch(flag, gpos, nv, sums, s));
+        HIP_TRY(group_ids_launch(sv, flag, gpos, nv, gid, gstart, s));
+        HIP_TRY(hipMemsetAsync(used, 0, sizeof(uint32_t) * nv, s));
+        HIP_TRY(keep_launch(tris, nt, gid, keep, used, s));
+        HIP_TRY(scan_u32_launch(keep, tpos, nt, sums, s));
+        uint32_t tot = 0;
+        HIP_TRY(hipMemcpyAsync(&tot, sums + mc_scan_sums_len(nt) - 1, sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, s));
+        uint32_t last_pos = 0, last_flag = 0;
+        HIP_TRY(hipMemcpyAsync(&last_pos, gpos + nv - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&last_flag, flag + nv - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        ngroups = (int64_t)last_pos + last_flag;
+        *kept = tot;
+        return RC_OK;
+    };
+    const int64_t target = (int64_t)floor((double)ratio * (double)nt);
+    double c_lo = ext / 1023.0, c_hi = ext, cs;
+    int64_t kept = 0;
+    st = group(c_lo, &kept);
+    if (st != RC_OK) return st;
+    if (kept <= target) {
+        cs = c_lo;
+    } else {
+        for (int it = 0; it < 24; ++it) {
+            const double mid = sqrt(c_lo * c_hi);
+            st = group(mid, &kept);
+            if (st != RC_OK) return st;
+            if (kept <= target) c_hi = mid;
+            else c_lo = mid;
+        }
+        cs = c_hi;
+    }
+    st = group(cs, &kept);
+    if (st != RC_OK) return st;
+    HIP_TRY(scan_u32_launch(used, newid, nv, sums, s));
+    uint32_t nused = 0;
+    HIP_TRY(hipMemcpyAsync(&nused, sums + mc_scan_sums_len(nv) - 1, sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(decimate_emit_launch(verts, Q, bnd, sv, gstart, ngroups, nv, used, newid, lo, cs, tris,
+                                 nt, gid, keep, tpos, out_verts, out_tris, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_verts_out = nused;
+    *n_tris_out = kept;
+    if (cell_out) *cell_out = (float)cs;
+    return RC_OK;
+}

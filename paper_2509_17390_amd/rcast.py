@@ -52,7 +52,7 @@ EXPORTED = [
     "rc_serve_copy", "rc_serve_get_stats", "rc_gauss_upload", "rc_gauss_build",
     "rc_gauss_release", "rc_voxelize", "rc_voxelize_counts", "rc_gauss_debug_copy",
     "rc_tsdf", "rc_marching_cubes", "rc_marching_cubes_table", "rc_nearest",
-    "rc_chamfer_fscore", "rc_taubin_smooth",
+    "rc_chamfer_fscore", "rc_taubin_smooth", "rc_decimate",
 ]
 
 RC_DEVICE_MOCK = -1
@@ -202,6 +202,8 @@ def load() -> ctypes.CDLL:
         "rc_marching_cubes_table": ([P, P], S),
         "rc_nearest": ([P, P, I64, P, I64, P, P, P], S),
         "rc_taubin_smooth": ([P, P, I64, P, I64, ctypes.c_float, ctypes.c_float, I32, P], S),
+        "rc_decimate": ([P, P, I64, P, I64, ctypes.c_float, P, P, ctypes.POINTER(I64),
+                         ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_float), P], S),
         "rc_chamfer_fscore": ([P, P, I64, P, I64, ctypes.c_float, ctypes.POINTER(rc_fidelity),
                                P], S),
     }
@@ -462,6 +464,18 @@ class Context:
         _check(load().rc_taubin_smooth(self._h, _ptr(verts), int(verts.shape[0]), _ptr(tris),
                                        int(tris.shape[0]), float(lam), float(mu),
                                        int(iterations), _stream_ptr(stream)))
+
+    def decimate(self, verts, tris, ratio: float = 0.1, stream=None):
+        """Quadric-error decimation of a device mesh: (verts, tris, cell size)."""
+        import torch
+        nv, nt = int(verts.shape[0]), int(tris.shape[0])
+        ov = torch.empty((nv, 3), dtype=torch.float32, device=verts.device)
+        ot_ = torch.empty((nt, 3), dtype=torch.int32, device=verts.device)
+        n_v, n_t, cell = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_float()
+        _check(load().rc_decimate(self._h, _ptr(verts), nv, _ptr(tris), nt, float(ratio),
+                                  _ptr(ov), _ptr(ot_), ctypes.byref(n_v), ctypes.byref(n_t),
+                                  ctypes.byref(cell), _stream_ptr(stream)))
+        return ov[:n_v.value], ot_[:n_t.value], cell.value
 
     # -- point-cloud fidelity --------------------------------------------------
     def nearest(self, ref, query, stream=None):

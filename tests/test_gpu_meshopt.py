@@ -89,3 +89,63 @@ def test_errors(ctx):
     with pytest.raises(rcast.RcastError) as e:
         ctx.taubin(cuda(vf), cuda(tf))
     assert e.value.status == rcast.RC_E_INVAL
+
+
+# ---- quadric-error decimation --------------------------------------------------
+
+def check_decimate(ctx, v, t, ratio, tag=""):
+    import torch
+    dv, dt, cell = ctx.decimate(cuda(v), cuda(t), ratio)
+    torch.cuda.synchronize()
+    dv, dt = dv.cpu().numpy(), dt.cpu().numpy()
+    ov, otr, oc = omesh.decimate(v, t, ratio)
+    assert np.float32(oc) == np.float32(cell), (oc, cell)
+    np.testing.assert_array_equal(dt, otr)
+    np.testing.assert_array_equal(dv.view(np.uint32), ov.view(np.uint32))
+    log(f"{tag}: {len(t)} -> {len(dt)} triangles, cell {cell:.4g}, bit-exact")
+    return dv, dt
+
+
+def mc_sphere(n=50, h=0.06):
+    iz, iy, ix = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    X, Y, Z = ((ix + 0.5) * h - 1.5, (iy + 0.5) * h - 1.5, (iz + 0.5) * h - 1.5)
+    phi = (np.sqrt(X ** 2 + Y ** 2 + Z ** 2) - 1.0).astype(np.float32)
+    return ot.marching_cubes(phi, (-1.5, -1.5, -1.5), h, 0.0)
+
+
+@pytest.mark.parametrize("ratio", [0.1, 0.3, 1.0])
+def test_decimate_sphere(ctx, ratio):
+    v, t = mc_sphere()
+    check_decimate(ctx, v, t, ratio, tag=f"sphere ratio {ratio}")
+
+
+def test_decimate_open_patch(ctx):
+    import sys
+    sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    from test_oracle_mesh_pins import box_mesh, grid_patch
+    v, t = grid_patch(25, jitter=0.05, seed=5)
+    check_decimate(ctx, v, t, 0.2, tag="patch")
+    v, t = box_mesh(16)
+    check_decimate(ctx, v, t, 0.1, tag="box")
+
+
+def test_decimate_then_smooth_a_tsdf_mesh(ctx):
+    rng = np.random.default_rng(3)
+    surf = (rng.random((30, 32, 34)) < 0.08).astype(np.uint8)
+    phi, vt, sgn, p = ot.tsdf(surf, 0.05, 0.05, 0.2, 0.15)
+    v, t = ot.marching_cubes(phi, (0, 0, 0), 0.05, 0.0)
+    dv, dt = check_decimate(ctx, v, t, 0.1, tag="tsdf mesh")
+    check(ctx, dv, dt, it=10, tag="tsdf mesh smoothed")
+
+
+def test_decimate_errors(ctx):
+    import torch
+    v = torch.zeros((3, 3), dtype=torch.float32, device="cuda")
+    t = torch.tensor([[0, 1, 5]], dtype=torch.int32, device="cuda")
+    with pytest.raises(rcast.RcastError) as e:
+        ctx.decimate(v, t, 0.1)
+    assert e.value.status == rcast.RC_E_INVAL
+    t = torch.tensor([[0, 1, 2]], dtype=torch.int32, device="cuda")
+    with pytest.raises(rcast.RcastError) as e:
+        ctx.decimate(v, t, 0.0)
+    assert e.value.status == rcast.RC_E_INVAL
