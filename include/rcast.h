@@ -550,7 +550,7 @@ rc_status rc_taubin_smooth(rc_ctx *ctx, float *verts_xyz, int64_t n_verts, const
  * incident triangles) when that is well posed and lies within the group's
  * cell widened by one cell, else at its vertices' mean; triangles whose
  * corners fall into three groups are kept in input order.  c is the
- * smallest of a geometric bisection (24 steps, between extent / 1023 and
+ * smallest of a geometric bisection (12 steps, between extent / 1023 and
  * the extent) whose face count is at most floor(ratio * n_tris).
  * verts_xyz, tri_idx: DEVICE input mesh; out_verts (DEVICE float32
  * [n_verts][3]) and out_tris (DEVICE int32 [n_tris][3]) receive the result

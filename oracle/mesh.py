@@ -83,7 +83,7 @@ def taubin(verts, tris, lam: float = 0.5, mu: float = -0.53, iterations: int = 1
 #       corners fall into three different groups are kept, in input order.
 #   D2  "Boundary protected": vertices on an edge of one triangle form
 #       groups of their own and keep their position.
-#   D3  The target face ratio sets c: geometric bisection (24 steps) of c
+#   D3  The target face ratio sets c: geometric bisection (12 steps) of c
 #       between extent / 1023 and the extent for the smallest tried c whose
 #       face count is at most floor(ratio * triangles).
 #   D4  Arithmetic: FP64 in the orders written below; positions rounded to
@@ -201,7 +201,7 @@ def decimate(verts, tris, ratio: float):
     if faces(c_lo) <= target:
         c = c_lo
     else:
-        for _ in range(24):
+        for _ in range(12):
             mid = float(np.sqrt(c_lo * c_hi))
             if faces(mid) <= target:
                 c_hi = mid

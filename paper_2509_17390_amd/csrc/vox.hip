@@ -787,7 +787,7 @@ rc_status rc_decimate(rc_ctx *c, const float *verts, int64_t nv, const int32_t *
     if (kept <= target) {
         cs = c_lo;
     } else {
-        for (int it = 0; it < 24; ++it) {
+        for (int it = 0; it < 12; ++it) {
             const double mid = sqrt(c_lo * c_hi);
             st = group(mid, &kept);
             if (st != RC_OK) return st;
