@@ -845,7 +845,8 @@ def run_mesh(args):
     """Occupancy to mesh (FGGS-LiDAR Sec. IV-B) on the surface mask of the
     Gaussian conversion workload (1M Gaussians, 510 x 410 x 160 voxels at
     2 cm, theta = 0.2): binomial smoothing (sigma 2 cm), tau = 0.15, outside
-    labelling, shells up to r = 6 cm, phi, then marching cubes at iso 0
+    labelling, shells up to r = 6 cm, phi, then marching cubes at iso 0 with
+    vertex normals
     (timed: the value); then decimation to 10 % and Taubin smoothing (timed
     apart); both meshes are uploaded, their BVHs built, a LiDAR frame cast
     and scored against the same frame on the ground-truth mesh (CD,
@@ -878,7 +879,7 @@ def run_mesh(args):
         t0 = time.perf_counter()
         ctx.tsdf(rg, S, phi, sigma, tau, band, out_vtilde=vt, stream=stream)
         t1 = time.perf_counter()
-        verts, tris = ctx.marching_cubes(rg, phi, 0.0, stream=stream)
+        verts, tris, _ = ctx.marching_cubes(rg, phi, 0.0, stream=stream, normals=True)
         t2 = time.perf_counter()
         return (t1 - t0) * 1e3, (t2 - t1) * 1e3, verts, tris
 
@@ -960,7 +961,8 @@ def run_mesh(args):
     P = int(np.ceil(float(np.float32(band)) / float(np.float32(grid.h))))
     per_vox = (sum(v for k, v in TSDF_PASS_BYTES.items() if k != "shell")
                + P * TSDF_PASS_BYTES["shell"])
-    alg_bytes = per_vox * n_vox + 12 * int(verts.shape[0]) + 12 * int(tris.shape[0])
+    # outputs: 12 B position + 12 B normal per vertex, 12 B per triangle
+    alg_bytes = per_vox * n_vox + 24 * int(verts.shape[0]) + 12 * int(tris.shape[0])
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     cpu = None
     if not args.no_cpu:
@@ -969,24 +971,39 @@ def run_mesh(args):
         sub = surf[40:104, 100:228, 150:278]            # 64 x 128 x 128 voxels
         t0 = time.perf_counter()
         phi_o, _, _, _ = ot.tsdf(sub, float(grid.h), sigma, tau, band)
-        vo, to = ot.marching_cubes(phi_o, (0, 0, 0), float(grid.h), 0.0)
+        vo, to, no = ot.marching_cubes(phi_o, (0, 0, 0), float(grid.h), 0.0, normals=True)
         dt = time.perf_counter() - t0
         sub_g = ctx.grid((0, 0, 0), float(grid.h), (128, 128, 64), 0.0)
         phi_g = torch.empty((64, 128, 128), dtype=torch.float32, device=dev)
         ctx.tsdf(sub_g, torch.from_numpy(np.ascontiguousarray(sub)).to(dev), phi_g, sigma, tau,
                  band)
-        vg, tg = ctx.marching_cubes(sub_g, phi_g, 0.0)
+        vg, tg, ng = ctx.marching_cubes(sub_g, phi_g, 0.0, normals=True)
         same = bool(np.array_equal(phi_g.cpu().numpy().view(np.uint32), phi_o.view(np.uint32))
                     and np.array_equal(vg.cpu().numpy().view(np.uint32), vo.view(np.uint32))
+                    and np.array_equal(ng.cpu().numpy().view(np.uint32), no.view(np.uint32))
                     and np.array_equal(tg.cpu().numpy(), to))
         from oracle import metrics as om
+        from oracle import mesh as omesh
         t0 = time.perf_counter()
         ocd = om.chamfer_fscore(pts_sim, pts_gt, 0.05)
         dt_m = time.perf_counter() - t0
+        # decimation + smoothing of the sub-grid's mesh, both sides
+        t0 = time.perf_counter()
+        dvo, dto, _ = omesh.decimate(vo, to, 0.1)
+        svo = omesh.taubin(dvo, dto, 0.5, -0.53, 10)
+        dt_d = time.perf_counter() - t0
+        dvg, dtg, _ = ctx.decimate(vg, tg, 0.1)
+        ctx.taubin(dvg, dtg, 0.5, -0.53, 10)
+        torch.cuda.synchronize()
+        same_opt = bool(np.array_equal(dtg.cpu().numpy(), dto)
+                        and np.array_equal(dvg.cpu().numpy().view(np.uint32), svo.view(np.uint32)))
         cpu = {"value": sub.size / dt / 1e6, "unit": "Mvoxels/s", "cores": 1, "kind": "oracle",
                "sample": f"a 128 x 128 x 64 sub-grid of the same surface mask, TSDF + marching "
                          f"cubes (numpy/scipy, one thread), {dt:.1f} s",
-               "gpu_agreement": {"bit_identical": same, "triangles": int(len(to))},
+               "gpu_agreement": {"bit_identical": same, "triangles": int(len(to)),
+                                 "decimate_smooth_bit_identical": same_opt,
+                                 "decimate_smooth_oracle_s": round(dt_d, 2),
+                                 "decimated_triangles": int(len(dto))},
                "fidelity_oracle": {"s": round(dt_m, 3), "chamfer": ocd[0], "fscore": ocd[5],
                                    "chamfer_rel_diff": abs(ocd[0] - fid["chamfer"]) / ocd[0],
                                    "fscore_equal": ocd[5] == fid["fscore"]}}

@@ -481,13 +481,20 @@ rc_status rc_tsdf(rc_ctx *ctx, const rc_grid *grid, const uint8_t *surf,
  * float32 [cap_verts][3]) and out_tris (DEVICE int32 [cap_tris][3]) given
  * and large enough, also writes the mesh; with both NULL only counts (call
  * once to size, once to fill; a capacity already large enough fills in one
- * call).  Synchronous.  Scratch of about 17 bytes per voxel is kept by the
- * context like rc_tsdf's.  Grids up to 2^29 voxels.
+ * call).  out_normals (DEVICE float32 [cap_verts][3], or NULL; needs
+ * out_verts) receives the unit vertex normals from the gradient of phi
+ * (Sec. IV-B isosurface extraction): per lattice point the central
+ * difference, one-sided on the grid's faces, interpolated along the
+ * vertex's edge like its position; they point toward growing phi, out of
+ * the solid; (0, 0, 0) where the gradient vanishes.  Synchronous.  Scratch
+ * of about 17 bytes per voxel is kept by the context like rc_tsdf's.  Grids
+ * up to 2^29 voxels.
  * Errors: RC_E_INVAL, RC_E_NOMEM (capacity too small: sizes still written),
  * RC_E_DEVICE. */
 rc_status rc_marching_cubes(rc_ctx *ctx, const rc_grid *grid, const float *phi, float iso,
-                            float *out_verts, int32_t *out_tris, int64_t cap_verts,
-                            int64_t cap_tris, int64_t *n_verts, int64_t *n_tris, void *stream);
+                            float *out_verts, int32_t *out_tris, float *out_normals,
+                            int64_t cap_verts, int64_t cap_tris, int64_t *n_verts,
+                            int64_t *n_tris, void *stream);
 
 /* The marching-cubes case table, HOST arrays: count[256] triangles per case
  * (corner k inside sets bit k; corner k = (k & 1, k >> 1 & 1, k >> 2 & 1))

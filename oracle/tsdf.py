@@ -51,6 +51,16 @@ notes):
       face (a diagonal lying on a face could overlap the neighbouring cell's
       triangles; every loop of the 256 cases has such a vertex).  Triangles
       face the outside region (phi >= iso).
+  T6  Vertex normals (Sec. IV-B: normals from the gradient of phi, pointing
+      outward): at every lattice point the gradient of phi in units of phi
+      per voxel, per axis the central difference (phi(+1) - phi(-1)) * 1/2,
+      one-sided (phi(1) - phi(0), phi(n-1) - phi(n-2)) on the grid's first
+      and last point, 0 on an axis of size 1.  A vertex at t on the edge from
+      a to b takes n = (1 - t) g_a + t g_b and returns n / |n| ((0, 0, 0) if
+      |n| = 0).  float32, one rounded operation at a time in this order:
+      w = 1 - t; n_k = w g_a,k + t g_b,k (two products, then the sum);
+      l = sqrt((n_x n_x + n_y n_y) + n_z n_z); n_k / l.  phi grows outward
+      (s = +1 outside), so the normals point out of the solid.
 """
 from __future__ import annotations
 
@@ -240,9 +250,30 @@ def tsdf(surf, h: float, sigma_m: float, tau: float, r: float):
     return phi, vt, sgn, p
 
 
-def marching_cubes(phi, origin, h: float, iso: float = 0.0):
+def lattice_gradient(phi):
+    """Gradient of phi at every lattice point, float32 [nz, ny, nx, 3] in
+    (x, y, z) order, phi per voxel (reading T6)."""
+    phi = np.asarray(phi, dtype=np.float32)
+    g = np.zeros(phi.shape + (3,), dtype=np.float32)
+    half = np.float32(0.5)
+    for a in range(3):
+        k = 2 - a                                   # array axis of x, y, z
+        n = phi.shape[k]
+        if n < 2:
+            continue
+        f = np.moveaxis(phi, k, 0)
+        d = np.zeros_like(f)
+        d[1:n - 1] = (f[2:] - f[:n - 2]) * half
+        d[0] = f[1] - f[0]
+        d[n - 1] = f[n - 1] - f[n - 2]
+        g[..., a] = np.moveaxis(d, 0, k)
+    return g
+
+
+def marching_cubes(phi, origin, h: float, iso: float = 0.0, normals: bool = False):
     """Mesh of phi at iso (reading T5): (verts float32 [nv, 3], tris int32
-    [nt, 3]) in the canonical numbering."""
+    [nt, 3]) in the canonical numbering; with normals=True also the vertex
+    normals float32 [nv, 3] (reading T6)."""
     phi = np.asarray(phi, dtype=np.float32)
     nz, ny, nx = phi.shape
     isof = np.float32(iso)
@@ -293,4 +324,15 @@ def marching_cubes(phi, origin, h: float, iso: float = 0.0):
                 ids.append(vid[c + dx + dy * nx + dz * nx * ny, axis])
             tris.append(ids)
     tris = np.array(tris, dtype=np.int32).reshape(-1, 3)
-    return verts, tris
+    if not normals:
+        return verts, tris
+    G = lattice_gradient(phi).reshape(-1, 3)
+    w = (np.float32(1.0) - t).astype(np.float32)
+    nrm = ((w[:, None] * G[pt]).astype(np.float32)
+           + (t[:, None] * G[pt + np.array(steps)[ax]]).astype(np.float32)).astype(np.float32)
+    l2 = ((nrm[:, 0] * nrm[:, 0] + nrm[:, 1] * nrm[:, 1]) + nrm[:, 2] * nrm[:, 2]).astype(np.float32)
+    ln = np.sqrt(l2).astype(np.float32)
+    ok = ln > 0
+    nrm[ok] = (nrm[ok] / ln[ok, None]).astype(np.float32)
+    nrm[~ok] = 0.0
+    return verts, tris, nrm

@@ -99,7 +99,8 @@ hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint8_t *lab, uint8_t
 
 // Marching cubes: the case table (count[256], tri[256][15] edge ids, -1
 // padded), the count pass with both exclusive scans (vsums / tsums hold
-// mc_scan_sums_len(n) entries, the grand total last), and the emit pass.
+// mc_scan_sums_len(n) entries, the grand total last), and the emit pass
+// (normals: float32 [nv][3] or null).
 void mc_table_copy(uint8_t *count, int8_t *tri);
 int64_t mc_scan_sums_len(int64_t n);
 hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
@@ -107,7 +108,8 @@ hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const
                            uint32_t *toff, uint32_t *vsums, uint32_t *tsums, hipStream_t s);
 hipError_t mc_emit_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
                           const int8_t *tris_of, const uint8_t *mask, const uint32_t *voff,
-                          const uint32_t *toff, float *verts, int32_t *tris, hipStream_t s);
+                          const uint32_t *toff, float *verts, int32_t *tris, float *normals,
+                          hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Nearest neighbours and fidelity metrics (nn.hip).

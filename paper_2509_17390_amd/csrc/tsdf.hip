@@ -263,6 +263,26 @@ __global__ __launch_bounds__(kBlock) void k_mc_count(const float *__restrict__ p
     tcount[i] = t;
 }
 
+// Gradient of phi at lattice point (x, y, z) along one axis, phi per voxel:
+// central difference halved inside, one-sided on the first and last point,
+// 0 on an axis of size 1.
+__device__ __forceinline__ float lattice_diff(const float *__restrict__ phi, int64_t i, int c,
+                                              int n, int64_t step)
+{
+    if (n < 2) return 0.0f;
+    if (c == 0) return __fsub_rn(phi[i + step], phi[i]);
+    if (c == n - 1) return __fsub_rn(phi[i], phi[i - step]);
+    return __fmul_rn(__fsub_rn(phi[i + step], phi[i - step]), 0.5f);
+}
+
+__device__ __forceinline__ void lattice_grad(const float *__restrict__ phi, const TsdfGrid &g,
+                                             int64_t i, int x, int y, int z, float out[3])
+{
+    out[0] = lattice_diff(phi, i, x, g.nx, 1);
+    out[1] = lattice_diff(phi, i, y, g.ny, g.nx);
+    out[2] = lattice_diff(phi, i, z, g.nz, (int64_t)g.nx * g.ny);
+}
+
 __global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ phi, TsdfGrid g,
                                                     float iso, const uint8_t *__restrict__ ntri,
                                                     const int8_t *__restrict__ tris_of,
@@ -270,7 +290,8 @@ __global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ ph
                                                     const uint32_t *__restrict__ voff,
                                                     const uint32_t *__restrict__ toff,
                                                     float *__restrict__ verts,
-                                                    int32_t *__restrict__ tris)
+                                                    int32_t *__restrict__ tris,
+                                                    float *__restrict__ normals)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= g.n) return;
@@ -294,6 +315,25 @@ __global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ ph
             verts[3 * (int64_t)v + 0] = p[0];
             verts[3 * (int64_t)v + 1] = p[1];
             verts[3 * (int64_t)v + 2] = p[2];
+            if (normals) {
+                // n = (1 - t) g_a + t g_b, normalised; float32, one rounded
+                // operation at a time
+                float ga[3], gb[3];
+                lattice_grad(phi, g, i, x, y, z, ga);
+                lattice_grad(phi, g, i + step[a], x + (a == 0), y + (a == 1), z + (a == 2), gb);
+                const float w = __fsub_rn(1.0f, t);
+                float nv[3];
+                for (int k = 0; k < 3; ++k)
+                    nv[k] = __fadd_rn(__fmul_rn(w, ga[k]), __fmul_rn(t, gb[k]));
+                const float l2 = __fadd_rn(__fadd_rn(__fmul_rn(nv[0], nv[0]), __fmul_rn(nv[1], nv[1])),
+                                           __fmul_rn(nv[2], nv[2]));
+                // correctly rounded float32 square root: the FP64 root
+                // rounded to float32 (53 >= 2 * 24 + 2 bits, so the double
+                // rounding is exact); v_sqrt_f32 alone is not exact
+                const float l = (float)sqrt((double)l2);
+                for (int k = 0; k < 3; ++k)
+                    normals[3 * (int64_t)v + k] = l > 0.0f ? __fdiv_rn(nv[k], l) : 0.0f;
+            }
             ++v;
         }
     }
@@ -574,10 +614,11 @@ hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const
 
 hipError_t mc_emit_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
                           const int8_t *tris_of, const uint8_t *mask, const uint32_t *voff,
-                          const uint32_t *toff, float *verts, int32_t *tris, hipStream_t s)
+                          const uint32_t *toff, float *verts, int32_t *tris, float *normals,
+                          hipStream_t s)
 {
     hipLaunchKernelGGL(k_mc_emit, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, phi, g, iso,
-                       ntri, tris_of, mask, voff, toff, verts, tris);
+                       ntri, tris_of, mask, voff, toff, verts, tris, normals);
     return hipGetLastError();
 }
 

@@ -460,13 +460,15 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
 }
 
 rc_status rc_marching_cubes(rc_ctx *c, const rc_grid *grid, const float *phi, float iso,
-                            float *out_verts, int32_t *out_tris, int64_t cap_verts,
-                            int64_t cap_tris, int64_t *n_verts, int64_t *n_tris, void *stream)
+                            float *out_verts, int32_t *out_tris, float *out_normals,
+                            int64_t cap_verts, int64_t cap_tris, int64_t *n_verts,
+                            int64_t *n_tris, void *stream)
 {
     if (!c || !phi || !n_verts || !n_tris) return fail(RC_E_INVAL, "null argument");
     if (!isfinite(iso)) return fail(RC_E_INVAL, "iso must be finite");
     if ((out_verts == nullptr) != (out_tris == nullptr))
         return fail(RC_E_INVAL, "give both output arrays or neither");
+    if (out_normals && !out_verts) return fail(RC_E_INVAL, "normals need the vertex array");
     TsdfGrid g;
     rc_status st = make_tsdf_grid(grid, g);
     if (st != RC_OK) return st;
@@ -512,7 +514,8 @@ rc_status rc_marching_cubes(rc_ctx *c, const rc_grid *grid, const float *phi, fl
     if (!out_verts) return RC_OK;
     if (cap_verts < (int64_t)tot[0] || cap_tris < (int64_t)tot[1])
         return fail(RC_E_NOMEM, "mesh needs %u vertices and %u triangles", tot[0], tot[1]);
-    HIP_TRY(mc_emit_launch(phi, g, iso, ntri, tris_of, mask, voff, toff, out_verts, out_tris, s));
+    HIP_TRY(mc_emit_launch(phi, g, iso, ntri, tris_of, mask, voff, toff, out_verts, out_tris,
+                           out_normals, s));
     HIP_TRY(hipStreamSynchronize(s));
     return RC_OK;
 }

@@ -197,7 +197,7 @@ def load() -> ctypes.CDLL:
         "rc_voxelize_counts": ([P, I32, ctypes.POINTER(rc_grid), P, P], S),
         "rc_gauss_debug_copy": ([P, I32, I32, P, U64], S),
         "rc_tsdf": ([P, ctypes.POINTER(rc_grid), P, ctypes.POINTER(rc_tsdf_opts), P, P, P], S),
-        "rc_marching_cubes": ([P, ctypes.POINTER(rc_grid), P, ctypes.c_float, P, P, I64, I64,
+        "rc_marching_cubes": ([P, ctypes.POINTER(rc_grid), P, ctypes.c_float, P, P, P, I64, I64,
                                ctypes.POINTER(I64), ctypes.POINTER(I64), P], S),
         "rc_marching_cubes_table": ([P, P], S),
         "rc_nearest": ([P, P, I64, P, I64, P, P, P], S),
@@ -424,37 +424,43 @@ class Context:
                               _ptr(out_phi), 0 if out_vtilde is None else _ptr(out_vtilde),
                               _stream_ptr(stream)))
 
-    def marching_cubes(self, grid: rc_grid, phi, iso: float = 0.0, stream=None):
+    def marching_cubes(self, grid: rc_grid, phi, iso: float = 0.0, stream=None,
+                       normals: bool = False):
         """Mesh of a device float32 field: (verts [nv, 3] float32, tris [nt, 3]
-        int32) as torch cuda tensors."""
+        int32) as torch cuda tensors; with normals=True also the unit vertex
+        normals [nv, 3] float32 from the gradient of phi."""
         import torch
         nv, nt = ctypes.c_int64(), ctypes.c_int64()
         lib = load()
         sp = _stream_ptr(stream)
         dev = phi.device
+
+        def fill(cv, ct):
+            verts = torch.empty((cv, 3), dtype=torch.float32, device=dev)
+            tris = torch.empty((ct, 3), dtype=torch.int32, device=dev)
+            nrm = torch.empty((cv, 3), dtype=torch.float32, device=dev) if normals else None
+            st = lib.rc_marching_cubes(self._h, ctypes.byref(grid), _ptr(phi), float(iso),
+                                       _ptr(verts), _ptr(tris), _ptr(nrm) if normals else None,
+                                       cv, ct, ctypes.byref(nv), ctypes.byref(nt), sp)
+            out = (verts[:nv.value], tris[:nt.value])
+            return st, (out + (nrm[:nv.value],) if normals else out)
+
         cap_v, cap_t = getattr(self, "_mc_cap", (0, 0))
         if cap_v and cap_t:
             # the previous mesh's size (+10 %) as capacity: one pass if it fits
-            verts = torch.empty((cap_v, 3), dtype=torch.float32, device=dev)
-            tris = torch.empty((cap_t, 3), dtype=torch.int32, device=dev)
-            st = lib.rc_marching_cubes(self._h, ctypes.byref(grid), _ptr(phi), float(iso),
-                                       _ptr(verts), _ptr(tris), cap_v, cap_t,
-                                       ctypes.byref(nv), ctypes.byref(nt), sp)
+            st, out = fill(cap_v, cap_t)
             if st == RC_OK:
-                return verts[:nv.value], tris[:nt.value]
+                return out
             if st != RC_E_NOMEM:
                 _check(st)
         else:
             _check(lib.rc_marching_cubes(self._h, ctypes.byref(grid), _ptr(phi), float(iso),
-                                         None, None, 0, 0, ctypes.byref(nv), ctypes.byref(nt),
-                                         sp))
+                                         None, None, None, 0, 0, ctypes.byref(nv),
+                                         ctypes.byref(nt), sp))
         self._mc_cap = (max(1, int(nv.value * 1.1) + 16), max(1, int(nt.value * 1.1) + 16))
-        verts = torch.empty((max(nv.value, 1), 3), dtype=torch.float32, device=dev)
-        tris = torch.empty((max(nt.value, 1), 3), dtype=torch.int32, device=dev)
-        _check(lib.rc_marching_cubes(self._h, ctypes.byref(grid), _ptr(phi), float(iso),
-                                     _ptr(verts), _ptr(tris), nv.value, nt.value,
-                                     ctypes.byref(nv), ctypes.byref(nt), sp))
-        return verts[:nv.value], tris[:nt.value]
+        st, out = fill(max(nv.value, 1), max(nt.value, 1))
+        _check(st)
+        return out
 
     # -- mesh optimisation -------------------------------------------------------
     def taubin(self, verts, tris, lam: float = 0.5, mu: float = -0.53, iterations: int = 10,

@@ -5,7 +5,9 @@ Parity bar: every output is bit-exact.  V~ is decided on exact integer sums,
 the sign and shell indices are integer, phi is one float32 product and a
 clip, and the mesh vertices are the same float32 operations in the same
 order (t = (iso - phi_a) / (phi_b - phi_a), x = c_a + t h); vertex and
-triangle numbering is canonical.
+triangle numbering is canonical.  Vertex normals are float32 central /
+one-sided differences interpolated with the same t, one rounded operation
+at a time on both sides.
 """
 import numpy as np
 import pytest
@@ -50,15 +52,19 @@ def check_tsdf(ctx, surf, origin, h, sigma, tau, band, tag=""):
 
 
 def check_mc(ctx, phi, g, origin, h, iso, tag=""):
+    """Mesh without normals, then with them: bit-exact both times."""
     import torch
-    v, t = ctx.marching_cubes(g, cuda(phi), iso)
-    torch.cuda.synchronize()
-    v, t = v.cpu().numpy(), t.cpu().numpy()
-    vo, to = ot.marching_cubes(phi, origin, h, iso)
-    assert v.shape == vo.shape and t.shape == to.shape, (v.shape, vo.shape, t.shape, to.shape)
-    np.testing.assert_array_equal(v.view(np.uint32), vo.view(np.uint32))
-    np.testing.assert_array_equal(t, to)
-    log(f"{tag}: {len(v)} vertices, {len(t)} triangles")
+    vo, to, no = ot.marching_cubes(phi, origin, h, iso, normals=True)
+    for with_n in (False, True):
+        out = ctx.marching_cubes(g, cuda(phi), iso, normals=with_n)
+        torch.cuda.synchronize()
+        v, t = out[0].cpu().numpy(), out[1].cpu().numpy()
+        assert v.shape == vo.shape and t.shape == to.shape, (v.shape, vo.shape, t.shape, to.shape)
+        np.testing.assert_array_equal(v.view(np.uint32), vo.view(np.uint32))
+        np.testing.assert_array_equal(t, to)
+        if with_n:
+            np.testing.assert_array_equal(out[2].cpu().numpy().view(np.uint32), no.view(np.uint32))
+    log(f"{tag}: {len(v)} vertices, {len(t)} triangles, normals equal")
     return v, t
 
 
@@ -158,10 +164,10 @@ def test_errors(ctx):
     V = torch.empty((1, 3), dtype=torch.float32, device="cuda")
     T = torch.empty((1, 3), dtype=torch.int32, device="cuda")
     st = lib.rc_marching_cubes(ctx._h, ctypes.byref(g), field.data_ptr(), 0.0, V.data_ptr(),
-                               T.data_ptr(), 1, 1, ctypes.byref(nv), ctypes.byref(nt),
+                               T.data_ptr(), None, 1, 1, ctypes.byref(nv), ctypes.byref(nt),
                                torch.cuda.current_stream().cuda_stream)
     assert st == rcast.RC_E_NOMEM and nv.value > 1 and nt.value > 1
     st = lib.rc_marching_cubes(ctx._h, ctypes.byref(g), field.data_ptr(), 0.0, V.data_ptr(),
-                               None, 1, 1, ctypes.byref(nv), ctypes.byref(nt),
+                               None, None, 1, 1, ctypes.byref(nv), ctypes.byref(nt),
                                torch.cuda.current_stream().cuda_stream)
     assert st == rcast.RC_E_INVAL

@@ -200,3 +200,96 @@ def test_half_space_tsdf_closed_form():
                    -np.float32(0.35), np.float32(0.35)).astype(np.float32)
     np.testing.assert_array_equal(phi, want)
     assert np.array_equal(sgn == 1, x <= 9)
+
+
+def _crossed_edges_brute(phi, iso=0.0):
+    """(lattice point (x, y, z), axis) of every crossed edge, in the vertex
+    numbering order (point z-major, then axis), by plain loops."""
+    nz, ny, nx = phi.shape
+    out = []
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                for a, (dx, dy, dz) in enumerate(((1, 0, 0), (0, 1, 0), (0, 0, 1))):
+                    X, Y, Z = x + dx, y + dy, z + dz
+                    if X >= nx or Y >= ny or Z >= nz:
+                        continue
+                    if (phi[z, y, x] < iso) != (phi[Z, Y, X] < iso):
+                        out.append(((x, y, z), (X, Y, Z)))
+    return out
+
+
+def test_normals_match_numpy_gradient_interpolated_along_the_edge():
+    """Random smooth field (boundary vertices included): the normal is the
+    FP64 interpolation of numpy's gradient (central inside, one-sided on the
+    grid's faces) at the edge's two lattice points, normalised."""
+    rng = np.random.default_rng(11)
+    for trial in range(4):
+        base = rng.normal(size=(7, 8, 9))
+        phi = ndimage.uniform_filter(base, 3).astype(np.float32) * 3.0
+        v, t, nrm = ot.marching_cubes(phi, (0.1, -0.2, 0.3), 0.25, 0.0, normals=True)
+        p64 = phi.astype(np.float64)
+        gz, gy, gx = np.gradient(p64)
+        edges = _crossed_edges_brute(phi)
+        assert len(edges) == len(v) > 50
+        for k, ((x, y, z), (X, Y, Z)) in enumerate(edges):
+            fa, fb = p64[z, y, x], p64[Z, Y, X]
+            tt = (0.0 - fa) / (fb - fa)
+            ga = np.array([gx[z, y, x], gy[z, y, x], gz[z, y, x]])
+            gb = np.array([gx[Z, Y, X], gy[Z, Y, X], gz[Z, Y, X]])
+            n = (1.0 - tt) * ga + tt * gb
+            n /= np.linalg.norm(n)
+            np.testing.assert_allclose(nrm[k], n, atol=2e-5, err_msg=f"{trial} {k}")
+
+
+def test_normals_of_a_linear_field_are_its_direction():
+    """phi = a . x + b: every normal equals a / |a| (central and one-sided
+    differences of a linear field agree)."""
+    n = (6, 7, 8)
+    iz, iy, ix = np.meshgrid(*(np.arange(k) for k in n), indexing="ij")
+    a = np.array([0.3, -0.5, 0.8])
+    phi = (a[0] * ix + a[1] * iy + a[2] * iz - 4.1).astype(np.float32)
+    v, t, nrm = ot.marching_cubes(phi, (0, 0, 0), 1.0, 0.0, normals=True)
+    assert len(v) > 20
+    np.testing.assert_allclose(nrm, np.broadcast_to(a / np.linalg.norm(a), nrm.shape), atol=2e-6)
+
+
+def test_sphere_normals_are_radial_and_agree_with_the_winding():
+    """phi = |x - c| - R: vertex normals within 1 degree of the radius, and
+    every vertex normal on the outward side of its incident triangles."""
+    h, R, n = 0.1, 1.3, 34
+    o = (-1.7, -1.7, -1.7)
+    iz, iy, ix = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    c = np.array([0.013, -0.021, 0.034])
+    X, Y, Z = (o[k] + (g + 0.5) * h - c[k] for k, g in enumerate((ix, iy, iz)))
+    phi = (np.sqrt(X ** 2 + Y ** 2 + Z ** 2) - R).astype(np.float32)
+    v, t, nrm = ot.marching_cubes(phi, o, h, 0.0, normals=True)
+    r = v.astype(np.float64) - c
+    r /= np.linalg.norm(r, axis=1, keepdims=True)
+    assert np.min(np.sum(r * nrm, axis=1)) > math.cos(math.radians(1.0))
+    np.testing.assert_allclose(np.linalg.norm(nrm.astype(np.float64), axis=1), 1.0, atol=1e-6)
+    a, b, cc = (v[t[:, k]].astype(np.float64) for k in range(3))
+    fn = np.cross(b - a, cc - a)
+    for k in range(3):
+        assert np.all(np.sum(fn * nrm[t[:, k]], axis=1) > 0)
+
+
+def test_normals_on_an_axis_of_size_one_and_at_a_flat_point():
+    """One z layer: no cells, the x/y vertices still get normals with z = 0.
+    A vertex where the interpolated gradient vanishes gets (0, 0, 0)."""
+    phi = np.array([[[-1.0, 1.0], [-1.0, 1.0]]], dtype=np.float32)
+    v, t, nrm = ot.marching_cubes(phi, (0, 0, 0), 1.0, 0.0, normals=True)
+    assert len(t) == 0 and len(v) == 2
+    np.testing.assert_array_equal(nrm, np.array([[1, 0, 0], [1, 0, 0]], np.float32))
+    # x profile -1, 1, -1: on the first edge the gradients are 2 (one-sided)
+    # and 0 (central); on the second 0 and -2
+    phi2 = np.array([[[-1.0, 1.0, -1.0]]], dtype=np.float32)
+    v2, _, n2 = ot.marching_cubes(phi2, (0, 0, 0), 1.0, 0.0, normals=True)
+    np.testing.assert_array_equal(n2, np.array([[1, 0, 0], [-1, 0, 0]], np.float32))
+    phi4 = np.array([[[1.0, -1.0, 1.0, -1.0, 1.0]]], dtype=np.float32)
+    v4, _, n4 = ot.marching_cubes(phi4, (0, 0, 0), 1.0, 0.0, normals=True)
+    # interior central differences are 0: the edge (1, 2) has g = (0, 0)
+    # at both ends
+    assert len(v4) == 4
+    np.testing.assert_array_equal(n4[1], np.zeros(3, np.float32))
+    np.testing.assert_array_equal(n4[0], np.array([-1, 0, 0], np.float32))
