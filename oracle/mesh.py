@@ -231,3 +231,53 @@ def decimate(verts, tris, ratio: float):
     out_v = np.array(out_v, dtype=np.float64).reshape(-1, 3).astype(np.float32)
     out_t = newid[gid[kt]].astype(np.int32)
     return out_v, out_t, c
+
+
+# ---------------------------------------------------------------------------
+# Removal of tiny components
+#
+# Sec. IV-B removes tiny components while decimating.  Readings (also in the
+# design notes):
+#   D5  Two triangles are connected when they share a vertex; a component is
+#       a class of the transitive closure, labelled by its lowest vertex
+#       index.  Components with fewer than min_faces triangles are removed
+#       (a component of exactly min_faces is kept).  The remaining triangles
+#       keep their input order; the vertices they reference keep their input
+#       order and are numbered densely, and vertices no triangle references
+#       are dropped.
+
+
+def component_labels(nv: int, tris):
+    """Lowest vertex index of each vertex's component in the graph whose
+    edges are the triangle sides (scipy's connected components as the
+    primitive); a vertex in no triangle is its own component."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    t = np.asarray(tris, dtype=np.int64).reshape(-1, 3)
+    if nv == 0:
+        return np.zeros(0, dtype=np.int64)
+    rows = np.concatenate([t[:, 0], t[:, 1], t[:, 2]])
+    cols = np.concatenate([t[:, 1], t[:, 2], t[:, 0]])
+    g = coo_matrix((np.ones(len(rows)), (rows, cols)), shape=(nv, nv))
+    ncomp, lab = connected_components(g, directed=False)
+    lowest = np.full(ncomp, nv, dtype=np.int64)
+    np.minimum.at(lowest, lab, np.arange(nv))
+    return lowest[lab]
+
+
+def remove_small_components(verts, tris, min_faces: int):
+    """(verts float32 [n, 3], tris int32 [m, 3], vertex labels [nv]) after
+    dropping the components of fewer than min_faces triangles (reading D5)."""
+    v = np.asarray(verts, dtype=np.float32).reshape(-1, 3)
+    t = np.asarray(tris, dtype=np.int64).reshape(-1, 3)
+    nv = len(v)
+    labels = component_labels(nv, t)
+    if len(t) == 0:
+        return np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32), labels
+    faces = np.bincount(labels[t[:, 0]], minlength=nv)
+    keep = faces[labels[t[:, 0]]] >= min_faces
+    kt = t[keep]
+    used = np.zeros(nv, dtype=bool)
+    used[kt.ravel()] = True
+    newid = np.cumsum(used) - 1
+    return v[used].copy(), newid[kt].astype(np.int32).reshape(-1, 3), labels

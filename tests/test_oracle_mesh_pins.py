@@ -195,3 +195,99 @@ def test_sphere_keeps_its_radius():
     assert len(dt) <= int(0.1 * len(t)) and len(dt) > 0.05 * len(t)
     r = np.linalg.norm(dv.astype(np.float64), axis=1)
     assert np.all(np.abs(r - 1.0) < 0.01)
+
+
+# ---- removal of tiny components (reading D5) -------------------------------
+
+def _components_brute(nv, tris):
+    """Triangle components by breadth-first search over 'shares a vertex',
+    then each vertex's label = lowest vertex of its component (its own index
+    when no triangle uses it)."""
+    t = [tuple(int(x) for x in r) for r in np.asarray(tris).reshape(-1, 3)]
+    by_vertex = {}
+    for i, tri in enumerate(t):
+        for v in tri:
+            by_vertex.setdefault(v, []).append(i)
+    comp = [-1] * len(t)
+    labels = list(range(nv))
+    for s in range(len(t)):
+        if comp[s] >= 0:
+            continue
+        comp[s] = s
+        queue, members = [s], [s]
+        while queue:
+            i = queue.pop()
+            for v in t[i]:
+                for j in by_vertex[v]:
+                    if comp[j] < 0:
+                        comp[j] = s
+                        queue.append(j)
+                        members.append(j)
+        verts = {v for i in members for v in t[i]}
+        low = min(verts)
+        for v in verts:
+            labels[v] = low
+    sizes = {}
+    for i in range(len(t)):
+        sizes[comp[i]] = sizes.get(comp[i], 0) + 1
+    return np.array(labels), [sizes[comp[i]] for i in range(len(t))]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_components_match_breadth_first_search(seed):
+    rng = np.random.default_rng(seed)
+    nv = int(rng.integers(5, 120))
+    nt = int(rng.integers(1, 80))
+    # sparse soups: many small components, some repeated corners
+    tris = rng.integers(0, nv, size=(nt, 3))
+    verts = rng.random((nv, 3)).astype(np.float32)
+    labels, size_of = _components_brute(nv, tris)
+    np.testing.assert_array_equal(omesh.component_labels(nv, tris), labels)
+    for k in (0, 1, 2, 3, 5, 1000):
+        keep = np.array(size_of) >= k
+        used = np.zeros(nv, bool)
+        used[tris[keep].ravel()] = True
+        ids = np.cumsum(used) - 1
+        v, t, _ = omesh.remove_small_components(verts, tris, k)
+        np.testing.assert_array_equal(v, verts[used])
+        np.testing.assert_array_equal(t, ids[tris[keep]])
+
+
+def test_components_closed_form():
+    """Two closed boxes (n = 3 and 2: 108 and 48 faces), a bow-tie (two
+    triangles sharing one vertex: one component) and a lone triangle."""
+    va, ta = box_mesh(3)
+    vb, tb = box_mesh(2, (0.5, 0.5, 0.5))
+    vb = vb + np.float32(5.0)
+    tb = tb + len(va)
+    o = len(va) + len(vb)
+    vc = np.random.default_rng(0).random((8, 3)).astype(np.float32) + 9
+    tc = np.array([[0, 1, 2], [2, 3, 4], [5, 6, 7]]) + o
+    verts = np.concatenate([va, vb, vc])
+    tris = np.concatenate([ta, tb, tc]).astype(np.int32)
+    assert len(ta) == 108 and len(tb) == 48
+    lab = omesh.component_labels(len(verts), tris)
+    assert set(lab[:len(va)]) == {0} and set(lab[len(va):o]) == {len(va)}
+    assert set(lab[o:o + 5]) == {o} and set(lab[o + 5:]) == {o + 5}
+    for k, nt_kept, nv_kept in ((1, 159, len(verts)), (2, 158, len(verts) - 3),
+                                (3, 156, len(va) + len(vb)), (48, 156, len(va) + len(vb)),
+                                (49, 108, len(va)), (108, 108, len(va)), (109, 0, 0)):
+        v, t, _ = omesh.remove_small_components(verts, tris, k)
+        assert (len(t), len(v)) == (nt_kept, nv_kept), k
+    # kept triangles in input order, renumbered onto the kept vertices
+    v, t, _ = omesh.remove_small_components(verts, tris, 49)
+    np.testing.assert_array_equal(t, ta)
+    np.testing.assert_array_equal(v, va)
+
+
+def test_components_drop_unreferenced_vertices_and_handle_empty_meshes():
+    verts = np.arange(18, dtype=np.float32).reshape(6, 3)
+    tris = np.array([[1, 3, 5]])
+    v, t, lab = omesh.remove_small_components(verts, tris, 0)
+    np.testing.assert_array_equal(v, verts[[1, 3, 5]])
+    np.testing.assert_array_equal(t, [[0, 1, 2]])
+    assert list(lab) == [0, 1, 2, 1, 4, 1]
+    v, t, lab = omesh.remove_small_components(verts, np.zeros((0, 3), int), 1)
+    assert v.shape == (0, 3) and t.shape == (0, 3) and list(lab) == list(range(6))
+    v, t, lab = omesh.remove_small_components(np.zeros((0, 3)), np.zeros((0, 3), int), 1)
+    assert v.shape == (0, 3) and t.shape == (0, 3) and len(lab) == 0
