@@ -834,6 +834,10 @@ def run_voxelize(args):
 
 # Narrow-band TSDF + marching cubes: algorithmic HBM bytes per voxel of each
 # pass (reads + writes of the dense arrays; neighbour re-reads hit the caches)
+# components of fewer triangles are removed after decimation (specks left
+# by floaters; a 30 cm object at the 6 cm decimation cell has ~150 faces)
+MIN_COMPONENT_FACES = 32
+
 TSDF_PASS_BYTES = {
     "smooth_x": 1 + 4, "smooth_y": 4 + 8, "smooth_z": 8 + 1, "flood_init": 1 + 1,
     "flood_sweep": 1 + 1, "shell0": 1 + 1, "shell": 1 + 1, "phi": 1 + 1 + 4,
@@ -893,18 +897,26 @@ def run_mesh(args):
     tsdf_ms, mc_ms = float(np.median(ts)), float(np.median(ms))
     ms_step = tsdf_ms + mc_ms
     # mesh optimisation (paper defaults): decimation to 10 % of the faces,
-    # then Taubin smoothing (0.5, -0.53), 10 iterations
-    dec_ms, smo_ms = [], []
+    # removal of components under MIN_COMPONENT_FACES triangles, then Taubin
+    # smoothing (0.5, -0.53), 10 iterations
+    dec_ms, cc_ms, smo_ms = [], [], []
     for k in range(max(3, args.steps // 2)):
         t0 = time.perf_counter()
         dverts, dtris, cell = ctx.decimate(verts, tris, 0.1, stream=stream)
         t1 = time.perf_counter()
-        ctx.taubin(dverts, dtris, 0.5, -0.53, 10, stream=stream)
+        cverts, ctris = ctx.remove_small_components(dverts, dtris, MIN_COMPONENT_FACES,
+                                                    stream=stream)
         t2 = time.perf_counter()
+        ctx.taubin(cverts, ctris, 0.5, -0.53, 10, stream=stream)
+        t3 = time.perf_counter()
         if k:
             dec_ms.append((t1 - t0) * 1e3)
-            smo_ms.append((t2 - t1) * 1e3)
+            cc_ms.append((t2 - t1) * 1e3)
+            smo_ms.append((t3 - t2) * 1e3)
     decimate_ms, smooth_ms = float(np.median(dec_ms)), float(np.median(smo_ms))
+    components_ms = float(np.median(cc_ms))
+    n_dec_tris = int(dtris.shape[0])
+    dverts, dtris = cverts, ctris
     # the meshes as LiDAR scenes: BVH build and one 8-environment frame each
     sdf = synth.indoor_sdf(1)
     poses = torch.from_numpy(synth.free_space_poses(sdf, 8, 77)).to(dev)
@@ -990,9 +1002,11 @@ def run_mesh(args):
         # decimation + smoothing of the sub-grid's mesh, both sides
         t0 = time.perf_counter()
         dvo, dto, _ = omesh.decimate(vo, to, 0.1)
+        dvo, dto, _ = omesh.remove_small_components(dvo, dto, MIN_COMPONENT_FACES)
         svo = omesh.taubin(dvo, dto, 0.5, -0.53, 10)
         dt_d = time.perf_counter() - t0
         dvg, dtg, _ = ctx.decimate(vg, tg, 0.1)
+        dvg, dtg = ctx.remove_small_components(dvg, dtg, MIN_COMPONENT_FACES)
         ctx.taubin(dvg, dtg, 0.5, -0.53, 10)
         torch.cuda.synchronize()
         same_opt = bool(np.array_equal(dtg.cpu().numpy(), dto)
@@ -1001,7 +1015,7 @@ def run_mesh(args):
                "sample": f"a 128 x 128 x 64 sub-grid of the same surface mask, TSDF + marching "
                          f"cubes (numpy/scipy, one thread), {dt:.1f} s",
                "gpu_agreement": {"bit_identical": same, "triangles": int(len(to)),
-                                 "decimate_smooth_bit_identical": same_opt,
+                                 "decimate_components_smooth_bit_identical": same_opt,
                                  "decimate_smooth_oracle_s": round(dt_d, 2),
                                  "decimated_triangles": int(len(dto))},
                "fidelity_oracle": {"s": round(dt_m, 3), "chamfer": ocd[0], "fscore": ocd[5],
@@ -1022,8 +1036,9 @@ def run_mesh(args):
         "lidar_on_mesh": {"rays": int(8 * len(dirs)), "ms": round(cast_ms, 3),
                           "hit_fraction": round(hit_frac, 4)},
         "mesh_optimisation": {
-            "decimate_ms": round(decimate_ms, 3), "smooth_ms": round(smooth_ms, 3),
-            "ratio": 0.1, "cell_m": round(float(cell), 5),
+            "decimate_ms": round(decimate_ms, 3), "components_ms": round(components_ms, 3),
+            "smooth_ms": round(smooth_ms, 3), "ratio": 0.1, "cell_m": round(float(cell), 5),
+            "decimated_triangles": n_dec_tris, "min_component_faces": MIN_COMPONENT_FACES,
             "vertices": int(dverts.shape[0]), "triangles": int(dtris.shape[0]),
             "lidar_ms": round(cast_f_ms, 3),
             "chamfer_m": fid_final["chamfer"], "fscore_at_0.05m": fid_final["fscore"]},

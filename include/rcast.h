@@ -568,6 +568,25 @@ rc_status rc_decimate(rc_ctx *ctx, const float *verts_xyz, int64_t n_verts, cons
                       int64_t n_tris, float ratio, float *out_verts, int32_t *out_tris,
                       int64_t *n_verts_out, int64_t *n_tris_out, float *cell_out, void *stream);
 
+/* Removal of tiny components (Sec. IV-B "Mesh optimization": decimation
+ * also removes tiny components).  Two triangles are connected when they
+ * share a vertex; components with fewer than min_faces triangles are
+ * dropped (exactly min_faces is kept; min_faces <= 1 keeps every
+ * triangle).  The kept triangles keep their input order; the vertices
+ * they reference keep their input order and are renumbered densely;
+ * vertices no kept triangle references are dropped.  verts_xyz, tri_idx:
+ * DEVICE input mesh (float32 [n_verts][3], int32 [n_tris][3]); out_verts
+ * (DEVICE float32 [n_verts][3]) and out_tris (DEVICE int32 [n_tris][3])
+ * receive the result (never larger than the input; must not alias the
+ * input); sizes in *n_verts_out / *n_tris_out.  Synchronous.  Scratch of
+ * 20 bytes per vertex and 8 per triangle is kept by the context.
+ * Errors: RC_E_INVAL (sizes, null arrays, an index out of range),
+ * RC_E_NOMEM, RC_E_DEVICE. */
+rc_status rc_remove_small_components(rc_ctx *ctx, const float *verts_xyz, int64_t n_verts,
+                                     const int32_t *tri_idx, int64_t n_tris, int64_t min_faces,
+                                     float *out_verts, int32_t *out_tris, int64_t *n_verts_out,
+                                     int64_t *n_tris_out, void *stream);
+
 /* Device id of a host-only context for rc_create: no HIP calls; scenes and
  * patterns hold their sizes only (rc_scene_upload needs host arrays);
  * rc_raycast_* report RC_E_STATE; the server runs requests on a simulated

@@ -184,6 +184,22 @@ hipError_t group_ids_launch(const uint32_t *vals, const uint32_t *flag, const ui
 // for every group a kept triangle touches (used must be zeroed first).
 hipError_t keep_launch(const int32_t *tris, int64_t nt, const uint32_t *gid, uint32_t *keep,
                        uint32_t *used, hipStream_t s);
+// Connected components of a mesh (triangles joined through shared
+// vertices): label[v] = a vertex of v's component shared by all its
+// vertices (which one depends on thread timing), faces[label] = its
+// triangle count (faces is indexed by vertex; nv entries).
+hipError_t components_launch(const int32_t *tris, int64_t nt, int64_t nv, uint32_t *parent,
+                             uint32_t *label, uint32_t *faces, hipStream_t s);
+// keep[t] = its component has >= min_faces triangles; used[v] = 1 for the
+// corners of kept triangles (used must be zero before).
+hipError_t components_keep_launch(const int32_t *tris, int64_t nt, const uint32_t *label,
+                                  const uint32_t *faces, uint32_t min_faces, uint32_t *keep,
+                                  uint32_t *used, hipStream_t s);
+// Kept vertices and triangles at their scanned positions, renumbered.
+hipError_t components_emit_launch(const float *verts, int64_t nv, const uint32_t *used,
+                                  const uint32_t *newid, const int32_t *tris, int64_t nt,
+                                  const uint32_t *keep, const uint32_t *tpos, float *out_verts,
+                                  int32_t *out_tris, hipStream_t s);
 // Representatives of the used groups and the kept triangles, renumbered.
 hipError_t decimate_emit_launch(const float *verts, const double *Q, const uint8_t *boundary,
                                 const uint32_t *vals, const uint32_t *gstart, int64_t ngroups,

@@ -8,6 +8,8 @@
 //   neighbours stay in place.
 //
 // Decimation: quadric-error vertex clustering (see decimate_emit below).
+// Removal of tiny components: union-find labels, per-component face counts,
+// stable compaction (see the components kernels below).
 //
 // Neighbour lists: every triangle appends its two other corners to each
 // corner's slots (atomic slot counter, at most kNbrCap per vertex); each
@@ -425,6 +427,171 @@ __global__ __launch_bounds__(kBlock) void k_emit_tris(const int32_t *__restrict_
     for (int k = 0; k < 3; ++k) out[3 * p + k] = (int32_t)newid[gid[tris[3 * t + k]]];
 }
 
+
+// ---- connected components and removal of tiny ones ------------------------
+// Lock-free union-find over the vertices, one thread per triangle joining
+// its corners.  Roots are ranked by a bijective hash of their index, and a
+// root is only ever hooked under a root of lower rank (CAS on its own parent
+// slot): ranks strictly decrease along every chain, so every loop ends, and
+// a failed CAS means another thread hooked that root.  Hashed ranks behave
+// like random linking and keep trees shallow; ranking by index instead
+// builds chains as long as the mesh on spatially ordered vertices.  Which
+// vertex ends up as a root depends on thread timing, but the partition does
+// not, and only the partition reaches the output.
+//
+// Parent loads are plain (cached) loads.  A stale value is an earlier
+// parent, still an ancestor of lower rank, so walks still end; the CAS
+// compares against the current value and hands back a fresh one when it
+// fails.  Coherent loads sent every find of the giant component to the one
+// L2 line holding its root.
+
+__device__ __forceinline__ uint32_t cc_load(const uint32_t *p) { return *p; }
+
+// a bijection of 32-bit integers (odd multiplies and xor-shifts)
+__device__ __forceinline__ uint32_t cc_rank(uint32_t x)
+{
+    x *= 0x9E3779B1u;
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    return x;
+}
+
+// root of x.  Read-only: linking by random rank keeps the expected depth
+// logarithmic without compression, and path-halving stores from thousands
+// of threads kept rewriting the same slots near the giant component's root.
+__device__ __forceinline__ uint32_t cc_find(const uint32_t *parent, uint32_t x)
+{
+    for (;;) {
+        const uint32_t p = cc_load(parent + x);
+        if (p == x) return x;
+        x = p;
+    }
+}
+
+__device__ __forceinline__ void cc_unite(uint32_t *parent, uint32_t a, uint32_t b)
+{
+    uint32_t ra = cc_find(parent, a), rb = cc_find(parent, b);
+    while (ra != rb) {
+        if (cc_rank(ra) > cc_rank(rb)) {
+            const uint32_t t = ra;
+            ra = rb;
+            rb = t;
+        }
+        const uint32_t old = atomicCAS(parent + rb, rb, ra);
+        if (old == rb) return;
+        rb = cc_find(parent, old);
+        ra = cc_find(parent, ra);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cc_init(uint32_t *__restrict__ parent, int64_t nv)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v < nv) parent[v] = (uint32_t)v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cc_union(const int32_t *__restrict__ tris, int64_t nt,
+                                                     uint32_t *parent)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nt) return;
+    const uint32_t a = (uint32_t)tris[3 * t], b = (uint32_t)tris[3 * t + 1],
+                   c = (uint32_t)tris[3 * t + 2];
+    if (a != b) cc_unite(parent, a, b);
+    if (b != c) cc_unite(parent, b, c);
+}
+
+// label = root; per-root face counts
+__global__ __launch_bounds__(kBlock) void k_cc_label(uint32_t *parent, int64_t nv,
+                                                     uint32_t *__restrict__ label)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v < nv) label[v] = cc_find(parent, (uint32_t)v);
+}
+
+// Most triangles of a mesh lie in one component and atomics on one counter
+// serialise, so each thread counts runs of equal labels over kFacesRun
+// consecutive triangles, and the wave then adds the counts of each distinct
+// final label with one atomic (one ballot and one reduction per label).
+constexpr int kFacesRun = 16;
+
+__global__ __launch_bounds__(kBlock) void k_cc_faces(const int32_t *__restrict__ tris, int64_t nt,
+                                                     const uint32_t *__restrict__ label,
+                                                     uint32_t *__restrict__ faces)
+{
+    const int64_t t0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kFacesRun;
+    uint32_t key = 0, cnt = 0;
+    for (int k = 0; k < kFacesRun; ++k) {
+        const int64_t t = t0 + k;
+        if (t >= nt) break;
+        const uint32_t L = label[tris[3 * t]];
+        if (cnt && L != key) {
+            atomicAdd(&faces[key], cnt);
+            cnt = 0;
+        }
+        key = L;
+        ++cnt;
+    }
+    const bool act = cnt > 0;
+    const int lane = (int)__lane_id();
+    unsigned long long pending = __ballot(act);
+    while (pending) {
+        const int first = __ffsll(pending) - 1;
+        const uint32_t k0 = __shfl(key, first, 64);
+        const bool mine = act && key == k0 && ((pending >> lane) & 1ull);
+        uint32_t sum = mine ? cnt : 0u;
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (lane == first) atomicAdd(&faces[k0], sum);
+        pending &= ~__ballot(mine);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cc_keep(const int32_t *__restrict__ tris, int64_t nt,
+                                                    const uint32_t *__restrict__ label,
+                                                    const uint32_t *__restrict__ faces,
+                                                    uint32_t min_faces, uint32_t *__restrict__ keep,
+                                                    uint32_t *__restrict__ used)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nt) return;
+    const int32_t a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
+    const uint32_t k = faces[label[a]] >= min_faces ? 1u : 0u;
+    keep[t] = k;
+    if (k) {
+        used[a] = 1u;
+        used[b] = 1u;
+        used[c] = 1u;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cc_emit_verts(const float *__restrict__ verts,
+                                                          int64_t nv,
+                                                          const uint32_t *__restrict__ used,
+                                                          const uint32_t *__restrict__ newid,
+                                                          float *__restrict__ out)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nv || !used[v]) return;
+    const int64_t o = newid[v];
+    out[3 * o] = verts[3 * v];
+    out[3 * o + 1] = verts[3 * v + 1];
+    out[3 * o + 2] = verts[3 * v + 2];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cc_emit_tris(const int32_t *__restrict__ tris,
+                                                         int64_t nt,
+                                                         const uint32_t *__restrict__ keep,
+                                                         const uint32_t *__restrict__ tpos,
+                                                         const uint32_t *__restrict__ newid,
+                                                         int32_t *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nt || !keep[t]) return;
+    const int64_t o = tpos[t];
+    for (int k = 0; k < 3; ++k) out[3 * o + k] = (int32_t)newid[tris[3 * t + k]];
+}
+
 }  // namespace
 
 hipError_t tri_lists_launch(const int32_t *tris, int64_t nt, int64_t nv, int32_t *slots,
@@ -521,5 +688,47 @@ hipError_t decimate_emit_launch(const float *verts, const double *Q, const uint8
     if (nt > 0)
         hipLaunchKernelGGL(k_emit_tris, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, s, tris, nt,
                            gid, keep, tpos, newid, out_tris);
+    return hipGetLastError();
+}
+
+hipError_t components_launch(const int32_t *tris, int64_t nt, int64_t nv, uint32_t *parent,
+                             uint32_t *label, uint32_t *faces, hipStream_t s)
+{
+    if (nv == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cc_init, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, parent, nv);
+    if (nt > 0)
+        hipLaunchKernelGGL(k_cc_union, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, s, tris, nt,
+                           parent);
+    hipLaunchKernelGGL(k_cc_label, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, parent, nv,
+                       label);
+    hipError_t e = hipMemsetAsync(faces, 0, sizeof(uint32_t) * (size_t)nv, s);
+    if (e != hipSuccess) return e;
+    if (nt > 0)
+        hipLaunchKernelGGL(k_cc_faces, dim3(grid_for((nt + kFacesRun - 1) / kFacesRun, kBlock)),
+                           dim3(kBlock), 0, s, tris, nt, label, faces);
+    return hipGetLastError();
+}
+
+hipError_t components_keep_launch(const int32_t *tris, int64_t nt, const uint32_t *label,
+                                  const uint32_t *faces, uint32_t min_faces, uint32_t *keep,
+                                  uint32_t *used, hipStream_t s)
+{
+    if (nt == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cc_keep, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, s, tris, nt, label,
+                       faces, min_faces, keep, used);
+    return hipGetLastError();
+}
+
+hipError_t components_emit_launch(const float *verts, int64_t nv, const uint32_t *used,
+                                  const uint32_t *newid, const int32_t *tris, int64_t nt,
+                                  const uint32_t *keep, const uint32_t *tpos, float *out_verts,
+                                  int32_t *out_tris, hipStream_t s)
+{
+    if (nv > 0)
+        hipLaunchKernelGGL(k_cc_emit_verts, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, verts,
+                           nv, used, newid, out_verts);
+    if (nt > 0)
+        hipLaunchKernelGGL(k_cc_emit_tris, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, s, tris,
+                           nt, keep, tpos, newid, out_tris);
     return hipGetLastError();
 }

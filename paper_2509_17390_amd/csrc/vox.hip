@@ -679,6 +679,66 @@ rc_status rc_taubin_smooth(rc_ctx *c, float *verts, int64_t nv, const int32_t *t
     return RC_OK;
 }
 
+rc_status rc_remove_small_components(rc_ctx *c, const float *verts, int64_t nv,
+                                     const int32_t *tris, int64_t nt, int64_t min_faces,
+                                     float *out_verts, int32_t *out_tris, int64_t *n_verts_out,
+                                     int64_t *n_tris_out, void *stream)
+{
+    if (!c || !n_verts_out || !n_tris_out) return fail(RC_E_INVAL, "null argument");
+    if (nv < 0 || nt < 0) return fail(RC_E_INVAL, "negative sizes");
+    if (nv > 0x7ffffffeLL || nt > 0x7ffffffeLL) return fail(RC_E_INVAL, "mesh too large");
+    if ((nv > 0 && (!verts || !out_verts)) || (nt > 0 && (!tris || !out_tris)))
+        return fail(RC_E_INVAL, "null mesh array");
+    if (nt > 0 && nv == 0) return fail(RC_E_INVAL, "triangles without vertices");
+    if (c->mock) return fail(RC_E_STATE, "a mock context does not edit meshes");
+    *n_verts_out = 0;
+    *n_tris_out = 0;
+    if (nt == 0) return RC_OK;
+    // components of fewer than 1 triangle do not exist: clamp, and counts
+    // never exceed nt
+    const uint32_t mf = (uint32_t)(min_faces < 0 ? 0 : (min_faces > nt ? nt + 1 : min_faces));
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(c->mesh_mu);
+    Scratch ws(c);
+    uint32_t *parent, *label, *faces, *used, *newid, *keep, *tpos, *sums;
+    int32_t *flags;
+    const size_t nss = (size_t)mc_scan_sums_len(nv > nt ? nv : nt);
+    ws.take(&parent, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&label, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&faces, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&used, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&newid, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&keep, sizeof(uint32_t) * (size_t)nt);
+    ws.take(&tpos, sizeof(uint32_t) * (size_t)nt);
+    ws.take(&sums, sizeof(uint32_t) * nss);
+    ws.take(&flags, sizeof(int32_t));
+    rc_status st = ws.commit();
+    if (st != RC_OK) return st;
+    int32_t hf = 0;
+    HIP_TRY(hipMemsetAsync(flags, 0, sizeof(int32_t), s));
+    HIP_TRY(validate_mesh_launch(verts, nv, tris, nt, flags, s));
+    HIP_TRY(hipMemcpyAsync(&hf, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hf & 1) return fail(RC_E_INVAL, "invalid mesh: index out of range");
+    HIP_TRY(components_launch(tris, nt, nv, parent, label, faces, s));
+    HIP_TRY(hipMemsetAsync(used, 0, sizeof(uint32_t) * (size_t)nv, s));
+    HIP_TRY(components_keep_launch(tris, nt, label, faces, mf, keep, used, s));
+    HIP_TRY(scan_u32_launch(keep, tpos, nt, sums, s));
+    uint32_t tot[2];
+    HIP_TRY(hipMemcpyAsync(&tot[1], sums + mc_scan_sums_len(nt) - 1, sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(scan_u32_launch(used, newid, nv, sums, s));
+    HIP_TRY(hipMemcpyAsync(&tot[0], sums + mc_scan_sums_len(nv) - 1, sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(components_emit_launch(verts, nv, used, newid, tris, nt, keep, tpos, out_verts, out_tris,
+                                   s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_verts_out = tot[0];
+    *n_tris_out = tot[1];
+    return RC_OK;
+}
+
 rc_status rc_decimate(rc_ctx *c, const float *verts, int64_t nv, const int32_t *tris, int64_t nt,
                       float ratio, float *out_verts, int32_t *out_tris, int64_t *n_verts_out,
                       int64_t *n_tris_out, float *cell_out, void *stream)

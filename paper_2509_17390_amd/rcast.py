@@ -52,7 +52,7 @@ EXPORTED = [
     "rc_serve_copy", "rc_serve_get_stats", "rc_gauss_upload", "rc_gauss_build",
     "rc_gauss_release", "rc_voxelize", "rc_voxelize_counts", "rc_gauss_debug_copy",
     "rc_tsdf", "rc_marching_cubes", "rc_marching_cubes_table", "rc_nearest",
-    "rc_chamfer_fscore", "rc_taubin_smooth", "rc_decimate",
+    "rc_chamfer_fscore", "rc_taubin_smooth", "rc_decimate", "rc_remove_small_components",
 ]
 
 RC_DEVICE_MOCK = -1
@@ -204,6 +204,8 @@ def load() -> ctypes.CDLL:
         "rc_taubin_smooth": ([P, P, I64, P, I64, ctypes.c_float, ctypes.c_float, I32, P], S),
         "rc_decimate": ([P, P, I64, P, I64, ctypes.c_float, P, P, ctypes.POINTER(I64),
                          ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_float), P], S),
+        "rc_remove_small_components": ([P, P, I64, P, I64, I64, P, P, ctypes.POINTER(I64),
+                                        ctypes.POINTER(I64), P], S),
         "rc_chamfer_fscore": ([P, P, I64, P, I64, ctypes.c_float, ctypes.POINTER(rc_fidelity),
                                P], S),
     }
@@ -482,6 +484,20 @@ class Context:
                                   _ptr(ov), _ptr(ot_), ctypes.byref(n_v), ctypes.byref(n_t),
                                   ctypes.byref(cell), _stream_ptr(stream)))
         return ov[:n_v.value], ot_[:n_t.value], cell.value
+
+    def remove_small_components(self, verts, tris, min_faces: int, stream=None):
+        """Drop the components of fewer than min_faces triangles of a device
+        mesh: (verts, tris) as torch cuda tensors."""
+        import torch
+        nv, nt = int(verts.shape[0]), int(tris.shape[0])
+        ov = torch.empty((max(nv, 1), 3), dtype=torch.float32, device=verts.device)
+        ot_ = torch.empty((max(nt, 1), 3), dtype=torch.int32, device=verts.device)
+        n_v, n_t = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().rc_remove_small_components(
+            self._h, _ptr(verts) if nv else None, nv, _ptr(tris) if nt else None, nt,
+            int(min_faces), _ptr(ov), _ptr(ot_), ctypes.byref(n_v), ctypes.byref(n_t),
+            _stream_ptr(stream)))
+        return ov[:n_v.value], ot_[:n_t.value]
 
     # -- point-cloud fidelity --------------------------------------------------
     def nearest(self, ref, query, stream=None):

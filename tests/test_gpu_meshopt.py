@@ -149,3 +149,78 @@ def test_decimate_errors(ctx):
     with pytest.raises(rcast.RcastError) as e:
         ctx.decimate(v, t, 0.0)
     assert e.value.status == rcast.RC_E_INVAL
+
+
+# ---- removal of tiny components: bit-exact (integer labels, copies) --------
+
+def check_components(ctx, v, t, min_faces, tag=""):
+    import torch
+    gv, gt = ctx.remove_small_components(cuda(v), cuda(np.ascontiguousarray(t, np.int32)),
+                                         min_faces)
+    torch.cuda.synchronize()
+    gv, gt = gv.cpu().numpy(), gt.cpu().numpy()
+    ov, otr, _ = omesh.remove_small_components(v, t, min_faces)
+    assert gv.shape == ov.shape and gt.shape == otr.shape, (gv.shape, ov.shape, gt.shape, otr.shape)
+    np.testing.assert_array_equal(gt, otr)
+    np.testing.assert_array_equal(gv.view(np.uint32), ov.view(np.uint32))
+    log(f"{tag}: min {min_faces}: {len(t)} -> {len(gt)} triangles, {len(v)} -> {len(gv)} vertices")
+    return gv, gt
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_components_of_random_soups(ctx, seed):
+    """Sparse random soups (many components, repeated corners, chains that
+    cross many launches' worth of vertices), several thresholds."""
+    rng = np.random.default_rng(seed)
+    nv = 20000 + 777 * seed
+    nt = 9000
+    t = rng.integers(0, nv, size=(nt, 3)).astype(np.int32)
+    # long chains: triangle k shares a vertex with triangle k + 1
+    chain = np.arange(3000)
+    t[:3000, 0] = 2 * chain
+    t[:3000, 1] = 2 * chain + 2
+    v = rng.random((nv, 3)).astype(np.float32)
+    for k in (0, 1, 2, 3, 4, 50, 3000, 100000):
+        check_components(ctx, v, t, k, tag=f"soup {seed}")
+
+
+def test_components_of_a_decimated_blob_field(ctx):
+    """30 balls of radii 4 to 44 cm (a union of sphere distance fields),
+    marching cubes, decimation to 30 %: 24 components of 4 to 742 faces."""
+    rng = np.random.default_rng(4)
+    n, h = 48, 0.05
+    iz, iy, ix = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    P = np.stack([(ix + 0.5) * h, (iy + 0.5) * h, (iz + 0.5) * h], -1)
+    phi = np.full((n, n, n), 1.0)
+    for _ in range(30):
+        c = rng.random(3) * n * h
+        r = 0.04 + 0.4 * rng.random() ** 3
+        phi = np.minimum(phi, np.linalg.norm(P - c, axis=-1) - r)
+    phi = phi.astype(np.float32)
+    v, t = ot.marching_cubes(phi, (0, 0, 0), h, 0.0)
+    dv, dt, _ = omesh.decimate(v, t, 0.3)
+    assert len(dt) > 1000
+    for k in (1, 8, 32, 100, 742, 743):
+        check_components(ctx, dv, dt, k, tag="blobs decimated")
+    check_components(ctx, v, t, 200, tag="blobs raw")
+
+
+def test_components_edge_cases(ctx):
+    import torch
+    v = np.arange(18, dtype=np.float32).reshape(6, 3)
+    check_components(ctx, v, np.array([[1, 3, 5]]), 0, tag="unreferenced vertices")
+    check_components(ctx, v, np.array([[2, 2, 2]]), 1, tag="degenerate triangle")
+    check_components(ctx, v, np.array([[0, 1, 2], [3, 4, 5]]), 2, tag="all removed")
+    # no triangles, and no mesh at all
+    gv, gt = ctx.remove_small_components(cuda(v), torch.zeros((0, 3), dtype=torch.int32,
+                                                               device="cuda"), 1)
+    assert gv.shape == (0, 3) and gt.shape == (0, 3)
+    gv, gt = ctx.remove_small_components(torch.zeros((0, 3), device="cuda"),
+                                         torch.zeros((0, 3), dtype=torch.int32, device="cuda"), 1)
+    assert gv.shape == (0, 3) and gt.shape == (0, 3)
+    with pytest.raises(rcast.RcastError) as e:
+        ctx.remove_small_components(cuda(v), cuda(np.array([[0, 1, 6]], np.int32)), 1)
+    assert e.value.status == rcast.RC_E_INVAL
+    with pytest.raises(rcast.RcastError) as e:
+        ctx.remove_small_components(cuda(v), cuda(np.array([[0, -1, 2]], np.int32)), 1)
+    assert e.value.status == rcast.RC_E_INVAL
