@@ -175,6 +175,12 @@ hipError_t boundary_flags_launch(const uint8_t *fixed, const int32_t *deg, int64
 hipError_t cell_keys_launch(const float *verts, int64_t nv, const uint8_t *boundary,
                             const double *lo, double c, int64_t n0, int64_t n1, uint32_t *keys,
                             uint32_t *vals, hipStream_t s);
+// Number of triangles whose corners fall into three groups for the keys of
+// one cell size (no sort needed), into *count (device); partial holds
+// count_kept_ws_bytes().
+size_t count_kept_ws_bytes();
+hipError_t count_kept_launch(const int32_t *tris, int64_t nt, const uint32_t *keys,
+                             uint32_t *partial, uint32_t *count, hipStream_t s);
 // From sorted (keys, vals): group-start flags, then (after a scan into gpos)
 // the group of every vertex and the first sorted position of every group.
 hipError_t group_flags_launch(const uint32_t *keys, int64_t nv, uint32_t *flag, hipStream_t s);

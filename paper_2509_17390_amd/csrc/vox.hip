@@ -755,7 +755,7 @@ rc_status rc_decimate(rc_ctx *c, const float *verts, int64_t nv, const int32_t *
     Scratch ws(c);
     int32_t *slots, *deg, *tdeg, *flags;
     uint32_t *cnt, *keys, *vals, *keys2, *vals2, *flag, *gpos, *gid, *gstart, *keep, *tpos, *used,
-        *newid, *sums;
+        *newid, *sums, *cpart;
     uint8_t *fixed, *bnd;
     double *Q, *lo;
     float *partial, *box;
@@ -785,6 +785,7 @@ rc_status rc_decimate(rc_ctx *c, const float *verts, int64_t nv, const int32_t *
     ws.take(&box, sizeof(float) * 8);
     ws.take(&lo, sizeof(double) * 4);
     ws.take(&sortws, radix_sort_ws_bytes(nv));
+    ws.take(&cpart, count_kept_ws_bytes());
     ws.take(&flags, sizeof(int32_t));
     rc_status st = ws.commit();
     if (st != RC_OK) return st;
@@ -842,17 +843,30 @@ rc_status rc_decimate(rc_ctx *c, const float *verts, int64_t nv, const int32_t *
         *kept = tot;
         return RC_OK;
     };
+    // the bisection only needs kept-face counts: keys and one triangle pass
+    auto count = [&](double cs, int64_t *kept) -> rc_status {
+        int64_t n[3];
+        for (int a = 0; a < 3; ++a) n[a] = (int64_t)floor(((double)hb[3 + a] - (double)hb[a]) / cs) + 1;
+        if (n[0] * n[1] * n[2] > (int64_t)kBoundaryKey) return fail(RC_E_DEVICE, "cell grid too fine");
+        HIP_TRY(cell_keys_launch(verts, nv, bnd, lo, cs, n[0], n[1], keys, vals, s));
+        HIP_TRY(count_kept_launch(tris, nt, keys, cpart, flag, s));
+        uint32_t tot = 0;
+        HIP_TRY(hipMemcpyAsync(&tot, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        *kept = tot;
+        return RC_OK;
+    };
     const int64_t target = (int64_t)floor((double)ratio * (double)nt);
     double c_lo = ext / 1023.0, c_hi = ext, cs;
     int64_t kept = 0;
-    st = group(c_lo, &kept);
+    st = count(c_lo, &kept);
     if (st != RC_OK) return st;
     if (kept <= target) {
         cs = c_lo;
     } else {
         for (int it = 0; it < 12; ++it) {
             const double mid = sqrt(c_lo * c_hi);
-            st = group(mid, &kept);
+            st = count(mid, &kept);
             if (st != RC_OK) return st;
             if (kept <= target) c_hi = mid;
             else c_lo = mid;
