@@ -118,7 +118,8 @@ __global__ __launch_bounds__(kBlock) void k_flood_lines(uint8_t *__restrict__ la
         len = g.nz;
     }
     // chunks of 16 voxels: the loads of a chunk are independent of each
-    // other and of the walk, so they are issued together
+    // other and of the walk, so they are issued together (64-voxel chunks
+    // were slower: more registers, fewer waves in flight)
     constexpr int CH = 16;
     bool any = false;
     bool reach = true;        // the frame before the first voxel
@@ -127,21 +128,21 @@ __global__ __launch_bounds__(kBlock) void k_flood_lines(uint8_t *__restrict__ la
 #pragma unroll
         for (int j = 0; j < CH; ++j)
             v[j] = k0 + j < len ? lab[base + (int64_t)(k0 + j) * step] : (uint8_t)0;
-        uint32_t set = 0;
+        uint64_t set = 0;
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             if (v[j] == 0) reach = false;
             else if (v[j] == 2) reach = true;
             else if (reach) {
                 v[j] = 2;
-                set |= 1u << j;
+                set |= 1ull << j;
             }
         }
         if (set) {
             any = true;
 #pragma unroll
             for (int j = 0; j < CH; ++j)
-                if ((set >> j) & 1u) lab[base + (int64_t)(k0 + j) * step] = 2;
+                if ((set >> j) & 1ull) lab[base + (int64_t)(k0 + j) * step] = 2;
         }
     }
     reach = true;             // the frame after the last voxel
@@ -150,24 +151,100 @@ __global__ __launch_bounds__(kBlock) void k_flood_lines(uint8_t *__restrict__ la
 #pragma unroll
         for (int j = 0; j < CH; ++j)
             v[j] = k1 - 1 - j >= 0 ? lab[base + (int64_t)(k1 - 1 - j) * step] : (uint8_t)0;
-        uint32_t set = 0;
+        uint64_t set = 0;
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             if (v[j] == 0) reach = false;
             else if (v[j] == 2) reach = true;
             else if (reach) {
                 v[j] = 2;
-                set |= 1u << j;
+                set |= 1ull << j;
             }
         }
         if (set) {
             any = true;
 #pragma unroll
             for (int j = 0; j < CH; ++j)
-                if ((set >> j) & 1u) lab[base + (int64_t)(k1 - 1 - j) * step] = 2;
+                if ((set >> j) & 1ull) lab[base + (int64_t)(k1 - 1 - j) * step] = 2;
         }
     }
-    if (any) atomicOr(changed, 1);
+    // every writer stores the same value: skip the store once it is seen set
+    // (one atomic per changed line on one address serialised)
+    if (any && *changed == 0) *changed = 1;
+}
+
+// Lines along x, one wave per line, 64 voxels per step (one coalesced
+// load).  Ballots give the step's free mask F (label != 0) and outside mask
+// O; "outside" reaches every free voxel joined to a seed (an outside voxel,
+// or the carry from the previous step / the frame at the line's end)
+// through free voxels, computed for all 64 at once by an occluded fill
+// (six shift-and-mask steps on wave-uniform masks).  Forward, then backward.
+__device__ __forceinline__ uint64_t fill_up(uint64_t gen, uint64_t pro)
+{
+    gen |= pro & (gen << 1);
+    pro &= pro << 1;
+    gen |= pro & (gen << 2);
+    pro &= pro << 2;
+    gen |= pro & (gen << 4);
+    pro &= pro << 4;
+    gen |= pro & (gen << 8);
+    pro &= pro << 8;
+    gen |= pro & (gen << 16);
+    pro &= pro << 16;
+    gen |= pro & (gen << 32);
+    return gen;
+}
+
+__device__ __forceinline__ uint64_t fill_down(uint64_t gen, uint64_t pro)
+{
+    gen |= pro & (gen >> 1);
+    pro &= pro >> 1;
+    gen |= pro & (gen >> 2);
+    pro &= pro >> 2;
+    gen |= pro & (gen >> 4);
+    pro &= pro >> 4;
+    gen |= pro & (gen >> 8);
+    pro &= pro >> 8;
+    gen |= pro & (gen >> 16);
+    pro &= pro >> 16;
+    gen |= pro & (gen >> 32);
+    return gen;
+}
+
+__global__ __launch_bounds__(kBlock) void k_flood_xwave(uint8_t *__restrict__ lab, TsdfGrid g,
+                                                        int32_t *__restrict__ changed)
+{
+    const int64_t line = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (line >= (int64_t)g.ny * g.nz) return;           // whole waves
+    const int lane = (int)(threadIdx.x & 63);
+    uint8_t *row = lab + line * g.nx;
+    const int len = g.nx;
+    const int nch = (len + 63) >> 6;
+    bool any = false;
+    uint64_t carry = 1;                                   // the frame before voxel 0
+    for (int c = 0; c < nch; ++c) {
+        const int k = (c << 6) + lane;
+        const uint8_t v = k < len ? row[k] : (uint8_t)0;
+        const uint64_t F = __ballot(v != 0), O = __ballot(v == 2);
+        const uint64_t gen = fill_up(O | (carry & F & 1ull), F);
+        const uint64_t add = gen & ~O;
+        if ((add >> lane) & 1ull) row[k] = 2;
+        any |= add != 0;
+        carry = gen >> 63;
+    }
+    carry = 1;                                            // the frame after the last voxel
+    for (int c = nch - 1; c >= 0; --c) {
+        const int k = (c << 6) + lane;
+        const uint8_t v = k < len ? row[k] : (uint8_t)0;
+        const uint64_t F = __ballot(v != 0), O = __ballot(v == 2);
+        const int top = len - 1 - (c << 6) < 63 ? len - 1 - (c << 6) : 63;
+        const uint64_t gen = fill_down(O | (carry ? (F & (1ull << top)) : 0ull), F);
+        const uint64_t add = gen & ~O;
+        if ((add >> lane) & 1ull) row[k] = 2;
+        any |= add != 0;
+        carry = gen & 1ull;
+    }
+    if (any && lane == 0 && *changed == 0) *changed = 1;
 }
 
 // ---- distance shells and phi -----------------------------------------------
@@ -581,7 +658,7 @@ hipError_t tsdf_flood_init_launch(const uint8_t *vt, uint8_t *lab, const TsdfGri
 hipError_t tsdf_flood_round_launch(uint8_t *lab, const TsdfGrid &g, int32_t *changed,
                                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_flood_lines<0>, dim3(grid_for((int64_t)g.ny * g.nz, kBlock)),
+    hipLaunchKernelGGL(k_flood_xwave, dim3(grid_for((int64_t)g.ny * g.nz, kBlock / 64)),
                        dim3(kBlock), 0, s, lab, g, changed);
     hipLaunchKernelGGL(k_flood_lines<1>, dim3(grid_for((int64_t)g.nx * g.nz, kBlock)),
                        dim3(kBlock), 0, s, lab, g, changed);
