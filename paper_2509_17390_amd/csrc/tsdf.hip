@@ -320,6 +320,7 @@ __device__ __forceinline__ int cell_case(const float *__restrict__ phi, int64_t 
 __global__ __launch_bounds__(kBlock) void k_mc_count(const float *__restrict__ phi, TsdfGrid g,
                                                      float iso, const uint8_t *__restrict__ ntri,
                                                      uint8_t *__restrict__ mask,
+                                                     uint8_t *__restrict__ cases,
                                                      uint32_t *__restrict__ vcount,
                                                      uint32_t *__restrict__ tcount)
 {
@@ -335,9 +336,10 @@ __global__ __launch_bounds__(kBlock) void k_mc_count(const float *__restrict__ p
     if (z < g.nz - 1 && (phi[i + sxy] < iso) != in) m |= 4;
     mask[i] = (uint8_t)m;
     vcount[i] = (uint32_t)__popc(m);
-    uint32_t t = 0;
-    if (x < g.nx - 1 && y < g.ny - 1 && z < g.nz - 1) t = ntri[cell_case(phi, i, sx, sxy, iso)];
-    tcount[i] = t;
+    int cs = 0;               // the case of the cell this point anchors (0: none)
+    if (x < g.nx - 1 && y < g.ny - 1 && z < g.nz - 1) cs = cell_case(phi, i, sx, sxy, iso);
+    cases[i] = (uint8_t)cs;
+    tcount[i] = ntri[cs];
 }
 
 // Gradient of phi at lattice point (x, y, z) along one axis, phi per voxel:
@@ -360,22 +362,21 @@ __device__ __forceinline__ void lattice_grad(const float *__restrict__ phi, cons
     out[2] = lattice_diff(phi, i, z, g.nz, (int64_t)g.nx * g.ny);
 }
 
-__global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ phi, TsdfGrid g,
-                                                    float iso, const uint8_t *__restrict__ ntri,
-                                                    const int8_t *__restrict__ tris_of,
-                                                    const uint8_t *__restrict__ mask,
-                                                    const uint32_t *__restrict__ voff,
-                                                    const uint32_t *__restrict__ toff,
-                                                    float *__restrict__ verts,
-                                                    int32_t *__restrict__ tris,
-                                                    float *__restrict__ normals)
+// Vertices and triangles of one lattice point with edge mask m and cell
+// case cs (nt triangles), into their canonical slots.
+__device__ __forceinline__ void mc_emit_point(const float *__restrict__ phi, const TsdfGrid &g,
+                                              float iso, const int8_t *__restrict__ tris_of,
+                                              const uint8_t *__restrict__ mask,
+                                              const uint32_t *__restrict__ voff,
+                                              const uint32_t *__restrict__ toff,
+                                              float *__restrict__ verts,
+                                              int32_t *__restrict__ tris,
+                                              float *__restrict__ normals, int64_t i, int m,
+                                              int cs, int nt)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= g.n) return;
     int x, y, z;
     coords(i, g, x, y, z);
     const int64_t sx = g.nx, sxy = (int64_t)g.nx * g.ny;
-    const int m = mask[i];
     if (m) {
         const float c[3] = {(float)(g.o[0] + ((double)x + 0.5) * g.h),
                             (float)(g.o[1] + ((double)y + 0.5) * g.h),
@@ -414,9 +415,7 @@ __global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ ph
             ++v;
         }
     }
-    if (x < g.nx - 1 && y < g.ny - 1 && z < g.nz - 1) {
-        const int cs = cell_case(phi, i, sx, sxy, iso);
-        const int nt = ntri[cs];
+    if (nt > 0) {
         uint32_t t0 = toff[i];
         for (int k = 0; k < nt; ++k) {
             for (int e = 0; e < 3; ++e) {
@@ -433,6 +432,46 @@ __global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ ph
                 tris[3 * ((int64_t)t0 + k) + e] = (int32_t)id;
             }
         }
+    }
+}
+
+
+// Points with a vertex or a triangle are a small share of the grid, so
+// each block first scans kEmitPer points per thread (two byte loads each),
+// lists the active ones in LDS, and then all its threads emit the list:
+// one thread per point left most lanes idle through the dependent loads
+// of the few active ones.  Output slots come from the scans, so the order
+// of the list does not matter.
+constexpr int kEmitPer = 8;
+
+__global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ phi, TsdfGrid g,
+                                                    float iso, const uint8_t *__restrict__ ntri,
+                                                    const int8_t *__restrict__ tris_of,
+                                                    const uint8_t *__restrict__ mask,
+                                                    const uint8_t *__restrict__ cases,
+                                                    const uint32_t *__restrict__ voff,
+                                                    const uint32_t *__restrict__ toff,
+                                                    float *__restrict__ verts,
+                                                    int32_t *__restrict__ tris,
+                                                    float *__restrict__ normals)
+{
+    __shared__ uint32_t list[kBlock * kEmitPer];
+    __shared__ uint32_t nlist;
+    if (threadIdx.x == 0) nlist = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * (kBlock * kEmitPer);
+    for (int r = 0; r < kEmitPer; ++r) {
+        const int64_t i = base + r * kBlock + threadIdx.x;
+        if (i < g.n && (mask[i] != 0 || ntri[cases[i]] != 0))
+            list[atomicAdd(&nlist, 1u)] = (uint32_t)(i - base);
+    }
+    __syncthreads();
+    const uint32_t n = nlist;
+    for (uint32_t j = threadIdx.x; j < n; j += kBlock) {
+        const int64_t i = base + list[j];
+        const int cs = cases[i];
+        mc_emit_point(phi, g, iso, tris_of, mask, voff, toff, verts, tris, normals, i, mask[i], cs,
+                      ntri[cs]);
     }
 }
 
@@ -477,19 +516,38 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const uint32_t *__restric
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// one block: exclusive scan of the tile sums in place, grand total after them
+// one block: exclusive scan of the tile sums in place, grand total after
+// them.  Each thread owns a contiguous chunk (sum it, one block scan of the
+// chunk totals, then write the chunk's prefixes): walking 256 sums per
+// block-wide step took 35 us for 32k tiles.
 __global__ __launch_bounds__(kBlock) void k_scan_sums(uint32_t *__restrict__ sums, int nb)
 {
-    uint32_t carry = 0;
-    for (int base = 0; base < nb; base += kBlock) {
-        const int i = base + threadIdx.x;
-        const uint32_t v = i < nb ? sums[i] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_scan_excl(v, &tot);
-        if (i < nb) sums[i] = carry + ex;
-        carry += tot;
+    const int per = (nb + kBlock - 1) / kBlock;
+    const int lo = (int)threadIdx.x * per;
+    const int hi = lo + per < nb ? lo + per : nb;
+    // chunks are read and written 16 entries at a time so that the loads
+    // of a group are in flight together
+    uint32_t s = 0;
+    for (int i0 = lo; i0 < hi; i0 += 16) {
+        uint32_t v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = i0 + k < hi ? sums[i0 + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s += v[k];
     }
-    if (threadIdx.x == 0) sums[nb] = carry;
+    uint32_t tot;
+    uint32_t run = block_scan_excl(s, &tot);
+    for (int i0 = lo; i0 < hi; i0 += 16) {
+        uint32_t v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = i0 + k < hi ? sums[i0 + k] : 0u;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (i0 + k < hi) sums[i0 + k] = run;
+            run += v[k];
+        }
+    }
+    if (threadIdx.x == 0) sums[nb] = tot;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t *__restrict__ out, int64_t n,
@@ -679,23 +737,24 @@ hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint8_t *lab, uint8_t
 }
 
 hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
-                           uint8_t *mask, uint32_t *vcount, uint32_t *tcount, uint32_t *voff,
-                           uint32_t *toff, uint32_t *vsums, uint32_t *tsums, hipStream_t s)
+                           uint8_t *mask, uint8_t *cases, uint32_t *vcount, uint32_t *tcount,
+                           uint32_t *voff, uint32_t *toff, uint32_t *vsums, uint32_t *tsums,
+                           hipStream_t s)
 {
     hipLaunchKernelGGL(k_mc_count, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, phi, g, iso,
-                       ntri, mask, vcount, tcount);
+                       ntri, mask, cases, vcount, tcount);
     hipError_t e = scan_launch(vcount, voff, g.n, vsums, s);
     if (e == hipSuccess) e = scan_launch(tcount, toff, g.n, tsums, s);
     return e;
 }
 
 hipError_t mc_emit_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
-                          const int8_t *tris_of, const uint8_t *mask, const uint32_t *voff,
-                          const uint32_t *toff, float *verts, int32_t *tris, float *normals,
-                          hipStream_t s)
+                          const int8_t *tris_of, const uint8_t *mask, const uint8_t *cases,
+                          const uint32_t *voff, const uint32_t *toff, float *verts, int32_t *tris,
+                          float *normals, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mc_emit, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, phi, g, iso,
-                       ntri, tris_of, mask, voff, toff, verts, tris, normals);
+    hipLaunchKernelGGL(k_mc_emit, dim3(grid_for(g.n, kBlock * kEmitPer)), dim3(kBlock), 0, s, phi,
+                       g, iso, ntri, tris_of, mask, cases, voff, toff, verts, tris, normals);
     return hipGetLastError();
 }
 

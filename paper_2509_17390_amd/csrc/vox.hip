@@ -492,10 +492,11 @@ rc_status rc_marching_cubes(rc_ctx *c, const rc_grid *grid, const float *phi, fl
     const int8_t *tris_of = reinterpret_cast<const int8_t *>(c->mc_table + 256);
     std::lock_guard<std::mutex> lk(c->mesh_mu);
     Scratch ws(c);
-    uint8_t *mask;
+    uint8_t *mask, *cases;
     uint32_t *vc, *tc, *voff, *toff, *vs, *ts;
     const int64_t ns = mc_scan_sums_len(g.n);
     ws.take(&mask, g.n);
+    ws.take(&cases, g.n);
     ws.take(&vc, sizeof(uint32_t) * g.n);
     ws.take(&tc, sizeof(uint32_t) * g.n);
     ws.take(&voff, sizeof(uint32_t) * g.n);
@@ -504,7 +505,7 @@ rc_status rc_marching_cubes(rc_ctx *c, const rc_grid *grid, const float *phi, fl
     ws.take(&ts, sizeof(uint32_t) * ns);
     st = ws.commit();
     if (st != RC_OK) return st;
-    HIP_TRY(mc_count_launch(phi, g, iso, ntri, mask, vc, tc, voff, toff, vs, ts, s));
+    HIP_TRY(mc_count_launch(phi, g, iso, ntri, mask, cases, vc, tc, voff, toff, vs, ts, s));
     uint32_t tot[2];
     HIP_TRY(hipMemcpyAsync(&tot[0], vs + ns - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&tot[1], ts + ns - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -514,8 +515,8 @@ rc_status rc_marching_cubes(rc_ctx *c, const rc_grid *grid, const float *phi, fl
     if (!out_verts) return RC_OK;
     if (cap_verts < (int64_t)tot[0] || cap_tris < (int64_t)tot[1])
         return fail(RC_E_NOMEM, "mesh needs %u vertices and %u triangles", tot[0], tot[1]);
-    HIP_TRY(mc_emit_launch(phi, g, iso, ntri, tris_of, mask, voff, toff, out_verts, out_tris,
-                           out_normals, s));
+    HIP_TRY(mc_emit_launch(phi, g, iso, ntri, tris_of, mask, cases, voff, toff, out_verts,
+                           out_tris, out_normals, s));
     HIP_TRY(hipStreamSynchronize(s));
     return RC_OK;
 }
