@@ -25,7 +25,7 @@
 //   collapse     optional: 4-wide nodes with 8-bit child boxes in each node's
 //                frame (node depths, prefix count of even-depth nodes, then
 //                one thread per 4-wide node)
-#include "gauss_internal.h"
+#include "mesh_internal.h"
 
 #include <math.h>
 

@@ -4,7 +4,7 @@
 
 #include "rcast.h"
 #include "rc_internal.h"
-#include "gauss_internal.h"
+#include "mesh_internal.h"
 
 #include <mutex>
 #include <string>

@@ -65,153 +65,3 @@ hipError_t voxelize_launch(int mode, const NodeRec *nodes, const GaussRec *recs,
                            float *density, uint8_t *occ, int32_t *tile_counts, hipStream_t s);
 // Surface mask from occupancy.
 hipError_t surface_launch(const uint8_t *occ, uint8_t *surf, const VoxGrid &g, hipStream_t s);
-
-// ---------------------------------------------------------------------------
-// Narrow-band TSDF and marching cubes (tsdf.hip).
-
-struct TsdfGrid {
-    double o[3];          // origin (float32 input, exact)
-    double h;             // spacing (float32 input, exact)
-    float hf;             // the same spacing as float32
-    int32_t nx, ny, nz;
-    int64_t n;            // voxels
-};
-
-// Binomial smoothing kernel: n steps, weights C(2n, n + k) for k = -n..n.
-constexpr int kMaxBinomial = 10;
-struct Binomial {
-    int32_t n;
-    uint32_t w[2 * kMaxBinomial + 1];
-};
-
-// V~ = [sum >= thr] of the separable binomial smoothing of `surf`; a (u32)
-// and b (u64) hold the x and xy passes.
-hipError_t tsdf_smooth_launch(const uint8_t *surf, uint32_t *a, uint64_t *b, uint8_t *vt,
-                              const TsdfGrid &g, const Binomial &w, uint64_t thr, hipStream_t s);
-hipError_t tsdf_flood_init_launch(const uint8_t *vt, uint8_t *lab, const TsdfGrid &g,
-                                  hipStream_t s);
-// One round of the outside labelling (line sweeps along x, y, z);
-// *changed |= 1 if any voxel changed.
-hipError_t tsdf_flood_round_launch(uint8_t *lab, const TsdfGrid &g, int32_t *changed,
-                                   hipStream_t s);
-hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint8_t *lab, uint8_t *p, float *phi,
-                                  const TsdfGrid &g, int shells, float h, float r, hipStream_t s);
-
-// Marching cubes: the case table (count[256], tri[256][15] edge ids, -1
-// padded), the count pass (edge masks and cell cases, one byte each per
-// point) with both exclusive scans (vsums / tsums hold mc_scan_sums_len(n)
-// entries, the grand total last), and the emit pass (normals: float32
-// [nv][3] or null).
-void mc_table_copy(uint8_t *count, int8_t *tri);
-int64_t mc_scan_sums_len(int64_t n);
-hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
-                           uint8_t *mask, uint8_t *cases, uint32_t *vcount, uint32_t *tcount,
-                           uint32_t *voff, uint32_t *toff, uint32_t *vsums, uint32_t *tsums,
-                           hipStream_t s);
-hipError_t mc_emit_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
-                          const int8_t *tris_of, const uint8_t *mask, const uint8_t *cases,
-                          const uint32_t *voff, const uint32_t *toff, float *verts, int32_t *tris,
-                          float *normals, hipStream_t s);
-
-// ---------------------------------------------------------------------------
-// Nearest neighbours and fidelity metrics (nn.hip).
-
-// Scratch of nearest_launch for a reference cloud of n_ref points (build
-// arrays, then the partial sums of metric_sums_launch at nn_metric_offset).
-size_t nn_scratch_bytes(int64_t n_ref);
-size_t nn_metric_offset(int64_t n_ref);
-// LBVH build workspace (BuildBuffers::ws) for n_ref points.
-size_t nn_workspace_bytes(int64_t n_ref);
-// d(q, ref) (FP64) and the lowest index of a nearest reference point for
-// every query; ref and query are float32 [n][3] on the device.
-hipError_t nearest_launch(const float *ref, int64_t n_ref, const float *query, int64_t n_q,
-                          double *out_d, int32_t *out_i, void *scratch, void *ws, size_t ws_bytes,
-                          hipStream_t s);
-// *out_sum = sum of d, *out_cnt = number of d <= tau (fixed summation order);
-// partial sums use the scratch at byte offset `off`.
-hipError_t metric_sums_launch(const double *d, int64_t n, double tau, void *scratch, size_t off,
-                              double *out_sum, unsigned long long *out_cnt, hipStream_t s);
-
-// ---------------------------------------------------------------------------
-// Mesh optimisation (meshopt.hip).
-
-constexpr int kNbrCap = 64;   // neighbour slots per vertex (two per incident triangle)
-// Distinct sorted neighbours (slots [nv][kNbrCap], deg [nv]) and the fixed
-// flag (boundary or isolated) of every vertex; *flags |= 1 when a vertex
-// has more than kNbrCap neighbour slots.  cnt: [nv] scratch.
-hipError_t nbr_build_launch(const int32_t *tris, int64_t nt, int64_t nv, int32_t *slots,
-                            uint32_t *cnt, int32_t *deg, uint8_t *fixed, int32_t *flags,
-                            hipStream_t s);
-// `iterations` Taubin iterations in place (tmp: [nv][3] scratch).
-hipError_t taubin_launch(float *verts, float *tmp, const int32_t *slots, const int32_t *deg,
-                         const uint8_t *fixed, int64_t nv, float lambda, float mu, int iterations,
-                         hipStream_t s);
-
-// Stable LSD radix sort of (keys, vals) by the low key_bits bits of keys
-// (build.hip); *in_tmp = 1 when the result is in (keys_tmp, vals_tmp).
-size_t radix_sort_ws_bytes(int64_t n);
-hipError_t radix_sort_launch(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp,
-                             int64_t n, int key_bits, void *ws, hipStream_t s, int *in_tmp);
-// Exclusive scan of uint32 (tsdf.hip); sums holds mc_scan_sums_len(n)
-// entries, the grand total last.
-hipError_t scan_u32_launch(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *sums,
-                           hipStream_t s);
-
-// Quadric-error decimation by vertex clustering (meshopt.hip).
-constexpr uint32_t kBoundaryKey = 0x40000000u;   // above every cell key (cells < 2^30)
-// incident triangles of every vertex, distinct and ascending (slots
-// [nv][kNbrCap], tdeg [nv]); *flags |= 1 on overflow.  cnt: [nv] scratch.
-hipError_t tri_lists_launch(const int32_t *tris, int64_t nt, int64_t nv, int32_t *slots,
-                            uint32_t *cnt, int32_t *tdeg, int32_t *flags, hipStream_t s);
-// Q [nv][10] FP64: sum of the incident triangles' area-weighted plane quadrics.
-hipError_t vertex_quadrics_launch(const float *verts, const int32_t *tris, const int32_t *slots,
-                                  const int32_t *tdeg, int64_t nv, double *Q, hipStream_t s);
-// Box of the vertices: out[6] = lo xyz, hi xyz (partial: kMinmaxBlocks x 6 scratch).
-constexpr int kMinmaxBlocks = 256;
-hipError_t points_box_launch(const float *verts, int64_t nv, float *partial, float *out,
-                             hipStream_t s);
-// bnd[v] = 1 for vertices on an edge of one triangle (from nbr_build_launch).
-hipError_t boundary_flags_launch(const uint8_t *fixed, const int32_t *deg, int64_t nv,
-                                 uint8_t *bnd, hipStream_t s);
-// Cell key of every vertex (kBoundaryKey for boundary vertices), vals = index.
-hipError_t cell_keys_launch(const float *verts, int64_t nv, const uint8_t *boundary,
-                            const double *lo, double c, int64_t n0, int64_t n1, uint32_t *keys,
-                            uint32_t *vals, hipStream_t s);
-// Number of triangles whose corners fall into three groups for the keys of
-// one cell size (no sort needed), into *count (device); partial holds
-// count_kept_ws_bytes().
-size_t count_kept_ws_bytes();
-hipError_t count_kept_launch(const int32_t *tris, int64_t nt, const uint32_t *keys,
-                             uint32_t *partial, uint32_t *count, hipStream_t s);
-// From sorted (keys, vals): group-start flags, then (after a scan into gpos)
-// the group of every vertex and the first sorted position of every group.
-hipError_t group_flags_launch(const uint32_t *keys, int64_t nv, uint32_t *flag, hipStream_t s);
-hipError_t group_ids_launch(const uint32_t *vals, const uint32_t *flag, const uint32_t *gpos,
-                            int64_t nv, uint32_t *gid, uint32_t *gstart, hipStream_t s);
-// keep[t] = 1 when the three corners of t lie in three groups; used[g] = 1
-// for every group a kept triangle touches (used must be zeroed first).
-hipError_t keep_launch(const int32_t *tris, int64_t nt, const uint32_t *gid, uint32_t *keep,
-                       uint32_t *used, hipStream_t s);
-// Connected components of a mesh (triangles joined through shared
-// vertices): label[v] = a vertex of v's component shared by all its
-// vertices (which one depends on thread timing), faces[label] = its
-// triangle count (faces is indexed by vertex; nv entries).
-hipError_t components_launch(const int32_t *tris, int64_t nt, int64_t nv, uint32_t *parent,
-                             uint32_t *label, uint32_t *faces, hipStream_t s);
-// keep[t] = its component has >= min_faces triangles; used[v] = 1 for the
-// corners of kept triangles (used must be zero before).
-hipError_t components_keep_launch(const int32_t *tris, int64_t nt, const uint32_t *label,
-                                  const uint32_t *faces, uint32_t min_faces, uint32_t *keep,
-                                  uint32_t *used, hipStream_t s);
-// Kept vertices and triangles at their scanned positions, renumbered.
-hipError_t components_emit_launch(const float *verts, int64_t nv, const uint32_t *used,
-                                  const uint32_t *newid, const int32_t *tris, int64_t nt,
-                                  const uint32_t *keep, const uint32_t *tpos, float *out_verts,
-                                  int32_t *out_tris, hipStream_t s);
-// Representatives of the used groups and the kept triangles, renumbered.
-hipError_t decimate_emit_launch(const float *verts, const double *Q, const uint8_t *boundary,
-                                const uint32_t *vals, const uint32_t *gstart, int64_t ngroups,
-                                int64_t nv, const uint32_t *used, const uint32_t *newid,
-                                const double *lo, double c, const int32_t *tris, int64_t nt,
-                                const uint32_t *gid, const uint32_t *keep, const uint32_t *tpos,
-                                float *out_verts, int32_t *out_tris, hipStream_t s);

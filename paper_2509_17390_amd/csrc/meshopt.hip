@@ -18,7 +18,7 @@
 // makes the lists independent of the append order, and the half-steps sum
 // neighbours in ascending index order, one rounded float32 operation at a
 // time, so results are deterministic and reproducible on the CPU.
-#include "gauss_internal.h"
+#include "mesh_internal.h"
 
 namespace {
 

@@ -10,7 +10,7 @@
 // exceeds a contained point's distance and pruning is exact.  Ties go to the
 // lowest reference index.  The sums of the metrics are reduced in a fixed
 // order (per-block partials, then one block), so results repeat exactly.
-#include "gauss_internal.h"
+#include "mesh_internal.h"
 
 #include <math.h>
 

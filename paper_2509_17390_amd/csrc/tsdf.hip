@@ -16,7 +16,7 @@
 //           triangles of the cell it anchors; exclusive scans give every
 //           vertex and triangle its slot; a second pass writes them.  The case
 //           table is built on the host from a walk over the cube's faces.
-#include "gauss_internal.h"
+#include "mesh_internal.h"
 
 #include <math.h>
 
