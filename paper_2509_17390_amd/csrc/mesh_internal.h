@@ -15,7 +15,14 @@ struct TsdfGrid {
     float hf;             // the same spacing as float32
     int32_t nx, ny, nz;
     int64_t n;            // voxels
+    // division by nx and ny for indices below 2^32: floor(i / d) is the
+    // high half of c * i with c = floor((2^64 - 1) / d) + 1 (exact for all
+    // 32-bit i and d >= 2); c = 0 marks d = 1
+    uint64_t cx, cy;
 };
+
+// the constant of the division above
+inline uint64_t fastdiv_constant(uint32_t d) { return d > 1 ? ~(uint64_t)0 / d + 1 : 0; }
 
 // Binomial smoothing kernel: n steps, weights C(2n, n + k) for k = -n..n.
 constexpr int kMaxBinomial = 10;

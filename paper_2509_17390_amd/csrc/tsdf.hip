@@ -30,6 +30,31 @@ constexpr int kScanTile = kBlock * kScanItems;
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// (x, y, z) of voxel i.  Below 2^32 voxels the divisions by nx and ny are
+// multiplications (64-bit integer division is a long emulated sequence,
+// and these kernels run it for every voxel).
+__device__ __forceinline__ uint32_t div_by(uint32_t n, uint64_t c)
+{
+    return c ? (uint32_t)__umul64hi(c, (uint64_t)n) : n;
+}
+
+__device__ __forceinline__ void coords(int64_t i, const TsdfGrid &g, int &x, int &y, int &z)
+{
+    if (g.n <= (int64_t)0xffffffffLL) {
+        const uint32_t u = (uint32_t)i;
+        const uint32_t r = div_by(u, g.cx);
+        x = (int)(u - r * (uint32_t)g.nx);
+        const uint32_t zz = div_by(r, g.cy);
+        y = (int)(r - zz * (uint32_t)g.ny);
+        z = (int)zz;
+        return;
+    }
+    x = (int)(i % g.nx);
+    const int64_t r = i / g.nx;
+    y = (int)(r % g.ny);
+    z = (int)(r / g.ny);
+}
+
 // ---- smoothing and re-threshold ------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_smooth_x(const uint8_t *__restrict__ v,
                                                      uint32_t *__restrict__ out, TsdfGrid g,
@@ -37,7 +62,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth_x(const uint8_t *__restrict__
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= g.n) return;
-    const int x = (int)(i % g.nx);
+    int x, y, z;
+    coords(i, g, x, y, z);
     uint32_t s = 0;
     for (int k = -w.n; k <= w.n; ++k) {
         const int xx = x + k;
@@ -52,7 +78,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth_y(const uint32_t *__restrict_
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= g.n) return;
-    const int y = (int)((i / g.nx) % g.ny);
+    int x, y, z;
+    coords(i, g, x, y, z);
     uint64_t s = 0;
     for (int k = -w.n; k <= w.n; ++k) {
         const int yy = y + k;
@@ -68,7 +95,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth_z(const uint64_t *__restrict_
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= g.n) return;
     const int64_t sxy = (int64_t)g.nx * g.ny;
-    const int z = (int)(i / sxy);
+    int x, y, z;
+    coords(i, g, x, y, z);
     uint64_t s = 0;
     for (int k = -w.n; k <= w.n; ++k) {
         const int zz = z + k;
@@ -248,13 +276,6 @@ __global__ __launch_bounds__(kBlock) void k_flood_xwave(uint8_t *__restrict__ la
 }
 
 // ---- distance shells and phi -----------------------------------------------
-__device__ __forceinline__ void coords(int64_t i, const TsdfGrid &g, int &x, int &y, int &z)
-{
-    x = (int)(i % g.nx);
-    const int64_t r = i / g.nx;
-    y = (int)(r % g.ny);
-    z = (int)(r / g.ny);
-}
 
 // p = 0 on S_0 (a 6-neighbour with the other V~ value; outside the grid is
 // 0), else 255 (not reached)

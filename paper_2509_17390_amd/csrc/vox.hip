@@ -359,6 +359,8 @@ rc_status make_tsdf_grid(const rc_grid *gr, TsdfGrid &g)
     g.nz = gr->dims[2];
     g.n = (int64_t)g.nx * g.ny * g.nz;
     if (g.n > ((int64_t)1 << 34)) return fail(RC_E_INVAL, "grid too large");
+    g.cx = fastdiv_constant((uint32_t)g.nx);
+    g.cy = fastdiv_constant((uint32_t)g.ny);
     return RC_OK;
 }
 
