@@ -41,6 +41,9 @@ hipError_t tsdf_flood_init_launch(const uint8_t *vt, uint8_t *lab, const TsdfGri
 // *changed |= 1 if any voxel changed.
 hipError_t tsdf_flood_round_launch(uint8_t *lab, const TsdfGrid &g, int32_t *changed,
                                    hipStream_t s);
+// Shells and phi.  p (one byte per voxel) must be 4-byte aligned with
+// tsdf_shell_pad(g) readable bytes before and after it.
+int64_t tsdf_shell_pad(const TsdfGrid &g);
 hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint8_t *lab, uint8_t *p, float *phi,
                                   const TsdfGrid &g, int shells, float h, float r, hipStream_t s);
 

@@ -298,18 +298,59 @@ __global__ __launch_bounds__(kBlock) void k_shell0(const uint8_t *__restrict__ v
 }
 
 // shell m: unreached voxels with a 6-neighbour in shell m - 1
+// Shell m: the unreached voxels (255) with a 6-neighbour in shell m - 1.
+// Four voxels per thread as one aligned word: byte-wide loads, one per lane
+// and neighbour, capped the one-voxel form at the rate the memory pipeline
+// issues instructions.  Neighbour words at any byte offset are put together
+// from two aligned words; `p` has kShellPad bytes of readable padding on
+// both sides, so every load stays inside the buffer (bytes outside the grid
+// are never used: the coordinate tests exclude them).  Voxels written in
+// this pass go from 255 to m, neither of which is m - 1, so a neighbour
+// read before or after the write gives the same answer; no two threads
+// write the same word.
+__device__ __forceinline__ uint32_t word_at(const uint8_t *__restrict__ p, int64_t idx)
+{
+    const int64_t a = idx & ~(int64_t)3;
+    const uint32_t lo = *reinterpret_cast<const uint32_t *>(p + a);
+    const int sh = (int)(idx & 3);
+    if (sh == 0) return lo;
+    const uint32_t hi = *reinterpret_cast<const uint32_t *>(p + a + 4);
+    return __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)sh);
+}
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t w, int j) { return (w >> (8 * j)) & 0xffu; }
+
 __global__ __launch_bounds__(kBlock) void k_shell(uint8_t *__restrict__ p, TsdfGrid g, int m)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= g.n || p[i] != 255) return;
-    int x, y, z;
-    coords(i, g, x, y, z);
+    const int64_t i0 = 4 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
+    if (i0 >= g.n) return;
+    const uint32_t c = *reinterpret_cast<const uint32_t *>(p + i0);
+    int live = 0;
+    for (int j = 0; j < 4; ++j)
+        if (i0 + j < g.n && byte_of(c, j) == 255u) live |= 1 << j;
+    if (!live) return;
     const int64_t sxy = (int64_t)g.nx * g.ny;
-    const uint8_t prev = (uint8_t)(m - 1);
-    const bool hit = (x > 0 && p[i - 1] == prev) || (x < g.nx - 1 && p[i + 1] == prev) ||
-                     (y > 0 && p[i - g.nx] == prev) || (y < g.ny - 1 && p[i + g.nx] == prev) ||
-                     (z > 0 && p[i - sxy] == prev) || (z < g.nz - 1 && p[i + sxy] == prev);
-    if (hit) p[i] = (uint8_t)m;
+    const uint32_t prev = (uint32_t)(m - 1);
+    const uint32_t wl = *reinterpret_cast<const uint32_t *>(p + i0 - 4);
+    const uint32_t wr = *reinterpret_cast<const uint32_t *>(p + i0 + 4);
+    const uint32_t xm = __builtin_amdgcn_alignbyte(c, wl, 3u);   // bytes i0 - 1 + j
+    const uint32_t xp = __builtin_amdgcn_alignbyte(wr, c, 1u);   // bytes i0 + 1 + j
+    const uint32_t ym = word_at(p, i0 - g.nx), yp = word_at(p, i0 + g.nx);
+    const uint32_t zm = word_at(p, i0 - sxy), zp = word_at(p, i0 + sxy);
+    uint32_t out = c;
+    for (int j = 0; j < 4; ++j) {
+        if (!((live >> j) & 1)) continue;
+        int x, y, z;
+        coords(i0 + j, g, x, y, z);
+        const bool hit = (x > 0 && byte_of(xm, j) == prev) ||
+                         (x < g.nx - 1 && byte_of(xp, j) == prev) ||
+                         (y > 0 && byte_of(ym, j) == prev) ||
+                         (y < g.ny - 1 && byte_of(yp, j) == prev) ||
+                         (z > 0 && byte_of(zm, j) == prev) ||
+                         (z < g.nz - 1 && byte_of(zp, j) == prev);
+        if (hit) out = (out & ~(0xffu << (8 * j))) | ((uint32_t)m << (8 * j));
+    }
+    if (out != c) *reinterpret_cast<uint32_t *>(p + i0) = out;
 }
 
 __global__ __launch_bounds__(kBlock) void k_phi(const uint8_t *__restrict__ p,
@@ -746,13 +787,18 @@ hipError_t tsdf_flood_round_launch(uint8_t *lab, const TsdfGrid &g, int32_t *cha
     return hipGetLastError();
 }
 
+// one z-layer plus two words, rounded up to a word: the farthest neighbour
+// word of the four-voxel shell kernel
+int64_t tsdf_shell_pad(const TsdfGrid &g) { return (((int64_t)g.nx * g.ny + 8) + 3) & ~(int64_t)3; }
+
 hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint8_t *lab, uint8_t *p, float *phi,
                                   const TsdfGrid &g, int shells, float h, float r, hipStream_t s)
 {
     const unsigned grid = grid_for(g.n, kBlock);
     hipLaunchKernelGGL(k_shell0, dim3(grid), dim3(kBlock), 0, s, vt, p, g);
+    const unsigned grid4 = grid_for((g.n + 3) / 4, kBlock);
     for (int m = 1; m <= shells; ++m)
-        hipLaunchKernelGGL(k_shell, dim3(grid), dim3(kBlock), 0, s, p, g, m);
+        hipLaunchKernelGGL(k_shell, dim3(grid4), dim3(kBlock), 0, s, p, g, m);
     hipLaunchKernelGGL(k_phi, dim3(grid), dim3(kBlock), 0, s, p, lab, phi, g, h, r);
     return hipGetLastError();
 }

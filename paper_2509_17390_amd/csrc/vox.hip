@@ -434,16 +434,19 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
     Scratch ws(c);
     uint32_t *a;
     uint64_t *b;
-    uint8_t *vt = out_vtilde, *lab, *p;
+    uint8_t *vt = out_vtilde, *lab, *pbuf;
     int32_t *flag;
+    // the shell kernel reads whole words up to one z-layer beyond the grid
+    const int64_t pad = tsdf_shell_pad(g);
     ws.take(&a, sizeof(uint32_t) * g.n);
     ws.take(&b, sizeof(uint64_t) * g.n);
     if (!vt) ws.take(&vt, g.n);
     ws.take(&lab, g.n);
-    ws.take(&p, g.n);
+    ws.take(&pbuf, g.n + 2 * pad + 4);
     ws.take(&flag, sizeof(int32_t));
     st = ws.commit();
     if (st != RC_OK) return st;
+    uint8_t *p = pbuf + pad;
     HIP_TRY(tsdf_smooth_launch(surf, a, b, vt, g, w, thr, s));
     HIP_TRY(tsdf_flood_init_launch(vt, lab, g, s));
     // rounds until one changes nothing (one flag read per round)
