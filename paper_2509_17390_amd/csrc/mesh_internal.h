@@ -35,12 +35,18 @@ struct Binomial {
 // and b (u64) hold the x and xy passes.
 hipError_t tsdf_smooth_launch(const uint8_t *surf, uint32_t *a, uint64_t *b, uint8_t *vt,
                               const TsdfGrid &g, const Binomial &w, uint64_t thr, hipStream_t s);
-hipError_t tsdf_flood_init_launch(const uint8_t *vt, uint8_t *lab, const TsdfGrid &g,
-                                  hipStream_t s);
-// One round of the outside labelling (line sweeps along x, y, z);
-// *changed |= 1 if any voxel changed.
-hipError_t tsdf_flood_round_launch(uint8_t *lab, const TsdfGrid &g, int32_t *changed,
-                                   hipStream_t s);
+// Outside labelling, bit-packed along x (tsdf_words_per_row words per
+// row, [nz][ny][W] uint64 each for F and O; seg holds 5 *
+// tsdf_seg_words(g) words): pack the free mask, sweep rounds (*changed set
+// when O grew), then lab = 2 outside / 0 occupied / 1 enclosed free.
+int tsdf_words_per_row(const TsdfGrid &g);
+int64_t tsdf_seg_words(const TsdfGrid &g);
+hipError_t tsdf_pack_launch(const uint8_t *vt, uint64_t *F, uint64_t *O, const TsdfGrid &g,
+                            hipStream_t s);
+hipError_t tsdf_flood_round_launch(const uint64_t *F, uint64_t *O, uint64_t *seg,
+                                   const TsdfGrid &g, int32_t *changed, hipStream_t s);
+hipError_t tsdf_unpack_launch(const uint64_t *O, const uint8_t *vt, uint8_t *lab,
+                              const TsdfGrid &g, hipStream_t s);
 // Shells and phi.  p (one byte per voxel) must be 4-byte aligned with
 // tsdf_shell_pad(g) readable bytes before and after it.
 int64_t tsdf_shell_pad(const TsdfGrid &g);

@@ -106,107 +106,24 @@ __global__ __launch_bounds__(kBlock) void k_smooth_z(const uint64_t *__restrict_
 }
 
 // ---- outside labelling -----------------------------------------------------
-// lab: 0 occupied, 1 free (not yet known to be outside), 2 outside
-__global__ __launch_bounds__(kBlock) void k_flood_init(const uint8_t *__restrict__ vt,
-                                                       uint8_t *__restrict__ lab, int64_t n)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) lab[i] = vt[i] ? 0 : 1;
-}
+// Bit-packed along x: word (z, y, wx) holds voxels x = 64 wx .. 64 wx + 63
+// of row (y, z); F = free (V~ = 0), O = known to be outside; bits beyond
+// nx are never free.  A sweep along an axis makes every run of free voxels
+// on a line that holds an outside voxel or touches the frame (beyond both
+// ends of the line) outside; sweeps along x, y and z repeat until a round
+// changes nothing, which is the 6-connected component joined to the frame
+// (a path to the frame is a chain of axis-parallel runs).  O only grows.
+//
+// x: one thread per row, an occluded fill per word with a carry bit.
+// y and z: 64 lines per thread (one word column), where one row step is
+// R = F & (R | O).  Lines are cut into kSegRows-row segments for
+// parallelism: (1) per segment, the reach out of its end and out of its
+// start from its own seeds, and the lines it is free on throughout; (2) per
+// column, the carries into each segment from the frame and the segments
+// before and after it; (3) per segment, the walk forward from its left
+// carry and backward from its right carry.
+constexpr int kSegRows = 16;
 
-// One line of the grid along `axis` per thread: "outside" spreads along
-// every run of free voxels that touches an outside voxel or the frame (the
-// frame lies beyond both ends of the line), in a forward and a backward walk.
-// Repeating the sweep along x, y and z reaches the 6-connected fixed point:
-// a path to the frame is a chain of axis-parallel runs, one run per sweep.
-// Labels only go from 1 to 2, so concurrent lines never undo each other.
-template <int AXIS>
-__global__ __launch_bounds__(kBlock) void k_flood_lines(uint8_t *__restrict__ lab, TsdfGrid g,
-                                                        int32_t *__restrict__ changed)
-{
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t sxy = (int64_t)g.nx * g.ny;
-    int64_t base, step;
-    int len;
-    if (AXIS == 0) {          // lines (y, z): t = z ny + y
-        if (t >= (int64_t)g.ny * g.nz) return;
-        base = t * g.nx;
-        step = 1;
-        len = g.nx;
-    } else if (AXIS == 1) {   // lines (x, z): t = z nx + x
-        if (t >= (int64_t)g.nx * g.nz) return;
-        const int64_t z = t / g.nx, x = t - z * g.nx;
-        base = z * sxy + x;
-        step = g.nx;
-        len = g.ny;
-    } else {                  // lines (x, y): t = y nx + x
-        if (t >= sxy) return;
-        base = t;
-        step = sxy;
-        len = g.nz;
-    }
-    // chunks of 16 voxels: the loads of a chunk are independent of each
-    // other and of the walk, so they are issued together (64-voxel chunks
-    // were slower: more registers, fewer waves in flight)
-    constexpr int CH = 16;
-    bool any = false;
-    bool reach = true;        // the frame before the first voxel
-    for (int k0 = 0; k0 < len; k0 += CH) {
-        uint8_t v[CH];
-#pragma unroll
-        for (int j = 0; j < CH; ++j)
-            v[j] = k0 + j < len ? lab[base + (int64_t)(k0 + j) * step] : (uint8_t)0;
-        uint64_t set = 0;
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            if (v[j] == 0) reach = false;
-            else if (v[j] == 2) reach = true;
-            else if (reach) {
-                v[j] = 2;
-                set |= 1ull << j;
-            }
-        }
-        if (set) {
-            any = true;
-#pragma unroll
-            for (int j = 0; j < CH; ++j)
-                if ((set >> j) & 1ull) lab[base + (int64_t)(k0 + j) * step] = 2;
-        }
-    }
-    reach = true;             // the frame after the last voxel
-    for (int k1 = len; k1 > 0; k1 -= CH) {
-        uint8_t v[CH];
-#pragma unroll
-        for (int j = 0; j < CH; ++j)
-            v[j] = k1 - 1 - j >= 0 ? lab[base + (int64_t)(k1 - 1 - j) * step] : (uint8_t)0;
-        uint64_t set = 0;
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            if (v[j] == 0) reach = false;
-            else if (v[j] == 2) reach = true;
-            else if (reach) {
-                v[j] = 2;
-                set |= 1ull << j;
-            }
-        }
-        if (set) {
-            any = true;
-#pragma unroll
-            for (int j = 0; j < CH; ++j)
-                if ((set >> j) & 1ull) lab[base + (int64_t)(k1 - 1 - j) * step] = 2;
-        }
-    }
-    // every writer stores the same value: skip the store once it is seen set
-    // (one atomic per changed line on one address serialised)
-    if (any && *changed == 0) *changed = 1;
-}
-
-// Lines along x, one wave per line, 64 voxels per step (one coalesced
-// load).  Ballots give the step's free mask F (label != 0) and outside mask
-// O; "outside" reaches every free voxel joined to a seed (an outside voxel,
-// or the carry from the previous step / the frame at the line's end)
-// through free voxels, computed for all 64 at once by an occluded fill
-// (six shift-and-mask steps on wave-uniform masks).  Forward, then backward.
 __device__ __forceinline__ uint64_t fill_up(uint64_t gen, uint64_t pro)
 {
     gen |= pro & (gen << 1);
@@ -239,40 +156,198 @@ __device__ __forceinline__ uint64_t fill_down(uint64_t gen, uint64_t pro)
     return gen;
 }
 
-__global__ __launch_bounds__(kBlock) void k_flood_xwave(uint8_t *__restrict__ lab, TsdfGrid g,
-                                                        int32_t *__restrict__ changed)
+// one wave per word: lane b reads voxel 64 wx + b (coalesced), a ballot
+// packs the word
+__global__ __launch_bounds__(kBlock) void k_pack_free(const uint8_t *__restrict__ vt, TsdfGrid g,
+                                                      int W, uint64_t *__restrict__ F,
+                                                      uint64_t *__restrict__ O)
 {
-    const int64_t line = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (line >= (int64_t)g.ny * g.nz) return;           // whole waves
+    const int64_t w = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)W * g.ny * g.nz;
+    if (w >= nw) return;                                  // whole waves
     const int lane = (int)(threadIdx.x & 63);
-    uint8_t *row = lab + line * g.nx;
-    const int len = g.nx;
-    const int nch = (len + 63) >> 6;
+    const int64_t row = w / W;
+    const int wx = (int)(w - row * W);
+    const int x = wx * 64 + lane;
+    const bool free_ = x < g.nx && vt[row * g.nx + x] == 0;
+    const uint64_t f = __ballot(free_);
+    if (lane == 0) {
+        F[w] = f;
+        O[w] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sweep_x(const uint64_t *__restrict__ F,
+                                                    uint64_t *__restrict__ O, TsdfGrid g, int W,
+                                                    int32_t *__restrict__ changed)
+{
+    const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (row >= (int64_t)g.ny * g.nz) return;
+    const uint64_t *f = F + row * W;
+    uint64_t *o = O + row * W;
+    const int top = (g.nx - 1) & 63;                      // last voxel's bit in the last word
     bool any = false;
-    uint64_t carry = 1;                                   // the frame before voxel 0
-    for (int c = 0; c < nch; ++c) {
-        const int k = (c << 6) + lane;
-        const uint8_t v = k < len ? row[k] : (uint8_t)0;
-        const uint64_t F = __ballot(v != 0), O = __ballot(v == 2);
-        const uint64_t gen = fill_up(O | (carry & F & 1ull), F);
-        const uint64_t add = gen & ~O;
-        if ((add >> lane) & 1ull) row[k] = 2;
-        any |= add != 0;
+    uint64_t carry = 1;                                   // the frame before x = 0
+    for (int wx = 0; wx < W; ++wx) {
+        const uint64_t fw = f[wx], ow = o[wx];
+        const uint64_t gen = fill_up(ow | (fw & carry), fw);
+        if (gen != ow) {
+            o[wx] = gen;
+            any = true;
+        }
         carry = gen >> 63;
     }
-    carry = 1;                                            // the frame after the last voxel
-    for (int c = nch - 1; c >= 0; --c) {
-        const int k = (c << 6) + lane;
-        const uint8_t v = k < len ? row[k] : (uint8_t)0;
-        const uint64_t F = __ballot(v != 0), O = __ballot(v == 2);
-        const int top = len - 1 - (c << 6) < 63 ? len - 1 - (c << 6) : 63;
-        const uint64_t gen = fill_down(O | (carry ? (F & (1ull << top)) : 0ull), F);
-        const uint64_t add = gen & ~O;
-        if ((add >> lane) & 1ull) row[k] = 2;
-        any |= add != 0;
+    carry = 1;                                            // the frame after x = nx - 1
+    for (int wx = W - 1; wx >= 0; --wx) {
+        const uint64_t fw = f[wx], ow = o[wx];
+        const uint64_t seed = carry ? (fw & (1ull << (wx == W - 1 ? top : 63))) : 0ull;
+        const uint64_t gen = fill_down(ow | seed, fw);
+        if (gen != ow) {
+            o[wx] = gen;
+            any = true;
+        }
         carry = gen & 1ull;
     }
-    if (any && lane == 0 && *changed == 0) *changed = 1;
+    if (any && *changed == 0) *changed = 1;
+}
+
+// word-column layout of a sweep along y (AXIS 1) or z (AXIS 2): column c,
+// row r -> word base + r * stride; rows = ny or nz
+struct Cols {
+    int64_t ncols, stride;
+    int rows, nseg;
+};
+
+template <int AXIS>
+__device__ __forceinline__ int64_t col_base(int64_t c, const TsdfGrid &g, int W)
+{
+    const int64_t a = c / W, wx = c - a * W;
+    return AXIS == 1 ? a * g.ny * W + wx      // a = z
+                     : a * W + wx;            // a = y
+}
+
+// (1) per segment: A = reach out of its end, B = reach out of its start
+// (from its own outside voxels), T = lines free on every row
+template <int AXIS>
+__global__ __launch_bounds__(kBlock) void k_seg_summary(const uint64_t *__restrict__ F,
+                                                        const uint64_t *__restrict__ O,
+                                                        TsdfGrid g, int W, Cols cl,
+                                                        uint64_t *__restrict__ A,
+                                                        uint64_t *__restrict__ B,
+                                                        uint64_t *__restrict__ T)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= cl.ncols * cl.nseg) return;
+    const int sg = (int)(t / cl.ncols);
+    const int64_t c = t - (int64_t)sg * cl.ncols;
+    const int64_t base = col_base<AXIS>(c, g, W);
+    const int r0 = sg * kSegRows;
+    const int nr = cl.rows - r0 < kSegRows ? cl.rows - r0 : kSegRows;
+    uint64_t f[kSegRows], o[kSegRows];
+#pragma unroll
+    for (int k = 0; k < kSegRows; ++k) {
+        f[k] = k < nr ? F[base + (int64_t)(r0 + k) * cl.stride] : 0ull;
+        o[k] = k < nr ? O[base + (int64_t)(r0 + k) * cl.stride] : 0ull;
+    }
+    uint64_t r = 0, tr = ~0ull;
+#pragma unroll
+    for (int k = 0; k < kSegRows; ++k)
+        if (k < nr) {
+            r = f[k] & (r | o[k]);
+            tr &= f[k];
+        }
+    uint64_t rb = 0;
+#pragma unroll
+    for (int k = kSegRows - 1; k >= 0; --k)
+        if (k < nr) rb = f[k] & (rb | o[k]);
+    A[t] = r;
+    B[t] = rb;
+    T[t] = tr;
+}
+
+// (2) per column: carries into each segment, C from the start side (the
+// frame before row 0), D from the end side (the frame after the last row)
+__global__ __launch_bounds__(kBlock) void k_seg_carry(const uint64_t *__restrict__ A,
+                                                      const uint64_t *__restrict__ B,
+                                                      const uint64_t *__restrict__ T, Cols cl,
+                                                      uint64_t *__restrict__ C,
+                                                      uint64_t *__restrict__ D)
+{
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= cl.ncols) return;
+    uint64_t carry = ~0ull;
+    for (int sg = 0; sg < cl.nseg; ++sg) {
+        const int64_t t = (int64_t)sg * cl.ncols + c;
+        C[t] = carry;
+        carry = A[t] | (T[t] & carry);
+    }
+    carry = ~0ull;
+    for (int sg = cl.nseg - 1; sg >= 0; --sg) {
+        const int64_t t = (int64_t)sg * cl.ncols + c;
+        D[t] = carry;
+        carry = B[t] | (T[t] & carry);
+    }
+}
+
+// (3) per segment: forward from C, backward from D, new outside bits out
+template <int AXIS>
+__global__ __launch_bounds__(kBlock) void k_seg_apply(const uint64_t *__restrict__ F,
+                                                      uint64_t *__restrict__ O, TsdfGrid g,
+                                                      int W, Cols cl,
+                                                      const uint64_t *__restrict__ C,
+                                                      const uint64_t *__restrict__ D,
+                                                      int32_t *__restrict__ changed)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= cl.ncols * cl.nseg) return;
+    const int sg = (int)(t / cl.ncols);
+    const int64_t c = t - (int64_t)sg * cl.ncols;
+    const int64_t base = col_base<AXIS>(c, g, W);
+    const int r0 = sg * kSegRows;
+    const int nr = cl.rows - r0 < kSegRows ? cl.rows - r0 : kSegRows;
+    uint64_t f[kSegRows], o[kSegRows], o0[kSegRows];
+#pragma unroll
+    for (int k = 0; k < kSegRows; ++k) {
+        f[k] = k < nr ? F[base + (int64_t)(r0 + k) * cl.stride] : 0ull;
+        o[k] = k < nr ? O[base + (int64_t)(r0 + k) * cl.stride] : 0ull;
+        o0[k] = o[k];
+    }
+    uint64_t r = C[t];
+#pragma unroll
+    for (int k = 0; k < kSegRows; ++k)
+        if (k < nr) {
+            r = f[k] & (r | o[k]);
+            o[k] = r;
+        }
+    r = D[t];
+#pragma unroll
+    for (int k = kSegRows - 1; k >= 0; --k)
+        if (k < nr) {
+            r = f[k] & (r | o[k]);
+            o[k] = r;
+        }
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < kSegRows; ++k)
+        if (k < nr && o[k] != o0[k]) {
+            O[base + (int64_t)(r0 + k) * cl.stride] = o[k];
+            any = true;
+        }
+    if (any && *changed == 0) *changed = 1;
+}
+
+// lab = 2 outside, else 0 occupied / 1 free (enclosed)
+__global__ __launch_bounds__(kBlock) void k_unpack_outside(const uint64_t *__restrict__ O,
+                                                           const uint8_t *__restrict__ vt,
+                                                           uint8_t *__restrict__ lab, TsdfGrid g,
+                                                           int W)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int x, y, z;
+    coords(i, g, x, y, z);
+    const uint64_t w = O[((int64_t)z * g.ny + y) * W + (x >> 6)];
+    lab[i] = ((w >> (x & 63)) & 1ull) ? 2 : (vt[i] ? 0 : 1);
 }
 
 // ---- distance shells and phi -----------------------------------------------
@@ -767,23 +842,70 @@ hipError_t tsdf_smooth_launch(const uint8_t *surf, uint32_t *a, uint64_t *b, uin
     return hipGetLastError();
 }
 
-hipError_t tsdf_flood_init_launch(const uint8_t *vt, uint8_t *lab, const TsdfGrid &g,
-                                  hipStream_t s)
+int tsdf_words_per_row(const TsdfGrid &g) { return (g.nx + 63) / 64; }
+
+static Cols cols_of(const TsdfGrid &g, int axis)
 {
-    hipLaunchKernelGGL(k_flood_init, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, vt, lab,
-                       g.n);
+    const int W = tsdf_words_per_row(g);
+    Cols c;
+    c.rows = axis == 1 ? g.ny : g.nz;
+    c.ncols = (int64_t)W * (axis == 1 ? g.nz : g.ny);
+    c.stride = axis == 1 ? W : (int64_t)W * g.ny;
+    c.nseg = (c.rows + kSegRows - 1) / kSegRows;
+    return c;
+}
+
+int64_t tsdf_seg_words(const TsdfGrid &g)
+{
+    const Cols a = cols_of(g, 1), b = cols_of(g, 2);
+    const int64_t na = a.ncols * a.nseg, nb = b.ncols * b.nseg;
+    return na > nb ? na : nb;
+}
+
+hipError_t tsdf_pack_launch(const uint8_t *vt, uint64_t *F, uint64_t *O, const TsdfGrid &g,
+                            hipStream_t s)
+{
+    const int W = tsdf_words_per_row(g);
+    const int64_t nw = (int64_t)W * g.ny * g.nz;
+    hipLaunchKernelGGL(k_pack_free, dim3(grid_for(nw, kBlock / 64)), dim3(kBlock), 0, s, vt, g, W,
+                       F, O);
     return hipGetLastError();
 }
 
-hipError_t tsdf_flood_round_launch(uint8_t *lab, const TsdfGrid &g, int32_t *changed,
-                                   hipStream_t s)
+hipError_t tsdf_flood_round_launch(const uint64_t *F, uint64_t *O, uint64_t *seg,
+                                   const TsdfGrid &g, int32_t *changed, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_flood_xwave, dim3(grid_for((int64_t)g.ny * g.nz, kBlock / 64)),
-                       dim3(kBlock), 0, s, lab, g, changed);
-    hipLaunchKernelGGL(k_flood_lines<1>, dim3(grid_for((int64_t)g.nx * g.nz, kBlock)),
-                       dim3(kBlock), 0, s, lab, g, changed);
-    hipLaunchKernelGGL(k_flood_lines<2>, dim3(grid_for((int64_t)g.nx * g.ny, kBlock)),
-                       dim3(kBlock), 0, s, lab, g, changed);
+    const int W = tsdf_words_per_row(g);
+    hipLaunchKernelGGL(k_sweep_x, dim3(grid_for((int64_t)g.ny * g.nz, kBlock)), dim3(kBlock), 0, s,
+                       F, O, g, W, changed);
+    const int64_t ns = tsdf_seg_words(g);
+    uint64_t *A = seg, *B = seg + ns, *T = seg + 2 * ns, *C = seg + 3 * ns, *D = seg + 4 * ns;
+    for (int axis = 1; axis <= 2; ++axis) {
+        const Cols cl = cols_of(g, axis);
+        const unsigned gs = grid_for(cl.ncols * cl.nseg, kBlock);
+        if (axis == 1)
+            hipLaunchKernelGGL(k_seg_summary<1>, dim3(gs), dim3(kBlock), 0, s, F, O, g, W, cl, A, B,
+                               T);
+        else
+            hipLaunchKernelGGL(k_seg_summary<2>, dim3(gs), dim3(kBlock), 0, s, F, O, g, W, cl, A, B,
+                               T);
+        hipLaunchKernelGGL(k_seg_carry, dim3(grid_for(cl.ncols, kBlock)), dim3(kBlock), 0, s, A, B,
+                           T, cl, C, D);
+        if (axis == 1)
+            hipLaunchKernelGGL(k_seg_apply<1>, dim3(gs), dim3(kBlock), 0, s, F, O, g, W, cl, C, D,
+                               changed);
+        else
+            hipLaunchKernelGGL(k_seg_apply<2>, dim3(gs), dim3(kBlock), 0, s, F, O, g, W, cl, C, D,
+                               changed);
+    }
+    return hipGetLastError();
+}
+
+hipError_t tsdf_unpack_launch(const uint64_t *O, const uint8_t *vt, uint8_t *lab,
+                              const TsdfGrid &g, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_unpack_outside, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, O, vt,
+                       lab, g, tsdf_words_per_row(g));
     return hipGetLastError();
 }
 

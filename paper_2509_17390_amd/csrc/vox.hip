@@ -435,30 +435,36 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
     uint32_t *a;
     uint64_t *b;
     uint8_t *vt = out_vtilde, *lab, *pbuf;
+    uint64_t *fw, *ow, *seg;
     int32_t *flag;
     // the shell kernel reads whole words up to one z-layer beyond the grid
     const int64_t pad = tsdf_shell_pad(g);
+    const int64_t nwords = (int64_t)tsdf_words_per_row(g) * g.ny * g.nz;
     ws.take(&a, sizeof(uint32_t) * g.n);
     ws.take(&b, sizeof(uint64_t) * g.n);
     if (!vt) ws.take(&vt, g.n);
     ws.take(&lab, g.n);
     ws.take(&pbuf, g.n + 2 * pad + 4);
+    ws.take(&fw, sizeof(uint64_t) * nwords);
+    ws.take(&ow, sizeof(uint64_t) * nwords);
+    ws.take(&seg, sizeof(uint64_t) * 5 * tsdf_seg_words(g));
     ws.take(&flag, sizeof(int32_t));
     st = ws.commit();
     if (st != RC_OK) return st;
     uint8_t *p = pbuf + pad;
     HIP_TRY(tsdf_smooth_launch(surf, a, b, vt, g, w, thr, s));
-    HIP_TRY(tsdf_flood_init_launch(vt, lab, g, s));
+    HIP_TRY(tsdf_pack_launch(vt, fw, ow, g, s));
     // rounds until one changes nothing (one flag read per round)
     for (int64_t it = 0;; ++it) {
         int32_t changed = 0;
         HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-        HIP_TRY(tsdf_flood_round_launch(lab, g, flag, s));
+        HIP_TRY(tsdf_flood_round_launch(fw, ow, seg, g, flag, s));
         HIP_TRY(hipMemcpyAsync(&changed, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (!changed) break;
         if (it > g.n) return fail(RC_E_DEVICE, "outside labelling did not settle");
     }
+    HIP_TRY(tsdf_unpack_launch(ow, vt, lab, g, s));
     HIP_TRY(tsdf_shells_phi_launch(vt, lab, p, out_phi, g, shells, g.hf, r, s));
     HIP_TRY(hipStreamSynchronize(s));
     return RC_OK;
