@@ -37,20 +37,18 @@ hipError_t tsdf_smooth_launch(const uint8_t *surf, uint32_t *a, uint64_t *b, uin
                               const TsdfGrid &g, const Binomial &w, uint64_t thr, hipStream_t s);
 // Outside labelling, bit-packed along x (tsdf_words_per_row words per
 // row, [nz][ny][W] uint64 each for F and O; seg holds 5 *
-// tsdf_seg_words(g) words): pack the free mask, sweep rounds (*changed set
-// when O grew), then lab = 2 outside / 0 occupied / 1 enclosed free.
+// tsdf_seg_words(g) words): pack the free mask, then sweep rounds
+// (*changed set when O grew).
 int tsdf_words_per_row(const TsdfGrid &g);
 int64_t tsdf_seg_words(const TsdfGrid &g);
 hipError_t tsdf_pack_launch(const uint8_t *vt, uint64_t *F, uint64_t *O, const TsdfGrid &g,
                             hipStream_t s);
 hipError_t tsdf_flood_round_launch(const uint64_t *F, uint64_t *O, uint64_t *seg,
                                    const TsdfGrid &g, int32_t *changed, hipStream_t s);
-hipError_t tsdf_unpack_launch(const uint64_t *O, const uint8_t *vt, uint8_t *lab,
-                              const TsdfGrid &g, hipStream_t s);
 // Shells and phi.  p (one byte per voxel) must be 4-byte aligned with
 // tsdf_shell_pad(g) readable bytes before and after it.
 int64_t tsdf_shell_pad(const TsdfGrid &g);
-hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint8_t *lab, uint8_t *p, float *phi,
+hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint64_t *O, uint8_t *p, float *phi,
                                   const TsdfGrid &g, int shells, float h, float r, hipStream_t s);
 
 // Marching cubes: the case table (count[256], tri[256][15] edge ids, -1

@@ -336,20 +336,6 @@ __global__ __launch_bounds__(kBlock) void k_seg_apply(const uint64_t *__restrict
     if (any && *changed == 0) *changed = 1;
 }
 
-// lab = 2 outside, else 0 occupied / 1 free (enclosed)
-__global__ __launch_bounds__(kBlock) void k_unpack_outside(const uint64_t *__restrict__ O,
-                                                           const uint8_t *__restrict__ vt,
-                                                           uint8_t *__restrict__ lab, TsdfGrid g,
-                                                           int W)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= g.n) return;
-    int x, y, z;
-    coords(i, g, x, y, z);
-    const uint64_t w = O[((int64_t)z * g.ny + y) * W + (x >> 6)];
-    lab[i] = ((w >> (x & 63)) & 1ull) ? 2 : (vt[i] ? 0 : 1);
-}
-
 // ---- distance shells and phi -----------------------------------------------
 
 // p = 0 on S_0 (a 6-neighbour with the other V~ value; outside the grid is
@@ -428,15 +414,19 @@ __global__ __launch_bounds__(kBlock) void k_shell(uint8_t *__restrict__ p, TsdfG
     if (out != c) *reinterpret_cast<uint32_t *>(p + i0) = out;
 }
 
+// phi = clip(s p h, -r, r); s = +1 where the packed outside bit is set
 __global__ __launch_bounds__(kBlock) void k_phi(const uint8_t *__restrict__ p,
-                                                const uint8_t *__restrict__ lab,
-                                                float *__restrict__ phi, TsdfGrid g, float h,
-                                                float r)
+                                                const uint64_t *__restrict__ O,
+                                                float *__restrict__ phi, TsdfGrid g, int W,
+                                                float h, float r)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= g.n) return;
+    int x, y, z;
+    coords(i, g, x, y, z);
+    const bool out = (O[((int64_t)z * g.ny + y) * W + (x >> 6)] >> (x & 63)) & 1ull;
     const float delta = p[i] == 255 ? r : (float)p[i] * h;
-    const float s = lab[i] == 2 ? delta : -delta;
+    const float s = out ? delta : -delta;
     phi[i] = fminf(fmaxf(s, -r), r);
 }
 
@@ -901,19 +891,11 @@ hipError_t tsdf_flood_round_launch(const uint64_t *F, uint64_t *O, uint64_t *seg
     return hipGetLastError();
 }
 
-hipError_t tsdf_unpack_launch(const uint64_t *O, const uint8_t *vt, uint8_t *lab,
-                              const TsdfGrid &g, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_unpack_outside, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, O, vt,
-                       lab, g, tsdf_words_per_row(g));
-    return hipGetLastError();
-}
-
 // one z-layer plus two words, rounded up to a word: the farthest neighbour
 // word of the four-voxel shell kernel
 int64_t tsdf_shell_pad(const TsdfGrid &g) { return (((int64_t)g.nx * g.ny + 8) + 3) & ~(int64_t)3; }
 
-hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint8_t *lab, uint8_t *p, float *phi,
+hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint64_t *O, uint8_t *p, float *phi,
                                   const TsdfGrid &g, int shells, float h, float r, hipStream_t s)
 {
     const unsigned grid = grid_for(g.n, kBlock);
@@ -921,7 +903,8 @@ hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint8_t *lab, uint8_t
     const unsigned grid4 = grid_for((g.n + 3) / 4, kBlock);
     for (int m = 1; m <= shells; ++m)
         hipLaunchKernelGGL(k_shell, dim3(grid4), dim3(kBlock), 0, s, p, g, m);
-    hipLaunchKernelGGL(k_phi, dim3(grid), dim3(kBlock), 0, s, p, lab, phi, g, h, r);
+    hipLaunchKernelGGL(k_phi, dim3(grid), dim3(kBlock), 0, s, p, O, phi, g, tsdf_words_per_row(g),
+                       h, r);
     return hipGetLastError();
 }
 

@@ -434,7 +434,7 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
     Scratch ws(c);
     uint32_t *a;
     uint64_t *b;
-    uint8_t *vt = out_vtilde, *lab, *pbuf;
+    uint8_t *vt = out_vtilde, *pbuf;
     uint64_t *fw, *ow, *seg;
     int32_t *flag;
     // the shell kernel reads whole words up to one z-layer beyond the grid
@@ -443,7 +443,6 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
     ws.take(&a, sizeof(uint32_t) * g.n);
     ws.take(&b, sizeof(uint64_t) * g.n);
     if (!vt) ws.take(&vt, g.n);
-    ws.take(&lab, g.n);
     ws.take(&pbuf, g.n + 2 * pad + 4);
     ws.take(&fw, sizeof(uint64_t) * nwords);
     ws.take(&ow, sizeof(uint64_t) * nwords);
@@ -464,8 +463,7 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
         if (!changed) break;
         if (it > g.n) return fail(RC_E_DEVICE, "outside labelling did not settle");
     }
-    HIP_TRY(tsdf_unpack_launch(ow, vt, lab, g, s));
-    HIP_TRY(tsdf_shells_phi_launch(vt, lab, p, out_phi, g, shells, g.hf, r, s));
+    HIP_TRY(tsdf_shells_phi_launch(vt, ow, p, out_phi, g, shells, g.hf, r, s));
     HIP_TRY(hipStreamSynchronize(s));
     return RC_OK;
 }
