@@ -31,9 +31,13 @@ struct Binomial {
     uint32_t w[2 * kMaxBinomial + 1];
 };
 
-// V~ = [sum >= thr] of the separable binomial smoothing of `surf`; a (u32)
-// and b (u64) hold the x and xy passes.
-hipError_t tsdf_smooth_launch(const uint8_t *surf, uint32_t *a, uint64_t *b, uint8_t *vt,
+// V~ = [sum >= thr] of the separable binomial smoothing of `surf`; abuf and
+// bbuf (tsdf_smooth_a_bytes / _b_bytes, 8-byte aligned) hold the x and xy
+// passes (narrow and padded for kernels of at most 3 steps when surf and
+// vt are 4-byte aligned, else u32 and u64).
+size_t tsdf_smooth_a_bytes(const TsdfGrid &g);
+size_t tsdf_smooth_b_bytes(const TsdfGrid &g);
+hipError_t tsdf_smooth_launch(const uint8_t *surf, void *abuf, void *bbuf, uint8_t *vt,
                               const TsdfGrid &g, const Binomial &w, uint64_t thr, hipStream_t s);
 // Outside labelling, bit-packed along x (tsdf_words_per_row words per
 // row, [nz][ny][W] uint64 each for F and O; seg holds 5 *

@@ -105,6 +105,154 @@ __global__ __launch_bounds__(kBlock) void k_smooth_z(const uint64_t *__restrict_
     vt[i] = s >= thr ? 1 : 0;
 }
 
+// Fast path for kernels of at most kFastSmooth steps (sums fit u8 after x,
+// u16 after y, u32 after z): four voxels per thread, word loads, narrow
+// intermediates.  One byte- or word-wide load per lane and tap capped the
+// one-voxel passes at the rate the memory pipeline issues instructions.
+// The intermediates carry readable padding of three taps plus two words on
+// both sides, so no load leaves the buffer; taps outside the grid are
+// excluded by coordinates, never by the values read.
+constexpr int kFastSmooth = 3;
+
+__device__ __forceinline__ uint32_t word_at(const uint8_t *__restrict__ p, int64_t idx)
+{
+    const int64_t a = idx & ~(int64_t)3;
+    const uint32_t lo = *reinterpret_cast<const uint32_t *>(p + a);
+    const int sh = (int)(idx & 3);
+    if (sh == 0) return lo;
+    const uint32_t hi = *reinterpret_cast<const uint32_t *>(p + a + 4);
+    return __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)sh);
+}
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t w, int j) { return (w >> (8 * j)) & 0xffu; }
+
+__device__ __forceinline__ uint32_t word_guarded(const uint8_t *__restrict__ p, int64_t idx,
+                                                 int64_t n)
+{
+    // bytes idx .. idx + 3 of p[0, n) (0 outside it); idx is a multiple of 4
+    if (idx >= 0 && idx + 4 <= n) return *reinterpret_cast<const uint32_t *>(p + idx);
+    uint32_t w = 0;
+    for (int j = 0; j < 4; ++j) {
+        const int64_t q = idx + j;
+        if (q >= 0 && q < n) w |= (uint32_t)p[q] << (8 * j);
+    }
+    return w;
+}
+
+// the 8 bytes at byte offset off (even) of a padded buffer
+__device__ __forceinline__ void bytes8_at(const uint8_t *__restrict__ p, int64_t off,
+                                          uint32_t &lo, uint32_t &hi)
+{
+    const int64_t a = off & ~(int64_t)3;
+    const uint32_t d0 = *reinterpret_cast<const uint32_t *>(p + a);
+    const uint32_t d1 = *reinterpret_cast<const uint32_t *>(p + a + 4);
+    if ((off & 3) == 0) {
+        lo = d0;
+        hi = d1;
+        return;
+    }
+    const uint32_t d2 = *reinterpret_cast<const uint32_t *>(p + a + 8);
+    lo = __builtin_amdgcn_alignbyte(d1, d0, 2u);
+    hi = __builtin_amdgcn_alignbyte(d2, d1, 2u);
+}
+
+__device__ __forceinline__ void step_voxel(const TsdfGrid &g, int &x, int &y, int &z)
+{
+    if (++x == g.nx) {
+        x = 0;
+        if (++y == g.ny) {
+            y = 0;
+            ++z;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_smooth_x4(const uint8_t *__restrict__ v,
+                                                      uint8_t *__restrict__ a8, TsdfGrid g,
+                                                      Binomial w)
+{
+    const int64_t i0 = 4 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
+    if (i0 >= g.n) return;
+    // bytes i0 - 4 .. i0 + 7 cover the taps of the four voxels
+    const uint32_t w0 = word_guarded(v, i0 - 4, g.n), w1 = word_guarded(v, i0, g.n),
+                   w2 = word_guarded(v, i0 + 4, g.n);
+    int x, y, z;
+    coords(i0, g, x, y, z);
+    uint32_t out = 0;
+    for (int j = 0; j < 4; ++j) {
+        uint32_t sum = 0;
+        for (int k = -w.n; k <= w.n; ++k) {
+            const int xx = x + k;
+            if (xx < 0 || xx >= g.nx) continue;
+            const int pos = 4 + j + k;                  // 1 .. 10
+            const uint32_t wd = pos < 4 ? w0 : (pos < 8 ? w1 : w2);
+            if ((wd >> (8 * (pos & 3))) & 0xffu) sum += w.w[k + w.n];
+        }
+        out |= sum << (8 * j);
+        step_voxel(g, x, y, z);
+    }
+    *reinterpret_cast<uint32_t *>(a8 + i0) = out;
+}
+
+__global__ __launch_bounds__(kBlock) void k_smooth_y4(const uint8_t *__restrict__ a8,
+                                                      uint16_t *__restrict__ b16, TsdfGrid g,
+                                                      Binomial w)
+{
+    const int64_t i0 = 4 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
+    if (i0 >= g.n) return;
+    int x, y, z;
+    coords(i0, g, x, y, z);
+    int yj[4];
+    for (int j = 0; j < 4; ++j) {
+        yj[j] = y;
+        step_voxel(g, x, y, z);
+    }
+    uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int k = -w.n; k <= w.n; ++k) {
+        const uint32_t wd = word_at(a8, i0 + (int64_t)k * g.nx);
+        const uint32_t c = w.w[k + w.n];
+        if ((unsigned)(yj[0] + k) < (unsigned)g.ny) s0 += c * (wd & 0xffu);
+        if ((unsigned)(yj[1] + k) < (unsigned)g.ny) s1 += c * ((wd >> 8) & 0xffu);
+        if ((unsigned)(yj[2] + k) < (unsigned)g.ny) s2 += c * ((wd >> 16) & 0xffu);
+        if ((unsigned)(yj[3] + k) < (unsigned)g.ny) s3 += c * (wd >> 24);
+    }
+    *reinterpret_cast<uint2 *>(b16 + i0) = make_uint2(s0 | (s1 << 16), s2 | (s3 << 16));
+}
+
+__global__ __launch_bounds__(kBlock) void k_smooth_z4(const uint8_t *__restrict__ b8,
+                                                      uint8_t *__restrict__ vt, TsdfGrid g,
+                                                      Binomial w, uint64_t thr)
+{
+    const int64_t i0 = 4 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
+    if (i0 >= g.n) return;
+    const int64_t sxy = (int64_t)g.nx * g.ny;
+    int x, y, z;
+    coords(i0, g, x, y, z);
+    int zj[4];
+    for (int j = 0; j < 4; ++j) {
+        zj[j] = z;
+        step_voxel(g, x, y, z);
+    }
+    uint32_t s[4] = {0, 0, 0, 0};
+    for (int k = -w.n; k <= w.n; ++k) {
+        uint32_t lo, hi;
+        bytes8_at(b8, 2 * (i0 + (int64_t)k * sxy), lo, hi);
+        const uint32_t c = w.w[k + w.n];
+        const uint32_t v4[4] = {lo & 0xffffu, lo >> 16, hi & 0xffffu, hi >> 16};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if ((unsigned)(zj[j] + k) < (unsigned)g.nz) s[j] += c * v4[j];
+    }
+    uint32_t out = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out |= ((uint64_t)s[j] >= thr ? 1u : 0u) << (8 * j);
+    if (i0 + 4 <= g.n) {
+        *reinterpret_cast<uint32_t *>(vt + i0) = out;
+    } else {
+        for (int j = 0; i0 + j < g.n; ++j) vt[i0 + j] = (uint8_t)((out >> (8 * j)) & 0xffu);
+    }
+}
+
 // ---- outside labelling -----------------------------------------------------
 // Bit-packed along x: word (z, y, wx) holds voxels x = 64 wx .. 64 wx + 63
 // of row (y, z); F = free (V~ = 0), O = known to be outside; bits beyond
@@ -369,17 +517,6 @@ __global__ __launch_bounds__(kBlock) void k_shell0(const uint8_t *__restrict__ v
 // this pass go from 255 to m, neither of which is m - 1, so a neighbour
 // read before or after the write gives the same answer; no two threads
 // write the same word.
-__device__ __forceinline__ uint32_t word_at(const uint8_t *__restrict__ p, int64_t idx)
-{
-    const int64_t a = idx & ~(int64_t)3;
-    const uint32_t lo = *reinterpret_cast<const uint32_t *>(p + a);
-    const int sh = (int)(idx & 3);
-    if (sh == 0) return lo;
-    const uint32_t hi = *reinterpret_cast<const uint32_t *>(p + a + 4);
-    return __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)sh);
-}
-
-__device__ __forceinline__ uint32_t byte_of(uint32_t w, int j) { return (w >> (8 * j)) & 0xffu; }
 
 __global__ __launch_bounds__(kBlock) void k_shell(uint8_t *__restrict__ p, TsdfGrid g, int m)
 {
@@ -822,9 +959,46 @@ void mc_table_copy(uint8_t *count, int8_t *tri)
 
 int64_t mc_scan_sums_len(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
-hipError_t tsdf_smooth_launch(const uint8_t *surf, uint32_t *a, uint64_t *b, uint8_t *vt,
+// padding of the fast path's intermediates: three taps plus two words
+static int64_t smooth_pad_a(const TsdfGrid &g)
+{
+    return ((int64_t)kFastSmooth * g.nx + 8 + 3) & ~(int64_t)3;
+}
+
+static int64_t smooth_pad_b(const TsdfGrid &g)
+{
+    return (2 * (int64_t)kFastSmooth * g.nx * g.ny + 16 + 7) & ~(int64_t)7;
+}
+
+size_t tsdf_smooth_a_bytes(const TsdfGrid &g)
+{
+    const int64_t fast = g.n + 2 * smooth_pad_a(g) + 8, wide = 4 * g.n;
+    return (size_t)(fast > wide ? fast : wide);
+}
+
+size_t tsdf_smooth_b_bytes(const TsdfGrid &g)
+{
+    const int64_t fast = 2 * g.n + 2 * smooth_pad_b(g) + 16, wide = 8 * g.n;
+    return (size_t)(fast > wide ? fast : wide);
+}
+
+hipError_t tsdf_smooth_launch(const uint8_t *surf, void *abuf, void *bbuf, uint8_t *vt,
                               const TsdfGrid &g, const Binomial &w, uint64_t thr, hipStream_t s)
 {
+    const bool fast = w.n <= kFastSmooth && ((uintptr_t)surf & 3) == 0 &&
+                      ((uintptr_t)vt & 3) == 0;
+    if (fast) {
+        uint8_t *a8 = static_cast<uint8_t *>(abuf) + smooth_pad_a(g);
+        uint8_t *b8 = static_cast<uint8_t *>(bbuf) + smooth_pad_b(g);
+        const unsigned grid4 = grid_for((g.n + 3) / 4, kBlock);
+        hipLaunchKernelGGL(k_smooth_x4, dim3(grid4), dim3(kBlock), 0, s, surf, a8, g, w);
+        hipLaunchKernelGGL(k_smooth_y4, dim3(grid4), dim3(kBlock), 0, s, a8,
+                           reinterpret_cast<uint16_t *>(b8), g, w);
+        hipLaunchKernelGGL(k_smooth_z4, dim3(grid4), dim3(kBlock), 0, s, b8, vt, g, w, thr);
+        return hipGetLastError();
+    }
+    uint32_t *a = static_cast<uint32_t *>(abuf);
+    uint64_t *b = static_cast<uint64_t *>(bbuf);
     const unsigned grid = grid_for(g.n, kBlock);
     hipLaunchKernelGGL(k_smooth_x, dim3(grid), dim3(kBlock), 0, s, surf, a, g, w);
     hipLaunchKernelGGL(k_smooth_y, dim3(grid), dim3(kBlock), 0, s, a, b, g, w);

@@ -440,8 +440,8 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
     // the shell kernel reads whole words up to one z-layer beyond the grid
     const int64_t pad = tsdf_shell_pad(g);
     const int64_t nwords = (int64_t)tsdf_words_per_row(g) * g.ny * g.nz;
-    ws.take(&a, sizeof(uint32_t) * g.n);
-    ws.take(&b, sizeof(uint64_t) * g.n);
+    ws.take(&a, tsdf_smooth_a_bytes(g));
+    ws.take(&b, tsdf_smooth_b_bytes(g));
     if (!vt) ws.take(&vt, g.n);
     ws.take(&pbuf, g.n + 2 * pad + 4);
     ws.take(&fw, sizeof(uint64_t) * nwords);
