@@ -423,17 +423,40 @@ __global__ __launch_bounds__(kBlock) void k_seg_carry(const uint64_t *__restrict
 {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= cl.ncols) return;
+    // 8 segments' summaries are loaded together, then chained in registers
+    // (one dependent load per segment left the walk latency-bound)
+    constexpr int G = 8;
     uint64_t carry = ~0ull;
-    for (int sg = 0; sg < cl.nseg; ++sg) {
-        const int64_t t = (int64_t)sg * cl.ncols + c;
-        C[t] = carry;
-        carry = A[t] | (T[t] & carry);
+    for (int s0 = 0; s0 < cl.nseg; s0 += G) {
+        uint64_t a[G], t[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int64_t i = (int64_t)(s0 + k) * cl.ncols + c;
+            a[k] = s0 + k < cl.nseg ? A[i] : 0ull;
+            t[k] = s0 + k < cl.nseg ? T[i] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+            if (s0 + k < cl.nseg) {
+                C[(int64_t)(s0 + k) * cl.ncols + c] = carry;
+                carry = a[k] | (t[k] & carry);
+            }
     }
     carry = ~0ull;
-    for (int sg = cl.nseg - 1; sg >= 0; --sg) {
-        const int64_t t = (int64_t)sg * cl.ncols + c;
-        D[t] = carry;
-        carry = B[t] | (T[t] & carry);
+    for (int s1 = cl.nseg - 1; s1 >= 0; s1 -= G) {
+        uint64_t b[G], t[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int64_t i = (int64_t)(s1 - k) * cl.ncols + c;
+            b[k] = s1 - k >= 0 ? B[i] : 0ull;
+            t[k] = s1 - k >= 0 ? T[i] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+            if (s1 - k >= 0) {
+                D[(int64_t)(s1 - k) * cl.ncols + c] = carry;
+                carry = b[k] | (t[k] & carry);
+            }
     }
 }
 
@@ -568,42 +591,73 @@ __global__ __launch_bounds__(kBlock) void k_phi(const uint8_t *__restrict__ p,
 }
 
 // ---- marching cubes --------------------------------------------------------
-// Per lattice point: mask of crossed edges +x/+y/+z (bits 0..2), vertex
-// count, and the triangle count of the cell it anchors.
-__device__ __forceinline__ int cell_case(const float *__restrict__ phi, int64_t i, int64_t sx,
-                                         int64_t sxy, float iso)
-{
-    int c = 0;
-    for (int k = 0; k < 8; ++k) {
-        const int64_t j = i + ((k & 1) ? 1 : 0) + ((k & 2) ? sx : 0) + ((k & 4) ? sxy : 0);
-        c |= (phi[j] < iso ? 1 : 0) << k;
-    }
-    return c;
-}
+// Count pass, per lattice point: mask of crossed edges +x/+y/+z (bits 0..2)
+// and vertex count; the case of the cell it anchors (bit k set when corner
+// k = (k & 1, k >> 1 & 1, k >> 2 & 1) is inside, phi < iso) and that case's
+// triangle count.
 
-__global__ __launch_bounds__(kBlock) void k_mc_count(const float *__restrict__ phi, TsdfGrid g,
-                                                     float iso, const uint8_t *__restrict__ ntri,
-                                                     uint8_t *__restrict__ mask,
-                                                     uint8_t *__restrict__ cases,
-                                                     uint32_t *__restrict__ vcount,
-                                                     uint32_t *__restrict__ tcount)
+// Four consecutive points per thread: the inside bits of the 4 x 5 window of rows (y, z), (y + 1, z), (y, z + 1), (y + 1, z + 1)
+// serve all four (20 loads where four separate points make 44).  Points
+// whose +x neighbour lies on the next row never use it: the coordinate
+// tests exclude them, and indices at or past n are never loaded.
+__global__ __launch_bounds__(kBlock) void k_mc_count4(const float *__restrict__ phi, TsdfGrid g,
+                                                      float iso,
+                                                      const uint8_t *__restrict__ ntri,
+                                                      uint8_t *__restrict__ mask,
+                                                      uint8_t *__restrict__ cases,
+                                                      uint32_t *__restrict__ vcount,
+                                                      uint32_t *__restrict__ tcount)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= g.n) return;
-    int x, y, z;
-    coords(i, g, x, y, z);
+    const int64_t i0 = 4 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
+    if (i0 >= g.n) return;
     const int64_t sx = g.nx, sxy = (int64_t)g.nx * g.ny;
-    const bool in = phi[i] < iso;
-    int m = 0;
-    if (x < g.nx - 1 && (phi[i + 1] < iso) != in) m |= 1;
-    if (y < g.ny - 1 && (phi[i + sx] < iso) != in) m |= 2;
-    if (z < g.nz - 1 && (phi[i + sxy] < iso) != in) m |= 4;
-    mask[i] = (uint8_t)m;
-    vcount[i] = (uint32_t)__popc(m);
-    int cs = 0;               // the case of the cell this point anchors (0: none)
-    if (x < g.nx - 1 && y < g.ny - 1 && z < g.nz - 1) cs = cell_case(phi, i, sx, sxy, iso);
-    cases[i] = (uint8_t)cs;
-    tcount[i] = ntri[cs];
+    const int64_t off[4] = {0, sx, sxy, sx + sxy};
+    uint32_t bits[4];                          // bit k: phi[i0 + off + k] < iso
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        uint32_t b = 0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const int64_t q = i0 + off[r] + k;
+            if (q < g.n && phi[q] < iso) b |= 1u << k;
+        }
+        bits[r] = b;
+    }
+    int x, y, z;
+    coords(i0, g, x, y, z);
+    uint32_t mw = 0, cw = 0, vc[4], tc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const bool in = (bits[0] >> j) & 1u;
+        int m = 0;
+        if (x < g.nx - 1 && (bool)((bits[0] >> (j + 1)) & 1u) != in) m |= 1;
+        if (y < g.ny - 1 && (bool)((bits[1] >> j) & 1u) != in) m |= 2;
+        if (z < g.nz - 1 && (bool)((bits[2] >> j) & 1u) != in) m |= 4;
+        int cs = 0;
+        if (x < g.nx - 1 && y < g.ny - 1 && z < g.nz - 1) {
+            // corner k = (k & 1, k >> 1 & 1, k >> 2 & 1): row (k >> 1), column j + (k & 1)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cs |= (int)((bits[k >> 1] >> (j + (k & 1))) & 1u) << k;
+        }
+        mw |= (uint32_t)m << (8 * j);
+        cw |= (uint32_t)cs << (8 * j);
+        vc[j] = (uint32_t)__popc(m);
+        tc[j] = ntri[cs];
+        step_voxel(g, x, y, z);
+    }
+    if (i0 + 4 <= g.n) {
+        *reinterpret_cast<uint32_t *>(mask + i0) = mw;
+        *reinterpret_cast<uint32_t *>(cases + i0) = cw;
+        *reinterpret_cast<uint4 *>(vcount + i0) = make_uint4(vc[0], vc[1], vc[2], vc[3]);
+        *reinterpret_cast<uint4 *>(tcount + i0) = make_uint4(tc[0], tc[1], tc[2], tc[3]);
+    } else {
+        for (int j = 0; i0 + j < g.n; ++j) {
+            mask[i0 + j] = (uint8_t)(mw >> (8 * j));
+            cases[i0 + j] = (uint8_t)(cw >> (8 * j));
+            vcount[i0 + j] = vc[j];
+            tcount[i0 + j] = tc[j];
+        }
+    }
 }
 
 // Gradient of phi at lattice point (x, y, z) along one axis, phi per voxel:
@@ -1087,8 +1141,8 @@ hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const
                            uint32_t *voff, uint32_t *toff, uint32_t *vsums, uint32_t *tsums,
                            hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mc_count, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, phi, g, iso,
-                       ntri, mask, cases, vcount, tcount);
+    hipLaunchKernelGGL(k_mc_count4, dim3(grid_for((g.n + 3) / 4, kBlock)), dim3(kBlock), 0, s, phi,
+                       g, iso, ntri, mask, cases, vcount, tcount);
     hipError_t e = scan_launch(vcount, voff, g.n, vsums, s);
     if (e == hipSuccess) e = scan_launch(tcount, toff, g.n, tsums, s);
     return e;
