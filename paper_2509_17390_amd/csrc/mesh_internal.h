@@ -121,16 +121,17 @@ constexpr uint32_t kBoundaryKey = 0x40000000u;   // above every cell key (cells 
 // [nv][kNbrCap], tdeg [nv]); *flags |= 1 on overflow.  cnt: [nv] scratch.
 hipError_t tri_lists_launch(const int32_t *tris, int64_t nt, int64_t nv, int32_t *slots,
                             uint32_t *cnt, int32_t *tdeg, int32_t *flags, hipStream_t s);
-// Q [nv][10] FP64: sum of the incident triangles' area-weighted plane quadrics.
+// Q [nv][10] FP64: sum of the incident triangles' area-weighted plane
+// quadrics; bnd[v] = 1 when some neighbour of v is reached through exactly
+// one of its triangles (the boundary); flags[0] |= 1 when a vertex has more
+// than kNbrCap / 2 triangles.
 hipError_t vertex_quadrics_launch(const float *verts, const int32_t *tris, const int32_t *slots,
-                                  const int32_t *tdeg, int64_t nv, double *Q, hipStream_t s);
+                                  const int32_t *tdeg, int64_t nv, double *Q, uint8_t *bnd,
+                                  int32_t *flags, hipStream_t s);
 // Box of the vertices: out[6] = lo xyz, hi xyz (partial: kMinmaxBlocks x 6 scratch).
 constexpr int kMinmaxBlocks = 256;
 hipError_t points_box_launch(const float *verts, int64_t nv, float *partial, float *out,
                              hipStream_t s);
-// bnd[v] = 1 for vertices on an edge of one triangle (from nbr_build_launch).
-hipError_t boundary_flags_launch(const uint8_t *fixed, const int32_t *deg, int64_t nv,
-                                 uint8_t *bnd, hipStream_t s);
 // Cell key of every vertex (kBoundaryKey for boundary vertices), vals = index.
 hipError_t cell_keys_launch(const float *verts, int64_t nv, const uint8_t *boundary,
                             const double *lo, double c, int64_t n0, int64_t n1, uint32_t *keys,

@@ -222,14 +222,6 @@ hipError_t taubin_launch(float *verts, float *tmp, const int32_t *slots, const i
 // so the mesh is deterministic.
 namespace {
 
-__global__ __launch_bounds__(kBlock) void k_boundary_flags(const uint8_t *__restrict__ fixed,
-                                                           const int32_t *__restrict__ deg,
-                                                           int64_t nv, uint8_t *__restrict__ bnd)
-{
-    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (v < nv) bnd[v] = (fixed[v] && deg[v] > 0) ? 1 : 0;
-}
-
 __global__ __launch_bounds__(kBlock) void k_tri_fill(const int32_t *__restrict__ tris, int64_t nt,
                                                      int32_t *__restrict__ slots,
                                                      uint32_t *__restrict__ cnt,
@@ -263,12 +255,41 @@ __global__ __launch_bounds__(kBlock) void k_tri_sort(int32_t *__restrict__ slots
     tdeg[v] = n;
 }
 
+// Boundary flags of the decimation from the sorted incident-triangle
+// lists: a vertex is on the boundary when some neighbour is reached through
+// exactly one of its triangles.  Per triangle t and vertex v the neighbour
+// entries are the two other corners when v is one corner, the third corner
+// twice when v is two corners, and none for three (the same multiset the
+// neighbour lists of the smoothing collect).  Computed in
+// k_vertex_quadrics: up to 8 triangles, the 16 entries sit in fixed
+// register slots and are sorted by the bitonic network; larger fans count
+// each entry's multiplicity by re-reading their triangles.  More than
+// kNbrCap / 2 triangles set flags (the limit of the neighbour lists this
+// replaces).
+__device__ __forceinline__ void tri_entries(const int32_t *__restrict__ tris, int32_t t, int32_t v,
+                                            int32_t &e0, int32_t &e1)
+{
+    const int32_t a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
+    const int n = (a == v ? 1 : 0) + (b == v ? 1 : 0) + (c == v ? 1 : 0);
+    if (n == 1) {
+        if (a == v) { e0 = b; e1 = c; }
+        else if (b == v) { e0 = c; e1 = a; }
+        else { e0 = a; e1 = b; }
+    } else if (n == 2) {
+        const int32_t u = a != v ? a : (b != v ? b : c);
+        e0 = u;
+        e1 = u;
+    } else {
+        e0 = INT32_MAX;       // no entry (no vertex index reaches INT32_MAX)
+        e1 = INT32_MAX;
+    }
+}
+
 // area-weighted plane quadric of triangle t (upper triangle of the 4x4
 // matrix, row by row), in a fixed operation order
-__device__ void face_quadric(const float *__restrict__ verts, const int32_t *__restrict__ tris,
-                             int64_t t, double K[10])
+__device__ void face_quadric(const float *__restrict__ verts, int64_t ia, int64_t ib, int64_t ic,
+                             double K[10])
 {
-    const int64_t ia = tris[3 * t], ib = tris[3 * t + 1], ic = tris[3 * t + 2];
     const double ax = verts[3 * ia], ay = verts[3 * ia + 1], az = verts[3 * ia + 2];
     const double e1x = (double)verts[3 * ib] - ax, e1y = (double)verts[3 * ib + 1] - ay,
                  e1z = (double)verts[3 * ib + 2] - az;
@@ -291,23 +312,99 @@ __device__ void face_quadric(const float *__restrict__ verts, const int32_t *__r
         for (int j = i; j < 4; ++j) K[k++] = w * (p[i] * p[j]);
 }
 
+// the two neighbour entries of triangle (a, b, c) for vertex v (see
+// tri_entries)
+__device__ __forceinline__ void corner_entries(int32_t a, int32_t b, int32_t c, int32_t v,
+                                               int32_t &e0, int32_t &e1)
+{
+    const int n = (a == v ? 1 : 0) + (b == v ? 1 : 0) + (c == v ? 1 : 0);
+    if (n == 1) {
+        if (a == v) { e0 = b; e1 = c; }
+        else if (b == v) { e0 = c; e1 = a; }
+        else { e0 = a; e1 = b; }
+    } else if (n == 2) {
+        const int32_t u = a != v ? a : (b != v ? b : c);
+        e0 = u;
+        e1 = u;
+    } else {
+        e0 = INT32_MAX;
+        e1 = INT32_MAX;
+    }
+}
+
+// Per vertex: the sum of its triangles' quadrics in ascending triangle
+// order, and its boundary flag (the test described above), from one
+// gather of each incident triangle.
 __global__ __launch_bounds__(kBlock) void k_vertex_quadrics(const float *__restrict__ verts,
                                                             const int32_t *__restrict__ tris,
                                                             const int32_t *__restrict__ slots,
                                                             const int32_t *__restrict__ tdeg,
-                                                            int64_t nv, double *__restrict__ Q)
+                                                            int64_t nv, double *__restrict__ Q,
+                                                            uint8_t *__restrict__ bnd,
+                                                            int32_t *__restrict__ flags)
 {
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (v >= nv) return;
     double q[10];
     for (int k = 0; k < 10; ++k) q[k] = 0.0;
     const int n = tdeg[v];
-    for (int j = 0; j < n; ++j) {
+    const int32_t *s = slots + v * kNbrCap;
+    const int32_t vv = (int32_t)v;
+    if (n > kNbrCap / 2) atomicOr(flags, 1);
+    int32_t r[kRegSort];
+#pragma unroll
+    for (int i = 0; i < kRegSort / 2; ++i) {
+        int32_t e0 = INT32_MAX, e1 = INT32_MAX;
+        if (i < n) {
+            const int32_t t = s[i];
+            const int32_t a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
+            double K[10];
+            face_quadric(verts, a, b, c, K);
+            for (int k = 0; k < 10; ++k) q[k] = q[k] + K[k];
+            corner_entries(a, b, c, vv, e0, e1);
+        }
+        r[2 * i] = e0;
+        r[2 * i + 1] = e1;
+    }
+    for (int j = kRegSort / 2; j < n; ++j) {
+        const int32_t t = s[j];
         double K[10];
-        face_quadric(verts, tris, slots[v * kNbrCap + j], K);
+        face_quadric(verts, tris[3 * t], tris[3 * t + 1], tris[3 * t + 2], K);
         for (int k = 0; k < 10; ++k) q[k] = q[k] + K[k];
     }
     for (int k = 0; k < 10; ++k) Q[10 * v + k] = q[k];
+    bool boundary = false;
+    if (n <= kRegSort / 2) {
+        sort16(r);
+        int run = 0;
+#pragma unroll
+        for (int k = 0; k < kRegSort; ++k) {
+            if (r[k] == INT32_MAX) continue;
+            if (k == 0 || r[k] != r[k - 1]) {
+                if (run == 1) boundary = true;
+                run = 1;
+            } else {
+                ++run;
+            }
+        }
+        if (run == 1) boundary = true;
+    } else if (n <= kNbrCap / 2) {
+        const int E = 2 * n;
+        for (int e = 0; e < E && !boundary; ++e) {
+            int32_t x0, x1;
+            tri_entries(tris, s[e >> 1], vv, x0, x1);
+            const int32_t x = (e & 1) ? x1 : x0;
+            if (x == INT32_MAX) continue;
+            int cnt = 0;
+            for (int f = 0; f < E && cnt < 2; ++f) {
+                int32_t y0, y1;
+                tri_entries(tris, s[f >> 1], vv, y0, y1);
+                if (((f & 1) ? y1 : y0) == x) ++cnt;
+            }
+            if (cnt == 1) boundary = true;
+        }
+    }
+    bnd[v] = boundary ? 1 : 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_points_minmax(const float *__restrict__ verts,
@@ -720,20 +817,12 @@ hipError_t tri_lists_launch(const int32_t *tris, int64_t nt, int64_t nv, int32_t
 }
 
 hipError_t vertex_quadrics_launch(const float *verts, const int32_t *tris, const int32_t *slots,
-                                  const int32_t *tdeg, int64_t nv, double *Q, hipStream_t s)
+                                  const int32_t *tdeg, int64_t nv, double *Q, uint8_t *bnd,
+                                  int32_t *flags, hipStream_t s)
 {
     if (nv == 0) return hipSuccess;
     hipLaunchKernelGGL(k_vertex_quadrics, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, verts,
-                       tris, slots, tdeg, nv, Q);
-    return hipGetLastError();
-}
-
-hipError_t boundary_flags_launch(const uint8_t *fixed, const int32_t *deg, int64_t nv,
-                                 uint8_t *bnd, hipStream_t s)
-{
-    if (nv == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_boundary_flags, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, fixed,
-                       deg, nv, bnd);
+                       tris, slots, tdeg, nv, Q, bnd, flags);
     return hipGetLastError();
 }
 

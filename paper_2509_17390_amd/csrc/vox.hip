@@ -763,19 +763,17 @@ rc_status rc_decimate(rc_ctx *c, const float *verts, int64_t nv, const int32_t *
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(c->mesh_mu);
     Scratch ws(c);
-    int32_t *slots, *deg, *tdeg, *flags;
+    int32_t *slots, *tdeg, *flags;
     uint32_t *cnt, *keys, *vals, *keys2, *vals2, *flag, *gpos, *gid, *gstart, *keep, *tpos, *used,
         *newid, *sums, *cpart;
-    uint8_t *fixed, *bnd;
+    uint8_t *bnd;
     double *Q, *lo;
     float *partial, *box;
     char *sortws;
     const size_t nss = (size_t)mc_scan_sums_len(nv > nt ? nv : nt);
     ws.take(&slots, sizeof(int32_t) * kNbrCap * (size_t)nv);
     ws.take(&cnt, sizeof(uint32_t) * (size_t)nv);
-    ws.take(&deg, sizeof(int32_t) * (size_t)nv);
     ws.take(&tdeg, sizeof(int32_t) * (size_t)nv);
-    ws.take(&fixed, (size_t)nv);
     ws.take(&bnd, (size_t)nv);
     ws.take(&Q, sizeof(double) * 10 * (size_t)nv);
     ws.take(&keys, sizeof(uint32_t) * (size_t)nv);
@@ -806,11 +804,9 @@ rc_status rc_decimate(rc_ctx *c, const float *verts, int64_t nv, const int32_t *
     HIP_TRY(hipStreamSynchronize(s));
     if (hf) return fail(RC_E_INVAL, "invalid mesh:%s%s", (hf & 1) ? " index out of range" : "",
                         (hf & 2) ? " non-finite vertex" : "");
-    // boundary vertices, per-vertex quadrics, box
-    HIP_TRY(nbr_build_launch(tris, nt, nv, slots, cnt, deg, fixed, flags, s));
-    HIP_TRY(boundary_flags_launch(fixed, deg, nv, bnd, s));
+    // incident-triangle lists, boundary vertices, per-vertex quadrics, box
     HIP_TRY(tri_lists_launch(tris, nt, nv, slots, cnt, tdeg, flags, s));
-    HIP_TRY(vertex_quadrics_launch(verts, tris, slots, tdeg, nv, Q, s));
+    HIP_TRY(vertex_quadrics_launch(verts, tris, slots, tdeg, nv, Q, bnd, flags, s));
     HIP_TRY(points_box_launch(verts, nv, partial, box, s));
     float hb[6];
     HIP_TRY(hipMemcpyAsync(hb, box, sizeof hb, hipMemcpyDeviceToHost, s));

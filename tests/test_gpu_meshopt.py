@@ -224,3 +224,25 @@ def test_components_edge_cases(ctx):
     with pytest.raises(rcast.RcastError) as e:
         ctx.remove_small_components(cuda(v), cuda(np.array([[0, -1, 2]], np.int32)), 1)
     assert e.value.status == rcast.RC_E_INVAL
+
+
+def test_decimate_high_valence_vertices(ctx):
+    """Vertices with more than 8 triangles take the boundary test's long
+    path: UV-sphere poles (24 triangles), the hub of an open fan (20), and
+    a closed fan of 40 exceeds the limit of 32."""
+    import torch
+    v, t = synth.uv_sphere((0.1, -0.2, 0.3), 1.0, 24, 16)
+    check_decimate(ctx, v, t, 0.5, tag="uv sphere")
+    k = 20
+    ang = np.linspace(0, 1.5 * np.pi, k + 1)
+    vf = np.concatenate([[[0, 0, 0.1]], np.stack([np.cos(ang), np.sin(ang), 0.05 * ang], 1)])
+    vf = vf.astype(np.float32)
+    tf = np.array([[0, 1 + i, 2 + i] for i in range(k)], np.int32)
+    check_decimate(ctx, vf, tf, 0.5, tag="open fan")
+    k = 40
+    ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
+    vf = np.concatenate([[[0, 0, 0]], np.stack([np.cos(ang), np.sin(ang), 0 * ang], 1)]).astype(np.float32)
+    tf = np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)], np.int32)
+    with pytest.raises(rcast.RcastError) as e:
+        ctx.decimate(cuda(vf), cuda(tf), 0.5)
+    assert e.value.status == rcast.RC_E_INVAL
