@@ -511,8 +511,59 @@ __global__ __launch_bounds__(kBlock) void k_seg_apply(const uint64_t *__restrict
 
 // p = 0 on S_0 (a 6-neighbour with the other V~ value; outside the grid is
 // 0), else 255 (not reached)
+// bytes idx .. idx + 3 of p[0, n) (0 outside it), p 4-byte aligned: two
+// aligned words where they lie inside the buffer, bytes near its ends
+__device__ __forceinline__ uint32_t word_any(const uint8_t *__restrict__ p, int64_t idx, int64_t n)
+{
+    const int64_t a = idx & ~(int64_t)3;
+    if (a >= 0 && a + 8 <= n) {
+        const uint32_t lo = *reinterpret_cast<const uint32_t *>(p + a);
+        const int sh = (int)(idx & 3);
+        if (sh == 0) return lo;
+        const uint32_t hi = *reinterpret_cast<const uint32_t *>(p + a + 4);
+        return __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)sh);
+    }
+    uint32_t w = 0;
+    for (int j = 0; j < 4; ++j) {
+        const int64_t q = idx + j;
+        if (q >= 0 && q < n) w |= (uint32_t)p[q] << (8 * j);
+    }
+    return w;
+}
+
+// p = 0 on S_0 (a 6-neighbour with the other V~ value; outside the grid is
+// 0), else 255 (not reached).  Four voxels per thread (V~ 4-byte aligned:
+// word loads; p has the shell kernel's padding).
 __global__ __launch_bounds__(kBlock) void k_shell0(const uint8_t *__restrict__ vt,
                                                    uint8_t *__restrict__ p, TsdfGrid g)
+{
+    const int64_t i0 = 4 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
+    if (i0 >= g.n) return;
+    const int64_t sxy = (int64_t)g.nx * g.ny;
+    const uint32_t c = word_any(vt, i0, g.n);
+    const uint32_t xm = word_any(vt, i0 - 1, g.n), xp = word_any(vt, i0 + 1, g.n);
+    const uint32_t ym = word_any(vt, i0 - g.nx, g.n), yp = word_any(vt, i0 + g.nx, g.n);
+    const uint32_t zm = word_any(vt, i0 - sxy, g.n), zp = word_any(vt, i0 + sxy, g.n);
+    int x, y, z;
+    coords(i0, g, x, y, z);
+    uint32_t out = 0;
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t cj = byte_of(c, j);
+        const bool edge = (x > 0 ? byte_of(xm, j) : 0u) != cj ||
+                          (x < g.nx - 1 ? byte_of(xp, j) : 0u) != cj ||
+                          (y > 0 ? byte_of(ym, j) : 0u) != cj ||
+                          (y < g.ny - 1 ? byte_of(yp, j) : 0u) != cj ||
+                          (z > 0 ? byte_of(zm, j) : 0u) != cj ||
+                          (z < g.nz - 1 ? byte_of(zp, j) : 0u) != cj;
+        out |= (edge ? 0u : 255u) << (8 * j);
+        step_voxel(g, x, y, z);
+    }
+    *reinterpret_cast<uint32_t *>(p + i0) = out;
+}
+
+// the same, one voxel per thread (V~ not 4-byte aligned)
+__global__ __launch_bounds__(kBlock) void k_shell0_1(const uint8_t *__restrict__ vt,
+                                                     uint8_t *__restrict__ p, TsdfGrid g)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= g.n) return;
@@ -529,7 +580,6 @@ __global__ __launch_bounds__(kBlock) void k_shell0(const uint8_t *__restrict__ v
     p[i] = edge ? 0 : 255;
 }
 
-// shell m: unreached voxels with a 6-neighbour in shell m - 1
 // Shell m: the unreached voxels (255) with a 6-neighbour in shell m - 1.
 // Four voxels per thread as one aligned word: byte-wide loads, one per lane
 // and neighbour, capped the one-voxel form at the rate the memory pipeline
@@ -574,20 +624,34 @@ __global__ __launch_bounds__(kBlock) void k_shell(uint8_t *__restrict__ p, TsdfG
     if (out != c) *reinterpret_cast<uint32_t *>(p + i0) = out;
 }
 
-// phi = clip(s p h, -r, r); s = +1 where the packed outside bit is set
+// phi = clip(s p h, -r, r); s = +1 where the packed outside bit is set.
+// Four voxels per thread (p padded and aligned); one float4 store when phi
+// is 16-byte aligned.
 __global__ __launch_bounds__(kBlock) void k_phi(const uint8_t *__restrict__ p,
                                                 const uint64_t *__restrict__ O,
                                                 float *__restrict__ phi, TsdfGrid g, int W,
-                                                float h, float r)
+                                                float h, float r, int vec)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= g.n) return;
+    const int64_t i0 = 4 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
+    if (i0 >= g.n) return;
+    const uint32_t pw = *reinterpret_cast<const uint32_t *>(p + i0);
     int x, y, z;
-    coords(i, g, x, y, z);
-    const bool out = (O[((int64_t)z * g.ny + y) * W + (x >> 6)] >> (x & 63)) & 1ull;
-    const float delta = p[i] == 255 ? r : (float)p[i] * h;
-    const float s = out ? delta : -delta;
-    phi[i] = fminf(fmaxf(s, -r), r);
+    coords(i0, g, x, y, z);
+    float f[4];
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t pj = byte_of(pw, j);
+        bool out = false;
+        if (i0 + j < g.n) out = (O[((int64_t)z * g.ny + y) * W + (x >> 6)] >> (x & 63)) & 1ull;
+        const float delta = pj == 255u ? r : (float)pj * h;
+        const float sg = out ? delta : -delta;
+        f[j] = fminf(fmaxf(sg, -r), r);
+        step_voxel(g, x, y, z);
+    }
+    if (vec && i0 + 4 <= g.n) {
+        *reinterpret_cast<float4 *>(phi + i0) = make_float4(f[0], f[1], f[2], f[3]);
+    } else {
+        for (int j = 0; i0 + j < g.n && j < 4; ++j) phi[i0 + j] = f[j];
+    }
 }
 
 // ---- marching cubes --------------------------------------------------------
@@ -1127,12 +1191,15 @@ hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint64_t *O, uint8_t 
                                   const TsdfGrid &g, int shells, float h, float r, hipStream_t s)
 {
     const unsigned grid = grid_for(g.n, kBlock);
-    hipLaunchKernelGGL(k_shell0, dim3(grid), dim3(kBlock), 0, s, vt, p, g);
     const unsigned grid4 = grid_for((g.n + 3) / 4, kBlock);
+    if (((uintptr_t)vt & 3) == 0)
+        hipLaunchKernelGGL(k_shell0, dim3(grid4), dim3(kBlock), 0, s, vt, p, g);
+    else
+        hipLaunchKernelGGL(k_shell0_1, dim3(grid), dim3(kBlock), 0, s, vt, p, g);
     for (int m = 1; m <= shells; ++m)
         hipLaunchKernelGGL(k_shell, dim3(grid4), dim3(kBlock), 0, s, p, g, m);
-    hipLaunchKernelGGL(k_phi, dim3(grid), dim3(kBlock), 0, s, p, O, phi, g, tsdf_words_per_row(g),
-                       h, r);
+    hipLaunchKernelGGL(k_phi, dim3(grid4), dim3(kBlock), 0, s, p, O, phi, g, tsdf_words_per_row(g),
+                       h, r, ((uintptr_t)phi & 15) == 0 ? 1 : 0);
     return hipGetLastError();
 }
 
