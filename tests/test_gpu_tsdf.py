@@ -171,3 +171,21 @@ def test_errors(ctx):
                                None, None, 1, 1, ctypes.byref(nv), ctypes.byref(nt),
                                torch.cuda.current_stream().cuda_stream)
     assert st == rcast.RC_E_INVAL
+
+
+@pytest.mark.parametrize("dims", [(150, 40, 37), (128, 17, 33), (65, 70, 18)])
+def test_wide_rows_and_long_columns(ctx, dims):
+    """Rows of several 64-voxel words (ragged and exact) and columns of
+    several 16-row segments, for the packed outside labelling, with both
+    smoothing paths (n = 2 and n = 6), then marching cubes."""
+    nx, ny, nz = dims
+    rng = np.random.default_rng(nx + ny + nz)
+    surf = (rng.random((nz, ny, nx)) < 0.12).astype(np.uint8)
+    # a closed box shell with one hole: its inside is reached only through it
+    surf[4:nz - 4, 5:ny - 5, 6:nx - 6] = 1
+    surf[5:nz - 5, 6:ny - 6, 7:nx - 7] = 0
+    surf[nz // 2, ny // 2, 6] = 0
+    for sigma, tau, band in ((0.02, 0.15, 0.06), (0.035, 0.2, 0.1)):
+        phi, g = check_tsdf(ctx, surf, (0.05, 0.0, -0.1), 0.02, sigma, tau, band,
+                            tag=f"wide {dims} sigma {sigma}")
+    check_mc(ctx, phi, g, (0.05, 0.0, -0.1), 0.02, 0.0, tag=f"wide {dims} mc")
