@@ -189,3 +189,30 @@ def test_wide_rows_and_long_columns(ctx, dims):
         phi, g = check_tsdf(ctx, surf, (0.05, 0.0, -0.1), 0.02, sigma, tau, band,
                             tag=f"wide {dims} sigma {sigma}")
     check_mc(ctx, phi, g, (0.05, 0.0, -0.1), 0.02, 0.0, tag=f"wide {dims} mc")
+
+
+def test_unaligned_output_buffers(ctx):
+    """The surface mask, phi and V~ as views one element into larger
+    buffers (not 4- / 16-byte aligned): the library falls back to its
+    element-wise paths and the results stay bit-exact."""
+    import torch
+    nz, ny, nx = 21, 26, 70
+    rng = np.random.default_rng(5)
+    surf = (rng.random((nz, ny, nx)) < 0.15).astype(np.uint8)
+    g = ctx.grid((0.1, -0.2, 0.3), 0.02, (nx, ny, nz), 0.0)
+    n = nx * ny * nz
+    phi_buf = torch.full((n + 1,), 7.0, dtype=torch.float32, device="cuda")
+    vt_buf = torch.full((n + 1,), 9, dtype=torch.uint8, device="cuda")
+    phi = phi_buf[1:].view(nz, ny, nx)
+    vt = vt_buf[1:].view(nz, ny, nx)
+    assert phi.data_ptr() % 16 != 0 and vt.data_ptr() % 4 != 0
+    surf_buf = torch.zeros((n + 1,), dtype=torch.uint8, device="cuda")
+    surf_buf[1:] = cuda(surf).reshape(-1)
+    surf_d = surf_buf[1:].view(nz, ny, nx)
+    ctx.tsdf(g, surf_d, phi, 0.02, 0.15, 0.06, out_vtilde=vt)
+    torch.cuda.synchronize()
+    phi_o, vt_o, _, _ = ot.tsdf(surf, 0.02, 0.02, 0.15, 0.06)
+    np.testing.assert_array_equal(vt.cpu().numpy(), vt_o)
+    np.testing.assert_array_equal(phi.cpu().numpy().view(np.uint32), phi_o.view(np.uint32))
+    # the elements before the views are untouched
+    assert float(phi_buf[0]) == 7.0 and int(vt_buf[0]) == 9
