@@ -832,16 +832,21 @@ def run_voxelize(args):
     return 0
 
 
-# Narrow-band TSDF + marching cubes: algorithmic HBM bytes per voxel of each
-# pass (reads + writes of the dense arrays; neighbour re-reads hit the caches)
 # components of fewer triangles are removed after decimation (specks left
 # by floaters; a 30 cm object at the 6 cm decimation cell has ~150 faces)
 MIN_COMPONENT_FACES = 32
 
+# Narrow-band TSDF + marching cubes: HBM bytes per voxel of each pass as
+# built (reads + writes of the dense arrays; neighbour re-reads hit the
+# caches): smoothing u8 -> u8 -> u16 -> V~ (kernels of up to 3 steps, as
+# here), labels packed to 2 bits, shells in bytes, phi float32, the
+# marching-cubes count writing mask, case and two u32 counts, two scans,
+# and the emit pass reading mask and case (the surface points' outputs are
+# counted separately)
 TSDF_PASS_BYTES = {
-    "smooth_x": 1 + 4, "smooth_y": 4 + 8, "smooth_z": 8 + 1, "flood_init": 1 + 1,
-    "flood_sweep": 1 + 1, "shell0": 1 + 1, "shell": 1 + 1, "phi": 1 + 1 + 4,
-    "mc_count": 4 + 1 + 4 + 4, "mc_scans": 2 * (4 + 4 + 4), "mc_emit": 4 + 1 + 4 + 4,
+    "smooth_x": 1 + 1, "smooth_y": 1 + 2, "smooth_z": 2 + 1, "pack": 1 + 0.25,
+    "flood_sweep": 0.375, "shell0": 1 + 1, "shell": 1 + 1, "phi": 1 + 0.125 + 4,
+    "mc_count": 4 + 1 + 1 + 4 + 4, "mc_scans": 2 * (4 + 4 + 4), "mc_emit": 1 + 1,
 }
 
 
@@ -974,7 +979,7 @@ def run_mesh(args):
     per_vox = (sum(v for k, v in TSDF_PASS_BYTES.items() if k != "shell")
                + P * TSDF_PASS_BYTES["shell"])
     # outputs: 12 B position + 12 B normal per vertex, 12 B per triangle
-    alg_bytes = per_vox * n_vox + 24 * int(verts.shape[0]) + 12 * int(tris.shape[0])
+    alg_bytes = int(per_vox * n_vox) + 24 * int(verts.shape[0]) + 12 * int(tris.shape[0])
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
     cpu = None
     if not args.no_cpu:
