@@ -63,9 +63,8 @@ hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint64_t *O, uint8_t 
 void mc_table_copy(uint8_t *count, int8_t *tri);
 int64_t mc_scan_sums_len(int64_t n);
 hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
-                           uint8_t *mask, uint8_t *cases, uint32_t *vcount, uint32_t *tcount,
-                           uint32_t *voff, uint32_t *toff, uint32_t *vsums, uint32_t *tsums,
-                           hipStream_t s);
+                           uint8_t *mask, uint8_t *cases, uint32_t *voff, uint32_t *toff,
+                           uint32_t *vsums, uint32_t *tsums, hipStream_t s);
 hipError_t mc_emit_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
                           const int8_t *tris_of, const uint8_t *mask, const uint8_t *cases,
                           const uint32_t *voff, const uint32_t *toff, float *verts, int32_t *tris,

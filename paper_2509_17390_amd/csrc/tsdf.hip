@@ -665,12 +665,8 @@ __global__ __launch_bounds__(kBlock) void k_phi(const uint8_t *__restrict__ p,
 // whose +x neighbour lies on the next row never use it: the coordinate
 // tests exclude them, and indices at or past n are never loaded.
 __global__ __launch_bounds__(kBlock) void k_mc_count4(const float *__restrict__ phi, TsdfGrid g,
-                                                      float iso,
-                                                      const uint8_t *__restrict__ ntri,
-                                                      uint8_t *__restrict__ mask,
-                                                      uint8_t *__restrict__ cases,
-                                                      uint32_t *__restrict__ vcount,
-                                                      uint32_t *__restrict__ tcount)
+                                                      float iso, uint8_t *__restrict__ mask,
+                                                      uint8_t *__restrict__ cases)
 {
     const int64_t i0 = 4 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
     if (i0 >= g.n) return;
@@ -689,7 +685,7 @@ __global__ __launch_bounds__(kBlock) void k_mc_count4(const float *__restrict__ 
     }
     int x, y, z;
     coords(i0, g, x, y, z);
-    uint32_t mw = 0, cw = 0, vc[4], tc[4];
+    uint32_t mw = 0, cw = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const bool in = (bits[0] >> j) & 1u;
@@ -705,21 +701,15 @@ __global__ __launch_bounds__(kBlock) void k_mc_count4(const float *__restrict__ 
         }
         mw |= (uint32_t)m << (8 * j);
         cw |= (uint32_t)cs << (8 * j);
-        vc[j] = (uint32_t)__popc(m);
-        tc[j] = ntri[cs];
         step_voxel(g, x, y, z);
     }
     if (i0 + 4 <= g.n) {
         *reinterpret_cast<uint32_t *>(mask + i0) = mw;
         *reinterpret_cast<uint32_t *>(cases + i0) = cw;
-        *reinterpret_cast<uint4 *>(vcount + i0) = make_uint4(vc[0], vc[1], vc[2], vc[3]);
-        *reinterpret_cast<uint4 *>(tcount + i0) = make_uint4(tc[0], tc[1], tc[2], tc[3]);
     } else {
         for (int j = 0; i0 + j < g.n; ++j) {
             mask[i0 + j] = (uint8_t)(mw >> (8 * j));
             cases[i0 + j] = (uint8_t)(cw >> (8 * j));
-            vcount[i0 + j] = vc[j];
-            tcount[i0 + j] = tc[j];
         }
     }
 }
@@ -896,6 +886,58 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const uint32_t *__restric
         run += v[k];
     }
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Marching-cubes scan tiles: the vertex count (edges set in the mask) and
+// the triangle count (of the cell's case) of each point are formed here
+// from the count pass's two bytes, and both are scanned in one pass (two
+// u32 count arrays written and read back cost 16 bytes per point).
+__global__ __launch_bounds__(kBlock) void k_mc_scan_tiles(const uint8_t *__restrict__ mask,
+                                                          const uint8_t *__restrict__ cases,
+                                                          const uint8_t *__restrict__ ntri,
+                                                          int64_t n, uint32_t *__restrict__ voff,
+                                                          uint32_t *__restrict__ toff,
+                                                          uint32_t *__restrict__ vsums,
+                                                          uint32_t *__restrict__ tsums)
+{
+    static_assert(kScanItems == 4, "one word of mask and case bytes per thread");
+    __shared__ uint8_t nt_lds[256];
+    nt_lds[threadIdx.x] = ntri[threadIdx.x];              // kBlock == 256 cases
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t mw = 0, cw = 0;
+    if (base + 4 <= n) {                                  // base is a multiple of 4
+        mw = *reinterpret_cast<const uint32_t *>(mask + base);
+        cw = *reinterpret_cast<const uint32_t *>(cases + base);
+    } else {
+        for (int k = 0; base + k < n && k < 4; ++k) {
+            mw |= (uint32_t)mask[base + k] << (8 * k);
+            cw |= (uint32_t)cases[base + k] << (8 * k);
+        }
+    }
+    uint32_t vc[kScanItems], tc[kScanItems], sv = 0, st = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        const bool in = base + k < n;
+        vc[k] = in ? (uint32_t)__popc((mw >> (8 * k)) & 0xffu) : 0u;
+        tc[k] = in ? (uint32_t)nt_lds[(cw >> (8 * k)) & 0xffu] : 0u;
+        sv += vc[k];
+        st += tc[k];
+    }
+    uint32_t totv, tott;
+    uint32_t rv = block_scan_excl(sv, &totv);
+    uint32_t rt = block_scan_excl(st, &tott);
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) {
+            voff[base + k] = rv;
+            toff[base + k] = rt;
+        }
+        rv += vc[k];
+        rt += tc[k];
+    }
+    if (threadIdx.x == 0) {
+        vsums[blockIdx.x] = totv;
+        tsums[blockIdx.x] = tott;
+    }
 }
 
 // one block: exclusive scan of the tile sums in place, grand total after
@@ -1204,15 +1246,19 @@ hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint64_t *O, uint8_t 
 }
 
 hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
-                           uint8_t *mask, uint8_t *cases, uint32_t *vcount, uint32_t *tcount,
-                           uint32_t *voff, uint32_t *toff, uint32_t *vsums, uint32_t *tsums,
-                           hipStream_t s)
+                           uint8_t *mask, uint8_t *cases, uint32_t *voff, uint32_t *toff,
+                           uint32_t *vsums, uint32_t *tsums, hipStream_t s)
 {
     hipLaunchKernelGGL(k_mc_count4, dim3(grid_for((g.n + 3) / 4, kBlock)), dim3(kBlock), 0, s, phi,
-                       g, iso, ntri, mask, cases, vcount, tcount);
-    hipError_t e = scan_launch(vcount, voff, g.n, vsums, s);
-    if (e == hipSuccess) e = scan_launch(tcount, toff, g.n, tsums, s);
-    return e;
+                       g, iso, mask, cases);
+    const int64_t nb = (g.n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_mc_scan_tiles, dim3((unsigned)nb), dim3(kBlock), 0, s, mask, cases, ntri,
+                       g.n, voff, toff, vsums, tsums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, vsums, (int)nb);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, tsums, (int)nb);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kBlock), 0, s, voff, g.n, vsums);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kBlock), 0, s, toff, g.n, tsums);
+    return hipGetLastError();
 }
 
 hipError_t mc_emit_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,

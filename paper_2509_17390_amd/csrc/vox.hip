@@ -502,19 +502,17 @@ rc_status rc_marching_cubes(rc_ctx *c, const rc_grid *grid, const float *phi, fl
     std::lock_guard<std::mutex> lk(c->mesh_mu);
     Scratch ws(c);
     uint8_t *mask, *cases;
-    uint32_t *vc, *tc, *voff, *toff, *vs, *ts;
+    uint32_t *voff, *toff, *vs, *ts;
     const int64_t ns = mc_scan_sums_len(g.n);
     ws.take(&mask, g.n);
     ws.take(&cases, g.n);
-    ws.take(&vc, sizeof(uint32_t) * g.n);
-    ws.take(&tc, sizeof(uint32_t) * g.n);
     ws.take(&voff, sizeof(uint32_t) * g.n);
     ws.take(&toff, sizeof(uint32_t) * g.n);
     ws.take(&vs, sizeof(uint32_t) * ns);
     ws.take(&ts, sizeof(uint32_t) * ns);
     st = ws.commit();
     if (st != RC_OK) return st;
-    HIP_TRY(mc_count_launch(phi, g, iso, ntri, mask, cases, vc, tc, voff, toff, vs, ts, s));
+    HIP_TRY(mc_count_launch(phi, g, iso, ntri, mask, cases, voff, toff, vs, ts, s));
     uint32_t tot[2];
     HIP_TRY(hipMemcpyAsync(&tot[0], vs + ns - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&tot[1], ts + ns - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
