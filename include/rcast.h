@@ -469,7 +469,7 @@ typedef struct {
 /* TSDF of the DEVICE uint8 surface mask `surf` [nz][ny][nx] into the DEVICE
  * float32 `out_phi` (same layout); `out_vtilde` (DEVICE uint8, or NULL)
  * receives V~.  Runs on `stream` and returns when phi is complete (the
- * outside labelling repeats until it settles, reading a flag each sweep).
+ * outside labelling repeats until it settles, reading a flag each round).
  * Scratch device memory of about 14 bytes per voxel is kept by the context
  * (grown on demand, reused by later calls, freed by rc_destroy).
  * Errors: RC_E_INVAL (grid, options), RC_E_NOMEM, RC_E_DEVICE. */
