@@ -108,8 +108,21 @@ typedef struct {
 rc_status rc_lbvh_build(rc_ctx *ctx, int32_t scene, const rc_build_opts *opts,
                         void *stream);
 
-/* Drop a scene.  Waits for the device to finish outstanding work, then
- * frees the scene's memory.  Errors: RC_E_NOTFOUND. */
+/* Drop a scene (the mesh M of Sec. IV-C stays resident for every cast that
+ * uses it).  The handle is invalid from the moment the call returns: new
+ * casts, builds and requests naming it fail with RC_E_NOTFOUND.  The
+ * scene's memory is reference-counted and its free deferred while it is in
+ * use: every cast, build or served batch that resolved the scene before the
+ * release holds a reference until its device work has finished, and a graph
+ * (rc_graph_create) holds one until it is destroyed.  When the last one
+ * goes, the memory is freed by the next call into the context that reclaims
+ * it (rc_scene_upload, rc_lbvh_build, rc_scene_release, rc_pattern_upload,
+ * rc_scene_get_info, rc_device_bytes, rc_graph_destroy, rc_destroy) or by
+ * the request server; a scene not in use is freed at once.  Never waits
+ * for the device.  Casts enqueued on a stream that is being captured into
+ * the caller's own graph hold no reference past the call: the caller keeps
+ * their scenes until that graph is destroyed.  Errors: RC_E_NOTFOUND
+ * (unknown or already released scene). */
 rc_status rc_scene_release(rc_ctx *ctx, int32_t scene);
 
 /* Copy a scan pattern (the unit directions d_j of Sec. IV-C) in.
@@ -190,7 +203,9 @@ enum { RC_DBG_MORTON = 1, RC_DBG_SORTED = 2, RC_DBG_TOPOLOGY = 3,
 rc_status rc_scene_debug_copy(rc_ctx *ctx, int32_t scene, int32_t what,
                               void *host_dst, uint64_t bytes);
 
-/* Bytes the context currently holds on the device. */
+/* Bytes the context currently holds on the device (a mock context counts
+ * the host copies of its scenes' vertices).  Frees released scenes whose
+ * last reference has gone first. */
 uint64_t rc_device_bytes(rc_ctx *ctx);
 
 /* Launch shape of the traversal.  Every setting gives bit-identical results
@@ -251,8 +266,9 @@ rc_status rc_autotune(rc_ctx *ctx, const rc_job *jobs, int32_t n_jobs, float *ou
  * replay, e.g. once per simulation frame.  The job table (scenes, patterns,
  * pose and output pointers, ranges, offsets) and the context's tuning are
  * fixed at creation; callers update pose contents in place between
- * replays.  Scenes must outlive the graph; rebuilding a scene's BVH in place
- * is allowed (ordered on the stream before the replay).  The graph holds no
+ * replays.  The graph holds a reference to each of its scenes until it is
+ * destroyed (a release meanwhile defers the free); rebuilding a scene's BVH
+ * in place is allowed (ordered on the stream before the replay).  The graph holds no
  * hipMemset node.  Replays on one graph must not overlap (they share the
  * graph's work queues): order them on one stream.
  * Errors: as rc_raycast_batch; RC_E_DEVICE if capture fails. */
@@ -271,9 +287,10 @@ void rc_graph_destroy(rc_graph *graph);
  * max_batch_rays_m million rays), and up to max_inflight launches run at
  * once on separate streams.  Each request's
  * results are bit-identical to casting it alone with rc_raycast_batch.
- * Scenes and patterns must stay resident while their requests are queued
- * or running (a request whose scene was released fails with
- * RC_E_NOTFOUND). */
+ * A request whose scene is released while it is still queued fails with
+ * RC_E_NOTFOUND; once its batch has been launched, the release defers the
+ * scene's free until the batch has finished and the request completes
+ * normally.  Patterns stay resident until rc_destroy. */
 typedef struct {
     int32_t scene;
     int32_t pattern;
@@ -300,7 +317,11 @@ typedef struct {
                                  older ones first in arrival order           */
     int32_t max_wait_ms;      /* policy 1: age after which a request goes
                                  ahead of younger ones (0 = 200 ms)          */
-    int32_t reserved[2];
+    int32_t mock_launch_delay_us; /* mock context: pause between resolving a
+                                 batch's scenes and handing it to the
+                                 simulated device (tests of a release racing
+                                 a launch; 0 = none)                         */
+    int32_t reserved[1];
 } rc_serve_opts;
 
 typedef struct {

@@ -81,6 +81,12 @@ void free_bvh(rc_ctx *c, Scene &s)
 
 void free_scene(rc_ctx *c, Scene &s)
 {
+    if (c->mock) {
+        free(s.host_verts);
+        c->used -= s.bytes;
+        s = Scene();
+        return;
+    }
     free_bvh(c, s);
     dev_free(c, s.verts, sizeof(float) * 3 * s.nv);
     dev_free(c, s.tris, sizeof(int32_t) * 3 * s.nt);
@@ -88,10 +94,87 @@ void free_scene(rc_ctx *c, Scene &s)
     s = Scene();
 }
 
+// A live (uploaded, not released) scene, or null.
 Scene *get_scene(rc_ctx *c, int32_t id)
 {
-    if (id < 0 || id >= (int32_t)c->scenes.size() || !c->scenes[id].alive) return nullptr;
-    return &c->scenes[id];
+    if (id < 0 || id >= (int32_t)c->scenes.size()) return nullptr;
+    Scene &s = c->scenes[id];
+    return s.alive && !s.dead ? &s : nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// Scene references.  `dead` is written with both c->mu and c->ref_mu held,
+// so it may be read under either; `refs` only under c->ref_mu.
+
+void hold_scene(rc_ctx *c, Scene *s)
+{
+    std::lock_guard<std::mutex> lk(c->ref_mu);
+    ++s->refs;
+}
+
+void drop_holds(rc_ctx *c, Scene *const *s, size_t n)
+{
+    std::lock_guard<std::mutex> lk(c->ref_mu);
+    for (size_t i = 0; i < n; ++i)
+        if (--s[i]->refs == 0 && s[i]->dead) c->reap.push_back(s[i]);
+}
+
+void reap_locked(rc_ctx *c)
+{
+    std::vector<Scene *> r;
+    {
+        std::lock_guard<std::mutex> lk(c->ref_mu);
+        if (c->reap.empty()) return;
+        r.swap(c->reap);
+    }
+    for (Scene *s : r) free_scene(c, *s);
+}
+
+namespace {
+
+// Host function behind a launch or build: no HIP call, no c->mu.
+void drop_host_fn(void *arg)
+{
+    DropRec *d = static_cast<DropRec *>(arg);
+    rc_ctx *c = d->c;
+    drop_holds(c, d->held.data(), d->held.size());
+    delete d;
+    std::lock_guard<std::mutex> lk(c->ref_mu);
+    --c->pending_drops;
+    c->ref_cv.notify_all();
+}
+
+bool stream_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+}  // namespace
+
+rc_status drop_after(rc_ctx *c, hipStream_t s, std::vector<Scene *> &held)
+{
+    if (held.empty()) return RC_OK;
+    if (stream_capturing(s)) {
+        drop_holds(c, held.data(), held.size());
+        held.clear();
+        return RC_OK;
+    }
+    DropRec *d = new DropRec();
+    d->c = c;
+    d->held.swap(held);
+    {
+        std::lock_guard<std::mutex> lk(c->ref_mu);
+        ++c->pending_drops;
+    }
+    hipError_t e = hipLaunchHostFunc(s, drop_host_fn, d);
+    if (e != hipSuccess) {
+        // no host function: wait for the stream, then drop here
+        (void)hipStreamSynchronize(s);
+        drop_host_fn(d);
+        return fail(RC_E_DEVICE, "hipLaunchHostFunc failed: %s", hipGetErrorString(e));
+    }
+    return RC_OK;
 }
 
 Pattern *get_pattern(rc_ctx *c, int32_t id)
@@ -139,19 +222,29 @@ rc_tuning default_tuning()
 }
 
 // Build the device job table for a batch; shared by every trace entry point.
+// out[] and held[] have room for n_jobs entries; *n_out jobs are written,
+// and held[k] is the scene of out[k], referenced on return (the caller drops
+// the references, also when this call fails: *n_out says how many).  With
+// `skipped`, a job whose scene or pattern is gone (or has no BVH) is left
+// out and its index listed instead of failing the call.
 rc_status prepare_jobs(rc_ctx *c, const rc_tuning &tuning, const rc_job *jobs, int32_t n_jobs,
-                       std::vector<DevJob> &out, int64_t &total, int &fmt)
+                       DevJob *out, Scene **held, int *n_out, int64_t &total, int &fmt,
+                       std::vector<int> *skipped)
 {
-    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(RC_E_INVAL, "bad job list");
-    out.resize(n_jobs);
+    *n_out = 0;
     total = 0;
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(RC_E_INVAL, "bad job list");
     bool all_q8 = true;
     std::lock_guard<std::mutex> lk(c->mu);
     for (int i = 0; i < n_jobs; ++i) {
         const rc_job &j = jobs[i];
         Scene *s = get_scene(c, j.scene);
-        if (!s) return fail(RC_E_NOTFOUND, "job %d: unknown scene %d", i, j.scene);
         Pattern *p = get_pattern(c, j.pattern);
+        if (skipped && (!s || !p || (s->nt > 0 && !s->has_bvh))) {
+            skipped->push_back(i);
+            continue;
+        }
+        if (!s) return fail(RC_E_NOTFOUND, "job %d: unknown scene %d", i, j.scene);
         if (!p) return fail(RC_E_NOTFOUND, "job %d: unknown pattern %d", i, j.pattern);
         if (s->nt > 0 && !s->has_bvh)
             return fail(RC_E_STATE, "job %d: scene %d has no BVH (call rc_lbvh_build)", i, j.scene);
@@ -162,7 +255,10 @@ rc_status prepare_jobs(rc_ctx *c, const rc_tuning &tuning, const rc_job *jobs, i
         if (j.out_offset < 0) return fail(RC_E_INVAL, "job %d: out_offset < 0", i);
         int64_t nr = (int64_t)j.n_envs * p->n_beams;
         if (nr > (int64_t)0x7fffffff) return fail(RC_E_INVAL, "job %d: more than 2^31-1 rays", i);
-        DevJob &d = out[i];
+        const int k = (*n_out)++;
+        hold_scene(c, s);
+        held[k] = s;
+        DevJob &d = out[k];
         d.nodes = s->nodes;
         if (s->node_format != RC_NODE_Q8) all_q8 = false;
         d.tris = s->trirecs;
@@ -181,9 +277,9 @@ rc_status prepare_jobs(rc_ctx *c, const rc_tuning &tuning, const rc_job *jobs, i
         total += nr;
     }
     // quantised nodes only when every scene of the launch has them
-    fmt = (all_q8 && n_jobs > 0) ? FMT_Q8 : FMT_BINARY;
+    fmt = (all_q8 && *n_out > 0) ? FMT_Q8 : FMT_BINARY;
     if (fmt == FMT_Q8)
-        for (int i = 0; i < n_jobs; ++i) out[i].nodes = get_scene(c, jobs[i].scene)->q8nodes;
+        for (int k = 0; k < *n_out; ++k) out[k].nodes = held[k]->q8nodes;
     return RC_OK;
 }
 
@@ -201,6 +297,8 @@ rc_status stage_jobs(rc_ctx *c, const std::vector<DevJob> &dj, int64_t total, hi
         int cap = 64;
         while (cap < need) cap *= 2;
         if (sl.host) (void)hipHostFree(sl.host);
+        // c->used is guarded by c->mu (taken inside job_mu, never the other way)
+        std::lock_guard<std::mutex> lk(c->mu);
         if (sl.dev) dev_free(c, sl.dev, slot_bytes(sl.cap));
         sl.host = nullptr;
         sl.dev = nullptr;
@@ -273,10 +371,11 @@ rc_status stage_own(rc_ctx *c, StageBuf &b, const std::vector<DevJob> &dj, int64
     return RC_OK;
 }
 
-// Stage and launch one batch; `forced` overrides the context's tuning.
+// Stage and launch one batch; `forced` overrides the context's tuning.  The
+// batch's scenes stay referenced until the launch has finished.
 rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, float *out_range,
                        int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, void *stream,
-                       const rc_tuning *forced, StageBuf *own)
+                       const rc_tuning *forced, StageBuf *own, std::vector<int> *skipped)
 {
     if (!c) return fail(RC_E_INVAL, "null context");
     if (c->mock) return fail(RC_E_STATE, "a mock context has no device to cast on");
@@ -285,10 +384,22 @@ rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, 
         std::lock_guard<std::mutex> lk(c->job_mu);
         tuning = forced ? *forced : c->tuning;
     }
-    std::vector<DevJob> dj;
+    const size_t cap = n_jobs > 0 ? (size_t)n_jobs : 0;
+    std::vector<DevJob> dj(cap);
+    std::vector<Scene *> held(cap);
+    int n_run = 0;
     int64_t total = 0;
     int fmt = FMT_BINARY;
-    rc_status st = prepare_jobs(c, tuning, jobs, n_jobs, dj, total, fmt);
+    rc_status st = prepare_jobs(c, tuning, jobs, n_jobs, dj.data(), held.data(), &n_run, total,
+                                fmt, skipped);
+    dj.resize(n_run);
+    held.resize(n_run);
+    // until the launch is enqueued, a failure drops the references here
+    struct Guard {
+        rc_ctx *c;
+        std::vector<Scene *> &h;
+        ~Guard() { if (!h.empty()) drop_holds(c, h.data(), h.size()); }
+    } guard{c, held};
     if (st != RC_OK) return st;
     if (total == 0) return RC_OK;
     if (!out_range || !out_hit) return fail(RC_E_INVAL, "null output");
@@ -297,22 +408,28 @@ rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     DevJob *djd = nullptr;
     WorkQueues *dq = nullptr;
+    hipError_t e = hipSuccess;
     if (own) {
         st = stage_own(c, *own, dj, total, s, &djd, &dq);
         if (st != RC_OK) return st;
-        HIP_TRY(trace_launch(mode, fmt, config_of(tuning), djd, n_jobs, dq, total, out_range,
-                             out_hit, out_nodes, out_tris, s));
-        return RC_OK;
+        e = trace_launch(mode, fmt, config_of(tuning), djd, n_run, dq, total, out_range, out_hit,
+                         out_nodes, out_tris, s);
+    } else {
+        std::lock_guard<std::mutex> lk(c->job_mu);
+        JobSlot *slot = nullptr;
+        st = stage_jobs(c, dj, total, s, &djd, &dq, &slot);
+        if (st != RC_OK) return st;
+        e = trace_launch(mode, fmt, config_of(tuning), djd, n_run, dq, total, out_range, out_hit,
+                         out_nodes, out_tris, s);
+        if (e == hipSuccess) e = hipEventRecord(slot->done, s);
+        if (e == hipSuccess) slot->used = true;
     }
-    std::lock_guard<std::mutex> lk(c->job_mu);
-    JobSlot *slot = nullptr;
-    st = stage_jobs(c, dj, total, s, &djd, &dq, &slot);
-    if (st != RC_OK) return st;
-    HIP_TRY(trace_launch(mode, fmt, config_of(tuning), djd, n_jobs, dq, total, out_range, out_hit,
-                         out_nodes, out_tris, s));
-    HIP_TRY(hipEventRecord(slot->done, s));
-    slot->used = true;
-    return RC_OK;
+    if (e != hipSuccess) {
+        // part of the batch may be on the device: let it finish first
+        (void)hipStreamSynchronize(s);
+        return fail(RC_E_DEVICE, "traversal launch failed: %s", hipGetErrorString(e));
+    }
+    return drop_after(c, s, held);
 }
 
 rc_status ensure_build_ws(rc_ctx *c, size_t need, hipStream_t s)
@@ -381,11 +498,18 @@ void rc_destroy(rc_ctx *c)
     if (!c) return;
     serve_shutdown(c);
     if (c->mock) {
+        for (auto &s : c->scenes)
+            if (s.alive) free_scene(c, s);
         delete c;
         return;
     }
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
+    {
+        // every drop host function has run before the scenes go
+        std::unique_lock<std::mutex> lk(c->ref_mu);
+        c->ref_cv.wait(lk, [&] { return c->pending_drops == 0; });
+    }
     for (auto &s : c->scenes)
         if (s.alive) free_scene(c, s);
     for (auto &p : c->patterns)
@@ -420,17 +544,38 @@ rc_status rc_scene_upload(rc_ctx *c, const float *verts, int64_t nv, const int32
         for (int64_t i = 0; i < 3 * nv; ++i)
             if (!isfinite(verts[i])) return fail(RC_E_INVAL, "invalid mesh: non-finite vertex");
         std::lock_guard<std::mutex> lk(c->mu);
+        reap_locked(c);
         Scene sc;
-        sc.alive = true;
         sc.nv = nv;
         sc.nt = nt;
-        c->scenes.push_back(sc);
-        *out_scene = (int32_t)c->scenes.size() - 1;
+        // the host copy of the vertices is the mock scene's "device" memory
+        sc.bytes = sizeof(float) * 3 * (uint64_t)(nv > 0 ? nv : 1);
+        if (c->budget && c->used + sc.bytes > c->budget)
+            return fail(RC_E_NOMEM, "device budget exceeded: %llu + %llu > %llu bytes",
+                        (unsigned long long)c->used, (unsigned long long)sc.bytes,
+                        (unsigned long long)c->budget);
+        sc.host_verts = static_cast<float *>(malloc(sc.bytes));
+        if (!sc.host_verts) return fail(RC_E_NOMEM, "host copy of the mock scene");
+        if (nv > 0) memcpy(sc.host_verts, verts, sizeof(float) * 3 * nv);
+        for (int64_t i = 0; i < 3 * nv; ++i) sc.host_sum += sc.host_verts[i];
+        c->used += sc.bytes;
+        sc.alive = true;
+        int32_t id = -1;
+        for (size_t i = 0; i < c->scenes.size(); ++i)
+            if (!c->scenes[i].alive) { id = (int32_t)i; break; }
+        if (id < 0) {
+            id = (int32_t)c->scenes.size();
+            c->scenes.push_back(sc);
+        } else {
+            c->scenes[id] = sc;
+        }
+        *out_scene = id;
         return RC_OK;
     }
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(c->mu);
+    reap_locked(c);
     Scene sc;
     sc.nv = nv;
     sc.nt = nt;
@@ -498,6 +643,7 @@ rc_status rc_lbvh_build(rc_ctx *c, int32_t scene, const rc_build_opts *opts, voi
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(c->mu);
+    reap_locked(c);
     Scene *sc = get_scene(c, scene);
     if (!sc) return fail(RC_E_NOTFOUND, "unknown scene %d", scene);
     const int64_t nt = sc->nt, ni = nt > 1 ? nt - 1 : 1;
@@ -538,9 +684,20 @@ rc_status rc_lbvh_build(rc_ctx *c, int32_t scene, const rc_build_opts *opts, voi
         b.depth_out = reinterpret_cast<int32_t *>(sc->box_dev + 6);
         b.q8nodes = fmt == RC_NODE_Q8 ? sc->q8nodes : nullptr;
         b.q8_count = reinterpret_cast<uint32_t *>(sc->box_dev + 7);
-        HIP_TRY(lbvh_build_launch(b, s));
-        HIP_TRY(hipEventRecord(c->ws_event, s));
+        // the build's kernels read and write the scene: it stays referenced
+        // until they have finished
+        hold_scene(c, sc);
+        std::vector<Scene *> held(1, sc);
+        hipError_t e = lbvh_build_launch(b, s);
+        if (e == hipSuccess) e = hipEventRecord(c->ws_event, s);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(s);
+            drop_holds(c, held.data(), 1);
+            return fail(RC_E_DEVICE, "LBVH build failed: %s", hipGetErrorString(e));
+        }
         c->ws_event_recorded = true;
+        rc_status st2 = drop_after(c, s, held);
+        if (st2 != RC_OK) return st2;
     }
     sc->has_bvh = true;
     sc->morton_bits = bits;
@@ -551,19 +708,19 @@ rc_status rc_lbvh_build(rc_ctx *c, int32_t scene, const rc_build_opts *opts, voi
 rc_status rc_scene_release(rc_ctx *c, int32_t scene)
 {
     if (!c) return fail(RC_E_INVAL, "null context");
-    if (c->mock) {
-        std::lock_guard<std::mutex> lk(c->mu);
-        Scene *sc = get_scene(c, scene);
-        if (!sc) return fail(RC_E_NOTFOUND, "unknown scene %d", scene);
-        *sc = Scene();
-        return RC_OK;
-    }
-    HIP_TRY(hipSetDevice(c->device));
+    if (!c->mock) HIP_TRY(hipSetDevice(c->device));
     std::lock_guard<std::mutex> lk(c->mu);
+    reap_locked(c);
     Scene *sc = get_scene(c, scene);
     if (!sc) return fail(RC_E_NOTFOUND, "unknown scene %d", scene);
-    HIP_TRY(hipDeviceSynchronize());
-    free_scene(c, *sc);
+    bool now = false;
+    {
+        std::lock_guard<std::mutex> rl(c->ref_mu);
+        sc->dead = true;
+        now = sc->refs == 0;
+    }
+    // in use: the last reference to go puts it on the reap list instead
+    if (now) free_scene(c, *sc);
     return RC_OK;
 }
 
@@ -591,6 +748,7 @@ rc_status rc_pattern_upload(rc_ctx *c, const float *dirs, int32_t n_beams, int32
     }
     HIP_TRY(hipSetDevice(c->device));
     std::lock_guard<std::mutex> lk(c->mu);
+    reap_locked(c);
     Pattern p;
     p.n_beams = n_beams;
     p.n_az = n_az_hint > 0 ? n_az_hint : n_beams;
@@ -653,6 +811,7 @@ rc_status rc_scene_get_info(rc_ctx *c, int32_t scene, rc_scene_info *out)
     }
     HIP_TRY(hipSetDevice(c->device));
     std::lock_guard<std::mutex> lk(c->mu);
+    reap_locked(c);
     Scene *sc = get_scene(c, scene);
     if (!sc) return fail(RC_E_NOTFOUND, "unknown scene %d", scene);
     memset(out, 0, sizeof *out);
@@ -715,7 +874,14 @@ rc_status rc_scene_debug_copy(rc_ctx *c, int32_t scene, int32_t what, void *dst,
     return RC_OK;
 }
 
-uint64_t rc_device_bytes(rc_ctx *c) { return c ? c->used : 0; }
+uint64_t rc_device_bytes(rc_ctx *c)
+{
+    if (!c) return 0;
+    if (!c->mock) (void)hipSetDevice(c->device);
+    std::lock_guard<std::mutex> lk(c->mu);
+    reap_locked(c);
+    return c->used;
+}
 
 rc_status rc_set_tuning(rc_ctx *c, const rc_tuning *t)
 {
@@ -858,6 +1024,7 @@ rc_status rc_get_tuning(rc_ctx *c, rc_tuning *t)
 
 struct rc_graph {
     rc_ctx *ctx = nullptr;
+    std::vector<Scene *> held;   // the graph's scenes, referenced until it is destroyed
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
@@ -879,15 +1046,27 @@ rc_status rc_graph_create(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *
         std::lock_guard<std::mutex> lk(c->job_mu);
         tuning = c->tuning;
     }
-    std::vector<DevJob> dj;
+    const size_t cap = n_jobs > 0 ? (size_t)n_jobs : 0;
+    std::vector<DevJob> dj(cap);
+    std::vector<Scene *> held(cap);
+    int n_run = 0;
     int64_t total = 0;
     int fmt = FMT_BINARY;
-    rc_status st = prepare_jobs(c, tuning, jobs, n_jobs, dj, total, fmt);
-    if (st != RC_OK) return st;
-    if (total > 0 && (!out_range || !out_hit)) return fail(RC_E_INVAL, "null output");
-    HIP_TRY(hipSetDevice(c->device));
+    rc_status st = prepare_jobs(c, tuning, jobs, n_jobs, dj.data(), held.data(), &n_run, total,
+                                fmt, nullptr);
+    held.resize(n_run);
+    dj.resize(n_run);
+    if (st == RC_OK && total > 0 && (!out_range || !out_hit))
+        st = fail(RC_E_INVAL, "null output");
+    if (st == RC_OK && hipSetDevice(c->device) != hipSuccess)
+        st = fail(RC_E_DEVICE, "hipSetDevice(%d) failed", c->device);
+    if (st != RC_OK) {
+        drop_holds(c, held.data(), held.size());
+        return st;
+    }
     rc_graph *g = new rc_graph();
     g->ctx = c;
+    g->held.swap(held);
     g->rays = total;
     const size_t nj = dj.empty() ? 1 : dj.size();
     g->bytes = sizeof(DevJob) * nj + 2 * sizeof(WorkQueues);
@@ -896,6 +1075,7 @@ rc_status rc_graph_create(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *
         st = dev_alloc(c, (void **)&g->dev, g->bytes);
     }
     if (st != RC_OK) {
+        drop_holds(c, g->held.data(), g->held.size());
         delete g;
         return st;
     }
@@ -913,7 +1093,7 @@ rc_status rc_graph_create(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *
     if (e == hipSuccess && total > 0) {
         e = queue_reset_launch(live, tmpl, g->cap);
         if (e == hipSuccess)
-            e = trace_launch(TRACE_BVH, fmt, config_of(tuning), djd, n_jobs, live, total,
+            e = trace_launch(TRACE_BVH, fmt, config_of(tuning), djd, n_run, live, total,
                              out_range, out_hit, nullptr, nullptr, g->cap);
         if (e != hipSuccess) {
             hipGraph_t junk = nullptr;
@@ -947,9 +1127,11 @@ void rc_graph_destroy(rc_graph *g)
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     if (g->cap) (void)hipStreamDestroy(g->cap);
-    if (g->dev) {
+    drop_holds(g->ctx, g->held.data(), g->held.size());
+    {
         std::lock_guard<std::mutex> lk(g->ctx->mu);
-        dev_free(g->ctx, g->dev, g->bytes);
+        if (g->dev) dev_free(g->ctx, g->dev, g->bytes);
+        reap_locked(g->ctx);
     }
     delete g;
 }

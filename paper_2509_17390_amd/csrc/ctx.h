@@ -6,6 +6,8 @@
 #include "rc_internal.h"
 #include "mesh_internal.h"
 
+#include <condition_variable>
+#include <deque>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -23,8 +25,15 @@ rc_status fail(rc_status s, const char *fmt, ...);
                               hipGetErrorString(e_), __FILE__, __LINE__);                   \
     } while (0)
 
+// A scene's life: upload makes it alive; rc_scene_release makes it dead
+// (no new work may resolve it) and its memory is freed once `refs` is zero.
+// Every launch, build or captured graph that resolved the scene holds one
+// reference until its device work has finished (graphs: until destroyed).
+// `refs` and `dead` are guarded by rc_ctx::ref_mu, the rest by rc_ctx::mu.
 struct Scene {
-    bool alive = false;
+    bool alive = false;   // the slot holds a scene and its memory
+    bool dead = false;    // released; freed when refs drops to zero
+    int refs = 0;
     int64_t nv = 0, nt = 0;
     float *verts = nullptr;
     int32_t *tris = nullptr;
@@ -39,6 +48,10 @@ struct Scene {
     NodeRec *q8nodes = nullptr;  // quantised 4-wide nodes (node_format == RC_NODE_Q8)
     float *box_dev = nullptr;    // [8]: box (6) + depth (int bits) + quantised node count
     uint64_t bytes = 0;
+    // mock context: a host copy of the vertices stands in for the device
+    // arrays, so the simulated device reads real scene memory
+    float *host_verts = nullptr;
+    double host_sum = 0.0;
 };
 
 struct Pattern {
@@ -87,6 +100,13 @@ struct JobSlot {
 
 struct ServeState;  // serve.hip
 
+// References dropped by a host function once the work enqueued before it on
+// a stream has finished.
+struct DropRec {
+    rc_ctx *c = nullptr;
+    std::vector<Scene *> held;
+};
+
 }  // namespace rc
 
 struct rc_ctx {
@@ -96,7 +116,7 @@ struct rc_ctx {
     uint64_t used = 0;
     std::mutex mu;        // scenes, patterns, workspace
     std::mutex job_mu;    // job slots, tuning
-    std::vector<rc::Scene> scenes;
+    std::deque<rc::Scene> scenes;  // elements never move: holds keep Scene pointers
     std::vector<rc::Pattern> patterns;
     std::vector<rc::GaussSet> gsets;
     void *ws = nullptr;
@@ -109,12 +129,29 @@ struct rc_ctx {
     rc_tuning tuning{};
     rc::ServeState *serve = nullptr;
     uint8_t *mc_table = nullptr;   // marching-cubes case table on the device (256 + 256 * 15 bytes)
+    // scene references (never held across a HIP call that waits for the
+    // device, so host functions on a stream can always take it)
+    std::mutex ref_mu;
+    std::condition_variable ref_cv;
+    std::vector<rc::Scene *> reap;       // dead scenes without references, freed under mu
+    int pending_drops = 0;               // drop host functions enqueued and not yet run
     std::mutex mesh_mu;            // TSDF / marching-cubes calls and their scratch
     void *mesh_ws = nullptr;       // grow-only scratch of those calls
     size_t mesh_ws_bytes = 0;
 };
 
 namespace rc {
+
+// Scene references (see Scene).  hold_scene: caller holds c->mu.
+// drop_holds: any thread, makes no HIP call; a dead scene left without
+// references goes to c->reap.  reap_locked: caller holds c->mu; frees the
+// scenes on c->reap.  drop_after: drops `held` once the work enqueued so
+// far on `s` has finished (a host function; at once when `s` is being
+// captured into a graph, whose owner keeps the scenes alive); empties `held`.
+void hold_scene(rc_ctx *c, Scene *s);
+void drop_holds(rc_ctx *c, Scene *const *s, size_t n);
+void reap_locked(rc_ctx *c);
+rc_status drop_after(rc_ctx *c, hipStream_t s, std::vector<Scene *> &held);
 
 rc_status dev_alloc(rc_ctx *c, void **p, size_t bytes);
 void dev_free(rc_ctx *c, void *p, size_t bytes);
@@ -140,9 +177,12 @@ struct StageBuf {
 // Stage one batch and launch it on `stream`; `forced` overrides the
 // context's tuning; `own` replaces the context's shared staging ring.
 // Thread-safe.
+// Jobs whose scene or pattern is gone are skipped and listed in `skipped`
+// when it is given (else the call fails with RC_E_NOTFOUND).
 rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, float *out_range,
                        int32_t *out_hit, int32_t *out_nodes, int32_t *out_tris, void *stream,
-                       const rc_tuning *forced = nullptr, StageBuf *own = nullptr);
+                       const rc_tuning *forced = nullptr, StageBuf *own = nullptr,
+                       std::vector<int> *skipped = nullptr);
 void stage_free(rc_ctx *c, StageBuf &b);
 
 // Serving scheduler hooks (serve.hip).

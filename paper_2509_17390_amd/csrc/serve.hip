@@ -108,6 +108,15 @@ struct Batch {
     ServeState *S = nullptr;
     std::vector<Request *> reqs;
     int stream = 0;
+    // mock device: each request's referenced scene and, like the pointers of
+    // a device job table, its memory as resolved when the batch was formed
+    struct MockJob {
+        Scene *sc = nullptr;
+        const float *verts = nullptr;
+        int64_t nv = 0;
+        double sum = 0.0;
+    };
+    std::vector<MockJob> mock;
 };
 
 struct ServeState {
@@ -212,9 +221,24 @@ void mock_loop(ServeState *Sp, int q)
         const int64_t ns = rays * (int64_t)S.opts.mock_ns_per_ray;
         lk.unlock();
         if (ns > 0) std::this_thread::sleep_for(std::chrono::nanoseconds(ns));
+        // "kernel": read each request's scene memory, which must still be the
+        // uploaded vertices (a scene released meanwhile is only freed after
+        // this batch has dropped its references)
+        std::vector<char> intact(b->reqs.size(), 1);
+        for (size_t i = 0; i < b->reqs.size(); ++i) {
+            const Batch::MockJob &m = b->mock[i];
+            double sum = 0.0;
+            for (int64_t k = 0; k < 3 * m.nv; ++k) sum += m.verts[k];
+            intact[i] = sum == m.sum;
+        }
         lk.lock();
-        for (Request *r : b->reqs) {
+        for (size_t i = 0; i < b->reqs.size(); ++i) {
+            Request *r = b->reqs[i];
             if (r->state != REQ_RUNNING) continue;
+            if (!intact[i]) {
+                fail_request_locked(S, r, RC_E_DEVICE, "scene memory changed during the launch");
+                continue;
+            }
             if (r->req.scene + 1 == S.opts.mock_fail_scene) {
                 fail_request_locked(S, r, RC_E_DEVICE, "simulated device error");
                 continue;
@@ -224,7 +248,19 @@ void mock_loop(ServeState *Sp, int q)
                 S.hit_buf[r->out_off + k] = r->req.scene;
             }
         }
+        std::vector<Scene *> held;
+        for (const Batch::MockJob &m : b->mock) held.push_back(m.sc);
         complete_batch_locked(S, b);
+        // the batch has finished: drop its scene references (S.mu is not
+        // held while c->mu is taken)
+        lk.unlock();
+        rc_ctx *c = S.ctx;
+        drop_holds(c, held.data(), held.size());
+        {
+            std::lock_guard<std::mutex> clk(c->mu);
+            reap_locked(c);
+        }
+        lk.lock();
     }
 }
 
@@ -234,34 +270,44 @@ rc_status launch_batch(ServeState &S, Batch *b, std::string &err)
 {
     rc_ctx *c = S.ctx;
     // a request whose scene or pattern has gone since it was submitted fails
-    // on its own; the rest of the batch proceeds
-    std::vector<Request *> ok;
-    {
-        std::vector<Request *> gone;
+    // on its own; the rest of the batch proceeds.  The scenes of the others
+    // are referenced in the same step (under c->mu), so a release from now on
+    // defers its free until the launch has finished.
+    if (c->mock) {
+        std::vector<Request *> gone, kept;
         {
             std::lock_guard<std::mutex> clk(c->mu);
             for (Request *r : b->reqs) {
                 Scene *sc = get_scene(c, r->req.scene);
                 Pattern *pt = get_pattern(c, r->req.pattern);
-                if (!sc || !pt || (sc->nt > 0 && !sc->has_bvh)) gone.push_back(r);
-                else ok.push_back(r);
+                if (!sc || !pt || (sc->nt > 0 && !sc->has_bvh)) {
+                    gone.push_back(r);
+                    continue;
+                }
+                hold_scene(c, sc);
+                Batch::MockJob m;
+                m.sc = sc;
+                m.verts = sc->host_verts;
+                m.nv = sc->nv;
+                m.sum = sc->host_sum;
+                b->mock.push_back(m);
+                kept.push_back(r);
+                memcpy(S.pose_buf + r->pose_off, r->poses.data(), r->poses.size() * sizeof(float));
             }
         }
-        if (!gone.empty()) {
-            std::lock_guard<std::mutex> lk(S.mu);
-            for (Request *r : gone)
-                fail_request_locked(S, r, RC_E_NOTFOUND, "scene or pattern no longer usable");
-        }
-    }
-    if (c->mock) {
-        for (Request *r : ok)
-            memcpy(S.pose_buf + r->pose_off, r->poses.data(), r->poses.size() * sizeof(float));
+        if (S.opts.mock_launch_delay_us > 0)   // the window between resolution and launch
+            std::this_thread::sleep_for(std::chrono::microseconds(S.opts.mock_launch_delay_us));
         std::lock_guard<std::mutex> lk(S.mu);
+        // a failed request leaves the batch: its caller may release it at once
+        b->reqs.swap(kept);
+        for (Request *r : gone)
+            fail_request_locked(S, r, RC_E_NOTFOUND, "scene or pattern no longer usable");
         S.mock_queue[b->stream].push_back(b);
         S.mock_cv.notify_all();
         return RC_OK;
     }
     hipStream_t s = S.streams[b->stream];
+    const std::vector<Request *> ok = b->reqs;
     std::vector<rc_job> jobs(ok.size());
     for (size_t i = 0; i < ok.size(); ++i) {
         Request *r = ok[i];
@@ -282,12 +328,27 @@ rc_status launch_batch(ServeState &S, Batch *b, std::string &err)
         j.out_offset = (int64_t)r->out_off;
     }
     rc_status st = RC_OK;
+    std::vector<int> skipped;
     if (!jobs.empty())
         st = trace_common(c, TRACE_BVH, jobs.data(), (int32_t)jobs.size(), S.range_buf, S.hit_buf,
-                          nullptr, nullptr, s, nullptr, &S.stage[b->stream]);
+                          nullptr, nullptr, s, nullptr, &S.stage[b->stream], &skipped);
     if (st != RC_OK) {
         err = rc_last_error();
         return st;
+    }
+    if (!skipped.empty()) {
+        // failed requests leave the batch before its completion function is
+        // enqueued: their callers may release them at once
+        std::lock_guard<std::mutex> lk(S.mu);
+        std::vector<char> drop(b->reqs.size(), 0);
+        for (int i : skipped) {
+            fail_request_locked(S, b->reqs[i], RC_E_NOTFOUND, "scene or pattern no longer usable");
+            drop[i] = 1;
+        }
+        size_t k = 0;
+        for (size_t i = 0; i < b->reqs.size(); ++i)
+            if (!drop[i]) b->reqs[k++] = b->reqs[i];
+        b->reqs.resize(k);
     }
     hipError_t e = hipLaunchHostFunc(s, on_device_done, b);
     if (e != hipSuccess) {
@@ -307,6 +368,17 @@ void worker_loop(ServeState *Sp)
             return S.stop || (!S.pending.empty() && S.inflight < S.opts.max_inflight);
         });
         if (S.stop) break;
+        if (!S.ctx->mock) {
+            // free scenes released while their batches ran (not under S.mu)
+            lk.unlock();
+            {
+                std::lock_guard<std::mutex> clk(S.ctx->mu);
+                reap_locked(S.ctx);
+            }
+            lk.lock();
+            if (S.stop) break;
+            if (S.pending.empty() || S.inflight >= S.opts.max_inflight) continue;
+        }
         Batch *b = new Batch();
         b->S = &S;
         int64_t rays = 0;
@@ -458,6 +530,7 @@ rc_status rc_serve_start(rc_ctx *c, const rc_serve_opts *opts)
     if (o.arena_bytes < (1u << 20)) return fail(RC_E_INVAL, "arena_bytes must be >= 1 MiB");
     if (o.policy != 0 && o.policy != 1) return fail(RC_E_INVAL, "policy must be 0 or 1");
     if (o.max_wait_ms < 0) return fail(RC_E_INVAL, "max_wait_ms < 0");
+    if (o.mock_launch_delay_us < 0) return fail(RC_E_INVAL, "mock_launch_delay_us < 0");
     if (o.max_wait_ms == 0) o.max_wait_ms = 200;
     ServeState *S = new ServeState();
     S->ctx = c;

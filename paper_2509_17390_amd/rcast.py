@@ -107,7 +107,8 @@ class rc_serve_opts(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32),
                 ("max_batch_rays_m", ctypes.c_int32), ("mock_ns_per_ray", ctypes.c_int32),
                 ("mock_fail_scene", ctypes.c_int32), ("policy", ctypes.c_int32),
-                ("max_wait_ms", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("max_wait_ms", ctypes.c_int32), ("mock_launch_delay_us", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class rc_serve_stats(ctypes.Structure):
@@ -575,9 +576,9 @@ class Context:
     # -- serving -------------------------------------------------------------
     def serve_start(self, arena_bytes: int = 0, max_inflight: int = 0, max_batch_rays_m: int = 0,
                     mock_ns_per_ray: int = 0, mock_fail_scene: int = 0, policy: int = 0,
-                    max_wait_ms: int = 0):
+                    max_wait_ms: int = 0, mock_launch_delay_us: int = 0):
         o = rc_serve_opts(arena_bytes, max_inflight, max_batch_rays_m, mock_ns_per_ray,
-                          mock_fail_scene, policy, max_wait_ms)
+                          mock_fail_scene, policy, max_wait_ms, mock_launch_delay_us)
         _check(load().rc_serve_start(self._h, ctypes.byref(o)))
 
     def serve_stop(self):

@@ -5,9 +5,14 @@
 // patterns, poll them to completion, check the simulated results
 // (range = ray index within the request, hit = scene id), copy them out and
 // release the ticket; a fifth thread polls statistics.  One scene's
-// requests fail on purpose.  Runs once with arrival-order admission and once
-// with small-first admission under a per-launch ray cap.  Exit status 0 when
-// every check passes.
+// requests fail on purpose.  A sixth thread keeps uploading a scene,
+// submitting requests on it and releasing it while they are queued or
+// running: each of those requests either completes with intact results or
+// fails with RC_E_NOTFOUND (never with the simulated device's "scene memory
+// changed"), and under AddressSanitizer any early free of the scene's memory
+// would be a use after free.  Runs once with arrival-order admission and
+// once with small-first admission under a per-launch ray cap.  Exit status 0
+// when every check passes.
 #include "rcast.h"
 
 #include <atomic>
@@ -66,6 +71,55 @@ int main()
         }
     });
     std::vector<std::thread> th;
+    th.emplace_back([&] {
+        std::vector<float> poses(12 * 4, 0.0f);
+        for (int e = 0; e < 4; ++e) poses[12 * e + 0] = poses[12 * e + 5] = poses[12 * e + 10] = 1.0f;
+        std::vector<float> vv(3 * 600);
+        std::vector<int32_t> tt(3 * 200);
+        for (int round = 0; round < 40; ++round) {
+            for (size_t k = 0; k < vv.size(); ++k) vv[k] = (float)((k * 7 + round) % 13);
+            for (size_t k = 0; k < tt.size(); ++k) tt[k] = (int32_t)k;
+            int32_t sc = -1;
+            CHECK(rc_scene_upload(c, vv.data(), 600, tt.data(), 200, 0, nullptr, &sc) == RC_OK);
+            CHECK(rc_lbvh_build(c, sc, nullptr, nullptr) == RC_OK);
+            uint64_t tk[6];
+            int n_sub = 0;
+            bool released = false;
+            for (int i = 0; i < 6; ++i) {
+                rc_request rq{};
+                rq.scene = sc;
+                rq.pattern = pat[i % 3];
+                rq.n_envs = 1 + i % 4;
+                rq.poses_3x4 = poses.data();
+                rq.t_max = 1.0f;
+                const rc_status st = rc_serve_submit(c, &rq, &tk[n_sub]);
+                if (released) CHECK(st == RC_E_NOTFOUND);   // the handle died with the release
+                else if (st == RC_OK) ++n_sub;
+                else CHECK(false);
+                if (i == 2 + round % 3) {
+                    CHECK(rc_scene_release(c, sc) == RC_OK);
+                    released = true;
+                }
+            }
+            for (int i = 0; i < n_sub; ++i) {
+                const float *rr = nullptr;
+                const int32_t *hh = nullptr;
+                double lat = 0.0;
+                rc_status st = rc_serve_poll(c, tk[i], -1, &rr, &hh, &lat);
+                CHECK(st == RC_OK || st == RC_E_NOTFOUND);
+                if (st == RC_OK) {
+                    const int n = (1 + i % 4) * nb[i % 3];
+                    for (int k = 0; k < n; ++k) {
+                        if (rr[k] != (float)k || hh[k] != sc) {
+                            CHECK(false);
+                            break;
+                        }
+                    }
+                }
+                CHECK(rc_serve_release(c, tk[i]) == RC_OK);
+            }
+        }
+    });
     for (int w = 0; w < 4; ++w) {
         th.emplace_back([&, w] {
             std::vector<float> poses(12 * 8, 0.0f);
@@ -114,9 +168,12 @@ int main()
     watcher.join();
     rc_serve_stats s;
     CHECK(rc_serve_get_stats(c, &s) == RC_OK);
-    CHECK(s.submitted == 240 && s.completed + s.failed == 240 && s.bytes_in_use == 0);
+    CHECK(s.completed + s.failed == s.submitted && s.bytes_in_use == 0);
+    CHECK(s.submitted >= 240 + 40 * 3);
     CHECK(rc_serve_stop(c) == RC_OK);
     }
+    // every released scene has been freed: only the three fixed ones remain
+    CHECK(rc_device_bytes(c) == 3 * sizeof(v));
     rc_destroy(c);
     std::printf("serve_stress: %s\n", g_bad.load() ? "FAILED" : "ok");
     return g_bad.load() ? 1 : 0;

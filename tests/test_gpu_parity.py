@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import cast_scene, compare_with_oracle, cuda, log
+from gpu_util import cast_scene, compare_with_oracle, cuda, log, oracle_checked
 from paper_2509_17390_amd import Context, Job, RcastError
 
 pytestmark = pytest.mark.gpu
@@ -211,9 +211,15 @@ TUNINGS = [
 ]
 
 
+def _variant_sample(s, n=700, seed=11):
+    idx = np.sort(np.random.default_rng(seed).choice(s.n_rays, n, replace=False))
+    return idx, oracle_checked(s.verts, s.tris, s.poses, s.dirs, s.t_min, s.t_max, idx)
+
+
 def test_tuning_variants_bit_identical(ctx):
     # every launch shape (persistent or not, stack depth in LDS, refill
-    # threshold, grid size, packet tile) must give bit-identical results
+    # threshold, grid size, packet tile) must give bit-identical results,
+    # and each one meets the oracle on the same sample of rays
     import torch
     s = synth.indoor_scene(seed=3, h=0.1, n_envs=6, n_az=256)
     scene = ctx.upload_scene(s.verts, s.tris)
@@ -221,6 +227,7 @@ def test_tuning_variants_bit_identical(ctx):
     pat = ctx.upload_pattern(s.dirs, s.n_az)
     poses = cuda(s.poses)
     job = [Job(scene, pat, poses, s.t_min, s.t_max)]
+    idx, orc = _variant_sample(s)
     ref = None
     try:
         for tn in TUNINGS:
@@ -230,6 +237,8 @@ def test_tuning_variants_bit_identical(ctx):
             r2, h2, nn, nt = ctx.cast(job, mode="stats")
             torch.cuda.synchronize()
             assert torch.equal(h, h2) and torch.equal(r.view(torch.int32), r2.view(torch.int32))
+            compare_with_oracle(s.verts, s.tris, s.poses, s.dirs, s.t_min, s.t_max,
+                                r.cpu().numpy(), h.cpu().numpy(), ray_idx=idx, oracle_out=orc)
             if ref is None:
                 ref = (r.clone(), h.clone())
                 assert bool((h >= 0).all())
@@ -398,6 +407,7 @@ def test_q8_tuning_variants_bit_identical(ctx):
     ctx.build(scene, node_format=1)
     pat = ctx.upload_pattern(s.dirs, s.n_az)
     job = [Job(scene, pat, cuda(s.poses), s.t_min, s.t_max)]
+    idx, orc = _variant_sample(s, seed=12)
     ref = None
     try:
         for tn in TUNINGS:
@@ -405,6 +415,8 @@ def test_q8_tuning_variants_bit_identical(ctx):
             ctx.set_tuning(**tn)
             r, h = ctx.cast(job)
             torch.cuda.synchronize()
+            compare_with_oracle(s.verts, s.tris, s.poses, s.dirs, s.t_min, s.t_max,
+                                r.cpu().numpy(), h.cpu().numpy(), ray_idx=idx, oracle_out=orc)
             if ref is None:
                 ref = (r.clone(), h.clone())
             else:
@@ -535,3 +547,35 @@ def test_batch_larger_than_one_dispatch(ctx):
     del r, h
     torch.cuda.empty_cache()
     ctx.release_scene(s1)
+
+
+def test_graph_keeps_its_scene_after_release(ctx):
+    """A captured graph holds its scene: released after capture, the scene
+    still serves every replay, and its memory returns when the graph goes."""
+    import torch
+    s = synth.indoor_scene(seed=8, h=0.1, n_envs=8, n_az=256)
+    scene = ctx.upload_scene(s.verts, s.tris)
+    ctx.build(scene, node_format=1)
+    pat = ctx.upload_pattern(s.dirs, s.n_az)
+    poses = cuda(s.poses)
+    job = [Job(scene, pat, poses, s.t_min, s.t_max)]
+    ref_r, ref_h = ctx.cast(job)
+    r = torch.empty_like(ref_r)
+    h = torch.empty_like(ref_h)
+    g = ctx.graph(job, r, h)
+    torch.cuda.synchronize()
+    held = ctx.device_bytes()
+    ctx.release_scene(scene)
+    assert ctx.device_bytes() == held          # still referenced by the graph
+    with pytest.raises(RcastError):
+        ctx.cast(job)
+    for rep in range(3):
+        r.fill_(-1.0)
+        h.fill_(-7)
+        torch.cuda.synchronize()
+        log(f"graph replay after release {rep}")
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(h, ref_h) and torch.equal(r.view(torch.int32), ref_r.view(torch.int32))
+    g.close()
+    assert ctx.device_bytes() < held           # freed with the graph

@@ -1,7 +1,9 @@
 """Serving on the GPU: each request's result is bit-identical whether cast
 alone or served in a continuously batched mix of scenes (FP32 and Q8
-nodes), environment counts and beam patterns; admission stays within the
-arena; results survive concurrent submitters."""
+nodes), environment counts and beam patterns, and meets the FP64 oracle on a
+sample of its rays; admission stays within the arena; results survive
+concurrent submitters; a scene released while its request runs is freed
+only after the request has finished."""
 import threading
 import time
 
@@ -9,7 +11,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import cuda, log
+from gpu_util import compare_with_oracle, cuda, log
 from paper_2509_17390_amd import Context, Job, RcastError
 from paper_2509_17390_amd.rcast import RC_OK
 
@@ -26,15 +28,21 @@ def world():
     sa = ctx.upload_scene(a.verts, a.tris)
     ctx.build(sa, node_format=0)
     scenes.append((sa, synth.free_space_poses(synth.indoor_sdf(0, n_prims=0), 64, 1)))
+    meshes = {sa: (a.verts, a.tris)}
     for k, fmt in ((1, 1), (2, 0)):
         sdf = synth.indoor_sdf(20 + k, n_prims=80)
         v, t = synth.polygonise(sdf, 0.08)
         s = ctx.upload_scene(v, t)
         ctx.build(s, node_format=fmt)
         scenes.append((s, synth.free_space_poses(sdf, 64, 2 + k)))
+        meshes[s] = (v, t)
     pats = [(ctx.upload_pattern(synth.lidar_pattern(16, -15, 15, 360), 360), 5760),
             (ctx.upload_pattern(synth.lidar_pattern(32, -16, 15, 512), 512), 16384),
             (ctx.upload_pattern(synth.lidar_pattern(8, -10, 10, 100), 100), 800)]
+    dirs = {pats[0][0]: synth.lidar_pattern(16, -15, 15, 360),
+            pats[1][0]: synth.lidar_pattern(32, -16, 15, 512),
+            pats[2][0]: synth.lidar_pattern(8, -10, 10, 100)}
+    ctx._test_meshes, ctx._test_dirs = meshes, dirs
     yield ctx, scenes, pats
     ctx.close()
 
@@ -88,6 +96,12 @@ def test_served_results_equal_alone(world, cap_m, policy):
             rng, hit = ctx.fetch(tickets[i], n)
             assert np.array_equal(hit, alone[i][1]), i
             assert np.array_equal(rng.view(np.int32), alone[i][0].view(np.int32)), i
+            if i % 4 == 0:
+                # the served result itself against the oracle on a sample
+                v, t = ctx._test_meshes[r["scene"]]
+                idx = np.sort(np.random.default_rng(i).choice(n, min(n, 300), replace=False))
+                compare_with_oracle(v, t, r["poses"], ctx._test_dirs[r["pattern"]], r["t_min"],
+                                    r["t_max"], rng, hit, ray_idx=idx, min_checked_frac=0.9)
             ctx.release(tickets[i])
         s = ctx.serve_stats()
         log(str(s))
@@ -117,3 +131,80 @@ def test_admission_within_small_arena(world):
         assert e.value.status == -2
     finally:
         ctx.serve_stop()
+
+
+def _wait(pred, timeout_s=10.0):
+    t0 = time.perf_counter()
+    while not pred():
+        assert time.perf_counter() - t0 < timeout_s
+        time.sleep(0.0002)
+
+
+def test_release_scene_while_served_request_runs(world):
+    """Release a scene while its served request (67M rays) is on the
+    device, then immediately upload and build another scene of the same size
+    (memory an early free would hand out again): the request completes with
+    its alone result, and the released scene's memory is returned afterwards."""
+    import torch
+    ctx, scenes, pats = world
+    sdf = synth.indoor_sdf(31, n_prims=120)
+    v, t = synth.polygonise(sdf, 0.05)
+    pool = synth.free_space_poses(sdf, 4096, 9)
+    s = ctx.upload_scene(v, t)
+    ctx.build(s, node_format=1)
+    pat, nb = pats[1]
+    log(f"release-in-flight: {len(t)} tris, {len(pool) * nb} rays")
+    alone_r, alone_h = cast_alone(ctx, dict(scene=s, pattern=pat, poses=pool, t_min=0.1,
+                                            t_max=120.0))
+    torch.cuda.synchronize()
+    ctx.serve_start(arena_bytes=1 << 30, max_inflight=1)
+    try:
+        before = ctx.device_bytes()
+        tk = ctx.submit(s, pat, pool, 0.1, 120.0)
+        _wait(lambda: ctx.serve_stats()["launches"] >= 1)
+        time.sleep(0.003)                   # resolved and launched; the kernel takes ~10 ms
+        ctx.release_scene(s)
+        with pytest.raises(RcastError) as e:
+            ctx.submit(s, pat, pool[:1], 0.1, 120.0)
+        assert e.value.status == -3
+        v2 = v[::-1].copy()                 # same size, different contents
+        s2 = ctx.upload_scene(v2, t)
+        ctx.build(s2, node_format=1)
+        st, _ = ctx.poll(tk, 30_000_000)
+        assert st == RC_OK
+        rng, hit = ctx.fetch(tk, len(pool) * nb)
+        assert np.array_equal(hit, alone_h)
+        assert np.array_equal(rng.view(np.int32), alone_r.view(np.int32))
+        ctx.release(tk)
+        torch.cuda.synchronize()
+        ctx.release_scene(s2)
+        assert ctx.device_bytes() < before  # both scenes' memory went back
+    finally:
+        ctx.serve_stop()
+
+
+def test_release_scene_right_after_direct_cast(world):
+    """rc_raycast_batch returns once the launch is enqueued; releasing the
+    scene at once (no synchronisation) must not free memory the running
+    kernel reads."""
+    import torch
+    ctx, scenes, pats = world
+    sdf = synth.indoor_sdf(32, n_prims=120)
+    v, t = synth.polygonise(sdf, 0.05)
+    pool = cuda(synth.free_space_poses(sdf, 4096, 10))
+    pat, nb = pats[1]
+    s = ctx.upload_scene(v, t)
+    ctx.build(s, node_format=1)
+    ref_r, ref_h = ctx.cast([Job(s, pat, pool, 0.1, 120.0)])
+    torch.cuda.synchronize()
+    log("release right after an enqueued cast")
+    r, h = ctx.cast([Job(s, pat, pool, 0.1, 120.0)])
+    ctx.release_scene(s)                    # the kernel is still running
+    s2 = ctx.upload_scene(v[::-1].copy(), t)
+    ctx.build(s2, node_format=1)
+    torch.cuda.synchronize()
+    assert torch.equal(h, ref_h) and torch.equal(r.view(torch.int32), ref_r.view(torch.int32))
+    with pytest.raises(RcastError) as e:
+        ctx.cast([Job(s, pat, pool, 0.1, 120.0)])
+    assert e.value.status == -3
+    ctx.release_scene(s2)

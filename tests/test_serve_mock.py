@@ -304,3 +304,126 @@ def test_mock_context_rules():
     c.serve_stop()
     assert c.poll(tks[0], 0)[0] == -6        # server gone
     c.close()
+
+
+# ---------------------------------------------------------------------------
+# Scene release while in use: the handle dies at once, the memory (a host
+# copy of the vertices that the simulated device reads during the launch)
+# is freed only after the last batch using it has finished.
+
+def _mock_scene(c, n_verts=4000, seed=3):
+    rng = np.random.default_rng(seed)
+    v = rng.uniform(-5, 5, (n_verts, 3)).astype(np.float32)
+    t = np.arange(3 * (n_verts // 3), dtype=np.int32).reshape(-1, 3)
+    s = c.upload_scene(v, t)
+    c.build(s)
+    return s, 12 * n_verts
+
+
+def _wait_inflight(c, n=1, timeout_s=5.0):
+    t0 = time.perf_counter()
+    while c.serve_stats()["inflight"] < n:
+        assert time.perf_counter() - t0 < timeout_s
+        time.sleep(0.0005)
+
+
+def test_release_while_running_defers_the_free():
+    c, scenes, pats = mock_ctx()
+    base = c.device_bytes()
+    s, nbytes = _mock_scene(c)
+    assert c.device_bytes() == base + nbytes
+    c.serve_start(arena_bytes=64 << 20, max_inflight=1, mock_ns_per_ray=2000)
+    tk = c.submit(s, pats[1], poses(100), 0.0, 1.0)              # 100k rays: 0.2 s
+    _wait_inflight(c)
+    time.sleep(0.01)
+    c.release_scene(s)                                           # returns at once
+    with pytest.raises(RcastError) as e:
+        c.scene_info(s)
+    assert e.value.status == -3
+    with pytest.raises(RcastError) as e:
+        c.submit(s, pats[0], poses(1), 0.0, 1.0)
+    assert e.value.status == -3
+    with pytest.raises(RcastError) as e:
+        c.release_scene(s)                                       # already released
+    assert e.value.status == -3
+    assert c.device_bytes() == base + nbytes                     # still in use
+    s2, nbytes2 = _mock_scene(c, 30, seed=4)
+    assert s2 != s                                               # the slot is not reused yet
+    st, _ = wait(c, tk)
+    assert st == RC_OK                                           # the scene stayed intact
+    rng, hit = c.fetch(tk, 100_000)
+    assert np.array_equal(rng, np.arange(100_000, dtype=np.float32)) and np.all(hit == s)
+    assert c.device_bytes() == base + nbytes2                    # freed after the batch
+    c.release(tk)
+    c.serve_stop()
+    c.release_scene(s2)
+    assert c.device_bytes() == base
+    c.close()
+
+
+def test_release_between_resolution_and_launch():
+    """The release lands in the window after the batch has resolved (and
+    referenced) its scene but before the launch is issued."""
+    c, scenes, pats = mock_ctx()
+    base = c.device_bytes()
+    s, nbytes = _mock_scene(c)
+    c.serve_start(arena_bytes=64 << 20, max_inflight=1, mock_ns_per_ray=0,
+                  mock_launch_delay_us=300_000)
+    tk = c.submit(s, pats[0], poses(3), 0.0, 1.0)
+    _wait_inflight(c)
+    time.sleep(0.05)                                             # inside the 0.3 s window
+    c.release_scene(s)
+    assert c.device_bytes() == base + nbytes
+    st, _ = wait(c, tk)
+    assert st == RC_OK
+    rng, hit = c.fetch(tk, 300)
+    assert np.array_equal(rng, np.arange(300, dtype=np.float32)) and np.all(hit == s)
+    assert c.device_bytes() == base
+    c.release(tk)
+    c.serve_stop()
+    c.close()
+
+
+def test_release_of_an_idle_scene_frees_at_once_and_reuses_the_slot():
+    c, scenes, pats = mock_ctx()
+    base = c.device_bytes()
+    s, nbytes = _mock_scene(c)
+    assert c.device_bytes() == base + nbytes
+    c.release_scene(s)
+    assert c.device_bytes() == base
+    s2, _ = _mock_scene(c, 60)
+    assert s2 == s                                               # the freed slot comes back
+    c.close()
+
+
+def test_released_scene_shared_by_running_and_queued_requests():
+    """One batch of a scene runs while another request on it is queued: the
+    release fails the queued one, the running one completes, and the memory
+    goes once the running batch has finished."""
+    c, scenes, pats = mock_ctx()
+    base = c.device_bytes()
+    s, nbytes = _mock_scene(c)
+    c.serve_start(arena_bytes=64 << 20, max_inflight=1, mock_ns_per_ray=2000)
+    running = c.submit(s, pats[1], poses(60), 0.0, 1.0)         # 60k rays: 0.12 s
+    _wait_inflight(c)
+    queued = c.submit(s, pats[0], poses(2), 0.0, 1.0)
+    c.release_scene(s)
+    assert wait(c, running)[0] == RC_OK
+    assert wait(c, queued)[0] == -3
+    assert c.device_bytes() == base
+    c.serve_stop()
+    c.close()
+
+
+def test_budget_counts_mock_scenes():
+    c = Context(RC_DEVICE_MOCK, budget_bytes=100_000)
+    v = np.zeros((6000, 3), np.float32)
+    t = np.arange(18000, dtype=np.int32).reshape(-1, 3) % 6000
+    a = c.upload_scene(v, t)                                     # 72 kB
+    with pytest.raises(RcastError) as e:
+        c.upload_scene(v, t)                                     # would exceed 100 kB
+    assert e.value.status == -2
+    c.release_scene(a)
+    b = c.upload_scene(v, t)                                     # fits again
+    assert b == a
+    c.close()
