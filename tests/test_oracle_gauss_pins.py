@@ -13,6 +13,7 @@ import pytest
 from scipy.spatial.transform import Rotation
 
 from oracle import gauss as og
+import synth
 
 
 def one(mu, quat, scale, alpha):
@@ -273,3 +274,159 @@ def test_density_at_matches_full_grid():
     t = vox // 8
     np.testing.assert_array_equal(K, counts[t[:, 2], t[:, 1], t[:, 0]])
     assert np.all(E >= D)
+
+
+# ---------------------------------------------------------------------------
+# The error scale E(v) that sets the GPU density tolerance,
+#   |D_fp32(v) - D(v)| <= 2^-24 (16 E(v) + 4 D(v)) + (K + 1) eps_abs,
+# (eps_abs: the absolute granularity of the evaluation -- 2^-126 per term for
+# float32 terms that underflow, 2^-31 for the GPU's fixed-point sum; K = the
+# tile's culling-set size),
+# pinned against an independent float32 evaluation of the density terms in
+# tile-local coordinates (each tile's corner subtracted in FP64, then every
+# operation in float32; the float32 terms summed exactly), on random cases
+# that stress each part of E: ordinary, thin (the L / s part), and far-tail
+# (a 6-sigma cutoff).  A planted mistake -- a dropped Gaussian, or E without
+# its L / s part -- must break the bound.  (The constant and q parts are not
+# separately necessary at these sizes: in a tail the q part and the L / s
+# part are of the same size, since L >= |v - mu|, and the factor 16 covers
+# the constant part's rounding of exp and alpha^2.)
+
+def _density_f32(params, grid, k, drop_at=None):
+    means, quats, scales, opac = params
+    mu = np.asarray(means, np.float32).astype(np.float64)
+    R32 = og.rotation_matrices(np.asarray(quats, np.float32)).astype(np.float32)
+    s32 = np.asarray(scales, np.float32)
+    al2 = np.asarray(opac, np.float32) * np.asarray(opac, np.float32)
+    boxes = og.gauss_boxes(means, quats, scales, k)
+    nx, ny, nz = grid.dims
+    D = np.zeros((nz, ny, nx))
+    h32 = np.float32(grid.h)
+    tx, ty, tz = grid.tiles
+    for kt in range(tz):
+        for jt in range(ty):
+            for it in range(tx):
+                t = (it, jt, kt)
+                mem = og.tile_members(boxes, grid.tile_box(t))
+                if mem.size == 0:
+                    continue
+                (x0, x1), (y0, y1), (z0, z1) = grid.tile_voxels(t)
+                corner = grid.origin.astype(np.float64) + np.array([x0, y0, z0]) * float(grid.h)
+                iz, iy, ix = np.meshgrid(np.arange(z0, z1), np.arange(y0, y1), np.arange(x0, x1),
+                                         indexing="ij")
+                loc = np.stack([(ix - x0).ravel(), (iy - y0).ravel(), (iz - z0).ravel()], axis=1)
+                v = (loc.astype(np.float32) + np.float32(0.5)) * h32          # [V, 3] f32
+                m = (mu[mem] - corner).astype(np.float32)                    # [K, 3] f32
+                d = v[:, None, :] - m[None, :, :]                           # f32
+                Rk = R32[mem]
+                u = (d[..., 0:1] * Rk[None, :, 0, :] + d[..., 1:2] * Rk[None, :, 1, :]) \
+                    + d[..., 2:3] * Rk[None, :, 2, :]                       # (R^T d)_b, f32
+                u = u / s32[mem][None]
+                q = (u[..., 0] * u[..., 0] + u[..., 1] * u[..., 1]) + u[..., 2] * u[..., 2]
+                terms = np.exp(np.float32(-0.5) * q) * al2[mem][None]       # f32
+                assert terms.dtype == np.float32
+                if drop_at is not None:
+                    terms[:, np.argmax(terms.sum(axis=0))] = 0.0             # planted: one term lost
+                D[z0:z1, y0:y1, x0:x1] = terms.astype(np.float64).sum(axis=1).reshape(iz.shape)
+    return D
+
+
+def _error_parts(params, grid, k):
+    """E(v) split into its parts sum t, sum t q, sum t g (the oracle's own
+    terms), for the planted checks."""
+    means, quats, scales, opac = params
+    mu = np.asarray(means, np.float32).astype(np.float64)
+    sc = np.asarray(scales, np.float32).astype(np.float64)
+    al = np.asarray(opac, np.float32).astype(np.float64)
+    R = og.rotation_matrices(np.asarray(quats, np.float32))
+    boxes = og.gauss_boxes(means, quats, scales, k)
+    nx, ny, nz = grid.dims
+    parts = np.zeros((3, nz, ny, nx))
+    diag = math.sqrt(3.0) * grid.tile * float(grid.h)
+    tx, ty, tz = grid.tiles
+    for kt in range(tz):
+        for jt in range(ty):
+            for it in range(tx):
+                t = (it, jt, kt)
+                mem = og.tile_members(boxes, grid.tile_box(t))
+                if mem.size == 0:
+                    continue
+                (x0, x1), (y0, y1), (z0, z1) = grid.tile_voxels(t)
+                iz, iy, ix = np.meshgrid(np.arange(z0, z1), np.arange(y0, y1), np.arange(x0, x1),
+                                         indexing="ij")
+                pts = np.stack(grid.centres(ix.ravel(), iy.ravel(), iz.ravel()), axis=1)
+                terms, u, q = og._terms(pts, mu[mem], R[mem], sc[mem], al[mem])
+                L = diag + np.linalg.norm(pts[:, None, :] - mu[mem][None], axis=2)
+                g = np.sum(np.abs(u) / sc[mem][None], axis=2) * L
+                for j, part in enumerate((terms, terms * q, terms * g)):
+                    parts[j, z0:z1, y0:y1, x0:x1] = part.sum(axis=1).reshape(iz.shape)
+    return parts
+
+
+CASES = {
+    # name: (seed, n, scale range, cutoff, grid spacing)
+    "ordinary": (31, 60, (0.02, 0.2), 3.0, 0.04),
+    "thin": (32, 40, (0.0004, 0.004), 3.0, 0.05),
+    "far_tail": (33, 30, (0.3, 0.6), 6.0, 0.01),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def f32_case(request):
+    seed, n, (s_lo, s_hi), k, h = CASES[request.param]
+    rng = np.random.default_rng(seed)
+    params = synth.random_gaussians(rng, n, (0.2, 0.1, 0.3), (0.9, 0.8, 0.7), s_lo, s_hi)
+    grid = og.Grid((0.13, 0.07, 0.21), h, (int(0.9 / h), int(0.8 / h), int(0.6 / h)), tile=8)
+    D, _, E = og.density(params, grid, k, with_error=True)
+    return request.param, params, grid, k, D, E
+
+
+def test_error_scale_bounds_an_independent_float32_evaluation(f32_case):
+    name, params, grid, k, D, E = f32_case
+    D32 = _density_f32(params, grid, k)
+    err = np.abs(D32 - D)
+    bound = 2.0 ** -24 * (16 * E + 4 * D) + (_counts(params, grid, k) + 1) * 2.0 ** -126
+    assert np.all(err <= bound), (name, float(np.max(err / np.maximum(bound, 1e-300))))
+    assert (D > 0).mean() > 0.05           # the case has substance
+    # the bound is not vacuous: the float32 error reaches a visible part of it
+    assert float(np.max(err / np.maximum(bound, 1e-300))) > 0.01
+
+
+def test_error_parts_sum_to_the_error_scale(f32_case):
+    name, params, grid, k, D, E = f32_case
+    parts = _error_parts(params, grid, k)
+    np.testing.assert_allclose(parts.sum(axis=0), E, rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(parts[0], D, rtol=1e-12, atol=1e-300)
+
+
+def _counts(params, grid, k):
+    """|C_tile| of every voxel's tile, [nz][ny][nx]."""
+    boxes = og.gauss_boxes(params[0], params[1], params[2], k)
+    c = og.tile_counts(boxes, grid)
+    B = grid.tile
+    nx, ny, nz = grid.dims
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return c[iz // B, iy // B, ix // B]
+
+
+def test_planted_dropped_gaussian_breaks_the_bound(f32_case):
+    name, params, grid, k, D, E = f32_case
+    D32 = _density_f32(params, grid, k, drop_at=True)
+    bound = 2.0 ** -24 * (16 * E + 4 * D) + (_counts(params, grid, k) + 1) * 2.0 ** -126
+    assert np.any(np.abs(D32 - D) > bound)
+
+
+@pytest.mark.parametrize("part,case", [(2, "thin")])
+def test_planted_error_scale_without_a_part_breaks_the_bound(part, case):
+    """Without its L / s part, the error scale no longer bounds the float32
+    evaluation of thin Gaussians."""
+    seed, n, (s_lo, s_hi), k, h = CASES[case]
+    rng = np.random.default_rng(seed)
+    params = synth.random_gaussians(rng, n, (0.2, 0.1, 0.3), (0.9, 0.8, 0.7), s_lo, s_hi)
+    grid = og.Grid((0.13, 0.07, 0.21), h, (int(0.9 / h), int(0.8 / h), int(0.6 / h)), tile=8)
+    D, _, E = og.density(params, grid, k, with_error=True)
+    parts = _error_parts(params, grid, k)
+    E_planted = E - parts[part]
+    D32 = _density_f32(params, grid, k)
+    slack = (_counts(params, grid, k) + 1) * 2.0 ** -126
+    assert np.any(np.abs(D32 - D) > 2.0 ** -24 * (16 * E_planted + 4 * D) + slack)
