@@ -19,10 +19,15 @@ Readings taken where the paper is silent (also in the design notes):
   S2  A boundary vertex is one with an incident edge that belongs to exactly
       one triangle; boundary vertices and vertices without neighbours do not
       move.
-  S3  Arithmetic is float32, one rounded operation at a time: the neighbour
-      sum runs over N(i) in ascending index order starting from 0, then the
-      division by |N(i)|, then x + f * (mean - x) (subtraction, product,
-      sum).  Both sides follow this order, so results are bit-identical.
+  S3  The definition is evaluated in FP64 (``taubin_fp64``), with the
+      parameters as the float32 values the library takes; it also returns a
+      per-vertex bound on any float32 evaluation that sums the neighbours in
+      some order, divides by |N(i)| and forms x + f (mean - x) (derivation in
+      its docstring), the tolerance of the GPU comparison.  ``taubin`` is one
+      such float32 evaluation, one rounded operation at a time: the neighbour
+      sum over N(i) in ascending index order starting from 0, the division,
+      then the subtraction, product and sum.  The GPU follows the same
+      order, so it is also compared bit for bit as a second check.
 """
 from __future__ import annotations
 
@@ -67,6 +72,57 @@ def taubin(verts, tris, lam: float = 0.5, mu: float = -0.53, iterations: int = 1
             step = (f * (mean - x)).astype(np.float32)
             x = np.where(move[:, None], (x + step).astype(np.float32), x)
     return x
+
+
+U32 = 2.0 ** -24   # unit roundoff of float32
+
+
+def taubin_fp64(verts, tris, lam: float = 0.5, mu: float = -0.53, iterations: int = 10):
+    """Taubin smoothing by its definition in FP64 (readings S1, S2), and a
+    per-vertex, per-coordinate bound on |x_fp32 - x| for a float32
+    evaluation of the same steps.  Returns (x [nv, 3], bound [nv, 3]).
+
+    One step with factor f in float32 from a state y (the float32 iterate):
+    the sum of d = |N(i)| neighbours, d - 1 roundings, errs by at most
+    gamma_(d-1) sum |y_j| (gamma_k = k u / (1 - k u), u = 2^-24); the
+    division, subtraction, product and sum each add u times their result's
+    magnitude, so the local error is at most
+      r_i = 1.01 (|f| (gamma_(d-1) M_i + u (|m_i| + |m_i - y_i|))
+                  + u (|s_i| + |y'_i|)),
+    M_i = mean |y_j|, m_i = the mean, s_i = f (m_i - y_i), y'_i = y_i + s_i
+    (1.01 covers the second-order terms).  The step is linear,
+    T(y)_i = (1 - f) y_i + f mean_j y_j, so an error e carried into it comes
+    out at most |1 - f| e_i + |f| mean_j e_j.  The bound is that recurrence
+    from e = 0, with the local terms evaluated on the FP64 iterate; fixed
+    vertices carry no error."""
+    x = np.asarray(verts, dtype=np.float32).astype(np.float64).copy()
+    nv = len(x)
+    nb, deg, boundary = neighbours(nv, tris)
+    move = (deg > 0) & ~boundary
+    e = np.zeros_like(x)
+    d = deg.astype(np.float64)
+    safe = np.maximum(d, 1.0)
+    gamma = (d - 1) * U32 / (1 - (d - 1) * U32)
+    for _ in range(iterations):
+        for f in (float(np.float32(lam)), float(np.float32(mu))):
+            acc = np.zeros_like(x)
+            acc_abs = np.zeros_like(x)
+            acc_e = np.zeros_like(x)
+            for k in range(nb.shape[1]):
+                m = k < deg
+                acc[m] += x[nb[m, k]]
+                acc_abs[m] += np.abs(x[nb[m, k]])
+                acc_e[m] += e[nb[m, k]]
+            mean = acc / safe[:, None]
+            step = f * (mean - x)
+            new = x + step
+            r = 1.01 * (abs(f) * (gamma[:, None] * acc_abs / safe[:, None]
+                                  + U32 * (np.abs(mean) + np.abs(mean - x)))
+                        + U32 * (np.abs(step) + np.abs(new)))
+            e_new = abs(1 - f) * e + abs(f) * acc_e / safe[:, None] + r
+            x = np.where(move[:, None], new, x)
+            e = np.where(move[:, None], e_new, 0.0)
+    return x, e
 
 
 # ---------------------------------------------------------------------------

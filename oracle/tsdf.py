@@ -57,10 +57,20 @@ notes):
       one-sided (phi(1) - phi(0), phi(n-1) - phi(n-2)) on the grid's first
       and last point, 0 on an axis of size 1.  A vertex at t on the edge from
       a to b takes n = (1 - t) g_a + t g_b and returns n / |n| ((0, 0, 0) if
-      |n| = 0).  float32, one rounded operation at a time in this order:
-      w = 1 - t; n_k = w g_a,k + t g_b,k (two products, then the sum);
-      l = sqrt((n_x n_x + n_y n_y) + n_z n_z); n_k / l.  phi grows outward
-      (s = +1 outside), so the normals point out of the solid.
+      |n| = 0).  phi grows outward (s = +1 outside), so the normals point
+      out of the solid.
+
+The definitions of T5 (vertex positions) and T6 (normals) are evaluated two
+ways.  ``marching_cubes_fp64`` is the definition itself: every quantity in
+FP64 from the float32 phi, origin and spacing, and it returns per-vertex
+bounds for any float32 evaluation (derivation in its docstring), the
+tolerance of the GPU comparison.  ``marching_cubes`` is one float32
+evaluation, one rounded operation at a time in a fixed order (t, then
+x = c_a + t h with c_a the float32 centre; w = 1 - t, n_k = w g_a,k +
+t g_b,k as two products and a sum, l = sqrt((n_x n_x + n_y n_y) + n_z n_z),
+n_k / l); the GPU follows the same order, so it is also compared bit for
+bit as a second check.  The inside/outside decisions, the case table and
+the numbering are exact comparisons of the same float32 phi in both.
 """
 from __future__ import annotations
 
@@ -336,3 +346,87 @@ def marching_cubes(phi, origin, h: float, iso: float = 0.0, normals: bool = Fals
     nrm[ok] = (nrm[ok] / ln[ok, None]).astype(np.float32)
     nrm[~ok] = 0.0
     return verts, tris, nrm
+
+
+U32 = 2.0 ** -24   # unit roundoff of float32
+
+
+def marching_cubes_fp64(phi, origin, h: float, iso: float = 0.0):
+    """Vertex positions and normals of the marching-cubes mesh of phi at iso
+    by the definitions T5 and T6 in FP64 (same vertices and numbering as
+    ``marching_cubes``), with per-vertex bounds on any float32 evaluation:
+
+      verts [nv, 3], normals [nv, 3] (FP64), pos_tol [nv, 3], nrm_tol [nv]
+
+    Position (T5): x = c_a + t h on the edge's axis, c_a elsewhere, with
+    c_a = o + (i + 1/2) h and t = (iso - phi_a) / (phi_b - phi_a).  In float32
+    c_a is one rounding from its exact value at most 1.01 u (|o| + 2 |c_a|)
+    away (u = 2^-24; a product and a sum, or a correct rounding); t comes
+    from two exact-input subtractions and a division, so
+    |t32 - t| <= 3.01 u t; then x32 = c_a32 + t32 h adds the rounding of the
+    product and the sum:
+      |x32 - x| <= 1.01 u (|o| + 2 |c_a|) + 4.1 u h + 1.01 u |x|.
+    Normal (T6): the float32 gradient differs from the exact difference of
+    the float32 phi by at most u |g| per component; w = 1 - t by at most
+    4.01 u, and the two products and the sum add three roundings, so
+      |n32_k - n_k| <= 7.1 u (|g_a,k| + |g_b,k|),
+    and the unit vector moves by at most 2 |dn| / |n| plus the rounding of
+    the length and the division (6 u):
+      |n32/|n32| - n/|n||_k <= 14.2 u |(|g_a| + |g_b|)| / |n| + 6 u.
+    Where |n| = 0 the direction is undefined and the bound is +inf."""
+    phi = np.asarray(phi, dtype=np.float32)
+    nz, ny, nx = phi.shape
+    isod = float(np.float32(iso))
+    hd = float(np.float32(h))
+    o = np.asarray(origin, dtype=np.float32).astype(np.float64)
+    inside = phi < np.float32(iso)
+    n_pts = nx * ny * nz
+    ins = inside.ravel()
+    flat = phi.ravel().astype(np.float64)
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ix, iy, iz = ix.ravel(), iy.ravel(), iz.ravel()
+    steps = (1, nx, nx * ny)
+    limits = (ix < nx - 1, iy < ny - 1, iz < nz - 1)
+    crossed = np.zeros((n_pts, 3), dtype=bool)
+    for axis in range(3):
+        idx = np.nonzero(limits[axis])[0]
+        crossed[idx, axis] = ins[idx] != ins[idx + steps[axis]]
+    order = np.nonzero(crossed.ravel())[0]
+    pt, ax = order // 3, order % 3
+    nb = pt + np.array(steps)[ax]
+    fa, fb = flat[pt], flat[nb]
+    t = (isod - fa) / (fb - fa)
+    c = np.stack([o[0] + (ix[pt] + 0.5) * hd, o[1] + (iy[pt] + 0.5) * hd,
+                  o[2] + (iz[pt] + 0.5) * hd], axis=1)
+    x = c.copy()
+    rows = np.arange(pt.size)
+    x[rows, ax] = c[rows, ax] + t * hd
+    moving = np.zeros_like(x, dtype=bool)
+    moving[rows, ax] = True
+    pos_tol = 1.01 * U32 * (np.abs(o)[None, :] + 2.0 * np.abs(c)) \
+        + np.where(moving, 4.1 * U32 * hd + 1.01 * U32 * np.abs(x), 0.0)
+    # normals: exact differences of the float32 phi
+    G = np.zeros((nz, ny, nx, 3))
+    p64 = phi.astype(np.float64)
+    for a in range(3):
+        k = 2 - a
+        n = phi.shape[k]
+        if n < 2:
+            continue
+        f = np.moveaxis(p64, k, 0)
+        d = np.zeros_like(f)
+        d[1:n - 1] = (f[2:] - f[:n - 2]) * 0.5
+        d[0] = f[1] - f[0]
+        d[n - 1] = f[n - 1] - f[n - 2]
+        G[..., a] = np.moveaxis(d, 0, k)
+    G = G.reshape(-1, 3)
+    ga, gb = G[pt], G[nb]
+    nvec = (1.0 - t)[:, None] * ga + t[:, None] * gb
+    ln = np.linalg.norm(nvec, axis=1)
+    ok = ln > 0
+    nrm = np.zeros_like(nvec)
+    nrm[ok] = nvec[ok] / ln[ok, None]
+    spread = np.linalg.norm(np.abs(ga) + np.abs(gb), axis=1)
+    nrm_tol = np.full(pt.size, np.inf)
+    nrm_tol[ok] = 14.2 * U32 * spread[ok] / ln[ok] + 6.0 * U32
+    return x, nrm, pos_tol, nrm_tol

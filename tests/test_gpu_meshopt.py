@@ -1,6 +1,9 @@
 """Taubin smoothing on the GPU vs the oracle (oracle/mesh.py), FGGS-LiDAR
-Sec. IV-B "Mesh optimization".  Parity bar: bit-exact vertex positions
-(both sides run the same float32 operations in the same order)."""
+Sec. IV-B "Mesh optimization".  Parity bar: vertex positions within the
+per-vertex float32 error bound of the FP64 definition (oracle taubin_fp64),
+checked after 2 iterations, where the bound is tight, and after the
+requested count; and, as a second check, bit-exact with the oracle's float32
+evaluation in the kernel's operation order."""
 import numpy as np
 import pytest
 
@@ -25,13 +28,18 @@ def ctx():
 
 def check(ctx, v, t, lam=0.5, mu=-0.53, it=10, tag=""):
     import torch
-    vd = cuda(v)
-    ctx.taubin(vd, cuda(t), lam, mu, it)
-    torch.cuda.synchronize()
-    got = vd.cpu().numpy()
-    want = omesh.taubin(v, t, lam, mu, it)
-    np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
-    log(f"{tag}: {len(v)} vertices, {len(t)} triangles, {it} iterations, bit-exact")
+    for n_it in sorted({min(2, it), it}):
+        vd = cuda(v)
+        ctx.taubin(vd, cuda(t), lam, mu, n_it)
+        torch.cuda.synchronize()
+        got = vd.cpu().numpy()
+        x64, bound = omesh.taubin_fp64(v, t, lam, mu, n_it)
+        ratio = np.abs(got.astype(np.float64) - x64) / np.maximum(bound, 1e-300)
+        assert np.all((ratio <= 1.0) | (got.astype(np.float64) == x64)), float(ratio.max())
+        want = omesh.taubin(v, t, lam, mu, n_it)
+        np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
+    log(f"{tag}: {len(v)} vertices, {len(t)} triangles, {it} iterations, within the FP64 "
+        f"bound and bit-exact")
     return got
 
 

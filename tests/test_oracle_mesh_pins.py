@@ -83,6 +83,55 @@ def test_matches_a_sparse_matrix_route():
     np.testing.assert_allclose(out, x, rtol=0, atol=2e-5)
 
 
+def test_fp64_definition_matches_the_sparse_matrix_route():
+    """taubin_fp64 and the sparse-matrix form of the same steps, both FP64,
+    agree to FP64 rounding."""
+    v, t = grid_patch(12, jitter=0.3, seed=4)
+    n = len(v)
+    e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
+    e = np.concatenate([e, e[:, ::-1]])
+    A = sp.coo_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(n, n)).tocsr()
+    A.data[:] = 1.0
+    deg = np.asarray(A.sum(axis=1)).ravel()
+    _, _, bnd = omesh.neighbours(n, t)
+    move = ~bnd & (deg > 0)
+    L = sp.diags(np.where(move, 1.0 / np.maximum(deg, 1), 0.0)) @ A - sp.diags(move.astype(float))
+    x = v.astype(np.float64)
+    f_mu = float(np.float32(-0.53))
+    for _ in range(5):
+        for f in (0.5, f_mu):
+            x = x + f * (L @ x)
+    got, bound = omesh.taubin_fp64(v, t, 0.5, -0.53, 5)
+    np.testing.assert_allclose(got, x, rtol=0, atol=1e-12)
+    assert np.all(bound[bnd] == 0) and np.all(bound[move] > 0)
+
+
+@pytest.mark.parametrize("iterations", [1, 2, 10])
+def test_float32_evaluation_within_the_fp64_bound(iterations):
+    """The float32 evaluation stays inside the derived bound of the FP64
+    definition on a noisy sphere away from the origin (high-valence poles
+    included); at two iterations the bound is within 20x of the error."""
+    v, t = synth.uv_sphere((3.0, -2.0, 1.0), 1.0, 48, 24)
+    rng = np.random.default_rng(1)
+    c = np.array([3.0, -2.0, 1.0])
+    noisy = (c + (v - c) * (1 + 0.01 * rng.normal(size=(len(v), 1)))).astype(np.float32)
+    o32 = omesh.taubin(noisy, t, 0.5, -0.53, iterations)
+    x, bound = omesh.taubin_fp64(noisy, t, 0.5, -0.53, iterations)
+    ratio = np.abs(o32 - x) / np.maximum(bound, 1e-300)
+    assert ratio.max() <= 1.0
+    if iterations <= 2:
+        assert ratio.max() > 0.05
+
+
+def test_planted_sign_error_breaks_the_fp64_bound():
+    v, t = synth.uv_sphere((0.5, 0.2, -0.1), 1.0, 32, 16)
+    rng = np.random.default_rng(2)
+    noisy = (v * (1 + 0.01 * rng.normal(size=(len(v), 1)))).astype(np.float32)
+    x, bound = omesh.taubin_fp64(noisy, t, 0.5, -0.53, 2)
+    wrong = omesh.taubin(noisy, t, 0.5, 0.53, 2)           # mu with the wrong sign
+    assert np.any(np.abs(wrong - x) > bound)
+
+
 # ---- quadric-error decimation by vertex clustering ----------------------------
 
 def box_mesh(n=12, size=(2.0, 1.5, 1.0)):

@@ -293,3 +293,74 @@ def test_normals_on_an_axis_of_size_one_and_at_a_flat_point():
     assert len(v4) == 4
     np.testing.assert_array_equal(n4[1], np.zeros(3, np.float32))
     np.testing.assert_array_equal(n4[0], np.array([-1, 0, 0], np.float32))
+
+
+# ---------------------------------------------------------------------------
+# The FP64 definitions of vertex positions and normals (T5, T6) and their
+# float32 error bounds, which are the GPU tolerance.
+
+def test_fp64_vertices_of_a_linear_field_lie_on_its_zero_set():
+    """phi = a . x + b sampled at the lattice centres (rounded to float32):
+    every FP64 vertex lies on the plane a . x + b = 0 up to the float32
+    rounding of the two phi values of its edge; normals are a / |a|."""
+    n = (7, 8, 9)
+    h, o = 0.0625, np.array([0.3125, -0.28125, 1.875])    # exact in float32
+    iz, iy, ix = np.meshgrid(*(np.arange(k) for k in n), indexing="ij")
+    a = np.array([0.3, -0.5, 0.8])
+    X = [o[k] + (g + 0.5) * h for k, g in enumerate((ix, iy, iz))]
+    b = 1.95
+    f64 = a[0] * X[0] + a[1] * X[1] + a[2] * X[2] - b
+    phi = f64.astype(np.float32)
+    x, nrm, ptol, ntol = ot.marching_cubes_fp64(phi, o, h, 0.0)
+    assert len(x) > 40
+    resid = np.abs(x @ a - b)
+    # each phi carries u |phi| of rounding, i.e. |phi| u / |a . e_axis| of
+    # position along the edge; |phi| <= |a|_1 h on a crossed edge
+    assert np.all(resid <= 2 * 2.0 ** -24 * np.abs(a).sum() * h + 1e-12)
+    np.testing.assert_allclose(nrm, np.broadcast_to(a / np.linalg.norm(a), nrm.shape), atol=1e-6)
+
+
+def test_fp64_matches_the_closed_form_two_point_field():
+    phi = np.broadcast_to(np.array([-1.0, 3.0], np.float32).reshape(1, 1, 2), (2, 2, 2)).copy()
+    x, nrm, _, _ = ot.marching_cubes_fp64(phi, (0, 0, 0), 0.5, 0.0)
+    np.testing.assert_array_equal(x[:, 0], 0.25 + 0.25 * 0.5)
+    np.testing.assert_array_equal(nrm, np.tile([1.0, 0.0, 0.0], (4, 1)))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_float32_evaluation_lies_within_the_fp64_bounds(seed):
+    """The float32 evaluation (one rounded operation at a time) differs from
+    the FP64 definition by less than the derived bounds, on rough and smooth
+    fields away from the origin; the bounds are not vacuous."""
+    rng = np.random.default_rng(seed)
+    base = rng.normal(size=(10, 12, 14))
+    phi = (ndimage.uniform_filter(base, 3) * 3.0 if seed else base).astype(np.float32)
+    o, h, iso = (17.3, -41.9, 5.02), 0.037, 0.05 * seed
+    v32, t32, n32 = ot.marching_cubes(phi, o, h, iso, normals=True)
+    x, nrm, ptol, ntol = ot.marching_cubes_fp64(phi, o, h, iso)
+    assert len(v32) == len(x) > 100
+    r_pos = np.abs(v32.astype(np.float64) - x) / ptol
+    r_nrm = np.abs(n32.astype(np.float64) - nrm).max(axis=1) / ntol
+    assert r_pos.max() <= 1.0 and r_nrm.max() <= 1.0
+    assert r_pos.max() > 0.02 and r_nrm.max() > 1e-3
+
+
+def test_planted_mistakes_break_the_fp64_bounds():
+    """t measured from the wrong end, or a normal that drops the far
+    gradient, is caught by the bounds."""
+    rng = np.random.default_rng(5)
+    phi = (ndimage.uniform_filter(rng.normal(size=(9, 10, 11)), 3) * 3.0).astype(np.float32)
+    o, h = (0.2, 0.4, -0.3), 0.05
+    v32, _, n32 = ot.marching_cubes(phi, o, h, 0.0, normals=True)
+    x, nrm, ptol, ntol = ot.marching_cubes_fp64(phi, o, h, 0.0)
+    c = np.floor((x - np.asarray(o)) / h - 0.5 + 1e-9) * h + np.asarray(o) + 0.5 * h
+    wrong = c + (h - (x - c))          # t -> 1 - t on the moving axis
+    moving = np.abs(x - c) > 1e-12
+    assert np.any(np.abs(np.where(moving, wrong, x) - x) > ptol)
+    # a normal from the near gradient only
+    G = ot.lattice_gradient(phi).reshape(-1, 3).astype(np.float64)
+    edges = _crossed_edges_brute(phi)
+    nz, ny, nx = phi.shape
+    near = np.array([G[(z * ny + y) * nx + xx] for (xx, y, z), _ in edges])
+    near /= np.maximum(np.linalg.norm(near, axis=1, keepdims=True), 1e-300)
+    assert np.any(np.abs(near - nrm).max(axis=1) > ntol)
