@@ -156,6 +156,23 @@ typedef struct {
 rc_status rc_raycast_batch(rc_ctx *ctx, const rc_job *jobs, int32_t n_jobs,
                            float *out_range, int32_t *out_hit, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): same contract and results
+ * as rc_raycast_batch, with no device or host-pinned allocation.  The
+ * launch's job table and work queues live in a fixed device array of 32,896
+ * bytes (work queues + 256 job records of 128 bytes), one per GPU, held
+ * until the process ends; the table reaches it through small kernel
+ * launches (no copy, no memset).  At most 256 jobs per call (RC_E_INVAL
+ * beyond).  Every call on one GPU shares that array and leaves the last
+ * call's table in it: calls ordered one after another on one stream are
+ * safe; calls that overlap on one GPU (on different streams, or from
+ * threads racing on one stream) race on it and may corrupt each other's
+ * launch.  Scenes are referenced as in rc_raycast_batch; at most 256 such
+ * launches may be in flight per context (RC_E_BUSY beyond).
+ * Errors: as rc_raycast_batch; RC_E_BUSY. */
+rc_status rc_raycast_batch_noalloc(rc_ctx *ctx, const rc_job *jobs, int32_t n_jobs,
+                                   float *out_range, int32_t *out_hit, void *stream);
+
 /* Same contract as rc_raycast_batch, but every ray is tested against every
  * triangle (the naive O(N_r * N_tri) baseline of Sec. IV-C) with the same
  * FP32 triangle test.  A GPU cross-check of the BVH path: for rays that

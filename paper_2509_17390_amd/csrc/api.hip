@@ -132,14 +132,20 @@ void reap_locked(rc_ctx *c)
 
 namespace {
 
-// Host function behind a launch or build: no HIP call, no c->mu.
+// Host function behind a launch or build: no HIP call, no c->mu.  A pooled
+// record goes back to the pool (clear() keeps its capacity).
 void drop_host_fn(void *arg)
 {
     DropRec *d = static_cast<DropRec *>(arg);
     rc_ctx *c = d->c;
     drop_holds(c, d->held.data(), d->held.size());
-    delete d;
+    const int slot = d->slot;
+    if (slot < 0) delete d;
     std::lock_guard<std::mutex> lk(c->ref_mu);
+    if (slot >= 0) {
+        d->held.clear();
+        c->drop_free.push_back(slot);
+    }
     --c->pending_drops;
     c->ref_cv.notify_all();
 }
@@ -152,20 +158,17 @@ bool stream_capturing(hipStream_t s)
 
 }  // namespace
 
-rc_status drop_after(rc_ctx *c, hipStream_t s, std::vector<Scene *> &held)
+// Drop the references of record d once the work enqueued so far on s has
+// finished (at once while s is being captured).
+rc_status enqueue_drop(rc_ctx *c, hipStream_t s, DropRec *d)
 {
-    if (held.empty()) return RC_OK;
-    if (stream_capturing(s)) {
-        drop_holds(c, held.data(), held.size());
-        held.clear();
-        return RC_OK;
-    }
-    DropRec *d = new DropRec();
-    d->c = c;
-    d->held.swap(held);
     {
         std::lock_guard<std::mutex> lk(c->ref_mu);
         ++c->pending_drops;
+    }
+    if (stream_capturing(s)) {
+        drop_host_fn(d);
+        return RC_OK;
     }
     hipError_t e = hipLaunchHostFunc(s, drop_host_fn, d);
     if (e != hipSuccess) {
@@ -175,6 +178,15 @@ rc_status drop_after(rc_ctx *c, hipStream_t s, std::vector<Scene *> &held)
         return fail(RC_E_DEVICE, "hipLaunchHostFunc failed: %s", hipGetErrorString(e));
     }
     return RC_OK;
+}
+
+rc_status drop_after(rc_ctx *c, hipStream_t s, std::vector<Scene *> &held)
+{
+    if (held.empty()) return RC_OK;
+    DropRec *d = new DropRec();
+    d->c = c;
+    d->held.swap(held);
+    return enqueue_drop(c, s, d);
 }
 
 Pattern *get_pattern(rc_ctx *c, int32_t id)
@@ -450,6 +462,62 @@ rc_status ensure_build_ws(rc_ctx *c, size_t need, hipStream_t s)
     return RC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Launch scratch of rc_raycast_batch_noalloc: the work queues and job table
+// of one launch in a fixed device array.  Each GPU holds its own copy until
+// the process ends; host code reaches it only through the address
+// hipGetSymbolAddress gives for that device (the array's name is a host
+// stand-in, not a device address).  Calls that overlap on one GPU share it.
+constexpr size_t kScratchBytes = sizeof(WorkQueues) + sizeof(DevJob) * kNoAllocJobs;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_dev[kMaxDevices] = {};
+
+// Address of this device's scratch; the device must be current.  Looked up
+// once per device.
+rc_status scratch_of_device(int device, char **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices)
+        return fail(RC_E_INVAL, "device %d: at most %d devices", device, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(RC_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s",
+                        device, hipGetErrorString(e));
+        g_scratch_dev[device] = static_cast<char *>(p);
+    }
+    *out = g_scratch_dev[device];
+    return RC_OK;
+}
+
+// The job table reaches the scratch as kernel arguments (16 records per
+// launch), so no host staging buffer is needed.
+constexpr int kFillJobs = 16;
+struct ScratchFill {
+    uint4 words[kFillJobs * sizeof(DevJob) / 16];
+    WorkQueues queues;
+    int32_t first, count, with_queues, pad;
+};
+static_assert(sizeof(DevJob) % 16 == 0, "job records are whole uint4s");
+static_assert(sizeof(ScratchFill) <= 4096, "kernel arguments stay within 4 KiB");
+
+__global__ void k_fill_scratch(char *scr, ScratchFill a)
+{
+    constexpr int per = (int)(sizeof(DevJob) / 16);
+    uint4 *jobs = reinterpret_cast<uint4 *>(scr + sizeof(WorkQueues)) + a.first * per;
+    for (int i = threadIdx.x; i < a.count * per; i += blockDim.x) jobs[i] = a.words[i];
+    if (a.with_queues && threadIdx.x < kQueues) {
+        WorkQueues *q = reinterpret_cast<WorkQueues *>(scr);
+        q->head[threadIdx.x] = a.queues.head[threadIdx.x];
+        q->end[threadIdx.x] = a.queues.end[threadIdx.x];
+    }
+}
+
 }  // namespace rc
 
 using namespace rc;
@@ -488,6 +556,20 @@ rc_status rc_create(int device, uint64_t hbm_budget_bytes, rc_ctx **out)
     if (e != hipSuccess) {
         rc_destroy(c);
         return fail(RC_E_DEVICE, "context setup failed: %s", hipGetErrorString(e));
+    }
+    rc_status st = scratch_of_device(device, &c->scratch);
+    if (st != RC_OK) {
+        rc_destroy(c);
+        return st;
+    }
+    // drop records of rc_raycast_batch_noalloc, allocated here once
+    c->drop_pool.resize(kDropPool);
+    c->drop_free.reserve(kDropPool);
+    for (int i = 0; i < kDropPool; ++i) {
+        c->drop_pool[i].c = c;
+        c->drop_pool[i].slot = i;
+        c->drop_pool[i].held.reserve(kNoAllocJobs);
+        c->drop_free.push_back(kDropPool - 1 - i);
     }
     *out = c;
     return RC_OK;
@@ -778,6 +860,76 @@ rc_status rc_raycast_batch(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float 
                            int32_t *out_hit, void *stream)
 {
     return trace_common(c, TRACE_BVH, jobs, n_jobs, out_range, out_hit, nullptr, nullptr, stream);
+}
+
+rc_status rc_raycast_batch_noalloc(rc_ctx *c, const rc_job *jobs, int32_t n_jobs,
+                                   float *out_range, int32_t *out_hit, void *stream)
+{
+    if (!c) return fail(RC_E_INVAL, "null context");
+    if (c->mock) return fail(RC_E_STATE, "a mock context has no device to cast on");
+    if (n_jobs < 0 || n_jobs > kNoAllocJobs)
+        return fail(RC_E_INVAL,
+                    "rc_raycast_batch_noalloc takes 0..%d jobs (%d given): its job table lives "
+                    "in a fixed %zu-byte device array", kNoAllocJobs, (int)n_jobs, kScratchBytes);
+    if (!c->scratch) return fail(RC_E_STATE, "no launch scratch on device %d", c->device);
+    rc_tuning tuning;
+    {
+        std::lock_guard<std::mutex> lk(c->job_mu);
+        tuning = c->tuning;
+    }
+    DevJob dj[kNoAllocJobs];
+    Scene *held[kNoAllocJobs];
+    int n_run = 0;
+    int64_t total = 0;
+    int fmt = FMT_BINARY;
+    rc_status st = prepare_jobs(c, tuning, jobs, n_jobs, dj, held, &n_run, total, fmt, nullptr);
+    if (st == RC_OK && total > 0 && (!out_range || !out_hit)) st = fail(RC_E_INVAL, "null output");
+    if (st == RC_OK && total > 0 && hipSetDevice(c->device) != hipSuccess)
+        st = fail(RC_E_DEVICE, "hipSetDevice(%d) failed", c->device);
+    DropRec *d = nullptr;
+    if (st == RC_OK && total > 0) {
+        std::lock_guard<std::mutex> lk(c->ref_mu);
+        if (!c->drop_free.empty()) {
+            d = &c->drop_pool[c->drop_free.back()];
+            c->drop_free.pop_back();
+        }
+    }
+    if (st == RC_OK && total > 0 && !d)
+        st = fail(RC_E_BUSY, "%d launches of rc_raycast_batch_noalloc are still in flight",
+                  kDropPool);
+    if (st != RC_OK || total == 0) {
+        drop_holds(c, held, (size_t)n_run);
+        return st;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    WorkQueues q;
+    init_queues(q, total);
+    hipError_t e = hipSuccess;
+    for (int first = 0; e == hipSuccess && first < n_run; first += kFillJobs) {
+        ScratchFill a;
+        a.first = first;
+        a.count = n_run - first < kFillJobs ? n_run - first : kFillJobs;
+        a.with_queues = first == 0;
+        a.pad = 0;
+        a.queues = q;
+        memcpy(a.words, dj + first, sizeof(DevJob) * (size_t)a.count);
+        hipLaunchKernelGGL(k_fill_scratch, dim3(1), dim3(64), 0, s, c->scratch, a);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = trace_launch(TRACE_BVH, fmt, config_of(tuning),
+                         reinterpret_cast<DevJob *>(c->scratch + sizeof(WorkQueues)), n_run,
+                         reinterpret_cast<WorkQueues *>(c->scratch), total, out_range, out_hit,
+                         nullptr, nullptr, s);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        drop_holds(c, held, (size_t)n_run);
+        std::lock_guard<std::mutex> lk(c->ref_mu);
+        c->drop_free.push_back(d->slot);
+        return fail(RC_E_DEVICE, "traversal launch failed: %s", hipGetErrorString(e));
+    }
+    d->held.assign(held, held + n_run);   // within the reserved capacity
+    return enqueue_drop(c, s, d);
 }
 
 rc_status rc_raycast_bruteforce(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *out_range,

@@ -101,11 +101,19 @@ struct JobSlot {
 struct ServeState;  // serve.hip
 
 // References dropped by a host function once the work enqueued before it on
-// a stream has finished.
+// a stream has finished.  Records with slot >= 0 belong to the context's
+// pool, preallocated for the launch entry point that allocates nothing.
 struct DropRec {
     rc_ctx *c = nullptr;
     std::vector<Scene *> held;
+    int slot = -1;
 };
+
+// rc_raycast_batch_noalloc: jobs per call (its job table lives in a fixed
+// device array of WorkQueues + kNoAllocJobs DevJob records) and pooled drop
+// records per context (launches of it in flight at once).
+constexpr int kNoAllocJobs = 256;
+constexpr int kDropPool = 256;
 
 }  // namespace rc
 
@@ -135,6 +143,9 @@ struct rc_ctx {
     std::condition_variable ref_cv;
     std::vector<rc::Scene *> reap;       // dead scenes without references, freed under mu
     int pending_drops = 0;               // drop host functions enqueued and not yet run
+    std::vector<rc::DropRec> drop_pool;  // kDropPool records, each with room for
+    std::vector<int> drop_free;          //   kNoAllocJobs scenes; indices of free ones
+    char *scratch = nullptr;             // this device's fixed launch array (api.hip)
     std::mutex mesh_mu;            // TSDF / marching-cubes calls and their scratch
     void *mesh_ws = nullptr;       // grow-only scratch of those calls
     size_t mesh_ws_bytes = 0;

@@ -45,6 +45,7 @@ RC_GDBG_RECORDS = 4
 EXPORTED = [
     "rc_last_error", "rc_version", "rc_create", "rc_destroy", "rc_scene_upload",
     "rc_lbvh_build", "rc_scene_release", "rc_pattern_upload", "rc_raycast_batch",
+    "rc_raycast_batch_noalloc",
     "rc_raycast_bruteforce", "rc_raycast_stats", "rc_scene_get_info",
     "rc_scene_debug_copy", "rc_device_bytes", "rc_set_tuning", "rc_get_tuning",
     "rc_autotune", "rc_graph_create", "rc_graph_launch", "rc_graph_destroy",
@@ -171,6 +172,7 @@ def load() -> ctypes.CDLL:
         "rc_scene_release": ([P, I32], S),
         "rc_pattern_upload": ([P, P, I32, I32, ctypes.POINTER(I32)], S),
         "rc_raycast_batch": ([P, ctypes.POINTER(rc_job), I32, P, P, P], S),
+        "rc_raycast_batch_noalloc": ([P, ctypes.POINTER(rc_job), I32, P, P, P], S),
         "rc_raycast_bruteforce": ([P, ctypes.POINTER(rc_job), I32, P, P, P], S),
         "rc_raycast_stats": ([P, ctypes.POINTER(rc_job), I32, P, P, P, P, P], S),
         "rc_scene_get_info": ([P, I32, ctypes.POINTER(rc_scene_info)], S),
@@ -550,6 +552,9 @@ class Context:
         sp = _stream_ptr(stream)
         if mode == "bvh":
             _check(lib.rc_raycast_batch(self._h, arr, len(jobs), _ptr(out_range), _ptr(out_hit), sp))
+        elif mode == "noalloc":
+            _check(lib.rc_raycast_batch_noalloc(self._h, arr, len(jobs), _ptr(out_range),
+                                                _ptr(out_hit), sp))
         elif mode == "brute":
             _check(lib.rc_raycast_bruteforce(self._h, arr, len(jobs), _ptr(out_range),
                                              _ptr(out_hit), sp))
