@@ -279,6 +279,22 @@ rc_status rc_autotune(rc_ctx *ctx, const rc_job *jobs, int32_t n_jobs, float *ou
                       int32_t *out_hit, void *stream, int32_t reps, rc_tuning *out_best,
                       float *out_ms);
 
+/* Persisted autotuner results.  Once rc_tuning_cache_load has been called on
+ * a context, rc_autotune first looks the batch up by its key -- the device
+ * (architecture name and compute-unit count), the node format, the size
+ * class of the largest scene (floor(log2(triangles))), the beam pattern
+ * (rings x azimuths of the first job, or "mixed" when jobs differ), the
+ * size class of the batch (floor(log2(rays))) and of its job count -- and on
+ * a hit sets and reports the stored tuning without launching anything
+ * (*out_ms = -1, outputs untouched); on a miss it tunes as above and stores
+ * the result under the key.  The file (host path) is plain text, one entry
+ * per line after a version line; a missing file loads as an empty cache.
+ * rc_tuning_cache_save writes every entry (to `path`.tmp, then renames).
+ * Errors: RC_E_INVAL (bad argument, malformed file or an entry whose tuning
+ * is out of range: nothing is loaded), RC_E_DEVICE (file I/O failed). */
+rc_status rc_tuning_cache_load(rc_ctx *ctx, const char *path);
+rc_status rc_tuning_cache_save(rc_ctx *ctx, const char *path);
+
 /* A batch captured in a hipGraph (queue reset + one traversal launch) for
  * replay, e.g. once per simulation frame.  The job table (scenes, patterns,
  * pose and output pointers, ranges, offsets) and the context's tuning are

@@ -6,6 +6,7 @@
 // small host-to-device copy and one traversal launch on the caller's stream.
 #include "ctx.h"
 
+#include <errno.h>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -1108,7 +1109,130 @@ std::vector<rc_tuning> tuning_candidates()
 
 }  // namespace rc
 
+namespace rc {
+
+int log2_class(int64_t n)
+{
+    int k = 0;
+    while (n > 1) { n >>= 1; ++k; }
+    return k;
+}
+
+// Cache key of a batch (see rc_tuning_cache_load): device, node format,
+// size class of the largest scene, pattern shape, ray and job-count classes.
+rc_status tune_key(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, std::string *key)
+{
+    if (n_jobs < 1 || !jobs) return fail(RC_E_INVAL, "bad job list");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, c->device));
+    int64_t max_tris = 0, rays = 0;
+    int fmt = -1;
+    int32_t n_beams = -1, n_az = -1;
+    bool mixed = false;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        for (int32_t i = 0; i < n_jobs; ++i) {
+            Scene *sc = get_scene(c, jobs[i].scene);
+            Pattern *pt = get_pattern(c, jobs[i].pattern);
+            if (!sc || !pt) return fail(RC_E_NOTFOUND, "job %d: unknown scene or pattern", i);
+            if (sc->nt > max_tris) max_tris = sc->nt;
+            const int f = sc->node_format;
+            fmt = fmt < 0 ? f : (fmt == f ? fmt : 2);
+            const int32_t na = pt->n_az > 0 ? pt->n_az : pt->n_beams;
+            if (n_beams < 0) { n_beams = pt->n_beams; n_az = na; }
+            else if (n_beams != pt->n_beams || n_az != na) mixed = true;
+            rays += (int64_t)jobs[i].n_envs * pt->n_beams;
+        }
+    }
+    char buf[256];
+    char pat[64];
+    if (mixed) snprintf(pat, sizeof pat, "mixed");
+    else snprintf(pat, sizeof pat, "%dx%d", n_beams / (n_az > 0 ? n_az : 1), n_az);
+    snprintf(buf, sizeof buf, "%s:%dcu|fmt%d|tris2^%d|pat%s|rays2^%d|jobs2^%d",
+             prop.gcnArchName, prop.multiProcessorCount, fmt, log2_class(max_tris), pat,
+             log2_class(rays), log2_class(n_jobs));
+    for (char *p = buf; *p; ++p)
+        if (*p == ' ' || *p == '\t' || *p == '\n') *p = '_';
+    *key = buf;
+    return RC_OK;
+}
+
+constexpr const char *kTuneCacheHeader = "rcast-tuning-cache v1";
+
+}  // namespace rc
+
 extern "C" {
+
+rc_status rc_tuning_cache_load(rc_ctx *c, const char *path)
+{
+    if (!c || !path) return fail(RC_E_INVAL, "null argument");
+    std::map<std::string, rc_tuning> entries;
+    FILE *f = fopen(path, "r");
+    if (f) {
+        char line[1024];
+        int ln = 0;
+        rc_status st = RC_OK;
+        while (st == RC_OK && fgets(line, sizeof line, f)) {
+            ++ln;
+            if (ln == 1) {
+                if (strncmp(line, kTuneCacheHeader, strlen(kTuneCacheHeader)) != 0)
+                    st = fail(RC_E_INVAL, "%s: not a tuning cache (first line)", path);
+                continue;
+            }
+            if (line[0] == '\n' || line[0] == '#') continue;
+            char key[512];
+            rc_tuning t;
+            memset(&t, 0, sizeof t);
+            const int n = sscanf(line, "%511s %d %d %d %d %d %d %d %d %d", key, &t.persistent,
+                                 &t.stack_lds, &t.refill_min, &t.blocks_per_cu, &t.tile_az,
+                                 &t.tile_el, &t.chunk_max, &t.waves_cap, &t.group_waves);
+            if (n != 10) {
+                st = fail(RC_E_INVAL, "%s:%d: malformed entry", path, ln);
+                break;
+            }
+            if (check_tuning(&t) != RC_OK) {
+                st = fail(RC_E_INVAL, "%s:%d: tuning out of range", path, ln);
+                break;
+            }
+            entries[key] = t;
+        }
+        if (st == RC_OK && ferror(f)) st = fail(RC_E_DEVICE, "%s: read error", path);
+        fclose(f);
+        if (st != RC_OK) return st;
+    } else if (errno != ENOENT) {
+        return fail(RC_E_DEVICE, "%s: cannot open (%s)", path, strerror(errno));
+    }
+    std::lock_guard<std::mutex> lk(c->job_mu);
+    for (auto &kv : entries) c->tune_cache[kv.first] = kv.second;
+    c->tune_cache_on = true;
+    return RC_OK;
+}
+
+rc_status rc_tuning_cache_save(rc_ctx *c, const char *path)
+{
+    if (!c || !path) return fail(RC_E_INVAL, "null argument");
+    std::map<std::string, rc_tuning> entries;
+    {
+        std::lock_guard<std::mutex> lk(c->job_mu);
+        entries = c->tune_cache;
+    }
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return fail(RC_E_DEVICE, "%s: cannot create (%s)", tmp.c_str(), strerror(errno));
+    bool ok = fprintf(f, "%s\n", kTuneCacheHeader) > 0;
+    for (auto &kv : entries) {
+        const rc_tuning &t = kv.second;
+        ok = ok && fprintf(f, "%s %d %d %d %d %d %d %d %d %d\n", kv.first.c_str(), t.persistent,
+                           t.stack_lds, t.refill_min, t.blocks_per_cu, t.tile_az, t.tile_el,
+                           t.chunk_max, t.waves_cap, t.group_waves) > 0;
+    }
+    ok = (fclose(f) == 0) && ok;
+    if (!ok || rename(tmp.c_str(), path) != 0) {
+        remove(tmp.c_str());
+        return fail(RC_E_DEVICE, "%s: write failed", path);
+    }
+    return RC_OK;
+}
 
 rc_status rc_autotune(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *out_range,
                       int32_t *out_hit, void *stream, int32_t reps, rc_tuning *out_best,
@@ -1118,6 +1242,24 @@ rc_status rc_autotune(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *out_
     if (c->mock) return fail(RC_E_STATE, "a mock context has no device to tune");
     if (reps < 1) reps = 1;
     HIP_TRY(hipSetDevice(c->device));
+    bool use_cache;
+    {
+        std::lock_guard<std::mutex> lk(c->job_mu);
+        use_cache = c->tune_cache_on;
+    }
+    std::string key;
+    if (use_cache) {
+        rc_status st = tune_key(c, jobs, n_jobs, &key);
+        if (st != RC_OK) return st;
+        std::lock_guard<std::mutex> lk(c->job_mu);
+        auto it = c->tune_cache.find(key);
+        if (it != c->tune_cache.end()) {
+            c->tuning = it->second;
+            if (out_best) *out_best = it->second;
+            if (out_ms) *out_ms = -1.0f;
+            return RC_OK;
+        }
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
@@ -1155,6 +1297,7 @@ rc_status rc_autotune(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *out_
     {
         std::lock_guard<std::mutex> lk(c->job_mu);
         c->tuning = best;
+        if (use_cache) c->tune_cache[key] = best;
     }
     if (out_best) *out_best = best;
     if (out_ms) *out_ms = best_ms;

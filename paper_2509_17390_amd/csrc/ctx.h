@@ -8,6 +8,7 @@
 
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -146,6 +147,8 @@ struct rc_ctx {
     std::vector<rc::DropRec> drop_pool;  // kDropPool records, each with room for
     std::vector<int> drop_free;          //   kNoAllocJobs scenes; indices of free ones
     char *scratch = nullptr;             // this device's fixed launch array (api.hip)
+    bool tune_cache_on = false;    // rc_tuning_cache_load was called (guarded by job_mu)
+    std::map<std::string, rc_tuning> tune_cache;
     std::mutex mesh_mu;            // TSDF / marching-cubes calls and their scratch
     void *mesh_ws = nullptr;       // grow-only scratch of those calls
     size_t mesh_ws_bytes = 0;

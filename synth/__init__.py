@@ -27,6 +27,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import json
 import math
 import os
 import subprocess
@@ -80,6 +81,17 @@ def _p(a):
 
 # --------------------------------------------------------------------------
 # Beam patterns and poses
+
+CONFIG_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs")
+
+
+def workload_config(name: str) -> dict:
+    """The stored definition of a benchmark workload -- its seeds, sizes,
+    beam pattern and range -- from synth/configs/<name>.json, so every run of
+    a workload draws the same inputs."""
+    with open(os.path.join(CONFIG_DIR, name + ".json")) as fh:
+        return json.load(fh)
+
 
 def lidar_pattern(n_el: int, el_lo_deg: float, el_hi_deg: float, n_az: int) -> np.ndarray:
     """Spinning-LiDAR directions: elevations linspace(lo, hi, n_el) inclusive,

@@ -66,3 +66,20 @@ def test_terrain_scene():
     poses = synth.terrain_poses(height, boxes, 5, 1)
     z = poses[:, 11] - height(poses[:, 3], poses[:, 7])
     assert np.all((z >= 1.5 - 1e-4) & (z <= 3.0 + 1e-4))
+
+
+def test_workload_configs_are_complete():
+    """Every benchmark workload's seeds and sizes are stored, and the stored
+    room-sphere pattern is the one the generator draws."""
+    for name in ("room_sphere", "indoor_1m", "batched_4096", "uneven_64", "serve_16"):
+        c = synth.workload_config(name)
+        assert c["name"] == name and c["description"]
+        assert len(c["t_range"]) == 2 and c["t_range"][0] < c["t_range"][1]
+    rs = synth.workload_config("room_sphere")
+    s = synth.room_sphere_scene(rs["scene_seed"])
+    p = rs["pattern"]
+    assert len(s.dirs) == p["rings"] * p["azimuths"] and s.n_az == p["azimuths"]
+    assert (s.t_min, s.t_max) == tuple(rs["t_range"])
+    b = synth.workload_config("batched_4096")
+    bp = b["pattern"]
+    assert b["envs"] * bp["rings"] * bp["azimuths"] == 134_217_728
