@@ -39,8 +39,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-VALU_PEAK_GWI = 256 * 4 * 2.4 / 4   # G wave64 VALU instructions/s
 NODE_BYTES, TRI_BYTES, OUT_BYTES = 64, 40, 8
+# calibration launches: lanes (8 waves per SIMD on 256 CUs x 4 SIMDs, four
+# times over) and iterations per lane
+CALIB_LANES = 256 * 4 * 8 * 64 * 4
+CALIB_GATHER_ITERS = 32
+CALIB_VALU_ITERS = 2048
 
 
 def log(msg):
@@ -81,9 +85,86 @@ def load_traffic(kernel_hash: str, rays: int, tris: int, tuning: dict):
     return d
 
 
-def cpu_baseline(verts, tris, poses, dirs, t_min, t_max, g_range, g_hit, budget_s):
+def load_calib_counters():
+    """Vector-instruction counts of the calibration kernels (rocprofv3
+    SQ_INSTS_VALU per launch, profiles/calib_counters.json), valid while the
+    calibration source is unchanged; None otherwise."""
+    p = os.path.join(ROOT, "profiles", "calib_counters.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        d = json.load(fh)
+    if d.get("calib_hash") != kernel_source_hash(("calib.hip",)):
+        return None
+    if d.get("lanes") != CALIB_LANES or d.get("valu_iters") != CALIB_VALU_ITERS:
+        return None
+    return d
+
+
+def calibrate(torch, dev, stream, scene_record_bytes, reps=5):
+    """Measured ceilings of this device (rc_calib_gather / rc_calib_valu),
+    each the best of `reps` launches timed with HIP events on the launch
+    stream: random 64-byte record gathers from an L2-resident working set
+    (2 MiB), from one the size of the scene's node and triangle records, and
+    from 4 GiB (HBM); FP32 vector-instruction issue for the FMA-only and the
+    node-test mixes (instruction counts from the profiled counters)."""
+    from paper_2509_17390_amd import rcast
+    lib = rcast.load()
+    sp = ctypes_void(stream.cuda_stream)
+    sink = torch.empty(1024, dtype=torch.int32, device=dev)
+    out = {}
+
+    def timed(fn):
+        best = float("inf")
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            b.synchronize()
+            best = min(best, a.elapsed_time(b))
+        return best
+
+    sets = (("l2_2MiB", 2 << 20), ("scene_records", int(scene_record_bytes)),
+            ("hbm_4GiB", 4 << 30))
+    for name, nbytes in sets:
+        n_rec = max(nbytes // 64, 1)
+        buf = torch.ones(n_rec * 16, dtype=torch.float32, device=dev)
+
+        def g():
+            rcast._check(lib.rc_calib_gather(buf.data_ptr(), n_rec, CALIB_LANES,
+                                             CALIB_GATHER_ITERS, sink.data_ptr(), sp))
+        g()
+        ms = timed(g)
+        gb = CALIB_LANES * CALIB_GATHER_ITERS * 256 / (ms * 1e-3) / 1e9
+        out[f"gather_{name}"] = {"working_set_MB": round(n_rec * 64 / 1e6, 1),
+                                 "ms": round(ms, 4), "GB_s": round(gb, 1)}
+        del buf
+    counters = load_calib_counters()
+    for mix in (0, 1):
+        def v():
+            rcast._check(lib.rc_calib_valu(CALIB_LANES, CALIB_VALU_ITERS, mix, sink.data_ptr(),
+                                           sp))
+        v()
+        ms = timed(v)
+        ent = {"ms": round(ms, 4)}
+        if counters is not None:
+            insts = counters[f"valu_mix{mix}_insts"]
+            ent["wave_insts"] = insts
+            ent["G_wave_insts_s"] = round(insts / (ms * 1e-3) / 1e9, 1)
+        out[f"valu_mix{mix}"] = ent
+    torch.cuda.synchronize()
+    return out
+
+
+def ctypes_void(p):
+    import ctypes
+    return ctypes.c_void_p(int(p))
+
+
+def cpu_baseline(verts, tris, poses, dirs, t_min, t_max, g_range, g_hit, budget_s, seed):
     import oracle
-    rng = np.random.default_rng(12345)
+    rng = np.random.default_rng(seed)
     n_rays = len(poses) * len(dirs)
     threads = oracle.default_threads()
     calib = np.sort(rng.choice(n_rays, threads * 4, replace=False))
@@ -118,8 +199,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--envs", type=int, default=4096)
-    ap.add_argument("--h", type=float, default=0.035, help="marching-cubes spacing (m)")
+    ap.add_argument("--envs", type=int, default=0, help="environments (0: the stored workload's)")
+    ap.add_argument("--h", type=float, default=None,
+                    help="marching-cubes spacing in m (default: the stored workload's)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -142,6 +224,11 @@ def main():
                     help="serve: admission order, 0 arrival order, 1 fewest rays first with aging")
     ap.add_argument("--max-wait-ms", type=int, default=0,
                     help="serve, policy 1: age after which a request goes first (0: 200 ms)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving block")
+    ap.add_argument("--uneven-rays-per-job", type=int, default=0,
+                    help="uneven: oracle rays sampled per job (0: the stored workload's)")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="default run: requests per rate of the serving block")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -168,7 +255,10 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     dev = torch.device("cuda", 0)
     log("building scene ...")
-    s = synth.indoor_scene(seed=1, h=args.h, n_envs=args.envs, pose_seed=100)
+    wc = synth.workload_config("batched_4096")
+    h_mesh = args.h if args.h is not None else wc["h"]
+    s = synth.indoor_scene(seed=wc["mesh_seed"], h=h_mesh, n_envs=args.envs or wc["envs"],
+                           pose_seed=wc["pose_seed"])
     n_rays = s.n_rays
     log(f"mesh: {len(s.tris)} tris, {len(s.verts)} verts; rays/step {n_rays}")
 
@@ -260,12 +350,20 @@ def main():
 
     mean_nodes, mean_tris, same = stats(0)
     q8_nodes, q8_tris, same_q8 = stats(1)
-    b_ray = NODE_BYTES * mean_nodes + TRI_BYTES * mean_tris + OUT_BYTES
+    # cost-model bytes of the timed kernel: its own (Q8) record counts with
+    # the canonical record sizes
+    b_ray = NODE_BYTES * q8_nodes + TRI_BYTES * q8_tris + OUT_BYTES
+    b_ray_fp32 = NODE_BYTES * mean_nodes + TRI_BYTES * mean_tris + OUT_BYTES
     alg_bytes = b_ray * n_rays
     achieved = alg_bytes / (trace_ms * 1e-3) / 1e9
     khash = kernel_source_hash()
     counters = load_traffic(khash, n_rays, int(len(s.tris)), forms["q8"]["tuning"])
     traffic = counters["bytes_per_launch"] if counters else None
+    rec_bytes = 64 * info.n_q8_nodes + 48 * info.n_tris
+    log("calibrating gather and issue ceilings ...")
+    cal = calibrate(torch, dev, stream, rec_bytes)
+    l2_peak = cal["gather_l2_2MiB"]["GB_s"]
+    valu_peak = max(cal[f"valu_mix{m}"].get("G_wave_insts_s", 0.0) for m in (0, 1)) or None
 
     g_range = out_r.cpu().numpy()
     g_hit = out_h.cpu().numpy()
@@ -274,11 +372,34 @@ def main():
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
         cpu = cpu_baseline(s.verts, s.tris, s.poses, s.dirs, s.t_min, s.t_max, g_range, g_hit,
-                           args.cpu_budget)
+                           args.cpu_budget, wc["oracle_sample_seed"])
+    ctx.close()
+    del outputs, out_r, out_h, graph
+    torch.cuda.empty_cache()
+
+    serving = None
+    if not args.no_serve:
+        serving = serve_measure(16, args.serve_requests, [0.5, 0.9], args.inflight,
+                                args.batch_cap_m, args.policy, args.max_wait_ms)
+
+    valu = None
+    if counters is not None:
+        v_ach = counters["valu_insts_per_wave"] * (n_rays / 64) / (trace_ms * 1e-3) / 1e9
+        valu = {"achieved": round(v_ach, 1), "unit": "G wave-instructions/s",
+                "peak": valu_peak, "peak_source": "rc_calib_valu (measured issue ceiling)",
+                "frac": round(v_ach / valu_peak, 4) if valu_peak else None,
+                "active_lanes_of_64": counters["valu_active_threads"],
+                "insts_per_wave": counters["valu_insts_per_wave"]}
+    hbm = None
+    if traffic is not None:
+        h_ach = traffic / (trace_ms * 1e-3) / 1e9
+        hbm = {"achieved": round(h_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(h_ach / HBM_PEAK_GBS, 4),
+               "source": "rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, scaled by a 1 GiB copy"}
 
     value = n_rays / (ms_step * 1e-3) / 1e6
     out = {
-        "metric": "Mrays/s at 4096 envs x 32x1024 beams, 1M tris",
+        "metric": "Mrays/s at 4096 envs x 32x1024 beams, 1M tris; p50/p99 request latency",
         "value": round(value, 2),
         "unit": "Mrays/s",
         "n_gpus": 1,
@@ -291,12 +412,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"batched raycast: {args.envs} envs x 32x1024 beams on a "
+            "workload": f"batched raycast: {len(s.poses)} envs x 32x1024 beams on a "
                         f"{len(s.tris)}-triangle closed indoor mesh (marching cubes at "
-                        f"{args.h} m), step = LBVH build (Q8 nodes) + one graph-captured "
-                        f"batched launch",
+                        f"{h_mesh} m), step = LBVH build (Q8 nodes) + one graph-captured "
+                        f"batched launch; serving: Poisson requests on 16 resident terrains",
             "node_format": "q8",
-            "envs": args.envs, "beams": int(len(s.dirs)), "tris": int(len(s.tris)),
+            "envs": int(len(s.poses)), "beams": int(len(s.dirs)), "tris": int(len(s.tris)),
+            "seeds": "synth/configs/batched_4096.json",
             "rays_per_step": int(n_rays), "t_range": [s.t_min, s.t_max],
         },
         "frame_only": {"ms": round(trace_ms, 3),
@@ -304,41 +426,37 @@ def main():
         "build_ms": round(ms_step - trace_ms, 3),
         "forms": forms,
         "forms_bit_identical": same_forms,
+        # cost-model bytes (the paper's per-ray cost with canonical record
+        # sizes) per launch over the kernel's time, against the measured
+        # ceiling of 64-byte record gathers from L2 (every record fetch is at
+        # least an L2 request; HBM sees far less, see "hbm")
         "roofline": {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "bound": "l2", "achieved": round(achieved, 1), "peak": l2_peak, "unit": "GB/s",
+            "frac": round(achieved / l2_peak, 4),
+            "peak_source": "rc_calib_gather, random 64 B records, 2 MiB working set",
             "traffic": traffic,
             "kernel": "k_trace<TRACE_BVH, FMT_Q8> (graph replay)",
-            "bytes_per_ray": round(b_ray, 1), "mean_node_records": round(mean_nodes, 2),
-            "mean_tri_tests": round(mean_tris, 2),
-            "q8_mean_node_records": round(q8_nodes, 2), "q8_mean_tri_tests": round(q8_tris, 2),
+            "bytes_per_ray": round(b_ray, 1), "q8_mean_node_records": round(q8_nodes, 2),
+            "q8_mean_tri_tests": round(q8_tris, 2),
+            "fp32_tree": {"bytes_per_ray": round(b_ray_fp32, 1),
+                          "mean_node_records": round(mean_nodes, 2),
+                          "mean_tri_tests": round(mean_tris, 2)},
             "kernel_hash": khash,
+            "hbm": hbm,
+            "valu": valu,
+            "calibration": cal,
             "counters": None if counters is None else {
                 k: counters[k] for k in ("hbm_GBs", "l2_hit_pct", "valu_util_pct",
                                          "valu_active_threads", "valu_insts_per_wave",
                                          "read_bytes", "write_bytes")},
         },
-        # the bound the counters show: vector-instruction issue.  Peak: one
-        # wave64 VALU instruction per SIMD every 4 cycles, 4 SIMDs x 256 CUs
-        # at 2.4 GHz = 614.4 G wave-instructions/s (gfx950 can co-issue a
-        # second one in some cycles, so the fraction can pass 1)
-        "roofline_valu": None if counters is None else {
-            "bound": "alu", "unit": "G wave-instructions/s",
-            "achieved": round(counters["valu_insts_per_wave"] * (n_rays / 64)
-                              / (trace_ms * 1e-3) / 1e9, 1),
-            "peak": VALU_PEAK_GWI,
-            "frac": round(counters["valu_insts_per_wave"] * (n_rays / 64)
-                          / (trace_ms * 1e-3) / 1e9 / VALU_PEAK_GWI, 4),
-            "active_lanes_of_64": counters["valu_active_threads"],
-        },
         "cpu_baseline": cpu,
         "misses": misses,
         "stats_pass_matches": same and same_q8,
         "bvh_depth": info.depth,
-        "serving": None,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
-    ctx.close()
     return 0
 
 
@@ -353,6 +471,56 @@ def _stats_bytes(ctx, jobs, n_rays, torch, dev, stream):
     return float(nn.double().mean()), float(nt.double().mean())
 
 
+def uneven_oracle_leg(w, jobs, job_meta, q8_out, per_job, seed):
+    """The FP64 oracle (with its checker flags) on `per_job` seeded rays of
+    every job of the uneven batch -- every scene, the multi-million-triangle
+    ones included -- timed on this host's cores and compared with the GPU's
+    Q8 results under the parity bar: on rays the checker does not flag,
+    hit/miss agreement, equal ids and |range error| <= 1e-4 + 1e-6 t; on
+    flagged rays the GPU range may not exceed the oracle's nearest hit by
+    more than 1e-3 + 1e-5 t.  Counts only; the GPU tests assert."""
+    import oracle
+    g_r = q8_out[0].cpu().numpy()
+    g_h = q8_out[1].cpu().numpy()
+    rng = np.random.default_rng(seed)
+    threads = oracle.default_threads()
+    tot = {"rays": 0, "clean": 0, "edge_near": 0, "ambiguous": 0, "bad_hitmiss": 0,
+           "bad_id": 0, "bad_range": 0, "flagged_beyond_nearest": 0, "max_range_err_m": 0.0}
+    tris_tested = 0
+    t0 = time.perf_counter()
+    for j, (k, pi, idx) in zip(jobs, job_meta):
+        n = len(idx) * len(w.patterns[pi])
+        sel = np.sort(rng.choice(n, min(n, per_job), replace=False))
+        v, tr = w.scenes[k]
+        t, ids, flags, _, _ = oracle.raycast(v, tr, w.poses[idx], w.patterns[pi], w.t_min,
+                                             w.t_max, ray_idx=sel, threads=threads, checked=True)
+        gr = g_r[j.out_offset + sel].astype(np.float64)
+        gh = g_h[j.out_offset + sel]
+        clean = flags == 0
+        oh = ids >= 0
+        tol = 1e-4 + 1e-6 * np.where(oh, t, 0.0)
+        err = np.where(oh & (gh >= 0), np.abs(gr - np.where(oh, t, 0.0)), 0.0)
+        tot["rays"] += len(sel)
+        tot["clean"] += int(clean.sum())
+        tot["edge_near"] += int((flags & 1).sum())
+        tot["ambiguous"] += int((flags & 2).sum())
+        tot["bad_hitmiss"] += int((clean & (oh != (gh >= 0))).sum())
+        tot["bad_id"] += int((clean & oh & (gh != ids)).sum())
+        tot["bad_range"] += int((clean & oh & (gh == ids) & ~(err <= tol)).sum())
+        tot["flagged_beyond_nearest"] += int((~clean & oh & (gh >= 0) &
+                                              (gr > t + 1e-3 + 1e-5 * np.abs(t))).sum())
+        if (clean & oh).any():
+            tot["max_range_err_m"] = max(tot["max_range_err_m"], float(err[clean & oh].max()))
+        tris_tested += len(sel) * len(tr)
+    dt = time.perf_counter() - t0
+    return {"value": tot["rays"] / dt / 1e6, "unit": "Mrays/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{per_job} seeded rays from each of the {len(jobs)} jobs (all scenes), "
+                      f"FP64 brute force with checker flags, {tris_tested / tot['rays']:.0f} "
+                      f"triangles per ray on average, {dt:.1f} s",
+            "gpu_agreement": tot}
+
+
 def run_uneven(args):
     """64 resident terrain scenes (50k..5M triangles, log-uniform), 1024
     environments each bound to a random scene and one of three beam patterns
@@ -363,16 +531,18 @@ def run_uneven(args):
     from paper_2509_17390_amd import Context, Job
 
     dev = torch.device("cuda", 0)
-    n_scenes = args.scenes or 64
+    wc = synth.workload_config("uneven_64")
+    n_scenes = args.scenes or wc["scenes"]
     log(f"generating {n_scenes} terrains ...")
-    w = synth.uneven_world(seed=0, n_scenes=n_scenes, n_envs=1024)
+    w = synth.uneven_world(seed=wc["world_seed"], n_scenes=n_scenes, n_envs=wc["envs"],
+                           tri_lo=wc["tris_range"][0], tri_hi=wc["tris_range"][1])
     tris_total = int(sum(len(t) for _, t in w.scenes))
     ctx = Context(0)
     stream = torch.cuda.current_stream()
     sids = [ctx.upload_scene(v, t) for v, t in w.scenes]
     pids = [ctx.upload_pattern(d, na) for d, na in zip(w.patterns, w.n_az)]
     # one job per (scene, pattern) group of environments
-    jobs, off = [], 0
+    jobs, job_meta, off = [], [], 0
     poses_keep = []
     for k in range(n_scenes):
         for pi in range(len(w.patterns)):
@@ -382,6 +552,7 @@ def run_uneven(args):
             pt = torch.from_numpy(w.poses[idx]).to(dev)
             poses_keep.append(pt)
             jobs.append(Job(sids[k], pids[pi], pt, w.t_min, w.t_max, off))
+            job_meta.append((k, pi, idx))
             off += len(idx) * len(w.patterns[pi])
     n_rays = off
     out_r = torch.empty(n_rays, dtype=torch.float32, device=dev)
@@ -419,9 +590,19 @@ def run_uneven(args):
         log(f"uneven {name}: {ms:.2f} ms/launch, {forms[name]['Mrays_s']} Mrays/s")
     same = bool(torch.equal(outputs["fp32"][1], outputs["q8"][1]) and
                 torch.equal(outputs["fp32"][0].view(torch.int32), outputs["q8"][0].view(torch.int32)))
-    b_ray = NODE_BYTES * forms["fp32"]["mean_node_records"] + TRI_BYTES * forms["fp32"]["mean_tri_tests"] + OUT_BYTES
+    b_ray = NODE_BYTES * forms["q8"]["mean_node_records"] + TRI_BYTES * forms["q8"]["mean_tri_tests"] + OUT_BYTES
     kms = forms["q8"]["kernel_ms"]
     achieved = b_ray * n_rays / (kms * 1e-3) / 1e9
+    scene_rec = max(64 * ctx.scene_info(sid).n_q8_nodes + 48 * ctx.scene_info(sid).n_tris
+                    for sid in sids)
+    cal = calibrate(torch, dev, stream, scene_rec)
+    l2_peak = cal["gather_l2_2MiB"]["GB_s"]
+    cpu = None
+    if not args.no_cpu:
+        log("oracle leg: seeded rays of every job, checker flags ...")
+        cpu = uneven_oracle_leg(w, jobs, job_meta, outputs["q8"],
+                                args.uneven_rays_per_job or wc["oracle_rays_per_job"],
+                                wc["oracle_sample_seed"])
     out = {
         "metric": "Mrays/s, uneven batch: 64 resident scenes, 1024 envs, mixed patterns, one launch",
         "value": forms["q8"]["Mrays_s"], "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
@@ -433,9 +614,11 @@ def run_uneven(args):
                    "scenes": n_scenes, "tris_total": tris_total, "envs": 1024, "jobs": len(jobs),
                    "rays_per_step": int(n_rays), "node_format": "q8"},
         "forms": forms, "forms_bit_identical": same,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_ray": round(b_ray, 1)},
+        "roofline": {"bound": "l2", "achieved": round(achieved, 1), "peak": l2_peak,
+                     "unit": "GB/s", "frac": round(achieved / l2_peak, 4), "traffic": None,
+                     "peak_source": "rc_calib_gather, random 64 B records, 2 MiB working set",
+                     "bytes_per_ray": round(b_ray, 1), "calibration": cal},
+        "cpu_baseline": cpu,
         "misses": int((outputs["q8"][1] < 0).sum()),
     }
     print(json.dumps(out), flush=True)
@@ -443,13 +626,16 @@ def run_uneven(args):
     return 0
 
 
-def run_serve(args):
-    """Poisson-arriving requests against 16 resident terrain scenes.  Each
-    request: 1..4096 environments (log-uniform), a pattern of 16/32/64/128
-    rings x 360..2048 azimuths, a random scene.  Served: continuous batching
-    on Q8 BVHs (rc_serve_*).  Baseline: the same requests one at a time in
-    arrival order with plain FP32 BVHs (rc_raycast_batch + synchronize).
-    Rates are fractions of the server's measured capacity."""
+def serve_measure(n_scenes, n_requests, rates, inflight, batch_cap_m, policy, max_wait_ms):
+    """Poisson-arriving requests against `n_scenes` resident terrain scenes
+    (50k..5M triangles, log-uniform).  Each request: 1..4096 environments
+    (log-uniform), a pattern of 16/32/64/128 rings x 360..2048 azimuths, a
+    random scene.  Served: continuous batching on Q8 BVHs (rc_serve_*).
+    Baseline: the same requests one at a time in arrival order with plain
+    FP32 BVHs (rc_raycast_batch + synchronize).  Rates are fractions of the
+    server's capacity, measured first with every request submitted at once.
+    Returns a dict with the capacity and, per rate, p50/p99 latency and
+    Mrays/s of both."""
     import threading
 
     import torch
@@ -458,22 +644,22 @@ def run_serve(args):
     from paper_2509_17390_amd.rcast import RC_OK, last_error
 
     dev = torch.device("cuda", 0)
-    n_scenes = args.scenes or 16
-    rng = np.random.default_rng(1)
-    log(f"generating {n_scenes} terrains ...")
+    wc = synth.workload_config("serve_16")
+    rng = np.random.default_rng(wc["size_seed"])
+    log(f"serving: generating {n_scenes} terrains ...")
     sizes = np.exp(rng.uniform(np.log(5e4), np.log(5e6), n_scenes))
     ctx = Context(0)
     stream = torch.cuda.current_stream()
     q8_ids, fp_ids, pose_pools = [], [], []
     for k, n in enumerate(sizes):
-        v, t, height, boxes = synth.terrain_scene(500 + k, int(n))
+        v, t, height, boxes = synth.terrain_scene(wc["terrain_seed_base"] + k, int(n))
         a = ctx.upload_scene(v, t)
         ctx.build(a, node_format=1, stream=stream)
         b = ctx.upload_scene(v, t)
         ctx.build(b, node_format=0, stream=stream)
         q8_ids.append(a)
         fp_ids.append(b)
-        pose_pools.append(synth.terrain_poses(height, boxes, 256, 900 + k))
+        pose_pools.append(synth.terrain_poses(height, boxes, 256, wc["pose_seed_base"] + k))
     torch.cuda.synchronize()
     spans = {16: (-15.0, 15.0), 32: (-16.0, 15.0), 64: (-25.0, 3.0), 128: (-22.5, 22.5)}
     bank = []
@@ -495,9 +681,8 @@ def run_serve(args):
         return out
 
     def serve_run(reqs, arrivals):
-        ctx.serve_start(arena_bytes=48 << 30, max_inflight=args.inflight,
-                        max_batch_rays_m=args.batch_cap_m, policy=args.policy,
-                        max_wait_ms=args.max_wait_ms)
+        ctx.serve_start(arena_bytes=48 << 30, max_inflight=inflight,
+                        max_batch_rays_m=batch_cap_m, policy=policy, max_wait_ms=max_wait_ms)
         tickets = [None] * len(reqs)
         t0 = time.perf_counter()
 
@@ -541,17 +726,17 @@ def run_serve(args):
         return np.array(lat), time.perf_counter() - t0
 
     # capacity: everything submitted at once
-    calib = make_reqs(args.requests, 7)
+    calib = make_reqs(n_requests, wc["capacity_request_seed"])
     lat, wall, _ = serve_run(calib, np.zeros(len(calib)))
     rays = sum(r[3] for r in calib)
     cap_rps = len(calib) / wall
-    log(f"capacity {cap_rps:.1f} req/s, {rays / wall / 1e6:.0f} Mrays/s saturated")
-    rates = [float(x) for x in args.rates.split(",")]
+    log(f"serving capacity {cap_rps:.1f} req/s, {rays / wall / 1e6:.0f} Mrays/s saturated")
     results = []
     for k, frac in enumerate(rates):
         lam = frac * cap_rps
-        reqs = make_reqs(args.requests, 100 + k)
-        arrivals = np.cumsum(np.random.default_rng(200 + k).exponential(1.0 / lam, len(reqs)))
+        reqs = make_reqs(n_requests, wc["rate_request_seed_base"] + k)
+        arrivals = np.cumsum(np.random.default_rng(wc["arrival_seed_base"] + k).exponential(
+            1.0 / lam, len(reqs)))
         arrivals -= arrivals[0]
         rays = sum(r[3] for r in reqs)
         sl, sw, st = serve_run(reqs, arrivals)
@@ -570,7 +755,27 @@ def run_serve(args):
                                  "Mrays_s": round(rays / bw / 1e6, 1)},
         })
         log(json.dumps(results[-1]))
-    head = results[-1]
+    ctx.close()
+    return {
+        "workload": f"Poisson requests, {n_scenes} resident terrains ({int(sizes.sum())} "
+                    f"triangles, 50k..5M each), 1..4096 envs (log-uniform), 20 patterns "
+                    f"(16/32/64/128 rings x 360..2048 azimuths); served = Q8 nodes, continuous "
+                    f"batching; per_request_fp32 = one rc_raycast_batch per request, FP32 "
+                    f"nodes, arrival order",
+        "capacity_req_s": round(cap_rps, 2),
+        "capacity_Mrays_s": round(sum(r[3] for r in calib) / wall / 1e6, 1),
+        "batch_cap_m_rays": batch_cap_m, "max_inflight": inflight, "policy": policy,
+        "max_wait_ms": max_wait_ms or 200, "rates": results,
+    }
+
+
+def run_serve(args):
+    """Serving sweep (see serve_measure), one JSON line."""
+    n_scenes = args.scenes or 16
+    rates = [float(x) for x in args.rates.split(",")]
+    res = serve_measure(n_scenes, args.requests, rates, args.inflight, args.batch_cap_m,
+                        args.policy, args.max_wait_ms)
+    head = res["rates"][-1]
     out = {
         "metric": "p50/p99 request latency and Mrays/s, served (Q8, continuous batching) vs "
                   "plain per-request FP32",
@@ -578,15 +783,10 @@ def run_serve(args):
         "steps": args.requests, "warmup": 0, "ms_per_step": head["served"]["p50_ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"Poisson requests, {n_scenes} resident terrains "
-                               f"({int(sizes.sum())} triangles), 1..4096 envs, 20 patterns",
-                   "capacity_req_s": round(cap_rps, 2), "batch_cap_m_rays": args.batch_cap_m,
-                   "max_inflight": args.inflight, "policy": args.policy,
-                   "max_wait_ms": args.max_wait_ms or 200},
-        "rates": results,
+        "config": {k: v for k, v in res.items() if k != "rates"},
+        "rates": res["rates"],
     }
     print(json.dumps(out), flush=True)
-    ctx.close()
     return 0
 
 
@@ -601,7 +801,7 @@ def run_frame(args):
     from paper_2509_17390_amd import Context, Job
 
     dev = torch.device("cuda", 0)
-    h = 0.0145 if args.h == 0.035 else args.h
+    h = 0.0145 if args.h is None else args.h
     log(f"polygonising at h = {h} m ...")
     sdf, v, t = synth.indoor_mesh(1, h)
     ctx = Context(0)

@@ -20,7 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT_DIR = os.path.join(PKG, "_lib")
 OBJ_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "librcast.so")
-SOURCES = ["api.hip", "build.hip", "trace.hip", "serve.hip", "gauss.hip", "vox.hip", "tsdf.hip", "nn.hip", "meshopt.hip"]
+SOURCES = ["api.hip", "build.hip", "trace.hip", "serve.hip", "gauss.hip", "vox.hip", "tsdf.hip", "nn.hip",
+           "meshopt.hip", "calib.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

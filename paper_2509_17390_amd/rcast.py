@@ -54,6 +54,7 @@ EXPORTED = [
     "rc_gauss_release", "rc_voxelize", "rc_voxelize_counts", "rc_gauss_debug_copy",
     "rc_tsdf", "rc_marching_cubes", "rc_marching_cubes_table", "rc_nearest",
     "rc_chamfer_fscore", "rc_taubin_smooth", "rc_decimate", "rc_remove_small_components",
+    "rc_calib_gather", "rc_calib_valu", "rc_tuning_cache_load", "rc_tuning_cache_save",
 ]
 
 RC_DEVICE_MOCK = -1
@@ -211,6 +212,10 @@ def load() -> ctypes.CDLL:
                                         ctypes.POINTER(I64), P], S),
         "rc_chamfer_fscore": ([P, P, I64, P, I64, ctypes.c_float, ctypes.POINTER(rc_fidelity),
                                P], S),
+        "rc_tuning_cache_load": ([P, ctypes.c_char_p], S),
+        "rc_tuning_cache_save": ([P, ctypes.c_char_p], S),
+        "rc_calib_gather": ([P, U64, I64, I32, P, P], S),
+        "rc_calib_valu": ([I64, I32, I32, P, P], S),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -574,6 +579,15 @@ class Context:
                                   _stream_ptr(stream), int(reps), ctypes.byref(best),
                                   ctypes.byref(ms)))
         return best.as_dict(), float(ms.value)
+
+    def tuning_cache_load(self, path: str):
+        """Load persisted autotuner results (a missing file is an empty cache)
+        and make autotune() consult and extend them; autotune() then reports
+        ms = -1 for a batch found in the cache."""
+        _check(load().rc_tuning_cache_load(self._h, os.fsencode(path)))
+
+    def tuning_cache_save(self, path: str):
+        _check(load().rc_tuning_cache_save(self._h, os.fsencode(path)))
 
     def graph(self, jobs: Sequence[Job], out_range, out_hit) -> "Graph":
         return Graph(self, jobs, out_range, out_hit)

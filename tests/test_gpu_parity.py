@@ -446,6 +446,44 @@ def test_autotune_keeps_results_and_sets_tuning(ctx):
         ctx.reset_tuning()
 
 
+def test_autotune_cache_persists_across_contexts(tmp_path):
+    # a context with a loaded (empty) cache tunes and stores the result; a
+    # second context loading the saved file gets the same tuning without
+    # launching (ms = -1, outputs untouched); a different batch size class
+    # misses and is tuned again
+    import torch
+    s = synth.indoor_scene(seed=4, h=0.1, n_envs=16, n_az=256)
+    path = str(tmp_path / "tuning.txt")
+    got = []
+    for k in range(2):
+        c = Context(0)
+        try:
+            c.tuning_cache_load(path)
+            scene = c.upload_scene(s.verts, s.tris)
+            c.build(scene, node_format=1)
+            pat = c.upload_pattern(s.dirs, s.n_az)
+            job = [Job(scene, pat, cuda(s.poses), s.t_min, s.t_max)]
+            n = len(s.poses) * len(s.dirs)
+            r = torch.full((n,), -1.0, device="cuda")
+            h = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+            best, ms = c.autotune(job, r, h, reps=1)
+            torch.cuda.synchronize()
+            got.append((best, ms, bool((h == -7).all())))
+            assert c.get_tuning() == best
+            if k == 1:
+                job1 = [Job(scene, pat, cuda(s.poses[:1]), s.t_min, s.t_max)]
+                _, ms1 = c.autotune(job1, r, h, reps=1)
+                assert ms1 > 0
+            c.tuning_cache_save(path)
+        finally:
+            c.close()
+    (b0, ms0, untouched0), (b1, ms1, untouched1) = got
+    assert ms0 > 0 and not untouched0
+    assert ms1 == -1.0 and untouched1 and b1 == b0
+    lines = open(path).read().splitlines()
+    assert lines[0] == "rcast-tuning-cache v1" and len(lines) == 3
+
+
 @pytest.mark.parametrize("fmt,persistent", [(0, 0), (1, 0), (1, 1)])
 def test_graph_replays_match_eager(ctx, fmt, persistent):
     # capture once, move the sensors between replays (eager torch work and a
@@ -515,6 +553,52 @@ def test_uneven_multi_scene_batch(ctx):
         compare_with_oracle(v, t, w.poses[idx], w.patterns[pi], w.t_min, w.t_max,
                             r1.cpu().numpy(), h1.cpu().numpy(), ray_idx=sample,
                             min_checked_frac=0.9)
+
+
+def test_large_terrain_sampled_parity(ctx):
+    # a 2.5M-triangle terrain (heightfield + boxes sunk into the ground, so
+    # interpenetrating surfaces give ambiguous rays), 32 poses x 64 x 1024
+    # beams in one launch, both node formats; the oracle checks a seeded
+    # sample with its checker flags
+    import torch
+    v, t, height, boxes = synth.terrain_scene(77, 2_500_000)
+    assert len(t) >= 2_000_000
+    poses = synth.terrain_poses(height, boxes, 32, 78)
+    dirs = synth.lidar_pattern(64, -25.0, 3.0, 1024)
+    n_rays = len(poses) * len(dirs)
+    log(f"terrain tris={len(t)} rays={n_rays}")
+    scene = ctx.upload_scene(v, t)
+    pat = ctx.upload_pattern(dirs, 1024)
+    out = {}
+    for fmt in (0, 1):
+        ctx.build(scene, node_format=fmt)
+        r, h = ctx.cast([Job(scene, pat, cuda(poses), 0.1, 120.0, 0)])
+        torch.cuda.synchronize()
+        out[fmt] = (r.cpu().numpy(), h.cpu().numpy())
+    (r32, h32), (rq, hq) = out[0], out[1]
+    assert np.array_equal(h32, hq) and np.array_equal(r32.view(np.int32), rq.view(np.int32))
+    idx = np.sort(np.random.default_rng(5).choice(n_rays, 384, replace=False))
+    st = compare_with_oracle(v, t, poses, dirs, 0.1, 120.0, rq, hq, ray_idx=idx,
+                             min_checked_frac=0.9)
+    log(str(st))
+
+
+def test_indoor_2cm_sampled_parity(ctx):
+    # the indoor mesh polygonised at 2 cm as written (3.39M triangles), 8
+    # poses x 32 x 1024 beams, Q8 nodes; seeded oracle sample
+    s = synth.indoor_scene(seed=1, h=0.02, n_envs=8)
+    assert len(s.tris) > 3_000_000
+    log(f"indoor 2 cm tris={len(s.tris)} rays={s.n_rays}")
+    scene = ctx.upload_scene(s.verts, s.tris)
+    ctx.build(scene, node_format=1)
+    pat = ctx.upload_pattern(s.dirs, s.n_az)
+    r, h = ctx.cast([Job(scene, pat, cuda(s.poses), s.t_min, s.t_max, 0)])
+    r, h = r.cpu().numpy(), h.cpu().numpy()
+    assert np.all(h >= 0)   # closed mesh, poses in free space
+    idx = np.sort(np.random.default_rng(9).choice(s.n_rays, 384, replace=False))
+    st = compare_with_oracle(s.verts, s.tris, s.poses, s.dirs, s.t_min, s.t_max, r, h,
+                             ray_idx=idx)
+    log(str(st))
 
 
 def test_batch_larger_than_one_dispatch(ctx):
