@@ -152,6 +152,57 @@ def box_room(lo=ROOM_LO, hi=ROOM_HI):
     return verts, np.array(tris, dtype=np.int32)
 
 
+def grid_patch(n: int, size: float = 1.0, z: float = 0.0):
+    """Open flat square [0, size]^2 at height z: an n x n grid of quads, each
+    split along its diagonal; (n + 1)^2 vertices, 2 n^2 triangles."""
+    g = np.linspace(0.0, size, n + 1)
+    X, Y = np.meshgrid(g, g, indexing="xy")
+    verts = np.stack([X.ravel(), Y.ravel(), np.full(X.size, z)], axis=1).astype(np.float32)
+    tris = []
+    for j in range(n):
+        for i in range(n):
+            a = j * (n + 1) + i
+            b, c, d = a + 1, a + n + 2, a + n + 1
+            tris.append((a, b, c))
+            tris.append((a, c, d))
+    return verts, np.array(tris, dtype=np.int32)
+
+
+def grid_box(lo, hi, n: int):
+    """Closed axis-aligned box whose six faces are n x n grids of quads split
+    along a diagonal, vertices shared along the box edges (watertight),
+    outward-facing; 12 n^2 triangles."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    index = {}
+    verts = []
+
+    def vid(p):
+        key = tuple(int(round(c)) for c in p)
+        if key not in index:
+            index[key] = len(verts)
+            verts.append([lo[k] + (hi[k] - lo[k]) * key[k] / n for k in range(3)])
+        return index[key]
+    tris = []
+    for ax in range(3):
+        a, b = (ax + 1) % 3, (ax + 2) % 3
+        for side in (0, n):
+            for i in range(n):
+                for j in range(n):
+                    def pt(ui, uj):
+                        p = [0, 0, 0]
+                        p[ax], p[a], p[b] = side, ui, uj
+                        return vid(p)
+                    p00, p10, p11, p01 = pt(i, j), pt(i + 1, j), pt(i + 1, j + 1), pt(i, j + 1)
+                    if side == n:
+                        tris.append((p00, p10, p11))
+                        tris.append((p00, p11, p01))
+                    else:
+                        tris.append((p00, p11, p10))
+                        tris.append((p00, p01, p11))
+    return np.array(verts, dtype=np.float32), np.array(tris, dtype=np.int32)
+
+
 def uv_sphere(center, r: float, n_seg: int = 64, n_ring: int = 32):
     """UV sphere with vertices on the sphere (FP64, rounded to float32).
     2 * n_seg * (n_ring - 1) triangles (64 x 32 -> 3,968)."""
