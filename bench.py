@@ -77,7 +77,7 @@ def load_traffic(kernel_hash: str, rays: int, tris: int, tuning: dict):
         d = json.load(fh)
     # the kernel variant is fixed by these fields (the packet tile only
     # reorders the rays of the same kernel)
-    variant = ("persistent", "stack_lds", "waves_cap", "group_waves")
+    variant = ("persistent", "stack_lds", "waves_cap", "group_waves", "leaf_batch")
     t0 = d.get("tuning") or {}
     if (d.get("kernel_hash") != kernel_hash or d.get("rays") != rays
             or d.get("tris") != tris or any(t0.get(k) != tuning.get(k) for k in variant)):
@@ -229,6 +229,9 @@ def main():
                     help="uneven: oracle rays sampled per job (0: the stored workload's)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="default run: requests per rate of the serving block")
+    ap.add_argument("--tuning", type=str, default="",
+                    help='batched: fixed launch shape instead of the autotuner, as JSON '
+                         'rc_tuning fields, e.g. {"leaf_batch": 32}')
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -280,7 +283,11 @@ def main():
         # real batch, capture the launch in a graph
         ctx.build(scene, node_format=fmt, stream=stream)
         torch.cuda.synchronize()
-        if args.no_autotune:
+        if args.tuning:
+            ctx.reset_tuning()
+            ctx.set_tuning(**json.loads(args.tuning))
+            best, tune_ms = ctx.get_tuning(), float("nan")
+        elif args.no_autotune:
             ctx.reset_tuning()
             best, tune_ms = ctx.get_tuning(), float("nan")
         else:

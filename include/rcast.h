@@ -258,6 +258,14 @@ typedef struct {
                               grid: 1 (default; a finished wave frees its slot
                               at once) or 4 (spreads a small launch over more
                               CUs) */
+    int32_t leaf_batch;    /* one-ray-per-thread grid on quantised (RC_NODE_Q8)
+                              trees: 0 tests each leaf's triangle when the
+                              lane reaches it; 1..64 queues (lane, leaf) pairs
+                              per wave and tests them 64 at a time, with every
+                              lane busy, once this many are queued (lanes keep
+                              traversing meanwhile).  Ignored for launches
+                              with a scene of more than 2^26 triangles, for
+                              plain FP32 trees and for persistent waves. */
 } rc_tuning;
 
 /* Set (NULL: reset to defaults) or read the context's traversal tuning.
@@ -271,6 +279,8 @@ rc_status rc_get_tuning(rc_ctx *ctx, rc_tuning *out);
  * one-ray-per-thread with stack_lds {0, 8} x waves_cap {1, 0} x tiles
  * {16x4, 8x8, 32x2, plain} in one-wave workgroups, and with stack_lds
  * {0, 8} x waves_cap {1, 0} x tiles {16x4, plain} in four-wave workgroups;
+ * queued leaf tests with leaf_batch {16, 32, 64} in one- and four-wave
+ * workgroups (16x4 tiles, register cap);
  * persistent with stack_lds {8, 16} x refill_min {48, 64} x blocks_per_cu
  * {2, 4}.  Every candidate writes the same,
  * complete results into out_range / out_hit.  Synchronises `stream`.

@@ -231,6 +231,7 @@ rc_tuning default_tuning()
     t.chunk_max = 4096;
     t.waves_cap = 1;
     t.group_waves = 1;
+    t.leaf_batch = 0;
     return t;
 }
 
@@ -334,9 +335,14 @@ rc_status stage_jobs(rc_ctx *c, const std::vector<DevJob> &dj, int64_t total, hi
     return RC_OK;
 }
 
-TraceConfig config_of(const rc_tuning &t)
+// Launch configuration of a batch: the tuning, with queued leaf tests off
+// when a scene is too large for the queue's packed (lane, leaf) words.
+TraceConfig config_of(const rc_tuning &t, const DevJob *jobs, int n_jobs)
 {
     TraceConfig cfg;
+    cfg.leaf_batch = t.leaf_batch;
+    for (int k = 0; k < n_jobs; ++k)
+        if ((int64_t)jobs[k].n_tris > kLeafBatchMaxTris) cfg.leaf_batch = 0;
     cfg.persistent = t.persistent;
     cfg.stack_lds = t.stack_lds;
     cfg.refill_min = t.refill_min;
@@ -425,15 +431,15 @@ rc_status trace_common(rc_ctx *c, int mode, const rc_job *jobs, int32_t n_jobs, 
     if (own) {
         st = stage_own(c, *own, dj, total, s, &djd, &dq);
         if (st != RC_OK) return st;
-        e = trace_launch(mode, fmt, config_of(tuning), djd, n_run, dq, total, out_range, out_hit,
-                         out_nodes, out_tris, s);
+        e = trace_launch(mode, fmt, config_of(tuning, dj.data(), n_run), djd, n_run, dq, total,
+                         out_range, out_hit, out_nodes, out_tris, s);
     } else {
         std::lock_guard<std::mutex> lk(c->job_mu);
         JobSlot *slot = nullptr;
         st = stage_jobs(c, dj, total, s, &djd, &dq, &slot);
         if (st != RC_OK) return st;
-        e = trace_launch(mode, fmt, config_of(tuning), djd, n_run, dq, total, out_range, out_hit,
-                         out_nodes, out_tris, s);
+        e = trace_launch(mode, fmt, config_of(tuning, dj.data(), n_run), djd, n_run, dq, total,
+                         out_range, out_hit, out_nodes, out_tris, s);
         if (e == hipSuccess) e = hipEventRecord(slot->done, s);
         if (e == hipSuccess) slot->used = true;
     }
@@ -918,7 +924,7 @@ rc_status rc_raycast_batch_noalloc(rc_ctx *c, const rc_job *jobs, int32_t n_jobs
         e = hipGetLastError();
     }
     if (e == hipSuccess)
-        e = trace_launch(TRACE_BVH, fmt, config_of(tuning),
+        e = trace_launch(TRACE_BVH, fmt, config_of(tuning, dj, n_run),
                          reinterpret_cast<DevJob *>(c->scratch + sizeof(WorkQueues)), n_run,
                          reinterpret_cast<WorkQueues *>(c->scratch), total, out_range, out_hit,
                          nullptr, nullptr, s);
@@ -1066,6 +1072,7 @@ rc_status check_tuning(const rc_tuning *t)
         return fail(RC_E_INVAL, "chunk_max must be 0 or 64..2^20");
     if (t->waves_cap != 0 && t->waves_cap != 1) return fail(RC_E_INVAL, "waves_cap must be 0 or 1");
     if (t->group_waves != 1 && t->group_waves != 4) return fail(RC_E_INVAL, "group_waves must be 1 or 4");
+    if (t->leaf_batch < 0 || t->leaf_batch > 64) return fail(RC_E_INVAL, "leaf_batch must be 0..64");
     if (t->refill_min < 1 || t->refill_min > 64) return fail(RC_E_INVAL, "refill_min must be 1..64");
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return fail(RC_E_INVAL, "blocks_per_cu must be 0..64");
     if (t->tile_az < 0 || t->tile_el < 0 || (int64_t)t->tile_az * t->tile_el > (1 << 20))
@@ -1092,6 +1099,15 @@ std::vector<rc_tuning> tuning_candidates()
                     t.group_waves = gw;
                     v.push_back(t);
                 }
+    // queued leaf tests (Q8 trees; ignored on plain trees, where these
+    // candidates repeat the first ones)
+    for (int lb : {16, 32, 64})
+        for (int gw : {1, 4}) {
+            rc_tuning t = default_tuning();
+            t.leaf_batch = lb;
+            t.group_waves = gw;
+            v.push_back(t);
+        }
     for (int ss : {8, 16})
         for (int rm : {48, 64})
             for (int b : {2, 4}) {
@@ -1157,7 +1173,8 @@ rc_status tune_key(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, std::string *k
     return RC_OK;
 }
 
-constexpr const char *kTuneCacheHeader = "rcast-tuning-cache v1";
+constexpr const char *kTuneCacheHeader = "rcast-tuning-cache v2";
+constexpr const char *kTuneCacheHeaderV1 = "rcast-tuning-cache v1";  // no leaf_batch column
 
 }  // namespace rc
 
@@ -1170,12 +1187,16 @@ rc_status rc_tuning_cache_load(rc_ctx *c, const char *path)
     FILE *f = fopen(path, "r");
     if (f) {
         char line[1024];
-        int ln = 0;
+        int ln = 0, fields = 11;
         rc_status st = RC_OK;
         while (st == RC_OK && fgets(line, sizeof line, f)) {
             ++ln;
             if (ln == 1) {
-                if (strncmp(line, kTuneCacheHeader, strlen(kTuneCacheHeader)) != 0)
+                if (strncmp(line, kTuneCacheHeader, strlen(kTuneCacheHeader)) == 0)
+                    fields = 11;
+                else if (strncmp(line, kTuneCacheHeaderV1, strlen(kTuneCacheHeaderV1)) == 0)
+                    fields = 10;
+                else
                     st = fail(RC_E_INVAL, "%s: not a tuning cache (first line)", path);
                 continue;
             }
@@ -1183,10 +1204,11 @@ rc_status rc_tuning_cache_load(rc_ctx *c, const char *path)
             char key[512];
             rc_tuning t;
             memset(&t, 0, sizeof t);
-            const int n = sscanf(line, "%511s %d %d %d %d %d %d %d %d %d", key, &t.persistent,
+            const int n = sscanf(line, "%511s %d %d %d %d %d %d %d %d %d %d", key, &t.persistent,
                                  &t.stack_lds, &t.refill_min, &t.blocks_per_cu, &t.tile_az,
-                                 &t.tile_el, &t.chunk_max, &t.waves_cap, &t.group_waves);
-            if (n != 10) {
+                                 &t.tile_el, &t.chunk_max, &t.waves_cap, &t.group_waves,
+                                 &t.leaf_batch);
+            if (n != fields) {
                 st = fail(RC_E_INVAL, "%s:%d: malformed entry", path, ln);
                 break;
             }
@@ -1222,9 +1244,10 @@ rc_status rc_tuning_cache_save(rc_ctx *c, const char *path)
     bool ok = fprintf(f, "%s\n", kTuneCacheHeader) > 0;
     for (auto &kv : entries) {
         const rc_tuning &t = kv.second;
-        ok = ok && fprintf(f, "%s %d %d %d %d %d %d %d %d %d\n", kv.first.c_str(), t.persistent,
-                           t.stack_lds, t.refill_min, t.blocks_per_cu, t.tile_az, t.tile_el,
-                           t.chunk_max, t.waves_cap, t.group_waves) > 0;
+        ok = ok && fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d\n", kv.first.c_str(),
+                           t.persistent, t.stack_lds, t.refill_min, t.blocks_per_cu, t.tile_az,
+                           t.tile_el, t.chunk_max, t.waves_cap, t.group_waves,
+                           t.leaf_batch) > 0;
     }
     ok = (fclose(f) == 0) && ok;
     if (!ok || rename(tmp.c_str(), path) != 0) {
@@ -1388,7 +1411,8 @@ rc_status rc_graph_create(rc_ctx *c, const rc_job *jobs, int32_t n_jobs, float *
     if (e == hipSuccess && total > 0) {
         e = queue_reset_launch(live, tmpl, g->cap);
         if (e == hipSuccess)
-            e = trace_launch(TRACE_BVH, fmt, config_of(tuning), djd, n_run, live, total,
+            e = trace_launch(TRACE_BVH, fmt, config_of(tuning, dj.data(), n_run), djd, n_run, live,
+                             total,
                              out_range, out_hit, nullptr, nullptr, g->cap);
         if (e != hipSuccess) {
             hipGraph_t junk = nullptr;

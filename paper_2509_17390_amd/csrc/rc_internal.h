@@ -104,7 +104,13 @@ struct TraceConfig {
     int chunk_max;      // largest ray chunk a persistent wave takes per atomic
     int waves_cap;      // 1: cap registers for 8 waves per SIMD (one-ray-per-thread kernel)
     int group_waves;    // waves per workgroup of the one-ray-per-thread grid (1 or 4)
+    int leaf_batch;     // Q8 grid: 0 tests leaves on the spot; 1..64 queues them per wave
+                        // and tests them once this many are queued (scenes < 2^26 tris)
 };
+
+// Largest scene (triangles) the queued-leaf traversal takes: a queued pair
+// packs the lane (6 bits) and the leaf (26 bits) into one word.
+constexpr int64_t kLeafBatchMaxTris = (int64_t)1 << 26;
 
 // ---------------------------------------------------------------------------
 // Launchers (implemented in build.hip / trace.hip).  All return hipError_t.

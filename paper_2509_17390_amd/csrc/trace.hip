@@ -582,6 +582,286 @@ __global__ __launch_bounds__(BLK, WAVES) void k_trace(const DevJob *__restrict__
     finish_ray<MODE>(L, out_range, out_hit, out_nodes, out_tris);
 }
 
+// ---------------------------------------------------------------------------
+// Deferred triangle tests (Q8 nodes, one ray per lane).
+//
+// In the kernels above a lane tests the leaves of a node as soon as it finds
+// them, so the whole wave runs the ~110-instruction triangle test whenever
+// any one of its lanes has reached a leaf, with the other lanes idle; at the
+// headline workload that happens in nearly every loop iteration.  Here the
+// node visits only collect (lane, leaf) pairs in a per-wave queue in LDS,
+// and the wave alternates between two kinds of step:
+//  * node step: every lane that still has nodes to visit visits one; the
+//    leaves it finds in range are appended to the queue (a wave prefix sum
+//    of the per-lane leaf counts gives each lane its slots);
+//  * triangle step, taken once `batch` pairs are queued (or when no lane has
+//    nodes left): lane i tests the i-th queued pair against the owner lane's
+//    ray (kept in LDS) and folds the hit into the owner's best (t, id) with
+//    a 64-bit LDS atomic minimum -- for t >= 0 the bit pattern of t followed
+//    by the id orders exactly like the (t, id) pairs -- so one step runs up
+//    to 64 tests with every lane busy.
+// A lane keeps traversing while its pairs wait: its culling distance is the
+// best hit known at the last triangle step, which is never below the true
+// best, so culling stays conservative and the result is the same (t, id)
+// minimum as on-the-spot testing -- bit-identical, only the set of nodes
+// visited changes.  A triangle step runs at most 64 tests and is taken
+// before the queue holds 64, so it never holds more than 63 + 4 x 64 pairs.
+constexpr int kRing = 320;            // >= 63 + 4 * 64 queued pairs
+constexpr int kLeafBits = 26;         // leaf index bits of a queued pair
+constexpr uint64_t kNoHit = ~0ull;
+
+struct DeferWave {
+    float o[3][64];         // triangle-test frame of each lane's ray: permuted origin
+    float s[3][64];         //   shear constants Sx, Sy, Sz
+    int k[64];              //   kx | ky << 2 | kz << 4
+    float tmin[64], tmax[64];
+    const TriRec *tris[64];
+    unsigned long long best[64];   // (t bits << 32) | triangle id, kNoHit when none
+    int best_leaf[64];
+    uint32_t ring[kRing];          // queued pairs: lane << 26 | leaf
+};
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Node visit without triangle tests: sets *lm to the in-range leaf children
+// (bit k: slot k of ref[], nearest first) and returns true when the lane has
+// no node left.
+template <int STK, int BLK>
+__device__ __forceinline__ bool node_step_q8_collect(LaneRay &L, LaneStack<0, STK, BLK> &S,
+                                                     int32_t ref[4], uint32_t *lm)
+{
+    *lm = 0u;
+    if (++L.fetched > L.n_tris_scene + 64) { L.corrupt = true; return true; }
+    const NodeRec nd = load_node(L.nodes, L.node);
+    ++L.n_nodes;
+    const float org[3] = {nd.q0.x, nd.q0.y, nd.q0.z};
+    const float scl[3] = {nd.q0.w, nd.q1.x, nd.q1.y};
+    const uint32_t qlo[3] = {__float_as_uint(nd.q1.z), __float_as_uint(nd.q2.x),
+                             __float_as_uint(nd.q2.z)};
+    const uint32_t qhi[3] = {__float_as_uint(nd.q1.w), __float_as_uint(nd.q2.y),
+                             __float_as_uint(nd.q2.w)};
+    float an[3], af[3], bb[3];
+    uint32_t qn[3], qf[3];
+    for (int a = 0; a < 3; ++a) {
+        const float inv = L.r.inv[a];
+        const float aa = (org[a] - L.r.org[a]) * inv;
+        const float b = scl[a] * inv;
+        const float E = kQErr * fmaf(255.0f, fabsf(b), fabsf(aa));
+        an[a] = aa - E;
+        af[a] = aa + E;
+        bb[a] = b;
+        const bool neg = inv < 0.0f;
+        qn[a] = neg ? qhi[a] : qlo[a];
+        qf[a] = neg ? qlo[a] : qhi[a];
+    }
+    const int32_t cref[4] = {nd.q3.x, nd.q3.y, nd.q3.z, nd.q3.w};
+    float t[4];
+    for (int k = 0; k < 4; ++k) {
+        const float en = fmaxf(fmaxf(fmaf(qbyte(qn[0], k), bb[0], an[0]),
+                                     fmaf(qbyte(qn[1], k), bb[1], an[1])),
+                               fmaxf(fmaf(qbyte(qn[2], k), bb[2], an[2]), L.t_lo));
+        const float ex = fminf(fminf(fmaf(qbyte(qf[0], k), bb[0], af[0]),
+                                     fmaf(qbyte(qf[1], k), bb[1], af[1])),
+                               fminf(fmaf(qbyte(qf[2], k), bb[2], af[2]), L.t_hi));
+        const bool hit = cref[k] != kEmptyChild && en <= ex;
+        t[k] = hit ? en : INFINITY;
+        ref[k] = cref[k];
+    }
+#define RC_CSWAP(i, j)                                                  \
+    if (t[j] < t[i]) {                                                  \
+        float tt = t[i]; t[i] = t[j]; t[j] = tt;                        \
+        int32_t rr = ref[i]; ref[i] = ref[j]; ref[j] = rr;              \
+    }
+    RC_CSWAP(0, 1) RC_CSWAP(2, 3) RC_CSWAP(0, 2) RC_CSWAP(1, 3) RC_CSWAP(1, 2)
+#undef RC_CSWAP
+    // missed children carry +inf, which an unbounded range must not admit
+    const float lim = fminf(L.t_hi, FLT_MAX);
+    uint32_t m = 0;
+    for (int k = 0; k < 4; ++k) m |= (ref[k] < 0 && t[k] <= lim) ? 1u << k : 0u;
+    *lm = m;
+    int next = -1;
+    float next_t = 0.0f;
+    for (int k = 3; k >= 0; --k) {
+        if (ref[k] >= 0 && t[k] <= lim) {
+            if (next >= 0) {
+                if (L.sp == STK) { L.corrupt = true; return true; }
+                S.put(L.sp, next, next_t);
+                ++L.sp;
+            }
+            next = ref[k];
+            next_t = t[k];
+        }
+    }
+    if (next >= 0) { L.node = next; return false; }
+    while (L.sp > 0) {
+        --L.sp;
+        int n;
+        float tt;
+        S.get(L.sp, n, tt);
+        if (tt <= L.t_hi) { L.node = n; return false; }
+    }
+    return true;
+}
+
+// Output location of flattened ray g (as setup_ray computes it).
+__device__ __forceinline__ void ray_location(const DevJob *__restrict__ jobs, int n_jobs, int64_t g,
+                                             const float **pose, const float **beam, int64_t *out)
+{
+    const DevJob &jb = jobs[find_job(jobs, n_jobs, g)];
+    const uint32_t local = (uint32_t)(g - jb.ray_begin);
+    const uint32_t nb = (uint32_t)jb.n_beams;
+    const uint32_t e = udiv(local, jb.div_beams);
+    const uint32_t q = local - e * nb;
+    const uint32_t bm = tile_beam(jb, q);
+    *pose = jb.poses + 12 * (int64_t)e;
+    *beam = jb.dirs + 3 * (int64_t)bm;
+    *out = jb.out_offset + (int64_t)e * nb + bm;
+}
+
+template <int MODE, int WAVES, int BLK>
+__global__ __launch_bounds__(BLK, WAVES) void k_trace_defer(const DevJob *__restrict__ jobs,
+                                                        int n_jobs, int64_t g0, int64_t total,
+                                                        int batch, float *__restrict__ out_range,
+                                                        int32_t *__restrict__ out_hit,
+                                                        int32_t *__restrict__ out_nodes,
+                                                        int32_t *__restrict__ out_tris)
+{
+    __shared__ DeferWave s_wave[BLK / 64];
+    DeferWave &W = s_wave[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
+    const int64_t g = g0 + (int64_t)blockIdx.x * BLK + threadIdx.x;
+    const bool valid = g < total;
+    LaneRay L;
+    LaneStack<0, kStackQ8, BLK> S;
+    S.ln = nullptr;
+    S.lt = nullptr;
+    bool trav = false;
+    L.corrupt = false;
+    L.n_tris = 0;
+    L.n_nodes = 0;
+    if (valid) {
+        trav = setup_ray(jobs, n_jobs, g, L);
+        W.o[0][lane] = L.r.o[0];
+        W.o[1][lane] = L.r.o[1];
+        W.o[2][lane] = L.r.o[2];
+        W.s[0][lane] = L.r.Sx;
+        W.s[1][lane] = L.r.Sy;
+        W.s[2][lane] = L.r.Sz;
+        W.k[lane] = L.r.kx | L.r.ky << 2 | L.r.kz << 4;
+        W.tmin[lane] = L.t_min;
+        W.tmax[lane] = L.t_max;
+        W.tris[lane] = L.tris;
+        // a one-triangle scene was tested in setup_ray
+        W.best[lane] = L.best_leaf >= 0
+                           ? ((unsigned long long)__float_as_uint(L.best_t + 0.0f) << 32) |
+                                 (uint32_t)L.best_id
+                           : kNoHit;
+        W.best_leaf[lane] = L.best_leaf;
+    } else {
+        W.best[lane] = kNoHit;
+        W.best_leaf[lane] = -1;
+    }
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint32_t qhead = 0, qtail = 0;   // wave-uniform ring positions in [0, kRing)
+    while (true) {
+        wave_sync_lds();
+        const unsigned long long tb = __ballot(trav);
+        uint32_t pend = qtail - qhead;
+        if ((int32_t)pend < 0) pend += kRing;
+        if (tb == 0 && pend == 0) break;
+        if (pend >= 64u || pend >= (uint32_t)batch || tb == 0) {
+            // triangle step: lane i tests queued pair i
+            const uint32_t n = pend < 64u ? pend : 64u;
+            unsigned long long cand = kNoHit;
+            int owner = 0, leaf = 0;
+            if ((uint32_t)lane < n) {
+                uint32_t at = qhead + (uint32_t)lane;
+                if (at >= (uint32_t)kRing) at -= kRing;
+                const uint32_t pr = W.ring[at];
+                owner = (int)(pr >> kLeafBits);
+                leaf = (int)(pr & ((1u << kLeafBits) - 1u));
+                RayW r;
+                r.o[0] = W.o[0][owner];
+                r.o[1] = W.o[1][owner];
+                r.o[2] = W.o[2][owner];
+                r.Sx = W.s[0][owner];
+                r.Sy = W.s[1][owner];
+                r.Sz = W.s[2][owner];
+                const int kk = W.k[owner];
+                r.kx = kk & 3;
+                r.ky = (kk >> 2) & 3;
+                r.kz = kk >> 4;
+                const TriRec tr = load_tri(W.tris[owner], leaf);
+                float t;
+                if (woop32(r, tr.a, tr.b, tr.c, &t) && t >= W.tmin[owner] && t <= W.tmax[owner]) {
+                    cand = ((unsigned long long)__float_as_uint(t + 0.0f) << 32) |
+                           (uint32_t)__float_as_int(tr.c.y);
+                    atomicMin(&W.best[owner], cand);
+                }
+            }
+            wave_sync_lds();
+            // the pair that now holds its owner's minimum records the leaf
+            // (keys are unique: a leaf is queued at most once per ray)
+            if (cand != kNoHit && W.best[owner] == cand) W.best_leaf[owner] = leaf;
+            qhead += n;
+            if (qhead >= (uint32_t)kRing) qhead -= kRing;
+            wave_sync_lds();
+            if (trav) {
+                const unsigned long long b = W.best[lane];
+                if (b != kNoHit) L.t_hi = __uint_as_float((uint32_t)(b >> 32)) * (1.0f + kCullRel);
+            }
+        } else {
+            // node step
+            int32_t ref[4];
+            uint32_t lm = 0;
+            if (trav) trav = !node_step_q8_collect<kStackQ8, BLK>(L, S, ref, &lm);
+            const uint32_t cnt = (uint32_t)__popc(lm);
+            L.n_tris += (int)cnt;
+            const unsigned long long c0 = __ballot(cnt & 1u);
+            const unsigned long long c1 = __ballot(cnt & 2u);
+            const unsigned long long c2 = __ballot(cnt & 4u);
+            uint32_t pos = qtail + lanes_below(c0 & below) + 2u * lanes_below(c1 & below) +
+                           4u * lanes_below(c2 & below);
+            const uint32_t added = (uint32_t)__popcll(c0) + 2u * (uint32_t)__popcll(c1) +
+                                   4u * (uint32_t)__popcll(c2);
+#pragma unroll 1
+            while (lm != 0u) {
+                const int k = __builtin_ctz(lm);
+                lm &= lm - 1u;
+                const int32_t rk = k == 0 ? ref[0] : (k == 1 ? ref[1] : (k == 2 ? ref[2] : ref[3]));
+                const uint32_t at = pos >= (uint32_t)kRing ? pos - kRing : pos;
+                W.ring[at] = (uint32_t)lane << kLeafBits | (uint32_t)(~rk);
+                ++pos;
+            }
+            qtail += added;
+            if (qtail >= (uint32_t)kRing) qtail -= kRing;
+        }
+    }
+    if (!valid) return;
+    const float *pose, *beam;
+    ray_location(jobs, n_jobs, g, &pose, &beam, &L.out);
+    L.pose = pose;
+    L.beam = beam;
+    const unsigned long long b = W.best[lane];
+    if (b != kNoHit) {
+        L.best_leaf = W.best_leaf[lane];
+        L.best_t = __uint_as_float((uint32_t)(b >> 32));
+        L.best_id = (int)(uint32_t)b;
+    } else {
+        L.best_leaf = -1;
+    }
+    finish_ray<MODE>(L, out_range, out_hit, out_nodes, out_tris);
+}
+
 // Persistent waves with per-XCD queues, stealing and ballot refill.  Each
 // wave keeps a private pool of consecutive ray indices [pool_next, pool_end)
 // in scalar registers and refills idle lanes from it; the pool itself is
@@ -732,12 +1012,20 @@ hipError_t launch_mode(const TraceConfig &cfg, const DevJob *jobs, int n_jobs, W
                            n_jobs, g0, total, out_range, out_hit, out_nodes, out_tris)
 #define RC_GRID(SS_, W_)                                                                     \
         if (blk == 256) RC_GRID2(SS_, W_, 256); else RC_GRID2(SS_, W_, 64)
+#define RC_DEFER(W_, B_)                                                                     \
+        hipLaunchKernelGGL((k_trace_defer<MODE, W_, B_>), grid, dim3(B_), 0, s, jobs, n_jobs,  \
+                           g0, total, cfg.leaf_batch, out_range, out_hit, out_nodes, out_tris)
         if (MODE == TRACE_BRUTE) RC_GRID2(0, 1, 64);
+        else if (FMT == FMT_Q8 && cfg.leaf_batch > 0) {
+            if (blk == 256) { if (cfg.waves_cap) RC_DEFER(8, 256); else RC_DEFER(1, 256); }
+            else { if (cfg.waves_cap) RC_DEFER(8, 64); else RC_DEFER(1, 64); }
+        }
         else if (cfg.stack_lds == 0 && cfg.waves_cap) RC_GRID(0, 8);
         else if (cfg.stack_lds == 0) RC_GRID(0, 1);
         else if (cfg.stack_lds == 8 && cfg.waves_cap) RC_GRID(8, 8);
         else if (cfg.stack_lds == 8) RC_GRID(8, 1);
         else RC_GRID(16, 1);
+#undef RC_DEFER
 #undef RC_GRID
 #undef RC_GRID2
         hipError_t e = hipGetLastError();

@@ -92,7 +92,7 @@ class rc_tuning(ctypes.Structure):
                 ("refill_min", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("tile_az", ctypes.c_int32), ("tile_el", ctypes.c_int32),
                 ("chunk_max", ctypes.c_int32), ("waves_cap", ctypes.c_int32),
-                ("group_waves", ctypes.c_int32)]
+                ("group_waves", ctypes.c_int32), ("leaf_batch", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

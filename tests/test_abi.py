@@ -37,7 +37,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(rcast.rc_job) == 40
     assert ctypes.sizeof(rcast.rc_build_opts) == 32
     assert rcast.rc_scene_info.scene_lo.offset == 56
-    assert ctypes.sizeof(rcast.rc_tuning) == 36
+    assert ctypes.sizeof(rcast.rc_tuning) == 40      # ten int32 fields
     assert ctypes.sizeof(rcast.rc_gauss_opts) == 32
     assert ctypes.sizeof(rcast.rc_grid) == 48
     assert ctypes.sizeof(rcast.rc_tsdf_opts) == 32

@@ -208,6 +208,11 @@ TUNINGS = [
     dict(persistent=1, stack_lds=16, refill_min=48, blocks_per_cu=0, tile_az=64, tile_el=1, chunk_max=1024, waves_cap=0),
     dict(persistent=0, stack_lds=0, refill_min=64, blocks_per_cu=0, tile_az=16, tile_el=4, chunk_max=4096, waves_cap=1, group_waves=4),
     dict(persistent=0, stack_lds=16, refill_min=64, blocks_per_cu=0, tile_az=0, tile_el=0, chunk_max=4096, waves_cap=0, group_waves=4),
+    # queued leaf tests (Q8 trees only; plain trees ignore leaf_batch)
+    dict(persistent=0, stack_lds=0, refill_min=64, blocks_per_cu=0, tile_az=16, tile_el=4, chunk_max=4096, waves_cap=1, group_waves=1, leaf_batch=64),
+    dict(persistent=0, stack_lds=0, refill_min=64, blocks_per_cu=0, tile_az=16, tile_el=4, chunk_max=4096, waves_cap=1, group_waves=1, leaf_batch=1),
+    dict(persistent=0, stack_lds=0, refill_min=64, blocks_per_cu=0, tile_az=8, tile_el=8, chunk_max=4096, waves_cap=0, group_waves=1, leaf_batch=17),
+    dict(persistent=0, stack_lds=0, refill_min=64, blocks_per_cu=0, tile_az=0, tile_el=0, chunk_max=4096, waves_cap=1, group_waves=4, leaf_batch=32),
 ]
 
 
@@ -414,7 +419,10 @@ def test_q8_tuning_variants_bit_identical(ctx):
             log(f"q8 tuning {tn}")
             ctx.set_tuning(**tn)
             r, h = ctx.cast(job)
+            r2, h2, nn, nt = ctx.cast(job, mode="stats")
             torch.cuda.synchronize()
+            assert torch.equal(h, h2) and torch.equal(r.view(torch.int32), r2.view(torch.int32))
+            assert int(nn.min()) >= 1
             compare_with_oracle(s.verts, s.tris, s.poses, s.dirs, s.t_min, s.t_max,
                                 r.cpu().numpy(), h.cpu().numpy(), ray_idx=idx, oracle_out=orc)
             if ref is None:
@@ -422,6 +430,46 @@ def test_q8_tuning_variants_bit_identical(ctx):
             else:
                 assert torch.equal(h, ref[1])
                 assert torch.equal(r.view(torch.int32), ref[0].view(torch.int32))
+    finally:
+        ctx.reset_tuning()
+
+
+@pytest.mark.parametrize("leaf_batch", [1, 32, 64])
+def test_q8_leaf_batch_waves_across_scenes(ctx, leaf_batch):
+    # queued leaf tests: a wave whose lanes belong to different jobs (other
+    # scene, pattern, range) tests each queued pair against its own lane's
+    # scene and ray; results equal each job cast alone with on-the-spot tests
+    import torch
+    a = synth.room_sphere_scene(6)
+    sdf = synth.indoor_sdf(4, n_prims=30)
+    bv, bt = synth.polygonise(sdf, 0.12)
+    bposes = synth.free_space_poses(sdf, 3, 5)
+    sa = ctx.upload_scene(a.verts, a.tris)
+    sb = ctx.upload_scene(bv, bt)
+    ctx.build(sa, node_format=1)
+    ctx.build(sb, node_format=1)
+    dirs = synth.lidar_pattern(7, -20, 10, 45)          # 315 beams: waves straddle jobs
+    pat = ctx.upload_pattern(dirs, 45)
+    jobs = [Job(sa, pat, cuda(a.poses), 0.0, 100.0, 0),
+            Job(sb, pat, cuda(bposes), 0.1, 120.0, 315),
+            Job(sa, pat, cuda(a.poses), 0.5, 4.0, 315 * 4),
+            Job(sb, pat, cuda(bposes[:1]), 0.1, 2.5, 315 * 5)]
+    try:
+        singles = []
+        for j in jobs:
+            singles.append(ctx.cast([Job(j.scene, j.pattern, j.poses, j.t_min, j.t_max, 0)]))
+        ctx.set_tuning(leaf_batch=leaf_batch, tile_az=0, tile_el=0)
+        log(f"leaf_batch {leaf_batch}: straddling batch")
+        r_all, h_all = ctx.cast(jobs)
+        torch.cuda.synchronize()
+        for j, (r1, h1) in zip(jobs, singles):
+            n = j.n_envs * 315
+            sl = slice(j.out_offset, j.out_offset + n)
+            assert torch.equal(h_all[sl], h1) and torch.equal(r_all[sl].view(torch.int32),
+                                                              r1.view(torch.int32))
+        pb = bposes[:1]
+        compare_with_oracle(bv, bt, pb, dirs, 0.1, 2.5, r_all[315 * 5:].cpu().numpy(),
+                            h_all[315 * 5:].cpu().numpy())
     finally:
         ctx.reset_tuning()
 
@@ -481,7 +529,7 @@ def test_autotune_cache_persists_across_contexts(tmp_path):
     assert ms0 > 0 and not untouched0
     assert ms1 == -1.0 and untouched1 and b1 == b0
     lines = open(path).read().splitlines()
-    assert lines[0] == "rcast-tuning-cache v1" and len(lines) == 3
+    assert lines[0] == "rcast-tuning-cache v2" and len(lines) == 3
 
 
 @pytest.mark.parametrize("fmt,persistent", [(0, 0), (1, 0), (1, 1)])
