@@ -40,6 +40,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES, OUT_BYTES = 64, 40, 8
+# FP32 vector issue of one MI355X: 256 CUs x 4 SIMDs x 32 lanes per cycle at
+# 2.4 GHz = 78.64 T lane-instructions/s (the published 157.3 TFLOP/s FP32
+# vector peak counts an FMA lane-instruction as 2 flops); a wave64 vector
+# instruction occupies its SIMD for 2 cycles, so 1,228.8 G wave-instructions/s
+LANE_PEAK_T = 256 * 4 * 32 * 2.4e9 / 1e12
+VALU_PEAK_GWI = LANE_PEAK_T * 1e3 / 64
 # calibration launches: lanes (8 waves per SIMD on 256 CUs x 4 SIMDs, four
 # times over) and iterations per lane
 CALIB_LANES = 256 * 4 * 8 * 64 * 4
@@ -83,6 +89,40 @@ def load_traffic(kernel_hash: str, rays: int, tris: int, tuning: dict):
             or d.get("tris") != tris or any(t0.get(k) != tuning.get(k) for k in variant)):
         return None
     return d
+
+
+def load_cost_model():
+    """Vector-instruction cost of the Q8 traversal per unit of the paper's
+    cost model (Sec. IV-C: cost = C_trav N_nodes + C_tri K per ray), measured
+    with coherent waves (64 copies of one ray per wave, so a wave's
+    instruction count is one ray's) and fitted over eight dispatches:
+    lane-instructions per ray (set-up and output), per node visit and per
+    triangle test (profiles/trace_cost_model.json, `bench.py --workload
+    costmodel`).  None when absent."""
+    p = os.path.join(ROOT, "profiles", "trace_cost_model.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        d = json.load(fh)
+    d["kernel_hash_matches"] = d.get("kernel_hash") == kernel_source_hash()
+    return d
+
+
+def alu_roofline(cm, rays, mean_nodes, mean_tris, kernel_ms):
+    """ALU roofline of the traversal: the cost model's lane-instructions per
+    ray (C_ray + C_node N + C_tri K, with N and K the kernel's own mean node
+    visits and triangle tests from the instrumented pass) times the rays of one
+    launch, over the launch's time, against the chip's lane-instruction peak.
+    Idle lanes (divergence) and issue stalls are what separates it from 1."""
+    if cm is None:
+        return None
+    per_ray = cm["C_ray"] + cm["C_node"] * mean_nodes + cm["C_tri"] * mean_tris
+    ach = per_ray * rays / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(ach, 3), "peak": round(LANE_PEAK_T, 3),
+            "unit": "T lane-instructions/s", "frac": round(ach / LANE_PEAK_T, 4),
+            "lane_instructions_per_ray": round(per_ray, 1),
+            "cost_model": {k: cm[k] for k in ("C_ray", "C_node", "C_tri", "kernel_hash",
+                                              "kernel_hash_matches")}}
 
 
 def load_calib_counters():
@@ -207,7 +247,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shape (profiling runs)")
     ap.add_argument("--workload", choices=("batched", "uneven", "serve", "frame", "voxelize",
-                                           "mesh"),
+                                           "mesh", "costmodel"),
                     default="batched",
                     help="batched: 4096 envs on the 1M-triangle mesh (default); uneven: 64 "
                          "resident terrains, 1024 envs, mixed patterns in one launch; serve: "
@@ -232,6 +272,9 @@ def main():
     ap.add_argument("--tuning", type=str, default="",
                     help='batched: fixed launch shape instead of the autotuner, as JSON '
                          'rc_tuning fields, e.g. {"leaf_batch": 32}')
+    ap.add_argument("--ingest", type=str, default="",
+                    help="write profiles/*.json from rocprofv3 output: 'costmodel:<run dir>' "
+                         "or 'traffic:<run dir>' (see profiles/*.md for the runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -250,6 +293,10 @@ def main():
         return run_voxelize(args)
     if args.workload == "mesh":
         return run_mesh(args)
+    if args.workload == "costmodel":
+        return run_costmodel(args)
+    if args.ingest:
+        return ingest(args.ingest)
 
     import torch
     import synth
@@ -364,6 +411,7 @@ def main():
     alg_bytes = b_ray * n_rays
     achieved = alg_bytes / (trace_ms * 1e-3) / 1e9
     khash = kernel_source_hash()
+    cost_model = load_cost_model()
     counters = load_traffic(khash, n_rays, int(len(s.tris)), forms["q8"]["tuning"])
     traffic = counters["bytes_per_launch"] if counters else None
     rec_bytes = 64 * info.n_q8_nodes + 48 * info.n_tris
@@ -393,8 +441,9 @@ def main():
     if counters is not None:
         v_ach = counters["valu_insts_per_wave"] * (n_rays / 64) / (trace_ms * 1e-3) / 1e9
         valu = {"achieved": round(v_ach, 1), "unit": "G wave-instructions/s",
-                "peak": valu_peak, "peak_source": "rc_calib_valu (measured issue ceiling)",
-                "frac": round(v_ach / valu_peak, 4) if valu_peak else None,
+                "peak": round(VALU_PEAK_GWI, 1), "frac": round(v_ach / VALU_PEAK_GWI, 4),
+                "calibrated_ceiling": valu_peak,
+                "calibrated_source": "rc_calib_valu, independent FP32 FMAs",
                 "active_lanes_of_64": counters["valu_active_threads"],
                 "insts_per_wave": counters["valu_insts_per_wave"]}
     hbm = None
@@ -433,18 +482,26 @@ def main():
         "build_ms": round(ms_step - trace_ms, 3),
         "forms": forms,
         "forms_bit_identical": same_forms,
-        # cost-model bytes (the paper's per-ray cost with canonical record
-        # sizes) per launch over the kernel's time, against the measured
-        # ceiling of 64-byte record gathers from L2 (every record fetch is at
-        # least an L2 request; HBM sees far less, see "hbm")
-        "roofline": {
-            "bound": "l2", "achieved": round(achieved, 1), "peak": l2_peak, "unit": "GB/s",
-            "frac": round(achieved / l2_peak, 4),
-            "peak_source": "rc_calib_gather, random 64 B records, 2 MiB working set",
+        # the traversal is bound by vector issue and lane divergence, not by
+        # memory: its node and triangle records stay in L2 and MALL.  The
+        # roofline is therefore the ALU one -- the cost model's
+        # lane-instructions per launch over the kernel's time, against the
+        # chip's lane-instruction peak; the cost model's bytes are reported
+        # beside it as demand (served mostly by the caches, so above any
+        # memory level's bandwidth), with the HBM traffic the counters measure
+        "roofline": dict(alu_roofline(cost_model, n_rays, q8_nodes, q8_tris, trace_ms) or
+                         {"bound": "alu", "achieved": None, "peak": round(LANE_PEAK_T, 3),
+                          "unit": "T lane-instructions/s", "frac": None}, **{
             "traffic": traffic,
             "kernel": "k_trace<TRACE_BVH, FMT_Q8> (graph replay)",
-            "bytes_per_ray": round(b_ray, 1), "q8_mean_node_records": round(q8_nodes, 2),
+            "q8_mean_node_records": round(q8_nodes, 2),
             "q8_mean_tri_tests": round(q8_tris, 2),
+            "demand_bytes": {"bytes_per_ray": round(b_ray, 1), "GB_s": round(achieved, 1),
+                             "l2_gather_ceiling_GB_s": l2_peak,
+                             "note": "cost-model bytes (64 B per node record, 40 B per "
+                                     "triangle, 8 B output): lanes of a wave share most "
+                                     "records, so this exceeds what any memory level "
+                                     "delivers and is not a roofline fraction"},
             "fp32_tree": {"bytes_per_ray": round(b_ray_fp32, 1),
                           "mean_node_records": round(mean_nodes, 2),
                           "mean_tri_tests": round(mean_tris, 2)},
@@ -453,10 +510,11 @@ def main():
             "valu": valu,
             "calibration": cal,
             "counters": None if counters is None else {
-                k: counters[k] for k in ("hbm_GBs", "l2_hit_pct", "valu_util_pct",
-                                         "valu_active_threads", "valu_insts_per_wave",
-                                         "read_bytes", "write_bytes")},
-        },
+                k: counters.get(k) for k in ("hbm_GBs", "l2_hit_pct", "valu_util_pct",
+                                             "valu_active_threads", "valu_insts_per_wave",
+                                             "vmem_insts_per_wave", "ta_busy_pct",
+                                             "td_busy_pct", "read_bytes", "write_bytes")},
+        }),
         "cpu_baseline": cpu,
         "misses": misses,
         "stats_pass_matches": same and same_q8,
@@ -621,15 +679,176 @@ def run_uneven(args):
                    "scenes": n_scenes, "tris_total": tris_total, "envs": 1024, "jobs": len(jobs),
                    "rays_per_step": int(n_rays), "node_format": "q8"},
         "forms": forms, "forms_bit_identical": same,
-        "roofline": {"bound": "l2", "achieved": round(achieved, 1), "peak": l2_peak,
-                     "unit": "GB/s", "frac": round(achieved / l2_peak, 4), "traffic": None,
-                     "peak_source": "rc_calib_gather, random 64 B records, 2 MiB working set",
-                     "bytes_per_ray": round(b_ray, 1), "calibration": cal},
+        "roofline": dict(alu_roofline(load_cost_model(), n_rays,
+                                      forms["q8"]["mean_node_records"],
+                                      forms["q8"]["mean_tri_tests"], kms) or
+                         {"bound": "alu", "achieved": None, "peak": round(LANE_PEAK_T, 3),
+                          "unit": "T lane-instructions/s", "frac": None},
+                         traffic=None,
+                         demand_bytes={"bytes_per_ray": round(b_ray, 1),
+                                       "GB_s": round(achieved, 1),
+                                       "l2_gather_ceiling_GB_s": l2_peak},
+                         calibration=cal),
         "cpu_baseline": cpu,
         "misses": int((outputs["q8"][1] < 0).sum()),
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+    return 0
+
+
+def run_costmodel(args):
+    """Coherent-wave dispatches for the traversal's cost model (run under
+    rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU ...): 4,096 beams of the headline
+    pattern from 16 poses on the headline mesh, Q8 nodes, plain beam order;
+    the directions are ranked by their node and triangle counts and cut into
+    eight buckets, and each bucket is cast as one dispatch in which every
+    beam is repeated 64 times, so each wave casts 64 copies of one ray and
+    its vector-instruction count is that ray's.  Prints one JSON line per
+    dispatch with its waves, node visits and triangle tests."""
+    import torch
+    import synth
+    from paper_2509_17390_amd import Context, Job
+
+    wc = synth.workload_config("batched_4096")
+    s = synth.indoor_scene(seed=wc["mesh_seed"], h=wc["h"], n_envs=16, pose_seed=wc["pose_seed"])
+    dev = torch.device("cuda", 0)
+    ctx = Context(0)
+    scene = ctx.upload_scene(s.verts, s.tris)
+    ctx.build(scene, node_format=1)
+    ctx.set_tuning(tile_az=0, tile_el=0)
+    poses = torch.from_numpy(s.poses).to(dev)
+    rng = np.random.default_rng(5)
+    cand = np.ascontiguousarray(s.dirs[rng.choice(len(s.dirs), 4096, replace=False)])
+    pat1 = ctx.upload_pattern(cand, 0)
+    _, _, nn, nt = ctx.cast([Job(scene, pat1, poses, s.t_min, s.t_max, 0)], mode="stats")
+    nn = nn.cpu().numpy().reshape(16, 4096).astype(np.int64)
+    nt = nt.cpu().numpy().reshape(16, 4096).astype(np.int64)
+    order = np.argsort(nn.mean(0) + 5 * nt.mean(0), kind="stable")
+    for b in range(8):
+        sel = order[b * 512:(b + 1) * 512]
+        pat = ctx.upload_pattern(np.ascontiguousarray(np.repeat(cand[sel], 64, axis=0)), 0)
+        ctx.cast([Job(scene, pat, poses, s.t_min, s.t_max, 0)])
+        torch.cuda.synchronize()
+        print(json.dumps({"dispatch": b, "waves": 16 * 512, "sum_nodes": int(nn[:, sel].sum()),
+                          "sum_tris": int(nt[:, sel].sum())}), flush=True)
+    ctx.close()
+    return 0
+
+
+def _counter_rows(path, name_has):
+    """{dispatch id: {counter: value}} for kernels whose name contains
+    name_has, from a rocprofv3 counter_collection.csv."""
+    import csv
+    out = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if name_has in r["Kernel_Name"]:
+                out.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = \
+                    float(r["Counter_Value"])
+    return out
+
+
+def _find_csv(run_dir, tag):
+    for dp, _, fs in os.walk(run_dir):
+        for f in fs:
+            if f.endswith("counter_collection.csv") and tag in os.path.join(dp, f):
+                return os.path.join(dp, f)
+    raise FileNotFoundError(f"no counter_collection.csv for '{tag}' under {run_dir}")
+
+
+def ingest(spec):
+    """Turn rocprofv3 runs (made with the commands in profiles/*.md) into the
+    JSON files bench.py reads: 'costmodel:<dir>' fits the traversal's cost
+    model; 'traffic:<dir>' writes the headline kernel's counters."""
+    kind, _, run_dir = spec.partition(":")
+    if kind == "costmodel":
+        rows = _counter_rows(_find_csv(run_dir, "cm"), "k_trace<0, 1")
+        lines = [json.loads(l) for l in open(os.path.join(run_dir, "cm.log"))
+                 if l.startswith("{")]
+        disp = sorted(rows)
+        assert len(disp) == len(lines) == 8, (len(disp), len(lines))
+        a = np.array([[l["waves"], l["sum_nodes"], l["sum_tris"]] for l in lines], np.float64)
+        y = np.array([rows[d]["SQ_INSTS_VALU"] for d in disp])
+        assert all(rows[d]["SQ_WAVES"] == l["waves"] for d, l in zip(disp, lines))
+        x = np.linalg.lstsq(a, y, rcond=None)[0]
+        res = float(np.abs(a @ x - y).max() / y.mean())
+        out = {"C_ray": round(float(x[0]), 1), "C_node": round(float(x[1]), 1),
+               "C_tri": round(float(x[2]), 1), "fit_max_rel_residual": res,
+               "kernel_hash": kernel_source_hash(),
+               "dispatches": [{"waves": l["waves"], "sum_nodes": l["sum_nodes"],
+                               "sum_tris": l["sum_tris"],
+                               "SQ_INSTS_VALU": rows[d]["SQ_INSTS_VALU"]}
+                              for d, l in zip(disp, lines)],
+               "note": "lane-instructions (= wave-instructions of a coherent wave) per ray, "
+                       "per Q8 node visit and per triangle test; least squares over the "
+                       "dispatches of bench.py --workload costmodel"}
+        path = os.path.join(ROOT, "profiles", "trace_cost_model.json")
+    elif kind == "traffic":
+        def one(tag, name):
+            rows = _counter_rows(_find_csv(run_dir, tag), name)
+            keys = sorted(rows)
+            return {c: float(np.mean([rows[k][c] for k in keys])) for c in rows[keys[0]]}, len(keys)
+
+        def largest(tag, counter):
+            # the 1 GiB copy: the copy dispatch with the largest count
+            rows = _counter_rows(_find_csv(run_dir, tag), "copy")
+            return max(rows.values(), key=lambda r: r[counter])
+        tr = "k_trace<0, 1, 0, 8, 64>"
+        fetch, n = one("fetch", tr)
+        write, _ = one("write", tr)
+        cfetch = largest("fetch", "FETCH_SIZE")
+        cwrite = largest("write", "WRITE_SIZE")
+        l2, _ = one("l2", tr)
+        sq, _ = one("sq", tr)
+        tt, _ = one("tatd", tr)
+        gib = 1 << 30
+        fs = gib / 1024 / cfetch["FETCH_SIZE"]
+        ws = gib / 1024 / cwrite["WRITE_SIZE"]
+        rd = fetch["FETCH_SIZE"] * 1024 * fs
+        wr = write["WRITE_SIZE"] * 1024 * ws
+        import csv
+        bl = [json.loads(l) for l in open(os.path.join(run_dir, "bench.json")) if l.startswith("{")][-1]
+        meta = {"rays": bl["config"]["rays_per_step"], "tris": bl["config"]["tris"],
+                "tuning": bl["forms"]["q8"]["tuning"]}
+        kt = None
+        for dp, _, names in os.walk(run_dir):
+            for f in names:
+                if f.endswith("kernel_stats.csv"):
+                    kt = os.path.join(dp, f)
+        ns = None
+        with open(kt) as fh:
+            for r in csv.DictReader(fh):
+                if r["Name"].startswith("void (anonymous namespace)::" + tr):
+                    ns = float(r["AverageNs"])
+        assert ns, "headline kernel missing from the kernel trace"
+        cyc = sq["GRBM_GUI_ACTIVE"] / 8
+        w = sq["SQ_WAVES"]
+        out = {"kernel_hash": kernel_source_hash(), "rays": meta["rays"], "tris": meta["tris"],
+               "tuning": meta["tuning"], "kernel": tr, "dispatches": n,
+               "bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
+               "fetch_kib": fetch["FETCH_SIZE"], "write_kib": write["WRITE_SIZE"],
+               "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+               "avg_kernel_ns": ns, "hbm_GBs": round((rd + wr) / ns, 1),
+               "l2_hit_pct": round(100 * l2["TCC_HIT_sum"] / (l2["TCC_HIT_sum"] + l2["TCC_MISS_sum"]), 2),
+               "valu_util_pct": round(100 * sq["SQ_INSTS_VALU"] * 2 / (1024 * cyc), 1),
+               "valu_active_threads": round(sq["SQ_THREAD_CYCLES_VALU"] / sq["SQ_INSTS_VALU"], 2),
+               "valu_insts_per_wave": round(sq["SQ_INSTS_VALU"] / w, 1),
+               "salu_insts_per_wave": round(sq["SQ_INSTS_SALU"] / w, 1),
+               "vmem_insts_per_wave": round((sq["SQ_INSTS_VMEM_RD"] + sq["SQ_INSTS_VMEM_WR"]) / w, 1),
+               "smem_insts_per_wave": round(sq["SQ_INSTS_SMEM"] / w, 1),
+               "ta_busy_pct": round(100 * tt["TA_TA_BUSY_sum"] / (256 * tt["GRBM_GUI_ACTIVE"] / 8), 1),
+               "td_busy_pct": round(100 * tt["TD_TD_BUSY_sum"] / (256 * tt["GRBM_GUI_ACTIVE"] / 8), 1),
+               "note": "rocprofv3 --pmc passes over bench.py --no-autotune --calib-copy: FETCH_SIZE "
+                       "and WRITE_SIZE scaled by the 1 GiB copy; TCC_HIT/MISS; SQ and TA/TD "
+                       "counters; VALU utilisation = 2 cycles per wave64 instruction over "
+                       "1024 SIMDs x cycles"}
+        path = os.path.join(ROOT, "profiles", "trace_traffic.json")
+    else:
+        raise SystemExit(f"unknown --ingest kind '{kind}'")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps({"wrote": path}))
     return 0
 
 
@@ -1023,7 +1242,7 @@ def run_voxelize(args):
                                                   "valu_active_threads", "valu_insts_per_wave",
                                                   "read_bytes", "write_bytes")}},
         # instruction issue of the same kernel (one wave64 VALU instruction per
-        # SIMD every 4 cycles, 1024 SIMDs at 2.4 GHz)
+        # SIMD every 2 cycles, 1024 SIMDs at 2.4 GHz)
         "roofline_valu": None if counters is None else {
             "bound": "alu", "unit": "G wave-instructions/s",
             "achieved": round(counters["valu_insts_per_wave"] * counters["waves"]

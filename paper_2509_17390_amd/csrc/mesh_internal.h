@@ -173,3 +173,60 @@ hipError_t decimate_emit_launch(const float *verts, const double *Q, const uint8
                                 const double *lo, double c, const int32_t *tris, int64_t nt,
                                 const uint32_t *gid, const uint32_t *keep, const uint32_t *tpos,
                                 float *out_verts, int32_t *out_tris, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Quadric-error decimation by rounds of parallel edge contraction (qem.hip).
+
+constexpr int kQemFaces = 64;   // incident triangles per vertex
+constexpr int kQemNbrs = 64;    // distinct neighbours per vertex
+
+struct QemBuffers {
+    double *P;            // [nv][3] positions
+    int32_t *F;           // [nt][3] faces; F[t][0] = -1 once removed
+    double *Q;            // [nv][10] quadrics (upper triangle, row by row)
+    uint8_t *prot;        // [nv] protected in this round
+    uint32_t *fcnt;       // [nv] incident-face fill counters
+    int32_t *fl;          // [nv][kQemFaces] incident faces, ascending
+    int32_t *fdeg;        // [nv]
+    int32_t *nb;          // [nv][kQemNbrs] distinct neighbours, ascending
+    int32_t *ndeg;        // [nv]
+    uint32_t *nlarge;     // [nv] neighbours above the vertex
+    uint32_t *eoff;       // [nv] first edge number of the vertex
+    uint64_t *key;        // [3 nt] candidate key (cost bits << 32 | edge) or ~0
+    double *X;            // [3 nt][3] contraction point of a candidate
+    int32_t *eu, *ev;     // [3 nt] edge ends
+    unsigned long long *best;   // [nv]
+    int32_t *remap;       // [nv] contracted into (or -1)
+    uint32_t *counters;   // [4] candidates, contracted, live faces, flags
+    char *sel;            // qem_sel_bytes(): radix-select state
+};
+
+size_t qem_sel_bytes();
+// P from the float32 vertices; F from the triangles, faces with a repeated
+// corner removed.
+hipError_t qem_init_launch(const float *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                           double *P, int32_t *F, hipStream_t s);
+// Incident faces, neighbours and neighbour counts above each vertex; at a
+// round's start also the quadrics and protected flags.  counters[3] |= 1
+// (2) when a vertex has more than kQemFaces faces (kQemNbrs neighbours).
+hipError_t qem_incidence_launch(const QemBuffers &b, int64_t nv, int64_t nt, int round_start,
+                                hipStream_t s);
+// Candidate keys and points of every edge (eoff must hold the exclusive
+// scan of nlarge); counters[0] += candidates.
+hipError_t qem_edges_launch(const QemBuffers &b, int64_t nv, hipStream_t s);
+// Radix select of the rank-th smallest key (1-based) of n_edges keys.
+hipError_t qem_select_launch(const QemBuffers &b, int64_t n_edges, uint64_t rank, hipStream_t s);
+// Contract the chosen edges among the eligible ones (all candidates when
+// `all`, else keys up to the selected one) and rename the faces;
+// counters[1] += contractions, counters[2] += live faces.
+hipError_t qem_contract_launch(const QemBuffers &b, int64_t nv, int64_t nt, int64_t n_edges,
+                               int all, hipStream_t s);
+// keep[t] = live face, used[v] = 1 for their corners (used zeroed first).
+hipError_t qem_used_launch(const int32_t *F, int64_t nt, uint32_t *used, uint32_t *keep,
+                           hipStream_t s);
+// Used vertices (rounded to float32) and live faces at their scanned
+// positions, renumbered.
+hipError_t qem_emit_launch(const double *P, int64_t nv, const uint32_t *used,
+                           const uint32_t *newid, const int32_t *F, int64_t nt,
+                           const uint32_t *keep, const uint32_t *tpos, float *out_verts,
+                           int32_t *out_tris, hipStream_t s);

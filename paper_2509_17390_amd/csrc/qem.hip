@@ -1,0 +1,604 @@
+// qem.hip -- quadric-error decimation by rounds of parallel edge
+// contraction on gfx950 (FGGS-LiDAR Sec. IV-B "Mesh optimization":
+// quadric-error decimation to a face ratio; Sec. V: ratio 0.1, three
+// rounds, boundary protected).
+//
+// The quadric error metric is Garland and Heckbert's (1997): a vertex
+// carries the sum of the squared-distance quadrics of its faces' planes, an
+// edge (u, v) contracts to the point x* minimising x^T (Q_u + Q_v) x at that
+// minimum's cost, cheapest first.  One contraction at a time is sequential;
+// here a step contracts an independent set of locally cheapest edges at
+// once, so the work of a step is data-parallel over vertices, edges and
+// faces:
+//
+//   round k = 1..R runs until at most ceil(F0 ratio^(k/R)) faces remain (or
+//   nothing can contract); at its start the plane quadrics are summed anew
+//   and the vertices on a boundary or non-manifold edge (an edge not on
+//   exactly two faces) are protected for the round.  One step:
+//   1. incidence from the live faces: each vertex's faces (ascending) and
+//      its distinct neighbours (ascending); edges (u < v) numbered in
+//      lexicographic order by a scan of the neighbour counts above u;
+//   2. candidates: edges on exactly two faces, both ends unprotected,
+//      exactly two common neighbours (the link condition, so a closed
+//      manifold stays closed and manifold); x* is A^-1 b by Cramer's rule
+//      when A (the 3x3 block of Q_u + Q_v) is well conditioned and x* lies
+//      near the edge, else the cheapest of the ends and the midpoint; an
+//      edge whose contraction would flip a face is dropped; key = (float32
+//      cost, edge number);
+//   3. the ceil((F - T) / 2) smallest keys are eligible (a radix select of
+//      the threshold key; an interior contraction removes two faces);
+//   4. an eligible edge contracts when no eligible edge at any vertex of
+//      its two closed one-rings has a smaller key (per-vertex 64-bit atomic
+//      minima); such edges share no endpoint and no neighbour, so their
+//      contractions touch disjoint faces and run in place;
+//   5. faces are renamed through the contraction map; the two faces of
+//      each contracted edge degenerate and are dropped.
+// Positions, quadrics and costs are FP64 throughout, each operation in a
+// fixed order (compiled with -ffp-contract=off), so a run is deterministic
+// and matches a plain CPU evaluation of the same steps; positions are
+// rounded to float32 once, at the end.
+#include "mesh_internal.h"
+
+#include <float.h>
+#include <math.h>
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr uint64_t kNone = ~0ull;
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double r[3])
+{
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ __forceinline__ double dot3(const double a[3], const double b[3])
+{
+    return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+
+// n = (b - a) x (c - a)
+__device__ __forceinline__ void face_normal(const double a[3], const double b[3],
+                                            const double c[3], double n[3])
+{
+    const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    cross3(e1, e2, n);
+}
+
+__device__ __forceinline__ void load3(const double *__restrict__ P, int i, double r[3])
+{
+    r[0] = P[3 * (int64_t)i];
+    r[1] = P[3 * (int64_t)i + 1];
+    r[2] = P[3 * (int64_t)i + 2];
+}
+
+// Plane quadric K = q q^T / (n.n) of a face, q = (n, -n.a), upper triangle
+// row by row: (00 01 02 03 11 12 13 22 23 33); zero for a degenerate face.
+__device__ void plane_quadric(const double a[3], const double b[3], const double c[3],
+                              double K[10])
+{
+    double n[3];
+    face_normal(a, b, c, n);
+    const double nn = dot3(n, n);
+    if (nn == 0.0) {
+        for (int i = 0; i < 10; ++i) K[i] = 0.0;
+        return;
+    }
+    const double q[4] = {n[0], n[1], n[2], -dot3(n, a)};
+    int k = 0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = i; j < 4; ++j) K[k++] = (q[i] * q[j]) / nn;
+}
+
+// [x 1] Q [x 1]^T
+__device__ __forceinline__ double quadric_cost(const double Q[10], const double x[3])
+{
+    const double r0 = ((Q[0] * x[0] + Q[1] * x[1]) + Q[2] * x[2]) + Q[3];
+    const double r1 = ((Q[1] * x[0] + Q[4] * x[1]) + Q[5] * x[2]) + Q[6];
+    const double r2 = ((Q[2] * x[0] + Q[5] * x[1]) + Q[7] * x[2]) + Q[8];
+    const double r3 = ((Q[3] * x[0] + Q[6] * x[1]) + Q[8] * x[2]) + Q[9];
+    return ((x[0] * r0 + x[1] * r1) + x[2] * r2) + r3;
+}
+
+// x* = A^-1 b by Cramer's rule (cofactors along the first row) when
+// trace(A) > 0 and |det A| > 1e-6 (trace / 3)^3; false otherwise.
+__device__ bool minimiser(const double Q[10], double x[3])
+{
+    const double a00 = Q[0], a01 = Q[1], a02 = Q[2], b0 = -Q[3];
+    const double a11 = Q[4], a12 = Q[5], b1 = -Q[6];
+    const double a22 = Q[7], b2 = -Q[8];
+    const double det = (a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02)) +
+                       a02 * (a01 * a12 - a11 * a02);
+    const double tr = (a00 + a11) + a22;
+    const double t3 = tr / 3.0;
+    if (!(tr > 0.0 && fabs(det) > 1e-6 * ((t3 * t3) * t3))) return false;
+    x[0] = ((b0 * (a11 * a22 - a12 * a12) - a01 * (b1 * a22 - a12 * b2)) +
+            a02 * (b1 * a12 - a11 * b2)) / det;
+    x[1] = ((a00 * (b1 * a22 - a12 * b2) - b0 * (a01 * a22 - a12 * a02)) +
+            a02 * (a01 * b2 - b1 * a02)) / det;
+    x[2] = ((a00 * (a11 * b2 - b1 * a12) - a01 * (a01 * b2 - b1 * a02)) +
+            b0 * (a01 * a12 - a11 * a02)) / det;
+    return true;
+}
+
+// Placement of an edge's contraction and its cost: x* when it lies within
+// twice the edge length of the midpoint m, else the cheapest of pu, pv, m
+// (the first on a tie).
+__device__ double placement(const double Q[10], const double pu[3], const double pv[3],
+                            double x[3])
+{
+    const double m[3] = {0.5 * (pu[0] + pv[0]), 0.5 * (pu[1] + pv[1]), 0.5 * (pu[2] + pv[2])};
+    bool ok = minimiser(Q, x);
+    if (ok) {
+        const double dx[3] = {x[0] - m[0], x[1] - m[1], x[2] - m[2]};
+        const double e[3] = {pv[0] - pu[0], pv[1] - pu[1], pv[2] - pu[2]};
+        ok = dot3(dx, dx) <= 4.0 * dot3(e, e);
+    }
+    if (!ok) {
+        const double *cand[3] = {pu, pv, m};
+        int best = 0;
+        double bc = quadric_cost(Q, pu);
+        for (int i = 1; i < 3; ++i) {
+            const double c = quadric_cost(Q, cand[i]);
+            if (c < bc) {
+                bc = c;
+                best = i;
+            }
+        }
+        for (int i = 0; i < 3; ++i) x[i] = cand[best][i];
+    }
+    return quadric_cost(Q, x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_qem_init(const float *__restrict__ verts, int64_t nv,
+                                                     const int32_t *__restrict__ tris, int64_t nt,
+                                                     double *__restrict__ P,
+                                                     int32_t *__restrict__ F)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < nv)
+        for (int k = 0; k < 3; ++k) P[3 * i + k] = (double)verts[3 * i + k];
+    if (i < nt) {
+        const int32_t a = tris[3 * i], b = tris[3 * i + 1], c = tris[3 * i + 2];
+        // a face with a repeated corner is no triangle: dropped at once
+        const bool dead = a == b || b == c || a == c;
+        F[3 * i] = dead ? -1 : a;
+        F[3 * i + 1] = b;
+        F[3 * i + 2] = c;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_qem_fill_faces(const int32_t *__restrict__ F,
+                                                           int64_t nt, uint32_t *__restrict__ fcnt,
+                                                           int32_t *__restrict__ fl,
+                                                           uint32_t *__restrict__ flags)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nt || F[3 * t] < 0) return;
+    for (int k = 0; k < 3; ++k) {
+        const int32_t v = F[3 * t + k];
+        const uint32_t s = atomicAdd(&fcnt[v], 1u);
+        if (s < (uint32_t)kQemFaces) fl[(int64_t)v * kQemFaces + s] = (int32_t)t;
+        else atomicOr(&flags[0], 1u);
+    }
+}
+
+__device__ __forceinline__ bool face_has(const int32_t *__restrict__ F, int32_t t, int32_t w)
+{
+    return F[3 * (int64_t)t] == w || F[3 * (int64_t)t + 1] == w || F[3 * (int64_t)t + 2] == w;
+}
+
+// Per vertex: sort its faces, collect its distinct neighbours (ascending),
+// count those above it; at a round's start also sum its faces' plane
+// quadrics (ascending face order) and protect it when an edge at it is not
+// on exactly two faces.
+__global__ __launch_bounds__(kBlock) void k_qem_vertex(const double *__restrict__ P,
+                                                       const int32_t *__restrict__ F, int64_t nv,
+                                                       const uint32_t *__restrict__ fcnt,
+                                                       int32_t *__restrict__ fl,
+                                                       int32_t *__restrict__ fdeg,
+                                                       int32_t *__restrict__ nb,
+                                                       int32_t *__restrict__ ndeg,
+                                                       uint32_t *__restrict__ nlarge,
+                                                       double *__restrict__ Q,
+                                                       uint8_t *__restrict__ prot,
+                                                       int round_start,
+                                                       uint32_t *__restrict__ flags)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nv) return;
+    const int n = fcnt[v] < (uint32_t)kQemFaces ? (int)fcnt[v] : kQemFaces;
+    int32_t *f = fl + v * kQemFaces;
+    for (int k = 1; k < n; ++k) {
+        const int32_t x = f[k];
+        int j = k;
+        while (j > 0 && f[j - 1] > x) {
+            f[j] = f[j - 1];
+            --j;
+        }
+        f[j] = x;
+    }
+    fdeg[v] = n;
+    int32_t *b = nb + v * kQemNbrs;
+    int m = 0;
+    for (int k = 0; k < n; ++k)
+        for (int c = 0; c < 3; ++c) {
+            const int32_t w = F[3 * (int64_t)f[k] + c];
+            if (w == (int32_t)v) continue;
+            int j = m;
+            while (j > 0 && b[j - 1] > w) --j;
+            if (j > 0 && b[j - 1] == w) continue;
+            if (m == kQemNbrs) {
+                atomicOr(&flags[0], 2u);
+                continue;
+            }
+            for (int i = m; i > j; --i) b[i] = b[i - 1];
+            b[j] = w;
+            ++m;
+        }
+    ndeg[v] = m;
+    uint32_t above = 0;
+    for (int k = 0; k < m; ++k) above += b[k] > (int32_t)v ? 1u : 0u;
+    nlarge[v] = above;
+    if (!round_start) return;
+    double acc[10];
+    for (int i = 0; i < 10; ++i) acc[i] = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const int64_t t = f[k];
+        double pa[3], pb[3], pc[3], K[10];
+        load3(P, F[3 * t], pa);
+        load3(P, F[3 * t + 1], pb);
+        load3(P, F[3 * t + 2], pc);
+        plane_quadric(pa, pb, pc, K);
+        for (int i = 0; i < 10; ++i) acc[i] = acc[i] + K[i];
+    }
+    for (int i = 0; i < 10; ++i) Q[10 * v + i] = acc[i];
+    uint8_t p = 0;
+    for (int k = 0; k < m && !p; ++k) {
+        int cnt = 0;
+        for (int i = 0; i < n; ++i) cnt += face_has(F, f[i], b[k]) ? 1 : 0;
+        p = cnt != 2 ? 1 : 0;
+    }
+    prot[v] = p;
+}
+
+// Per vertex u: every edge (u, v > u) in ascending v, numbered from
+// eoff[u]; candidate evaluation (readings of the header comment).
+__global__ __launch_bounds__(kBlock) void k_qem_edges(
+    const double *__restrict__ P, const int32_t *__restrict__ F, int64_t nv,
+    const int32_t *__restrict__ fl, const int32_t *__restrict__ fdeg,
+    const int32_t *__restrict__ nb, const int32_t *__restrict__ ndeg,
+    const uint32_t *__restrict__ eoff, const double *__restrict__ Q,
+    const uint8_t *__restrict__ prot, uint64_t *__restrict__ key, double *__restrict__ X,
+    int32_t *__restrict__ eu, int32_t *__restrict__ ev, uint32_t *__restrict__ counters)
+{
+    const int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (u >= nv) return;
+    const int nu = ndeg[u], fu = fdeg[u];
+    const int32_t *bu = nb + u * kQemNbrs;
+    const int32_t *lu = fl + u * kQemFaces;
+    uint32_t e = eoff[u];
+    uint32_t found = 0;
+    for (int k = 0; k < nu; ++k) {
+        const int32_t v = bu[k];
+        if (v <= (int32_t)u) continue;
+        eu[e] = (int32_t)u;
+        ev[e] = v;
+        uint64_t kv = kNone;
+        int fc = 0;
+        for (int i = 0; i < fu; ++i) fc += face_has(F, lu[i], v) ? 1 : 0;
+        if (fc == 2 && !prot[u] && !prot[v]) {
+            // link condition: exactly two common neighbours
+            const int32_t *bv = nb + (int64_t)v * kQemNbrs;
+            const int nvv = ndeg[v];
+            int i = 0, j = 0, common = 0;
+            while (i < nu && j < nvv) {
+                if (bu[i] < bv[j]) ++i;
+                else if (bu[i] > bv[j]) ++j;
+                else { ++common; ++i; ++j; }
+            }
+            if (common == 2) {
+                double Qe[10], pu[3], pv[3], x[3];
+                for (int q = 0; q < 10; ++q) Qe[q] = Q[10 * u + q] + Q[10 * (int64_t)v + q];
+                load3(P, (int32_t)u, pu);
+                load3(P, v, pv);
+                const double c = placement(Qe, pu, pv, x);
+                // no face of u or v (other than the two on the edge) may flip
+                bool flip = false;
+                for (int side = 0; side < 2 && !flip; ++side) {
+                    const int64_t w = side == 0 ? u : (int64_t)v;
+                    const int32_t *lw = fl + w * kQemFaces;
+                    const int fw = fdeg[w];
+                    for (int i2 = 0; i2 < fw && !flip; ++i2) {
+                        const int64_t t = lw[i2];
+                        const int32_t c0 = F[3 * t], c1 = F[3 * t + 1], c2 = F[3 * t + 2];
+                        const bool hu = c0 == (int32_t)u || c1 == (int32_t)u || c2 == (int32_t)u;
+                        const bool hv = c0 == v || c1 == v || c2 == v;
+                        if (hu && hv) continue;
+                        double a[3], b[3], cc[3], n0[3], n1[3];
+                        load3(P, c0, a);
+                        load3(P, c1, b);
+                        load3(P, c2, cc);
+                        face_normal(a, b, cc, n0);
+                        if (!(dot3(n0, n0) > 0.0)) continue;
+                        double *moved = c0 == (int32_t)u || c0 == v ? a
+                                      : (c1 == (int32_t)u || c1 == v ? b : cc);
+                        moved[0] = x[0];
+                        moved[1] = x[1];
+                        moved[2] = x[2];
+                        face_normal(a, b, cc, n1);
+                        flip = !(dot3(n0, n1) > 0.0);
+                    }
+                }
+                if (!flip) {
+                    // cost clamped at 0 (a NaN stays) and rounded to
+                    // float32; -0 and +0 share one key
+                    const double cl = 0.0 > c ? 0.0 : c;
+                    float c32 = (float)cl;
+                    if (c32 == 0.0f) c32 = 0.0f;
+                    kv = ((uint64_t)__float_as_uint(c32) << 32) | e;
+                    X[3 * (int64_t)e] = x[0];
+                    X[3 * (int64_t)e + 1] = x[1];
+                    X[3 * (int64_t)e + 2] = x[2];
+                    ++found;
+                }
+            }
+        }
+        key[e] = kv;
+        ++e;
+    }
+    if (found) atomicAdd(&counters[0], found);
+}
+
+// Radix select of the rank-th smallest key (1-based), one byte per pass
+// from the top: sel = {prefix, mask, rank}.
+struct SelState {
+    unsigned long long prefix, mask;
+    unsigned long long rank;
+};
+
+__global__ __launch_bounds__(kBlock) void k_qem_hist(const uint64_t *__restrict__ key, int64_t n,
+                                                     const SelState *__restrict__ st, int shift,
+                                                     uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t prefix = st->prefix, mask = st->mask;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const uint64_t k = key[i];
+        if ((k & mask) == prefix) atomicAdd(&h[(k >> shift) & 0xffu], 1u);
+    }
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_qem_pick(SelState *st, uint32_t *hist, int shift)
+{
+    if (threadIdx.x != 0) return;
+    unsigned long long r = st->rank, cum = 0;
+    int d = 0;
+    for (; d < 255; ++d) {
+        if (cum + hist[d] >= r) break;
+        cum += hist[d];
+    }
+    st->rank = r - cum;
+    st->prefix |= (unsigned long long)d << shift;
+    st->mask |= 0xffull << shift;
+    for (int i = 0; i < 256; ++i) hist[i] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_qem_best(const uint64_t *__restrict__ key, int64_t n,
+                                                     const int32_t *__restrict__ eu,
+                                                     const int32_t *__restrict__ ev,
+                                                     const SelState *__restrict__ st, int all,
+                                                     unsigned long long *__restrict__ best)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= n) return;
+    const uint64_t k = key[e];
+    if (k == kNone || (!all && k > st->prefix)) return;
+    atomicMin(&best[eu[e]], k);
+    atomicMin(&best[ev[e]], k);
+}
+
+__global__ __launch_bounds__(kBlock) void k_qem_choose(
+    const uint64_t *__restrict__ key, int64_t n, const int32_t *__restrict__ eu,
+    const int32_t *__restrict__ ev, const SelState *__restrict__ st, int all,
+    const unsigned long long *__restrict__ best, const int32_t *__restrict__ nb,
+    const int32_t *__restrict__ ndeg, const double *__restrict__ X, double *__restrict__ P,
+    double *__restrict__ Q, int32_t *__restrict__ remap, uint32_t *__restrict__ counters)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= n) return;
+    const uint64_t k = key[e];
+    if (k == kNone || (!all && k > st->prefix)) return;
+    const int32_t u = eu[e], v = ev[e];
+    bool ok = best[u] >= k && best[v] >= k;
+    for (int side = 0; side < 2 && ok; ++side) {
+        const int64_t w = side == 0 ? u : v;
+        const int32_t *b = nb + w * kQemNbrs;
+        const int m = ndeg[w];
+        for (int i = 0; i < m && ok; ++i) ok = best[b[i]] >= k;
+    }
+    if (!ok) return;
+    // the contractions chosen in one step share no endpoint and no
+    // neighbour: each updates its own u in place
+    for (int i = 0; i < 10; ++i) Q[10 * (int64_t)u + i] = Q[10 * (int64_t)u + i] + Q[10 * (int64_t)v + i];
+    for (int i = 0; i < 3; ++i) P[3 * (int64_t)u + i] = X[3 * e + i];
+    remap[v] = u;
+    atomicAdd(&counters[1], 1u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_qem_faces(int32_t *__restrict__ F, int64_t nt,
+                                                      const int32_t *__restrict__ remap,
+                                                      uint32_t *__restrict__ counters)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    uint32_t live = 0;
+    if (t < nt && F[3 * t] >= 0) {
+        int32_t c[3];
+        for (int k = 0; k < 3; ++k) {
+            const int32_t x = F[3 * t + k];
+            const int32_t r = remap[x];
+            c[k] = r >= 0 ? r : x;
+        }
+        if (c[0] == c[1] || c[1] == c[2] || c[0] == c[2]) {
+            F[3 * t] = -1;
+        } else {
+            F[3 * t] = c[0];
+            F[3 * t + 1] = c[1];
+            F[3 * t + 2] = c[2];
+            live = 1;
+        }
+    }
+    // one atomic per wave
+    const unsigned long long b = __ballot(live);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&counters[2], (uint32_t)__popcll(b));
+}
+
+__global__ __launch_bounds__(kBlock) void k_qem_used(const int32_t *__restrict__ F, int64_t nt,
+                                                     uint32_t *__restrict__ used,
+                                                     uint32_t *__restrict__ keep)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nt) return;
+    const bool live = F[3 * t] >= 0;
+    keep[t] = live ? 1u : 0u;
+    if (live)
+        for (int k = 0; k < 3; ++k) used[F[3 * t + k]] = 1u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_qem_emit(const double *__restrict__ P, int64_t nv,
+                                                     const uint32_t *__restrict__ used,
+                                                     const uint32_t *__restrict__ newid,
+                                                     const int32_t *__restrict__ F, int64_t nt,
+                                                     const uint32_t *__restrict__ keep,
+                                                     const uint32_t *__restrict__ tpos,
+                                                     float *__restrict__ out_verts,
+                                                     int32_t *__restrict__ out_tris)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < nv && used[i])
+        for (int k = 0; k < 3; ++k) out_verts[3 * (int64_t)newid[i] + k] = (float)P[3 * i + k];
+    if (i < nt && keep[i])
+        for (int k = 0; k < 3; ++k)
+            out_tris[3 * (int64_t)tpos[i] + k] = (int32_t)newid[F[3 * i + k]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u64(unsigned long long *p, int64_t n,
+                                                     unsigned long long v)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_sel_init(SelState *st, unsigned long long rank, uint32_t *hist)
+{
+    if (threadIdx.x == 0) {
+        st->prefix = 0;
+        st->mask = 0;
+        st->rank = rank;
+    }
+    if (threadIdx.x < 256) hist[threadIdx.x] = 0;
+}
+
+}  // namespace
+
+size_t qem_sel_bytes() { return sizeof(SelState) + 256 * sizeof(uint32_t); }
+
+hipError_t qem_init_launch(const float *verts, int64_t nv, const int32_t *tris, int64_t nt,
+                           double *P, int32_t *F, hipStream_t s)
+{
+    const int64_t n = nv > nt ? nv : nt;
+    hipLaunchKernelGGL(k_qem_init, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, verts, nv, tris,
+                       nt, P, F);
+    return hipGetLastError();
+}
+
+hipError_t qem_incidence_launch(const QemBuffers &b, int64_t nv, int64_t nt, int round_start,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, b.fcnt, nv, 0u);
+    hipLaunchKernelGGL(k_qem_fill_faces, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, s, b.F, nt,
+                       b.fcnt, b.fl, b.counters + 3);
+    hipLaunchKernelGGL(k_qem_vertex, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, b.P, b.F, nv,
+                       b.fcnt, b.fl, b.fdeg, b.nb, b.ndeg, b.nlarge, b.Q, b.prot, round_start,
+                       b.counters + 3);
+    return hipGetLastError();
+}
+
+hipError_t qem_edges_launch(const QemBuffers &b, int64_t nv, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_qem_edges, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, b.P, b.F, nv,
+                       b.fl, b.fdeg, b.nb, b.ndeg, b.eoff, b.Q, b.prot, b.key, b.X, b.eu, b.ev,
+                       b.counters);
+    return hipGetLastError();
+}
+
+hipError_t qem_select_launch(const QemBuffers &b, int64_t n_edges, uint64_t rank, hipStream_t s)
+{
+    SelState *st = reinterpret_cast<SelState *>(b.sel);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(b.sel + sizeof(SelState));
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, st, (unsigned long long)rank, hist);
+    unsigned g = grid_for(n_edges, kBlock);
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(k_qem_hist, dim3(g), dim3(kBlock), 0, s, b.key, n_edges, st, shift,
+                           hist);
+        hipLaunchKernelGGL(k_qem_pick, dim3(1), dim3(64), 0, s, st, hist, shift);
+    }
+    return hipGetLastError();
+}
+
+hipError_t qem_contract_launch(const QemBuffers &b, int64_t nv, int64_t nt, int64_t n_edges,
+                               int all, hipStream_t s)
+{
+    const SelState *st = reinterpret_cast<const SelState *>(b.sel);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, b.best, nv,
+                       ~0ull);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s,
+                       reinterpret_cast<uint32_t *>(b.remap), nv, 0xffffffffu);
+    if (n_edges > 0) {
+        hipLaunchKernelGGL(k_qem_best, dim3(grid_for(n_edges, kBlock)), dim3(kBlock), 0, s, b.key,
+                           n_edges, b.eu, b.ev, st, all, b.best);
+        hipLaunchKernelGGL(k_qem_choose, dim3(grid_for(n_edges, kBlock)), dim3(kBlock), 0, s,
+                           b.key, n_edges, b.eu, b.ev, st, all, b.best, b.nb, b.ndeg, b.X, b.P,
+                           b.Q, b.remap, b.counters);
+    }
+    hipLaunchKernelGGL(k_qem_faces, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, s, b.F, nt,
+                       b.remap, b.counters);
+    return hipGetLastError();
+}
+
+hipError_t qem_used_launch(const int32_t *F, int64_t nt, uint32_t *used, uint32_t *keep,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_qem_used, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, s, F, nt, used,
+                       keep);
+    return hipGetLastError();
+}
+
+hipError_t qem_emit_launch(const double *P, int64_t nv, const uint32_t *used,
+                           const uint32_t *newid, const int32_t *F, int64_t nt,
+                           const uint32_t *keep, const uint32_t *tpos, float *out_verts,
+                           int32_t *out_tris, hipStream_t s)
+{
+    const int64_t n = nv > nt ? nv : nt;
+    hipLaunchKernelGGL(k_qem_emit, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, P, nv, used,
+                       newid, F, nt, keep, tpos, out_verts, out_tris);
+    return hipGetLastError();
+}

@@ -91,7 +91,7 @@ __device__ __forceinline__ float4 ldg4(const void *p, int64_t i)
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
-__device__ __forceinline__ NodeRec load_node(const NodeRec *nodes, int i)
+__device__ __forceinline__ NodeRec load_node_vec(const NodeRec *nodes, int i)
 {
     NodeRec n;
     n.q0 = ldg4(nodes, 4 * (int64_t)i);
@@ -101,6 +101,34 @@ __device__ __forceinline__ NodeRec load_node(const NodeRec *nodes, int i)
     n.q3 = make_int4(__float_as_int(w.x), __float_as_int(w.y), __float_as_int(w.z),
                      __float_as_int(w.w));
     return n;
+}
+
+// Node records never change while a traversal runs, so a record that every
+// active lane of the wave needs can be read once through the scalar data
+// cache (the constant address space with a wave-uniform address) instead of
+// by 64 lanes through the vector memory path, whose address and data units
+// are the traversal's busiest resource.
+typedef __attribute__((address_space(4))) const gvec4 gvec4_c;
+
+__device__ __forceinline__ NodeRec load_node(const NodeRec *nodes, int i)
+{
+    const int i0 = __builtin_amdgcn_readfirstlane(i);
+    const uint64_t p = (uint64_t)(uintptr_t)nodes;
+    const uint32_t plo = __builtin_amdgcn_readfirstlane((uint32_t)p);
+    const uint32_t phi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+    const uint64_t p0 = ((uint64_t)phi << 32) | plo;
+    if (__ballot(i != i0 || p != p0) == 0ull) {
+        const gvec4_c *q = (const gvec4_c *)(uintptr_t)p0 + 4 * (int64_t)i0;
+        const gvec4 a = q[0], b = q[1], c = q[2], d = q[3];
+        NodeRec n;
+        n.q0 = make_float4(a.x, a.y, a.z, a.w);
+        n.q1 = make_float4(b.x, b.y, b.z, b.w);
+        n.q2 = make_float4(c.x, c.y, c.z, c.w);
+        n.q3 = make_int4(__float_as_int(d.x), __float_as_int(d.y), __float_as_int(d.z),
+                         __float_as_int(d.w));
+        return n;
+    }
+    return load_node_vec(nodes, i);
 }
 
 __device__ __forceinline__ TriRec load_tri(const TriRec *tris, int i)
@@ -268,17 +296,22 @@ template <int SS, int STK, int BLK>
 struct LaneStack {
     int *ln;     // LDS: entry k of this lane at ln[k * BLK] (BLK = workgroup size)
     float *lt;
-    int sn[STK - SS];    // entries SS.. in scratch (only touched when deep)
-    float st[STK - SS];
+    // entries SS.. in scratch, node and distance packed in one 8-byte word so
+    // a push or pop is one memory instruction
+    uint64_t sw[STK - SS];
     __device__ __forceinline__ void put(int k, int n, float t)
     {
         if (SS > 0 && k < SS) { ln[k * BLK] = n; lt[k * BLK] = t; }
-        else { sn[k - SS] = n; st[k - SS] = t; }
+        else sw[k - SS] = (uint64_t)(uint32_t)n | ((uint64_t)__float_as_uint(t) << 32);
     }
     __device__ __forceinline__ void get(int k, int &n, float &t) const
     {
         if (SS > 0 && k < SS) { n = ln[k * BLK]; t = lt[k * BLK]; }
-        else { n = sn[k - SS]; t = st[k - SS]; }
+        else {
+            const uint64_t w = sw[k - SS];
+            n = (int)(uint32_t)w;
+            t = __uint_as_float((uint32_t)(w >> 32));
+        }
     }
 };
 
