@@ -49,9 +49,20 @@ Readings (also listed in the design notes):
   Q6  A candidate is dropped when moving u and v to x* flips a face: for
       every face that has u or v but not both, with old normal n and new
       normal n', n.n > 0 requires n.n' > 0.
-  Q7  One step: candidates are ordered by (float32 cost, u, v).  With F
-      faces left and target T, only the ceil((F - T) / 2) first ones are
-      eligible (an interior contraction removes two faces).  An eligible edge
+  Q7  One step: candidates are ordered by (float32 cost, pi(e)), where e is
+      the edge's rank in the lexicographic order of all (u, v), u < v, edges
+      of the live faces and pi is a fixed bijection of 32-bit integers (the
+      "lowbias32" integer hash of C. Wellons' hash prospector: xorshift 16,
+      multiply 0x7feb352d, xorshift 15, multiply 0x846ca68b, xorshift 16, all
+      mod 2^32).  The hash, not the plain index order, breaks ties: flat
+      regions give many exactly equal costs, and index order (spatially
+      coherent on generated meshes) would leave one local minimum per flat
+      region and step, so a step would contract about one edge; hashed
+      priorities make the locally cheapest edges an independent set of a
+      constant fraction of the candidates, as parallel decimation needs.
+      Keys are unique (pi is a bijection).  With F faces left and target T,
+      only the ceil((F - T) / 2) first ones are eligible (an interior
+      contraction removes two faces).  An eligible edge
       is contracted when no eligible edge at any vertex of its two closed
       1-rings comes before it; such edges have no two endpoints in common or
       adjacent, so their contractions touch disjoint faces and commute.  Contraction: u takes x* and Q_u + Q_v; v is removed; faces
@@ -149,6 +160,21 @@ def placement(Q, pu, pv):
     return tuple(x), float(np.float32(max(c, 0.0)))
 
 
+MASK32 = 0xFFFFFFFF
+
+
+def perm32(e: int) -> int:
+    """pi(e) of reading Q7: lowbias32 (xorshift-multiply), a bijection of
+    32-bit integers."""
+    x = e & MASK32
+    x ^= x >> 16
+    x = (x * 0x7FEB352D) & MASK32
+    x ^= x >> 15
+    x = (x * 0x846CA68B) & MASK32
+    x ^= x >> 16
+    return x
+
+
 def round_targets(f0: int, ratio: float, rounds: int):
     """T_k = ceil(F0 * ratio^(k / R)), k = 1..R (reading Q1)."""
     r = float(np.float32(ratio))
@@ -210,10 +236,11 @@ def _flips(m: _Mesh, vf, u, v, x):
 
 
 def candidates(m: _Mesh, Q, protected):
-    """{(u, v): (key, x*)} with key = (float32 cost, u, v) (readings Q4-Q6)."""
+    """{(u, v): (key, x*)} with key = (float32 cost, pi(edge rank)) (readings
+    Q4-Q7)."""
     vf, nb, ec = m.incidence()
     out = {}
-    for (u, v), cnt in sorted(ec.items()):
+    for e, ((u, v), cnt) in enumerate(sorted(ec.items())):
         if cnt != 2 or u in protected or v in protected:
             continue
         if len(nb[u] & nb[v]) != 2:
@@ -222,7 +249,7 @@ def candidates(m: _Mesh, Q, protected):
         x, cost = placement(Qe, m.p[u], m.p[v])
         if _flips(m, vf, u, v, x):
             continue
-        out[(u, v)] = ((cost, u, v), x, Qe)
+        out[(u, v)] = ((cost, perm32(e)), x, Qe)
     return out, vf, nb
 
 
@@ -234,7 +261,7 @@ def select(cands, nb, need: int):
         for w in (u, v):
             if w not in best or key < best[w]:
                 best[w] = key
-    none = (math.inf, math.inf, math.inf)
+    none = (math.inf, math.inf)
     chosen = []
     for (u, v), (key, x, Qe) in order:
         ring = {u, v} | nb[u] | nb[v]

@@ -252,3 +252,38 @@ def test_planted_missing_link_condition_breaks_closure(monkeypatch):
     v, t = synth.uv_sphere((0, 0, 0), 1.0, 8, 4)
     ov, ot = qem.decimate_qem(v, t, 0.0, 3)
     assert len(ot) == 0 or closed_manifold_euler(ov, ot) != 2
+
+
+def _inv_xorshift(x, s):
+    y = x
+    for _ in range(32 // s + 1):
+        y = x ^ (y >> s)
+    return y & qem.MASK32
+
+
+def test_tie_hash_is_a_bijection():
+    # undo each step (xorshifts by iteration, odd multipliers by their
+    # inverses mod 2^32): every key is distinct, so ties cannot occur
+    i1 = pow(0x846CA68B, -1, 1 << 32)
+    i2 = pow(0x7FEB352D, -1, 1 << 32)
+
+    def inv(x):
+        x = _inv_xorshift(x, 16)
+        x = (x * i1) & qem.MASK32
+        x = _inv_xorshift(x, 15)
+        x = (x * i2) & qem.MASK32
+        return _inv_xorshift(x, 16)
+    rng = np.random.default_rng(4)
+    for e in list(range(2000)) + [int(x) for x in rng.integers(0, 1 << 32, 2000)]:
+        assert inv(qem.perm32(e)) == e
+    assert len({qem.perm32(e) for e in range(1 << 16)}) == 1 << 16
+
+
+def test_hashed_ties_contract_many_edges_per_step():
+    # a flat marching-cubes wall region: costs tie at zero, and the hashed
+    # order lets each step contract a good fraction of the eligible edges
+    v, t = synth.grid_patch(16, 1.0, 0.25)
+    trace = []
+    qem.decimate_qem(v, t, 0.1, 3, trace=trace)
+    assert trace[0][2] >= 15, trace[:3]
+    assert len(trace) < 60
