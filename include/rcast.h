@@ -632,6 +632,44 @@ rc_status rc_decimate(rc_ctx *ctx, const float *verts_xyz, int64_t n_verts, cons
                       int64_t n_tris, float ratio, float *out_verts, int32_t *out_tris,
                       int64_t *n_verts_out, int64_t *n_tris_out, float *cell_out, void *stream);
 
+/* Quadric-error decimation by rounds of parallel edge contraction
+ * (Sec. IV-B "Mesh optimization": quadric-error decimation to a face ratio;
+ * Sec. V "Implementation": ratio 0.1, three rounds, boundary protected).
+ * Faces with a repeated corner are dropped first; F0 faces remain.  Round
+ * k = 1..rounds runs until at most ceil(F0 * ratio^(k / rounds)) faces
+ * remain or no edge can contract; at its start every vertex's quadric is
+ * the sum of its faces' plane quadrics (Garland and Heckbert 1997; squared
+ * distance to the plane, faces weighted equally) and the vertices on an
+ * edge that is not on exactly two faces are protected (never moved, their
+ * edges never contracted).  A step contracts, at once, every edge that
+ * (a) lies on exactly two faces, (b) has two unprotected ends, (c) has
+ * exactly two common neighbours (link condition), (d) flips no face when
+ * both ends move to its point x* (the minimiser of Q_u + Q_v when well
+ * conditioned and within twice the edge length of the midpoint, else the
+ * cheapest of the ends and the midpoint), (e) is among the
+ * ceil((F - target) / 2) smallest keys (float32 cost, pi(e)) -- e the
+ * edge's rank among all edges (u < v) in lexicographic order, pi the
+ * "lowbias32" bijection of 32-bit integers, so equal costs (flat regions)
+ * are ordered pseudo-randomly and many edges contract per step -- and (f) has
+ * the smallest key among those at every vertex of its two closed
+ * one-rings; the contracted vertex takes x* and Q_u + Q_v.  FP64 inside,
+ * positions rounded to float32 at the end; the result is deterministic.
+ * Output: the vertices a remaining face uses, in ascending input order,
+ * renumbered densely, and the remaining faces in ascending input order.
+ * verts_xyz (float32 [n_verts][3]) and tri_idx (int32 [n_tris][3]) are
+ * DEVICE arrays; out_verts / out_tris are DEVICE arrays of at least
+ * n_verts / n_tris entries (never larger than the input; must not alias
+ * it); *n_steps_out (may be NULL) receives the number of contraction
+ * steps.  Synchronous.  Scratch of about 900 bytes per vertex and 120 per
+ * triangle is kept by the context.  Errors: RC_E_INVAL (sizes, null
+ * arrays, an index out of range or a non-finite vertex, ratio outside
+ * (0, 1], rounds outside 1..64, a vertex with more than 64 incident faces
+ * or 64 neighbours at some step), RC_E_NOMEM, RC_E_DEVICE. */
+rc_status rc_decimate_qem(rc_ctx *ctx, const float *verts_xyz, int64_t n_verts,
+                          const int32_t *tri_idx, int64_t n_tris, float ratio, int32_t rounds,
+                          float *out_verts, int32_t *out_tris, int64_t *n_verts_out,
+                          int64_t *n_tris_out, int32_t *n_steps_out, void *stream);
+
 /* Removal of tiny components (Sec. IV-B "Mesh optimization": decimation
  * also removes tiny components).  Two triangles are connected when they
  * share a vertex; components with fewer than min_faces triangles are

@@ -21,7 +21,7 @@ OUT_DIR = os.path.join(PKG, "_lib")
 OBJ_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "librcast.so")
 SOURCES = ["api.hip", "build.hip", "trace.hip", "serve.hip", "gauss.hip", "vox.hip", "tsdf.hip", "nn.hip",
-           "meshopt.hip", "calib.hip"]
+           "meshopt.hip", "calib.hip", "qem.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -24,7 +24,9 @@
 //      when A (the 3x3 block of Q_u + Q_v) is well conditioned and x* lies
 //      near the edge, else the cheapest of the ends and the midpoint; an
 //      edge whose contraction would flip a face is dropped; key = (float32
-//      cost, edge number);
+//      cost, pi(edge number)) with pi a fixed bijection of 32-bit integers,
+//      so exactly equal costs (flat regions) are ordered pseudo-randomly
+//      and the locally cheapest edges are many, not one per flat region;
 //   3. the ceil((F - T) / 2) smallest keys are eligible (a radix select of
 //      the threshold key; an interior contraction removes two faces);
 //   4. an eligible edge contracts when no eligible edge at any vertex of
@@ -48,6 +50,18 @@ constexpr int kBlock = 256;
 constexpr uint64_t kNone = ~0ull;
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+// pi: "lowbias32" of C. Wellons' hash prospector (xorshift-multiply rounds,
+// each invertible mod 2^32, so pi is a bijection and keys stay unique)
+__device__ __forceinline__ uint32_t perm32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
 
 __device__ __forceinline__ void cross3(const double a[3], const double b[3], double r[3])
 {
@@ -341,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_qem_edges(
                     const double cl = 0.0 > c ? 0.0 : c;
                     float c32 = (float)cl;
                     if (c32 == 0.0f) c32 = 0.0f;
-                    kv = ((uint64_t)__float_as_uint(c32) << 32) | e;
+                    kv = ((uint64_t)__float_as_uint(c32) << 32) | perm32(e);
                     X[3 * (int64_t)e] = x[0];
                     X[3 * (int64_t)e + 1] = x[1];
                     X[3 * (int64_t)e + 2] = x[2];

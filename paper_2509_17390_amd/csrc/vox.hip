@@ -891,3 +891,123 @@ rc_status rc_decimate(rc_ctx *c, const float *verts, int64_t nv, const int32_t *
     if (cell_out) *cell_out = (float)cs;
     return RC_OK;
 }
+
+rc_status rc_decimate_qem(rc_ctx *c, const float *verts, int64_t nv, const int32_t *tris,
+                          int64_t nt, float ratio, int32_t rounds, float *out_verts,
+                          int32_t *out_tris, int64_t *n_verts_out, int64_t *n_tris_out,
+                          int32_t *n_steps_out, void *stream)
+{
+    if (!c || !n_verts_out || !n_tris_out) return fail(RC_E_INVAL, "null argument");
+    if (nv < 1 || nt < 1) return fail(RC_E_INVAL, "the mesh needs vertices and triangles");
+    if (nv > 0x7ffffffeLL || nt > 0x3fffffffLL) return fail(RC_E_INVAL, "mesh too large");
+    if (!verts || !tris || !out_verts || !out_tris) return fail(RC_E_INVAL, "null mesh array");
+    if (!(ratio > 0.0f) || !(ratio <= 1.0f)) return fail(RC_E_INVAL, "ratio must be in (0, 1]");
+    if (rounds < 1 || rounds > 64) return fail(RC_E_INVAL, "rounds must be 1..64");
+    if (c->mock) return fail(RC_E_STATE, "a mock context does not decimate meshes");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(c->mesh_mu);
+    Scratch ws(c);
+    QemBuffers b;
+    uint32_t *used, *newid, *keep, *tpos, *sums;
+    int32_t *flags;
+    const int64_t ne_cap = 3 * nt;
+    const size_t nss = (size_t)mc_scan_sums_len(nv > nt ? nv : nt);
+    ws.take(&b.P, sizeof(double) * 3 * (size_t)nv);
+    ws.take(&b.F, sizeof(int32_t) * 3 * (size_t)nt);
+    ws.take(&b.Q, sizeof(double) * 10 * (size_t)nv);
+    ws.take(&b.prot, (size_t)nv);
+    ws.take(&b.fcnt, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&b.fl, sizeof(int32_t) * kQemFaces * (size_t)nv);
+    ws.take(&b.fdeg, sizeof(int32_t) * (size_t)nv);
+    ws.take(&b.nb, sizeof(int32_t) * kQemNbrs * (size_t)nv);
+    ws.take(&b.ndeg, sizeof(int32_t) * (size_t)nv);
+    ws.take(&b.nlarge, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&b.eoff, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&b.key, sizeof(uint64_t) * (size_t)ne_cap);
+    ws.take(&b.X, sizeof(double) * 3 * (size_t)ne_cap);
+    ws.take(&b.eu, sizeof(int32_t) * (size_t)ne_cap);
+    ws.take(&b.ev, sizeof(int32_t) * (size_t)ne_cap);
+    ws.take(&b.best, sizeof(unsigned long long) * (size_t)nv);
+    ws.take(&b.remap, sizeof(int32_t) * (size_t)nv);
+    ws.take(&b.counters, sizeof(uint32_t) * 4);
+    ws.take(&b.sel, qem_sel_bytes());
+    ws.take(&used, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&newid, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&keep, sizeof(uint32_t) * (size_t)nt);
+    ws.take(&tpos, sizeof(uint32_t) * (size_t)nt);
+    ws.take(&sums, sizeof(uint32_t) * nss);
+    ws.take(&flags, sizeof(int32_t));
+    rc_status st = ws.commit();
+    if (st != RC_OK) return st;
+    int32_t hf = 0;
+    HIP_TRY(hipMemsetAsync(flags, 0, sizeof(int32_t), s));
+    HIP_TRY(validate_mesh_launch(verts, nv, tris, nt, flags, s));
+    HIP_TRY(hipMemcpyAsync(&hf, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hf) return fail(RC_E_INVAL, "invalid mesh:%s%s", (hf & 1) ? " index out of range" : "",
+                        (hf & 2) ? " non-finite vertex" : "");
+    HIP_TRY(qem_init_launch(verts, nv, tris, nt, b.P, b.F, s));
+    uint32_t hc[4] = {0, 0, 0, 0};
+    // live faces after dropping repeated-corner faces: one renaming pass
+    // with an empty contraction map counts them
+    HIP_TRY(hipMemsetAsync(b.counters, 0, sizeof(uint32_t) * 4, s));
+    HIP_TRY(qem_contract_launch(b, nv, nt, 0, 1, s));
+    HIP_TRY(hipMemcpyAsync(hc, b.counters, sizeof hc, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int64_t f0 = hc[2];
+    int64_t nf = f0;
+    int32_t steps = 0;
+    const double r = (double)ratio;
+    for (int k = 1; k <= rounds; ++k) {
+        const int64_t target = (int64_t)ceil((double)f0 * pow(r, (double)k / (double)rounds));
+        for (int first = 1;; first = 0) {
+            if (nf <= target) break;
+            // incidence of the live faces (a round's start also sums the
+            // quadrics and protects boundary vertices), edge numbering
+            HIP_TRY(hipMemsetAsync(b.counters, 0, sizeof(uint32_t) * 4, s));
+            HIP_TRY(qem_incidence_launch(b, nv, nt, first, s));
+            HIP_TRY(scan_u32_launch(b.nlarge, b.eoff, nv, sums, s));
+            uint32_t n_edges = 0;
+            HIP_TRY(hipMemcpyAsync(&n_edges, sums + mc_scan_sums_len(nv) - 1, sizeof(uint32_t),
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(hc, b.counters, sizeof hc, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (hc[3] & 1) return fail(RC_E_INVAL, "a vertex has more than %d incident triangles",
+                                       kQemFaces);
+            if (hc[3] & 2) return fail(RC_E_INVAL, "a vertex has more than %d neighbours",
+                                       kQemNbrs);
+            // every edge lies on a live face: at most three per face
+            if ((int64_t)n_edges > ne_cap) return fail(RC_E_DEVICE, "edge count overflow");
+            HIP_TRY(qem_edges_launch(b, nv, s));
+            HIP_TRY(hipMemcpyAsync(hc, b.counters, sizeof hc, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            const uint64_t cands = hc[0];
+            if (cands == 0) break;
+            const uint64_t need = (uint64_t)((nf - target + 1) / 2);
+            const int all = need >= cands ? 1 : 0;
+            if (!all) HIP_TRY(qem_select_launch(b, n_edges, need, s));
+            HIP_TRY(qem_contract_launch(b, nv, nt, n_edges, all, s));
+            HIP_TRY(hipMemcpyAsync(hc, b.counters, sizeof hc, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            ++steps;
+            if (hc[1] == 0) return fail(RC_E_DEVICE, "decimation step contracted nothing");
+            nf = hc[2];
+        }
+    }
+    HIP_TRY(hipMemsetAsync(used, 0, sizeof(uint32_t) * (size_t)nv, s));
+    HIP_TRY(qem_used_launch(b.F, nt, used, keep, s));
+    uint32_t tot[2] = {0, 0};
+    HIP_TRY(scan_u32_launch(keep, tpos, nt, sums, s));
+    HIP_TRY(hipMemcpyAsync(&tot[1], sums + mc_scan_sums_len(nt) - 1, sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(scan_u32_launch(used, newid, nv, sums, s));
+    HIP_TRY(hipMemcpyAsync(&tot[0], sums + mc_scan_sums_len(nv) - 1, sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(qem_emit_launch(b.P, nv, used, newid, b.F, nt, keep, tpos, out_verts, out_tris, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_verts_out = tot[0];
+    *n_tris_out = tot[1];
+    if (n_steps_out) *n_steps_out = steps;
+    return RC_OK;
+}

@@ -53,7 +53,8 @@ EXPORTED = [
     "rc_serve_copy", "rc_serve_get_stats", "rc_gauss_upload", "rc_gauss_build",
     "rc_gauss_release", "rc_voxelize", "rc_voxelize_counts", "rc_gauss_debug_copy",
     "rc_tsdf", "rc_marching_cubes", "rc_marching_cubes_table", "rc_nearest",
-    "rc_chamfer_fscore", "rc_taubin_smooth", "rc_decimate", "rc_remove_small_components",
+    "rc_chamfer_fscore", "rc_taubin_smooth", "rc_decimate", "rc_decimate_qem",
+    "rc_remove_small_components",
     "rc_calib_gather", "rc_calib_valu", "rc_tuning_cache_load", "rc_tuning_cache_save",
 ]
 
@@ -208,6 +209,8 @@ def load() -> ctypes.CDLL:
         "rc_taubin_smooth": ([P, P, I64, P, I64, ctypes.c_float, ctypes.c_float, I32, P], S),
         "rc_decimate": ([P, P, I64, P, I64, ctypes.c_float, P, P, ctypes.POINTER(I64),
                          ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_float), P], S),
+        "rc_decimate_qem": ([P, P, I64, P, I64, ctypes.c_float, I32, P, P, ctypes.POINTER(I64),
+                             ctypes.POINTER(I64), ctypes.POINTER(I32), P], S),
         "rc_remove_small_components": ([P, P, I64, P, I64, I64, P, P, ctypes.POINTER(I64),
                                         ctypes.POINTER(I64), P], S),
         "rc_chamfer_fscore": ([P, P, I64, P, I64, ctypes.c_float, ctypes.POINTER(rc_fidelity),
@@ -492,6 +495,19 @@ class Context:
                                   _ptr(ov), _ptr(ot_), ctypes.byref(n_v), ctypes.byref(n_t),
                                   ctypes.byref(cell), _stream_ptr(stream)))
         return ov[:n_v.value], ot_[:n_t.value], cell.value
+
+    def decimate_qem(self, verts, tris, ratio: float = 0.1, rounds: int = 3, stream=None):
+        """Quadric-error decimation by rounds of parallel edge contraction of a
+        device mesh: (verts, tris, contraction steps)."""
+        import torch
+        nv, nt = int(verts.shape[0]), int(tris.shape[0])
+        ov = torch.empty((max(nv, 1), 3), dtype=torch.float32, device=verts.device)
+        ot_ = torch.empty((max(nt, 1), 3), dtype=torch.int32, device=verts.device)
+        n_v, n_t, n_s = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(load().rc_decimate_qem(self._h, _ptr(verts), nv, _ptr(tris), nt, float(ratio),
+                                      int(rounds), _ptr(ov), _ptr(ot_), ctypes.byref(n_v),
+                                      ctypes.byref(n_t), ctypes.byref(n_s), _stream_ptr(stream)))
+        return ov[:n_v.value], ot_[:n_t.value], n_s.value
 
     def remove_small_components(self, verts, tris, min_faces: int, stream=None):
         """Drop the components of fewer than min_faces triangles of a device
