@@ -10,7 +10,7 @@ re-thresholding", "Narrow-band TSDF", "Isosurface extraction") on the
 surface mask V of Sec. IV-A, written out directly with numpy and scipy:
 
   V'      = G * V                       (smoothing eq.)
-  V~      = [V' >= tau]                 (fixed re-threshold eq.)
+  V~      = [V' >= tau]  or  [V' >= Quantile_q(V')]   (re-threshold eqs.)
   O       = the 6-connected component of free voxels (V~ = 0) joined to a
             padded frame around the grid;  s = +1 on O, -1 elsewhere
   S_0     = { x : some 6-neighbour y has V~(y) != V~(x) }   (boundary set)
@@ -28,7 +28,20 @@ notes):
       Gaussian of integer weights), separable on the three axes, zero outside
       the grid; V' = sum / 2^(6n).  All sums are exact integers, and V~ is
       decided exactly: sum >= ceil(tau 2^(6n)).  n <= 10.
-  T2  Fixed threshold only (the quantile variant is not built).
+  T2  Quantile re-threshold: Quantile_q(V') over all N voxels of the grid,
+      interpolated linearly between consecutive order statistics (numpy's
+      default): with V' sorted ascending, x_0 <= ... <= x_(N-1), position
+      p = q (N - 1) (FP64, q the float32 input), k = floor(p), Quantile =
+      x_k + (p - k)(x_(k+1) - x_k).  No value of V' lies strictly between
+      x_k and x_(k+1), so V' >= Quantile exactly when V' >= x_k (p = k) or
+      V' >= x_(k+1) (p > k); decided on the integer sums like the fixed form.
+  T2b mc_step (Isosurface extraction): marching cubes of phi sampled at
+      every mc_step-th lattice point of each axis, (i, j, k) mc_step for
+      i <= (nx - 1) / mc_step and so on, as a grid of spacing fl32(s h) and
+      origin fl32(o - (s - 1) h / 2) per axis (FP64 from the float32 o and
+      h, rounded once; s = mc_step), whose voxel centres o' + (i + 1/2) s h
+      fall on the fine centres o + (i s + 1/2) h (mc_step = 1: the plain
+      form).
   T3  The padded frame is free, so a free voxel on the grid boundary is
       outside; in S_0 a neighbour outside the grid counts as free (0).
   T4  Shells are counted up to P = ceil(r / h); a voxel not reached by then
@@ -213,6 +226,22 @@ def denoise(surf, sigma_m: float, h: float, tau: float):
     return (acc >= thr).astype(np.uint8), acc
 
 
+def quantile_threshold(acc, q: float) -> int:
+    """The integer sum thr with [V' >= Quantile_q(V')] = [sum >= thr]
+    (reading T2)."""
+    flat = np.sort(np.asarray(acc, dtype=np.int64).ravel())
+    n = flat.size
+    pos = float(np.float32(q)) * float(n - 1)
+    k = int(math.floor(pos))
+    return int(flat[k]) if pos == k else int(flat[k + 1])
+
+
+def denoise_quantile(surf, sigma_m: float, h: float, q: float):
+    """V~ = [G * V >= Quantile_q(G * V)] (readings T1, T2).  Returns (V~, sum)."""
+    _, acc = denoise(surf, sigma_m, h, 0.0)
+    return (acc >= quantile_threshold(acc, q)).astype(np.uint8), acc
+
+
 def outside(vt):
     """O: free voxels 6-connected to the padded frame (reading T3)."""
     free = np.pad(np.asarray(vt) == 0, 1, mode="constant", constant_values=True)
@@ -248,9 +277,13 @@ def shells(s0, P: int):
     return p
 
 
-def tsdf(surf, h: float, sigma_m: float, tau: float, r: float):
-    """(phi float32, V~, sign, p) for the surface mask `surf` (readings T1-T4)."""
-    vt, _ = denoise(surf, sigma_m, h, tau)
+def tsdf(surf, h: float, sigma_m: float, tau: float, r: float, quantile=None):
+    """(phi float32, V~, sign, p) for the surface mask `surf` (readings T1-T4);
+    with quantile = q the re-threshold is the quantile form (tau unused)."""
+    if quantile is None:
+        vt, _ = denoise(surf, sigma_m, h, tau)
+    else:
+        vt, _ = denoise_quantile(surf, sigma_m, h, quantile)
     sgn = np.where(outside(vt), 1, -1).astype(np.int8)
     hf, rf = np.float32(h), np.float32(r)
     P = int(math.ceil(float(rf) / float(hf)))
@@ -258,6 +291,17 @@ def tsdf(surf, h: float, sigma_m: float, tau: float, r: float):
     delta = np.where(p >= 0, p.astype(np.float32) * hf, rf).astype(np.float32)
     phi = np.clip(sgn.astype(np.float32) * delta, -rf, rf).astype(np.float32)
     return phi, vt, sgn, p
+
+
+def marching_cubes_step(phi, origin, h: float, step: int, iso: float = 0.0,
+                        normals: bool = False):
+    """Marching cubes with mc_step (reading T2b): the plain extraction on
+    phi[::step, ::step, ::step] with spacing fl32(step h)."""
+    h32 = float(np.float32(h))
+    hs = float(np.float32(h32 * step))
+    o2 = tuple(float(np.float32(float(np.float32(o)) - (step - 1) * h32 / 2.0)) for o in origin)
+    sub = np.ascontiguousarray(np.asarray(phi)[::step, ::step, ::step])
+    return marching_cubes(sub, o2, hs, iso, normals=normals)
 
 
 def lattice_gradient(phi):

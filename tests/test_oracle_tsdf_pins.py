@@ -364,3 +364,105 @@ def test_planted_mistakes_break_the_fp64_bounds():
     near = np.array([G[(z * ny + y) * nx + xx] for (xx, y, z), _ in edges])
     near /= np.maximum(np.linalg.norm(near, axis=1, keepdims=True), 1e-300)
     assert np.any(np.abs(near - nrm).max(axis=1) > ntol)
+
+
+# ---- quantile re-threshold (reading T2) and mc_step (reading T2b) ---------
+
+def _random_mask(seed, shape=(9, 11, 13), p=0.3):
+    return (np.random.default_rng(seed).random(shape) < p).astype(np.uint8)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_quantile_threshold_matches_numpy_quantile(seed):
+    # n = 1 step: sums <= 64, exact in float64, so numpy's linearly
+    # interpolated quantile decides the same voxels
+    from oracle import tsdf as ot
+    surf = _random_mask(seed)
+    _, acc = ot.denoise(surf, 0.02, 0.04, 0.0)
+    rng = np.random.default_rng(seed + 10)
+    for q in [0.0, 1.0, 0.5, 0.25, 0.9] + list(rng.random(20)):
+        q32 = float(np.float32(q))
+        vt, _ = ot.denoise_quantile(surf, 0.02, 0.04, q32)
+        want = acc >= np.quantile(acc.astype(np.float64), q32)
+        assert np.array_equal(vt.astype(bool), want), q32
+
+
+def test_quantile_extremes():
+    from oracle import tsdf as ot
+    surf = _random_mask(3)
+    vt0, acc = ot.denoise_quantile(surf, 0.02, 0.04, 0.0)
+    assert vt0.all()
+    vt1, _ = ot.denoise_quantile(surf, 0.02, 0.04, 1.0)
+    assert np.array_equal(vt1.astype(bool), acc == acc.max())
+
+
+def test_planted_quantile_lower_statistic_is_caught(monkeypatch):
+    # taking x_k even when the position lies between order statistics
+    from oracle import tsdf as ot
+    surf = _random_mask(4)
+    _, acc = ot.denoise(surf, 0.02, 0.04, 0.0)
+
+    def wrong(a, q):
+        flat = np.sort(np.asarray(a, dtype=np.int64).ravel())
+        return int(flat[int(math.floor(float(np.float32(q)) * (flat.size - 1)))])
+    monkeypatch.setattr(ot, "quantile_threshold", wrong)
+    # positions half-way between two distinct order statistics
+    flat = np.sort(acc.ravel())
+    ks = np.nonzero(flat[1:] != flat[:-1])[0][:10]
+    assert len(ks) > 3
+    bad = 0
+    for k in ks:
+        q = float(np.float32((k + 0.5) / (flat.size - 1)))
+        vt, _ = ot.denoise_quantile(surf, 0.02, 0.04, q)
+        bad += not np.array_equal(vt.astype(bool),
+                                  acc >= np.quantile(acc.astype(np.float64), q))
+    assert bad == len(ks)
+
+
+def _sampled(f, origin, h, dims, stride=1):
+    """f at the centres of voxels (i, j, k) * stride of a grid (origin, h)."""
+    nx, ny, nz = dims
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return f(origin[0] + (x * stride + 0.5) * h, origin[1] + (y * stride + 0.5) * h,
+             origin[2] + (z * stride + 0.5) * h).astype(np.float32)
+
+
+@pytest.mark.parametrize("step", [1, 2, 3])
+def test_mc_step_equals_the_field_sampled_on_the_coarse_lattice(step):
+    # an independent route: the analytic field evaluated directly at the
+    # coarse lattice points (not sliced out of the fine one)
+    from oracle import tsdf as ot
+    h = float(np.float32(0.05))
+    o = (0.1, -0.2, 0.05)
+    f = lambda x, y, z: np.sqrt((x - 0.6) ** 2 + (y - 0.4) ** 2 + (z - 0.5) ** 2) - 0.33
+    fine = _sampled(f, o, h, (25, 22, 23))
+    v, t = ot.marching_cubes_step(fine, o, h, step)
+    hs = float(np.float32(np.float32(h) * np.float32(step)))
+    dims = tuple((n - 1) // step + 1 for n in (25, 22, 23))
+    # f evaluated at the fine centres (i step, ...) directly, and the plain
+    # extraction of those samples on a grid whose centres are those points
+    direct = _sampled(f, o, h, dims, stride=step)
+    assert np.array_equal(direct, np.ascontiguousarray(fine[::step, ::step, ::step]))
+    o2 = tuple(c - (step - 1) * h / 2.0 for c in o)
+    v2, t2 = ot.marching_cubes(direct, o2, hs, 0.0)
+    assert np.array_equal(t, t2)
+    assert np.allclose(v, v2, atol=2e-7 * (1 + np.abs(v).max()))
+    # vertices of the coarse mesh lie on the sphere within its cell size
+    r = np.linalg.norm(v.astype(np.float64) - (0.6, 0.4, 0.5), axis=1)
+    assert np.all(np.abs(r - 0.33) < 0.25 * hs), float(np.abs(r - 0.33).max())
+    if step == 1:
+        v1, t1 = ot.marching_cubes(fine, o, h, 0.0)
+        assert np.array_equal(t, t1) and np.array_equal(v, v1)
+
+
+@pytest.mark.parametrize("step", [2, 3, 4])
+def test_mc_step_plane_vertices_on_the_plane(step):
+    from oracle import tsdf as ot
+    h = 0.03125
+    f = lambda x, y, z: x - 0.4 + 0 * y + 0 * z
+    fine = _sampled(f, (0.0, 0.0, 0.0), h, (33, 9, 10))
+    v, t = ot.marching_cubes_step(fine, (0.0, 0.0, 0.0), h, step)
+    assert len(t) > 0
+    assert np.all(np.abs(v[:, 0] - 0.4) < 1e-6)
+    # the coarse lattice spans the fine centres 0.5 h .. (8 // step * step + 0.5) h in y
+    assert np.isclose(v[:, 1].min(), 0.5 * h) and np.isclose(v[:, 1].max(), (8 // step * step + 0.5) * h)
