@@ -1277,6 +1277,29 @@ TSDF_PASS_BYTES = {
 }
 
 
+def mesh_properties(v0, t0, v1, t1):
+    """What quadric-error decimation must keep, checked at full size on the
+    CPU: boundary edges (a face's edge on no other face) and non-manifold
+    edges stay as they were, no new non-manifold edge appears, every face
+    is a triangle of distinct used vertices, and the Euler characteristic
+    of the whole mesh is unchanged (the link condition keeps the topology)."""
+    def edges(t):
+        e = np.sort(np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]]), axis=1)
+        _, cnt = np.unique(e[:, 0].astype(np.int64) << 32 | e[:, 1], return_counts=True)
+        return cnt
+
+    def euler(t, nv):
+        return len(np.unique(t)) - len(edges(t)) + len(t)
+    c0, c1 = edges(t0), edges(t1)
+    return {"faces_in": int(len(t0)), "faces_out": int(len(t1)),
+            "boundary_edges_in": int((c0 == 1).sum()), "boundary_edges_out": int((c1 == 1).sum()),
+            "nonmanifold_edges_in": int((c0 > 2).sum()), "nonmanifold_edges_out": int((c1 > 2).sum()),
+            "euler_in": int(euler(t0, len(v0))), "euler_out": int(euler(t1, len(v1))),
+            "degenerate_faces_out": int(((t1[:, 0] == t1[:, 1]) | (t1[:, 1] == t1[:, 2]) |
+                                         (t1[:, 0] == t1[:, 2])).sum()),
+            "all_vertices_used": bool(len(np.unique(t1)) == len(v1))}
+
+
 def run_mesh(args):
     """Occupancy to mesh (FGGS-LiDAR Sec. IV-B) on the surface mask of the
     Gaussian conversion workload (1M Gaussians, 510 x 410 x 160 voxels at
@@ -1328,13 +1351,20 @@ def run_mesh(args):
         ms.append(b_ms)
     tsdf_ms, mc_ms = float(np.median(ts)), float(np.median(ms))
     ms_step = tsdf_ms + mc_ms
-    # mesh optimisation (paper defaults): decimation to 10 % of the faces,
-    # removal of components under MIN_COMPONENT_FACES triangles, then Taubin
-    # smoothing (0.5, -0.53), 10 iterations
-    dec_ms, cc_ms, smo_ms = [], [], []
+    # mesh optimisation (paper defaults): quadric-error decimation to 10 % of
+    # the faces in three rounds, removal of components under
+    # MIN_COMPONENT_FACES triangles, then Taubin smoothing (0.5, -0.53), 10
+    # iterations; the one-pass vertex clustering is timed beside it
+    dec_ms, cc_ms, smo_ms, clu_ms = [], [], [], []
+    for k in range(3):
+        t0 = time.perf_counter()
+        _, clu_tris, cell = ctx.decimate(verts, tris, 0.1, stream=stream)
+        if k:
+            clu_ms.append((time.perf_counter() - t0) * 1e3)
+    n_clu_tris = int(clu_tris.shape[0])
     for k in range(max(3, args.steps // 2)):
         t0 = time.perf_counter()
-        dverts, dtris, cell = ctx.decimate(verts, tris, 0.1, stream=stream)
+        dverts, dtris, qem_steps = ctx.decimate_qem(verts, tris, 0.1, 3, stream=stream)
         t1 = time.perf_counter()
         cverts, ctris = ctx.remove_small_components(dverts, dtris, MIN_COMPONENT_FACES,
                                                     stream=stream)
@@ -1348,6 +1378,8 @@ def run_mesh(args):
     decimate_ms, smooth_ms = float(np.median(dec_ms)), float(np.median(smo_ms))
     components_ms = float(np.median(cc_ms))
     n_dec_tris = int(dtris.shape[0])
+    qem_props = mesh_properties(verts.cpu().numpy(), tris.cpu().numpy(),
+                                dverts.cpu().numpy(), dtris.cpu().numpy())
     dverts, dtris = cverts, ctris
     # the meshes as LiDAR scenes: BVH build and one 8-environment frame each
     sdf = synth.indoor_sdf(1)
@@ -1431,13 +1463,18 @@ def run_mesh(args):
         t0 = time.perf_counter()
         ocd = om.chamfer_fscore(pts_sim, pts_gt, 0.05)
         dt_m = time.perf_counter() - t0
-        # decimation + smoothing of the sub-grid's mesh, both sides
+        # decimation + smoothing of a smaller sub-grid's mesh, both sides
+        from oracle import qem as oqem
+        small = surf[40:72, 100:148, 150:198]           # 32 x 48 x 48 voxels
+        phi_s, _, _, _ = ot.tsdf(small, float(grid.h), sigma, tau, band)
+        vo2, to2 = ot.marching_cubes(phi_s, (0, 0, 0), float(grid.h), 0.0)
         t0 = time.perf_counter()
-        dvo, dto, _ = omesh.decimate(vo, to, 0.1)
+        dvo, dto = oqem.decimate_qem(vo2, to2, 0.1, 3)
         dvo, dto, _ = omesh.remove_small_components(dvo, dto, MIN_COMPONENT_FACES)
         svo = omesh.taubin(dvo, dto, 0.5, -0.53, 10)
         dt_d = time.perf_counter() - t0
-        dvg, dtg, _ = ctx.decimate(vg, tg, 0.1)
+        dvg, dtg, _ = ctx.decimate_qem(torch.from_numpy(vo2).to(dev),
+                                       torch.from_numpy(to2).to(dev), 0.1, 3)
         dvg, dtg = ctx.remove_small_components(dvg, dtg, MIN_COMPONENT_FACES)
         ctx.taubin(dvg, dtg, 0.5, -0.53, 10)
         torch.cuda.synchronize()
@@ -1449,6 +1486,7 @@ def run_mesh(args):
                "gpu_agreement": {"bit_identical": same, "triangles": int(len(to)),
                                  "decimate_components_smooth_bit_identical": same_opt,
                                  "decimate_smooth_oracle_s": round(dt_d, 2),
+                                 "decimate_input_triangles": int(len(to2)),
                                  "decimated_triangles": int(len(dto))},
                "fidelity_oracle": {"s": round(dt_m, 3), "chamfer": ocd[0], "fscore": ocd[5],
                                    "chamfer_rel_diff": abs(ocd[0] - fid["chamfer"]) / ocd[0],
@@ -1469,7 +1507,11 @@ def run_mesh(args):
                           "hit_fraction": round(hit_frac, 4)},
         "mesh_optimisation": {
             "decimate_ms": round(decimate_ms, 3), "components_ms": round(components_ms, 3),
-            "smooth_ms": round(smooth_ms, 3), "ratio": 0.1, "cell_m": round(float(cell), 5),
+            "smooth_ms": round(smooth_ms, 3), "ratio": 0.1, "rounds": 3,
+            "decimation": "quadric error, parallel edge contraction (rc_decimate_qem)",
+            "contraction_steps": int(qem_steps), "decimated_properties": qem_props,
+            "clustering": {"ms": round(float(np.median(clu_ms)), 3),
+                           "cell_m": round(float(cell), 5), "triangles": n_clu_tris},
             "decimated_triangles": n_dec_tris, "min_component_faces": MIN_COMPONENT_FACES,
             "vertices": int(dverts.shape[0]), "triangles": int(dtris.shape[0]),
             "lidar_ms": round(cast_f_ms, 3),

@@ -510,7 +510,8 @@ rc_status rc_gauss_debug_copy(rc_ctx *ctx, int32_t set, int32_t what, void *host
  *   V'    = G * V, G the binomial kernel of n = max(1, round(2 sigma^2))
  *           steps (sigma in voxels, halves rounded up): integer weights
  *           C(2n, n + k), k = -n..n, separable, zero outside the grid;
- *           V~ = [V' >= tau], decided exactly on the integer sums
+ *           V~ = [V' >= tau] (or the quantile form, see rc_tsdf_opts),
+ *           decided exactly on the integer sums
  *   O     = free voxels (V~ = 0) 6-connected to a free frame around the grid;
  *           s = +1 on O, -1 elsewhere
  *   S_0   = voxels with a 6-neighbour of the other V~ value (frame = 0)
@@ -525,16 +526,25 @@ rc_status rc_gauss_debug_copy(rc_ctx *ctx, int32_t set, int32_t what, void *host
  * ---------------------------------------------------------------------- */
 typedef struct {
     float sigma_smooth;   /* smoothing scale, metres, > 0 (n <= 10)          */
-    float tau;            /* re-threshold (finite)                           */
+    float tau;            /* fixed re-threshold (finite; mode 0)             */
     float band;           /* r, metres, > 0; band / spacing <= 250           */
-    int32_t reserved[5];
+    int32_t threshold_mode; /* 0: V~ = [V' >= tau]; 1: V~ = [V' >= Quantile_q(V')]
+                               (Sec. IV-B quantile re-threshold eq.): over all
+                               N voxels, the quantile interpolated linearly
+                               between the order statistics x_k and x_(k+1),
+                               k = floor(q (N - 1)); decided exactly on the
+                               integer sums (sum >= x_k when q (N - 1) is an
+                               integer, else sum >= x_(k+1))               */
+    float quantile;       /* q in [0, 1] (mode 1)                            */
+    int32_t reserved[3];
 } rc_tsdf_opts;
 
 /* TSDF of the DEVICE uint8 surface mask `surf` [nz][ny][nx] into the DEVICE
  * float32 `out_phi` (same layout); `out_vtilde` (DEVICE uint8, or NULL)
  * receives V~.  Runs on `stream` and returns when phi is complete (the
  * outside labelling repeats until it settles, reading a flag each round).
- * Scratch device memory of about 14 bytes per voxel is kept by the context
+ * Scratch device memory of about 14 bytes per voxel (22 with the quantile
+ * re-threshold, which keeps the smoothing's integer sums) is kept by the context
  * (grown on demand, reused by later calls, freed by rc_destroy).
  * Errors: RC_E_INVAL (grid, options), RC_E_NOMEM, RC_E_DEVICE. */
 rc_status rc_tsdf(rc_ctx *ctx, const rc_grid *grid, const uint8_t *surf,
@@ -559,6 +569,21 @@ rc_status rc_marching_cubes(rc_ctx *ctx, const rc_grid *grid, const float *phi, 
                             float *out_verts, int32_t *out_tris, float *out_normals,
                             int64_t cap_verts, int64_t cap_tris, int64_t *n_verts,
                             int64_t *n_tris, void *stream);
+
+/* Marching cubes with the step-size parameter mc_step of Sec. IV-B
+ * ("Isosurface extraction"): the same extraction on the lattice of every
+ * step-th voxel centre along each axis -- points (i, j, k) * step with
+ * i <= (nx - 1) / step and so on, as a grid of spacing fl32(step * h) and
+ * origin fl32(o - (step - 1) h / 2) per axis (FP64, rounded once), whose
+ * voxel centres fall on the fine centres -- so vertex and triangle
+ * numbering follow that coarser lattice.
+ * step = 1 is rc_marching_cubes.  Other arguments, sizes and errors as
+ * rc_marching_cubes, plus RC_E_INVAL for step < 1; a temporary device
+ * buffer of 4 bytes per coarse point is allocated and freed by the call. */
+rc_status rc_marching_cubes_step(rc_ctx *ctx, const rc_grid *grid, const float *phi, float iso,
+                                 int32_t step, float *out_verts, int32_t *out_tris,
+                                 float *out_normals, int64_t cap_verts, int64_t cap_tris,
+                                 int64_t *n_verts, int64_t *n_tris, void *stream);
 
 /* The marching-cubes case table, HOST arrays: count[256] triangles per case
  * (corner k inside sets bit k; corner k = (k & 1, k >> 1 & 1, k >> 2 & 1))
@@ -606,7 +631,7 @@ rc_status rc_chamfer_fscore(rc_ctx *ctx, const float *p_xyz, int64_t n_p, const 
  * umbrella operator (mean of its distinct edge neighbours minus itself);
  * vertices on an edge of a single triangle and vertices without neighbours
  * stay in place.  Float32, neighbours summed in ascending index order.
- * Synchronous.  At most 32 triangles per vertex.
+ * Synchronous.  At most 64 triangles per vertex.
  * Errors: RC_E_INVAL (sizes, indices, non-finite vertex or parameters,
  * valence), RC_E_NOMEM, RC_E_DEVICE. */
 rc_status rc_taubin_smooth(rc_ctx *ctx, float *verts_xyz, int64_t n_verts, const int32_t *tri_idx,
@@ -626,7 +651,7 @@ rc_status rc_taubin_smooth(rc_ctx *ctx, float *verts_xyz, int64_t n_verts, const
  * verts_xyz, tri_idx: DEVICE input mesh; out_verts (DEVICE float32
  * [n_verts][3]) and out_tris (DEVICE int32 [n_tris][3]) receive the result
  * (never larger than the input); sizes in *n_verts_out / *n_tris_out and
- * the cell size in *cell_out (may be NULL).  Synchronous.  At most 32
+ * the cell size in *cell_out (may be NULL).  Synchronous.  At most 64
  * triangles per vertex.  Errors: RC_E_INVAL, RC_E_NOMEM, RC_E_DEVICE. */
 rc_status rc_decimate(rc_ctx *ctx, const float *verts_xyz, int64_t n_verts, const int32_t *tri_idx,
                       int64_t n_tris, float ratio, float *out_verts, int32_t *out_tris,

@@ -39,6 +39,17 @@ size_t tsdf_smooth_a_bytes(const TsdfGrid &g);
 size_t tsdf_smooth_b_bytes(const TsdfGrid &g);
 hipError_t tsdf_smooth_launch(const uint8_t *surf, void *abuf, void *bbuf, uint8_t *vt,
                               const TsdfGrid &g, const Binomial &w, uint64_t thr, hipStream_t s);
+// The integer sums of the same smoothing ([nz][ny][nx] uint64, u32 x and
+// u64 xy passes in abuf / bbuf), and V~ = [sums >= *thr] with thr on the
+// device (the quantile re-threshold).
+hipError_t tsdf_smooth_sums_launch(const uint8_t *surf, void *abuf, void *bbuf, uint64_t *sums,
+                                   const TsdfGrid &g, const Binomial &w, hipStream_t s);
+hipError_t tsdf_threshold_launch(const uint64_t *sums, const uint64_t *thr, uint8_t *vt,
+                                 int64_t n, hipStream_t s);
+// phi at every step-th lattice point of each axis ([mz][my][mx], m = (n - 1)
+// / step + 1 per axis) into out.
+hipError_t mc_stride_gather_launch(const float *phi, const TsdfGrid &g, int step, int mx, int my,
+                                   int mz, float *out, hipStream_t s);
 // Outside labelling, bit-packed along x (tsdf_words_per_row words per
 // row, [nz][ny][W] uint64 each for F and O; seg holds 5 *
 // tsdf_seg_words(g) words): pack the free mask, then sweep rounds
@@ -92,7 +103,7 @@ hipError_t metric_sums_launch(const double *d, int64_t n, double tau, void *scra
 // ---------------------------------------------------------------------------
 // Mesh optimisation (meshopt.hip).
 
-constexpr int kNbrCap = 64;   // neighbour slots per vertex (two per incident triangle)
+constexpr int kNbrCap = 128;  // neighbour slots per vertex (two per incident triangle)
 // Distinct sorted neighbours (slots [nv][kNbrCap], deg [nv]) and the fixed
 // flag (boundary or isolated) of every vertex; *flags |= 1 when a vertex
 // has more than kNbrCap neighbour slots.  cnt: [nv] scratch.
@@ -230,3 +241,12 @@ hipError_t qem_emit_launch(const double *P, int64_t nv, const uint32_t *used,
                            const uint32_t *newid, const int32_t *F, int64_t nt,
                            const uint32_t *keep, const uint32_t *tpos, float *out_verts,
                            int32_t *out_tris, hipStream_t s);
+
+// Radix select over 64-bit keys (qem.hip): the rank-th smallest (1-based,
+// rank <= n) of keys[0..n) into the state (radix_select_state_bytes()),
+// readable on the device through radix_select_value(state) once the
+// launches have run.
+size_t radix_select_state_bytes();
+hipError_t radix_select_u64_launch(const uint64_t *keys, int64_t n, uint64_t rank, char *state,
+                                   hipStream_t s);
+const uint64_t *radix_select_value(const char *state);

@@ -43,6 +43,7 @@
 
 #include <float.h>
 #include <math.h>
+#include <stddef.h>
 
 namespace {
 
@@ -370,11 +371,13 @@ __global__ __launch_bounds__(kBlock) void k_qem_edges(
 }
 
 // Radix select of the rank-th smallest key (1-based), one byte per pass
-// from the top: sel = {prefix, mask, rank}.
+// from the top: sel = {prefix, mask, rank}; after the eight passes prefix
+// holds the selected key.
 struct SelState {
     unsigned long long prefix, mask;
     unsigned long long rank;
 };
+static_assert(offsetof(SelState, prefix) == 0, "the selected key is read at offset 0");
 
 __global__ __launch_bounds__(kBlock) void k_qem_hist(const uint64_t *__restrict__ key, int64_t n,
                                                      const SelState *__restrict__ st, int shift,
@@ -532,6 +535,7 @@ __global__ void k_sel_init(SelState *st, unsigned long long rank, uint32_t *hist
 }  // namespace
 
 size_t qem_sel_bytes() { return sizeof(SelState) + 256 * sizeof(uint32_t); }
+size_t radix_select_state_bytes() { return qem_sel_bytes(); }
 
 hipError_t qem_init_launch(const float *verts, int64_t nv, const int32_t *tris, int64_t nt,
                            double *P, int32_t *F, hipStream_t s)
@@ -562,20 +566,30 @@ hipError_t qem_edges_launch(const QemBuffers &b, int64_t nv, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t qem_select_launch(const QemBuffers &b, int64_t n_edges, uint64_t rank, hipStream_t s)
+hipError_t radix_select_u64_launch(const uint64_t *keys, int64_t n, uint64_t rank, char *state,
+                                   hipStream_t s)
 {
-    SelState *st = reinterpret_cast<SelState *>(b.sel);
-    uint32_t *hist = reinterpret_cast<uint32_t *>(b.sel + sizeof(SelState));
+    SelState *st = reinterpret_cast<SelState *>(state);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(state + sizeof(SelState));
     hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, st, (unsigned long long)rank, hist);
-    unsigned g = grid_for(n_edges, kBlock);
+    unsigned g = grid_for(n, kBlock);
     if (g > 2048) g = 2048;
     if (g < 1) g = 1;
     for (int shift = 56; shift >= 0; shift -= 8) {
-        hipLaunchKernelGGL(k_qem_hist, dim3(g), dim3(kBlock), 0, s, b.key, n_edges, st, shift,
-                           hist);
+        hipLaunchKernelGGL(k_qem_hist, dim3(g), dim3(kBlock), 0, s, keys, n, st, shift, hist);
         hipLaunchKernelGGL(k_qem_pick, dim3(1), dim3(64), 0, s, st, hist, shift);
     }
     return hipGetLastError();
+}
+
+const uint64_t *radix_select_value(const char *state)
+{
+    return reinterpret_cast<const uint64_t *>(state);   // SelState::prefix
+}
+
+hipError_t qem_select_launch(const QemBuffers &b, int64_t n_edges, uint64_t rank, hipStream_t s)
+{
+    return radix_select_u64_launch(b.key, n_edges, rank, b.sel, s);
 }
 
 hipError_t qem_contract_launch(const QemBuffers &b, int64_t nv, int64_t nt, int64_t n_edges,

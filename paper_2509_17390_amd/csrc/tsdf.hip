@@ -105,6 +105,33 @@ __global__ __launch_bounds__(kBlock) void k_smooth_z(const uint64_t *__restrict_
     vt[i] = s >= thr ? 1 : 0;
 }
 
+// The same z pass keeping the integer sums (for the quantile re-threshold),
+// and the threshold of such sums against a value held on the device.
+__global__ __launch_bounds__(kBlock) void k_smooth_z_sum(const uint64_t *__restrict__ b,
+                                                         uint64_t *__restrict__ out, TsdfGrid g,
+                                                         Binomial w)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    const int64_t sxy = (int64_t)g.nx * g.ny;
+    int x, y, z;
+    coords(i, g, x, y, z);
+    uint64_t s = 0;
+    for (int k = -w.n; k <= w.n; ++k) {
+        const int zz = z + k;
+        if (zz >= 0 && zz < g.nz) s += (uint64_t)w.w[k + w.n] * b[i + (int64_t)k * sxy];
+    }
+    out[i] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_threshold_sums(const uint64_t *__restrict__ sums,
+                                                           const uint64_t *__restrict__ thr,
+                                                           uint8_t *__restrict__ vt, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) vt[i] = sums[i] >= *thr ? 1 : 0;
+}
+
 // Fast path for kernels of at most kFastSmooth steps (sums fit u8 after x,
 // u16 after y, u32 after z): four voxels per thread, word loads, narrow
 // intermediates.  One byte- or word-wide load per lane and tap capped the
@@ -1163,6 +1190,46 @@ hipError_t tsdf_smooth_launch(const uint8_t *surf, void *abuf, void *bbuf, uint8
     hipLaunchKernelGGL(k_smooth_x, dim3(grid), dim3(kBlock), 0, s, surf, a, g, w);
     hipLaunchKernelGGL(k_smooth_y, dim3(grid), dim3(kBlock), 0, s, a, b, g, w);
     hipLaunchKernelGGL(k_smooth_z, dim3(grid), dim3(kBlock), 0, s, b, vt, g, w, thr);
+    return hipGetLastError();
+}
+
+hipError_t tsdf_smooth_sums_launch(const uint8_t *surf, void *abuf, void *bbuf, uint64_t *sums,
+                                   const TsdfGrid &g, const Binomial &w, hipStream_t s)
+{
+    uint32_t *a = static_cast<uint32_t *>(abuf);
+    uint64_t *b = static_cast<uint64_t *>(bbuf);
+    const unsigned grid = grid_for(g.n, kBlock);
+    hipLaunchKernelGGL(k_smooth_x, dim3(grid), dim3(kBlock), 0, s, surf, a, g, w);
+    hipLaunchKernelGGL(k_smooth_y, dim3(grid), dim3(kBlock), 0, s, a, b, g, w);
+    hipLaunchKernelGGL(k_smooth_z_sum, dim3(grid), dim3(kBlock), 0, s, b, sums, g, w);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_stride_gather(const float *__restrict__ phi, TsdfGrid g,
+                                                          int step, int mx, int my, int64_t m,
+                                                          float *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    const int64_t x = i % mx, yz = i / mx;
+    const int64_t y = yz % my, z = yz / my;
+    out[i] = phi[((z * step) * g.ny + y * step) * (int64_t)g.nx + x * step];
+}
+
+hipError_t mc_stride_gather_launch(const float *phi, const TsdfGrid &g, int step, int mx, int my,
+                                   int mz, float *out, hipStream_t s)
+{
+    const int64_t m = (int64_t)mx * my * mz;
+    hipLaunchKernelGGL(k_stride_gather, dim3(grid_for(m, kBlock)), dim3(kBlock), 0, s, phi, g,
+                       step, mx, my, m, out);
+    return hipGetLastError();
+}
+
+hipError_t tsdf_threshold_launch(const uint64_t *sums, const uint64_t *thr, uint8_t *vt,
+                                 int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_threshold_sums, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, sums,
+                       thr, vt, n);
     return hipGetLastError();
 }
 

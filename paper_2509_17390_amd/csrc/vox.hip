@@ -409,7 +409,11 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
     if (st != RC_OK) return st;
     const float sigma = opts->sigma_smooth, tau = opts->tau, r = opts->band;
     if (!(sigma > 0.0f) || !isfinite(sigma)) return fail(RC_E_INVAL, "sigma_smooth must be finite and > 0");
-    if (!isfinite(tau)) return fail(RC_E_INVAL, "tau must be finite");
+    const int quant = opts->threshold_mode;
+    if (quant != 0 && quant != 1) return fail(RC_E_INVAL, "threshold_mode must be 0 or 1");
+    if (quant == 0 && !isfinite(tau)) return fail(RC_E_INVAL, "tau must be finite");
+    if (quant == 1 && !(opts->quantile >= 0.0f && opts->quantile <= 1.0f))
+        return fail(RC_E_INVAL, "quantile must be in [0, 1]");
     if (!(r > 0.0f) || !isfinite(r)) return fail(RC_E_INVAL, "band must be finite and > 0");
     const double sv = (double)sigma / (double)g.hf;
     const double nn = floor(2.0 * sv * sv + 0.5);
@@ -422,8 +426,19 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
         for (int q = 1; q <= k; ++q) b = b * (uint64_t)(2 * w.n - q + 1) / (uint64_t)q;
         w.w[k] = (uint32_t)b;
     }
-    const double thr_d = ceil((double)tau * ldexp(1.0, 6 * w.n));
+    const double thr_d = quant ? 0.0 : ceil((double)tau * ldexp(1.0, 6 * w.n));
     const uint64_t thr = thr_d <= 0.0 ? 0ull : (uint64_t)thr_d;
+    // quantile re-threshold: V' >= Quantile_q(V') with the quantile
+    // interpolated linearly between the order statistics x_k and x_(k+1),
+    // k = floor(q (N - 1)); no sum lies strictly between them, so the test
+    // is sum >= x_k when q (N - 1) is an integer, else sum >= x_(k+1)
+    uint64_t q_rank = 0;
+    if (quant) {
+        const double pos = (double)opts->quantile * (double)(g.n - 1);
+        const double k = floor(pos);
+        q_rank = (uint64_t)k + (pos > k ? 2 : 1);
+        if (q_rank > (uint64_t)g.n) q_rank = (uint64_t)g.n;
+    }
     const double shells_d = ceil((double)r / (double)g.hf);
     if (shells_d > 250.0) return fail(RC_E_INVAL, "band / spacing above 250 shells");
     const int shells = (int)shells_d;
@@ -448,10 +463,22 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
     ws.take(&ow, sizeof(uint64_t) * nwords);
     ws.take(&seg, sizeof(uint64_t) * 5 * tsdf_seg_words(g));
     ws.take(&flag, sizeof(int32_t));
+    uint64_t *sums = nullptr;
+    char *sel = nullptr;
+    if (quant) {
+        ws.take(&sums, sizeof(uint64_t) * (size_t)g.n);
+        ws.take(&sel, radix_select_state_bytes());
+    }
     st = ws.commit();
     if (st != RC_OK) return st;
     uint8_t *p = pbuf + pad;
-    HIP_TRY(tsdf_smooth_launch(surf, a, b, vt, g, w, thr, s));
+    if (quant) {
+        HIP_TRY(tsdf_smooth_sums_launch(surf, a, b, sums, g, w, s));
+        HIP_TRY(radix_select_u64_launch(sums, g.n, q_rank, sel, s));
+        HIP_TRY(tsdf_threshold_launch(sums, radix_select_value(sel), vt, g.n, s));
+    } else {
+        HIP_TRY(tsdf_smooth_launch(surf, a, b, vt, g, w, thr, s));
+    }
     HIP_TRY(tsdf_pack_launch(vt, fw, ow, g, s));
     // rounds until one changes nothing (one flag read per round)
     for (int64_t it = 0;; ++it) {
@@ -526,6 +553,52 @@ rc_status rc_marching_cubes(rc_ctx *c, const rc_grid *grid, const float *phi, fl
                            out_tris, out_normals, s));
     HIP_TRY(hipStreamSynchronize(s));
     return RC_OK;
+}
+
+rc_status rc_marching_cubes_step(rc_ctx *c, const rc_grid *grid, const float *phi, float iso,
+                                 int32_t step, float *out_verts, int32_t *out_tris,
+                                 float *out_normals, int64_t cap_verts, int64_t cap_tris,
+                                 int64_t *n_verts, int64_t *n_tris, void *stream)
+{
+    if (step < 1) return fail(RC_E_INVAL, "mc_step must be >= 1");
+    if (step == 1)
+        return rc_marching_cubes(c, grid, phi, iso, out_verts, out_tris, out_normals, cap_verts,
+                                 cap_tris, n_verts, n_tris, stream);
+    if (!c || !phi || !n_verts || !n_tris) return fail(RC_E_INVAL, "null argument");
+    TsdfGrid g;
+    rc_status st = make_tsdf_grid(grid, g);
+    if (st != RC_OK) return st;
+    if (c->mock) return fail(RC_E_STATE, "a mock context does not extract meshes");
+    // the lattice of every step-th voxel centre: a grid of spacing
+    // fl32(step h) and origin fl32(o - (step - 1) h / 2), whose voxel
+    // centres fall on the fine centres (i step + 1/2) h
+    rc_grid sub = *grid;
+    sub.spacing = (float)((double)grid->spacing * (double)step);
+    for (int a = 0; a < 3; ++a) {
+        sub.dims[a] = (grid->dims[a] - 1) / step + 1;
+        sub.origin[a] =
+            (float)((double)grid->origin[a] - (double)(step - 1) * (double)grid->spacing / 2.0);
+    }
+    const int64_t m = (int64_t)sub.dims[0] * sub.dims[1] * sub.dims[2];
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float *fine = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        st = dev_alloc(c, (void **)&fine, sizeof(float) * (size_t)m);
+    }
+    if (st != RC_OK) return st;
+    hipError_t e = mc_stride_gather_launch(phi, g, step, sub.dims[0], sub.dims[1], sub.dims[2],
+                                           fine, s);
+    if (e != hipSuccess) st = fail(RC_E_DEVICE, "stride gather: %s", hipGetErrorString(e));
+    if (st == RC_OK)
+        st = rc_marching_cubes(c, &sub, fine, iso, out_verts, out_tris, out_normals, cap_verts,
+                               cap_tris, n_verts, n_tris, stream);
+    // rc_marching_cubes is synchronous, so the gathered field is no longer read
+    if (st != RC_OK) (void)hipStreamSynchronize(s);
+    std::lock_guard<std::mutex> lk(c->mu);
+    dev_free(c, fine, sizeof(float) * (size_t)m);
+    return st;
 }
 
 rc_status rc_marching_cubes_table(uint8_t *count, int8_t *tris)

@@ -52,7 +52,8 @@ EXPORTED = [
     "rc_serve_start", "rc_serve_stop", "rc_serve_submit", "rc_serve_poll", "rc_serve_release",
     "rc_serve_copy", "rc_serve_get_stats", "rc_gauss_upload", "rc_gauss_build",
     "rc_gauss_release", "rc_voxelize", "rc_voxelize_counts", "rc_gauss_debug_copy",
-    "rc_tsdf", "rc_marching_cubes", "rc_marching_cubes_table", "rc_nearest",
+    "rc_tsdf", "rc_marching_cubes", "rc_marching_cubes_step", "rc_marching_cubes_table",
+    "rc_nearest",
     "rc_chamfer_fscore", "rc_taubin_smooth", "rc_decimate", "rc_decimate_qem",
     "rc_remove_small_components",
     "rc_calib_gather", "rc_calib_valu", "rc_tuning_cache_load", "rc_tuning_cache_save",
@@ -137,7 +138,8 @@ class rc_grid(ctypes.Structure):
 
 class rc_tsdf_opts(ctypes.Structure):
     _fields_ = [("sigma_smooth", ctypes.c_float), ("tau", ctypes.c_float),
-                ("band", ctypes.c_float), ("reserved", ctypes.c_int32 * 5)]
+                ("band", ctypes.c_float), ("threshold_mode", ctypes.c_int32),
+                ("quantile", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
 
 
 class rc_fidelity(ctypes.Structure):
@@ -204,6 +206,8 @@ def load() -> ctypes.CDLL:
         "rc_tsdf": ([P, ctypes.POINTER(rc_grid), P, ctypes.POINTER(rc_tsdf_opts), P, P, P], S),
         "rc_marching_cubes": ([P, ctypes.POINTER(rc_grid), P, ctypes.c_float, P, P, P, I64, I64,
                                ctypes.POINTER(I64), ctypes.POINTER(I64), P], S),
+        "rc_marching_cubes_step": ([P, ctypes.POINTER(rc_grid), P, ctypes.c_float, I32, P, P, P,
+                                    I64, I64, ctypes.POINTER(I64), ctypes.POINTER(I64), P], S),
         "rc_marching_cubes_table": ([P, P], S),
         "rc_nearest": ([P, P, I64, P, I64, P, P, P], S),
         "rc_taubin_smooth": ([P, P, I64, P, I64, ctypes.c_float, ctypes.c_float, I32, P], S),
@@ -429,19 +433,23 @@ class Context:
         return a
 
     def tsdf(self, grid: rc_grid, surf, out_phi, sigma_smooth: float, tau: float, band: float,
-             out_vtilde=None, stream=None):
+             out_vtilde=None, stream=None, quantile=None):
         """Narrow-band TSDF of a device uint8 surface mask into device float32
-        out_phi (both [nz, ny, nx]); synchronous."""
-        o = rc_tsdf_opts(float(sigma_smooth), float(tau), float(band))
+        out_phi (both [nz, ny, nx]); synchronous.  With quantile = q the
+        re-threshold is V' >= Quantile_q(V') (tau unused)."""
+        o = rc_tsdf_opts(float(sigma_smooth), float(tau), float(band),
+                         0 if quantile is None else 1,
+                         0.0 if quantile is None else float(quantile))
         _check(load().rc_tsdf(self._h, ctypes.byref(grid), _ptr(surf), ctypes.byref(o),
                               _ptr(out_phi), 0 if out_vtilde is None else _ptr(out_vtilde),
                               _stream_ptr(stream)))
 
     def marching_cubes(self, grid: rc_grid, phi, iso: float = 0.0, stream=None,
-                       normals: bool = False):
+                       normals: bool = False, step: int = 1):
         """Mesh of a device float32 field: (verts [nv, 3] float32, tris [nt, 3]
         int32) as torch cuda tensors; with normals=True also the unit vertex
-        normals [nv, 3] float32 from the gradient of phi."""
+        normals [nv, 3] float32 from the gradient of phi; step = mc_step
+        (every step-th lattice point, rc_marching_cubes_step)."""
         import torch
         nv, nt = ctypes.c_int64(), ctypes.c_int64()
         lib = load()
@@ -452,9 +460,10 @@ class Context:
             verts = torch.empty((cv, 3), dtype=torch.float32, device=dev)
             tris = torch.empty((ct, 3), dtype=torch.int32, device=dev)
             nrm = torch.empty((cv, 3), dtype=torch.float32, device=dev) if normals else None
-            st = lib.rc_marching_cubes(self._h, ctypes.byref(grid), _ptr(phi), float(iso),
-                                       _ptr(verts), _ptr(tris), _ptr(nrm) if normals else None,
-                                       cv, ct, ctypes.byref(nv), ctypes.byref(nt), sp)
+            st = lib.rc_marching_cubes_step(self._h, ctypes.byref(grid), _ptr(phi), float(iso),
+                                            int(step), _ptr(verts), _ptr(tris),
+                                            _ptr(nrm) if normals else None, cv, ct,
+                                            ctypes.byref(nv), ctypes.byref(nt), sp)
             out = (verts[:nv.value], tris[:nt.value])
             return st, (out + (nrm[:nv.value],) if normals else out)
 
@@ -467,9 +476,9 @@ class Context:
             if st != RC_E_NOMEM:
                 _check(st)
         else:
-            _check(lib.rc_marching_cubes(self._h, ctypes.byref(grid), _ptr(phi), float(iso),
-                                         None, None, None, 0, 0, ctypes.byref(nv),
-                                         ctypes.byref(nt), sp))
+            _check(lib.rc_marching_cubes_step(self._h, ctypes.byref(grid), _ptr(phi),
+                                              float(iso), int(step), None, None, None, 0, 0,
+                                              ctypes.byref(nv), ctypes.byref(nt), sp))
         self._mc_cap = (max(1, int(nv.value * 1.1) + 16), max(1, int(nt.value * 1.1) + 16))
         st, out = fill(max(nv.value, 1), max(nt.value, 1))
         _check(st)

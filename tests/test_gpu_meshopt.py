@@ -89,8 +89,8 @@ def test_errors(ctx):
     with pytest.raises(rcast.RcastError) as e:
         ctx.taubin(v, bad)
     assert e.value.status == rcast.RC_E_INVAL
-    # valence above the limit: a fan of 40 triangles around vertex 0
-    k = 40
+    # valence above the limit: a fan of 70 triangles around vertex 0
+    k = 70
     ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
     vf = np.concatenate([[[0, 0, 0]], np.stack([np.cos(ang), np.sin(ang), 0 * ang], 1)]).astype(np.float32)
     tf = np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)], np.int32)
@@ -236,8 +236,8 @@ def test_components_edge_cases(ctx):
 
 def test_decimate_high_valence_vertices(ctx):
     """Vertices with more than 8 triangles take the boundary test's long
-    path: UV-sphere poles (24 triangles), the hub of an open fan (20), and
-    a closed fan of 40 exceeds the limit of 32."""
+    path: UV-sphere poles (24 triangles), the hub of an open fan (20) and
+    of a closed fan (40); a closed fan of 70 exceeds the limit of 64."""
     import torch
     v, t = synth.uv_sphere((0.1, -0.2, 0.3), 1.0, 24, 16)
     check_decimate(ctx, v, t, 0.5, tag="uv sphere")
@@ -247,10 +247,13 @@ def test_decimate_high_valence_vertices(ctx):
     vf = vf.astype(np.float32)
     tf = np.array([[0, 1 + i, 2 + i] for i in range(k)], np.int32)
     check_decimate(ctx, vf, tf, 0.5, tag="open fan")
-    k = 40
-    ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
-    vf = np.concatenate([[[0, 0, 0]], np.stack([np.cos(ang), np.sin(ang), 0 * ang], 1)]).astype(np.float32)
-    tf = np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)], np.int32)
+    def closed_fan(k):
+        ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
+        vf = np.concatenate([[[0, 0, 0]], np.stack([np.cos(ang), np.sin(ang), 0 * ang], 1)])
+        tf = np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)], np.int32)
+        return vf.astype(np.float32), tf
+    check_decimate(ctx, *closed_fan(40), 0.5, tag="closed fan")
+    vf, tf = closed_fan(70)
     with pytest.raises(rcast.RcastError) as e:
         ctx.decimate(cuda(vf), cuda(tf), 0.5)
     assert e.value.status == rcast.RC_E_INVAL

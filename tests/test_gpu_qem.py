@@ -104,3 +104,40 @@ def test_errors(ctx):
     with pytest.raises(RcastError) as e:
         ctx.decimate_qem(vd, cuda(bad), 0.1, 3)
     assert e.value.status == RC_E_INVAL
+
+
+def edge_counts(t):
+    e = np.sort(np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]]), axis=1)
+    _, cnt = np.unique(e[:, 0].astype(np.int64) << 32 | e[:, 1], return_counts=True)
+    return cnt
+
+
+@pytest.mark.parametrize("h", [0.1, 0.06])
+def test_large_marching_cubes_mesh_properties(ctx, h):
+    # 88k / 244k faces (the oracle's pure-Python steps would take hours):
+    # what the definition guarantees at any size -- the round targets are
+    # met to within one face, the mesh stays closed and manifold with the
+    # same Euler characteristic, faces are proper triangles of used
+    # vertices, and every vertex is finite
+    sdf = synth.indoor_sdf(2, n_prims=40)
+    v, t = synth.polygonise(sdf, h)
+    c0 = edge_counts(t)
+    assert np.all(c0 == 2)
+    log(f"qem large: {len(t)} faces")
+    gv, gt, steps = ctx.decimate_qem(cuda(v), cuda(t), 0.1, 3)
+    gv, gt = gv.cpu().numpy(), gt.cpu().numpy()
+    T = qem.round_targets(len(t), 0.1, 3)[-1]
+    assert T - 1 <= len(gt) <= T
+    c1 = edge_counts(gt)
+    assert np.all(c1 == 2)
+    eu0 = len(np.unique(t)) - len(c0) + len(t)
+    eu1 = len(np.unique(gt)) - len(c1) + len(gt)
+    assert eu0 == eu1
+    assert len(np.unique(gt)) == len(gv)
+    assert not np.any((gt[:, 0] == gt[:, 1]) | (gt[:, 1] == gt[:, 2]) | (gt[:, 0] == gt[:, 2]))
+    assert np.all(np.isfinite(gv))
+    # and the same call twice gives the same bits
+    gv2, gt2, steps2 = ctx.decimate_qem(cuda(v), cuda(t), 0.1, 3)
+    assert steps2 == steps and np.array_equal(gt2.cpu().numpy(), gt)
+    assert np.array_equal(gv2.cpu().numpy().view(np.uint32), gv.view(np.uint32))
+    log(f"qem large: {len(t)} -> {len(gt)} faces in {steps} steps")

@@ -227,3 +227,88 @@ def test_unaligned_output_buffers(ctx):
     np.testing.assert_array_equal(phi.cpu().numpy().view(np.uint32), phi_o.view(np.uint32))
     # the elements before the views are untouched
     assert float(phi_buf[0]) == 7.0 and int(vt_buf[0]) == 9
+
+
+# ---- quantile re-threshold and mc_step -------------------------------------
+
+@pytest.mark.parametrize("q", [0.0, 0.35, 0.5, 0.93, 1.0])
+def test_quantile_rethreshold(ctx, q):
+    # V~ = [V' >= Quantile_q(V')] decided on the exact integer sums: V~ and
+    # phi bit-exact with the oracle, on a ragged grid with a 2-step kernel
+    import torch
+    rng = np.random.default_rng(21)
+    surf = (rng.random((13, 17, 29)) < 0.2).astype(np.uint8)
+    h, sigma, band = 0.05, 0.05, 0.15
+    nz, ny, nx = surf.shape
+    g = ctx.grid((0.1, -0.3, 0.0), h, (nx, ny, nz), 0.0)
+    phi = torch.full((nz, ny, nx), 7.0, dtype=torch.float32, device="cuda")
+    vt = torch.full((nz, ny, nx), 9, dtype=torch.uint8, device="cuda")
+    ctx.tsdf(g, cuda(surf), phi, sigma, 0.0, band, out_vtilde=vt, quantile=q)
+    torch.cuda.synchronize()
+    phi_o, vt_o, _, _ = ot.tsdf(surf, h, sigma, 0.0, band, quantile=q)
+    np.testing.assert_array_equal(vt.cpu().numpy(), vt_o)
+    np.testing.assert_array_equal(phi.cpu().numpy().view(np.uint32), phi_o.view(np.uint32))
+    log(f"quantile {q}: V~ {int(vt_o.sum())} of {surf.size}")
+
+
+def test_quantile_rethreshold_large_kernel(ctx):
+    # 8-step kernel: sums up to 2^48, many distinct values
+    import torch
+    rng = np.random.default_rng(22)
+    surf = (rng.random((20, 24, 30)) < 0.15).astype(np.uint8)
+    h, sigma, band = 0.02, 0.04, 0.06
+    nz, ny, nx = surf.shape
+    g = ctx.grid((0.0, 0.0, 0.0), h, (nx, ny, nz), 0.0)
+    phi = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
+    vt = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda")
+    for q in (0.6, 0.85):
+        ctx.tsdf(g, cuda(surf), phi, sigma, 0.0, band, out_vtilde=vt, quantile=q)
+        torch.cuda.synchronize()
+        phi_o, vt_o, _, _ = ot.tsdf(surf, h, sigma, 0.0, band, quantile=q)
+        np.testing.assert_array_equal(vt.cpu().numpy(), vt_o)
+        np.testing.assert_array_equal(phi.cpu().numpy().view(np.uint32), phi_o.view(np.uint32))
+
+
+def test_quantile_rejects_bad_values(ctx):
+    import torch
+    surf = np.zeros((4, 4, 4), np.uint8)
+    g = ctx.grid((0, 0, 0), 0.1, (4, 4, 4), 0.0)
+    phi = torch.empty((4, 4, 4), dtype=torch.float32, device="cuda")
+    for q in (-0.1, 1.5, float("nan")):
+        with pytest.raises(rcast.RcastError) as e:
+            ctx.tsdf(g, cuda(surf), phi, 0.1, 0.0, 0.2, quantile=q)
+        assert e.value.status == rcast.RC_E_INVAL
+
+
+@pytest.mark.parametrize("step", [1, 2, 3, 5])
+def test_mc_step(ctx, step):
+    # marching cubes on every step-th lattice point: topology, numbering and
+    # float32 positions and normals bit-exact with the oracle's evaluation
+    # on the coarse lattice, positions within the FP64 definition's bounds
+    import torch
+    rng = np.random.default_rng(30 + step)
+    surf = (rng.random((26, 31, 37)) < 0.05).astype(np.uint8)
+    origin, h = (0.25, -0.5, 0.125), 0.04
+    phi, g = check_tsdf(ctx, surf, origin, h, 0.04, 0.1, 0.16, tag=f"mc_step {step} field")
+    vo, to, no = ot.marching_cubes_step(phi, origin, h, step, 0.0, normals=True)
+    hs = float(np.float32(np.float32(h) * np.float32(step)))
+    o2 = tuple(float(np.float32(float(np.float32(o)) - (step - 1) * float(np.float32(h)) / 2.0))
+               for o in origin)
+    coarse = np.ascontiguousarray(phi[::step, ::step, ::step])
+    x64, n64, ptol, ntol = ot.marching_cubes_fp64(coarse, o2, hs, 0.0)
+    v, t, n = ctx.marching_cubes(g, cuda(phi), 0.0, normals=True, step=step)
+    torch.cuda.synchronize()
+    v, t, n = v.cpu().numpy(), t.cpu().numpy(), n.cpu().numpy()
+    np.testing.assert_array_equal(t, to)
+    np.testing.assert_array_equal(v.view(np.uint32), vo.view(np.uint32))
+    np.testing.assert_array_equal(n.view(np.uint32), no.view(np.uint32))
+    assert np.all(np.abs(v.astype(np.float64) - x64) <= ptol)
+    log(f"mc_step {step}: {len(v)} vertices, {len(t)} triangles")
+
+
+def test_mc_step_rejects_zero(ctx):
+    surf = np.zeros((4, 4, 4), np.float32)
+    g = ctx.grid((0, 0, 0), 0.1, (4, 4, 4), 0.0)
+    with pytest.raises(rcast.RcastError) as e:
+        ctx.marching_cubes(g, cuda(surf), 0.0, step=0)
+    assert e.value.status == rcast.RC_E_INVAL
