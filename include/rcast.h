@@ -346,7 +346,10 @@ typedef struct {
 typedef struct {
     uint64_t arena_bytes;     /* device memory for admitted requests
                                  (0 = 4 GiB; >= 1 MiB); 1/64 holds poses     */
-    int32_t max_inflight;     /* launches in flight at once, 1..8 (0 = 2)    */
+    int32_t max_inflight;     /* launches in flight at once, 1..8 (0 = 2);
+                                 each has its own stream, but a process gets
+                                 4 hardware queues by default, so launches
+                                 beyond 4 share queues and wait in them */
     int32_t max_batch_rays_m; /* cap on rays per launch, millions (0 = none):
                                  admission stops before a request that would
                                  exceed it; a larger request runs alone     */

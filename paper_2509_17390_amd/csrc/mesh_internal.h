@@ -58,8 +58,11 @@ int tsdf_words_per_row(const TsdfGrid &g);
 int64_t tsdf_seg_words(const TsdfGrid &g);
 hipError_t tsdf_pack_launch(const uint8_t *vt, uint64_t *F, uint64_t *O, const TsdfGrid &g,
                             hipStream_t s);
+// A round whose `prev` flag (the previous round's *changed; null: always
+// run) reads 0 does nothing, so rounds can be enqueued ahead in batches.
 hipError_t tsdf_flood_round_launch(const uint64_t *F, uint64_t *O, uint64_t *seg,
-                                   const TsdfGrid &g, int32_t *changed, hipStream_t s);
+                                   const TsdfGrid &g, const int32_t *prev, int32_t *changed,
+                                   hipStream_t s);
 // Shells and phi.  p (one byte per voxel) must be 4-byte aligned with
 // tsdf_shell_pad(g) readable bytes before and after it.
 int64_t tsdf_shell_pad(const TsdfGrid &g);

@@ -354,8 +354,12 @@ __global__ __launch_bounds__(kBlock) void k_pack_free(const uint8_t *__restrict_
 
 __global__ __launch_bounds__(kBlock) void k_sweep_x(const uint64_t *__restrict__ F,
                                                     uint64_t *__restrict__ O, TsdfGrid g, int W,
-                                                    int32_t *__restrict__ changed)
+                                                    int32_t *__restrict__ changed,
+                                                    const int32_t *__restrict__ skip)
 {
+    // a round enqueued after the labelling settled does nothing
+    if (skip && *skip == 0) return;
+
     const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (row >= (int64_t)g.ny * g.nz) return;
     const uint64_t *f = F + row * W;
@@ -409,8 +413,12 @@ __global__ __launch_bounds__(kBlock) void k_seg_summary(const uint64_t *__restri
                                                         TsdfGrid g, int W, Cols cl,
                                                         uint64_t *__restrict__ A,
                                                         uint64_t *__restrict__ B,
-                                                        uint64_t *__restrict__ T)
+                                                        uint64_t *__restrict__ T,
+                                                        const int32_t *__restrict__ skip)
 {
+    // a round enqueued after the labelling settled does nothing
+    if (skip && *skip == 0) return;
+
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= cl.ncols * cl.nseg) return;
     const int sg = (int)(t / cl.ncols);
@@ -446,8 +454,12 @@ __global__ __launch_bounds__(kBlock) void k_seg_carry(const uint64_t *__restrict
                                                       const uint64_t *__restrict__ B,
                                                       const uint64_t *__restrict__ T, Cols cl,
                                                       uint64_t *__restrict__ C,
-                                                      uint64_t *__restrict__ D)
+                                                      uint64_t *__restrict__ D,
+                                                      const int32_t *__restrict__ skip)
 {
+    // a round enqueued after the labelling settled does nothing
+    if (skip && *skip == 0) return;
+
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= cl.ncols) return;
     // 8 segments' summaries are loaded together, then chained in registers
@@ -494,8 +506,12 @@ __global__ __launch_bounds__(kBlock) void k_seg_apply(const uint64_t *__restrict
                                                       int W, Cols cl,
                                                       const uint64_t *__restrict__ C,
                                                       const uint64_t *__restrict__ D,
-                                                      int32_t *__restrict__ changed)
+                                                      int32_t *__restrict__ changed,
+                                                      const int32_t *__restrict__ skip)
 {
+    // a round enqueued after the labelling settled does nothing
+    if (skip && *skip == 0) return;
+
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= cl.ncols * cl.nseg) return;
     const int sg = (int)(t / cl.ncols);
@@ -1264,11 +1280,12 @@ hipError_t tsdf_pack_launch(const uint8_t *vt, uint64_t *F, uint64_t *O, const T
 }
 
 hipError_t tsdf_flood_round_launch(const uint64_t *F, uint64_t *O, uint64_t *seg,
-                                   const TsdfGrid &g, int32_t *changed, hipStream_t s)
+                                   const TsdfGrid &g, const int32_t *prev, int32_t *changed,
+                                   hipStream_t s)
 {
     const int W = tsdf_words_per_row(g);
     hipLaunchKernelGGL(k_sweep_x, dim3(grid_for((int64_t)g.ny * g.nz, kBlock)), dim3(kBlock), 0, s,
-                       F, O, g, W, changed);
+                       F, O, g, W, changed, prev);
     const int64_t ns = tsdf_seg_words(g);
     uint64_t *A = seg, *B = seg + ns, *T = seg + 2 * ns, *C = seg + 3 * ns, *D = seg + 4 * ns;
     for (int axis = 1; axis <= 2; ++axis) {
@@ -1276,18 +1293,18 @@ hipError_t tsdf_flood_round_launch(const uint64_t *F, uint64_t *O, uint64_t *seg
         const unsigned gs = grid_for(cl.ncols * cl.nseg, kBlock);
         if (axis == 1)
             hipLaunchKernelGGL(k_seg_summary<1>, dim3(gs), dim3(kBlock), 0, s, F, O, g, W, cl, A, B,
-                               T);
+                               T, prev);
         else
             hipLaunchKernelGGL(k_seg_summary<2>, dim3(gs), dim3(kBlock), 0, s, F, O, g, W, cl, A, B,
-                               T);
+                               T, prev);
         hipLaunchKernelGGL(k_seg_carry, dim3(grid_for(cl.ncols, kBlock)), dim3(kBlock), 0, s, A, B,
-                           T, cl, C, D);
+                           T, cl, C, D, prev);
         if (axis == 1)
             hipLaunchKernelGGL(k_seg_apply<1>, dim3(gs), dim3(kBlock), 0, s, F, O, g, W, cl, C, D,
-                               changed);
+                               changed, prev);
         else
             hipLaunchKernelGGL(k_seg_apply<2>, dim3(gs), dim3(kBlock), 0, s, F, O, g, W, cl, C, D,
-                               changed);
+                               changed, prev);
     }
     return hipGetLastError();
 }

@@ -400,6 +400,8 @@ struct Scratch {
 
 }  // namespace
 
+constexpr int kFloodBatch = 6;   // outside-labelling rounds enqueued per flag read
+
 rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_tsdf_opts *opts,
                   float *out_phi, uint8_t *out_vtilde, void *stream)
 {
@@ -462,7 +464,7 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
     ws.take(&fw, sizeof(uint64_t) * nwords);
     ws.take(&ow, sizeof(uint64_t) * nwords);
     ws.take(&seg, sizeof(uint64_t) * 5 * tsdf_seg_words(g));
-    ws.take(&flag, sizeof(int32_t));
+    ws.take(&flag, sizeof(int32_t) * kFloodBatch);
     uint64_t *sums = nullptr;
     char *sel = nullptr;
     if (quant) {
@@ -480,14 +482,18 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
         HIP_TRY(tsdf_smooth_launch(surf, a, b, vt, g, w, thr, s));
     }
     HIP_TRY(tsdf_pack_launch(vt, fw, ow, g, s));
-    // rounds until one changes nothing (one flag read per round)
-    for (int64_t it = 0;; ++it) {
-        int32_t changed = 0;
-        HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-        HIP_TRY(tsdf_flood_round_launch(fw, ow, seg, g, flag, s));
-        HIP_TRY(hipMemcpyAsync(&changed, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    // rounds until one changes nothing, enqueued kFloodBatch at a time with
+    // one flag read per batch: a round after a round that changed nothing
+    // returns at once, and repeating a settled round changes nothing
+    for (int64_t it = 0;; it += kFloodBatch) {
+        int32_t changed[kFloodBatch];
+        HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int32_t) * kFloodBatch, s));
+        for (int r = 0; r < kFloodBatch; ++r)
+            HIP_TRY(tsdf_flood_round_launch(fw, ow, seg, g, r ? flag + r - 1 : nullptr, flag + r,
+                                            s));
+        HIP_TRY(hipMemcpyAsync(changed, flag, sizeof changed, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        if (!changed) break;
+        if (!changed[kFloodBatch - 1]) break;
         if (it > g.n) return fail(RC_E_DEVICE, "outside labelling did not settle");
     }
     HIP_TRY(tsdf_shells_phi_launch(vt, ow, p, out_phi, g, shells, g.hf, r, s));
