@@ -206,11 +206,22 @@ struct QemBuffers {
     int32_t *ndeg;        // [nv]
     uint32_t *nlarge;     // [nv] neighbours above the vertex
     uint32_t *eoff;       // [nv] first edge number of the vertex
-    uint64_t *key;        // [3 nt] candidate key (cost bits << 32 | edge) or ~0
+    uint64_t *key;        // [3 nt] candidate key (cost bits << 32 | pi(edge)) or ~0
+    uint8_t *cand;        // [3 nt] edge is a candidate
     double *X;            // [3 nt][3] contraction point of a candidate
+    // the previous step's eoff, key, cand and X (the host swaps the pairs
+    // before each step): an edge whose two ends are clean keeps its result
+    uint32_t *eoff_old;
+    uint64_t *key_old;
+    uint8_t *cand_old;
+    double *X_old;
     int32_t *eu, *ev;     // [3 nt] edge ends
     unsigned long long *best;   // [nv]
     int32_t *remap;       // [nv] contracted into (or -1)
+    // [nv] in the closed one-rings of an edge contracted in the last step:
+    // the vertex's faces, neighbours and edges are evaluated anew
+    uint8_t *dirty;
+    int32_t *absorbed;    // [nv] the vertex contracted into this one in the last step, or -1
     uint32_t *counters;   // [4] candidates, contracted, live faces, flags
     char *sel;            // qem_sel_bytes(): radix-select state
 };
@@ -221,20 +232,30 @@ size_t qem_sel_bytes();
 hipError_t qem_init_launch(const float *verts, int64_t nv, const int32_t *tris, int64_t nt,
                            double *P, int32_t *F, hipStream_t s);
 // Incident faces, neighbours and neighbour counts above each vertex; at a
-// round's start also the quadrics and protected flags.  counters[3] |= 1
-// (2) when a vertex has more than kQemFaces faces (kQemNbrs neighbours).
+// round's start from all live faces, with the quadrics and protected
+// flags, else for the dirty vertices only, from their previous lists.
+// counters[3] |= 1 (2) when a vertex has more than kQemFaces faces
+// (kQemNbrs neighbours).
 hipError_t qem_incidence_launch(const QemBuffers &b, int64_t nv, int64_t nt, int round_start,
                                 hipStream_t s);
 // Candidate keys and points of every edge (eoff must hold the exclusive
-// scan of nlarge); counters[0] += candidates.
-hipError_t qem_edges_launch(const QemBuffers &b, int64_t nv, hipStream_t s);
+// scan of nlarge, n_edges its total); counters[0] += candidates.  At a
+// round's start every edge is evaluated, else only those with a dirty end;
+// the others take their previous result (eoff_old, key_old, cand_old,
+// X_old) under their new number.
+hipError_t qem_edges_launch(const QemBuffers &b, int64_t nv, int64_t n_edges, int round_start,
+                            hipStream_t s);
 // Radix select of the rank-th smallest key (1-based) of n_edges keys.
 hipError_t qem_select_launch(const QemBuffers &b, int64_t n_edges, uint64_t rank, hipStream_t s);
+// counters[2] += live faces.
+hipError_t qem_live_launch(const QemBuffers &b, int64_t nt, hipStream_t s);
 // Contract the chosen edges among the eligible ones (all candidates when
-// `all`, else keys up to the selected one) and rename the faces;
-// counters[1] += contractions, counters[2] += live faces.
-hipError_t qem_contract_launch(const QemBuffers &b, int64_t nv, int64_t nt, int64_t n_edges,
-                               int all, hipStream_t s);
+// `all`, else keys up to the selected one): u takes x and Q_u + Q_v, v's
+// faces are renamed to u (the two on the edge dropped), the closed
+// one-rings are marked dirty (after clearing the marks); counters[1] +=
+// contractions, counters[2] += faces dropped.
+hipError_t qem_contract_launch(const QemBuffers &b, int64_t nv, int64_t n_edges, int all,
+                               hipStream_t s);
 // keep[t] = live face, used[v] = 1 for their corners (used zeroed first).
 hipError_t qem_used_launch(const int32_t *F, int64_t nt, uint32_t *used, uint32_t *keep,
                            hipStream_t s);

@@ -31,10 +31,15 @@
 //      the threshold key; an interior contraction removes two faces);
 //   4. an eligible edge contracts when no eligible edge at any vertex of
 //      its two closed one-rings has a smaller key (per-vertex 64-bit atomic
-//      minima); such edges share no endpoint and no neighbour, so their
-//      contractions touch disjoint faces and run in place;
+//      minima); no end of such an edge is an end or a neighbour of an end
+//      of another, so their contractions touch disjoint faces and run in
+//      place;
 //   5. faces are renamed through the contraction map; the two faces of
 //      each contracted edge degenerate and are dropped.
+// A step changes the mesh only inside the closed one-rings of the edges it
+// contracts: the next step rebuilds the incidence and evaluates the edges
+// of those ("dirty") vertices alone, and every other edge keeps its cost
+// and point under its new number.
 // Positions, quadrics and costs are FP64 throughout, each operation in a
 // fixed order (compiled with -ffp-contract=off), so a run is deterministic
 // and matches a plain CPU evaluation of the same steps; positions are
@@ -51,6 +56,24 @@ constexpr int kBlock = 256;
 constexpr uint64_t kNone = ~0ull;
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+// Adds v of every thread of the block to *dst with one atomic: a
+// shuffle-reduction per wave, then the waves' sums through LDS (a counter
+// that every thread of a large launch hit directly serialised the launch).
+// Every thread of the block must call it.
+__device__ __forceinline__ void block_add(uint32_t v, uint32_t *dst)
+{
+    __shared__ uint32_t part[kBlock / 64];
+    __syncthreads();   // an earlier call's sum is read before part is reused
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += part[w];
+        if (t) atomicAdd(dst, t);
+    }
+}
 
 // pi: "lowbias32" of C. Wellons' hash prospector (xorshift-multiply rounds,
 // each invertible mod 2^32, so pi is a bijection and keys stay unique)
@@ -155,17 +178,12 @@ __device__ double placement(const double Q[10], const double pu[3], const double
         ok = dot3(dx, dx) <= 4.0 * dot3(e, e);
     }
     if (!ok) {
-        const double *cand[3] = {pu, pv, m};
-        int best = 0;
-        double bc = quadric_cost(Q, pu);
-        for (int i = 1; i < 3; ++i) {
-            const double c = quadric_cost(Q, cand[i]);
-            if (c < bc) {
-                bc = c;
-                best = i;
-            }
-        }
-        for (int i = 0; i < 3; ++i) x[i] = cand[best][i];
+        // the cheapest of pu, pv, m; the first on a tie
+        const double cu = quadric_cost(Q, pu), cv = quadric_cost(Q, pv), cm = quadric_cost(Q, m);
+        const bool tv = cv < cu;
+        const double cb = tv ? cv : cu;
+        const bool tm = cm < cb;
+        for (int i = 0; i < 3; ++i) x[i] = tm ? m[i] : (tv ? pv[i] : pu[i]);
     }
     return quadric_cost(Q, x);
 }
@@ -208,38 +226,11 @@ __device__ __forceinline__ bool face_has(const int32_t *__restrict__ F, int32_t 
     return F[3 * (int64_t)t] == w || F[3 * (int64_t)t + 1] == w || F[3 * (int64_t)t + 2] == w;
 }
 
-// Per vertex: sort its faces, collect its distinct neighbours (ascending),
-// count those above it; at a round's start also sum its faces' plane
-// quadrics (ascending face order) and protect it when an edge at it is not
-// on exactly two faces.
-__global__ __launch_bounds__(kBlock) void k_qem_vertex(const double *__restrict__ P,
-                                                       const int32_t *__restrict__ F, int64_t nv,
-                                                       const uint32_t *__restrict__ fcnt,
-                                                       int32_t *__restrict__ fl,
-                                                       int32_t *__restrict__ fdeg,
-                                                       int32_t *__restrict__ nb,
-                                                       int32_t *__restrict__ ndeg,
-                                                       uint32_t *__restrict__ nlarge,
-                                                       double *__restrict__ Q,
-                                                       uint8_t *__restrict__ prot,
-                                                       int round_start,
-                                                       uint32_t *__restrict__ flags)
+// The distinct neighbours of v (ascending) from its n faces f into b;
+// returns their number (at most kQemNbrs, else flags[0] |= 2).
+__device__ int build_ring(const int32_t *__restrict__ F, const int32_t *f, int n, int64_t v,
+                          int32_t *b, uint32_t *__restrict__ flags)
 {
-    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (v >= nv) return;
-    const int n = fcnt[v] < (uint32_t)kQemFaces ? (int)fcnt[v] : kQemFaces;
-    int32_t *f = fl + v * kQemFaces;
-    for (int k = 1; k < n; ++k) {
-        const int32_t x = f[k];
-        int j = k;
-        while (j > 0 && f[j - 1] > x) {
-            f[j] = f[j - 1];
-            --j;
-        }
-        f[j] = x;
-    }
-    fdeg[v] = n;
-    int32_t *b = nb + v * kQemNbrs;
     int m = 0;
     for (int k = 0; k < n; ++k)
         for (int c = 0; c < 3; ++c) {
@@ -256,6 +247,44 @@ __global__ __launch_bounds__(kBlock) void k_qem_vertex(const double *__restrict_
             b[j] = w;
             ++m;
         }
+    return m;
+}
+
+// Per vertex: sort its faces, collect its distinct neighbours (ascending),
+// count those above it; at a round's start also sum its faces' plane
+// quadrics (ascending face order) and protect it when an edge at it is not
+// on exactly two faces.
+__global__ __launch_bounds__(kBlock) void k_qem_vertex(const double *__restrict__ P,
+                                                       const int32_t *__restrict__ F, int64_t nv,
+                                                       const uint32_t *__restrict__ fcnt,
+                                                       int32_t *__restrict__ fl,
+                                                       int32_t *__restrict__ fdeg,
+                                                       int32_t *__restrict__ nb,
+                                                       int32_t *__restrict__ ndeg,
+                                                       uint32_t *__restrict__ nlarge,
+                                                       double *__restrict__ Q,
+                                                       uint8_t *__restrict__ prot,
+                                                       int round_start,
+                                                       int32_t *__restrict__ absorbed,
+                                                       uint32_t *__restrict__ flags)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nv) return;
+    absorbed[v] = -1;
+    const int n = fcnt[v] < (uint32_t)kQemFaces ? (int)fcnt[v] : kQemFaces;
+    int32_t *f = fl + v * kQemFaces;
+    for (int k = 1; k < n; ++k) {
+        const int32_t x = f[k];
+        int j = k;
+        while (j > 0 && f[j - 1] > x) {
+            f[j] = f[j - 1];
+            --j;
+        }
+        f[j] = x;
+    }
+    fdeg[v] = n;
+    int32_t *b = nb + v * kQemNbrs;
+    const int m = build_ring(F, f, n, v, b, flags);
     ndeg[v] = m;
     uint32_t above = 0;
     for (int k = 0; k < m; ++k) above += b[k] > (int32_t)v ? 1u : 0u;
@@ -282,92 +311,203 @@ __global__ __launch_bounds__(kBlock) void k_qem_vertex(const double *__restrict_
     prot[v] = p;
 }
 
-// Per vertex u: every edge (u, v > u) in ascending v, numbered from
-// eoff[u]; candidate evaluation (readings of the header comment).
-__global__ __launch_bounds__(kBlock) void k_qem_edges(
-    const double *__restrict__ P, const int32_t *__restrict__ F, int64_t nv,
-    const int32_t *__restrict__ fl, const int32_t *__restrict__ fdeg,
-    const int32_t *__restrict__ nb, const int32_t *__restrict__ ndeg,
-    const uint32_t *__restrict__ eoff, const double *__restrict__ Q,
-    const uint8_t *__restrict__ prot, uint64_t *__restrict__ key, double *__restrict__ X,
-    int32_t *__restrict__ eu, int32_t *__restrict__ ev, uint32_t *__restrict__ counters)
+// Between a round's steps, per dirty vertex: its live faces are those of
+// its previous list still alive (a contraction renames faces, it never
+// adds a face to a vertex it did not touch), plus, for the u of a
+// contracted edge (u, v), the live faces of v's list, merged in ascending
+// order; then its neighbours anew.  v itself is left to u's thread, which
+// empties v's lists after reading them.
+__global__ __launch_bounds__(kBlock) void k_qem_vertex_update(
+    const int32_t *__restrict__ F, int64_t nv, const uint8_t *__restrict__ dirty,
+    const int32_t *__restrict__ remap, int32_t *__restrict__ absorbed, int32_t *__restrict__ fl,
+    int32_t *__restrict__ fdeg, int32_t *__restrict__ nb, int32_t *__restrict__ ndeg,
+    uint32_t *__restrict__ nlarge, uint32_t *__restrict__ flags)
 {
-    const int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (u >= nv) return;
-    const int nu = ndeg[u], fu = fdeg[u];
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nv || !dirty[v] || remap[v] >= 0) return;
+    int32_t *f = fl + v * kQemFaces;
+    const int n0 = fdeg[v];
+    int a = 0;
+    for (int k = 0; k < n0; ++k) {
+        const int32_t t = f[k];
+        if (F[3 * (int64_t)t] >= 0) f[a++] = t;
+    }
+    int n = a;
+    const int32_t w = absorbed[v];
+    if (w >= 0) {
+        absorbed[v] = -1;
+        const int32_t *g = fl + (int64_t)w * kQemFaces;
+        const int m0 = fdeg[w];
+        int nb_live = 0;
+        for (int k = 0; k < m0; ++k) nb_live += F[3 * (int64_t)g[k]] >= 0 ? 1 : 0;
+        if (a + nb_live > kQemFaces) {
+            atomicOr(&flags[0], 1u);
+        } else {
+            // merge from the top: v's own list sits at the front of the
+            // destination, so no entry is overwritten before it is read
+            int i = a - 1, j = m0 - 1;
+            for (int o = a + nb_live - 1; o > i; --o) {
+                while (F[3 * (int64_t)g[j]] < 0) --j;
+                if (i < 0 || g[j] > f[i]) f[o] = g[j--];
+                else f[o] = f[i--];
+            }
+            n = a + nb_live;
+        }
+        fdeg[w] = 0;
+        ndeg[w] = 0;
+        nlarge[w] = 0;
+    }
+    fdeg[v] = n;
+    int32_t *b = nb + v * kQemNbrs;
+    const int m = build_ring(F, f, n, v, b, flags);
+    ndeg[v] = m;
+    uint32_t above = 0;
+    for (int k = 0; k < m; ++k) above += b[k] > (int32_t)v ? 1u : 0u;
+    nlarge[v] = above;
+}
+
+// Candidate test of the edge (u, v): true with the contraction point x and
+// the float32 cost bits when the edge may contract (readings of the header
+// comment).
+__device__ bool edge_candidate(const double *__restrict__ P, const int32_t *__restrict__ F,
+                               const int32_t *__restrict__ fl, const int32_t *__restrict__ fdeg,
+                               const int32_t *__restrict__ nb, const int32_t *__restrict__ ndeg,
+                               const double *__restrict__ Q, const uint8_t *__restrict__ prot,
+                               int64_t u, int32_t v, int nu, int fu, double x[3],
+                               uint32_t *cbits)
+{
     const int32_t *bu = nb + u * kQemNbrs;
     const int32_t *lu = fl + u * kQemFaces;
+    int fc = 0;
+    for (int i = 0; i < fu; ++i) fc += face_has(F, lu[i], v) ? 1 : 0;
+    if (fc != 2 || prot[u] || prot[v]) return false;
+    // link condition: exactly two common neighbours
+    const int32_t *bv = nb + (int64_t)v * kQemNbrs;
+    const int nvv = ndeg[v];
+    int i = 0, j = 0, common = 0;
+    while (i < nu && j < nvv) {
+        if (bu[i] < bv[j]) ++i;
+        else if (bu[i] > bv[j]) ++j;
+        else { ++common; ++i; ++j; }
+    }
+    if (common != 2) return false;
+    double Qe[10], pu[3], pv[3];
+    for (int q = 0; q < 10; ++q) Qe[q] = Q[10 * u + q] + Q[10 * (int64_t)v + q];
+    load3(P, (int32_t)u, pu);
+    load3(P, v, pv);
+    const double c = placement(Qe, pu, pv, x);
+    // no face of u or v (other than the two on the edge) may flip
+    for (int side = 0; side < 2; ++side) {
+        const int64_t w = side == 0 ? u : (int64_t)v;
+        const int32_t *lw = fl + w * kQemFaces;
+        const int fw = fdeg[w];
+        for (int i2 = 0; i2 < fw; ++i2) {
+            const int64_t t = lw[i2];
+            const int32_t c0 = F[3 * t], c1 = F[3 * t + 1], c2 = F[3 * t + 2];
+            const bool hu = c0 == (int32_t)u || c1 == (int32_t)u || c2 == (int32_t)u;
+            const bool hv = c0 == v || c1 == v || c2 == v;
+            if (hu && hv) continue;
+            double a[3], b[3], cc[3], n0[3], n1[3];
+            load3(P, c0, a);
+            load3(P, c1, b);
+            load3(P, c2, cc);
+            face_normal(a, b, cc, n0);
+            if (!(dot3(n0, n0) > 0.0)) continue;
+            // the corner at u or v moves to x (selects, not a pointer, so
+            // the corners stay in registers)
+            const bool m0 = c0 == (int32_t)u || c0 == v;
+            const bool m1 = !m0 && (c1 == (int32_t)u || c1 == v);
+            const bool m2 = !m0 && !m1;
+            for (int q = 0; q < 3; ++q) {
+                a[q] = m0 ? x[q] : a[q];
+                b[q] = m1 ? x[q] : b[q];
+                cc[q] = m2 ? x[q] : cc[q];
+            }
+            face_normal(a, b, cc, n1);
+            if (!(dot3(n0, n1) > 0.0)) return false;
+        }
+    }
+    // cost clamped at 0 (a NaN stays) and rounded to float32; -0 and +0
+    // share one key
+    const double cl = 0.0 > c ? 0.0 : c;
+    float c32 = (float)cl;
+    if (c32 == 0.0f) c32 = 0.0f;
+    *cbits = __float_as_uint(c32);
+    return true;
+}
+
+// Per vertex u: every edge (u, v > u) in ascending v, numbered from
+// eoff[u].  An edge whose two ends are clean keeps its previous result,
+// read at its previous number eoff_old[u] + j: its ends, their faces,
+// neighbours, positions and quadrics are all unchanged since then; the
+// key's low word becomes pi of the current number.  Any other edge (every
+// edge at a round's start) is marked for k_qem_eval (cand = 2).
+__global__ __launch_bounds__(kBlock) void k_qem_edges(
+    int64_t nv, const int32_t *__restrict__ nb, const int32_t *__restrict__ ndeg,
+    const uint32_t *__restrict__ eoff, const uint8_t *__restrict__ dirty, int full,
+    const uint32_t *__restrict__ eoff_old, const uint64_t *__restrict__ key_old,
+    const uint8_t *__restrict__ cand_old, const double *__restrict__ X_old,
+    uint64_t *__restrict__ key, uint8_t *__restrict__ cand, double *__restrict__ X,
+    int32_t *__restrict__ eu, int32_t *__restrict__ ev, uint32_t *__restrict__ counters)
+{
+    const int64_t u0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t u = u0 < nv ? u0 : nv - 1;
+    const int nu = u0 < nv ? ndeg[u] : 0;
+    const int32_t *bu = nb + u * kQemNbrs;
+    const bool du = full || dirty[u];
     uint32_t e = eoff[u];
+    uint32_t eo = full ? 0u : eoff_old[u];
     uint32_t found = 0;
     for (int k = 0; k < nu; ++k) {
         const int32_t v = bu[k];
         if (v <= (int32_t)u) continue;
         eu[e] = (int32_t)u;
         ev[e] = v;
-        uint64_t kv = kNone;
-        int fc = 0;
-        for (int i = 0; i < fu; ++i) fc += face_has(F, lu[i], v) ? 1 : 0;
-        if (fc == 2 && !prot[u] && !prot[v]) {
-            // link condition: exactly two common neighbours
-            const int32_t *bv = nb + (int64_t)v * kQemNbrs;
-            const int nvv = ndeg[v];
-            int i = 0, j = 0, common = 0;
-            while (i < nu && j < nvv) {
-                if (bu[i] < bv[j]) ++i;
-                else if (bu[i] > bv[j]) ++j;
-                else { ++common; ++i; ++j; }
-            }
-            if (common == 2) {
-                double Qe[10], pu[3], pv[3], x[3];
-                for (int q = 0; q < 10; ++q) Qe[q] = Q[10 * u + q] + Q[10 * (int64_t)v + q];
-                load3(P, (int32_t)u, pu);
-                load3(P, v, pv);
-                const double c = placement(Qe, pu, pv, x);
-                // no face of u or v (other than the two on the edge) may flip
-                bool flip = false;
-                for (int side = 0; side < 2 && !flip; ++side) {
-                    const int64_t w = side == 0 ? u : (int64_t)v;
-                    const int32_t *lw = fl + w * kQemFaces;
-                    const int fw = fdeg[w];
-                    for (int i2 = 0; i2 < fw && !flip; ++i2) {
-                        const int64_t t = lw[i2];
-                        const int32_t c0 = F[3 * t], c1 = F[3 * t + 1], c2 = F[3 * t + 2];
-                        const bool hu = c0 == (int32_t)u || c1 == (int32_t)u || c2 == (int32_t)u;
-                        const bool hv = c0 == v || c1 == v || c2 == v;
-                        if (hu && hv) continue;
-                        double a[3], b[3], cc[3], n0[3], n1[3];
-                        load3(P, c0, a);
-                        load3(P, c1, b);
-                        load3(P, c2, cc);
-                        face_normal(a, b, cc, n0);
-                        if (!(dot3(n0, n0) > 0.0)) continue;
-                        double *moved = c0 == (int32_t)u || c0 == v ? a
-                                      : (c1 == (int32_t)u || c1 == v ? b : cc);
-                        moved[0] = x[0];
-                        moved[1] = x[1];
-                        moved[2] = x[2];
-                        face_normal(a, b, cc, n1);
-                        flip = !(dot3(n0, n1) > 0.0);
-                    }
-                }
-                if (!flip) {
-                    // cost clamped at 0 (a NaN stays) and rounded to
-                    // float32; -0 and +0 share one key
-                    const double cl = 0.0 > c ? 0.0 : c;
-                    float c32 = (float)cl;
-                    if (c32 == 0.0f) c32 = 0.0f;
-                    kv = ((uint64_t)__float_as_uint(c32) << 32) | perm32(e);
-                    X[3 * (int64_t)e] = x[0];
-                    X[3 * (int64_t)e + 1] = x[1];
-                    X[3 * (int64_t)e + 2] = x[2];
-                    ++found;
-                }
-            }
+        if (du || dirty[v]) {
+            cand[e] = 2;
+        } else if (cand_old[eo]) {
+            for (int q = 0; q < 3; ++q) X[3 * (int64_t)e + q] = X_old[3 * (int64_t)eo + q];
+            key[e] = (key_old[eo] & 0xffffffff00000000ull) | perm32(e);
+            cand[e] = 1;
+            ++found;
+        } else {
+            key[e] = kNone;
+            cand[e] = 0;
         }
-        key[e] = kv;
         ++e;
+        ++eo;
     }
-    if (found) atomicAdd(&counters[0], found);
+    block_add(found, &counters[0]);
+}
+
+// One thread per edge marked by k_qem_edges: the candidate test, its key
+// (float32 cost bits, pi(e)) or "none", and its point.
+__global__ __launch_bounds__(kBlock) void k_qem_eval(
+    const double *__restrict__ P, const int32_t *__restrict__ F, int64_t n,
+    const int32_t *__restrict__ fl, const int32_t *__restrict__ fdeg,
+    const int32_t *__restrict__ nb, const int32_t *__restrict__ ndeg,
+    const double *__restrict__ Q, const uint8_t *__restrict__ prot,
+    const int32_t *__restrict__ eu, const int32_t *__restrict__ ev,
+    uint64_t *__restrict__ key, uint8_t *__restrict__ cand, double *__restrict__ X,
+    uint32_t *__restrict__ counters)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    uint32_t found = 0;
+    if (e < n && cand[e] == 2) {
+        const int64_t u = eu[e];
+        const int32_t v = ev[e];
+        double x[3];
+        uint32_t cbits = 0;
+        const bool c = edge_candidate(P, F, fl, fdeg, nb, ndeg, Q, prot, u, v, ndeg[u], fdeg[u],
+                                      x, &cbits);
+        if (c) {
+            for (int q = 0; q < 3; ++q) X[3 * e + q] = x[q];
+            found = 1;
+        }
+        key[e] = c ? ((uint64_t)cbits << 32) | perm32((uint32_t)e) : kNone;
+        cand[e] = c ? 1 : 0;
+    }
+    block_add(found, &counters[0]);
 }
 
 // Radix select of the rank-th smallest key (1-based), one byte per pass
@@ -396,19 +536,31 @@ __global__ __launch_bounds__(kBlock) void k_qem_hist(const uint64_t *__restrict_
     if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void k_qem_pick(SelState *st, uint32_t *hist, int shift)
+// The digit holding the rank-th key: the first d whose inclusive count
+// reaches rank (digit 255 takes any rest), by a scan of the 256 counts in
+// LDS, one thread per digit; the counts are cleared for the next pass.
+__global__ __launch_bounds__(256) void k_qem_pick(SelState *st, uint32_t *hist, int shift)
 {
-    if (threadIdx.x != 0) return;
-    unsigned long long r = st->rank, cum = 0;
-    int d = 0;
-    for (; d < 255; ++d) {
-        if (cum + hist[d] >= r) break;
-        cum += hist[d];
+    __shared__ unsigned long long c[256];
+    const int i = threadIdx.x;
+    const unsigned long long h = hist[i];
+    c[i] = h;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const unsigned long long add = i >= o ? c[i - o] : 0ull;
+        __syncthreads();
+        c[i] += add;
+        __syncthreads();
     }
-    st->rank = r - cum;
-    st->prefix |= (unsigned long long)d << shift;
-    st->mask |= 0xffull << shift;
-    for (int i = 0; i < 256; ++i) hist[i] = 0;
+    const unsigned long long r = st->rank, before = c[i] - h;
+    const bool mine = before < r && (i == 255 || c[i] >= r);
+    __syncthreads();   // every thread has read the rank before it changes
+    if (mine) {
+        st->rank = r - before;
+        st->prefix |= (unsigned long long)i << shift;
+        st->mask |= 0xffull << shift;
+    }
+    hist[i] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_qem_best(const uint64_t *__restrict__ key, int64_t n,
@@ -430,54 +582,64 @@ __global__ __launch_bounds__(kBlock) void k_qem_choose(
     const int32_t *__restrict__ ev, const SelState *__restrict__ st, int all,
     const unsigned long long *__restrict__ best, const int32_t *__restrict__ nb,
     const int32_t *__restrict__ ndeg, const double *__restrict__ X, double *__restrict__ P,
-    double *__restrict__ Q, int32_t *__restrict__ remap, uint32_t *__restrict__ counters)
+    const int32_t *__restrict__ fl, const int32_t *__restrict__ fdeg, int32_t *__restrict__ F,
+    double *__restrict__ Q, int32_t *__restrict__ remap, uint8_t *__restrict__ dirty,
+    int32_t *__restrict__ absorbed, uint32_t *__restrict__ counters)
 {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= n) return;
-    const uint64_t k = key[e];
-    if (k == kNone || (!all && k > st->prefix)) return;
-    const int32_t u = eu[e], v = ev[e];
-    bool ok = best[u] >= k && best[v] >= k;
+    const uint64_t k = e < n ? key[e] : kNone;
+    bool ok = k != kNone && (all || k <= st->prefix);
+    const int32_t u = ok ? eu[e] : 0, v = ok ? ev[e] : 0;
+    ok = ok && best[u] >= k && best[v] >= k;
+    uint32_t killed = 0;
     for (int side = 0; side < 2 && ok; ++side) {
         const int64_t w = side == 0 ? u : v;
         const int32_t *b = nb + w * kQemNbrs;
         const int m = ndeg[w];
         for (int i = 0; i < m && ok; ++i) ok = best[b[i]] >= k;
     }
-    if (!ok) return;
-    // the contractions chosen in one step share no endpoint and no
-    // neighbour: each updates its own u in place
-    for (int i = 0; i < 10; ++i) Q[10 * (int64_t)u + i] = Q[10 * (int64_t)u + i] + Q[10 * (int64_t)v + i];
-    for (int i = 0; i < 3; ++i) P[3 * (int64_t)u + i] = X[3 * e + i];
-    remap[v] = u;
-    atomicAdd(&counters[1], 1u);
-}
-
-__global__ __launch_bounds__(kBlock) void k_qem_faces(int32_t *__restrict__ F, int64_t nt,
-                                                      const int32_t *__restrict__ remap,
-                                                      uint32_t *__restrict__ counters)
-{
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    uint32_t live = 0;
-    if (t < nt && F[3 * t] >= 0) {
-        int32_t c[3];
-        for (int k = 0; k < 3; ++k) {
-            const int32_t x = F[3 * t + k];
-            const int32_t r = remap[x];
-            c[k] = r >= 0 ? r : x;
+    if (ok) {
+        // no end of an edge chosen in this step is an end or a neighbour of
+        // an end of another: each updates its own u in place
+        for (int i = 0; i < 10; ++i)
+            Q[10 * (int64_t)u + i] = Q[10 * (int64_t)u + i] + Q[10 * (int64_t)v + i];
+        for (int i = 0; i < 3; ++i) P[3 * (int64_t)u + i] = X[3 * e + i];
+        remap[v] = u;
+        absorbed[u] = v;
+        // v's faces: the two on the edge degenerate and are dropped, the
+        // others take u for v (no face has ends of two chosen edges)
+        const int32_t *lv = fl + (int64_t)v * kQemFaces;
+        const int fv = fdeg[v];
+        for (int i = 0; i < fv; ++i) {
+            const int64_t t = lv[i];
+            const int32_t c0 = F[3 * t], c1 = F[3 * t + 1], c2 = F[3 * t + 2];
+            if (c0 == u || c1 == u || c2 == u) {
+                F[3 * t] = -1;
+                ++killed;
+            } else {
+                F[3 * t + (c0 == v ? 0 : (c1 == v ? 1 : 2))] = u;
+            }
         }
-        if (c[0] == c[1] || c[1] == c[2] || c[0] == c[2]) {
-            F[3 * t] = -1;
-        } else {
-            F[3 * t] = c[0];
-            F[3 * t + 1] = c[1];
-            F[3 * t + 2] = c[2];
-            live = 1;
+        // the closed one-rings change: their vertices are evaluated anew
+        // in the next step (two rings may share a vertex: equal stores)
+        dirty[u] = 1;
+        dirty[v] = 1;
+        for (int side = 0; side < 2; ++side) {
+            const int64_t w = side == 0 ? u : v;
+            const int32_t *b = nb + w * kQemNbrs;
+            const int m = ndeg[w];
+            for (int i = 0; i < m; ++i) dirty[b[i]] = 1;
         }
     }
-    // one atomic per wave
-    const unsigned long long b = __ballot(live);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&counters[2], (uint32_t)__popcll(b));
+    block_add(ok ? 1u : 0u, &counters[1]);
+    block_add(killed, &counters[2]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_qem_live(const int32_t *__restrict__ F, int64_t nt,
+                                                     uint32_t *__restrict__ counters)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    block_add(t < nt && F[3 * t] >= 0 ? 1u : 0u, &counters[2]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_qem_used(const int32_t *__restrict__ F, int64_t nt,
@@ -510,6 +672,12 @@ __global__ __launch_bounds__(kBlock) void k_qem_emit(const double *__restrict__ 
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u8(uint8_t *p, int64_t n, uint8_t v)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) p[i] = v;
@@ -549,20 +717,31 @@ hipError_t qem_init_launch(const float *verts, int64_t nv, const int32_t *tris, 
 hipError_t qem_incidence_launch(const QemBuffers &b, int64_t nv, int64_t nt, int round_start,
                                 hipStream_t s)
 {
+    if (!round_start) {
+        hipLaunchKernelGGL(k_qem_vertex_update, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s,
+                           b.F, nv, b.dirty, b.remap, b.absorbed, b.fl, b.fdeg, b.nb, b.ndeg,
+                           b.nlarge, b.counters + 3);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, b.fcnt, nv, 0u);
     hipLaunchKernelGGL(k_qem_fill_faces, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, s, b.F, nt,
                        b.fcnt, b.fl, b.counters + 3);
     hipLaunchKernelGGL(k_qem_vertex, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, b.P, b.F, nv,
                        b.fcnt, b.fl, b.fdeg, b.nb, b.ndeg, b.nlarge, b.Q, b.prot, round_start,
-                       b.counters + 3);
+                       b.absorbed, b.counters + 3);
     return hipGetLastError();
 }
 
-hipError_t qem_edges_launch(const QemBuffers &b, int64_t nv, hipStream_t s)
+hipError_t qem_edges_launch(const QemBuffers &b, int64_t nv, int64_t n_edges, int round_start,
+                            hipStream_t s)
 {
-    hipLaunchKernelGGL(k_qem_edges, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, b.P, b.F, nv,
-                       b.fl, b.fdeg, b.nb, b.ndeg, b.eoff, b.Q, b.prot, b.key, b.X, b.eu, b.ev,
-                       b.counters);
+    hipLaunchKernelGGL(k_qem_edges, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, nv, b.nb,
+                       b.ndeg, b.eoff, b.dirty, round_start, b.eoff_old, b.key_old, b.cand_old,
+                       b.X_old, b.key, b.cand, b.X, b.eu, b.ev, b.counters);
+    if (n_edges > 0)
+        hipLaunchKernelGGL(k_qem_eval, dim3(grid_for(n_edges, kBlock)), dim3(kBlock), 0, s, b.P,
+                           b.F, n_edges, b.fl, b.fdeg, b.nb, b.ndeg, b.Q, b.prot, b.eu, b.ev,
+                           b.key, b.cand, b.X, b.counters);
     return hipGetLastError();
 }
 
@@ -577,7 +756,7 @@ hipError_t radix_select_u64_launch(const uint64_t *keys, int64_t n, uint64_t ran
     if (g < 1) g = 1;
     for (int shift = 56; shift >= 0; shift -= 8) {
         hipLaunchKernelGGL(k_qem_hist, dim3(g), dim3(kBlock), 0, s, keys, n, st, shift, hist);
-        hipLaunchKernelGGL(k_qem_pick, dim3(1), dim3(64), 0, s, st, hist, shift);
+        hipLaunchKernelGGL(k_qem_pick, dim3(1), dim3(256), 0, s, st, hist, shift);
     }
     return hipGetLastError();
 }
@@ -592,23 +771,30 @@ hipError_t qem_select_launch(const QemBuffers &b, int64_t n_edges, uint64_t rank
     return radix_select_u64_launch(b.key, n_edges, rank, b.sel, s);
 }
 
-hipError_t qem_contract_launch(const QemBuffers &b, int64_t nv, int64_t nt, int64_t n_edges,
-                               int all, hipStream_t s)
+hipError_t qem_live_launch(const QemBuffers &b, int64_t nt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_qem_live, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, s, b.F, nt,
+                       b.counters);
+    return hipGetLastError();
+}
+
+hipError_t qem_contract_launch(const QemBuffers &b, int64_t nv, int64_t n_edges, int all,
+                               hipStream_t s)
 {
     const SelState *st = reinterpret_cast<const SelState *>(b.sel);
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, b.best, nv,
                        ~0ull);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s,
                        reinterpret_cast<uint32_t *>(b.remap), nv, 0xffffffffu);
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, b.dirty, nv,
+                       (uint8_t)0);
     if (n_edges > 0) {
         hipLaunchKernelGGL(k_qem_best, dim3(grid_for(n_edges, kBlock)), dim3(kBlock), 0, s, b.key,
                            n_edges, b.eu, b.ev, st, all, b.best);
         hipLaunchKernelGGL(k_qem_choose, dim3(grid_for(n_edges, kBlock)), dim3(kBlock), 0, s,
                            b.key, n_edges, b.eu, b.ev, st, all, b.best, b.nb, b.ndeg, b.X, b.P,
-                           b.Q, b.remap, b.counters);
+                           b.fl, b.fdeg, b.F, b.Q, b.remap, b.dirty, b.absorbed, b.counters);
     }
-    hipLaunchKernelGGL(k_qem_faces, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, s, b.F, nt,
-                       b.remap, b.counters);
     return hipGetLastError();
 }
 

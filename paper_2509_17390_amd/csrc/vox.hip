@@ -1004,7 +1004,14 @@ rc_status rc_decimate_qem(rc_ctx *c, const float *verts, int64_t nv, const int32
     ws.take(&b.nlarge, sizeof(uint32_t) * (size_t)nv);
     ws.take(&b.eoff, sizeof(uint32_t) * (size_t)nv);
     ws.take(&b.key, sizeof(uint64_t) * (size_t)ne_cap);
+    ws.take(&b.cand, (size_t)ne_cap);
     ws.take(&b.X, sizeof(double) * 3 * (size_t)ne_cap);
+    ws.take(&b.eoff_old, sizeof(uint32_t) * (size_t)nv);
+    ws.take(&b.key_old, sizeof(uint64_t) * (size_t)ne_cap);
+    ws.take(&b.cand_old, (size_t)ne_cap);
+    ws.take(&b.X_old, sizeof(double) * 3 * (size_t)ne_cap);
+    ws.take(&b.dirty, (size_t)nv);
+    ws.take(&b.absorbed, sizeof(int32_t) * (size_t)nv);
     ws.take(&b.eu, sizeof(int32_t) * (size_t)ne_cap);
     ws.take(&b.ev, sizeof(int32_t) * (size_t)ne_cap);
     ws.take(&b.best, sizeof(unsigned long long) * (size_t)nv);
@@ -1028,10 +1035,9 @@ rc_status rc_decimate_qem(rc_ctx *c, const float *verts, int64_t nv, const int32
                         (hf & 2) ? " non-finite vertex" : "");
     HIP_TRY(qem_init_launch(verts, nv, tris, nt, b.P, b.F, s));
     uint32_t hc[4] = {0, 0, 0, 0};
-    // live faces after dropping repeated-corner faces: one renaming pass
-    // with an empty contraction map counts them
+    // live faces after dropping repeated-corner faces
     HIP_TRY(hipMemsetAsync(b.counters, 0, sizeof(uint32_t) * 4, s));
-    HIP_TRY(qem_contract_launch(b, nv, nt, 0, 1, s));
+    HIP_TRY(qem_live_launch(b, nt, s));
     HIP_TRY(hipMemcpyAsync(hc, b.counters, sizeof hc, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const int64_t f0 = hc[2];
@@ -1042,6 +1048,11 @@ rc_status rc_decimate_qem(rc_ctx *c, const float *verts, int64_t nv, const int32
         const int64_t target = (int64_t)ceil((double)f0 * pow(r, (double)k / (double)rounds));
         for (int first = 1;; first = 0) {
             if (nf <= target) break;
+            // the previous step's edge results become the old ones
+            std::swap(b.eoff, b.eoff_old);
+            std::swap(b.key, b.key_old);
+            std::swap(b.cand, b.cand_old);
+            std::swap(b.X, b.X_old);
             // incidence of the live faces (a round's start also sums the
             // quadrics and protects boundary vertices), edge numbering
             HIP_TRY(hipMemsetAsync(b.counters, 0, sizeof(uint32_t) * 4, s));
@@ -1058,7 +1069,7 @@ rc_status rc_decimate_qem(rc_ctx *c, const float *verts, int64_t nv, const int32
                                        kQemNbrs);
             // every edge lies on a live face: at most three per face
             if ((int64_t)n_edges > ne_cap) return fail(RC_E_DEVICE, "edge count overflow");
-            HIP_TRY(qem_edges_launch(b, nv, s));
+            HIP_TRY(qem_edges_launch(b, nv, n_edges, first, s));
             HIP_TRY(hipMemcpyAsync(hc, b.counters, sizeof hc, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             const uint64_t cands = hc[0];
@@ -1066,12 +1077,14 @@ rc_status rc_decimate_qem(rc_ctx *c, const float *verts, int64_t nv, const int32
             const uint64_t need = (uint64_t)((nf - target + 1) / 2);
             const int all = need >= cands ? 1 : 0;
             if (!all) HIP_TRY(qem_select_launch(b, n_edges, need, s));
-            HIP_TRY(qem_contract_launch(b, nv, nt, n_edges, all, s));
+            HIP_TRY(qem_contract_launch(b, nv, n_edges, all, s));
             HIP_TRY(hipMemcpyAsync(hc, b.counters, sizeof hc, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             ++steps;
             if (hc[1] == 0) return fail(RC_E_DEVICE, "decimation step contracted nothing");
-            nf = hc[2];
+            // a contraction drops exactly the two faces on its edge
+            if (hc[2] != 2 * hc[1]) return fail(RC_E_DEVICE, "decimation face count mismatch");
+            nf -= hc[2];
         }
     }
     HIP_TRY(hipMemsetAsync(used, 0, sizeof(uint32_t) * (size_t)nv, s));
