@@ -231,9 +231,9 @@ uint64_t rc_device_bytes(rc_ctx *ctx);
  *   persistent    1: persistent waves that take rays from per-XCD work
  *                 queues and refill idle lanes by wavefront ballot;
  *                 0: one ray per thread, one launch-wide grid (default)
- *   stack_lds     traversal-stack entries per lane kept in LDS (deeper
- *                 entries spill to scratch): 8, 16 or 24 for the persistent
- *                 kernel; 0 (default), 8 or 16 otherwise
+ *   stack_lds     the top entries of each lane's traversal stack kept in
+ *                 LDS, as a ring (deeper entries in scratch): 8, 16 or 24
+ *                 for the persistent kernel; 0 (default), 8 or 16 otherwise
  *   refill_min    a persistent wave refills once this many of its 64 lanes
  *                 are idle (1..64, default 64)
  *   blocks_per_cu persistent grid = CUs x this (0 = occupancy limit)

@@ -294,24 +294,44 @@ __device__ __forceinline__ float slab(const RayW &r, float lox, float hix, float
 
 template <int SS, int STK, int BLK>
 struct LaneStack {
-    int *ln;     // LDS: entry k of this lane at ln[k * BLK] (BLK = workgroup size)
-    float *lt;
-    // entries SS.. in scratch, node and distance packed in one 8-byte word so
-    // a push or pop is one memory instruction
+    static_assert(SS >= 0 && SS < STK, "the LDS ring is smaller than the stack");
+    // Node and distance packed in one 8-byte word, so a push or pop is one
+    // memory instruction.  With SS > 0 the top min(sp, SS) entries sit in an
+    // LDS ring of SS slots (entry k in slot k mod SS, this lane's word at
+    // lw[slot * BLK]) and only the entries below it in scratch: a push that
+    // finds the ring full moves the ring's oldest entry down, a pop refills
+    // the slot it frees from below.  Typical depths never leave LDS, so the
+    // scratch lines (which the other resident waves evict from L2 before
+    // they come back) are rarely touched.
+    uint64_t *lw;
     uint64_t sw[STK - SS];
+    static __device__ __forceinline__ uint64_t pack(int n, float t)
+    {
+        return (uint64_t)(uint32_t)n | ((uint64_t)__float_as_uint(t) << 32);
+    }
     __device__ __forceinline__ void put(int k, int n, float t)
     {
-        if (SS > 0 && k < SS) { ln[k * BLK] = n; lt[k * BLK] = t; }
-        else sw[k - SS] = (uint64_t)(uint32_t)n | ((uint64_t)__float_as_uint(t) << 32);
-    }
-    __device__ __forceinline__ void get(int k, int &n, float &t) const
-    {
-        if (SS > 0 && k < SS) { n = ln[k * BLK]; t = lt[k * BLK]; }
-        else {
-            const uint64_t w = sw[k - SS];
-            n = (int)(uint32_t)w;
-            t = __uint_as_float((uint32_t)(w >> 32));
+        const uint64_t w = pack(n, t);
+        if constexpr (SS == 0) {
+            sw[k] = w;
+        } else {
+            uint64_t *slot = lw + (k % SS) * BLK;
+            if (k >= SS) sw[k - SS] = *slot;
+            *slot = w;
         }
+    }
+    __device__ __forceinline__ void get(int k, int &n, float &t)
+    {
+        uint64_t w;
+        if constexpr (SS == 0) {
+            w = sw[k];
+        } else {
+            uint64_t *slot = lw + (k % SS) * BLK;
+            w = *slot;
+            if (k >= SS) *slot = sw[k - SS];
+        }
+        n = (int)(uint32_t)w;
+        t = __uint_as_float((uint32_t)(w >> 32));
     }
 };
 
@@ -598,14 +618,12 @@ __global__ __launch_bounds__(BLK, WAVES) void k_trace(const DevJob *__restrict__
                                                   int32_t *__restrict__ out_nodes,
                                                   int32_t *__restrict__ out_tris)
 {
-    __shared__ int s_node[SS > 0 ? SS * BLK : 1];
-    __shared__ float s_t[SS > 0 ? SS * BLK : 1];
+    __shared__ uint64_t s_stk[SS > 0 ? SS * BLK : 1];
     const int64_t g = g0 + (int64_t)blockIdx.x * BLK + threadIdx.x;
     if (g >= total) return;
     LaneRay L;
     LaneStack<SS, FMT == FMT_Q8 ? kStackQ8 : kStack, BLK> S;
-    S.ln = s_node + threadIdx.x;
-    S.lt = s_t + threadIdx.x;
+    S.lw = s_stk + threadIdx.x;
     bool go = setup_ray(jobs, n_jobs, g, L);
     if (MODE == TRACE_BRUTE) {
         for (int k = 0; go && k < L.n_tris_scene; ++k) test_leaf(L, k);
@@ -775,8 +793,7 @@ __global__ __launch_bounds__(BLK, WAVES) void k_trace_defer(const DevJob *__rest
     const bool valid = g < total;
     LaneRay L;
     LaneStack<0, kStackQ8, BLK> S;
-    S.ln = nullptr;
-    S.lt = nullptr;
+    S.lw = nullptr;
     bool trav = false;
     L.corrupt = false;
     L.n_tris = 0;
@@ -907,15 +924,13 @@ __global__ __launch_bounds__(kBlock) void k_trace_persistent(
     float *__restrict__ out_range, int32_t *__restrict__ out_hit,
     int32_t *__restrict__ out_nodes, int32_t *__restrict__ out_tris)
 {
-    __shared__ int s_node[SS * kBlock];
-    __shared__ float s_t[SS * kBlock];
+    __shared__ uint64_t s_stk[SS > 0 ? SS * kBlock : 1];
     const int lane = threadIdx.x & 63;
     const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const unsigned long long n_waves = (unsigned long long)gridDim.x * (kBlock / 64);
     LaneRay L;
     LaneStack<SS, FMT == FMT_Q8 ? kStackQ8 : kStack, kBlock> S;
-    S.ln = s_node + threadIdx.x;
-    S.lt = s_t + threadIdx.x;
+    S.lw = s_stk + threadIdx.x;
     int xq = blockIdx.x % kQueues;
     bool exhausted = false;   // wave-uniform
     bool active = false;
