@@ -216,6 +216,7 @@ struct QemBuffers {
     uint8_t *cand_old;
     double *X_old;
     int32_t *eu, *ev;     // [3 nt] edge ends
+    int32_t *eu_old, *ev_old;   // the previous step's
     unsigned long long *best;   // [nv]
     int32_t *remap;       // [nv] contracted into (or -1)
     // [nv] in the closed one-rings of an edge contracted in the last step:
@@ -240,22 +241,25 @@ hipError_t qem_incidence_launch(const QemBuffers &b, int64_t nv, int64_t nt, int
                                 hipStream_t s);
 // Candidate keys and points of every edge (eoff must hold the exclusive
 // scan of nlarge, n_edges its total); counters[0] += candidates.  At a
-// round's start every edge is evaluated, else only those with a dirty end;
-// the others take their previous result (eoff_old, key_old, cand_old,
-// X_old) under their new number.
-hipError_t qem_edges_launch(const QemBuffers &b, int64_t nv, int64_t n_edges, int round_start,
-                            hipStream_t s);
-// Radix select of the rank-th smallest key (1-based) of n_edges keys.
-hipError_t qem_select_launch(const QemBuffers &b, int64_t n_edges, uint64_t rank, hipStream_t s);
+// round's start every edge is evaluated; later the n_old edges of the
+// previous step (eu_old, ev_old, eoff_old, key_old, cand_old, X_old) whose
+// lower end is clean move to their new numbers, keeping their result when
+// the upper end is clean too, and only edges with a dirty end are
+// evaluated.
+hipError_t qem_edges_launch(const QemBuffers &b, int64_t nv, int64_t n_edges, int64_t n_old,
+                            int round_start, hipStream_t s);
+// Eligibility: the need smallest candidate keys; all of them when need is
+// at least counters[0] (decided on the device), else a radix select of the
+// need-th smallest of the n_edges keys.
+hipError_t qem_select_launch(const QemBuffers &b, int64_t n_edges, uint64_t need, hipStream_t s);
 // counters[2] += live faces.
 hipError_t qem_live_launch(const QemBuffers &b, int64_t nt, hipStream_t s);
-// Contract the chosen edges among the eligible ones (all candidates when
-// `all`, else keys up to the selected one): u takes x and Q_u + Q_v, v's
+// Contract the chosen edges among the eligible ones (as qem_select_launch
+// left them): u takes x and Q_u + Q_v, v's
 // faces are renamed to u (the two on the edge dropped), the closed
 // one-rings are marked dirty (after clearing the marks); counters[1] +=
 // contractions, counters[2] += faces dropped.
-hipError_t qem_contract_launch(const QemBuffers &b, int64_t nv, int64_t n_edges, int all,
-                               hipStream_t s);
+hipError_t qem_contract_launch(const QemBuffers &b, int64_t nv, int64_t n_edges, hipStream_t s);
 // keep[t] = live face, used[v] = 1 for their corners (used zeroed first).
 hipError_t qem_used_launch(const int32_t *F, int64_t nt, uint32_t *used, uint32_t *keep,
                            hipStream_t s);

@@ -436,46 +436,67 @@ __device__ bool edge_candidate(const double *__restrict__ P, const int32_t *__re
     return true;
 }
 
-// Per vertex u: every edge (u, v > u) in ascending v, numbered from
-// eoff[u].  An edge whose two ends are clean keeps its previous result,
-// read at its previous number eoff_old[u] + j: its ends, their faces,
-// neighbours, positions and quadrics are all unchanged since then; the
-// key's low word becomes pi of the current number.  Any other edge (every
-// edge at a round's start) is marked for k_qem_eval (cand = 2).
-__global__ __launch_bounds__(kBlock) void k_qem_edges(
-    int64_t nv, const int32_t *__restrict__ nb, const int32_t *__restrict__ ndeg,
-    const uint32_t *__restrict__ eoff, const uint8_t *__restrict__ dirty, int full,
-    const uint32_t *__restrict__ eoff_old, const uint64_t *__restrict__ key_old,
-    const uint8_t *__restrict__ cand_old, const double *__restrict__ X_old,
-    uint64_t *__restrict__ key, uint8_t *__restrict__ cand, double *__restrict__ X,
-    int32_t *__restrict__ eu, int32_t *__restrict__ ev, uint32_t *__restrict__ counters)
+// Per vertex u with a dirty end role (every vertex at a round's start, else
+// the dirty ones): every edge (u, v > u) in ascending v, numbered from
+// eoff[u], is marked for k_qem_eval (cand = 2).
+__global__ __launch_bounds__(kBlock) void k_qem_edges(int64_t nv, const int32_t *__restrict__ nb,
+                                                      const int32_t *__restrict__ ndeg,
+                                                      const uint32_t *__restrict__ eoff,
+                                                      const uint8_t *__restrict__ dirty, int full,
+                                                      uint8_t *__restrict__ cand,
+                                                      int32_t *__restrict__ eu,
+                                                      int32_t *__restrict__ ev)
 {
-    const int64_t u0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t u = u0 < nv ? u0 : nv - 1;
-    const int nu = u0 < nv ? ndeg[u] : 0;
+    const int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (u >= nv || !(full || dirty[u])) return;
+    const int nu = ndeg[u];
     const int32_t *bu = nb + u * kQemNbrs;
-    const bool du = full || dirty[u];
     uint32_t e = eoff[u];
-    uint32_t eo = full ? 0u : eoff_old[u];
-    uint32_t found = 0;
     for (int k = 0; k < nu; ++k) {
         const int32_t v = bu[k];
         if (v <= (int32_t)u) continue;
         eu[e] = (int32_t)u;
         ev[e] = v;
-        if (du || dirty[v]) {
-            cand[e] = 2;
-        } else if (cand_old[eo]) {
-            for (int q = 0; q < 3; ++q) X[3 * (int64_t)e + q] = X_old[3 * (int64_t)eo + q];
-            key[e] = (key_old[eo] & 0xffffffff00000000ull) | perm32(e);
-            cand[e] = 1;
-            ++found;
-        } else {
-            key[e] = kNone;
-            cand[e] = 0;
-        }
+        cand[e] = 2;
         ++e;
-        ++eo;
+    }
+}
+
+// One thread per edge of the previous step whose lower end u is clean:
+// u's edges are the same, in the same order, so the edge moves from its
+// previous number to e - eoff_old[u] + eoff[u].  With v clean too its
+// result is unchanged (its ends, their faces, neighbours, positions and
+// quadrics are all as before) and only the key's low word becomes pi of
+// the new number; with v dirty it is marked for k_qem_eval.
+__global__ __launch_bounds__(kBlock) void k_qem_carry(
+    int64_t n_old, const int32_t *__restrict__ eu_old, const int32_t *__restrict__ ev_old,
+    const uint8_t *__restrict__ dirty, const uint32_t *__restrict__ eoff,
+    const uint32_t *__restrict__ eoff_old, const uint64_t *__restrict__ key_old,
+    const uint8_t *__restrict__ cand_old, const double *__restrict__ X_old,
+    uint64_t *__restrict__ key, uint8_t *__restrict__ cand, double *__restrict__ X,
+    int32_t *__restrict__ eu, int32_t *__restrict__ ev, uint32_t *__restrict__ counters)
+{
+    const int64_t eo = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    uint32_t found = 0;
+    if (eo < n_old) {
+        const int32_t u = eu_old[eo];
+        if (!dirty[u]) {
+            const int32_t v = ev_old[eo];
+            const uint32_t e = (uint32_t)eo - eoff_old[u] + eoff[u];
+            eu[e] = u;
+            ev[e] = v;
+            if (dirty[v]) {
+                cand[e] = 2;
+            } else if (cand_old[eo]) {
+                for (int q = 0; q < 3; ++q) X[3 * (int64_t)e + q] = X_old[3 * eo + q];
+                key[e] = (key_old[eo] & 0xffffffff00000000ull) | perm32(e);
+                cand[e] = 1;
+                found = 1;
+            } else {
+                key[e] = kNone;
+                cand[e] = 0;
+            }
+        }
     }
     block_add(found, &counters[0]);
 }
@@ -516,6 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_qem_eval(
 struct SelState {
     unsigned long long prefix, mask;
     unsigned long long rank;
+    unsigned long long all;   // every key is eligible: the passes do nothing
 };
 static_assert(offsetof(SelState, prefix) == 0, "the selected key is read at offset 0");
 
@@ -523,6 +545,7 @@ __global__ __launch_bounds__(kBlock) void k_qem_hist(const uint64_t *__restrict_
                                                      const SelState *__restrict__ st, int shift,
                                                      uint32_t *__restrict__ hist)
 {
+    if (st->all) return;
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -541,6 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_qem_hist(const uint64_t *__restrict_
 // LDS, one thread per digit; the counts are cleared for the next pass.
 __global__ __launch_bounds__(256) void k_qem_pick(SelState *st, uint32_t *hist, int shift)
 {
+    if (st->all) return;
     __shared__ unsigned long long c[256];
     const int i = threadIdx.x;
     const unsigned long long h = hist[i];
@@ -566,20 +590,20 @@ __global__ __launch_bounds__(256) void k_qem_pick(SelState *st, uint32_t *hist, 
 __global__ __launch_bounds__(kBlock) void k_qem_best(const uint64_t *__restrict__ key, int64_t n,
                                                      const int32_t *__restrict__ eu,
                                                      const int32_t *__restrict__ ev,
-                                                     const SelState *__restrict__ st, int all,
+                                                     const SelState *__restrict__ st,
                                                      unsigned long long *__restrict__ best)
 {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= n) return;
     const uint64_t k = key[e];
-    if (k == kNone || (!all && k > st->prefix)) return;
+    if (k == kNone || (!st->all && k > st->prefix)) return;
     atomicMin(&best[eu[e]], k);
     atomicMin(&best[ev[e]], k);
 }
 
 __global__ __launch_bounds__(kBlock) void k_qem_choose(
     const uint64_t *__restrict__ key, int64_t n, const int32_t *__restrict__ eu,
-    const int32_t *__restrict__ ev, const SelState *__restrict__ st, int all,
+    const int32_t *__restrict__ ev, const SelState *__restrict__ st,
     const unsigned long long *__restrict__ best, const int32_t *__restrict__ nb,
     const int32_t *__restrict__ ndeg, const double *__restrict__ X, double *__restrict__ P,
     const int32_t *__restrict__ fl, const int32_t *__restrict__ fdeg, int32_t *__restrict__ F,
@@ -588,7 +612,7 @@ __global__ __launch_bounds__(kBlock) void k_qem_choose(
 {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint64_t k = e < n ? key[e] : kNone;
-    bool ok = k != kNone && (all || k <= st->prefix);
+    bool ok = k != kNone && (st->all || k <= st->prefix);
     const int32_t u = ok ? eu[e] : 0, v = ok ? ev[e] : 0;
     ok = ok && best[u] >= k && best[v] >= k;
     uint32_t killed = 0;
@@ -696,6 +720,21 @@ __global__ void k_sel_init(SelState *st, unsigned long long rank, uint32_t *hist
         st->prefix = 0;
         st->mask = 0;
         st->rank = rank;
+        st->all = 0;
+    }
+    if (threadIdx.x < 256) hist[threadIdx.x] = 0;
+}
+
+// The need smallest candidate keys are eligible: all of them when need is
+// at least the candidate count (counters[0]), else a select of the need-th.
+__global__ void k_sel_init_need(SelState *st, unsigned long long need,
+                                const uint32_t *__restrict__ counters, uint32_t *hist)
+{
+    if (threadIdx.x == 0) {
+        st->prefix = 0;
+        st->mask = 0;
+        st->rank = need;
+        st->all = need >= (unsigned long long)counters[0] ? 1ull : 0ull;
     }
     if (threadIdx.x < 256) hist[threadIdx.x] = 0;
 }
@@ -732,12 +771,15 @@ hipError_t qem_incidence_launch(const QemBuffers &b, int64_t nv, int64_t nt, int
     return hipGetLastError();
 }
 
-hipError_t qem_edges_launch(const QemBuffers &b, int64_t nv, int64_t n_edges, int round_start,
-                            hipStream_t s)
+hipError_t qem_edges_launch(const QemBuffers &b, int64_t nv, int64_t n_edges, int64_t n_old,
+                            int round_start, hipStream_t s)
 {
+    if (!round_start && n_old > 0)
+        hipLaunchKernelGGL(k_qem_carry, dim3(grid_for(n_old, kBlock)), dim3(kBlock), 0, s, n_old,
+                           b.eu_old, b.ev_old, b.dirty, b.eoff, b.eoff_old, b.key_old, b.cand_old,
+                           b.X_old, b.key, b.cand, b.X, b.eu, b.ev, b.counters);
     hipLaunchKernelGGL(k_qem_edges, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, nv, b.nb,
-                       b.ndeg, b.eoff, b.dirty, round_start, b.eoff_old, b.key_old, b.cand_old,
-                       b.X_old, b.key, b.cand, b.X, b.eu, b.ev, b.counters);
+                       b.ndeg, b.eoff, b.dirty, round_start, b.cand, b.eu, b.ev);
     if (n_edges > 0)
         hipLaunchKernelGGL(k_qem_eval, dim3(grid_for(n_edges, kBlock)), dim3(kBlock), 0, s, b.P,
                            b.F, n_edges, b.fl, b.fdeg, b.nb, b.ndeg, b.Q, b.prot, b.eu, b.ev,
@@ -745,12 +787,9 @@ hipError_t qem_edges_launch(const QemBuffers &b, int64_t nv, int64_t n_edges, in
     return hipGetLastError();
 }
 
-hipError_t radix_select_u64_launch(const uint64_t *keys, int64_t n, uint64_t rank, char *state,
-                                   hipStream_t s)
+static hipError_t radix_passes(const uint64_t *keys, int64_t n, SelState *st, uint32_t *hist,
+                               hipStream_t s)
 {
-    SelState *st = reinterpret_cast<SelState *>(state);
-    uint32_t *hist = reinterpret_cast<uint32_t *>(state + sizeof(SelState));
-    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, st, (unsigned long long)rank, hist);
     unsigned g = grid_for(n, kBlock);
     if (g > 2048) g = 2048;
     if (g < 1) g = 1;
@@ -761,14 +800,27 @@ hipError_t radix_select_u64_launch(const uint64_t *keys, int64_t n, uint64_t ran
     return hipGetLastError();
 }
 
+hipError_t radix_select_u64_launch(const uint64_t *keys, int64_t n, uint64_t rank, char *state,
+                                   hipStream_t s)
+{
+    SelState *st = reinterpret_cast<SelState *>(state);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(state + sizeof(SelState));
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, st, (unsigned long long)rank, hist);
+    return radix_passes(keys, n, st, hist, s);
+}
+
 const uint64_t *radix_select_value(const char *state)
 {
     return reinterpret_cast<const uint64_t *>(state);   // SelState::prefix
 }
 
-hipError_t qem_select_launch(const QemBuffers &b, int64_t n_edges, uint64_t rank, hipStream_t s)
+hipError_t qem_select_launch(const QemBuffers &b, int64_t n_edges, uint64_t need, hipStream_t s)
 {
-    return radix_select_u64_launch(b.key, n_edges, rank, b.sel, s);
+    SelState *st = reinterpret_cast<SelState *>(b.sel);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(b.sel + sizeof(SelState));
+    hipLaunchKernelGGL(k_sel_init_need, dim3(1), dim3(256), 0, s, st, (unsigned long long)need,
+                       b.counters, hist);
+    return radix_passes(b.key, n_edges, st, hist, s);
 }
 
 hipError_t qem_live_launch(const QemBuffers &b, int64_t nt, hipStream_t s)
@@ -778,8 +830,7 @@ hipError_t qem_live_launch(const QemBuffers &b, int64_t nt, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t qem_contract_launch(const QemBuffers &b, int64_t nv, int64_t n_edges, int all,
-                               hipStream_t s)
+hipError_t qem_contract_launch(const QemBuffers &b, int64_t nv, int64_t n_edges, hipStream_t s)
 {
     const SelState *st = reinterpret_cast<const SelState *>(b.sel);
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nv, kBlock)), dim3(kBlock), 0, s, b.best, nv,
@@ -790,9 +841,9 @@ hipError_t qem_contract_launch(const QemBuffers &b, int64_t nv, int64_t n_edges,
                        (uint8_t)0);
     if (n_edges > 0) {
         hipLaunchKernelGGL(k_qem_best, dim3(grid_for(n_edges, kBlock)), dim3(kBlock), 0, s, b.key,
-                           n_edges, b.eu, b.ev, st, all, b.best);
+                           n_edges, b.eu, b.ev, st, b.best);
         hipLaunchKernelGGL(k_qem_choose, dim3(grid_for(n_edges, kBlock)), dim3(kBlock), 0, s,
-                           b.key, n_edges, b.eu, b.ev, st, all, b.best, b.nb, b.ndeg, b.X, b.P,
+                           b.key, n_edges, b.eu, b.ev, st, b.best, b.nb, b.ndeg, b.X, b.P,
                            b.fl, b.fdeg, b.F, b.Q, b.remap, b.dirty, b.absorbed, b.counters);
     }
     return hipGetLastError();

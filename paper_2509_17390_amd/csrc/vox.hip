@@ -1014,6 +1014,8 @@ rc_status rc_decimate_qem(rc_ctx *c, const float *verts, int64_t nv, const int32
     ws.take(&b.absorbed, sizeof(int32_t) * (size_t)nv);
     ws.take(&b.eu, sizeof(int32_t) * (size_t)ne_cap);
     ws.take(&b.ev, sizeof(int32_t) * (size_t)ne_cap);
+    ws.take(&b.eu_old, sizeof(int32_t) * (size_t)ne_cap);
+    ws.take(&b.ev_old, sizeof(int32_t) * (size_t)ne_cap);
     ws.take(&b.best, sizeof(unsigned long long) * (size_t)nv);
     ws.take(&b.remap, sizeof(int32_t) * (size_t)nv);
     ws.take(&b.counters, sizeof(uint32_t) * 4);
@@ -1042,6 +1044,7 @@ rc_status rc_decimate_qem(rc_ctx *c, const float *verts, int64_t nv, const int32
     HIP_TRY(hipStreamSynchronize(s));
     const int64_t f0 = hc[2];
     int64_t nf = f0;
+    int64_t n_old = 0;
     int32_t steps = 0;
     const double r = (double)ratio;
     for (int k = 1; k <= rounds; ++k) {
@@ -1053,6 +1056,8 @@ rc_status rc_decimate_qem(rc_ctx *c, const float *verts, int64_t nv, const int32
             std::swap(b.key, b.key_old);
             std::swap(b.cand, b.cand_old);
             std::swap(b.X, b.X_old);
+            std::swap(b.eu, b.eu_old);
+            std::swap(b.ev, b.ev_old);
             // incidence of the live faces (a round's start also sums the
             // quadrics and protects boundary vertices), edge numbering
             HIP_TRY(hipMemsetAsync(b.counters, 0, sizeof(uint32_t) * 4, s));
@@ -1069,17 +1074,17 @@ rc_status rc_decimate_qem(rc_ctx *c, const float *verts, int64_t nv, const int32
                                        kQemNbrs);
             // every edge lies on a live face: at most three per face
             if ((int64_t)n_edges > ne_cap) return fail(RC_E_DEVICE, "edge count overflow");
-            HIP_TRY(qem_edges_launch(b, nv, n_edges, first, s));
-            HIP_TRY(hipMemcpyAsync(hc, b.counters, sizeof hc, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            const uint64_t cands = hc[0];
-            if (cands == 0) break;
+            HIP_TRY(qem_edges_launch(b, nv, n_edges, n_old, first, s));
+            n_old = n_edges;
+            // candidates, eligibility and contraction without a host read in
+            // between: the select decides on the device whether every
+            // candidate is eligible, and no candidate contracts nothing
             const uint64_t need = (uint64_t)((nf - target + 1) / 2);
-            const int all = need >= cands ? 1 : 0;
-            if (!all) HIP_TRY(qem_select_launch(b, n_edges, need, s));
-            HIP_TRY(qem_contract_launch(b, nv, n_edges, all, s));
+            HIP_TRY(qem_select_launch(b, n_edges, need, s));
+            HIP_TRY(qem_contract_launch(b, nv, n_edges, s));
             HIP_TRY(hipMemcpyAsync(hc, b.counters, sizeof hc, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
+            if (hc[0] == 0) break;
             ++steps;
             if (hc[1] == 0) return fail(RC_E_DEVICE, "decimation step contracted nothing");
             // a contraction drops exactly the two faces on its edge
