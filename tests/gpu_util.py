@@ -122,8 +122,11 @@ def check_flagged(verts, tris, poses, dirs, t_min, t_max, ray_idx, t, ids, flags
                             for i in np.flatnonzero(far)[:10]])
     # a miss only where the oracle's hit is edge-near or at the range limits
     tol = TOL_ABS + TOL_REL * np.where(o_hit, np.abs(t), 0.0)
-    at_limit = o_hit & ((np.abs(t - t_min) <= tol) |
-                        (np.isfinite(t_max) & (np.abs(t - t_max) <= tol)))
+    # (a miss carries t = +inf, and t_max may be +inf: no inf - inf)
+    t_fin = np.where(o_hit, t, 0.0)
+    fin_max = np.isfinite(t_max)
+    near_max = fin_max & (np.abs(t_fin - np.where(fin_max, t_max, 0.0)) <= tol)
+    at_limit = o_hit & ((np.abs(t_fin - t_min) <= tol) | near_max)
     lost = flagged & o_hit & ~g_is_hit & ((flags & oracle.FLAG_EDGE_NEAR) == 0) & ~at_limit
     assert not lost.any(), ("flagged ray missed where the oracle hits",
                             [(int(i), float(t[i]), int(flags[i])) for i in np.flatnonzero(lost)[:10]])
