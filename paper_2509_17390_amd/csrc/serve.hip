@@ -231,6 +231,17 @@ void mock_loop(ServeState *Sp, int q)
             for (int64_t k = 0; k < 3 * m.nv; ++k) sum += m.verts[k];
             intact[i] = sum == m.sum;
         }
+        // the "kernel" has finished: drop the batch's scene references
+        // before its requests complete, as the device path's stream order
+        // does (c->mu is taken without S.mu)
+        {
+            std::vector<Scene *> held;
+            for (const Batch::MockJob &m : b->mock) held.push_back(m.sc);
+            rc_ctx *c = S.ctx;
+            drop_holds(c, held.data(), held.size());
+            std::lock_guard<std::mutex> clk(c->mu);
+            reap_locked(c);
+        }
         lk.lock();
         for (size_t i = 0; i < b->reqs.size(); ++i) {
             Request *r = b->reqs[i];
@@ -248,19 +259,7 @@ void mock_loop(ServeState *Sp, int q)
                 S.hit_buf[r->out_off + k] = r->req.scene;
             }
         }
-        std::vector<Scene *> held;
-        for (const Batch::MockJob &m : b->mock) held.push_back(m.sc);
         complete_batch_locked(S, b);
-        // the batch has finished: drop its scene references (S.mu is not
-        // held while c->mu is taken)
-        lk.unlock();
-        rc_ctx *c = S.ctx;
-        drop_holds(c, held.data(), held.size());
-        {
-            std::lock_guard<std::mutex> clk(c->mu);
-            reap_locked(c);
-        }
-        lk.lock();
     }
 }
 
