@@ -1266,14 +1266,14 @@ MIN_COMPONENT_FACES = 32
 # built (reads + writes of the dense arrays; neighbour re-reads hit the
 # caches): smoothing u8 -> u8 -> u16 -> V~ (kernels of up to 3 steps, as
 # here), labels packed to 2 bits, shells in bytes, phi float32, the
-# marching-cubes count writing mask and case bytes, the scans forming both
-# counts from those bytes (write two u32 offsets, then the tile-sum add
-# reads and writes them), and the emit pass reading mask and case (the
-# surface points' outputs are counted separately)
+# marching-cubes count writing mask and case bytes, the tile scan forming
+# both counts from those bytes and writing each point's u32 vertex offset
+# within its tile, and the emit pass reading mask and case (the surface
+# points' outputs are counted separately)
 TSDF_PASS_BYTES = {
     "smooth_x": 1 + 1, "smooth_y": 1 + 2, "smooth_z": 2 + 1, "pack": 1 + 0.25,
     "flood_sweep": 0.375, "shell0": 1 + 1, "shell": 1 + 1, "phi": 1 + 0.125 + 4,
-    "mc_count": 4 + 1 + 1, "mc_scans": 1 + 1 + 2 * 4 + 2 * (4 + 4), "mc_emit": 1 + 1,
+    "mc_count": 4 + 1 + 1, "mc_scans": 1 + 1 + 4, "mc_emit": 1 + 1,
 }
 
 

@@ -778,16 +778,18 @@ __device__ __forceinline__ void lattice_grad(const float *__restrict__ phi, cons
 }
 
 // Vertices and triangles of one lattice point with edge mask m and cell
-// case cs (nt triangles), into their canonical slots.
+// case cs (nt triangles), into their canonical slots: its first vertex is
+// v0 and its first triangle t0; a point q's first vertex is voff[q] (its
+// offset within its scan tile) + vbase[q / kScanTile].
 __device__ __forceinline__ void mc_emit_point(const float *__restrict__ phi, const TsdfGrid &g,
                                               float iso, const int8_t *__restrict__ tris_of,
                                               const uint8_t *__restrict__ mask,
                                               const uint32_t *__restrict__ voff,
-                                              const uint32_t *__restrict__ toff,
+                                              const uint32_t *__restrict__ vbase,
                                               float *__restrict__ verts,
                                               int32_t *__restrict__ tris,
                                               float *__restrict__ normals, int64_t i, int m,
-                                              int cs, int nt)
+                                              int cs, int nt, uint32_t v0, uint32_t t0)
 {
     int x, y, z;
     coords(i, g, x, y, z);
@@ -798,7 +800,7 @@ __device__ __forceinline__ void mc_emit_point(const float *__restrict__ phi, con
                             (float)(g.o[2] + ((double)z + 0.5) * g.h)};
         const float fa = phi[i];
         const int64_t step[3] = {1, sx, sxy};
-        uint32_t v = voff[i];
+        uint32_t v = v0;
         for (int a = 0; a < 3; ++a) {
             if (!((m >> a) & 1)) continue;
             const float fb = phi[i + step[a]];
@@ -831,7 +833,6 @@ __device__ __forceinline__ void mc_emit_point(const float *__restrict__ phi, con
         }
     }
     if (nt > 0) {
-        uint32_t t0 = toff[i];
         for (int k = 0; k < nt; ++k) {
             for (int e = 0; e < 3; ++e) {
                 const int edge = tris_of[cs * 15 + 3 * k + e];
@@ -843,7 +844,8 @@ __device__ __forceinline__ void mc_emit_point(const float *__restrict__ phi, con
                 const int64_t q = i + ((corner & 1) ? 1 : 0) + ((corner & 2) ? sx : 0) +
                                   ((corner & 4) ? sxy : 0);
                 const int mq = mask[q];
-                const uint32_t id = voff[q] + (uint32_t)__popc(mq & ((1 << axis) - 1));
+                const uint32_t id = voff[q] + vbase[q / kScanTile] +
+                                    (uint32_t)__popc(mq & ((1 << axis) - 1));
                 tris[3 * ((int64_t)t0 + k) + e] = (int32_t)id;
             }
         }
@@ -851,46 +853,6 @@ __device__ __forceinline__ void mc_emit_point(const float *__restrict__ phi, con
 }
 
 
-// Points with a vertex or a triangle are a small share of the grid, so
-// each block first scans kEmitPer points per thread (two byte loads each),
-// lists the active ones in LDS, and then all its threads emit the list:
-// one thread per point left most lanes idle through the dependent loads
-// of the few active ones.  Output slots come from the scans, so the order
-// of the list does not matter.
-constexpr int kEmitPer = 8;
-
-__global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ phi, TsdfGrid g,
-                                                    float iso, const uint8_t *__restrict__ ntri,
-                                                    const int8_t *__restrict__ tris_of,
-                                                    const uint8_t *__restrict__ mask,
-                                                    const uint8_t *__restrict__ cases,
-                                                    const uint32_t *__restrict__ voff,
-                                                    const uint32_t *__restrict__ toff,
-                                                    float *__restrict__ verts,
-                                                    int32_t *__restrict__ tris,
-                                                    float *__restrict__ normals)
-{
-    __shared__ uint32_t list[kBlock * kEmitPer];
-    __shared__ uint32_t nlist;
-    if (threadIdx.x == 0) nlist = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * (kBlock * kEmitPer);
-    for (int r = 0; r < kEmitPer; ++r) {
-        const int64_t i = base + r * kBlock + threadIdx.x;
-        if (i < g.n && (mask[i] != 0 || ntri[cases[i]] != 0))
-            list[atomicAdd(&nlist, 1u)] = (uint32_t)(i - base);
-    }
-    __syncthreads();
-    const uint32_t n = nlist;
-    for (uint32_t j = threadIdx.x; j < n; j += kBlock) {
-        const int64_t i = base + list[j];
-        const int cs = cases[i];
-        mc_emit_point(phi, g, iso, tris_of, mask, voff, toff, verts, tris, normals, i, mask[i], cs,
-                      ntri[cs]);
-    }
-}
-
-// ---- exclusive scan of uint32 (three kernels) ------------------------------
 __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *total)
 {
     __shared__ uint32_t ws[kBlock / 64];
@@ -911,6 +873,73 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *total)
     *total = tot;
     return off + x - v;
 }
+
+// Points with a vertex or a triangle are a small share of the grid, so
+// each block takes one scan tile (kScanItems consecutive points per
+// thread), lists the active points in LDS, and then all its threads emit
+// the list: one thread per point left most lanes idle through the
+// dependent loads of the few active ones.  The tile's triangle offsets
+// come from an in-block scan of its points' triangle counts (only the
+// point itself needs them); vertex offsets are per point in voff (offset
+// within the tile) plus the tile's base, since triangles also name the
+// vertices of neighbouring points.
+__global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ phi, TsdfGrid g,
+                                                    float iso, const uint8_t *__restrict__ ntri,
+                                                    const int8_t *__restrict__ tris_of,
+                                                    const uint8_t *__restrict__ mask,
+                                                    const uint8_t *__restrict__ cases,
+                                                    const uint32_t *__restrict__ voff,
+                                                    const uint32_t *__restrict__ vbase,
+                                                    const uint32_t *__restrict__ tbase,
+                                                    float *__restrict__ verts,
+                                                    int32_t *__restrict__ tris,
+                                                    float *__restrict__ normals)
+{
+    static_assert(kScanItems == 4, "one word of mask and case bytes per thread");
+    static_assert(kScanTile <= 1024 && 5 * kScanTile < (1 << 21), "list entry packing");
+    __shared__ uint8_t nt_lds[256];
+    __shared__ uint32_t list[kScanTile];     // point in tile | triangle offset << 10
+    __shared__ uint32_t nlist;
+    nt_lds[threadIdx.x] = ntri[threadIdx.x];              // kBlock == 256 cases
+    if (threadIdx.x == 0) nlist = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const int64_t p0 = base + (int64_t)threadIdx.x * kScanItems;
+    uint32_t mw = 0, cw = 0;
+    if (p0 + 4 <= g.n) {                                  // p0 is a multiple of 4
+        mw = *reinterpret_cast<const uint32_t *>(mask + p0);
+        cw = *reinterpret_cast<const uint32_t *>(cases + p0);
+    } else {
+        for (int k = 0; p0 + k < g.n && k < 4; ++k) {
+            mw |= (uint32_t)mask[p0 + k] << (8 * k);
+            cw |= (uint32_t)cases[p0 + k] << (8 * k);
+        }
+    }
+    uint32_t tc[kScanItems], st = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        tc[k] = p0 + k < g.n ? (uint32_t)nt_lds[(cw >> (8 * k)) & 0xffu] : 0u;
+        st += tc[k];
+    }
+    uint32_t tot;
+    uint32_t rt = block_scan_excl(st, &tot);
+    for (int k = 0; k < kScanItems; ++k) {
+        if (p0 + k < g.n && (((mw >> (8 * k)) & 0xffu) != 0u || tc[k] != 0u))
+            list[atomicAdd(&nlist, 1u)] = (uint32_t)(threadIdx.x * kScanItems + k) | (rt << 10);
+        rt += tc[k];
+    }
+    __syncthreads();
+    const uint32_t n = nlist;
+    const uint32_t vb = vbase[blockIdx.x], tb = tbase[blockIdx.x];
+    for (uint32_t j = threadIdx.x; j < n; j += kBlock) {
+        const uint32_t e = list[j];
+        const int64_t i = base + (e & 1023u);
+        const int cs = cases[i];
+        mc_emit_point(phi, g, iso, tris_of, mask, voff, vbase, verts, tris, normals, i, mask[i],
+                      cs, nt_lds[cs], voff[i] + vb, tb + (e >> 10));
+    }
+}
+
+// ---- exclusive scan of uint32 (three kernels) ------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_scan_tiles(const uint32_t *__restrict__ in,
                                                        uint32_t *__restrict__ out, int64_t n,
@@ -933,13 +962,13 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const uint32_t *__restric
 
 // Marching-cubes scan tiles: the vertex count (edges set in the mask) and
 // the triangle count (of the cell's case) of each point are formed here
-// from the count pass's two bytes, and both are scanned in one pass (two
-// u32 count arrays written and read back cost 16 bytes per point).
+// from the count pass's two bytes; each point gets its vertex offset within
+// the tile, and the tile its two totals (the emit pass scans the triangle
+// counts of its tile again, since only the point itself needs them).
 __global__ __launch_bounds__(kBlock) void k_mc_scan_tiles(const uint8_t *__restrict__ mask,
                                                           const uint8_t *__restrict__ cases,
                                                           const uint8_t *__restrict__ ntri,
                                                           int64_t n, uint32_t *__restrict__ voff,
-                                                          uint32_t *__restrict__ toff,
                                                           uint32_t *__restrict__ vsums,
                                                           uint32_t *__restrict__ tsums)
 {
@@ -968,18 +997,97 @@ __global__ __launch_bounds__(kBlock) void k_mc_scan_tiles(const uint8_t *__restr
     }
     uint32_t totv, tott;
     uint32_t rv = block_scan_excl(sv, &totv);
-    uint32_t rt = block_scan_excl(st, &tott);
+    (void)block_scan_excl(st, &tott);
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) {
-            voff[base + k] = rv;
-            toff[base + k] = rt;
-        }
+        if (base + k < n) voff[base + k] = rv;
         rv += vc[k];
-        rt += tc[k];
     }
     if (threadIdx.x == 0) {
         vsums[blockIdx.x] = totv;
         tsums[blockIdx.x] = tott;
+    }
+}
+
+// One 1024-thread block: exclusive scans of the vertex and the triangle
+// tile totals in place, grand totals after them.
+constexpr int kSums2Block = 1024;
+
+__device__ __forceinline__ uint32_t block_scan_excl_1024(uint32_t v, uint32_t *total,
+                                                         uint32_t *ws)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) ws[w] = x;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int k = 0; k < kSums2Block / 64; ++k) {
+        if (k < w) off += ws[k];
+        tot += ws[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+// Chunks of kSums2Chunk entries of both arrays go through LDS: loaded and
+// stored coalesced, scanned there with eight consecutive entries per
+// thread (one block on one CU: per-thread contiguous global reads were
+// uncoalesced and took 95 us for 32k tiles).
+constexpr int kSums2Chunk = kSums2Block * 8;
+
+__global__ __launch_bounds__(kSums2Block) void k_scan_sums2(uint32_t *__restrict__ a,
+                                                            uint32_t *__restrict__ b, int nb)
+{
+    __shared__ uint32_t la[kSums2Chunk], lb[kSums2Chunk];
+    __shared__ uint32_t ws[kSums2Block / 64];
+    uint32_t carry_a = 0, carry_b = 0;
+    for (int c0 = 0; c0 < nb; c0 += kSums2Chunk) {
+        const int m = nb - c0 < kSums2Chunk ? nb - c0 : kSums2Chunk;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = k * kSums2Block + (int)threadIdx.x;
+            la[i] = i < m ? a[c0 + i] : 0u;
+            lb[i] = i < m ? b[c0 + i] : 0u;
+        }
+        __syncthreads();
+        uint32_t va[8], vb[8], sa = 0, sb = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            va[k] = la[8 * threadIdx.x + k];
+            vb[k] = lb[8 * threadIdx.x + k];
+            sa += va[k];
+            sb += vb[k];
+        }
+        uint32_t ta, tb;
+        uint32_t ra = carry_a + block_scan_excl_1024(sa, &ta, ws);
+        uint32_t rb = carry_b + block_scan_excl_1024(sb, &tb, ws);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            la[8 * threadIdx.x + k] = ra;
+            lb[8 * threadIdx.x + k] = rb;
+            ra += va[k];
+            rb += vb[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = k * kSums2Block + (int)threadIdx.x;
+            if (i < m) {
+                a[c0 + i] = la[i];
+                b[c0 + i] = lb[i];
+            }
+        }
+        carry_a += ta;
+        carry_b += tb;
+        __syncthreads();   // la / lb are refilled by the next chunk
+    }
+    if (threadIdx.x == 0) {
+        a[nb] = carry_a;
+        b[nb] = carry_b;
     }
 }
 
@@ -1330,28 +1438,25 @@ hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint64_t *O, uint8_t 
 }
 
 hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
-                           uint8_t *mask, uint8_t *cases, uint32_t *voff, uint32_t *toff,
-                           uint32_t *vsums, uint32_t *tsums, hipStream_t s)
+                           uint8_t *mask, uint8_t *cases, uint32_t *voff, uint32_t *vsums,
+                           uint32_t *tsums, hipStream_t s)
 {
     hipLaunchKernelGGL(k_mc_count4, dim3(grid_for((g.n + 3) / 4, kBlock)), dim3(kBlock), 0, s, phi,
                        g, iso, mask, cases);
     const int64_t nb = (g.n + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_mc_scan_tiles, dim3((unsigned)nb), dim3(kBlock), 0, s, mask, cases, ntri,
-                       g.n, voff, toff, vsums, tsums);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, vsums, (int)nb);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, tsums, (int)nb);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kBlock), 0, s, voff, g.n, vsums);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kBlock), 0, s, toff, g.n, tsums);
+                       g.n, voff, vsums, tsums);
+    hipLaunchKernelGGL(k_scan_sums2, dim3(1), dim3(kSums2Block), 0, s, vsums, tsums, (int)nb);
     return hipGetLastError();
 }
 
 hipError_t mc_emit_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
                           const int8_t *tris_of, const uint8_t *mask, const uint8_t *cases,
-                          const uint32_t *voff, const uint32_t *toff, float *verts, int32_t *tris,
-                          float *normals, hipStream_t s)
+                          const uint32_t *voff, const uint32_t *vsums, const uint32_t *tsums,
+                          float *verts, int32_t *tris, float *normals, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mc_emit, dim3(grid_for(g.n, kBlock * kEmitPer)), dim3(kBlock), 0, s, phi,
-                       g, iso, ntri, tris_of, mask, cases, voff, toff, verts, tris, normals);
+    hipLaunchKernelGGL(k_mc_emit, dim3(grid_for(g.n, kScanTile)), dim3(kBlock), 0, s, phi, g, iso,
+                       ntri, tris_of, mask, cases, voff, vsums, tsums, verts, tris, normals);
     return hipGetLastError();
 }
 

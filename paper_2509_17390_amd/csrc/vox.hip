@@ -400,7 +400,11 @@ struct Scratch {
 
 }  // namespace
 
-constexpr int kFloodBatch = 6;   // outside-labelling rounds enqueued per flag read
+// Outside-labelling rounds enqueued per flag read: 6 first (the usual
+// masks settle in 5 to 10 rounds), then 2, 4 and 8 at a time, so that few
+// rounds run after the fixed point and a slow mask still costs few reads.
+constexpr int kFloodBatchMax = 8;
+inline int flood_batch(int k) { return k == 0 ? 6 : (k == 1 ? 2 : (k == 2 ? 4 : 8)); }
 
 rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_tsdf_opts *opts,
                   float *out_phi, uint8_t *out_vtilde, void *stream)
@@ -464,7 +468,7 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
     ws.take(&fw, sizeof(uint64_t) * nwords);
     ws.take(&ow, sizeof(uint64_t) * nwords);
     ws.take(&seg, sizeof(uint64_t) * 5 * tsdf_seg_words(g));
-    ws.take(&flag, sizeof(int32_t) * kFloodBatch);
+    ws.take(&flag, sizeof(int32_t) * kFloodBatchMax);
     uint64_t *sums = nullptr;
     char *sel = nullptr;
     if (quant) {
@@ -482,18 +486,20 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
         HIP_TRY(tsdf_smooth_launch(surf, a, b, vt, g, w, thr, s));
     }
     HIP_TRY(tsdf_pack_launch(vt, fw, ow, g, s));
-    // rounds until one changes nothing, enqueued kFloodBatch at a time with
-    // one flag read per batch: a round after a round that changed nothing
-    // returns at once, and repeating a settled round changes nothing
-    for (int64_t it = 0;; it += kFloodBatch) {
-        int32_t changed[kFloodBatch];
-        HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int32_t) * kFloodBatch, s));
-        for (int r = 0; r < kFloodBatch; ++r)
+    // rounds until one changes nothing, enqueued in batches with one flag
+    // read per batch: a round after a round that changed nothing returns at
+    // once, and repeating a settled round changes nothing
+    for (int64_t it = 0, k = 0;; ++k) {
+        const int nb = flood_batch((int)(k < 3 ? k : 3));
+        int32_t changed[kFloodBatchMax];
+        HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int32_t) * nb, s));
+        for (int r = 0; r < nb; ++r)
             HIP_TRY(tsdf_flood_round_launch(fw, ow, seg, g, r ? flag + r - 1 : nullptr, flag + r,
                                             s));
-        HIP_TRY(hipMemcpyAsync(changed, flag, sizeof changed, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(changed, flag, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        if (!changed[kFloodBatch - 1]) break;
+        if (!changed[nb - 1]) break;
+        it += nb;
         if (it > g.n) return fail(RC_E_DEVICE, "outside labelling did not settle");
     }
     HIP_TRY(tsdf_shells_phi_launch(vt, ow, p, out_phi, g, shells, g.hf, r, s));
@@ -535,17 +541,16 @@ rc_status rc_marching_cubes(rc_ctx *c, const rc_grid *grid, const float *phi, fl
     std::lock_guard<std::mutex> lk(c->mesh_mu);
     Scratch ws(c);
     uint8_t *mask, *cases;
-    uint32_t *voff, *toff, *vs, *ts;
+    uint32_t *voff, *vs, *ts;
     const int64_t ns = mc_scan_sums_len(g.n);
     ws.take(&mask, g.n);
     ws.take(&cases, g.n);
     ws.take(&voff, sizeof(uint32_t) * g.n);
-    ws.take(&toff, sizeof(uint32_t) * g.n);
     ws.take(&vs, sizeof(uint32_t) * ns);
     ws.take(&ts, sizeof(uint32_t) * ns);
     st = ws.commit();
     if (st != RC_OK) return st;
-    HIP_TRY(mc_count_launch(phi, g, iso, ntri, mask, cases, voff, toff, vs, ts, s));
+    HIP_TRY(mc_count_launch(phi, g, iso, ntri, mask, cases, voff, vs, ts, s));
     uint32_t tot[2];
     HIP_TRY(hipMemcpyAsync(&tot[0], vs + ns - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&tot[1], ts + ns - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -555,7 +560,7 @@ rc_status rc_marching_cubes(rc_ctx *c, const rc_grid *grid, const float *phi, fl
     if (!out_verts) return RC_OK;
     if (cap_verts < (int64_t)tot[0] || cap_tris < (int64_t)tot[1])
         return fail(RC_E_NOMEM, "mesh needs %u vertices and %u triangles", tot[0], tot[1]);
-    HIP_TRY(mc_emit_launch(phi, g, iso, ntri, tris_of, mask, cases, voff, toff, out_verts,
+    HIP_TRY(mc_emit_launch(phi, g, iso, ntri, tris_of, mask, cases, voff, vs, ts, out_verts,
                            out_tris, out_normals, s));
     HIP_TRY(hipStreamSynchronize(s));
     return RC_OK;

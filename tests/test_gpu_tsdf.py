@@ -312,3 +312,25 @@ def test_mc_step_rejects_zero(ctx):
     with pytest.raises(rcast.RcastError) as e:
         ctx.marching_cubes(g, cuda(surf), 0.0, step=0)
     assert e.value.status == rcast.RC_E_INVAL
+
+
+def test_marching_cubes_many_scan_tiles(ctx):
+    # 9.2M lattice points: 9,000 scan tiles of 1,024 points, more than the
+    # 8,192 tile totals one LDS chunk of the tile-offset scan holds, so the
+    # scan carries its running totals across chunks; two spheres, compared
+    # bit for bit with the oracle's float32 evaluation
+    import torch
+    nz, ny, nx = 96, 300, 320
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    phi = (np.minimum(np.sqrt((x - 100.3) ** 2 + (y - 150.2) ** 2 + (z - 48.1) ** 2) - 40.7,
+                      np.sqrt((x - 230.6) ** 2 + (y - 120.4) ** 2 + (z - 50.3) ** 2) - 35.2)
+           * 0.01).astype(np.float32)
+    g = ctx.grid((0.0, 0.0, 0.0), 0.01, (nx, ny, nz), 0.0)
+    log(f"marching cubes on {phi.size} points")
+    vg, tg, ng = ctx.marching_cubes(g, torch.from_numpy(phi).cuda(), 0.0, normals=True)
+    torch.cuda.synchronize()
+    vo, to, no = ot.marching_cubes(phi, (0.0, 0.0, 0.0), 0.01, 0.0, normals=True)
+    assert len(to) > 100_000
+    np.testing.assert_array_equal(tg.cpu().numpy(), to)
+    np.testing.assert_array_equal(vg.cpu().numpy().view(np.uint32), vo.view(np.uint32))
+    np.testing.assert_array_equal(ng.cpu().numpy().view(np.uint32), no.view(np.uint32))
