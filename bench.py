@@ -1263,18 +1263,31 @@ def run_voxelize(args):
 MIN_COMPONENT_FACES = 32
 
 # Narrow-band TSDF + marching cubes: HBM bytes per voxel of each pass as
-# built (reads + writes of the dense arrays; neighbour re-reads hit the
-# caches): smoothing u8 -> u8 -> u16 -> V~ (kernels of up to 3 steps, as
-# here), labels packed to 2 bits, shells in bytes, phi float32, the
-# marching-cubes count writing mask and case bytes, the tile scan forming
-# both counts from those bytes and writing each point's u32 vertex offset
-# within its tile, and the emit pass reading mask and case (the surface
-# points' outputs are counted separately)
+# built (reads + writes of the dense arrays; neighbour and tile-halo
+# re-reads hit the caches): smoothing u8 -> u8 -> u16 -> V~ (kernels of up
+# to 3 steps, as here), labels packed to 2 bits, then for bands of at most
+# 4 shells one tiled pass from V~ and the outside bits to phi float32 (S_0
+# and the shells stay in LDS; wider bands: S_0 and each shell as byte
+# passes, then phi), the marching-cubes count writing mask and case bytes,
+# the tile scan forming both counts from those bytes and writing each
+# point's u32 vertex offset within its tile, and the emit pass reading mask
+# and case (the surface points' outputs are counted separately)
 TSDF_PASS_BYTES = {
     "smooth_x": 1 + 1, "smooth_y": 1 + 2, "smooth_z": 2 + 1, "pack": 1 + 0.25,
-    "flood_sweep": 0.375, "shell0": 1 + 1, "shell": 1 + 1, "phi": 1 + 0.125 + 4,
+    "flood_sweep": 0.375, "shells_phi_tiled": 1 + 0.125 + 4,
+    "shell0": 1 + 1, "shell": 1 + 1, "phi": 1 + 0.125 + 4,
     "mc_count": 4 + 1 + 1, "mc_scans": 1 + 1 + 4, "mc_emit": 1 + 1,
 }
+
+
+def tsdf_bytes_per_voxel(shells: int) -> float:
+    """Bytes per voxel of TSDF_PASS_BYTES for a band of `shells` shells."""
+    b = TSDF_PASS_BYTES
+    common = sum(v for k, v in b.items()
+                 if k not in ("shells_phi_tiled", "shell0", "shell", "phi"))
+    if shells <= 4:
+        return common + b["shells_phi_tiled"]
+    return common + b["shell0"] + shells * b["shell"] + b["phi"]
 
 
 def mesh_properties(v0, t0, v1, t1):
@@ -1435,8 +1448,7 @@ def run_mesh(args):
     # iterations of the outside labelling are not visible from here: count
     # the passes as one sweep (a lower bound of the bytes)
     P = int(np.ceil(float(np.float32(band)) / float(np.float32(grid.h))))
-    per_vox = (sum(v for k, v in TSDF_PASS_BYTES.items() if k != "shell")
-               + P * TSDF_PASS_BYTES["shell"])
+    per_vox = tsdf_bytes_per_voxel(P)
     # outputs: 12 B position + 12 B normal per vertex, 12 B per triangle
     alg_bytes = int(per_vox * n_vox) + 24 * int(verts.shape[0]) + 12 * int(tris.shape[0])
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9

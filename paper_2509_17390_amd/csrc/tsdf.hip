@@ -8,13 +8,14 @@
 //           rounds of line sweeps along x, y and z (one thread per line,
 //           spreading along whole free runs) until a round changes nothing
 //   S_0   = voxels with a 6-neighbour of the other V~ value (frame = free)
-//   p     = shell index of a 6-neighbour expansion from S_0, one launch per
-//           shell up to ceil(r / h)
+//   p     = shell index of a 6-neighbour expansion from S_0, up to ceil(r / h)
+//           shells: for at most 4, S_0, the shells and phi in one pass over
+//           LDS tiles; else one launch each
 //   phi   = clip(s p h, -r, r), s = +1 on O, -1 elsewhere
 //   mesh  = marching cubes of phi at iso on the voxel-centre lattice:
 //           per point, count crossed lattice edges (one vertex each) and the
-//           triangles of the cell it anchors; exclusive scans give every
-//           vertex and triangle its slot; a second pass writes them.  The case
+//           triangles of the cell it anchors; tile scans give every vertex
+//           and triangle its slot; a second pass writes them.  The case
 //           table is built on the host from a walk over the cube's faces.
 #include "mesh_internal.h"
 
@@ -665,6 +666,120 @@ __global__ __launch_bounds__(kBlock) void k_shell(uint8_t *__restrict__ p, TsdfG
         if (hit) out = (out & ~(0xffu << (8 * j))) | ((uint32_t)m << (8 * j));
     }
     if (out != c) *reinterpret_cast<uint32_t *>(p + i0) = out;
+}
+
+// S_0, the P <= 4 shells and phi in one pass over LDS tiles.  A block
+// owns a 64 x 8 x 8 tile of voxels and loads V~ over it with a halo of
+// P + 1 voxels in y and z and 8 in x (two LDS words: the tile's rows stay
+// word aligned), then runs in LDS what the per-grid passes above do: S_0,
+// then P shell steps, four voxels per 32-bit word with bytewise tests.
+// The values of a step are correct wherever the previous step's were
+// correct one voxel further in, so after P steps they are correct on the
+// tile itself; voxels outside the grid read V~ = 0 and hold a p that never
+// equals a shell index m - 1 < 4 and is never overwritten.  phi is written
+// from the tile's p with the same operations as k_phi, so the results are
+// the same bits; p never goes to memory.  V~ is 0 or 1 (the threshold
+// pass's output).
+constexpr int kShTX = 64, kShTY = 8, kShTZ = 8, kShHX = 8;
+
+// 0xff in each byte of v that is zero, 0 elsewhere (exact, no carries
+// between bytes)
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t v)
+{
+    uint32_t t = (v & 0x7f7f7f7fu) + 0x7f7f7f7fu;
+    t = ~(t | v | 0x7f7f7f7fu);
+    return (t >> 7) * 0xffu;
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_shells_phi_tile(const uint8_t *__restrict__ vt,
+                                                            const uint64_t *__restrict__ O,
+                                                            float *__restrict__ phi, TsdfGrid g,
+                                                            int W, float h, float r)
+{
+    static_assert(P >= 1 && P <= 4 && P + 1 <= kShHX, "tile halo");
+    constexpr int H = P + 1;
+    constexpr int LX = kShTX + 2 * kShHX, WX = LX / 4;
+    constexpr int LY = kShTY + 2 * H, LZ = kShTZ + 2 * H;
+    constexpr int NW = WX * LY * LZ, SY = WX, SZ = WX * LY;
+    // one byte per voxel: V~ (0 or 1) in bit 7, p in bits 0..6 with 0x7f
+    // for "not reached" (255 of the per-grid passes) and 0x7e outside the
+    // grid; S_0 reads only bit 7 and writes only bits 0..6, so it runs in
+    // place
+    constexpr uint32_t kHi = 0x80808080u, kLo = 0x7f7f7f7fu;
+    __shared__ uint32_t T[NW];
+    const int x0 = (int)blockIdx.x * kShTX - kShHX;
+    const int y0 = (int)blockIdx.y * kShTY - H, z0 = (int)blockIdx.z * kShTZ - H;
+    for (int w = threadIdx.x; w < NW; w += kBlock) {
+        const int wx = w % WX, t = w / WX, ly = t % LY, lz = t / LY;
+        const int gx = x0 + 4 * wx, gy = y0 + ly, gz = z0 + lz;
+        uint32_t v = 0x7e7e7e7eu;
+        if (gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz) {
+            const int64_t row = ((int64_t)gz * g.ny + gy) * g.nx;
+            for (int j = 0; j < 4; ++j)
+                if (gx + j >= 0 && gx + j < g.nx)
+                    v = (v & ~(0xffu << (8 * j))) | ((vt[row + gx + j] ? 0x80u : 0x00u) << (8 * j));
+        }
+        T[w] = v;
+    }
+    __syncthreads();
+    // interior words: every 6-neighbour of their voxels lies in the tile
+    constexpr int IX = WX - 2, IY = LY - 2, IZ = LZ - 2;
+    // a thread keeps one (word, row) column and walks it along z
+    for (int q = threadIdx.x; q < IX * IY; q += kBlock) {
+        int w = (LY + 1 + q / IX) * WX + 1 + q % IX;   // lz = 1
+        for (int lz = 1; lz <= IZ; ++lz, w += SZ) {
+            const uint32_t c = T[w];
+            const uint32_t xm = __builtin_amdgcn_alignbyte(c, T[w - 1], 3u);
+            const uint32_t xp = __builtin_amdgcn_alignbyte(T[w + 1], c, 1u);
+            const uint32_t d = ((c ^ xm) | (c ^ xp) | (c ^ T[w - SY]) | (c ^ T[w + SY]) |
+                                (c ^ T[w - SZ]) | (c ^ T[w + SZ])) & kHi;
+            // in-grid bytes (low bits 0x7f after the load: 0x00 or 0x80 there)
+            const uint32_t in = zero_bytes(c & kLo);
+            const uint32_t p = zero_bytes(d) & kLo;   // 0x7f: no neighbour differs; 0: S_0
+            T[w] = (c & kHi) | (p & in) | (0x7e7e7e7eu & ~in);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 1; m <= P; ++m) {
+        const uint32_t prev = (uint32_t)(m - 1) * 0x01010101u;
+        for (int q = threadIdx.x; q < IX * IY; q += kBlock) {
+          int w = (LY + 1 + q / IX) * WX + 1 + q % IX;   // lz = 1
+          for (int lz = 1; lz <= IZ; ++lz, w += SZ) {
+            const uint32_t c = T[w];
+            const uint32_t live = zero_bytes((c & kLo) ^ kLo);   // not reached yet
+            if (!live) continue;
+            const uint32_t xm = __builtin_amdgcn_alignbyte(c, T[w - 1], 3u);
+            const uint32_t xp = __builtin_amdgcn_alignbyte(T[w + 1], c, 1u);
+            const uint32_t hit = zero_bytes((xm & kLo) ^ prev) | zero_bytes((xp & kLo) ^ prev) |
+                                 zero_bytes((T[w - SY] & kLo) ^ prev) |
+                                 zero_bytes((T[w + SY] & kLo) ^ prev) |
+                                 zero_bytes((T[w - SZ] & kLo) ^ prev) |
+                                 zero_bytes((T[w + SZ] & kLo) ^ prev);
+            const uint32_t set = live & hit & kLo;
+            // 0x7f becomes m: a neighbour read before or after this store
+            // sees a value other than m - 1 either way
+            if (set) T[w] = (c & ~set) | (((uint32_t)m * 0x01010101u) & set);
+          }
+        }
+        __syncthreads();
+    }
+    static_assert(kBlock % kShTX == 0, "whole rows per round");
+    const int lx = (int)threadIdx.x % kShTX;
+    const int gx = (int)blockIdx.x * kShTX + lx;
+    for (int t = (int)threadIdx.x / kShTX; t < kShTY * kShTZ; t += kBlock / kShTX) {
+        const int ly = t % kShTY, lz = t / kShTY;
+        const int gy = (int)blockIdx.y * kShTY + ly, gz = (int)blockIdx.z * kShTZ + lz;
+        if (gx >= g.nx || gy >= g.ny || gz >= g.nz) continue;
+        const int cx = kShHX + lx;
+        const uint32_t pj = byte_of(T[((H + lz) * LY + H + ly) * WX + (cx >> 2)], cx & 3) & 0x7fu;
+        const int64_t row = (int64_t)gz * g.ny + gy;
+        const bool out = (O[row * W + (gx >> 6)] >> (gx & 63)) & 1ull;
+        const float delta = pj == 0x7fu ? r : (float)pj * h;
+        const float sg = out ? delta : -delta;
+        phi[row * g.nx + gx] = fminf(fmaxf(sg, -r), r);
+    }
 }
 
 // phi = clip(s p h, -r, r); s = +1 where the packed outside bit is set.
@@ -1424,6 +1539,18 @@ int64_t tsdf_shell_pad(const TsdfGrid &g) { return (((int64_t)g.nx * g.ny + 8) +
 hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint64_t *O, uint8_t *p, float *phi,
                                   const TsdfGrid &g, int shells, float h, float r, hipStream_t s)
 {
+    if (shells >= 1 && shells <= 4) {
+        const dim3 tiles((unsigned)((g.nx + kShTX - 1) / kShTX), (unsigned)((g.ny + kShTY - 1) / kShTY),
+                         (unsigned)((g.nz + kShTZ - 1) / kShTZ));
+        const int W = tsdf_words_per_row(g);
+        switch (shells) {
+        case 1: hipLaunchKernelGGL(k_shells_phi_tile<1>, tiles, dim3(kBlock), 0, s, vt, O, phi, g, W, h, r); break;
+        case 2: hipLaunchKernelGGL(k_shells_phi_tile<2>, tiles, dim3(kBlock), 0, s, vt, O, phi, g, W, h, r); break;
+        case 3: hipLaunchKernelGGL(k_shells_phi_tile<3>, tiles, dim3(kBlock), 0, s, vt, O, phi, g, W, h, r); break;
+        default: hipLaunchKernelGGL(k_shells_phi_tile<4>, tiles, dim3(kBlock), 0, s, vt, O, phi, g, W, h, r); break;
+        }
+        return hipGetLastError();
+    }
     const unsigned grid = grid_for(g.n, kBlock);
     const unsigned grid4 = grid_for((g.n + 3) / 4, kBlock);
     if (((uintptr_t)vt & 3) == 0)
