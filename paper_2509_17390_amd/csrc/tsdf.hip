@@ -814,61 +814,68 @@ __global__ __launch_bounds__(kBlock) void k_phi(const uint8_t *__restrict__ p,
 
 // ---- marching cubes --------------------------------------------------------
 // Count pass, per lattice point: mask of crossed edges +x/+y/+z (bits 0..2)
-// and vertex count; the case of the cell it anchors (bit k set when corner
-// k = (k & 1, k >> 1 & 1, k >> 2 & 1) is inside, phi < iso) and that case's
-// triangle count.
+// and the case of the cell it anchors (bit k set when corner k = (k & 1,
+// k >> 1 & 1, k >> 2 & 1) is inside, phi < iso), one byte each; the vertex
+// and triangle counts follow from them.
+// Over 64 x 4 x 4 tiles: a block loads the inside bits of its tile plus
+// one point further along each axis into LDS (each phi read once per tile,
+// about 1.6x over the grid), then each thread takes four consecutive
+// points of a row from LDS.  Points whose +x, +y or +z
+// neighbour lies outside the grid never use it (the coordinate tests), so
+// those LDS bytes are only placeholders.
+constexpr int kMcTX = 64, kMcTY = 4, kMcTZ = 4;
 
-// Four consecutive points per thread: the inside bits of the 4 x 5 window of rows (y, z), (y + 1, z), (y, z + 1), (y + 1, z + 1)
-// serve all four (20 loads where four separate points make 44).  Points
-// whose +x neighbour lies on the next row never use it: the coordinate
-// tests exclude them, and indices at or past n are never loaded.
-__global__ __launch_bounds__(kBlock) void k_mc_count4(const float *__restrict__ phi, TsdfGrid g,
-                                                      float iso, uint8_t *__restrict__ mask,
-                                                      uint8_t *__restrict__ cases)
+__global__ __launch_bounds__(kBlock) void k_mc_count_tile(const float *__restrict__ phi,
+                                                          TsdfGrid g, float iso,
+                                                          uint8_t *__restrict__ mask,
+                                                          uint8_t *__restrict__ cases)
 {
-    const int64_t i0 = 4 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
-    if (i0 >= g.n) return;
-    const int64_t sx = g.nx, sxy = (int64_t)g.nx * g.ny;
-    const int64_t off[4] = {0, sx, sxy, sx + sxy};
-    uint32_t bits[4];                          // bit k: phi[i0 + off + k] < iso
+    constexpr int LX = kMcTX + 1, LY = kMcTY + 1, LZ = kMcTZ + 1, NL = LX * LY * LZ;
+    static_assert((kMcTX / 4) * kMcTY * kMcTZ == kBlock, "four points per thread");
+    __shared__ uint8_t ins[NL];
+    const int bx = (int)blockIdx.x * kMcTX, by = (int)blockIdx.y * kMcTY;
+    const int bz = (int)blockIdx.z * kMcTZ;
+    constexpr int PER = (NL + kBlock - 1) / kBlock;
+    uint8_t v[PER];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        uint32_t b = 0;
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const int64_t q = i0 + off[r] + k;
-            if (q < g.n && phi[q] < iso) b |= 1u << k;
-        }
-        bits[r] = b;
+    for (int k = 0; k < PER; ++k) {
+        const int q = (int)threadIdx.x + k * kBlock;
+        const int lx = q % LX, t = q / LX, ly = t % LY, lz = t / LY;
+        const int gx = bx + lx, gy = by + ly, gz = bz + lz;
+        v[k] = q < NL && gx < g.nx && gy < g.ny && gz < g.nz &&
+                       phi[((int64_t)gz * g.ny + gy) * g.nx + gx] < iso
+                   ? 1
+                   : 0;
     }
-    int x, y, z;
-    coords(i0, g, x, y, z);
-    uint32_t mw = 0, cw = 0;
 #pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int q = (int)threadIdx.x + k * kBlock;
+        if (q < NL) ins[q] = v[k];
+    }
+    __syncthreads();
+    const int lx0 = ((int)threadIdx.x % (kMcTX / 4)) * 4;
+    const int t = (int)threadIdx.x / (kMcTX / 4), ly = t % kMcTY, lz = t / kMcTY;
+    const int gy = by + ly, gz = bz + lz;
+    if (gy >= g.ny || gz >= g.nz) return;
+    const int64_t row = ((int64_t)gz * g.ny + gy) * g.nx;
     for (int j = 0; j < 4; ++j) {
-        const bool in = (bits[0] >> j) & 1u;
+        const int lx = lx0 + j, gx = bx + lx;
+        if (gx >= g.nx) break;
+        const uint8_t *c = ins + (lz * LY + ly) * LX + lx;
+        const int in = c[0];
         int m = 0;
-        if (x < g.nx - 1 && (bool)((bits[0] >> (j + 1)) & 1u) != in) m |= 1;
-        if (y < g.ny - 1 && (bool)((bits[1] >> j) & 1u) != in) m |= 2;
-        if (z < g.nz - 1 && (bool)((bits[2] >> j) & 1u) != in) m |= 4;
+        if (gx < g.nx - 1 && c[1] != in) m |= 1;
+        if (gy < g.ny - 1 && c[LX] != in) m |= 2;
+        if (gz < g.nz - 1 && c[LX * LY] != in) m |= 4;
         int cs = 0;
-        if (x < g.nx - 1 && y < g.ny - 1 && z < g.nz - 1) {
-            // corner k = (k & 1, k >> 1 & 1, k >> 2 & 1): row (k >> 1), column j + (k & 1)
+        if (gx < g.nx - 1 && gy < g.ny - 1 && gz < g.nz - 1) {
+            // corner k = (k & 1, k >> 1 & 1, k >> 2 & 1)
 #pragma unroll
-            for (int k = 0; k < 8; ++k) cs |= (int)((bits[k >> 1] >> (j + (k & 1))) & 1u) << k;
+            for (int k = 0; k < 8; ++k)
+                cs |= (int)c[(k & 1) + ((k >> 1) & 1) * LX + ((k >> 2) & 1) * LX * LY] << k;
         }
-        mw |= (uint32_t)m << (8 * j);
-        cw |= (uint32_t)cs << (8 * j);
-        step_voxel(g, x, y, z);
-    }
-    if (i0 + 4 <= g.n) {
-        *reinterpret_cast<uint32_t *>(mask + i0) = mw;
-        *reinterpret_cast<uint32_t *>(cases + i0) = cw;
-    } else {
-        for (int j = 0; i0 + j < g.n; ++j) {
-            mask[i0 + j] = (uint8_t)(mw >> (8 * j));
-            cases[i0 + j] = (uint8_t)(cw >> (8 * j));
-        }
+        mask[row + gx] = (uint8_t)m;
+        cases[row + gx] = (uint8_t)cs;
     }
 }
 
@@ -1568,8 +1575,9 @@ hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const
                            uint8_t *mask, uint8_t *cases, uint32_t *voff, uint32_t *vsums,
                            uint32_t *tsums, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mc_count4, dim3(grid_for((g.n + 3) / 4, kBlock)), dim3(kBlock), 0, s, phi,
-                       g, iso, mask, cases);
+    const dim3 tiles((unsigned)((g.nx + kMcTX - 1) / kMcTX), (unsigned)((g.ny + kMcTY - 1) / kMcTY),
+                     (unsigned)((g.nz + kMcTZ - 1) / kMcTZ));
+    hipLaunchKernelGGL(k_mc_count_tile, tiles, dim3(kBlock), 0, s, phi, g, iso, mask, cases);
     const int64_t nb = (g.n + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_mc_scan_tiles, dim3((unsigned)nb), dim3(kBlock), 0, s, mask, cases, ntri,
                        g.n, voff, vsums, tsums);
