@@ -1264,8 +1264,10 @@ MIN_COMPONENT_FACES = 32
 
 # Narrow-band TSDF + marching cubes: HBM bytes per voxel of each pass as
 # built (reads + writes of the dense arrays; neighbour and tile-halo
-# re-reads hit the caches): smoothing u8 -> u8 -> u16 -> V~ (kernels of up
-# to 3 steps, as here), labels packed to 2 bits, then for bands of at most
+# re-reads hit the caches): for kernels of 1 to 3 steps (as here) and the
+# fixed threshold one tiled pass from the mask to V~ and the packed free
+# bits (else smoothing u8 -> u8 -> u16 -> V~ and the packing to 2-bit
+# labels as passes of their own), then for bands of at most
 # 4 shells one tiled pass from V~ and the outside bits to phi float32 (S_0
 # and the shells stay in LDS; wider bands: S_0 and each shell as byte
 # passes, then phi), the marching-cubes count writing mask and case bytes,
@@ -1273,6 +1275,7 @@ MIN_COMPONENT_FACES = 32
 # point's u32 vertex offset within its tile, and the emit pass reading mask
 # and case (the surface points' outputs are counted separately)
 TSDF_PASS_BYTES = {
+    "smooth_pack_tiled": 1 + 1 + 0.25,
     "smooth_x": 1 + 1, "smooth_y": 1 + 2, "smooth_z": 2 + 1, "pack": 1 + 0.25,
     "flood_sweep": 0.375, "shells_phi_tiled": 1 + 0.125 + 4,
     "shell0": 1 + 1, "shell": 1 + 1, "phi": 1 + 0.125 + 4,
@@ -1280,14 +1283,18 @@ TSDF_PASS_BYTES = {
 }
 
 
-def tsdf_bytes_per_voxel(shells: int) -> float:
-    """Bytes per voxel of TSDF_PASS_BYTES for a band of `shells` shells."""
+def tsdf_bytes_per_voxel(shells: int, steps: int, quantile: bool = False) -> float:
+    """Bytes per voxel of TSDF_PASS_BYTES for a band of `shells` shells and a
+    smoothing kernel of `steps` steps."""
     b = TSDF_PASS_BYTES
-    common = sum(v for k, v in b.items()
-                 if k not in ("shells_phi_tiled", "shell0", "shell", "phi"))
+    total = b["flood_sweep"] + b["mc_count"] + b["mc_scans"] + b["mc_emit"]
+    if 1 <= steps <= 3 and not quantile:
+        total += b["smooth_pack_tiled"]
+    else:
+        total += b["smooth_x"] + b["smooth_y"] + b["smooth_z"] + b["pack"]
     if shells <= 4:
-        return common + b["shells_phi_tiled"]
-    return common + b["shell0"] + shells * b["shell"] + b["phi"]
+        return total + b["shells_phi_tiled"]
+    return total + b["shell0"] + shells * b["shell"] + b["phi"]
 
 
 def mesh_properties(v0, t0, v1, t1):
@@ -1448,7 +1455,9 @@ def run_mesh(args):
     # iterations of the outside labelling are not visible from here: count
     # the passes as one sweep (a lower bound of the bytes)
     P = int(np.ceil(float(np.float32(band)) / float(np.float32(grid.h))))
-    per_vox = tsdf_bytes_per_voxel(P)
+    sv = float(np.float32(sigma)) / float(np.float32(grid.h))
+    steps = max(1, int(np.floor(2.0 * sv * sv + 0.5)))
+    per_vox = tsdf_bytes_per_voxel(P, steps)
     # outputs: 12 B position + 12 B normal per vertex, 12 B per triangle
     alg_bytes = int(per_vox * n_vox) + 24 * int(verts.shape[0]) + 12 * int(tris.shape[0])
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9

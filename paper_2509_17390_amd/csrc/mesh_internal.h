@@ -56,6 +56,12 @@ hipError_t mc_stride_gather_launch(const float *phi, const TsdfGrid &g, int step
 // (*changed set when O grew).
 int tsdf_words_per_row(const TsdfGrid &g);
 int64_t tsdf_seg_words(const TsdfGrid &g);
+// Smoothing, threshold and packing in one tiled pass (V~ into vt, the free
+// and cleared outside words into F and O), for kernels of 1 to 3 steps.
+bool tsdf_smooth_pack_fused(const Binomial &w);
+hipError_t tsdf_smooth_pack_launch(const uint8_t *surf, uint8_t *vt, uint64_t *F, uint64_t *O,
+                                   const TsdfGrid &g, const Binomial &w, uint64_t thr,
+                                   hipStream_t s);
 hipError_t tsdf_pack_launch(const uint8_t *vt, uint64_t *F, uint64_t *O, const TsdfGrid &g,
                             hipStream_t s);
 // A round whose `prev` flag (the previous round's *changed; null: always

@@ -281,6 +281,84 @@ __global__ __launch_bounds__(kBlock) void k_smooth_z4(const uint8_t *__restrict_
     }
 }
 
+// Smoothing, threshold and packing in one pass over 64 x 8 x 8 tiles, for
+// kernels of at most 3 steps: a block loads the surface bytes over its tile
+// with a halo of n voxels (0 outside the grid, which is what the per-grid
+// passes' skipped taps add), forms the x sums (u8), the x-y sums (u16) and
+// the full sums in LDS in the same integer arithmetic, writes V~ and, one
+// wave per row, the row's free word (the tile's 64 columns are one word)
+// with a clear outside word.
+constexpr int kSmTX = 64, kSmTY = 8, kSmTZ = 8;
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_smooth_pack_tile(const uint8_t *__restrict__ surf,
+                                                             uint8_t *__restrict__ vt, TsdfGrid g,
+                                                             Binomial w, uint64_t thr, int W,
+                                                             uint64_t *__restrict__ F,
+                                                             uint64_t *__restrict__ O)
+{
+    static_assert(N >= 1 && N <= 3, "u8 x sums: at most 2^(2N) <= 64");
+    constexpr int SX = kSmTX + 2 * N, SY = kSmTY + 2 * N, SZ = kSmTZ + 2 * N;
+    constexpr int NS = SX * SY * SZ;                      // surface bytes
+    constexpr int NA = kSmTX * SY * SZ;                   // x sums, u8
+    constexpr int NB = kSmTX * kSmTY * SZ;                // x-y sums, u16
+    constexpr int R1 = NS > 2 * NB ? NS : 2 * NB;
+    // the surface bytes are dead once the x sums exist: the x-y sums reuse
+    // their space
+    __shared__ __align__(16) uint8_t r1[R1];
+    __shared__ uint8_t A[NA];
+    uint8_t *S = r1;
+    uint16_t *B = reinterpret_cast<uint16_t *>(r1);
+    const int bx = (int)blockIdx.x * kSmTX, by = (int)blockIdx.y * kSmTY;
+    const int bz = (int)blockIdx.z * kSmTZ;
+    for (int q = threadIdx.x; q < NS; q += kBlock) {
+        const int lx = q % SX, t = q / SX, ly = t % SY, lz = t / SY;
+        const int gx = bx - N + lx, gy = by - N + ly, gz = bz - N + lz;
+        uint8_t v = 0;
+        if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz)
+            v = surf[((int64_t)gz * g.ny + gy) * g.nx + gx] != 0 ? 1 : 0;
+        S[q] = v;
+    }
+    __syncthreads();
+    const int lx = (int)threadIdx.x % kSmTX, r0 = (int)threadIdx.x / kSmTX;
+    constexpr int RPI = kBlock / kSmTX;                   // rows per round
+    for (int r = r0; r < SY * SZ; r += RPI) {             // row (ly, lz) of the halo'd tile
+        const uint8_t *src = S + r * SX + lx;
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k <= 2 * N; ++k) sum += w.w[k] * src[k];
+        A[r * kSmTX + lx] = (uint8_t)sum;
+    }
+    __syncthreads();
+    for (int r = r0; r < kSmTY * SZ; r += RPI) {          // ly in [0, TY), lz in [0, SZ)
+        const int ly = r % kSmTY, lz = r / kSmTY;
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k <= 2 * N; ++k) sum += w.w[k] * A[(lz * SY + ly + k) * kSmTX + lx];
+        B[r * kSmTX + lx] = (uint16_t)sum;
+    }
+    __syncthreads();
+    const int gx = bx + lx;
+    for (int r = r0; r < kSmTY * kSmTZ; r += RPI) {       // one wave per output row
+        const int ly = r % kSmTY, lz = r / kSmTY;
+        const int gy = by + ly, gz = bz + lz;
+        if (gy >= g.ny || gz >= g.nz) continue;           // the whole wave
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k <= 2 * N; ++k)
+            sum += w.w[k] * B[((lz + k) * kSmTY + ly) * kSmTX + lx];
+        const bool in = gx < g.nx;
+        const bool v = in && (uint64_t)sum >= thr;
+        const int64_t row = (int64_t)gz * g.ny + gy;
+        if (in) vt[row * g.nx + gx] = v ? 1 : 0;
+        const uint64_t f = __ballot(in && !v);
+        if (lx == 0) {
+            F[row * W + blockIdx.x] = f;
+            O[row * W + blockIdx.x] = 0;
+        }
+    }
+}
+
 // ---- outside labelling -----------------------------------------------------
 // Bit-packed along x: word (z, y, wx) holds voxels x = 64 wx .. 64 wx + 63
 // of row (y, z); F = free (V~ = 0), O = known to be outside; bits beyond
@@ -1497,6 +1575,24 @@ int64_t tsdf_seg_words(const TsdfGrid &g)
     const Cols a = cols_of(g, 1), b = cols_of(g, 2);
     const int64_t na = a.ncols * a.nseg, nb = b.ncols * b.nseg;
     return na > nb ? na : nb;
+}
+
+bool tsdf_smooth_pack_fused(const Binomial &w) { return w.n >= 1 && w.n <= 3; }
+
+hipError_t tsdf_smooth_pack_launch(const uint8_t *surf, uint8_t *vt, uint64_t *F, uint64_t *O,
+                                   const TsdfGrid &g, const Binomial &w, uint64_t thr,
+                                   hipStream_t s)
+{
+    const dim3 tiles((unsigned)((g.nx + kSmTX - 1) / kSmTX), (unsigned)((g.ny + kSmTY - 1) / kSmTY),
+                     (unsigned)((g.nz + kSmTZ - 1) / kSmTZ));
+    const int W = tsdf_words_per_row(g);
+    switch (w.n) {
+    case 1: hipLaunchKernelGGL(k_smooth_pack_tile<1>, tiles, dim3(kBlock), 0, s, surf, vt, g, w, thr, W, F, O); break;
+    case 2: hipLaunchKernelGGL(k_smooth_pack_tile<2>, tiles, dim3(kBlock), 0, s, surf, vt, g, w, thr, W, F, O); break;
+    case 3: hipLaunchKernelGGL(k_smooth_pack_tile<3>, tiles, dim3(kBlock), 0, s, surf, vt, g, w, thr, W, F, O); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t tsdf_pack_launch(const uint8_t *vt, uint64_t *F, uint64_t *O, const TsdfGrid &g,

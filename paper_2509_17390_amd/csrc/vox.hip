@@ -482,10 +482,13 @@ rc_status rc_tsdf(rc_ctx *c, const rc_grid *grid, const uint8_t *surf, const rc_
         HIP_TRY(tsdf_smooth_sums_launch(surf, a, b, sums, g, w, s));
         HIP_TRY(radix_select_u64_launch(sums, g.n, q_rank, sel, s));
         HIP_TRY(tsdf_threshold_launch(sums, radix_select_value(sel), vt, g.n, s));
+        HIP_TRY(tsdf_pack_launch(vt, fw, ow, g, s));
+    } else if (tsdf_smooth_pack_fused(w)) {
+        HIP_TRY(tsdf_smooth_pack_launch(surf, vt, fw, ow, g, w, thr, s));
     } else {
         HIP_TRY(tsdf_smooth_launch(surf, a, b, vt, g, w, thr, s));
+        HIP_TRY(tsdf_pack_launch(vt, fw, ow, g, s));
     }
-    HIP_TRY(tsdf_pack_launch(vt, fw, ow, g, s));
     // rounds until one changes nothing, enqueued in batches with one flag
     // read per batch: a round after a round that changed nothing returns at
     // once, and repeating a settled round changes nothing

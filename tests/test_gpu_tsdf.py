@@ -83,7 +83,9 @@ def check_mc(ctx, phi, g, origin, h, iso, tag=""):
 def test_random_masks(ctx, seed):
     rng = np.random.default_rng(seed)
     surf = (rng.random((19, 23, 29)) < 0.15).astype(np.uint8)
-    for sigma, tau, band in ((0.02, 0.05, 0.06), (0.035, 0.2, 0.1), (0.01, 0.5, 0.02)):
+    # smoothing of n = 2, 6, 1 and 3 steps (the tiled pass takes 1..3)
+    for sigma, tau, band in ((0.02, 0.05, 0.06), (0.035, 0.2, 0.1), (0.01, 0.5, 0.02),
+                             (0.025, 0.15, 0.08)):
         phi, g = check_tsdf(ctx, surf, (0.1, -0.2, 0.3), 0.02, sigma, tau, band,
                             tag=f"random {seed} sigma {sigma}")
         check_mc(ctx, phi, g, (0.1, -0.2, 0.3), 0.02, 0.0, tag=f"random {seed} mc")
