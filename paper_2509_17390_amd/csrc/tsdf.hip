@@ -977,81 +977,75 @@ __device__ __forceinline__ void lattice_grad(const float *__restrict__ phi, cons
     out[2] = lattice_diff(phi, i, z, g.nz, (int64_t)g.nx * g.ny);
 }
 
-// Vertices and triangles of one lattice point with edge mask m and cell
-// case cs (nt triangles), into their canonical slots: its first vertex is
-// v0 and its first triangle t0; a point q's first vertex is voff[q] (its
-// offset within its scan tile) + vbase[q / kScanTile].
-__device__ __forceinline__ void mc_emit_point(const float *__restrict__ phi, const TsdfGrid &g,
-                                              float iso, const int8_t *__restrict__ tris_of,
-                                              const uint8_t *__restrict__ mask,
-                                              const uint32_t *__restrict__ voff,
-                                              const uint32_t *__restrict__ vbase,
-                                              float *__restrict__ verts,
-                                              int32_t *__restrict__ tris,
-                                              float *__restrict__ normals, int64_t i, int m,
-                                              int cs, int nt, uint32_t v0, uint32_t t0)
+// The vertex on edge `a` (0: +x, 1: +y, 2: +z) of lattice point i, into
+// slot v: the crossing of iso by linear interpolation along the edge, and
+// with normals the normalised interpolation of the lattice gradients at the
+// edge's ends.
+__device__ __forceinline__ void mc_emit_vertex(const float *__restrict__ phi, const TsdfGrid &g,
+                                               float iso, float *__restrict__ verts,
+                                               float *__restrict__ normals, int64_t i, int a,
+                                               uint32_t v)
 {
     int x, y, z;
     coords(i, g, x, y, z);
-    const int64_t sx = g.nx, sxy = (int64_t)g.nx * g.ny;
-    if (m) {
-        const float c[3] = {(float)(g.o[0] + ((double)x + 0.5) * g.h),
-                            (float)(g.o[1] + ((double)y + 0.5) * g.h),
-                            (float)(g.o[2] + ((double)z + 0.5) * g.h)};
-        const float fa = phi[i];
-        const int64_t step[3] = {1, sx, sxy};
-        uint32_t v = v0;
-        for (int a = 0; a < 3; ++a) {
-            if (!((m >> a) & 1)) continue;
-            const float fb = phi[i + step[a]];
-            const float t = __fdiv_rn(iso - fa, fb - fa);
-            float p[3] = {c[0], c[1], c[2]};
-            p[a] = __fadd_rn(c[a], __fmul_rn(t, g.hf));
-            verts[3 * (int64_t)v + 0] = p[0];
-            verts[3 * (int64_t)v + 1] = p[1];
-            verts[3 * (int64_t)v + 2] = p[2];
-            if (normals) {
-                // n = (1 - t) g_a + t g_b, normalised; float32, one rounded
-                // operation at a time
-                float ga[3], gb[3];
-                lattice_grad(phi, g, i, x, y, z, ga);
-                lattice_grad(phi, g, i + step[a], x + (a == 0), y + (a == 1), z + (a == 2), gb);
-                const float w = __fsub_rn(1.0f, t);
-                float nv[3];
-                for (int k = 0; k < 3; ++k)
-                    nv[k] = __fadd_rn(__fmul_rn(w, ga[k]), __fmul_rn(t, gb[k]));
-                const float l2 = __fadd_rn(__fadd_rn(__fmul_rn(nv[0], nv[0]), __fmul_rn(nv[1], nv[1])),
-                                           __fmul_rn(nv[2], nv[2]));
-                // correctly rounded float32 square root: the FP64 root
-                // rounded to float32 (53 >= 2 * 24 + 2 bits, so the double
-                // rounding is exact); v_sqrt_f32 alone is not exact
-                const float l = (float)sqrt((double)l2);
-                for (int k = 0; k < 3; ++k)
-                    normals[3 * (int64_t)v + k] = l > 0.0f ? __fdiv_rn(nv[k], l) : 0.0f;
-            }
-            ++v;
-        }
-    }
-    if (nt > 0) {
-        for (int k = 0; k < nt; ++k) {
-            for (int e = 0; e < 3; ++e) {
-                const int edge = tris_of[cs * 15 + 3 * k + e];
-                // edges are numbered (axis, lower corner): 4 per axis
-                const int axis = edge >> 2, nth = edge & 3;
-                // the nth corner (ascending) whose bit `axis` is clear
-                const int lo = nth & ((1 << axis) - 1);
-                const int corner = ((nth >> axis) << (axis + 1)) | lo;
-                const int64_t q = i + ((corner & 1) ? 1 : 0) + ((corner & 2) ? sx : 0) +
-                                  ((corner & 4) ? sxy : 0);
-                const int mq = mask[q];
-                const uint32_t id = voff[q] + vbase[q / kScanTile] +
-                                    (uint32_t)__popc(mq & ((1 << axis) - 1));
-                tris[3 * ((int64_t)t0 + k) + e] = (int32_t)id;
-            }
-        }
+    const float c0 = (float)(g.o[0] + ((double)x + 0.5) * g.h);
+    const float c1 = (float)(g.o[1] + ((double)y + 0.5) * g.h);
+    const float c2 = (float)(g.o[2] + ((double)z + 0.5) * g.h);
+    const int64_t step = a == 0 ? 1 : (a == 1 ? (int64_t)g.nx : (int64_t)g.nx * g.ny);
+    const float fa = phi[i], fb = phi[i + step];
+    const float t = __fdiv_rn(iso - fa, fb - fa);
+    const float pa = __fadd_rn(a == 0 ? c0 : (a == 1 ? c1 : c2), __fmul_rn(t, g.hf));
+    verts[3 * (int64_t)v + 0] = a == 0 ? pa : c0;
+    verts[3 * (int64_t)v + 1] = a == 1 ? pa : c1;
+    verts[3 * (int64_t)v + 2] = a == 2 ? pa : c2;
+    if (normals) {
+        // n = (1 - t) g_a + t g_b, normalised; float32, one rounded
+        // operation at a time
+        float ga[3], gb[3];
+        lattice_grad(phi, g, i, x, y, z, ga);
+        lattice_grad(phi, g, i + step, x + (a == 0), y + (a == 1), z + (a == 2), gb);
+        const float w = __fsub_rn(1.0f, t);
+        float nv[3];
+        for (int k = 0; k < 3; ++k)
+            nv[k] = __fadd_rn(__fmul_rn(w, ga[k]), __fmul_rn(t, gb[k]));
+        const float l2 = __fadd_rn(__fadd_rn(__fmul_rn(nv[0], nv[0]), __fmul_rn(nv[1], nv[1])),
+                                   __fmul_rn(nv[2], nv[2]));
+        // correctly rounded float32 square root: the FP64 root rounded to
+        // float32 (53 >= 2 * 24 + 2 bits, so the double rounding is exact);
+        // v_sqrt_f32 alone is not exact
+        const float l = (float)sqrt((double)l2);
+        for (int k = 0; k < 3; ++k)
+            normals[3 * (int64_t)v + k] = l > 0.0f ? __fdiv_rn(nv[k], l) : 0.0f;
     }
 }
 
+// Triangle k of the cell at lattice point i (case cs), into slot t: its
+// corners are the vertices of the cell edges the case table names; a point
+// q's first vertex is voff[q] (its offset within its scan tile) +
+// vbase[q / kScanTile], and its edges' vertices follow in axis order.
+__device__ __forceinline__ void mc_emit_tri(const TsdfGrid &g, const int8_t *__restrict__ tris_of,
+                                            const uint8_t *__restrict__ mask,
+                                            const uint32_t *__restrict__ voff,
+                                            const uint32_t *__restrict__ vbase,
+                                            int32_t *__restrict__ tris, int64_t i, int cs, int k,
+                                            uint32_t t)
+{
+    const int64_t sx = g.nx, sxy = (int64_t)g.nx * g.ny;
+    for (int e = 0; e < 3; ++e) {
+        const int edge = tris_of[cs * 15 + 3 * k + e];
+        // edges are numbered (axis, lower corner): 4 per axis
+        const int axis = edge >> 2, nth = edge & 3;
+        // the nth corner (ascending) whose bit `axis` is clear
+        const int lo = nth & ((1 << axis) - 1);
+        const int corner = ((nth >> axis) << (axis + 1)) | lo;
+        const int64_t q = i + ((corner & 1) ? 1 : 0) + ((corner & 2) ? sx : 0) +
+                          ((corner & 4) ? sxy : 0);
+        const int mq = mask[q];
+        const uint32_t id = voff[q] + vbase[q / kScanTile] +
+                            (uint32_t)__popc(mq & ((1 << axis) - 1));
+        tris[3 * (int64_t)t + e] = (int32_t)id;
+    }
+}
 
 __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *total)
 {
@@ -1074,15 +1068,13 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *total)
     return off + x - v;
 }
 
-// Points with a vertex or a triangle are a small share of the grid, so
-// each block takes one scan tile (kScanItems consecutive points per
-// thread), lists the active points in LDS, and then all its threads emit
-// the list: one thread per point left most lanes idle through the
-// dependent loads of the few active ones.  The tile's triangle offsets
-// come from an in-block scan of its points' triangle counts (only the
-// point itself needs them); vertex offsets are per point in voff (offset
-// within the tile) plus the tile's base, since triangles also name the
-// vertices of neighbouring points.
+// One block per scan tile.  Points with a vertex or a triangle are a small
+// share of the grid and need different amounts of work (0 to 3 vertices, 0
+// to 5 triangles), so the block lists the tile's vertices, then its
+// triangles, as items in LDS, in slot order (the slots come from an
+// in-block scan of the per-point counts, the same offsets the count pass
+// stored), and each thread emits one item at a time: every lane runs the
+// same code on every item.
 __global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ phi, TsdfGrid g,
                                                     float iso, const uint8_t *__restrict__ ntri,
                                                     const int8_t *__restrict__ tris_of,
@@ -1096,12 +1088,12 @@ __global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ ph
                                                     float *__restrict__ normals)
 {
     static_assert(kScanItems == 4, "one word of mask and case bytes per thread");
-    static_assert(kScanTile <= 1024 && 5 * kScanTile < (1 << 21), "list entry packing");
+    static_assert(kScanTile == 1024, "item packing: point in tile in bits 0..9");
     __shared__ uint8_t nt_lds[256];
-    __shared__ uint32_t list[kScanTile];     // point in tile | triangle offset << 10
-    __shared__ uint32_t nlist;
+    // vertex items (point | axis << 10), then triangle items (point |
+    // k << 10 | case << 13): at most 3 and 5 per point
+    __shared__ uint32_t items[5 * kScanTile];
     nt_lds[threadIdx.x] = ntri[threadIdx.x];              // kBlock == 256 cases
-    if (threadIdx.x == 0) nlist = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     const int64_t p0 = base + (int64_t)threadIdx.x * kScanItems;
@@ -1115,27 +1107,40 @@ __global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ ph
             cw |= (uint32_t)cases[p0 + k] << (8 * k);
         }
     }
-    uint32_t tc[kScanItems], st = 0;
+    uint32_t tc[kScanItems], sv = 0, st = 0;
     for (int k = 0; k < kScanItems; ++k) {
         tc[k] = p0 + k < g.n ? (uint32_t)nt_lds[(cw >> (8 * k)) & 0xffu] : 0u;
         st += tc[k];
+        sv += (uint32_t)__popc((mw >> (8 * k)) & 7u);
     }
+    // both counts in one scan: a tile has at most 3072 vertices, so they
+    // stay in the low 16 bits
     uint32_t tot;
-    uint32_t rt = block_scan_excl(st, &tot);
+    const uint32_t r = block_scan_excl(sv | (st << 16), &tot);
+    const uint32_t nv = tot & 0xffffu, ntr = tot >> 16;
+    uint32_t rv = r & 0xffffu, rt = r >> 16;
+    const uint32_t lp = threadIdx.x * kScanItems;
     for (int k = 0; k < kScanItems; ++k) {
-        if (p0 + k < g.n && (((mw >> (8 * k)) & 0xffu) != 0u || tc[k] != 0u))
-            list[atomicAdd(&nlist, 1u)] = (uint32_t)(threadIdx.x * kScanItems + k) | (rt << 10);
-        rt += tc[k];
+        const uint32_t m = (mw >> (8 * k)) & 7u;
+        for (int a = 0; a < 3; ++a)
+            if ((m >> a) & 1u) items[rv++] = (lp + k) | ((uint32_t)a << 10);
     }
     __syncthreads();
-    const uint32_t n = nlist;
     const uint32_t vb = vbase[blockIdx.x], tb = tbase[blockIdx.x];
-    for (uint32_t j = threadIdx.x; j < n; j += kBlock) {
-        const uint32_t e = list[j];
-        const int64_t i = base + (e & 1023u);
-        const int cs = cases[i];
-        mc_emit_point(phi, g, iso, tris_of, mask, voff, vbase, verts, tris, normals, i, mask[i],
-                      cs, nt_lds[cs], voff[i] + vb, tb + (e >> 10));
+    for (uint32_t j = threadIdx.x; j < nv; j += kBlock) {
+        const uint32_t e = items[j];
+        mc_emit_vertex(phi, g, iso, verts, normals, base + (e & 1023u), (int)(e >> 10), vb + j);
+    }
+    __syncthreads();
+    for (int k = 0; k < kScanItems; ++k) {
+        const uint32_t cs = (cw >> (8 * k)) & 0xffu;
+        for (uint32_t q = 0; q < tc[k]; ++q) items[rt++] = (lp + k) | (q << 10) | (cs << 13);
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < ntr; j += kBlock) {
+        const uint32_t e = items[j];
+        mc_emit_tri(g, tris_of, mask, voff, vbase, tris, base + (e & 1023u), (int)(e >> 13),
+                    (int)((e >> 10) & 7u), tb + j);
     }
 }
 
