@@ -629,6 +629,98 @@ __global__ __launch_bounds__(kBlock) void k_seg_apply(const uint64_t *__restrict
     if (any && *changed == 0) *changed = 1;
 }
 
+// (1) to (3) in one kernel, for columns of at most kFusedSegs segments: a
+// block takes cj adjacent columns (threads column-fastest, so the words of
+// one row are read together; cj * nseg <= kBlock), keeps each segment's
+// words in registers, and one thread per column chains the summaries
+// through LDS into the carries; the same recurrences as the three kernels,
+// without two launches and the summary and carry arrays.
+constexpr int kFusedSegs = 32;
+
+template <int AXIS>
+__global__ __launch_bounds__(kBlock) void k_seg_fused(const uint64_t *__restrict__ F,
+                                                      uint64_t *__restrict__ O, TsdfGrid g,
+                                                      int W, Cols cl, int cj,
+                                                      int32_t *__restrict__ changed,
+                                                      const int32_t *__restrict__ skip)
+{
+    // a round enqueued after the labelling settled does nothing
+    if (skip && *skip == 0) return;
+
+    __shared__ uint64_t sA[kBlock], sB[kBlock], sT[kBlock];
+    const int j = (int)threadIdx.x % cj, sg = (int)threadIdx.x / cj;
+    const int64_t c = (int64_t)blockIdx.x * cj + j;
+    const bool act = sg < cl.nseg && c < cl.ncols;
+    const int64_t base = act ? col_base<AXIS>(c, g, W) : 0;
+    const int r0 = sg * kSegRows;
+    const int nr = !act ? 0 : (cl.rows - r0 < kSegRows ? cl.rows - r0 : kSegRows);
+    uint64_t f[kSegRows], o[kSegRows], o0[kSegRows];
+#pragma unroll
+    for (int k = 0; k < kSegRows; ++k) {
+        f[k] = k < nr ? F[base + (int64_t)(r0 + k) * cl.stride] : 0ull;
+        o[k] = k < nr ? O[base + (int64_t)(r0 + k) * cl.stride] : 0ull;
+        o0[k] = o[k];
+    }
+    // summary: reach out of the end, out of the start, free throughout
+    uint64_t r = 0, tr = ~0ull;
+#pragma unroll
+    for (int k = 0; k < kSegRows; ++k)
+        if (k < nr) {
+            r = f[k] & (r | o[k]);
+            tr &= f[k];
+        }
+    uint64_t rb = 0;
+#pragma unroll
+    for (int k = kSegRows - 1; k >= 0; --k)
+        if (k < nr) rb = f[k] & (rb | o[k]);
+    sA[threadIdx.x] = r;
+    sB[threadIdx.x] = rb;
+    sT[threadIdx.x] = tr;
+    __syncthreads();
+    // carries, in place of the summaries: threads 0 .. cj - 1 are column j
+    // of segment 0
+    if ((int)threadIdx.x < cj && c < cl.ncols) {
+        uint64_t carry = ~0ull;                           // the frame before row 0
+        for (int q = 0; q < cl.nseg; ++q) {
+            const int i = q * cj + j;
+            const uint64_t a = sA[i];
+            sA[i] = carry;
+            carry = a | (sT[i] & carry);
+        }
+        carry = ~0ull;                                    // the frame after the last row
+        for (int q = cl.nseg - 1; q >= 0; --q) {
+            const int i = q * cj + j;
+            const uint64_t b = sB[i];
+            sB[i] = carry;
+            carry = b | (sT[i] & carry);
+        }
+    }
+    __syncthreads();
+    if (!act) return;
+    r = sA[threadIdx.x];
+#pragma unroll
+    for (int k = 0; k < kSegRows; ++k)
+        if (k < nr) {
+            r = f[k] & (r | o[k]);
+            o[k] = r;
+        }
+    r = sB[threadIdx.x];
+#pragma unroll
+    for (int k = kSegRows - 1; k >= 0; --k)
+        if (k < nr) {
+            r = f[k] & (r | o[k]);
+            o[k] = r;
+        }
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < kSegRows; ++k)
+        if (k < nr && o[k] != o0[k]) {
+            O[base + (int64_t)(r0 + k) * cl.stride] = o[k];
+            any = true;
+        }
+    if (any && *changed == 0) *changed = 1;
+}
+
 // ---- distance shells and phi -----------------------------------------------
 
 // p = 0 on S_0 (a 6-neighbour with the other V~ value; outside the grid is
@@ -1621,6 +1713,17 @@ hipError_t tsdf_flood_round_launch(const uint64_t *F, uint64_t *O, uint64_t *seg
     uint64_t *A = seg, *B = seg + ns, *T = seg + 2 * ns, *C = seg + 3 * ns, *D = seg + 4 * ns;
     for (int axis = 1; axis <= 2; ++axis) {
         const Cols cl = cols_of(g, axis);
+        if (cl.nseg <= kFusedSegs) {
+            const int cj = (kBlock / cl.nseg) & ~7;       // >= 8: whole 64-byte rows of words
+            const unsigned gb = (unsigned)((cl.ncols + cj - 1) / cj);
+            if (axis == 1)
+                hipLaunchKernelGGL(k_seg_fused<1>, dim3(gb), dim3(kBlock), 0, s, F, O, g, W, cl,
+                                   cj, changed, prev);
+            else
+                hipLaunchKernelGGL(k_seg_fused<2>, dim3(gb), dim3(kBlock), 0, s, F, O, g, W, cl,
+                                   cj, changed, prev);
+            continue;
+        }
         const unsigned gs = grid_for(cl.ncols * cl.nseg, kBlock);
         if (axis == 1)
             hipLaunchKernelGGL(k_seg_summary<1>, dim3(gs), dim3(kBlock), 0, s, F, O, g, W, cl, A, B,

@@ -186,11 +186,14 @@ def test_errors(ctx):
     assert st == rcast.RC_E_INVAL
 
 
-@pytest.mark.parametrize("dims", [(150, 40, 37), (128, 17, 33), (65, 70, 18)])
+@pytest.mark.parametrize("dims", [(150, 40, 37), (128, 17, 33), (65, 70, 18), (70, 530, 12),
+                                  (66, 12, 600)])
 def test_wide_rows_and_long_columns(ctx, dims):
     """Rows of several 64-voxel words (ragged and exact) and columns of
     several 16-row segments, for the packed outside labelling, with both
-    smoothing paths (n = 2 and n = 6), then marching cubes."""
+    smoothing paths (n = 2 and n = 6), then marching cubes.  Columns of up
+    to 32 segments take the one-kernel column pass, longer ones (530 rows
+    along y, 600 along z) the three-kernel one."""
     nx, ny, nz = dims
     rng = np.random.default_rng(nx + ny + nz)
     surf = (rng.random((nz, ny, nx)) < 0.12).astype(np.uint8)
