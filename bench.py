@@ -91,6 +91,23 @@ def load_traffic(kernel_hash: str, rays: int, tris: int, tuning: dict):
     return d
 
 
+MESH_KERNEL_FILES = ("tsdf.hip", "vox.hip", "mesh_internal.h", "rc_internal.h")
+
+
+def load_mesh_traffic(n_vox: int):
+    """HBM bytes of one TSDF + marching-cubes call measured by rocprofv3
+    (profiles/tsdf_traffic.json); None when absent or taken on other kernel
+    code or another grid."""
+    p = os.path.join(ROOT, "profiles", "tsdf_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        d = json.load(fh)
+    if d.get("kernel_hash") != kernel_source_hash(MESH_KERNEL_FILES) or d.get("voxels") != n_vox:
+        return None
+    return d
+
+
 def load_cost_model():
     """Vector-instruction cost of the Q8 traversal per unit of the paper's
     cost model (Sec. IV-C: cost = C_trav N_nodes + C_tri K per ray), measured
@@ -844,6 +861,63 @@ def ingest(spec):
                        "counters; VALU utilisation = 2 cycles per wave64 instruction over "
                        "1024 SIMDs x cycles"}
         path = os.path.join(ROOT, "profiles", "trace_traffic.json")
+    elif kind == "mesh_traffic":
+        # the last TSDF + marching-cubes call of `--workload mesh --steps 2
+        # --warmup 0 --no-cpu --calib-copy` (the first marching-cubes call
+        # counts twice, to size its outputs): every dispatch from its
+        # smoothing pass to its triangle emission
+        import csv
+
+        def per_dispatch(tag, counter):
+            out = {}
+            with open(_find_csv(run_dir, tag)) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] == counter:
+                        out[int(r["Dispatch_Id"])] = (r["Kernel_Name"], float(r["Counter_Value"]))
+            return out
+
+        def short(name):
+            import re
+            m = re.search(r"(k_[A-Za-z0-9_]+(<[^>(]*>)?)\(", name)
+            return m.group(1) if m else name[:40]
+
+        fetch = per_dispatch("fetch", "FETCH_SIZE")
+        write = per_dispatch("write", "WRITE_SIZE")
+        cf = max(v for n, v in fetch.values() if "copy" in n)
+        cw = max(v for n, v in write.values() if "copy" in n)
+        fs, ws = (1 << 30) / 1024 / cf, (1 << 30) / 1024 / cw
+
+        def window(d):
+            ids = sorted(d)
+            a = max(i for i in ids if "k_smooth" in d[i][0])
+            b = next(i for i in ids if i > a and "k_mc_emit" in d[i][0])
+            return [i for i in ids if a <= i <= b]
+        wf, ww = window(fetch), window(write)
+        assert [short(fetch[i][0]) for i in wf] == [short(write[i][0]) for i in ww]
+        per = {}
+        for i, j in zip(wf, ww):
+            k = short(fetch[i][0])
+            e = per.setdefault(k, {"dispatches": 0, "read_bytes": 0.0, "write_bytes": 0.0})
+            e["dispatches"] += 1
+            e["read_bytes"] += fetch[i][1] * 1024 * fs
+            e["write_bytes"] += write[j][1] * 1024 * ws
+        rd = sum(e["read_bytes"] for e in per.values())
+        wr = sum(e["write_bytes"] for e in per.values())
+        bl = [json.loads(l) for l in open(os.path.join(run_dir, "bench.json")) if l.startswith("{")][-1]
+        nv = bl["config"]["voxels"]
+        out = {"kernel_hash": kernel_source_hash(MESH_KERNEL_FILES), "voxels": nv,
+               "dispatches": len(wf), "bytes_per_step": rd + wr, "read_bytes": rd,
+               "write_bytes": wr, "bytes_per_voxel": round((rd + wr) / nv, 3),
+               "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+               "per_kernel": {k: {"dispatches": e["dispatches"],
+                                  "read_MB": round(e["read_bytes"] / 1e6, 2),
+                                  "write_MB": round(e["write_bytes"] / 1e6, 2)}
+                              for k, e in sorted(per.items(), key=lambda x: -(x[1]["read_bytes"]
+                                                                              + x[1]["write_bytes"]))},
+               "note": "rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, over bench.py --workload mesh "
+                       "--steps 2 --warmup 0 --no-cpu --calib-copy; the dispatches of its last "
+                       "TSDF + marching-cubes call, scaled by the 1 GiB copy"}
+        path = os.path.join(ROOT, "profiles", "tsdf_traffic.json")
     else:
         raise SystemExit(f"unknown --ingest kind '{kind}'")
     with open(path, "w") as fh:
@@ -1353,6 +1427,14 @@ def run_mesh(args):
     phi = torch.empty((nz, ny, nx), dtype=torch.float32, device=dev)
     vt = torch.empty((nz, ny, nx), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
+    if args.calib_copy:
+        # 1 GiB read + 1 GiB written, to scale the byte counters of a
+        # rocprofv3 --pmc run of this workload
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         t0 = time.perf_counter()
@@ -1461,6 +1543,7 @@ def run_mesh(args):
     # outputs: 12 B position + 12 B normal per vertex, 12 B per triangle
     alg_bytes = int(per_vox * n_vox) + 24 * int(verts.shape[0]) + 12 * int(tris.shape[0])
     achieved = alg_bytes / (ms_step * 1e-3) / 1e9
+    mesh_counters = load_mesh_traffic(n_vox)
     cpu = None
     if not args.no_cpu:
         log("timing the CPU oracle on a sub-grid ...")
@@ -1545,9 +1628,17 @@ def run_mesh(args):
             "setup": "8 free-space poses x 32x1024 beams on the reconstructed mesh and on the "
                      "h = 3.5 cm ground-truth mesh the Gaussians were drawn from"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if mesh_counters is None else mesh_counters["bytes_per_step"],
                      "kernel": "rc_tsdf + rc_marching_cubes (all passes)",
-                     "bytes_per_voxel": per_vox},
+                     "bytes_per_voxel": per_vox,
+                     "measured": None if mesh_counters is None else {
+                         "GB_s": round(mesh_counters["bytes_per_step"] / (ms_step * 1e-3) / 1e9, 1),
+                         "frac": round(mesh_counters["bytes_per_step"] / (ms_step * 1e-3) / 1e9
+                                       / HBM_PEAK_GBS, 4),
+                         "bytes_per_voxel": round(mesh_counters["bytes_per_step"] / n_vox, 2),
+                         "source": "rocprofv3 FETCH_SIZE + WRITE_SIZE over one TSDF + marching "
+                                   "cubes call, scaled by a 1 GiB copy (profiles/tsdf_traffic.json)"}},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
