@@ -1346,14 +1346,14 @@ MIN_COMPONENT_FACES = 32
 # and the shells stay in LDS; wider bands: S_0 and each shell as byte
 # passes, then phi), the marching-cubes count writing mask and case bytes,
 # the tile scan forming both counts from those bytes and writing each
-# point's u32 vertex offset within its tile, and the emit pass reading mask
+# point's u16 vertex offset within its tile, and the emit pass reading mask
 # and case (the surface points' outputs are counted separately)
 TSDF_PASS_BYTES = {
     "smooth_pack_tiled": 1 + 1 + 0.25,
     "smooth_x": 1 + 1, "smooth_y": 1 + 2, "smooth_z": 2 + 1, "pack": 1 + 0.25,
     "flood_sweep": 0.375, "shells_phi_tiled": 1 + 0.125 + 4,
     "shell0": 1 + 1, "shell": 1 + 1, "phi": 1 + 0.125 + 4,
-    "mc_count": 4 + 1 + 1, "mc_scans": 1 + 1 + 4, "mc_emit": 1 + 1,
+    "mc_count": 4 + 1 + 1, "mc_scans": 1 + 1 + 2, "mc_emit": 1 + 1,
 }
 
 

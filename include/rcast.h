@@ -564,7 +564,7 @@ rc_status rc_tsdf(rc_ctx *ctx, const rc_grid *grid, const uint8_t *surf,
  * difference, one-sided on the grid's faces, interpolated along the
  * vertex's edge like its position; they point toward growing phi, out of
  * the solid; (0, 0, 0) where the gradient vanishes.  Synchronous.  Scratch
- * of about 10 bytes per voxel is kept by the context like rc_tsdf's.  Grids
+ * of about 4 bytes per voxel is kept by the context like rc_tsdf's.  Grids
  * up to 2^29 voxels.
  * Errors: RC_E_INVAL, RC_E_NOMEM (capacity too small: sizes still written),
  * RC_E_DEVICE. */

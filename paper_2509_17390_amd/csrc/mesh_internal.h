@@ -77,18 +77,18 @@ hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint64_t *O, uint8_t 
 
 // Marching cubes: the case table (count[256], tri[256][15] edge ids, -1
 // padded), the count pass (edge masks and cell cases, one byte each per
-// point; voff: each point's vertex offset within its scan tile; vsums /
+// point; voff: each point's vertex offset within its scan tile (u16); vsums /
 // tsums: exclusive scans of the tiles' vertex and triangle totals, with
 // mc_scan_sums_len(n) entries, the grand total last), and the emit pass
 // (normals: float32 [nv][3] or null).
 void mc_table_copy(uint8_t *count, int8_t *tri);
 int64_t mc_scan_sums_len(int64_t n);
 hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
-                           uint8_t *mask, uint8_t *cases, uint32_t *voff, uint32_t *vsums,
+                           uint8_t *mask, uint8_t *cases, uint16_t *voff, uint32_t *vsums,
                            uint32_t *tsums, hipStream_t s);
 hipError_t mc_emit_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
                           const int8_t *tris_of, const uint8_t *mask, const uint8_t *cases,
-                          const uint32_t *voff, const uint32_t *vsums, const uint32_t *tsums,
+                          const uint16_t *voff, const uint32_t *vsums, const uint32_t *tsums,
                           float *verts, int32_t *tris, float *normals, hipStream_t s);
 
 // ---------------------------------------------------------------------------

@@ -1117,7 +1117,7 @@ __device__ __forceinline__ void mc_emit_vertex(const float *__restrict__ phi, co
 // vbase[q / kScanTile], and its edges' vertices follow in axis order.
 __device__ __forceinline__ void mc_emit_tri(const TsdfGrid &g, const int8_t *__restrict__ tris_of,
                                             const uint8_t *__restrict__ mask,
-                                            const uint32_t *__restrict__ voff,
+                                            const uint16_t *__restrict__ voff,
                                             const uint32_t *__restrict__ vbase,
                                             int32_t *__restrict__ tris, int64_t i, int cs, int k,
                                             uint32_t t)
@@ -1133,7 +1133,7 @@ __device__ __forceinline__ void mc_emit_tri(const TsdfGrid &g, const int8_t *__r
         const int64_t q = i + ((corner & 1) ? 1 : 0) + ((corner & 2) ? sx : 0) +
                           ((corner & 4) ? sxy : 0);
         const int mq = mask[q];
-        const uint32_t id = voff[q] + vbase[q / kScanTile] +
+        const uint32_t id = (uint32_t)voff[q] + vbase[q / kScanTile] +
                             (uint32_t)__popc(mq & ((1 << axis) - 1));
         tris[3 * (int64_t)t + e] = (int32_t)id;
     }
@@ -1172,7 +1172,7 @@ __global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ ph
                                                     const int8_t *__restrict__ tris_of,
                                                     const uint8_t *__restrict__ mask,
                                                     const uint8_t *__restrict__ cases,
-                                                    const uint32_t *__restrict__ voff,
+                                                    const uint16_t *__restrict__ voff,
                                                     const uint32_t *__restrict__ vbase,
                                                     const uint32_t *__restrict__ tbase,
                                                     float *__restrict__ verts,
@@ -1265,7 +1265,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const uint32_t *__restric
 __global__ __launch_bounds__(kBlock) void k_mc_scan_tiles(const uint8_t *__restrict__ mask,
                                                           const uint8_t *__restrict__ cases,
                                                           const uint8_t *__restrict__ ntri,
-                                                          int64_t n, uint32_t *__restrict__ voff,
+                                                          int64_t n, uint16_t *__restrict__ voff,
                                                           uint32_t *__restrict__ vsums,
                                                           uint32_t *__restrict__ tsums)
 {
@@ -1284,24 +1284,33 @@ __global__ __launch_bounds__(kBlock) void k_mc_scan_tiles(const uint8_t *__restr
             cw |= (uint32_t)cases[base + k] << (8 * k);
         }
     }
-    uint32_t vc[kScanItems], tc[kScanItems], sv = 0, st = 0;
+    uint32_t vc[kScanItems], sv = 0, st = 0;
     for (int k = 0; k < kScanItems; ++k) {
         const bool in = base + k < n;
         vc[k] = in ? (uint32_t)__popc((mw >> (8 * k)) & 0xffu) : 0u;
-        tc[k] = in ? (uint32_t)nt_lds[(cw >> (8 * k)) & 0xffu] : 0u;
+        st += in ? (uint32_t)nt_lds[(cw >> (8 * k)) & 0xffu] : 0u;
         sv += vc[k];
-        st += tc[k];
     }
-    uint32_t totv, tott;
-    uint32_t rv = block_scan_excl(sv, &totv);
-    (void)block_scan_excl(st, &tott);
+    // both totals in one scan: a tile has at most 3 * kScanTile = 3072
+    // vertices, so they stay in the low 16 bits (and a point's offset
+    // within its tile fits a u16)
+    static_assert(3 * kScanTile < (1 << 16), "tile vertex offsets in 16 bits");
+    uint32_t tot;
+    uint32_t rv = block_scan_excl(sv | (st << 16), &tot) & 0xffffu;
+    uint16_t o[kScanItems];
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) voff[base + k] = rv;
+        o[k] = (uint16_t)rv;
         rv += vc[k];
     }
+    if (base + 4 <= n) {                                  // 8-byte aligned: base % 4 == 0
+        *reinterpret_cast<uint2 *>(voff + base) =
+            make_uint2((uint32_t)o[0] | ((uint32_t)o[1] << 16), (uint32_t)o[2] | ((uint32_t)o[3] << 16));
+    } else {
+        for (int k = 0; base + k < n && k < 4; ++k) voff[base + k] = o[k];
+    }
     if (threadIdx.x == 0) {
-        vsums[blockIdx.x] = totv;
-        tsums[blockIdx.x] = tott;
+        vsums[blockIdx.x] = tot & 0xffffu;
+        tsums[blockIdx.x] = tot >> 16;
     }
 }
 
@@ -1776,7 +1785,7 @@ hipError_t tsdf_shells_phi_launch(const uint8_t *vt, const uint64_t *O, uint8_t 
 }
 
 hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
-                           uint8_t *mask, uint8_t *cases, uint32_t *voff, uint32_t *vsums,
+                           uint8_t *mask, uint8_t *cases, uint16_t *voff, uint32_t *vsums,
                            uint32_t *tsums, hipStream_t s)
 {
     const dim3 tiles((unsigned)((g.nx + kMcTX - 1) / kMcTX), (unsigned)((g.ny + kMcTY - 1) / kMcTY),
@@ -1791,7 +1800,7 @@ hipError_t mc_count_launch(const float *phi, const TsdfGrid &g, float iso, const
 
 hipError_t mc_emit_launch(const float *phi, const TsdfGrid &g, float iso, const uint8_t *ntri,
                           const int8_t *tris_of, const uint8_t *mask, const uint8_t *cases,
-                          const uint32_t *voff, const uint32_t *vsums, const uint32_t *tsums,
+                          const uint16_t *voff, const uint32_t *vsums, const uint32_t *tsums,
                           float *verts, int32_t *tris, float *normals, hipStream_t s)
 {
     hipLaunchKernelGGL(k_mc_emit, dim3(grid_for(g.n, kScanTile)), dim3(kBlock), 0, s, phi, g, iso,

@@ -544,11 +544,12 @@ rc_status rc_marching_cubes(rc_ctx *c, const rc_grid *grid, const float *phi, fl
     std::lock_guard<std::mutex> lk(c->mesh_mu);
     Scratch ws(c);
     uint8_t *mask, *cases;
-    uint32_t *voff, *vs, *ts;
+    uint16_t *voff;
+    uint32_t *vs, *ts;
     const int64_t ns = mc_scan_sums_len(g.n);
     ws.take(&mask, g.n);
     ws.take(&cases, g.n);
-    ws.take(&voff, sizeof(uint32_t) * g.n);
+    ws.take(&voff, sizeof(uint16_t) * g.n);
     ws.take(&vs, sizeof(uint32_t) * ns);
     ws.take(&ts, sizeof(uint32_t) * ns);
     st = ws.commit();
