@@ -289,6 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_z4(const uint8_t *__restrict_
 // wave per row, the row's free word (the tile's 64 columns are one word)
 // with a clear outside word.
 constexpr int kSmTX = 64, kSmTY = 8, kSmTZ = 8;
+constexpr int kLoadBatch = 8;
 
 template <int N>
 __global__ __launch_bounds__(kBlock) void k_smooth_pack_tile(const uint8_t *__restrict__ surf,
@@ -311,13 +312,24 @@ __global__ __launch_bounds__(kBlock) void k_smooth_pack_tile(const uint8_t *__re
     uint16_t *B = reinterpret_cast<uint16_t *>(r1);
     const int bx = (int)blockIdx.x * kSmTX, by = (int)blockIdx.y * kSmTY;
     const int bz = (int)blockIdx.z * kSmTZ;
-    for (int q = threadIdx.x; q < NS; q += kBlock) {
-        const int lx = q % SX, t = q / SX, ly = t % SY, lz = t / SY;
-        const int gx = bx - N + lx, gy = by - N + ly, gz = bz - N + lz;
-        uint8_t v = 0;
-        if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz)
-            v = surf[((int64_t)gz * g.ny + gy) * g.nx + gx] != 0 ? 1 : 0;
-        S[q] = v;
+    // kLoadBatch loads per thread in flight at once: a voxel outside the
+    // grid reads voxel 0 (always there) and counts as 0, so no branch
+    // separates a load from the next
+    for (int q0 = threadIdx.x; q0 < NS; q0 += kLoadBatch * kBlock) {
+        uint8_t v[kLoadBatch];
+#pragma unroll
+        for (int k = 0; k < kLoadBatch; ++k) {
+            const int q = q0 + k * kBlock;
+            const int lx = q % SX, t = q / SX, ly = t % SY, lz = t / SY;
+            const int gx = bx - N + lx, gy = by - N + ly, gz = bz - N + lz;
+            const bool ok = q < NS && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 &&
+                            gz < g.nz;
+            v[k] = surf[ok ? ((int64_t)gz * g.ny + gy) * g.nx + gx : 0];
+            v[k] = ok && v[k] != 0 ? 1 : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kLoadBatch; ++k)
+            if (q0 + k * kBlock < NS) S[q0 + k * kBlock] = v[k];
     }
     __syncthreads();
     const int lx = (int)threadIdx.x % kSmTX, r0 = (int)threadIdx.x / kSmTX;
@@ -1012,10 +1024,11 @@ __global__ __launch_bounds__(kBlock) void k_mc_count_tile(const float *__restric
         const int q = (int)threadIdx.x + k * kBlock;
         const int lx = q % LX, t = q / LX, ly = t % LY, lz = t / LY;
         const int gx = bx + lx, gy = by + ly, gz = bz + lz;
-        v[k] = q < NL && gx < g.nx && gy < g.ny && gz < g.nz &&
-                       phi[((int64_t)gz * g.ny + gy) * g.nx + gx] < iso
-                   ? 1
-                   : 0;
+        // points outside the grid read point 0 and count as outside: no
+        // branch between the loads, so all PER are in flight at once
+        const bool ok = q < NL && gx < g.nx && gy < g.ny && gz < g.nz;
+        const float f = phi[ok ? ((int64_t)gz * g.ny + gy) * g.nx + gx : 0];
+        v[k] = ok && f < iso ? 1 : 0;
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -1049,24 +1062,26 @@ __global__ __launch_bounds__(kBlock) void k_mc_count_tile(const float *__restric
     }
 }
 
-// Gradient of phi at lattice point (x, y, z) along one axis, phi per voxel:
+// Gradient of phi at a lattice point along one axis, phi per voxel:
 // central difference halved inside, one-sided on the first and last point,
-// 0 on an axis of size 1.
-__device__ __forceinline__ float lattice_diff(const float *__restrict__ phi, int64_t i, int c,
-                                              int n, int64_t step)
+// 0 on an axis of size 1.  The two reads are split from the arithmetic and
+// made unconditional (the point itself where a neighbour is missing), so
+// that the twelve reads of a vertex's two gradients are all in flight
+// before the first is used.
+__device__ __forceinline__ void lattice_reads(const float *__restrict__ phi, int64_t i, int c,
+                                              int n, int64_t step, float &a, float &b)
 {
-    if (n < 2) return 0.0f;
-    if (c == 0) return __fsub_rn(phi[i + step], phi[i]);
-    if (c == n - 1) return __fsub_rn(phi[i], phi[i - step]);
-    return __fmul_rn(__fsub_rn(phi[i + step], phi[i - step]), 0.5f);
+    a = phi[c < n - 1 ? i + step : i];
+    b = phi[c > 0 ? i - step : i];
 }
 
-__device__ __forceinline__ void lattice_grad(const float *__restrict__ phi, const TsdfGrid &g,
-                                             int64_t i, int x, int y, int z, float out[3])
+// the same operations as the three cases: phi[i+1] - phi[i] at c = 0,
+// phi[i] - phi[i-1] at c = n - 1, (phi[i+1] - phi[i-1]) / 2 between
+__device__ __forceinline__ float lattice_diff(float a, float b, int c, int n)
 {
-    out[0] = lattice_diff(phi, i, x, g.nx, 1);
-    out[1] = lattice_diff(phi, i, y, g.ny, g.nx);
-    out[2] = lattice_diff(phi, i, z, g.nz, (int64_t)g.nx * g.ny);
+    const float d = __fsub_rn(a, b);
+    if (n < 2) return 0.0f;
+    return (c == 0 || c == n - 1) ? d : __fmul_rn(d, 0.5f);
 }
 
 // The vertex on edge `a` (0: +x, 1: +y, 2: +z) of lattice point i, into
@@ -1083,8 +1098,20 @@ __device__ __forceinline__ void mc_emit_vertex(const float *__restrict__ phi, co
     const float c0 = (float)(g.o[0] + ((double)x + 0.5) * g.h);
     const float c1 = (float)(g.o[1] + ((double)y + 0.5) * g.h);
     const float c2 = (float)(g.o[2] + ((double)z + 0.5) * g.h);
-    const int64_t step = a == 0 ? 1 : (a == 1 ? (int64_t)g.nx : (int64_t)g.nx * g.ny);
+    const int64_t sx = g.nx, sxy = (int64_t)g.nx * g.ny;
+    const int64_t step = a == 0 ? 1 : (a == 1 ? sx : sxy);
     const float fa = phi[i], fb = phi[i + step];
+    // gradient reads at both ends of the edge, issued before any is used
+    const int xb = x + (a == 0), yb = y + (a == 1), zb = z + (a == 2);
+    float r[12];
+    if (normals) {
+        lattice_reads(phi, i, x, g.nx, 1, r[0], r[1]);
+        lattice_reads(phi, i, y, g.ny, sx, r[2], r[3]);
+        lattice_reads(phi, i, z, g.nz, sxy, r[4], r[5]);
+        lattice_reads(phi, i + step, xb, g.nx, 1, r[6], r[7]);
+        lattice_reads(phi, i + step, yb, g.ny, sx, r[8], r[9]);
+        lattice_reads(phi, i + step, zb, g.nz, sxy, r[10], r[11]);
+    }
     const float t = __fdiv_rn(iso - fa, fb - fa);
     const float pa = __fadd_rn(a == 0 ? c0 : (a == 1 ? c1 : c2), __fmul_rn(t, g.hf));
     verts[3 * (int64_t)v + 0] = a == 0 ? pa : c0;
@@ -1093,9 +1120,11 @@ __device__ __forceinline__ void mc_emit_vertex(const float *__restrict__ phi, co
     if (normals) {
         // n = (1 - t) g_a + t g_b, normalised; float32, one rounded
         // operation at a time
-        float ga[3], gb[3];
-        lattice_grad(phi, g, i, x, y, z, ga);
-        lattice_grad(phi, g, i + step, x + (a == 0), y + (a == 1), z + (a == 2), gb);
+        const float ga[3] = {lattice_diff(r[0], r[1], x, g.nx), lattice_diff(r[2], r[3], y, g.ny),
+                             lattice_diff(r[4], r[5], z, g.nz)};
+        const float gb[3] = {lattice_diff(r[6], r[7], xb, g.nx),
+                             lattice_diff(r[8], r[9], yb, g.ny),
+                             lattice_diff(r[10], r[11], zb, g.nz)};
         const float w = __fsub_rn(1.0f, t);
         float nv[3];
         for (int k = 0; k < 3; ++k)
@@ -1185,7 +1214,12 @@ __global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ ph
     // vertex items (point | axis << 10), then triangle items (point |
     // k << 10 | case << 13): at most 3 and 5 per point
     __shared__ uint32_t items[5 * kScanTile];
+    // the case table's triangle edges (256 x 15 bytes, word aligned), read
+    // from LDS by the triangle items
+    __shared__ uint32_t tri_lds[256 * 15 / 4];
     nt_lds[threadIdx.x] = ntri[threadIdx.x];              // kBlock == 256 cases
+    for (int k = threadIdx.x; k < 256 * 15 / 4; k += kBlock)
+        tri_lds[k] = reinterpret_cast<const uint32_t *>(tris_of)[k];
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     const int64_t p0 = base + (int64_t)threadIdx.x * kScanItems;
@@ -1231,7 +1265,8 @@ __global__ __launch_bounds__(kBlock) void k_mc_emit(const float *__restrict__ ph
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < ntr; j += kBlock) {
         const uint32_t e = items[j];
-        mc_emit_tri(g, tris_of, mask, voff, vbase, tris, base + (e & 1023u), (int)(e >> 13),
+        mc_emit_tri(g, reinterpret_cast<const int8_t *>(tri_lds), mask, voff, vbase, tris,
+                    base + (e & 1023u), (int)(e >> 13),
                     (int)((e >> 10) & 7u), tb + j);
     }
 }
