@@ -229,7 +229,7 @@ def check_q8(ctx, v, t):
         return
     raw = ctx.debug_copy(s, rcast.RC_DBG_Q8NODES)[: info.n_q8_nodes]
     assert 0 < info.n_q8_nodes <= n - 1
-    f = raw.astype(np.float64)
+    f = raw[:, :6].astype(np.float64)      # origin and scales (the rest are packed bytes and refs)
     u = raw.view(np.uint32)
     refs = raw[:, 12:16].view(np.int32)
     seen = np.zeros(n, np.int64)
