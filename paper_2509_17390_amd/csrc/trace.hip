@@ -187,19 +187,22 @@ __device__ __forceinline__ void make_ray(const float *p, const float *b, RayW &r
 }
 
 // FP64 re-evaluation from the FP32 sheared coordinates (products exact).
-__device__ __noinline__ bool woop64(float Ax, float Ay, float Bx, float By, float Cx, float Cy,
-                                    float Az, float Bz, float Cz, float Sz, float *t_out)
+// Returns the FP32 ray parameter of a hit, NaN on a miss (by value: an
+// out-parameter lives in private memory, and the caller's loop would wait
+// for its reload before the next triangle's loads).
+__device__ __noinline__ float woop64(float Ax, float Ay, float Bx, float By, float Cx, float Cy,
+                                    float Az, float Bz, float Cz, float Sz)
 {
+    const float miss = __int_as_float(0x7fc00000);
     double U = (double)Cx * (double)By - (double)Cy * (double)Bx;
     double V = (double)Ax * (double)Cy - (double)Ay * (double)Cx;
     double W = (double)Bx * (double)Ay - (double)By * (double)Ax;
-    if ((U < 0.0 || V < 0.0 || W < 0.0) && (U > 0.0 || V > 0.0 || W > 0.0)) return false;
+    if ((U < 0.0 || V < 0.0 || W < 0.0) && (U > 0.0 || V > 0.0 || W > 0.0)) return miss;
     double det = U + V + W;
-    if (det == 0.0) return false;
+    if (det == 0.0) return miss;
     double T = U * ((double)Sz * (double)Az) + V * ((double)Sz * (double)Bz) +
                W * ((double)Sz * (double)Cz);
-    *t_out = (float)(T / det);
-    return true;
+    return (float)(T / det);
 }
 
 // Watertight test of one triangle record; returns true and the FP32 ray
@@ -232,8 +235,11 @@ __device__ __forceinline__ bool woop32(const RayW &r, const float4 &q0, const fl
     const bool pV = V > eV, nV = V < -eV;
     const bool pW = W > eW, nW = W < -eW;
     if ((pU || pV || pW) && (nU || nV || nW)) return false;  // certain miss
-    if (!((pU || nU) && (pV || nV) && (pW || nW)))
-        return woop64(Ax, Ay, Bx, By, Cx, Cy, A_z, B_z, C_z, r.Sz, t_out);
+    if (!((pU || nU) && (pV || nV) && (pW || nW))) {
+        const float t64 = woop64(Ax, Ay, Bx, By, Cx, Cy, A_z, B_z, C_z, r.Sz);
+        *t_out = t64;
+        return t64 == t64;
+    }
     // all three signs certain and equal
     const float det = U + V + W;
     const float T = r.Sz * fmaf(U, A_z, fmaf(V, B_z, W * C_z));
@@ -241,9 +247,11 @@ __device__ __forceinline__ bool woop32(const RayW &r, const float4 &q0, const fl
     return true;
 }
 
+// (t, id) before (bt, bid) in lexicographic order; evaluated without
+// branches
 __device__ __forceinline__ bool better(float t, int id, float bt, int bid)
 {
-    return t < bt || (t == bt && id < bid);
+    return (t < bt) | ((t == bt) & (id < bid));
 }
 
 // FP64 range of the winning triangle along the FP64 ray (plane equation).
@@ -372,14 +380,15 @@ __device__ __forceinline__ void test_leaf(LaneRay &L, int leaf)
     const TriRec tr = load_tri(L.tris, leaf);
     float t;
     ++L.n_tris;
-    if (woop32(L.r, tr.a, tr.b, tr.c, &t) && t >= L.t_min && t <= L.t_max) {
+    if (woop32(L.r, tr.a, tr.b, tr.c, &t)) {
+        // the update as selects rather than nested branches: each level of
+        // divergent branching costs the wave scalar exec-mask instructions
         const int id = __float_as_int(tr.c.y);
-        if (better(t, id, L.best_t, L.best_id)) {
-            L.best_t = t;
-            L.best_id = id;
-            L.best_leaf = leaf;
-            L.t_hi = t * (1.0f + kCullRel);
-        }
+        const bool upd = (t >= L.t_min) & (t <= L.t_max) & better(t, id, L.best_t, L.best_id);
+        L.best_t = upd ? t : L.best_t;
+        L.best_id = upd ? id : L.best_id;
+        L.best_leaf = upd ? leaf : L.best_leaf;
+        L.t_hi = upd ? t * (1.0f + kCullRel) : L.t_hi;
     }
 }
 
