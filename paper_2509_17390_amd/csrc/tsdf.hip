@@ -890,8 +890,17 @@ __global__ __launch_bounds__(kBlock) void k_shells_phi_tile(const uint8_t *__res
     // place
     constexpr uint32_t kHi = 0x80808080u, kLo = 0x7f7f7f7fu;
     __shared__ uint32_t T[NW];
+    // the outside word of each of the tile's rows (the tile's 64 columns
+    // are one word), read here so that the phi pass at the end does not
+    // wait on one load per row
+    __shared__ uint64_t Ow[kShTY * kShTZ];
     const int x0 = (int)blockIdx.x * kShTX - kShHX;
     const int y0 = (int)blockIdx.y * kShTY - H, z0 = (int)blockIdx.z * kShTZ - H;
+    if (threadIdx.x < kShTY * kShTZ) {
+        const int gy = (int)blockIdx.y * kShTY + (int)threadIdx.x % kShTY;
+        const int gz = (int)blockIdx.z * kShTZ + (int)threadIdx.x / kShTY;
+        Ow[threadIdx.x] = gy < g.ny && gz < g.nz ? O[((int64_t)gz * g.ny + gy) * W + blockIdx.x] : 0ull;
+    }
     for (int w = threadIdx.x; w < NW; w += kBlock) {
         const int wx = w % WX, t = w / WX, ly = t % LY, lz = t / LY;
         const int gx = x0 + 4 * wx, gy = y0 + ly, gz = z0 + lz;
@@ -957,7 +966,7 @@ __global__ __launch_bounds__(kBlock) void k_shells_phi_tile(const uint8_t *__res
         const int cx = kShHX + lx;
         const uint32_t pj = byte_of(T[((H + lz) * LY + H + ly) * WX + (cx >> 2)], cx & 3) & 0x7fu;
         const int64_t row = (int64_t)gz * g.ny + gy;
-        const bool out = (O[row * W + (gx >> 6)] >> (gx & 63)) & 1ull;
+        const bool out = (Ow[lz * kShTY + ly] >> (gx & 63)) & 1ull;   // gx >> 6 == blockIdx.x
         const float delta = pj == 0x7fu ? r : (float)pj * h;
         const float sg = out ? delta : -delta;
         phi[row * g.nx + gx] = fminf(fmaxf(sg, -r), r);
