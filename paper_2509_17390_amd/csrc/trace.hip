@@ -435,9 +435,6 @@ __device__ __forceinline__ bool setup_ray(const DevJob *__restrict__ jobs, int n
 template <int SS, int STK, int BLK>
 __device__ __forceinline__ bool node_step(LaneRay &L, LaneStack<SS, STK, BLK> &S)
 {
-    // a correct traversal fetches each of the n_tris - 1 records at most
-    // once; the cap only guards against a corrupted tree
-    if (++L.fetched > L.n_tris_scene + 64) { L.corrupt = true; return true; }
     const NodeRec nd = load_node(L.nodes, L.node);
     ++L.n_nodes;
     const float tl = slab(L.r, nd.q0.x, nd.q0.y, nd.q1.x, nd.q1.y, nd.q2.x, nd.q2.y, L.t_lo, L.t_hi);
@@ -497,7 +494,6 @@ __device__ __forceinline__ float qbyte(uint32_t w, int k)
 template <int SS, int STK, int BLK>
 __device__ __forceinline__ bool node_step_q8(LaneRay &L, LaneStack<SS, STK, BLK> &S)
 {
-    if (++L.fetched > L.n_tris_scene + 64) { L.corrupt = true; return true; }
     const NodeRec nd = load_node(L.nodes, L.node);
     ++L.n_nodes;
     const float org[3] = {nd.q0.x, nd.q0.y, nd.q0.z};
@@ -565,10 +561,13 @@ __device__ __forceinline__ bool node_step_q8(LaneRay &L, LaneStack<SS, STK, BLK>
     int next = -1;
     float next_t = 0.0f;
     const float lim = fminf(L.t_hi, FLT_MAX);
+    // at most 3 pushes below, so one bound check covers them (a push site
+    // of a valid tree has sp <= 3 (31 - 1) = 90); an early exit inside the
+    // unrolled pushes costs every visit more exec-mask work than this
+    if (L.sp > STK - 3) { L.corrupt = true; return true; }
     for (int k = 3; k >= 0; --k) {
         if (ref[k] >= 0 && t[k] <= lim) {
             if (next >= 0) {
-                if (L.sp == STK) { L.corrupt = true; return true; }
                 S.put(L.sp, next, next_t);
                 ++L.sp;
             }
@@ -592,6 +591,19 @@ __device__ __forceinline__ bool visit(LaneRay &L, LaneStack<SS, STK, BLK> &S)
 {
     if (FMT == FMT_Q8) return node_step_q8<SS, STK, BLK>(L, S);
     return node_step<SS, STK, BLK>(L, S);
+}
+
+// One node visit, then the node-fetch cap: a correct traversal fetches each
+// of the n_tris - 1 records at most once, so the cap only stops a corrupted
+// tree.  Applied with selects after the visit rather than as a branch out
+// of it.  Returns true when the ray has finished.
+template <int FMT, int SS, int STK, int BLK>
+__device__ __forceinline__ bool visit_capped(LaneRay &L, LaneStack<SS, STK, BLK> &S)
+{
+    const bool done = visit<FMT>(L, S);
+    const bool over = ++L.fetched > L.n_tris_scene + 64;
+    L.corrupt = L.corrupt | (!done & over);
+    return done | over;
 }
 
 template <int MODE>
@@ -637,7 +649,7 @@ __global__ __launch_bounds__(BLK, WAVES) void k_trace(const DevJob *__restrict__
     if (MODE == TRACE_BRUTE) {
         for (int k = 0; go && k < L.n_tris_scene; ++k) test_leaf(L, k);
     } else {
-        while (go) go = !visit<FMT>(L, S);
+        while (go) go = !visit_capped<FMT>(L, S);
     }
     finish_ray<MODE>(L, out_range, out_hit, out_nodes, out_tris);
 }
@@ -1000,7 +1012,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_persistent(
         }
         while (true) {
             if (active) {
-                if (visit<FMT>(L, S)) {
+                if (visit_capped<FMT>(L, S)) {
                     finish_ray<MODE>(L, out_range, out_hit, out_nodes, out_tris);
                     active = false;
                 }
