@@ -562,12 +562,14 @@ __device__ __forceinline__ bool node_step_q8(LaneRay &L, LaneStack<SS, STK, BLK>
     float next_t = 0.0f;
     const float lim = fminf(L.t_hi, FLT_MAX);
     // at most 3 pushes below, so one bound check covers them (a push site
-    // of a valid tree has sp <= 3 (31 - 1) = 90); an early exit inside the
-    // unrolled pushes costs every visit more exec-mask work than this
-    if (L.sp > STK - 3) { L.corrupt = true; return true; }
+    // of a valid tree has sp <= 3 (31 - 1) = 90).  It and the exits below
+    // are selects rather than early returns: every divergent exit costs
+    // each visit scalar exec-mask work
+    const bool full = L.sp > STK - 3;
+    L.corrupt = L.corrupt | full;
     for (int k = 3; k >= 0; --k) {
         if (ref[k] >= 0 && t[k] <= lim) {
-            if (next >= 0) {
+            if (next >= 0 && !full) {
                 S.put(L.sp, next, next_t);
                 ++L.sp;
             }
@@ -575,15 +577,22 @@ __device__ __forceinline__ bool node_step_q8(LaneRay &L, LaneStack<SS, STK, BLK>
             next_t = t[k];
         }
     }
-    if (next >= 0) { L.node = next; return false; }
-    while (L.sp > 0) {
+    // one exit: continue with the nearest child, else pop the nearest
+    // pending subtree still in range
+    bool more = next >= 0;
+    L.node = more ? next : L.node;
+    bool pop = !more;
+    while (pop & (L.sp > 0)) {
         --L.sp;
         int n;
         float tt;
         S.get(L.sp, n, tt);
-        if (tt <= L.t_hi) { L.node = n; return false; }
+        const bool ok = tt <= L.t_hi;
+        L.node = ok ? n : L.node;
+        more = ok;
+        pop = !ok;
     }
-    return true;
+    return !more | full;
 }
 
 template <int FMT, int SS, int STK, int BLK>
